@@ -1,0 +1,205 @@
+"""FP64 CPU oracle of WR3L (Wiener init + robust, regularised Richardson-Lucy).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import it; the product path never does.
+It shares no code with the GPU path (it has its own C library, liborc.so,
+built from oracle.c by `build()`).
+
+Passages followed (Welk et al., "Fast and Robust Linear Motion Deblurring"):
+  * blur model and adjoint PSF: Sec. 2, eq. (1) and the definition of h*;
+  * Wiener filter: Sec. 2.1, eq. (2), with periodic continuation (Sec. 4.2);
+  * replacement of non-positive Wiener values by a small positive value
+    before RRRL: Sec. 3.2 (WR3L);
+  * RRRL iteration: Sec. 2.3, eqs. (6)-(12), multiplicative in u^k;
+  * diffusion term by central differences: Sec. 4.1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liborc.so")
+BC_REPLICATE = 0
+BC_PERIODIC = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liborc.so (gcc, -O2, no fast-math, no FMA contraction)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
+                               "-fno-fast-math", "-fPIC", "-shared", src, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("eps_data", ctypes.c_double),
+                ("eps_tv", ctypes.c_double), ("s_min", ctypes.c_double),
+                ("robust", ctypes.c_int), ("bc", ctypes.c_int)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        lib = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i = ctypes.c_int
+        for name in ("orc_blur", "orc_corr"):
+            fn = getattr(lib, name)
+            fn.argtypes = [dp, i, i, dp, i, i, i, dp, i]
+            fn.restype = None
+        lib.orc_rf.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_rf.restype = ctypes.c_double
+        lib.orc_tv.argtypes = [dp, i, i, ctypes.c_double, dp, i]
+        lib.orc_tv.restype = None
+        lib.orc_rrrl_step.argtypes = [dp, dp, dp, i, i, dp, i, i, ctypes.POINTER(_Params), dp, i]
+        lib.orc_rrrl_step.restype = None
+        lib.orc_rrrl.argtypes = [dp, dp, dp, i, i, dp, i, i, ctypes.POINTER(_Params), i, dp, i]
+        lib.orc_rrrl.restype = None
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def default_threads() -> int:
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:  # pragma: no cover
+        return max(1, min(16, os.cpu_count() or 1))
+
+
+@dataclass
+class Params:
+    """RRRL parameters (eq. (9)) and the conventions the paper leaves open."""
+    alpha: float = 0.003
+    eps_data: float = 0.1
+    eps_tv: float = 0.1
+    s_min: float = 1e-12
+    robust: bool = True
+    bc: int = BC_REPLICATE
+
+    def c(self) -> _Params:
+        return _Params(self.alpha, self.eps_data, self.eps_tv, self.s_min,
+                       int(bool(self.robust)), int(self.bc))
+
+
+# ---------------------------------------------------------------- operators
+def blur(v, h, bc: int = BC_REPLICATE, threads: int | None = None) -> np.ndarray:
+    """A v(x) = sum_d h(d) E(v)(x-d) (eq. (1))."""
+    v, h = _f64(v), _f64(h)
+    out = np.empty_like(v)
+    _load().orc_blur(_ptr(v), v.shape[0], v.shape[1], _ptr(h), h.shape[0], h.shape[1],
+                     int(bc), _ptr(out), threads or default_threads())
+    return out
+
+
+def corr(v, h, bc: int = BC_REPLICATE, threads: int | None = None) -> np.ndarray:
+    """B v(x) = sum_d h(d) E(v)(x+d): convolution with h*(x) = h(-x) (Sec. 2)."""
+    v, h = _f64(v), _f64(h)
+    out = np.empty_like(v)
+    _load().orc_corr(_ptr(v), v.shape[0], v.shape[1], _ptr(h), h.shape[0], h.shape[1],
+                     int(bc), _ptr(out), threads or default_threads())
+    return out
+
+
+def rf(f: float, s: float) -> float:
+    """Information divergence r_f(s) = s - f - f ln(s/f) (eq. (7)); r_0(s) = s."""
+    return _load().orc_rf(float(f), float(s))
+
+
+def tv(u, eps_tv: float, threads: int | None = None) -> np.ndarray:
+    """D(u) = div(Psi'(|grad u|^2) grad u) by central differences (eq. (11), Sec. 4.1)."""
+    u = _f64(u)
+    out = np.empty_like(u)
+    _load().orc_tv(_ptr(u), u.shape[0], u.shape[1], float(eps_tv), _ptr(out),
+                   threads or default_threads())
+    return out
+
+
+def rrrl_step(f, u, h, p: Params, threads: int | None = None, parts: bool = False):
+    """One RRRL step (eqs. (9)-(12)).  With parts=True also returns the
+    intermediate planes (s, W, q, Bq, BW, D) as a dict."""
+    f, u, h = _f64(f), _f64(u), _f64(h)
+    out = np.empty_like(u)
+    pp = p.c()
+    buf = np.empty((6,) + u.shape) if parts else None
+    _load().orc_rrrl_step(_ptr(f), _ptr(u), _ptr(out), u.shape[0], u.shape[1], _ptr(h),
+                          h.shape[0], h.shape[1], ctypes.byref(pp),
+                          _ptr(buf) if parts else None, threads or default_threads())
+    if parts:
+        return out, dict(zip(("s", "W", "q", "N1", "N2", "D"), buf))
+    return out
+
+
+def rrrl(f, u0, h, p: Params, iters: int, threads: int | None = None,
+         checkpoints: bool = False):
+    """`iters` RRRL steps from u0.  With checkpoints=True also returns the
+    iterates u^0..u^{iters-1} stacked."""
+    f, u0, h = _f64(f), _f64(u0), _f64(h)
+    out = np.empty_like(u0)
+    pp = p.c()
+    ck = np.empty((iters,) + u0.shape) if checkpoints else None
+    _load().orc_rrrl(_ptr(f), _ptr(u0), _ptr(out), u0.shape[0], u0.shape[1], _ptr(h),
+                     h.shape[0], h.shape[1], ctypes.byref(pp), int(iters),
+                     _ptr(ck) if checkpoints else None, threads or default_threads())
+    return (out, ck) if checkpoints else out
+
+
+# ------------------------------------------------------------------- Wiener
+def psf_spectrum(h, H: int, W: int) -> np.ndarray:
+    """h^(k) = sum_d h(d) exp(-2 pi i (k_y d_y / H + k_x d_x / W)): the DFT of
+    the PSF placed with its centre at index (0,0) under periodic wrap."""
+    h = _f64(h)
+    Py, Px = h.shape
+    cy, cx = (Py - 1) // 2, (Px - 1) // 2
+    pad = np.zeros((H, W))
+    for j in range(Py):
+        for i in range(Px):
+            pad[(j - cy) % H, (i - cx) % W] += h[j, i]
+    return np.fft.fft2(pad)
+
+
+def wiener_multiplier(h, H: int, W: int, K: float) -> np.ndarray:
+    """M = conj(h^) / (|h^|^2 + K) (eq. (2))."""
+    hh = psf_spectrum(h, H, W)
+    return np.conj(hh) / (np.abs(hh) ** 2 + K)
+
+
+def wiener(f, h, K: float) -> np.ndarray:
+    """Wiener filter, eq. (2): u = Re IDFT(DFT(f) * conj(h^)/(|h^|^2+K)),
+    periodic continuation (Sec. 4.2).  FP64."""
+    f = _f64(f)
+    M = wiener_multiplier(h, f.shape[0], f.shape[1], K)
+    return np.real(np.fft.ifft2(np.fft.fft2(f) * M))
+
+
+def wiener_init(f, h, K: float, pos_floor: float) -> np.ndarray:
+    """WR3L initialisation (Sec. 3.2): Wiener output with values below the
+    positive floor replaced, u^0 = max(u_pre, pos_floor)."""
+    return np.maximum(wiener(f, h, K), pos_floor)
+
+
+def wr3l(f, h, K: float, p: Params, iters: int, pos_floor: float = 1.0,
+         threads: int | None = None) -> np.ndarray:
+    """WR3L (Sec. 3.2): Wiener initialisation followed by `iters` RRRL steps."""
+    u0 = wiener_init(f, h, K, pos_floor)
+    return rrrl(f, u0, h, p, iters, threads=threads)
