@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""WR3L benchmark on one MI355X.
+
+Workload (default): one 1024x1024 float32 image (rectangles on a gradient plus
+band-limited texture), oblique linear motion blur of length 31 px at a seeded
+random angle (31x31 bilinear line PSF), noise sigma 3; Wiener initialisation
+(K = 0.01) followed by 20 RRRL iterations with alpha = 0.002.
+
+One step = the whole hot path on that image: deblur_wiener + 20 iterations of
+deblur_rrrl_iterate, inputs resident in HBM.  value = RRRL megapixel-
+iterations per second of the whole step (H*W*iters / step time, Wiener time
+included).  The JSON line also carries:
+  * roofline: the dominant kernel's algorithmic rate (timed alone with HIP
+    events on its launch stream) against the MI355X peak for its bound;
+  * hbm: the iteration's algorithmic bytes (12 B per pixel-iteration read u, f,
+    write u; 8 B per pixel for Wiener) per second against 8 TB/s;
+  * cpu_baseline: the FP64 oracle on the host cores for the same workload.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+       python bench.py --ingest-pmc DIR   (turn rocprofv3 --pmc results into
+                                           profiles/<kernel>_traffic.json)
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (packed FMA), TFLOP/s
+CSRC = os.path.join(ROOT, "paper_1212_2245_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+METRIC = "RRRL megapixel-iterations/s + % HBM peak at ≤1e-4 rel-L2 vs FP64; batched images/s"
+
+# kernel name fragments as they appear in rocprofv3 traces
+KERNELS = {"stage1": "rrrl_taps_stage1", "stage2": "rrrl_taps_stage2"}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        with open(p, "rb") as fh:
+            h.update(os.path.basename(p).encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--kernel-reps", type=int, default=50, help="launches per stage kernel for the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=20, help="RRRL iterations in the oracle sample")
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--ingest-pmc", metavar="DIR", help="parse rocprofv3 --pmc output and exit")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------- pmc ingest
+def ingest_pmc(d: str) -> None:
+    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the stage kernels
+    and of the calibration copy kernel from rocprofv3 counter_collection CSVs
+    under `d`, scaled by the copy's bytes, into profiles/<kernel>_traffic.json."""
+    import csv
+    rows = []
+    for p in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(p) as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    vals: dict[tuple[str, str], list[float]] = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        ctr = r.get("Counter_Name", "")
+        v = float(r.get("Counter_Value", "nan"))
+        key = None
+        for k, frag in KERNELS.items():
+            if frag in name:
+                key = k
+        if "copy" in name.lower() or "elementwise" in name.lower():
+            key = "copy"
+        if key:
+            vals.setdefault((key, ctr), []).append(v)
+    meta = json.load(open(os.path.join(d, "calib.json"))) if os.path.exists(os.path.join(d, "calib.json")) else {}
+    out = {}
+    for (k, c), v in vals.items():
+        out.setdefault(k, {})[c] = sum(v) / len(v)
+    copy_bytes = meta.get("copy_bytes")
+    res = {"source_hash": kernel_source_hash(), "raw_kib_per_dispatch": out, "copy_bytes": copy_bytes}
+    if copy_bytes and "copy" in out:
+        # a copy of N bytes reads N and writes N: scale = true bytes / counter reading
+        fs = out["copy"].get("FETCH_SIZE")
+        ws = out["copy"].get("WRITE_SIZE")
+        res["fetch_scale"] = copy_bytes / (fs * 1024.0) if fs else None
+        res["write_scale"] = copy_bytes / (ws * 1024.0) if ws else None
+    for k in KERNELS:
+        if k in out:
+            fs, ws = out[k].get("FETCH_SIZE"), out[k].get("WRITE_SIZE")
+            tb = 0.0
+            ok = True
+            for v, sc in ((fs, res.get("fetch_scale")), (ws, res.get("write_scale"))):
+                if v is None or sc is None:
+                    ok = False
+                else:
+                    tb += v * 1024.0 * sc
+            res[k] = {"traffic_bytes": tb if ok else None}
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(os.path.join(PROFILES, "stage_kernels_traffic.json"), "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def load_traffic(kernel: str):
+    p = os.path.join(PROFILES, "stage_kernels_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_hash") != kernel_source_hash():
+        return None  # kernels changed since the counters were taken
+    return (d.get(kernel) or {}).get("traffic_bytes")
+
+
+# ------------------------------------------------------------------- bench
+def main():
+    args = parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(args.ingest_pmc)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(images are independent; see the sharding notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1212_2245_amd as dbl
+    import synth
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    case = synth.make_case(1)
+    H, W = case.f.shape
+    iters = case.iters
+    f = torch.from_numpy(case.f).to(dev)
+    psf = dbl.Psf.from_taps(torch.from_numpy(case.psf).to(dev))
+    params = dbl.Params(alpha=case.alpha, iters=iters)
+    u = torch.empty_like(f)
+    ws_w = torch.empty(dbl.deblur_workspace_bytes(0, H, W, W, psf), dtype=torch.uint8, device=dev)
+    ws_i = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, psf, params), dtype=torch.uint8, device=dev)
+
+    def step():
+        dbl.deblur_wiener(f, u, psf, case.K, 1.0, ws=ws_w)
+        dbl.deblur_rrrl_iterate(f, u, u, psf, params, ws=ws_i)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps), timing {args.steps} steps", file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    ms_step = max(ms_step, 1e3 * wall / args.steps)
+    mpxit = H * W * iters / (ms_step * 1e-3) / 1e6
+    result_gpu = u.cpu().numpy()
+
+    # Wiener alone and one iteration alone (context)
+    ev0.record()
+    for _ in range(args.kernel_reps):
+        dbl.deblur_wiener(f, u, psf, case.K, 1.0, ws=ws_w)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_wiener = ev0.elapsed_time(ev1) / args.kernel_reps
+
+    # per-kernel timing of the two stage kernels, each launched alone
+    taps = dbl.deblur_compile_taps(psf)
+    qw = torch.empty((H, W, 2), dtype=torch.float32, device=dev)
+    u2 = torch.empty_like(u)
+    p1 = dbl.Params(alpha=case.alpha, iters=1)
+    dbl.deblur_rrrl_weights(f, u, qw, psf, taps, p1)
+    dbl.deblur_rrrl_update(qw, u, u2, psf, taps, p1)
+    torch.cuda.synchronize()
+    kt = {}
+    for name, fn in (("stage1", lambda: dbl.deblur_rrrl_weights(f, u, qw, psf, taps, p1)),
+                     ("stage2", lambda: dbl.deblur_rrrl_update(qw, u, u2, psf, taps, p1))):
+        ev0.record()
+        for _ in range(args.kernel_reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        kt[name] = ev0.elapsed_time(ev1) / args.kernel_reps * 1e-3   # seconds per launch
+    T = int(np.count_nonzero(case.psf))
+    # algorithmic flops per pixel: stage 1 = A (T FMA) + robust weight and
+    # quotient (~40); stage 2 = B on two channels (2T FMA) + diffusion term and
+    # update (~40).  One FMA = 2 flops.
+    flops = {"stage1": (2 * T + 40) * H * W, "stage2": (4 * T + 40) * H * W}
+    dom = max(kt, key=lambda k: kt[k])
+    ach = flops[dom] / kt[dom] / 1e12
+    traffic = load_traffic(dom)
+    roofline = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
+                "kernel": KERNELS[dom], "avg_launch_us": round(kt[dom] * 1e6, 3),
+                "flops_per_launch": flops[dom], "nonzero_taps": T,
+                "other_kernel": {"name": KERNELS["stage1" if dom == "stage2" else "stage2"],
+                                 "avg_launch_us": round(kt["stage1" if dom == "stage2" else "stage2"] * 1e6, 3)}}
+    alg_bytes = 12.0 * H * W * iters + 8.0 * H * W
+    hbm_gbs = alg_bytes / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(mpxit, 3), "unit": "Mpx-it/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "oblique line blur L=31 (31x31 bilinear PSF), 1024x1024, Wiener K=0.01 + "
+                               "20 RRRL iterations alpha=0.002, robust, TV, replicate border",
+                   "H": H, "W": W, "iters": iters, "psf_theta_rad": round(case.meta["theta"], 6)},
+        "roofline": roofline,
+        "hbm": {"algorithmic_bytes_per_step": alg_bytes, "achieved_GBs": round(hbm_gbs, 2),
+                "peak_GBs": HBM_PEAK_GBS, "frac": round(hbm_gbs / HBM_PEAK_GBS, 5)},
+        "wiener_ms": round(ms_wiener, 5),
+        "iteration_us": round((ms_step - ms_wiener) * 1e3 / iters, 3),
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.default_threads()
+        t0 = time.perf_counter()
+        want = oracle.wr3l(case.f, case.psf, case.K, oracle.Params(alpha=case.alpha), args.cpu_iters,
+                           threads=threads)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(H * W * args.cpu_iters / dt / 1e6, 4), "unit": "Mpx-it/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"the full workload image (1024x1024), FP64 oracle Wiener + "
+                                         f"{args.cpu_iters} RRRL iterations, {dt:.2f} s wall"}
+        if args.cpu_iters == iters:
+            e = float(np.linalg.norm(result_gpu.astype(np.float64) - want) / np.linalg.norm(want))
+            out["parity"] = {"rel_l2": e, "max_abs": float(np.abs(result_gpu - want).max()), "tol": 1e-4}
+
+    if args.pmc_calibrate:
+        nbytes = 256 << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        out["pmc_calibration_copy_bytes"] = nbytes
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

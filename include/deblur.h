@@ -1,0 +1,154 @@
+/*
+ * deblur.h - C ABI of the MI355X (gfx950) WR3L deblurring library.
+ *
+ * Method: Welk, Raudaschl, Schwarzbauer, Erler, Lauter, "Fast and Robust
+ * Linear Motion Deblurring".  WR3L (Sec. 3.2) is a Wiener filter (Sec. 2.1,
+ * eq. (2)) whose non-positive outputs are replaced by a small positive value,
+ * followed by a few iterations of robust and regularised Richardson-Lucy
+ * deconvolution, RRRL (Sec. 2.3, eqs. (6)-(12)), for a known space-invariant
+ * point-spread function (PSF, blur model eq. (1)).
+ *
+ * Conventions for every entry point:
+ *  - Images are row-major float32 arrays of H rows and W columns with a row
+ *    pitch of `pitch` elements (pitch >= W).  Image, PSF-tap, checkpoint,
+ *    gradient and workspace pointers are DEVICE pointers; descriptor structs
+ *    (deblur_psf, deblur_params) are HOST pointers read during the call.
+ *  - The caller owns all memory.  The library allocates nothing on these
+ *    calls; scratch space is the caller's workspace of at least
+ *    deblur_workspace_bytes(...) bytes, 256-byte aligned.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *    null stream) and the call returns without synchronising.  Inputs must
+ *    stay valid until the stream reaches the work.  Calls on distinct streams
+ *    with distinct workspaces may run concurrently.
+ *  - Every argument is validated on the host before anything is enqueued; on
+ *    an error nothing is written.  Return value: DEBLUR_OK or a negative
+ *    deblur_status (deblur_status_string gives the text).  Launch failures
+ *    are reported as DEBLUR_EDEVICE.
+ *  - Preconditions that are not checked: PSF taps non-negative with sum 1
+ *    (normalised PSF, eq. (1)); observed image values >= 0 (values <= 0 are
+ *    treated as 0 in the data term, where r_f(s) = s); buffers not
+ *    overlapping except where an entry point says so.
+ */
+#ifndef DEBLUR_H
+#define DEBLUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DEBLUR_OK = 0,
+    DEBLUR_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad enum, ...) */
+    DEBLUR_EUNSUPPORTED = -2, /* valid but not implemented (FFT length, PSF radius, ...) */
+    DEBLUR_EWORKSPACE = -3,   /* workspace missing or smaller than required */
+    DEBLUR_EDEVICE = -4       /* HIP launch or runtime failure */
+} deblur_status;
+
+/* Boundary continuation of the blur A and adjoint blur B (Sec. 4.2): the
+ * paper uses constant continuation for spatial-domain convolutions and
+ * periodic continuation for Fourier-domain ones.  The Wiener step is always
+ * periodic; the diffusion term always has zero flux across the border. */
+typedef enum { DEBLUR_BC_REPLICATE = 0, DEBLUR_BC_PERIODIC = 1 } deblur_boundary;
+
+/* PSF kinds (Sec. 4.3).  Offsets d = (dy, dx) are relative to the centre of
+ * an odd-sized array.  BOX_H / BOX_V: uniform linear motion of integer length
+ * L >= 1 along x / y, taps 1/L at d in [-floor((L-1)/2), floor(L/2)] (array
+ * length L + (L even)).  TAPS: a general ph x pw array (ph, pw odd). */
+typedef enum { DEBLUR_PSF_BOX_H = 0, DEBLUR_PSF_BOX_V = 1, DEBLUR_PSF_TAPS = 2 } deblur_psf_kind;
+
+/* How the RRRL iteration evaluates A and B: AUTO picks the fastest exact
+ * spatial method for the PSF kind (running sums for boxes, LDS stencil for
+ * taps). */
+typedef enum { DEBLUR_CONV_AUTO = 0, DEBLUR_CONV_RUNSUM = 1, DEBLUR_CONV_STENCIL = 2 } deblur_conv;
+
+typedef struct {
+    int32_t kind;       /* deblur_psf_kind */
+    int32_t length;     /* box length L (BOX_H, BOX_V); ignored for TAPS */
+    int32_t ph, pw;     /* TAPS: odd array dims, 1..65 each; ignored for boxes */
+    const float* taps;  /* TAPS: device array ph*pw, row-major; may be NULL for boxes */
+} deblur_psf;
+
+typedef struct {
+    float alpha;     /* regulariser weight alpha >= 0 (eq. (9)) */
+    float eps_data;  /* epsilon > 0 of the data penaliser Phi(z) = sqrt(z + eps^2) (Sec. 2.3) */
+    float eps_tv;    /* epsilon > 0 of the TV penaliser Psi (Sec. 2.3) */
+    float s_min;     /* > 0: the blurred iterate is bounded below by s_min before dividing */
+    int32_t iters;   /* number of RRRL iterations, >= 0 */
+    int32_t robust;  /* 1: W = Phi'(r_f(u*h)) (eq. (10)); 0: W = 1 (plain RL data term) */
+    int32_t boundary;/* deblur_boundary */
+    int32_t conv;    /* deblur_conv */
+} deblur_params;
+
+/* Text for a status code (static storage). */
+const char* deblur_status_string(int status);
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int deblur_version(void);
+
+/* Workspace bytes needed by an entry point: op 0 = deblur_wiener,
+ * 1 = deblur_rrrl_iterate.  Returns 0 for invalid arguments (the matching
+ * call then returns DEBLUR_EINVAL or DEBLUR_EUNSUPPORTED). */
+size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                              const deblur_params* p);
+
+/* Wiener initialisation of WR3L (Sec. 2.1 eq. (2); Sec. 3.2):
+ *   u0 = max( Re IDFT( DFT(f) conj(h^) / (|h^|^2 + K) ), pos_floor )
+ * with h^ the DFT of the PSF centred at index (0,0), periodic continuation.
+ * f, u0: device H x W, pitch `pitch` (must not overlap).  K > 0,
+ * pos_floor > 0.  H and W must factor as 2^a 3^b with H, W <= 2048 (only W
+ * for a PSF on one row, where the filter runs along rows).  The spectral
+ * division is done in FP64, the transforms in FP32. */
+int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                  double K, float pos_floor, void* ws, size_t ws_bytes, void* stream);
+
+/* p->iters RRRL iterations (Sec. 2.3 eq. (9)-(12)) from u_in:
+ *   s = max(A u, s_min),  W = Phi'(r_f(s)) (or 1),  q = W max(f,0) / s,
+ *   u <- u (B q + alpha [D(u)]_+) / (B W - alpha [D(u)]_-),
+ * A = blur with h, B = blur with h*(x) = h(-x), D = div(Psi'(|grad u|^2) grad u)
+ * by central differences (Sec. 4.1).  f, u_in, u_out: device H x W, pitch
+ * `pitch`; u_in == u_out is allowed, other overlaps are not.  ckpt
+ * (nullable): device array of p->iters * H * pitch floats receiving the
+ * iterates u^0 .. u^{iters-1} (for the backward pass).  PSF radius <= 32 in
+ * each direction and <= min(H, W). */
+int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t H, int32_t W, int32_t pitch,
+                        const deblur_psf* psf, const deblur_params* p, float* ckpt, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* ---- Stage-level entry points of one RRRL iteration (spatial stencil path).
+ * deblur_rrrl_iterate chains them; they are exported for callers that
+ * schedule the iteration themselves, and for per-stage verification and
+ * profiling.  Each is one kernel launch. */
+
+/* Bytes of the compiled tap list of a PSF (0 for an invalid descriptor). */
+size_t deblur_taps_bytes(const deblur_psf* psf);
+
+/* Compiles the PSF into the list of its non-zero taps (offsets d and
+ * weights h(d), row-major order) in the device buffer `taps_out` of at least
+ * deblur_taps_bytes(psf) bytes, 256-byte aligned.  The list is read by the
+ * two stage entry points below and stays valid while the PSF is unchanged. */
+int deblur_compile_taps(const deblur_psf* psf, void* taps_out, size_t taps_bytes, void* stream);
+
+/* Stage 1 of eq. (9): s = max(A u, s_min) (blur with h, eq. (1)), robust
+ * weight W = Phi'(r_f(s)) (eq. (10), or 1 if p->robust == 0) and quotient
+ * q = W max(f,0) / s.  f, u: device H x W, pitch `pitch`; qw: device output
+ * of H*W interleaved pairs (q, W), row pitch 2*W floats.  p->iters is
+ * ignored.  PSF radius <= 32. */
+int deblur_rrrl_weights(const float* f, const float* u, float* qw, int32_t H, int32_t W, int32_t pitch,
+                        const deblur_psf* psf, const void* taps, const deblur_params* p, void* stream);
+
+/* Stage 2 of eq. (9): N1 = B q, N2 = B W (blur with h*), diffusion term
+ * D(u) (eq. (11)) and the update u_out = u (N1 + alpha [D]_+) / (N2 - alpha [D]_-).
+ * qw as written by deblur_rrrl_weights; u, u_out: device H x W, pitch
+ * `pitch`, must not overlap; u_copy (nullable) receives a copy of u (the
+ * checkpoint of this iteration).  p->iters is ignored. */
+int deblur_rrrl_update(const float* qw, const float* u, float* u_out, float* u_copy, int32_t H, int32_t W,
+                       int32_t pitch, const deblur_psf* psf, const void* taps, const deblur_params* p,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEBLUR_H */

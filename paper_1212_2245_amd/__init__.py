@@ -1,0 +1,202 @@
+"""WR3L deblurring on MI355X (gfx950): Wiener initialisation followed by
+robust and regularised Richardson-Lucy iterations (Welk et al., "Fast and
+Robust Linear Motion Deblurring", Sec. 2.1, 2.3, 3.2).
+
+The compute runs in hand-written HIP kernels behind the C ABI of
+include/deblur.h (libdeblur.so).  This module only marshals arguments:
+PyTorch provides device memory and the current stream.  The binding
+functions carry the C names (deblur_wiener, deblur_rrrl_iterate, ...);
+`wr3l` chains them.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import (BC_PERIODIC, BC_REPLICATE, CONV_AUTO, CONV_RUNSUM, CONV_STENCIL, PSF_BOX_H, PSF_BOX_V,
+                   PSF_TAPS, DeblurError)
+
+__all__ = ["Psf", "Params", "deblur_workspace_bytes", "deblur_wiener", "deblur_rrrl_iterate", "wr3l",
+           "DeblurError", "BC_REPLICATE", "BC_PERIODIC", "PSF_BOX_H", "PSF_BOX_V", "PSF_TAPS",
+           "CONV_AUTO", "CONV_RUNSUM", "CONV_STENCIL", "library_path"]
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+@dataclass
+class Psf:
+    """Point-spread function: a box of integer length along x or y, or a
+    general odd-sized tap array (device float32, row-major, normalised)."""
+    kind: int
+    length: int = 0
+    taps: torch.Tensor | None = None
+
+    @staticmethod
+    def box(length: int, axis: str = "h") -> "Psf":
+        return Psf(PSF_BOX_H if axis == "h" else PSF_BOX_V, int(length), None)
+
+    @staticmethod
+    def from_taps(taps: torch.Tensor) -> "Psf":
+        if taps.dim() != 2 or taps.dtype != torch.float32 or not taps.is_cuda:
+            raise ValueError("taps must be a 2D float32 device tensor")
+        return Psf(PSF_TAPS, 0, taps.contiguous())
+
+    def c(self) -> _lib.deblur_psf:
+        if self.kind == PSF_TAPS:
+            return _lib.deblur_psf(PSF_TAPS, 0, self.taps.shape[0], self.taps.shape[1], self.taps.data_ptr())
+        return _lib.deblur_psf(self.kind, self.length, 0, 0, None)
+
+
+@dataclass
+class Params:
+    """RRRL parameters (eq. (9)) and the conventions the paper leaves open."""
+    alpha: float = 0.003
+    iters: int = 10
+    eps_data: float = 0.1
+    eps_tv: float = 0.1
+    s_min: float = 1e-12
+    robust: bool = True
+    boundary: int = BC_REPLICATE
+    conv: int = CONV_AUTO
+
+    def c(self) -> _lib.deblur_params:
+        return _lib.deblur_params(self.alpha, self.eps_data, self.eps_tv, self.s_min, int(self.iters),
+                                  int(bool(self.robust)), int(self.boundary), int(self.conv))
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _image(t: torch.Tensor, name: str) -> tuple[int, int, int]:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2:
+        raise ValueError(f"{name} must be a 2D float32 device tensor")
+    if t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    return t.shape[0], t.shape[1], t.stride(0)
+
+
+def _same_layout(a, b, na, nb):
+    if a != b:
+        raise ValueError(f"{na} and {nb} must have the same shape and row pitch")
+
+
+def _workspace(nbytes: int, ref: torch.Tensor, ws: torch.Tensor | None) -> torch.Tensor:
+    if ws is not None:
+        return ws
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=ref.device)
+
+
+def deblur_workspace_bytes(op: int, H: int, W: int, pitch: int, psf: Psf, params: Params | None = None) -> int:
+    cpsf = psf.c()
+    cpar = params.c() if params is not None else None
+    return int(_lib.load().deblur_workspace_bytes(op, H, W, pitch, ctypes.byref(cpsf),
+                                                  ctypes.byref(cpar) if cpar is not None else None))
+
+
+def deblur_wiener(f: torch.Tensor, u0: torch.Tensor, psf: Psf, K: float = 0.01, pos_floor: float = 1.0,
+                  ws: torch.Tensor | None = None) -> torch.Tensor:
+    """u0 <- max(Re IDFT(DFT(f) conj(h^)/(|h^|^2+K)), pos_floor), on f's stream."""
+    lib = _lib.load()
+    H, W, pitch = _image(f, "f")
+    _same_layout((H, W, pitch), _image(u0, "u0"), "f", "u0")
+    cpsf = psf.c()
+    need = lib.deblur_workspace_bytes(_lib.OP_WIENER, H, W, pitch, ctypes.byref(cpsf), None)
+    wst = _workspace(need, f, ws)
+    st = lib.deblur_wiener(f.data_ptr(), u0.data_ptr(), H, W, pitch, ctypes.byref(cpsf), float(K),
+                           float(pos_floor), wst.data_ptr(), wst.numel(), _stream(f))
+    _lib.check(st, "deblur_wiener")
+    return u0
+
+
+def deblur_rrrl_iterate(f: torch.Tensor, u_in: torch.Tensor, u_out: torch.Tensor, psf: Psf, params: Params,
+                        ckpt: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """params.iters RRRL iterations u_in -> u_out (u_in may be u_out).  ckpt
+    (optional, [iters, H, pitch] float32) receives u^0 .. u^{iters-1}."""
+    lib = _lib.load()
+    H, W, pitch = _image(f, "f")
+    _same_layout((H, W, pitch), _image(u_in, "u_in"), "f", "u_in")
+    _same_layout((H, W, pitch), _image(u_out, "u_out"), "f", "u_out")
+    if ckpt is not None:
+        if (not ckpt.is_cuda or ckpt.dtype != torch.float32 or not ckpt.is_contiguous()
+                or ckpt.numel() < params.iters * H * pitch):
+            raise ValueError("ckpt must be a contiguous float32 device tensor of iters*H*pitch elements")
+    cpsf, cpar = psf.c(), params.c()
+    need = lib.deblur_workspace_bytes(_lib.OP_ITERATE, H, W, pitch, ctypes.byref(cpsf), ctypes.byref(cpar))
+    wst = _workspace(need, f, ws)
+    st = lib.deblur_rrrl_iterate(f.data_ptr(), u_in.data_ptr(), u_out.data_ptr(), H, W, pitch,
+                                 ctypes.byref(cpsf), ctypes.byref(cpar),
+                                 ckpt.data_ptr() if ckpt is not None else None,
+                                 wst.data_ptr(), wst.numel(), _stream(f))
+    _lib.check(st, "deblur_rrrl_iterate")
+    return u_out
+
+
+def wr3l(f: torch.Tensor, psf: Psf, K: float = 0.01, params: Params | None = None,
+         pos_floor: float = 1.0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """WR3L (Sec. 3.2): Wiener initialisation, then params.iters RRRL steps."""
+    params = params or Params()
+    u = out if out is not None else torch.empty_like(f)
+    deblur_wiener(f, u, psf, K, pos_floor)
+    return deblur_rrrl_iterate(f, u, u, psf, params)
+
+
+# ----------------------------------------------------------- stage level
+__all__ += ["deblur_taps_bytes", "deblur_compile_taps", "deblur_rrrl_weights", "deblur_rrrl_update"]
+
+
+def deblur_taps_bytes(psf: Psf) -> int:
+    return int(_lib.load().deblur_taps_bytes(ctypes.byref(psf.c())))
+
+
+def deblur_compile_taps(psf: Psf, out: torch.Tensor | None = None, device=None) -> torch.Tensor:
+    """Compiled non-zero tap list of `psf` in a device byte buffer."""
+    lib = _lib.load()
+    cpsf = psf.c()
+    n = lib.deblur_taps_bytes(ctypes.byref(cpsf))
+    if n == 0:
+        raise DeblurError(_lib.DEBLUR_EINVAL, "deblur_taps_bytes")
+    if out is None:
+        dev = device if device is not None else (psf.taps.device if psf.taps is not None else "cuda")
+        out = torch.empty(n, dtype=torch.uint8, device=dev)
+    st = lib.deblur_compile_taps(ctypes.byref(cpsf), out.data_ptr(), out.numel(), _stream(out))
+    _lib.check(st, "deblur_compile_taps")
+    return out
+
+
+def deblur_rrrl_weights(f: torch.Tensor, u: torch.Tensor, qw: torch.Tensor, psf: Psf, taps: torch.Tensor,
+                        params: Params) -> torch.Tensor:
+    """Stage 1 of one RRRL step: qw[..., 0] = q, qw[..., 1] = W ([H, W, 2] float32)."""
+    lib = _lib.load()
+    H, W, pitch = _image(f, "f")
+    _same_layout((H, W, pitch), _image(u, "u"), "f", "u")
+    if qw.shape != (H, W, 2) or not qw.is_contiguous() or qw.dtype != torch.float32:
+        raise ValueError("qw must be a contiguous [H, W, 2] float32 device tensor")
+    cpsf, cpar = psf.c(), params.c()
+    st = lib.deblur_rrrl_weights(f.data_ptr(), u.data_ptr(), qw.data_ptr(), H, W, pitch, ctypes.byref(cpsf),
+                                 taps.data_ptr(), ctypes.byref(cpar), _stream(f))
+    _lib.check(st, "deblur_rrrl_weights")
+    return qw
+
+
+def deblur_rrrl_update(qw: torch.Tensor, u: torch.Tensor, u_out: torch.Tensor, psf: Psf, taps: torch.Tensor,
+                       params: Params, u_copy: torch.Tensor | None = None) -> torch.Tensor:
+    """Stage 2 of one RRRL step: correlation, diffusion term and update."""
+    lib = _lib.load()
+    H, W, pitch = _image(u, "u")
+    _same_layout((H, W, pitch), _image(u_out, "u_out"), "u", "u_out")
+    if u_copy is not None:
+        _same_layout((H, W, pitch), _image(u_copy, "u_copy"), "u", "u_copy")
+    if qw.shape != (H, W, 2) or not qw.is_contiguous() or qw.dtype != torch.float32:
+        raise ValueError("qw must be a contiguous [H, W, 2] float32 device tensor")
+    cpsf, cpar = psf.c(), params.c()
+    st = lib.deblur_rrrl_update(qw.data_ptr(), u.data_ptr(), u_out.data_ptr(),
+                                u_copy.data_ptr() if u_copy is not None else None, H, W, pitch,
+                                ctypes.byref(cpsf), taps.data_ptr(), ctypes.byref(cpar), _stream(u))
+    _lib.check(st, "deblur_rrrl_update")
+    return u_out

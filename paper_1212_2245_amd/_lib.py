@@ -1,0 +1,79 @@
+"""ctypes binding of libdeblur.so: the C ABI of include/deblur.h, argument
+marshalling only (every step of the method runs in the library's kernels)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdeblur.so")
+
+DEBLUR_OK = 0
+DEBLUR_EINVAL = -1
+DEBLUR_EUNSUPPORTED = -2
+DEBLUR_EWORKSPACE = -3
+DEBLUR_EDEVICE = -4
+
+PSF_BOX_H, PSF_BOX_V, PSF_TAPS = 0, 1, 2
+BC_REPLICATE, BC_PERIODIC = 0, 1
+CONV_AUTO, CONV_RUNSUM, CONV_STENCIL = 0, 1, 2
+
+OP_WIENER, OP_ITERATE = 0, 1
+
+
+class deblur_psf(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("length", ctypes.c_int32), ("ph", ctypes.c_int32),
+                ("pw", ctypes.c_int32), ("taps", ctypes.c_void_p)]
+
+
+class deblur_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_float), ("eps_data", ctypes.c_float), ("eps_tv", ctypes.c_float),
+                ("s_min", ctypes.c_float), ("iters", ctypes.c_int32), ("robust", ctypes.c_int32),
+                ("boundary", ctypes.c_int32), ("conv", ctypes.c_int32)]
+
+
+# (name, restype, argtypes) of every exported entry point
+_VP, _SZ, _I32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+_PSF, _PAR = ctypes.POINTER(deblur_psf), ctypes.POINTER(deblur_params)
+SIGNATURES = [
+    ("deblur_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("deblur_version", ctypes.c_int, []),
+    ("deblur_workspace_bytes", _SZ, [_I32, _I32, _I32, _I32, _PSF, _PAR]),
+    ("deblur_wiener", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _PSF, ctypes.c_double, ctypes.c_float,
+                                     _VP, _SZ, _VP]),
+    ("deblur_rrrl_iterate", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP, _SZ, _VP]),
+    ("deblur_taps_bytes", _SZ, [_PSF]),
+    ("deblur_compile_taps", ctypes.c_int, [_PSF, _VP, _SZ, _VP]),
+    ("deblur_rrrl_weights", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _VP, _PAR, _VP]),
+    ("deblur_rrrl_update", ctypes.c_int, [_VP, _VP, _VP, _VP, _I32, _I32, _I32, _PSF, _VP, _PAR, _VP]),
+]
+
+_lib = None
+
+
+class DeblurError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        text = load().deblur_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{where}: {text} (status {status})")
+
+
+def load() -> ctypes.CDLL:
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m "
+                               f"paper_1212_2245_amd.build` (hipcc, gfx950)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(status: int, where: str) -> None:
+    if status != DEBLUR_OK:
+        raise DeblurError(status, where)

@@ -1,0 +1,235 @@
+// Host side of the C ABI declared in include/deblur.h: argument validation,
+// workspace sizing and dispatch to the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "deblur.h"
+#include "psf.hpp"
+
+#include "launch.hpp"
+
+using namespace deblur;
+
+namespace {
+
+constexpr int kMaxFft = 2048;
+constexpr int kMaxTapDim = 65;
+
+bool is_2a3b(int n)
+{
+    if (n < 1) return false;
+    while (n % 3 == 0) n /= 3;
+    while (n % 2 == 0) n /= 2;
+    return n == 1;
+}
+
+// Validates a PSF descriptor and converts it; DEBLUR_OK or an error code.
+int convert_psf(const deblur_psf* psf, PsfDev* out)
+{
+    if (!psf) return DEBLUR_EINVAL;
+    PsfDev d{};
+    d.kind = psf->kind;
+    d.taps = psf->taps;
+    if (psf->kind == DEBLUR_PSF_BOX_H || psf->kind == DEBLUR_PSF_BOX_V) {
+        if (psf->length < 1) return DEBLUR_EINVAL;
+        const int P = psf->length + (psf->length % 2 == 0 ? 1 : 0);
+        if (P > kMaxTapDim) return DEBLUR_EUNSUPPORTED;
+        d.length = psf->length;
+        d.ph = psf->kind == DEBLUR_PSF_BOX_H ? 1 : P;
+        d.pw = psf->kind == DEBLUR_PSF_BOX_H ? P : 1;
+    } else if (psf->kind == DEBLUR_PSF_TAPS) {
+        if (!psf->taps || psf->ph < 1 || psf->pw < 1 || psf->ph % 2 == 0 || psf->pw % 2 == 0)
+            return DEBLUR_EINVAL;
+        if (psf->ph > kMaxTapDim || psf->pw > kMaxTapDim) return DEBLUR_EUNSUPPORTED;
+        d.length = 0;
+        d.ph = psf->ph;
+        d.pw = psf->pw;
+    } else {
+        return DEBLUR_EINVAL;
+    }
+    *out = d;
+    return DEBLUR_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+int check_image(int32_t H, int32_t W, int32_t pitch)
+{
+    if (H < 1 || W < 1 || pitch < W) return DEBLUR_EINVAL;
+    if ((int64_t)H * pitch > (int64_t)1 << 31) return DEBLUR_EUNSUPPORTED;
+    return DEBLUR_OK;
+}
+
+bool wiener_rowwise(const PsfDev& d) { return d.ph == 1; }
+
+int check_wiener(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, PsfDev* d)
+{
+    int s = check_image(H, W, pitch);
+    if (s) return s;
+    if ((s = convert_psf(psf, d))) return s;
+    if (d->ph > H || d->pw > W) return DEBLUR_EINVAL;
+    if (!is_2a3b(W) || W > kMaxFft) return DEBLUR_EUNSUPPORTED;
+    if (!wiener_rowwise(*d) && (!is_2a3b(H) || H > kMaxFft)) return DEBLUR_EUNSUPPORTED;
+    return DEBLUR_OK;
+}
+
+int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, const deblur_params* p, PsfDev* d)
+{
+    int s = check_image(H, W, pitch);
+    if (s) return s;
+    if ((s = convert_psf(psf, d))) return s;
+    if (!p) return DEBLUR_EINVAL;
+    if (!(p->alpha >= 0.0f) || !std::isfinite(p->alpha)) return DEBLUR_EINVAL;
+    if (!(p->eps_data > 0.0f) || !std::isfinite(p->eps_data)) return DEBLUR_EINVAL;
+    if (!(p->eps_tv > 0.0f) || !std::isfinite(p->eps_tv)) return DEBLUR_EINVAL;
+    if (!(p->s_min > 0.0f) || !std::isfinite(p->s_min)) return DEBLUR_EINVAL;
+    if (p->iters < 0 || (p->robust != 0 && p->robust != 1)) return DEBLUR_EINVAL;
+    if (p->boundary != DEBLUR_BC_REPLICATE && p->boundary != DEBLUR_BC_PERIODIC) return DEBLUR_EINVAL;
+    if (p->conv < DEBLUR_CONV_AUTO || p->conv > DEBLUR_CONV_STENCIL) return DEBLUR_EINVAL;
+    if (p->conv == DEBLUR_CONV_RUNSUM && d->kind == DEBLUR_PSF_TAPS) return DEBLUR_EINVAL;
+    if (p->conv == DEBLUR_CONV_RUNSUM) return DEBLUR_EUNSUPPORTED;
+    const int rad = (d->ph - 1) / 2 > (d->pw - 1) / 2 ? (d->ph - 1) / 2 : (d->pw - 1) / 2;
+    if (tap_radius_class(rad) < 0) return DEBLUR_EUNSUPPORTED;
+    if ((d->ph - 1) / 2 > H || (d->pw - 1) / 2 > W) return DEBLUR_EINVAL;
+    return DEBLUR_OK;
+}
+
+IterParams iter_params(const deblur_params* p)
+{
+    IterParams q;
+    q.alpha = p->alpha;
+    q.eps_d2 = p->eps_data * p->eps_data;
+    q.eps_t2 = p->eps_tv * p->eps_tv;
+    q.s_min = p->s_min;
+    q.robust = p->robust;
+    q.bc = p->boundary;
+    return q;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* deblur_status_string(int status)
+{
+    switch (status) {
+        case DEBLUR_OK: return "ok";
+        case DEBLUR_EINVAL: return "invalid argument";
+        case DEBLUR_EUNSUPPORTED: return "unsupported configuration";
+        case DEBLUR_EWORKSPACE: return "workspace missing or too small";
+        case DEBLUR_EDEVICE: return "HIP device or launch failure";
+        default: return "unknown status";
+    }
+}
+
+int deblur_version(void) { return 100; }
+
+size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                              const deblur_params* p)
+{
+    PsfDev d;
+    if (op == 0) {
+        if (check_wiener(H, W, pitch, psf, &d)) return 0;
+        return wiener_ws_bytes(H, W, wiener_rowwise(d));
+    }
+    if (op == 1) {
+        if (check_iterate(H, W, pitch, psf, p, &d)) return 0;
+        return taps_ws_bytes(H, W, pitch, d);
+    }
+    return 0;
+}
+
+int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                  double K, float pos_floor, void* ws, size_t ws_bytes, void* stream)
+{
+    PsfDev d;
+    if (!f || !u0) return DEBLUR_EINVAL;
+    int s = check_wiener(H, W, pitch, psf, &d);
+    if (s) return s;
+    if (!(K > 0.0) || !std::isfinite(K) || !(pos_floor > 0.0f) || !std::isfinite(pos_floor)) return DEBLUR_EINVAL;
+    const size_t img = (size_t)H * pitch * sizeof(float);
+    if (overlaps(f, img, u0, img)) return DEBLUR_EINVAL;
+    const size_t need = wiener_ws_bytes(H, W, wiener_rowwise(d));
+    if (!ws || ws_bytes < need) return DEBLUR_EWORKSPACE;
+    return launch_wiener(f, u0, H, W, pitch, d, K, pos_floor, ws, wiener_rowwise(d),
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t H, int32_t W, int32_t pitch,
+                        const deblur_psf* psf, const deblur_params* p, float* ckpt, void* ws, size_t ws_bytes,
+                        void* stream)
+{
+    PsfDev d;
+    if (!f || !u_in || !u_out) return DEBLUR_EINVAL;
+    int s = check_iterate(H, W, pitch, psf, p, &d);
+    if (s) return s;
+    const size_t img = (size_t)H * pitch * sizeof(float);
+    if (overlaps(f, img, u_out, img) || (u_in != u_out && overlaps(u_in, img, u_out, img))) return DEBLUR_EINVAL;
+    if (ckpt) {
+        const size_t ck = img * (size_t)p->iters;
+        if (overlaps(ckpt, ck, f, img) || overlaps(ckpt, ck, u_in, img) || overlaps(ckpt, ck, u_out, img))
+            return DEBLUR_EINVAL;
+    }
+    const size_t need = taps_ws_bytes(H, W, pitch, d);
+    if (!ws || ws_bytes < need) return DEBLUR_EWORKSPACE;
+    return launch_rrrl_taps(f, u_in, u_out, H, W, pitch, d, iter_params(p), p->iters, ckpt, ws,
+                            reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t deblur_taps_bytes(const deblur_psf* psf)
+{
+    PsfDev d;
+    if (convert_psf(psf, &d)) return 0;
+    return tap_list_bytes(d);
+}
+
+int deblur_compile_taps(const deblur_psf* psf, void* taps_out, size_t taps_bytes, void* stream)
+{
+    PsfDev d;
+    int s = convert_psf(psf, &d);
+    if (s) return s;
+    if (!taps_out || taps_bytes < tap_list_bytes(d)) return DEBLUR_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(taps_out) % 256 != 0) return DEBLUR_EINVAL;
+    launch_compile_taps(d, taps_out, reinterpret_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? DEBLUR_OK : DEBLUR_EDEVICE;
+}
+
+int deblur_rrrl_weights(const float* f, const float* u, float* qw, int32_t H, int32_t W, int32_t pitch,
+                        const deblur_psf* psf, const void* taps, const deblur_params* p, void* stream)
+{
+    PsfDev d;
+    if (!f || !u || !qw || !taps) return DEBLUR_EINVAL;
+    int s = check_iterate(H, W, pitch, psf, p, &d);
+    if (s) return s;
+    const size_t img = (size_t)H * pitch * sizeof(float), q = (size_t)H * W * 2 * sizeof(float);
+    if (overlaps(qw, q, f, img) || overlaps(qw, q, u, img)) return DEBLUR_EINVAL;
+    s = launch_taps_stage1(f, u, qw, H, W, pitch, d, taps, iter_params(p), reinterpret_cast<hipStream_t>(stream));
+    if (s) return DEBLUR_EUNSUPPORTED;
+    return hipGetLastError() == hipSuccess ? DEBLUR_OK : DEBLUR_EDEVICE;
+}
+
+int deblur_rrrl_update(const float* qw, const float* u, float* u_out, float* u_copy, int32_t H, int32_t W,
+                       int32_t pitch, const deblur_psf* psf, const void* taps, const deblur_params* p,
+                       void* stream)
+{
+    PsfDev d;
+    if (!qw || !u || !u_out || !taps) return DEBLUR_EINVAL;
+    int s = check_iterate(H, W, pitch, psf, p, &d);
+    if (s) return s;
+    const size_t img = (size_t)H * pitch * sizeof(float), q = (size_t)H * W * 2 * sizeof(float);
+    if (overlaps(u, img, u_out, img) || overlaps(qw, q, u_out, img)) return DEBLUR_EINVAL;
+    if (u_copy && (overlaps(u_copy, img, u, img) || overlaps(u_copy, img, u_out, img) || overlaps(u_copy, img, qw, q)))
+        return DEBLUR_EINVAL;
+    s = launch_taps_stage2(qw, u, u_out, u_copy, H, W, pitch, d, taps, iter_params(p),
+                           reinterpret_cast<hipStream_t>(stream));
+    if (s) return DEBLUR_EUNSUPPORTED;
+    return hipGetLastError() == hipSuccess ? DEBLUR_OK : DEBLUR_EDEVICE;
+}
+
+}  // extern "C"

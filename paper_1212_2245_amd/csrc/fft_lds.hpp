@@ -1,0 +1,140 @@
+// Mixed-radix (2, 3, 4, 8) Stockham FFT of a batch of rows held in LDS.
+//
+// The paper uses its own power-of-two FFT with twiddles precomputed once
+// (Sec. 4.1).  Here the transform lengths are n = 2^a 3^b (image sides such as
+// 192, 384, 768 occur in the batched workload), the butterflies run in FP32
+// in LDS and the twiddles exp(-2 pi i m / n) are generated in FP64 per
+// workgroup and rounded once to FP32.
+//
+// Stockham autosort formulation: pass p with radix R and stride Ns (product of
+// the radices already applied) maps butterfly j (0 <= j < n/R), k = j mod Ns,
+//   inputs   x[j + r n/R],  r = 0..R-1
+//   twiddle  x_r *= w_n^(k r n/(Ns R))
+//   outputs  y[(j - k) R + k + r Ns] = DFT_R(x)_r
+// and leaves the result in natural order after the last pass.  Forward
+// transforms only (sign -1); inverses use conj(FFT(conj(X)))/n.
+#pragma once
+
+#include "common.hpp"
+
+namespace deblur {
+
+struct FftPlan {
+    int n;
+    int npass;
+    int radix[16];
+};
+
+DEBLUR_DEV float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+DEBLUR_DEV float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+DEBLUR_DEV float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+DEBLUR_DEV float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i
+DEBLUR_DEV float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
+
+// Twiddle table tw[m] = exp(-2 pi i m / n), m < n, computed in FP64.
+DEBLUR_DEV void fft_twiddles(float2* tw, int n)
+{
+    for (int m = threadIdx.x; m < n; m += blockDim.x) {
+        double s, c;
+        sincospi(2.0 * (double)m / (double)n, &s, &c);
+        tw[m] = make_float2((float)c, (float)-s);
+    }
+}
+
+template <int R>
+DEBLUR_DEV void dft_small(float2* v)
+{
+    if constexpr (R == 2) {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 3) {
+        const float c = 0.86602540378443864676f;  // sqrt(3)/2
+        const float2 t1 = cadd(v[1], v[2]);
+        const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+        const float2 d = csub(v[1], v[2]);
+        const float2 t3 = make_float2(c * d.y, -c * d.x);  // -i * c * (v1 - v2)
+        v[0] = cadd(v[0], t1);
+        v[1] = cadd(t2, t3);
+        v[2] = csub(t2, t3);
+    } else if constexpr (R == 4) {
+        const float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const float2 s13 = cadd(v[1], v[3]), d13 = cmul_mi(csub(v[1], v[3]));
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    } else if constexpr (R == 8) {
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<4>(e);
+        dft_small<4>(o);
+        const float r = 0.70710678118654752440f;
+        const float2 w1 = make_float2(r * (o[1].x + o[1].y), r * (o[1].y - o[1].x));   // (1-i)/sqrt2
+        const float2 w2 = cmul_mi(o[2]);                                               // -i
+        const float2 w3 = make_float2(r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)); // (-1-i)/sqrt2
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], w1);
+        v[5] = csub(e[1], w1);
+        v[2] = cadd(e[2], w2);
+        v[6] = csub(e[2], w2);
+        v[3] = cadd(e[3], w3);
+        v[7] = csub(e[3], w3);
+    }
+}
+
+template <int R>
+DEBLUR_DEV void fft_pass(const float2* __restrict__ src, float2* __restrict__ dst, int nb,
+                         int n, int Ns, const float2* __restrict__ tw)
+{
+    const int m = n / R;
+    const int tstride = n / (Ns * R);
+    for (int t = 0; t < nb; ++t) {
+        const float2* s = src + t * n;
+        float2* d = dst + t * n;
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            const int k = j % Ns;
+            float2 v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = s[j + r * m];
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * tstride]);
+            }
+            dft_small<R>(v);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) d[base + r * Ns] = v[r];
+        }
+    }
+}
+
+// Forward FFT of nb rows of length p.n stored contiguously in `a`; `b` is a
+// scratch buffer of the same size.  Returns the buffer holding the result.
+// Must be called by all threads of the block; ends with a barrier.
+DEBLUR_DEV float2* fft_rows(float2* a, float2* b, int nb, const FftPlan& p, const float2* tw)
+{
+    int Ns = 1;
+    for (int q = 0; q < p.npass; ++q) {
+        const int R = p.radix[q];
+        switch (R) {
+            case 2: fft_pass<2>(a, b, nb, p.n, Ns, tw); break;
+            case 3: fft_pass<3>(a, b, nb, p.n, Ns, tw); break;
+            case 4: fft_pass<4>(a, b, nb, p.n, Ns, tw); break;
+            default: fft_pass<8>(a, b, nb, p.n, Ns, tw); break;
+        }
+        __syncthreads();
+        float2* t = a;
+        a = b;
+        b = t;
+        Ns *= R;
+    }
+    return a;
+}
+
+}  // namespace deblur

@@ -1,0 +1,34 @@
+// Host-side launchers of the gfx950 kernels, called by the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "psf.hpp"
+
+namespace deblur {
+
+// Per-iteration constants of the RRRL update (squares of the penaliser
+// epsilons are precomputed).
+struct IterParams {
+    float alpha, eps_d2, eps_t2, s_min;
+    int robust, bc;
+};
+
+size_t wiener_ws_bytes(int H, int W, bool rowwise);
+int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
+                  float pos_floor, void* ws, bool rowwise, hipStream_t st);
+
+int tap_radius_class(int rad);
+size_t taps_ws_bytes(int H, int W, int pitch, const PsfDev& psf);
+size_t tap_list_bytes(const PsfDev& psf);
+void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st);
+int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, int pitch, const PsfDev& psf,
+                       const void* list, const IterParams& p, hipStream_t st);
+int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
+                       const PsfDev& psf, const void* list, const IterParams& p, hipStream_t st);
+int launch_rrrl_taps(const float* f, const float* u_in, float* u_out, int H, int W, int pitch, const PsfDev& psf,
+                     const IterParams& p, int iters, float* ckpt, void* ws, hipStream_t st);
+
+}  // namespace deblur

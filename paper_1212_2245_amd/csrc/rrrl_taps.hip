@@ -1,0 +1,289 @@
+// RRRL iteration (Sec. 2.3, eqs. (9)-(12)) for a general PSF given as taps,
+// by direct summation in the spatial domain (Sec. 4.1, 4.3) on LDS tiles.
+//
+// One iteration = two kernels:
+//   stage 1: s = A u (blur), W = Phi'(r_f(s)), q = W f / s   -> plane (q, W)
+//   stage 2: N1 = B q, N2 = B W (correlation with h, i.e. convolution with
+//            h*), TV term D(u), update u' = u (N1 + a[D]_+) / (N2 - a[D]_-)
+// A and B use constant or periodic continuation at the border (Sec. 4.2);
+// the diffusion term always has zero flux across the border.
+//
+// Tiles are 64 columns wide (one wavefront: lane = column, so LDS reads are
+// consecutive and conflict-free) and TH rows tall; each of the 4 wavefronts
+// of a workgroup owns TH/4 consecutive rows, so one LDS address computation
+// per tap serves TH/4 reads with immediate offsets.  Only non-zero taps are
+// visited (a compacted tap list built on the device from the PSF).
+#include "common.hpp"
+#include "launch.hpp"
+#include "psf.hpp"
+
+namespace deblur {
+
+// Compacted list of the non-zero taps, row-major order: {dy, dx, w bits, 0},
+// count stored in list_count[0].  Single workgroup.
+__global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restrict__ list,
+                                                      int* __restrict__ list_count)
+{
+    __shared__ int counts[256];
+    const int n = psf.ph * psf.pw;
+    const int per = (n + 255) / 256;
+    const int b = threadIdx.x * per, e = min(n, b + per);
+    int c = 0;
+    for (int k = b; k < e; ++k) c += psf_weight(psf, k / psf.pw, k % psf.pw) != 0.0f;
+    counts[threadIdx.x] = c;
+    __syncthreads();
+    // inclusive Hillis-Steele scan
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = threadIdx.x >= off ? counts[threadIdx.x - off] : 0;
+        __syncthreads();
+        counts[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int o = counts[threadIdx.x] - c;
+    const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
+    for (int k = b; k < e; ++k) {
+        const int j = k / psf.pw, i = k % psf.pw;
+        const float w = psf_weight(psf, j, i);
+        if (w != 0.0f) list[o++] = make_int4(j - cy, i - cx, __float_as_int(w), 0);
+    }
+    if (threadIdx.x == 255) list_count[0] = counts[255];
+}
+
+template <int RAD, int TH>
+__global__ void __launch_bounds__(256) rrrl_taps_stage1(const float* __restrict__ u, const float* __restrict__ f,
+                                                        float2* __restrict__ qw, int H, int W, int pitch,
+                                                        const int4* __restrict__ taps,
+                                                        const int* __restrict__ ntaps, IterParams p)
+{
+    constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / 4;
+    __shared__ float tile[LH * LW];
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < LH * LW; idx += 256) {
+        const int ly = idx / LW, lx = idx - ly * LW;
+        const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
+        tile[idx] = u[(size_t)gy * pitch + gx];
+    }
+    __syncthreads();
+    const int tx = tid & 63, ty = tid >> 6;
+    float acc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] = 0.0f;
+    const float* base = tile + (ty * R + RAD) * LW + tx + RAD;
+    const int n = ntaps[0];
+    for (int t = 0; t < n; ++t) {
+        const int4 e = taps[t];
+        const float w = __int_as_float(e.z);
+        const float* s = base - e.x * LW - e.y;   // A: E(u)(x - d)
+#pragma unroll
+        for (int i = 0; i < R; ++i) acc[i] = fmaf(w, s[i * LW], acc[i]);
+    }
+    const int x = x0 + tx;
+    if (x >= W) return;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int y = y0 + ty * R + i;
+        if (y >= H) break;
+        const float s = fmaxf(acc[i], p.s_min);
+        const float fv = f[(size_t)y * pitch + x];
+        const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
+        const float q = wt * fmaxf(fv, 0.0f) / s;
+        qw[(size_t)y * W + x] = make_float2(q, wt);
+    }
+}
+
+template <int RAD, int TH>
+__global__ void __launch_bounds__(256) rrrl_taps_stage2(const float2* __restrict__ qw, const float* __restrict__ u,
+                                                        float* __restrict__ u_next, float* __restrict__ ckpt,
+                                                        int H, int W, int pitch, const int4* __restrict__ taps,
+                                                        const int* __restrict__ ntaps, IterParams p)
+{
+    constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / 4;
+    constexpr int UW = TW + 4, UH = TH + 4, GW = TW + 2, GH = TH + 2;
+    __shared__ float2 qt[LH * LW];
+    __shared__ float ut[UH * UW];
+    __shared__ float gt[GH * GW];
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < LH * LW; idx += 256) {
+        const int ly = idx / LW, lx = idx - ly * LW;
+        const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
+        qt[idx] = qw[(size_t)gy * W + gx];
+    }
+    for (int idx = tid; idx < UH * UW; idx += 256) {
+        const int ly = idx / UW, lx = idx - ly * UW;
+        ut[idx] = u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
+    }
+    __syncthreads();
+    // diffusivity g = Psi'(|grad u|^2) by central differences at pixels
+    for (int idx = tid; idx < GH * GW; idx += 256) {
+        const int a = idx / GW, b = idx - a * GW;
+        const float gx = 0.5f * (ut[(a + 1) * UW + b + 2] - ut[(a + 1) * UW + b]);
+        const float gy = 0.5f * (ut[(a + 2) * UW + b + 1] - ut[a * UW + b + 1]);
+        gt[idx] = pen_deriv(gx * gx + gy * gy, p.eps_t2);
+    }
+    const int tx = tid & 63, ty = tid >> 6;
+    float n1[R], n2[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) n1[i] = n2[i] = 0.0f;
+    const float2* base = qt + (ty * R + RAD) * LW + tx + RAD;
+    const int n = ntaps[0];
+    for (int t = 0; t < n; ++t) {
+        const int4 e = taps[t];
+        const float w = __int_as_float(e.z);
+        const float2* s = base + e.x * LW + e.y;   // B: E(q, W)(x + d)
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const float2 v = s[i * LW];
+            n1[i] = fmaf(w, v.x, n1[i]);
+            n2[i] = fmaf(w, v.y, n2[i]);
+        }
+    }
+    __syncthreads();   // gt complete
+    const int x = x0 + tx;
+    if (x >= W) return;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int ry = ty * R + i;
+        const int y = y0 + ry;
+        if (y >= H) break;
+        const int c = (ry + 2) * UW + tx + 2;
+        const int cg = (ry + 1) * GW + tx + 1;
+        const float up = ut[c], gp = gt[cg];
+        // neighbours outside the image read the clamped value u_p: zero flux
+        const float D = 0.5f * (gp + gt[cg - GW]) * (ut[c - UW] - up)
+                      + 0.5f * (gp + gt[cg + GW]) * (ut[c + UW] - up)
+                      + 0.5f * (gp + gt[cg - 1]) * (ut[c - 1] - up)
+                      + 0.5f * (gp + gt[cg + 1]) * (ut[c + 1] - up);
+        const float num = n1[i] + p.alpha * fmaxf(D, 0.0f);
+        const float den = n2[i] - p.alpha * fminf(D, 0.0f);
+        const size_t o = (size_t)y * pitch + x;
+        if (ckpt) ckpt[o] = up;
+        u_next[o] = up * num / den;
+    }
+}
+
+// ------------------------------------------------------------ host launchers
+int tap_radius_class(int rad)
+{
+    if (rad <= 4) return 4;
+    if (rad <= 8) return 8;
+    if (rad <= 16) return 16;
+    if (rad <= 32) return 32;
+    return -1;
+}
+
+template <int RAD>
+static void launch_stage1_t(const float* f, const float* u, float2* qw, int H, int W, int pitch,
+                            const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+{
+    constexpr int TH1 = RAD >= 32 ? 32 : 64;
+    const dim3 g1((W + 63) / 64, (H + TH1 - 1) / TH1);
+    hipLaunchKernelGGL((rrrl_taps_stage1<RAD, TH1>), g1, dim3(256), 0, st, u, f, qw, H, W, pitch, taps, nt, p);
+}
+
+template <int RAD>
+static void launch_stage2_t(const float2* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
+                            const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+{
+    constexpr int TH2 = 32;
+    const dim3 g2((W + 63) / 64, (H + TH2 - 1) / TH2);
+    hipLaunchKernelGGL((rrrl_taps_stage2<RAD, TH2>), g2, dim3(256), 0, st, qw, u, un, ckpt, H, W, pitch, taps,
+                       nt, p);
+}
+
+size_t tap_list_bytes(const PsfDev& psf) { return 256 + 16 * (size_t)psf.ph * psf.pw; }
+
+void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st)
+{
+    unsigned char* w8 = reinterpret_cast<unsigned char*>(list);
+    hipLaunchKernelGGL(build_tap_list, dim3(1), dim3(256), 0, st, psf, reinterpret_cast<int4*>(w8 + 256),
+                       reinterpret_cast<int*>(w8));
+}
+
+static int psf_radius_class(const PsfDev& psf)
+{
+    return tap_radius_class(max((psf.ph - 1) / 2, (psf.pw - 1) / 2));
+}
+
+int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, int pitch, const PsfDev& psf,
+                       const void* list, const IterParams& p, hipStream_t st)
+{
+    const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
+    const int* nt = reinterpret_cast<const int*>(w8);
+    const int4* taps = reinterpret_cast<const int4*>(w8 + 256);
+    float2* q2 = reinterpret_cast<float2*>(qw);
+    switch (psf_radius_class(psf)) {
+        case 4: launch_stage1_t<4>(f, u, q2, H, W, pitch, taps, nt, p, st); break;
+        case 8: launch_stage1_t<8>(f, u, q2, H, W, pitch, taps, nt, p, st); break;
+        case 16: launch_stage1_t<16>(f, u, q2, H, W, pitch, taps, nt, p, st); break;
+        case 32: launch_stage1_t<32>(f, u, q2, H, W, pitch, taps, nt, p, st); break;
+        default: return -2;
+    }
+    return 0;
+}
+
+int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
+                       const PsfDev& psf, const void* list, const IterParams& p, hipStream_t st)
+{
+    const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
+    const int* nt = reinterpret_cast<const int*>(w8);
+    const int4* taps = reinterpret_cast<const int4*>(w8 + 256);
+    const float2* q2 = reinterpret_cast<const float2*>(qw);
+    switch (psf_radius_class(psf)) {
+        case 4: launch_stage2_t<4>(q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 8: launch_stage2_t<8>(q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 16: launch_stage2_t<16>(q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 32: launch_stage2_t<32>(q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        default: return -2;
+    }
+    return 0;
+}
+
+size_t taps_ws_bytes(int H, int W, int pitch, const PsfDev& psf)
+{
+    const size_t lr = (tap_list_bytes(psf) + 255) & ~(size_t)255;
+    const size_t qw = ((size_t)H * W * sizeof(float2) + 255) & ~(size_t)255;
+    const size_t pl = ((size_t)H * pitch * sizeof(float) + 255) & ~(size_t)255;
+    return lr + qw + 2 * pl;
+}
+
+int launch_rrrl_taps(const float* f, const float* u_in, float* u_out, int H, int W, int pitch, const PsfDev& psf,
+                     const IterParams& p, int iters, float* ckpt, void* ws, hipStream_t st)
+{
+    if (psf_radius_class(psf) < 0) return -2;
+    unsigned char* w8 = reinterpret_cast<unsigned char*>(ws);
+    const size_t lr = (tap_list_bytes(psf) + 255) & ~(size_t)255;
+    float* qw = reinterpret_cast<float*>(w8 + lr);
+    const size_t qwb = ((size_t)H * W * sizeof(float2) + 255) & ~(size_t)255;
+    float* t0 = reinterpret_cast<float*>(w8 + lr + qwb);
+    const size_t pl = ((size_t)H * pitch * sizeof(float) + 255) & ~(size_t)255;
+    float* t1 = reinterpret_cast<float*>(w8 + lr + qwb + pl);
+
+    launch_compile_taps(psf, ws, st);
+    if (iters == 0) {
+        if (u_out != u_in)
+            (void)hipMemcpy2DAsync(u_out, pitch * sizeof(float), u_in, pitch * sizeof(float), W * sizeof(float), H,
+                                   hipMemcpyDeviceToDevice, st);
+        return hipGetLastError() == hipSuccess ? 0 : -4;
+    }
+    // Ping-pong so that the last iteration writes u_out; iteration k writes
+    // u_out when (iters-1-k) is even.  If u_in aliases u_out and the first
+    // write would land there, start from a copy.
+    const float* src = u_in;
+    if (u_in == u_out && ((iters - 1) % 2 == 0)) {
+        (void)hipMemcpy2DAsync(t1, pitch * sizeof(float), u_in, pitch * sizeof(float), W * sizeof(float), H,
+                               hipMemcpyDeviceToDevice, st);
+        src = t1;
+    }
+    for (int k = 0; k < iters; ++k) {
+        float* dst = ((iters - 1 - k) % 2 == 0) ? u_out : t0;
+        float* ck = ckpt ? ckpt + (size_t)k * H * pitch : nullptr;
+        launch_taps_stage1(f, src, qw, H, W, pitch, psf, ws, p, st);
+        launch_taps_stage2(qw, src, dst, ck, H, W, pitch, psf, ws, p, st);
+        src = dst;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+}  // namespace deblur

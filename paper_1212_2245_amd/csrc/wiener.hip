@@ -1,0 +1,296 @@
+// Wiener filter initialisation of WR3L (Sec. 2.1 eq. (2), Sec. 3.2).
+//
+//   u^0 = max( Re IDFT( DFT(f) * M ), pos_floor ),  M = conj(h^) / (|h^|^2 + K)
+//
+// with periodic continuation (Fourier domain, Sec. 4.2).  M is formed in FP64
+// (the division by |h^|^2 + K with small K) and stored as complex64; the
+// transforms run in FP32 in LDS.
+//
+// Two paths:
+//  * PSF supported on one row (horizontal motion): the 2D filter reduces to a
+//    1D filter along every row (Sec. 4.3, non-uniform linear motion).  One
+//    fused kernel per pair of rows: pack z = f_a + i f_b, FFT, multiply by M
+//    (Hermitian, so both real rows stay separated), inverse FFT, floor, store.
+//  * general PSF: half-spectrum 2D real FFT.  Row pass (pairs of rows packed
+//    as one complex row, unpacked to two half spectra), column pass (FFT,
+//    multiply by M, inverse FFT), inverse row pass (Hermitian extension,
+//    rows packed again, inverse FFT, floor).
+#include "fft_lds.hpp"
+#include "launch.hpp"
+#include "psf.hpp"
+
+namespace deblur {
+
+// M(k) = conj(h^(k)) / (|h^(k)|^2 + K) for a PSF on one row, k < n.
+__global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double K, float2* __restrict__ M)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int cx = (psf.pw - 1) / 2;
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < psf.pw; ++i) {
+        const double w = (double)psf_weight(psf, 0, i);
+        if (w == 0.0) continue;
+        long long m = ((long long)k * (long long)(i - cx)) % n;
+        if (m < 0) m += n;
+        double s, c;
+        sincospi(2.0 * (double)m / (double)n, &s, &c);
+        re += w * c;       // exp(-2 pi i k d / n)
+        im -= w * s;
+    }
+    const double den = re * re + im * im + K;
+    M[k] = make_float2((float)(re / den), (float)(-im / den));
+}
+
+// One workgroup per `nb` row pairs; LDS: two ping-pong buffers of nb*n
+// complex plus the twiddle table.
+__global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict__ f, float* __restrict__ u,
+                                                         int H, int W, int pitch, int nb, FftPlan plan,
+                                                         const float2* __restrict__ M, float pos_floor)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* tw = reinterpret_cast<float2*>(smem_raw);
+    float2* a = tw + W;
+    float2* b = a + nb * W;
+    fft_twiddles(tw, W);
+
+    const int pair0 = blockIdx.x * nb;
+    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+        const int t = idx / W, x = idx - t * W;
+        const int ya = 2 * (pair0 + t), yb = ya + 1;
+        const float va = ya < H ? f[(size_t)ya * pitch + x] : 0.0f;
+        const float vb = yb < H ? f[(size_t)yb * pitch + x] : 0.0f;
+        a[idx] = make_float2(va, vb);
+    }
+    __syncthreads();
+    float2* X = fft_rows(a, b, nb, plan, tw);
+    float2* Y = X == a ? b : a;
+    // Y = conj(X * M): the inverse transform is conj(FFT(conj(.)))/n
+    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+        const int x = idx % W;
+        X[idx] = cconj(cmul(X[idx], M[x]));
+    }
+    __syncthreads();
+    X = fft_rows(X, Y, nb, plan, tw);
+    const float inv = 1.0f / (float)W;
+    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+        const int t = idx / W, x = idx - t * W;
+        const int ya = 2 * (pair0 + t), yb = ya + 1;
+        const float2 z = X[idx];
+        if (ya < H) u[(size_t)ya * pitch + x] = fmaxf(z.x * inv, pos_floor);
+        if (yb < H) u[(size_t)yb * pitch + x] = fmaxf(-z.y * inv, pos_floor);
+    }
+}
+
+// M(ky, kx) for kx <= W/2, stored row-major with row pitch W/2+1.  One
+// workgroup per column kx: G_j(kx) = sum_i h[j][i] w_W^(kx (i-cx)) first,
+// then h^(ky,kx) = sum_j G_j(kx) w_H^(ky (j-cy)) with an FP64 twiddle table.
+__global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, double K, float2* __restrict__ M)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double2* twh = reinterpret_cast<double2*>(smem_raw);  // H entries
+    double2* G = twh + H;                                  // ph entries
+    const int kx = blockIdx.x;
+    const int Wh = W / 2 + 1;
+    const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
+    for (int m = threadIdx.x; m < H; m += blockDim.x) {
+        double s, c;
+        sincospi(2.0 * (double)m / (double)H, &s, &c);
+        twh[m] = make_double2(c, -s);
+    }
+    for (int j = threadIdx.x; j < psf.ph; j += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < psf.pw; ++i) {
+            const double w = (double)psf_weight(psf, j, i);
+            if (w == 0.0) continue;
+            long long m = ((long long)kx * (long long)(i - cx)) % W;
+            if (m < 0) m += W;
+            double s, c;
+            sincospi(2.0 * (double)m / (double)W, &s, &c);
+            re += w * c;
+            im -= w * s;
+        }
+        G[j] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int ky = threadIdx.x; ky < H; ky += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < psf.ph; ++j) {
+            int m = (int)(((long long)ky * (long long)(j - cy)) % H);
+            if (m < 0) m += H;
+            const double2 t = twh[m], g = G[j];
+            re += g.x * t.x - g.y * t.y;
+            im += g.x * t.y + g.y * t.x;
+        }
+        const double den = re * re + im * im + K;
+        M[(size_t)ky * Wh + kx] = make_float2((float)(re / den), (float)(-im / den));
+    }
+}
+
+// Row pass: rows (2p, 2p+1) packed as z = f_a + i f_b, FFT along x, unpacked
+// into the half spectra F_a(k), F_b(k), k <= W/2, written to S (row pitch W/2+1).
+__global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__ f, float2* __restrict__ S,
+                                                       int H, int W, int pitch, int nb, FftPlan plan)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* tw = reinterpret_cast<float2*>(smem_raw);
+    float2* a = tw + W;
+    float2* b = a + nb * W;
+    fft_twiddles(tw, W);
+    const int pair0 = blockIdx.x * nb;
+    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+        const int t = idx / W, x = idx - t * W;
+        const int ya = 2 * (pair0 + t), yb = ya + 1;
+        const float va = ya < H ? f[(size_t)ya * pitch + x] : 0.0f;
+        const float vb = yb < H ? f[(size_t)yb * pitch + x] : 0.0f;
+        a[idx] = make_float2(va, vb);
+    }
+    __syncthreads();
+    const float2* Z = fft_rows(a, b, nb, plan, tw);
+    const int Wh = W / 2 + 1;
+    for (int idx = threadIdx.x; idx < nb * Wh; idx += blockDim.x) {
+        const int t = idx / Wh, k = idx - t * Wh;
+        const int ya = 2 * (pair0 + t), yb = ya + 1;
+        const float2 zk = Z[t * W + k];
+        const float2 zm = Z[t * W + (k == 0 ? 0 : W - k)];
+        // F_a = (Z(k) + conj Z(-k))/2,  F_b = (Z(k) - conj Z(-k))/(2i)
+        if (ya < H) S[(size_t)ya * Wh + k] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        if (yb < H) S[(size_t)yb * Wh + k] = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+    }
+}
+
+// Column pass: for `cb` consecutive columns kx of S: FFT along y, multiply by
+// M, inverse FFT along y (scaled by 1/H), written back in place.
+__global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const float2* __restrict__ M,
+                                                   int H, int W, int cb, FftPlan plan)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* tw = reinterpret_cast<float2*>(smem_raw);
+    float2* a = tw + H;
+    float2* b = a + cb * H;
+    fft_twiddles(tw, H);
+    const int Wh = W / 2 + 1;
+    const int c0 = blockIdx.x * cb;
+    for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
+        const int y = idx / cb, c = idx - y * cb;
+        a[c * H + y] = (c0 + c < Wh) ? S[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+    }
+    __syncthreads();
+    float2* X = fft_rows(a, b, cb, plan, tw);
+    float2* Y = X == a ? b : a;
+    for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
+        const int c = idx / H, y = idx - c * H;
+        const float2 m = (c0 + c < Wh) ? M[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+        X[idx] = cconj(cmul(X[idx], m));
+    }
+    __syncthreads();
+    X = fft_rows(X, Y, cb, plan, tw);
+    const float inv = 1.0f / (float)H;
+    for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
+        const int y = idx / cb, c = idx - y * cb;
+        if (c0 + c < Wh) {
+            const float2 z = X[c * H + y];
+            S[(size_t)y * Wh + c0 + c] = make_float2(z.x * inv, -z.y * inv);
+        }
+    }
+}
+
+// Inverse row pass: U_a, U_b extended to full length by Hermitian symmetry,
+// packed as Z = U_a + i U_b, inverse FFT (scaled by 1/W): u_a = Re, u_b = Im;
+// non-positive values replaced by pos_floor (Sec. 3.2).
+__global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict__ S, float* __restrict__ u,
+                                                       int H, int W, int pitch, int nb, FftPlan plan,
+                                                       float pos_floor)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* tw = reinterpret_cast<float2*>(smem_raw);
+    float2* a = tw + W;
+    float2* b = a + nb * W;
+    fft_twiddles(tw, W);
+    const int Wh = W / 2 + 1;
+    const int pair0 = blockIdx.x * nb;
+    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+        const int t = idx / W, k = idx - t * W;
+        const int ya = 2 * (pair0 + t), yb = ya + 1;
+        const bool lo = k < Wh;
+        const int kk = lo ? k : W - k;
+        float2 ua = ya < H ? S[(size_t)ya * Wh + kk] : make_float2(0.0f, 0.0f);
+        float2 ub = yb < H ? S[(size_t)yb * Wh + kk] : make_float2(0.0f, 0.0f);
+        if (!lo) {
+            ua = cconj(ua);
+            ub = cconj(ub);
+        }
+        // conj(U_a + i U_b) for the inverse via the forward transform
+        a[idx] = make_float2(ua.x - ub.y, -(ua.y + ub.x));
+    }
+    __syncthreads();
+    const float2* Z = fft_rows(a, b, nb, plan, tw);
+    const float inv = 1.0f / (float)W;
+    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+        const int t = idx / W, x = idx - t * W;
+        const int ya = 2 * (pair0 + t), yb = ya + 1;
+        const float2 z = Z[idx];
+        if (ya < H) u[(size_t)ya * pitch + x] = fmaxf(z.x * inv, pos_floor);
+        if (yb < H) u[(size_t)yb * pitch + x] = fmaxf(-z.y * inv, pos_floor);
+    }
+}
+
+// ------------------------------------------------------------ host launchers
+static FftPlan make_plan(int n)
+{
+    FftPlan p{};
+    p.n = n;
+    int m = n;
+    while (m % 3 == 0) {
+        p.radix[p.npass++] = 3;
+        m /= 3;
+    }
+    while (m % 8 == 0) {
+        p.radix[p.npass++] = 8;
+        m /= 8;
+    }
+    if (m == 4) p.radix[p.npass++] = 4;
+    if (m == 2) p.radix[p.npass++] = 2;
+    return p;
+}
+
+size_t wiener_ws_bytes(int H, int W, bool rowwise)
+{
+    if (rowwise) return (size_t)W * sizeof(float2);
+    const size_t Wh = (size_t)W / 2 + 1;
+    return 2 * (size_t)H * Wh * sizeof(float2);  // M and S
+}
+
+int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
+                  float pos_floor, void* ws, bool rowwise, hipStream_t st)
+{
+    if (rowwise) {
+        float2* M = reinterpret_cast<float2*>(ws);
+        hipLaunchKernelGGL(wiener_mult_1d, dim3((W + 255) / 256), dim3(256), 0, st, psf, W, K, M);
+        const int pairs = (H + 1) / 2;
+        const int nb = W >= 1024 ? 1 : 1024 / W;
+        const size_t lds = (size_t)(W + 2 * nb * W) * sizeof(float2);
+        hipLaunchKernelGGL(wiener_rows_fused, dim3((pairs + nb - 1) / nb), dim3(256), lds, st, f, u, H, W,
+                           pitch, nb, make_plan(W), (const float2*)M, pos_floor);
+    } else {
+        const int Wh = W / 2 + 1;
+        float2* M = reinterpret_cast<float2*>(ws);
+        float2* S = M + (size_t)H * Wh;
+        hipLaunchKernelGGL(wiener_mult_2d, dim3(Wh), dim3(256), (size_t)(H + psf.ph) * sizeof(double2), st,
+                           psf, H, W, K, M);
+        const int pairs = (H + 1) / 2;
+        const int nb = W >= 1024 ? 1 : 1024 / W;
+        const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(float2);
+        hipLaunchKernelGGL(wiener_rows_fwd, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st, f, S, H, W,
+                           pitch, nb, make_plan(W));
+        const int cb = H >= 2048 ? 1 : (2048 / H > 8 ? 8 : 2048 / H);
+        const size_t lds_c = (size_t)(H + 2 * cb * H) * sizeof(float2);
+        hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), lds_c, st, S, (const float2*)M,
+                           H, W, cb, make_plan(H));
+        hipLaunchKernelGGL(wiener_rows_inv, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st,
+                           (const float2*)S, u, H, W, pitch, nb, make_plan(W), pos_floor);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+}  // namespace deblur

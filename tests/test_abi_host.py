@@ -1,0 +1,137 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/deblur.h declares, and rejects invalid arguments
+before touching the device.  Only error paths are exercised here (every
+call below fails validation, so nothing is enqueued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1212_2245_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "deblur.h")
+
+# fake, far-apart device addresses: only used on paths that fail validation
+F, U, V, CK, WS = 0x10000000, 0x20000000, 0x30000000, 0x40000000, 0x50000000
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(deblur_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1212_2245_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert {"deblur_wiener", "deblur_rrrl_iterate", "deblur_workspace_bytes"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert {n for n, _, _ in _lib.SIGNATURES} == set(names)
+
+
+def test_status_strings(lib):
+    for s in (0, -1, -2, -3, -4):
+        assert lib.deblur_status_string(s)
+    assert lib.deblur_status_string(7) == b"unknown status"
+    assert lib.deblur_version() >= 100
+
+
+def box(L=15, kind=_lib.PSF_BOX_H):
+    return _lib.deblur_psf(kind, L, 0, 0, None)
+
+
+def taps(ph, pw, ptr=0x60000000):
+    return _lib.deblur_psf(_lib.PSF_TAPS, 0, ph, pw, ptr)
+
+
+def params(**kw):
+    d = dict(alpha=0.003, eps_data=0.1, eps_tv=0.1, s_min=1e-12, iters=3, robust=1, boundary=0, conv=0)
+    d.update(kw)
+    return _lib.deblur_params(*[d[k] for k, _ in _lib.deblur_params._fields_])
+
+
+def wiener(lib, f=F, u=U, H=256, W=256, pitch=256, psf=None, K=0.01, floor=1.0, ws=None, wsb=0):
+    psf = psf if psf is not None else box()
+    return lib.deblur_wiener(f, u, H, W, pitch, ctypes.byref(psf), K, floor, ws, wsb, None)
+
+
+def iterate(lib, f=F, ui=U, uo=V, H=64, W=64, pitch=64, psf=None, p=None, ck=None, ws=None, wsb=0):
+    psf = psf if psf is not None else box()
+    p = p if p is not None else params()
+    return lib.deblur_rrrl_iterate(f, ui, uo, H, W, pitch, ctypes.byref(psf), ctypes.byref(p), ck, ws, wsb,
+                                   None)
+
+
+def test_workspace_bytes(lib):
+    p = params()
+    assert lib.deblur_workspace_bytes(0, 256, 256, 256, ctypes.byref(box()), None) > 0
+    assert lib.deblur_workspace_bytes(0, 256, 256, 256, ctypes.byref(taps(31, 31)), None) > 0
+    assert lib.deblur_workspace_bytes(1, 100, 77, 80, ctypes.byref(taps(31, 31)), ctypes.byref(p)) > 0
+    assert lib.deblur_workspace_bytes(0, 256, 250, 256, ctypes.byref(box()), None) == 0   # 250 = 2 * 5^3
+    assert lib.deblur_workspace_bytes(2, 256, 256, 256, ctypes.byref(box()), None) == 0   # unknown op
+    assert lib.deblur_workspace_bytes(1, 64, 64, 63, ctypes.byref(box()), ctypes.byref(p)) == 0
+
+
+def test_wiener_validation(lib):
+    E, U_, W_ = _lib.DEBLUR_EINVAL, _lib.DEBLUR_EUNSUPPORTED, _lib.DEBLUR_EWORKSPACE
+    assert wiener(lib, f=None) == E
+    assert wiener(lib, u=None) == E
+    assert wiener(lib, H=0) == E
+    assert wiener(lib, pitch=255) == E
+    assert wiener(lib, K=0.0) == E
+    assert wiener(lib, K=float("nan")) == E
+    assert wiener(lib, floor=0.0) == E
+    assert wiener(lib, psf=box(0)) == E
+    assert wiener(lib, psf=_lib.deblur_psf(9, 3, 0, 0, None)) == E
+    assert wiener(lib, psf=taps(4, 5)) == E                      # even dims
+    assert wiener(lib, psf=_lib.deblur_psf(_lib.PSF_TAPS, 0, 3, 3, None)) == E
+    assert wiener(lib, psf=taps(67, 3)) == U_                    # beyond the tap limit
+    assert wiener(lib, W=250, pitch=256) == U_                   # prime factor 5
+    assert wiener(lib, H=250, psf=taps(3, 3)) == U_              # 2D path needs H = 2^a 3^b
+    assert wiener(lib, H=250) == W_                              # row-wise path: H free
+    assert wiener(lib, W=8192, pitch=8192) == U_
+    assert wiener(lib, u=F + 100) == E                           # overlapping f and u0
+    assert wiener(lib) == W_
+    assert wiener(lib, ws=WS, wsb=16) == W_
+
+
+def test_iterate_validation(lib):
+    E, U_, W_ = _lib.DEBLUR_EINVAL, _lib.DEBLUR_EUNSUPPORTED, _lib.DEBLUR_EWORKSPACE
+    assert iterate(lib, f=None) == E
+    assert iterate(lib, ui=None) == E
+    assert iterate(lib, uo=None) == E
+    assert iterate(lib, W=0) == E
+    assert iterate(lib, pitch=10) == E
+    assert iterate(lib, p=params(alpha=-1.0)) == E
+    assert iterate(lib, p=params(eps_data=0.0)) == E
+    assert iterate(lib, p=params(eps_tv=-1.0)) == E
+    assert iterate(lib, p=params(s_min=0.0)) == E
+    assert iterate(lib, p=params(iters=-1)) == E
+    assert iterate(lib, p=params(robust=2)) == E
+    assert iterate(lib, p=params(boundary=5)) == E
+    assert iterate(lib, p=params(conv=9)) == E
+    assert iterate(lib, psf=taps(3, 3), p=params(conv=_lib.CONV_RUNSUM)) == E
+    assert iterate(lib, psf=taps(67, 1)) == U_
+    assert iterate(lib, uo=F) == E                                # u_out overlaps f
+    assert iterate(lib, ui=V + 4) == E                            # partial overlap u_in / u_out
+    assert iterate(lib, ck=F) == E                                # ckpt overlaps f
+    assert iterate(lib, ui=V) == W_                               # u_in == u_out is allowed
+    assert iterate(lib) == W_
+    assert iterate(lib, ws=WS, wsb=64) == W_
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.load()

@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Tolerance from the method's target: relative L2 error
+<= 1e-4 after the stated iteration count; the Wiener step alone, which has
+no iteration, is held to 1e-5."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1212_2245_amd as dbl  # noqa: E402
+
+RTOL_ITER = 1e-4
+RTOL_WIENER = 1e-5
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def gpu_psf(kind, length, taps):
+    if kind in (synth.KIND_BOX_H, synth.KIND_BOX_V):
+        return dbl.Psf.box(length, "h" if kind == synth.KIND_BOX_H else "v")
+    return dbl.Psf.from_taps(dev(taps))
+
+
+def pitched(a, pitch):
+    """Device tensor view of a with row pitch `pitch` >= width."""
+    H, W = a.shape
+    buf = torch.full((H, pitch), -7.0, dtype=torch.float32, device="cuda")
+    buf[:, :W] = dev(a)
+    return buf[:, :W]
+
+
+def report(name, got, want):
+    e = rel_l2(got, want)
+    m = float(np.abs(np.asarray(got, np.float64) - want).max())
+    print(f"[parity] {name}: rel_l2={e:.3e} max_abs={m:.3e}", flush=True)
+    return e
+
+
+# ------------------------------------------------------------------ Wiener
+WIENER_CASES = [
+    # (name, H, W, psf builder, kind, length)
+    ("box_h_15_256", 256, 256, lambda: synth.box_psf(15, "h"), synth.KIND_BOX_H, 15),
+    ("box_h_16_192x384", 192, 384, lambda: synth.box_psf(16, "h"), synth.KIND_BOX_H, 16),
+    ("box_v_9_128", 128, 128, lambda: synth.box_psf(9, "v"), synth.KIND_BOX_V, 9),
+    ("line31_256", 256, 256, lambda: synth.line_psf(31, 0.7), synth.KIND_TAPS, 0),
+    ("line17_96x144", 96, 144, lambda: synth.line_psf(17, 2.0), synth.KIND_TAPS, 0),
+    ("gauss31_512", 512, 512, lambda: synth.gauss_mixture_psf(synth.rng_for(2), 31), synth.KIND_TAPS, 0),
+    ("taps_row_odd_H", 27, 64, lambda: synth.random_psf(np.random.default_rng(3), 1, 7), synth.KIND_TAPS, 0),
+    ("taps_3x5_81x48", 81, 48, lambda: synth.random_psf(np.random.default_rng(4), 3, 5), synth.KIND_TAPS, 0),
+    ("line31_2048", 2048, 2048, lambda: synth.line_psf(31, 1.1), synth.KIND_TAPS, 0),
+]
+
+
+@pytest.mark.parametrize("name,H,W,mk,kind,L", WIENER_CASES, ids=[c[0] for c in WIENER_CASES])
+def test_wiener_parity(name, H, W, mk, kind, L):
+    rng = np.random.default_rng(H * 7 + W)
+    g = synth.ground_truth(rng, H, W)
+    h = mk().astype(np.float32)
+    f = synth.observe(rng, g, h.astype(np.float64), 2.0)
+    K = 0.01
+    want = oracle.wiener_init(f, h, K, 1.0)
+    u = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    dbl.deblur_wiener(dev(f), u, gpu_psf(kind, L, h), K, 1.0)
+    got = u.cpu().numpy()
+    assert report("wiener " + name, got, want) <= RTOL_WIENER
+
+
+def test_wiener_pitch_and_small_K():
+    rng = np.random.default_rng(11)
+    g = synth.ground_truth(rng, 64, 96)
+    h = synth.line_psf(9, 0.3).astype(np.float32)
+    f = synth.observe(rng, g, h.astype(np.float64), 1.0)
+    for K in (1e-4, 0.3):
+        want = oracle.wiener_init(f, h, K, 0.5)
+        fd = pitched(f, 128)
+        u = pitched(np.zeros_like(f), 128)
+        dbl.deblur_wiener(fd, u, gpu_psf(synth.KIND_TAPS, 0, h), K, 0.5)
+        assert report(f"wiener pitch K={K}", u.cpu().numpy(), want) <= (1e-4 if K < 1e-3 else RTOL_WIENER)
+        assert torch.all(u.base[:, 96:] == -7.0)   # padding untouched
+
+
+# ------------------------------------------------------------- iterations
+def iterate_case(H, W, h, kind, L, iters, alpha=0.003, robust=True, bc=oracle.BC_REPLICATE, seed=0,
+                 eps_d=0.1, eps_t=0.1, pitch=None):
+    rng = np.random.default_rng(seed)
+    g = synth.ground_truth(rng, H, W)
+    f = synth.observe(rng, g, h.astype(np.float64), 2.0)
+    u0 = np.maximum(f, 1.0) + rng.uniform(0, 3, size=f.shape).astype(np.float32)
+    p = oracle.Params(alpha=alpha, eps_data=eps_d, eps_tv=eps_t, robust=robust, bc=bc)
+    want = oracle.rrrl(f, u0, h, p, iters)
+    gp = dbl.Params(alpha=alpha, iters=iters, eps_data=eps_d, eps_tv=eps_t, robust=robust, boundary=bc)
+    if pitch:
+        fd, ui, uo = pitched(f, pitch), pitched(u0, pitch), pitched(np.zeros_like(f), pitch)
+    else:
+        fd, ui, uo = dev(f), dev(u0), torch.empty((H, W), dtype=torch.float32, device="cuda")
+    dbl.deblur_rrrl_iterate(fd, ui, uo, gpu_psf(kind, L, h), gp)
+    return uo.cpu().numpy(), want
+
+
+ITER_CASES = [
+    ("box_h15_256_k10", 256, 256, lambda: synth.box_psf(15, "h"), synth.KIND_BOX_H, 15, 10, {}),
+    ("box_v8_ragged", 77, 129, lambda: synth.box_psf(8, "v"), synth.KIND_BOX_V, 8, 5, {}),
+    ("line31_192_k20", 192, 192, lambda: synth.line_psf(31, 0.4), synth.KIND_TAPS, 0, 20, dict(alpha=0.002)),
+    ("line9_ragged_periodic", 100, 70, lambda: synth.line_psf(9, 2.5), synth.KIND_TAPS, 0, 6,
+     dict(bc=oracle.BC_PERIODIC)),
+    ("gauss31_128_k30", 128, 128, lambda: synth.gauss_mixture_psf(synth.rng_for(2), 31), synth.KIND_TAPS, 0, 30,
+     {}),
+    ("asym5x3_strong_tv", 64, 80, lambda: synth.random_psf(np.random.default_rng(5), 5, 3), synth.KIND_TAPS, 0, 8,
+     dict(alpha=0.5)),
+    ("line21_nonrobust", 96, 96, lambda: synth.line_psf(21, 0.785), synth.KIND_TAPS, 0, 10, dict(robust=False)),
+    ("eps_small", 64, 64, lambda: synth.line_psf(11, 1.3), synth.KIND_TAPS, 0, 5, dict(eps_d=0.01, eps_t=0.01)),
+    ("eps_large", 64, 64, lambda: synth.line_psf(11, 1.3), synth.KIND_TAPS, 0, 5, dict(eps_d=1.0, eps_t=1.0)),
+    ("taps_63x1_periodic", 70, 90, lambda: synth.box_psf(63, "v"), synth.KIND_TAPS, 0, 4,
+     dict(bc=oracle.BC_PERIODIC)),
+    ("tiny_5x3", 5, 3, lambda: synth.random_psf(np.random.default_rng(6), 3, 3), synth.KIND_TAPS, 0, 3, {}),
+    ("single_row", 1, 40, lambda: synth.box_psf(5, "h"), synth.KIND_BOX_H, 5, 4, {}),
+    ("pitch_160", 100, 130, lambda: synth.line_psf(15, 0.2), synth.KIND_TAPS, 0, 5, dict(pitch=160)),
+]
+
+
+@pytest.mark.parametrize("name,H,W,mk,kind,L,iters,kw", ITER_CASES, ids=[c[0] for c in ITER_CASES])
+def test_iterate_parity(name, H, W, mk, kind, L, iters, kw):
+    h = mk().astype(np.float32)
+    got, want = iterate_case(H, W, h, kind, L, iters, **kw)
+    assert np.all(np.isfinite(got))
+    assert report("iterate " + name, got, want) <= RTOL_ITER
+
+
+def test_iterate_edge_counts_and_aliasing():
+    rng = np.random.default_rng(21)
+    H, W = 48, 72
+    h = synth.line_psf(13, 0.9).astype(np.float32)
+    g = synth.ground_truth(rng, H, W)
+    f = synth.observe(rng, g, h.astype(np.float64), 2.0)
+    u0 = np.maximum(f, 1.0)
+    psf = gpu_psf(synth.KIND_TAPS, 0, h)
+    for iters in (0, 1, 2, 3):
+        want = oracle.rrrl(f, u0, h, oracle.Params(alpha=0.01), iters)
+        gp = dbl.Params(alpha=0.01, iters=iters)
+        out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        dbl.deblur_rrrl_iterate(dev(f), dev(u0), out, psf, gp)
+        assert report(f"iters={iters}", out.cpu().numpy(), want) <= RTOL_ITER
+        u = dev(u0)   # in place: u_in == u_out
+        dbl.deblur_rrrl_iterate(dev(f), u, u, psf, gp)
+        assert report(f"iters={iters} in-place", u.cpu().numpy(), want) <= RTOL_ITER
+
+
+def test_checkpoints_are_the_iterates():
+    rng = np.random.default_rng(22)
+    H, W, K = 64, 64, 4
+    h = synth.line_psf(9, 0.2).astype(np.float32)
+    f = synth.observe(rng, synth.ground_truth(rng, H, W), h.astype(np.float64), 2.0)
+    u0 = np.maximum(f, 1.0)
+    want, ck_want = oracle.rrrl(f, u0, h, oracle.Params(alpha=0.01), K, checkpoints=True)
+    ck = torch.full((K, H, W), -1.0, dtype=torch.float32, device="cuda")
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    dbl.deblur_rrrl_iterate(dev(f), dev(u0), out, gpu_psf(synth.KIND_TAPS, 0, h), dbl.Params(alpha=0.01, iters=K),
+                            ckpt=ck)
+    ck = ck.cpu().numpy()
+    np.testing.assert_array_equal(ck[0], u0.astype(np.float32))
+    for k in range(K):
+        assert report(f"ckpt {k}", ck[k], ck_want[k]) <= RTOL_ITER
+
+
+def test_determinism_and_resume():
+    """Run-to-run bitwise determinism; K1 + K2 iterations == K1+K2 (bitwise)."""
+    rng = np.random.default_rng(23)
+    H, W = 96, 128
+    h = synth.line_psf(21, 2.2).astype(np.float32)
+    f = dev(synth.observe(rng, synth.ground_truth(rng, H, W), h.astype(np.float64), 2.0))
+    psf = gpu_psf(synth.KIND_TAPS, 0, h)
+    u0 = torch.clamp(f, min=1.0)
+    a = torch.empty_like(f)
+    b = torch.empty_like(f)
+    dbl.deblur_rrrl_iterate(f, u0, a, psf, dbl.Params(iters=7))
+    dbl.deblur_rrrl_iterate(f, u0, b, psf, dbl.Params(iters=7))
+    assert torch.equal(a, b)
+    c = torch.empty_like(f)
+    dbl.deblur_rrrl_iterate(f, u0, c, psf, dbl.Params(iters=3))
+    dbl.deblur_rrrl_iterate(f, c, c, psf, dbl.Params(iters=4))
+    assert torch.equal(a, c)
+
+
+# --------------------------------------------------------------- workloads
+@pytest.mark.parametrize("config,size", [(0, None), (1, 256), (4, 128), (3, None)])
+def test_wr3l_workload_parity(config, size):
+    """End to end WR3L (Wiener + RRRL) on the seeded workloads at reduced size."""
+    c = synth.make_case(config, size=size) if config != 3 else synth.make_case(3, image=5, size=192)
+    p = oracle.Params(alpha=c.alpha)
+    want = oracle.wr3l(c.f, c.psf, c.K, p, c.iters)
+    got = dbl.wr3l(dev(c.f), gpu_psf(c.kind, c.length, c.psf), c.K, dbl.Params(alpha=c.alpha, iters=c.iters))
+    assert report(f"wr3l config {config} size {size}", got.cpu().numpy(), want) <= RTOL_ITER
+
+
+def test_wr3l_full_size_workload_1():
+    """The benchmarked workload at its full size: 1024^2, oblique line L=31,
+    20 iterations, full-image comparison against the oracle."""
+    c = synth.make_case(1)
+    want = oracle.wr3l(c.f, c.psf, c.K, oracle.Params(alpha=c.alpha), c.iters)
+    got = dbl.wr3l(dev(c.f), gpu_psf(c.kind, c.length, c.psf), c.K, dbl.Params(alpha=c.alpha, iters=c.iters))
+    assert report("wr3l config 1 full", got.cpu().numpy(), want) <= RTOL_ITER
+
+
+@pytest.mark.parametrize("robust", [True, False])
+@pytest.mark.parametrize("bc", [oracle.BC_REPLICATE, oracle.BC_PERIODIC])
+def test_stage_parity(robust, bc):
+    """Stage 1 (W, q) and stage 2 (update) each against the oracle's step."""
+    rng = np.random.default_rng(31)
+    H, W = 70, 133
+    h = synth.random_psf(rng, 7, 9, density=0.4).astype(np.float32)
+    f = synth.observe(rng, synth.ground_truth(rng, H, W), h.astype(np.float64), 2.0)
+    f[5:9, 10:20] = 0.0
+    u = np.maximum(f, 1.0) + rng.uniform(0, 5, size=f.shape).astype(np.float32)
+    p = oracle.Params(alpha=0.2, robust=robust, bc=bc)
+    want_u, parts = oracle.rrrl_step(f, u, h, p, parts=True)
+    psf = gpu_psf(synth.KIND_TAPS, 0, h)
+    gp = dbl.Params(alpha=0.2, robust=robust, boundary=bc, iters=1)
+    taps = dbl.deblur_compile_taps(psf)
+    qw = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
+    ud = dev(u)
+    dbl.deblur_rrrl_weights(dev(f), ud, qw, psf, taps, gp)
+    q = qw.cpu().numpy()
+    assert report("stage1 W", q[..., 1], parts["W"]) <= 1e-5
+    assert report("stage1 q", q[..., 0], parts["q"]) <= 1e-5
+    out = torch.empty_like(ud)
+    cp = torch.empty_like(ud)
+    dbl.deblur_rrrl_update(qw, ud, out, psf, taps, gp, u_copy=cp)
+    assert torch.equal(cp, ud)
+    assert report("stage2 u'", out.cpu().numpy(), want_u) <= 1e-5
