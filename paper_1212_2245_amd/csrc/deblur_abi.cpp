@@ -93,11 +93,15 @@ int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, co
     if (p->boundary != DEBLUR_BC_REPLICATE && p->boundary != DEBLUR_BC_PERIODIC) return DEBLUR_EINVAL;
     if (p->conv < DEBLUR_CONV_AUTO || p->conv > DEBLUR_CONV_STENCIL) return DEBLUR_EINVAL;
     if (p->conv == DEBLUR_CONV_RUNSUM && d->kind == DEBLUR_PSF_TAPS) return DEBLUR_EINVAL;
-    if (p->conv == DEBLUR_CONV_RUNSUM) return DEBLUR_EUNSUPPORTED;
     const int rad = (d->ph - 1) / 2 > (d->pw - 1) / 2 ? (d->ph - 1) / 2 : (d->pw - 1) / 2;
     if (tap_radius_class(rad) < 0) return DEBLUR_EUNSUPPORTED;
     if ((d->ph - 1) / 2 > H || (d->pw - 1) / 2 > W) return DEBLUR_EINVAL;
     return DEBLUR_OK;
+}
+
+bool use_box(const PsfDev& d, const deblur_params* p)
+{
+    return d.kind != DEBLUR_PSF_TAPS && p->conv != DEBLUR_CONV_STENCIL;
 }
 
 IterParams iter_params(const deblur_params* p)
@@ -140,7 +144,7 @@ size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, c
     }
     if (op == 1) {
         if (check_iterate(H, W, pitch, psf, p, &d)) return 0;
-        return taps_ws_bytes(H, W, pitch, d);
+        return iterate_ws_bytes(H, W, pitch, d, use_box(d, p));
     }
     return 0;
 }
@@ -176,10 +180,12 @@ int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t
         if (overlaps(ckpt, ck, f, img) || overlaps(ckpt, ck, u_in, img) || overlaps(ckpt, ck, u_out, img))
             return DEBLUR_EINVAL;
     }
-    const size_t need = taps_ws_bytes(H, W, pitch, d);
+    const bool box = use_box(d, p);
+    const size_t need = iterate_ws_bytes(H, W, pitch, d, box);
     if (!ws || ws_bytes < need) return DEBLUR_EWORKSPACE;
-    return launch_rrrl_taps(f, u_in, u_out, H, W, pitch, d, iter_params(p), p->iters, ckpt, ws,
+    s = launch_rrrl_iterate(f, u_in, u_out, H, W, pitch, d, iter_params(p), p->iters, ckpt, box, ws,
                             reinterpret_cast<hipStream_t>(stream));
+    return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EUNSUPPORTED : DEBLUR_EDEVICE);
 }
 
 size_t deblur_taps_bytes(const deblur_psf* psf)

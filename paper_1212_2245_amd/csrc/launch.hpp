@@ -21,14 +21,23 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
                   float pos_floor, void* ws, bool rowwise, hipStream_t st);
 
 int tap_radius_class(int rad);
-size_t taps_ws_bytes(int H, int W, int pitch, const PsfDev& psf);
 size_t tap_list_bytes(const PsfDev& psf);
 void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st);
 int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, int pitch, const PsfDev& psf,
                        const void* list, const IterParams& p, hipStream_t st);
 int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
                        const PsfDev& psf, const void* list, const IterParams& p, hipStream_t st);
-int launch_rrrl_taps(const float* f, const float* u_in, float* u_out, int H, int W, int pitch, const PsfDev& psf,
-                     const IterParams& p, int iters, float* ckpt, void* ws, hipStream_t st);
+
+// One fused RRRL iteration for a box PSF of length L along x (vert = false)
+// or y (vert = true).
+int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
+                         bool vert, const IterParams& p, hipStream_t st);
+
+// Iteration driver: `iters` iterations u_in -> u_out with ping-pong buffers
+// in the workspace; box kinds use the fused running-sum kernel when use_box.
+size_t iterate_ws_bytes(int H, int W, int pitch, const PsfDev& psf, bool use_box);
+int launch_rrrl_iterate(const float* f, const float* u_in, float* u_out, int H, int W, int pitch,
+                        const PsfDev& psf, const IterParams& p, int iters, float* ckpt, bool use_box, void* ws,
+                        hipStream_t st);
 
 }  // namespace deblur

@@ -240,50 +240,4 @@ int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, 
     return 0;
 }
 
-size_t taps_ws_bytes(int H, int W, int pitch, const PsfDev& psf)
-{
-    const size_t lr = (tap_list_bytes(psf) + 255) & ~(size_t)255;
-    const size_t qw = ((size_t)H * W * sizeof(float2) + 255) & ~(size_t)255;
-    const size_t pl = ((size_t)H * pitch * sizeof(float) + 255) & ~(size_t)255;
-    return lr + qw + 2 * pl;
-}
-
-int launch_rrrl_taps(const float* f, const float* u_in, float* u_out, int H, int W, int pitch, const PsfDev& psf,
-                     const IterParams& p, int iters, float* ckpt, void* ws, hipStream_t st)
-{
-    if (psf_radius_class(psf) < 0) return -2;
-    unsigned char* w8 = reinterpret_cast<unsigned char*>(ws);
-    const size_t lr = (tap_list_bytes(psf) + 255) & ~(size_t)255;
-    float* qw = reinterpret_cast<float*>(w8 + lr);
-    const size_t qwb = ((size_t)H * W * sizeof(float2) + 255) & ~(size_t)255;
-    float* t0 = reinterpret_cast<float*>(w8 + lr + qwb);
-    const size_t pl = ((size_t)H * pitch * sizeof(float) + 255) & ~(size_t)255;
-    float* t1 = reinterpret_cast<float*>(w8 + lr + qwb + pl);
-
-    launch_compile_taps(psf, ws, st);
-    if (iters == 0) {
-        if (u_out != u_in)
-            (void)hipMemcpy2DAsync(u_out, pitch * sizeof(float), u_in, pitch * sizeof(float), W * sizeof(float), H,
-                                   hipMemcpyDeviceToDevice, st);
-        return hipGetLastError() == hipSuccess ? 0 : -4;
-    }
-    // Ping-pong so that the last iteration writes u_out; iteration k writes
-    // u_out when (iters-1-k) is even.  If u_in aliases u_out and the first
-    // write would land there, start from a copy.
-    const float* src = u_in;
-    if (u_in == u_out && ((iters - 1) % 2 == 0)) {
-        (void)hipMemcpy2DAsync(t1, pitch * sizeof(float), u_in, pitch * sizeof(float), W * sizeof(float), H,
-                               hipMemcpyDeviceToDevice, st);
-        src = t1;
-    }
-    for (int k = 0; k < iters; ++k) {
-        float* dst = ((iters - 1 - k) % 2 == 0) ? u_out : t0;
-        float* ck = ckpt ? ckpt + (size_t)k * H * pitch : nullptr;
-        launch_taps_stage1(f, src, qw, H, W, pitch, psf, ws, p, st);
-        launch_taps_stage2(qw, src, dst, ck, H, W, pitch, psf, ws, p, st);
-        src = dst;
-    }
-    return hipGetLastError() == hipSuccess ? 0 : -4;
-}
-
 }  // namespace deblur

@@ -241,3 +241,32 @@ def test_stage_parity(robust, bc):
     dbl.deblur_rrrl_update(qw, ud, out, psf, taps, gp, u_copy=cp)
     assert torch.equal(cp, ud)
     assert report("stage2 u'", out.cpu().numpy(), want_u) <= 1e-5
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 8, 15, 16, 27, 40, 41, 64])
+@pytest.mark.parametrize("axis", ["h", "v"])
+@pytest.mark.parametrize("bc", [oracle.BC_REPLICATE, oracle.BC_PERIODIC])
+def test_box_running_sum_lengths(L, axis, bc):
+    """Running-sum box path (every length, odd and even, both continuations)
+    against the oracle's direct summation."""
+    H, W = (70, 150) if axis == "h" else (150, 70)
+    if bc == oracle.BC_PERIODIC and L > min(H, W):
+        pytest.skip("PSF longer than the image")
+    h = synth.box_psf(L, axis).astype(np.float32)
+    kind = synth.KIND_BOX_H if axis == "h" else synth.KIND_BOX_V
+    got, want = iterate_case(H, W, h, kind, L, 3, alpha=0.05, bc=bc, seed=L)
+    assert report(f"box {axis} L={L} bc={bc}", got, want) <= RTOL_ITER
+
+
+def test_box_running_sum_matches_stencil_path():
+    """The same box PSF through the running-sum kernel and the tap stencil."""
+    rng = np.random.default_rng(41)
+    H, W = 200, 256
+    f = synth.observe(rng, synth.ground_truth(rng, H, W), synth.box_psf(21, "v"), 2.0)
+    u0 = np.maximum(f, 1.0)
+    outs = []
+    for conv in (dbl.CONV_RUNSUM, dbl.CONV_STENCIL):
+        out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        dbl.deblur_rrrl_iterate(dev(f), dev(u0), out, dbl.Psf.box(21, "v"), dbl.Params(iters=8, conv=conv))
+        outs.append(out.cpu().numpy())
+    assert report("runsum vs stencil", outs[0], outs[1]) <= 1e-5
