@@ -6,9 +6,10 @@
 // window sum by one addition and one subtraction per pixel.  Here every
 // workgroup owns a tile and forms inclusive prefix sums of its tile rows
 // along the blur axis in LDS, so a window sum is a difference of two prefix
-// values; the prefix restarts at every tile (at most a few hundred terms), so
-// FP32 drift stays bounded.  Window sums of non-negative data are clamped at
-// zero (the prefix difference can round below zero where the true sum is 0).
+// values.  The prefix restarts at every tile (a few hundred terms) and is
+// accumulated in FP64, so a window sum is as accurate as a direct FP32 sum of
+// its L terms even for short windows; window sums of non-negative data are
+// clamped at zero.
 //
 // Per tile (TA outputs along the blur axis x TC across it):
 //   1. u on the tile plus halo L-1 along (for A evaluated on the halo that B
@@ -22,6 +23,8 @@
 // vertical motion (along = y).  LDS rows are "lines" of the tile along the
 // blur axis for horizontal motion and image rows for vertical motion, so that
 // global accesses stay coalesced along x in both cases.
+#include <mutex>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -70,7 +73,7 @@ DEBLUR_DEV void prefix_lines(T* buf, int n, int lines, T* sums)
     __syncthreads();
 }
 
-DEBLUR_DEV float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+DEBLUR_DEV double2 operator+(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
 template <bool VERT, int TA, int TC>
 __global__ void __launch_bounds__(256) rrrl_box_iter(const float* __restrict__ u, const float* __restrict__ f,
@@ -83,12 +86,12 @@ __global__ void __launch_bounds__(256) rrrl_box_iter(const float* __restrict__ u
     constexpr int G = 256 / TC;
     const int nu = bt.nu, nq = bt.nq;
     float* us = reinterpret_cast<float*>(smem_raw);                 // CU lines of nu (u tile)
-    float* ps = us + CU * (nu + 1);                                  // TC lines of nu: prefix of u
-    float* gs = ps + TC * (nu + 1);                                  // (TC+2) x (TA+2) diffusivity
-    const int qoff = (CU * (nu + 1) + TC * (nu + 1) + (TC + 2) * (TA + 3) + 1) & ~1;
-    float2* qs = reinterpret_cast<float2*>(us + qoff);               // TC lines of nq: (q, W)
-    float2* sums2 = qs + TC * (nq + 1);
-    float* sums = reinterpret_cast<float*>(sums2 + 256);
+    float* gs = us + CU * (nu + 1);                                  // (TC+2) x (TA+2) diffusivity
+    const int doff = (CU * (nu + 1) + (TC + 2) * (TA + 3) + 3) & ~3;
+    double* ps = reinterpret_cast<double*>(us + doff);               // TC lines of nu: prefix of u
+    double2* qs = reinterpret_cast<double2*>(ps + TC * (nu + 1));    // TC lines of nq: prefix of (q, W)
+    double2* sums2 = qs + TC * (nq + 1);
+    double* sums = reinterpret_cast<double*>(sums2 + 256);
 
     const int a0 = (VERT ? blockIdx.y : blockIdx.x) * TA;   // first output along
     const int c0 = (VERT ? blockIdx.x : blockIdx.y) * TC;   // first output across
@@ -111,7 +114,7 @@ __global__ void __launch_bounds__(256) rrrl_box_iter(const float* __restrict__ u
     for (int i = t; i < TC * nu; i += 256) {
         int c, j;
         if (VERT) { j = i / TC; c = i - j * TC; } else { c = i / nu; j = i - c * nu; }
-        ps[Lay::at(c, j, nu, TC)] = us[Lay::at(c + 2, j, nu, CU)];
+        ps[Lay::at(c, j, nu, TC)] = (double)us[Lay::at(c + 2, j, nu, CU)];
     }
     // tile positions of the first/last image index along (clamping for TV)
     const int jmin = max(0, -lo), jmax = min(nu - 1, bt.along_n - 1 - lo);
@@ -127,14 +130,14 @@ __global__ void __launch_bounds__(256) rrrl_box_iter(const float* __restrict__ u
         gs[VERT ? k * (TC + 2) + c : c * (GA + 1) + k] = pen_deriv(da * da + dc * dc, p.eps_t2);
     }
     __syncthreads();
-    prefix_lines<VERT, TA, TC, float>(ps, nu, TC, sums);
+    prefix_lines<VERT, TA, TC, double>(ps, nu, TC, sums);
     // 3. s = A u, W, q on positions m = 0..nq-1 (along a0 - aL + m)
     const float invL = 1.0f / (float)bt.L;
     for (int i = t; i < TC * nq; i += 256) {
         int c, m;
         if (VERT) { m = i / TC; c = i - m * TC; } else { c = i / nq; m = i - c * nq; }
         const int gc = c0 + c;
-        float2 qw = make_float2(0.0f, 0.0f);
+        double2 qw = make_double2(0.0, 0.0);
         if (gc < bt.across_n) {
             // B reads E(q)(x'): q at the continued position.  Periodic: the
             // tile holds the wrapped u, so x' itself is used; constant
@@ -143,17 +146,17 @@ __global__ void __launch_bounds__(256) rrrl_box_iter(const float* __restrict__ u
             const int ga = ext_index(xa, bt.along_n, p.bc);
             const int j = (p.bc == BC_PERIODIC ? xa : ga) - lo;  // tile position of the sample
             const int hi = j + bt.aL, lo2 = j - bt.bL - 1;          // A window [j - bL, j + aL]
-            const float sum = ps[Lay::at(c, hi, nu, TC)] - (lo2 >= 0 ? ps[Lay::at(c, lo2, nu, TC)] : 0.0f);
-            const float s = fmaxf(fmaxf(sum, 0.0f) * invL, p.s_min);
+            const double sum = ps[Lay::at(c, hi, nu, TC)] - (lo2 >= 0 ? ps[Lay::at(c, lo2, nu, TC)] : 0.0);
+            const float s = fmaxf((float)fmax(sum, 0.0) * invL, p.s_min);
             const int y = VERT ? ga : gc, x = VERT ? gc : ga;
             const float fv = f[(size_t)y * pitch + x];
             const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
-            qw = make_float2(wt * fmaxf(fv, 0.0f) / s, wt);
+            qw = make_double2((double)(wt * fmaxf(fv, 0.0f) / s), (double)wt);
         }
         qs[Lay::at(c, m, nq, TC)] = qw;
     }
     __syncthreads();
-    prefix_lines<VERT, TA, TC, float2>(qs, nq, TC, sums2);
+    prefix_lines<VERT, TA, TC, double2>(qs, nq, TC, sums2);
     // 5. correlation, diffusion term, update
     for (int i = t; i < TC * TA; i += 256) {
         int c, o;
@@ -161,9 +164,9 @@ __global__ void __launch_bounds__(256) rrrl_box_iter(const float* __restrict__ u
         const int gc = c0 + c, ga = a0 + o;
         if (gc >= bt.across_n || ga >= bt.along_n) continue;
         // B window [o, o + L - 1] in q positions
-        const float2 hi = qs[Lay::at(c, o + bt.L - 1, nq, TC)];
-        const float2 lw = o > 0 ? qs[Lay::at(c, o - 1, nq, TC)] : make_float2(0.0f, 0.0f);
-        const float n1 = fmaxf(hi.x - lw.x, 0.0f) * invL, n2 = fmaxf(hi.y - lw.y, 0.0f) * invL;
+        const double2 hi = qs[Lay::at(c, o + bt.L - 1, nq, TC)];
+        const double2 lw = o > 0 ? qs[Lay::at(c, o - 1, nq, TC)] : make_double2(0.0, 0.0);
+        const float n1 = (float)fmax(hi.x - lw.x, 0.0) * invL, n2 = (float)fmax(hi.y - lw.y, 0.0) * invL;
         const int j = bt.hA + o;
         const int jm = max(j - 1, jmin), jp = min(j + 1, jmax);
         const float up = us[Lay::at(c + 2, j, nu, CU)];
@@ -192,9 +195,8 @@ template <bool VERT, int TA, int TC>
 static size_t box_lds_bytes(const BoxTile& bt)
 {
     constexpr int CU = TC + 4;
-    const size_t fl = ((size_t)CU * (bt.nu + 1) + (size_t)TC * (bt.nu + 1) + (size_t)(TC + 2) * (TA + 3) + 1) &
-                      ~(size_t)1;
-    return fl * 4 + ((size_t)TC * (bt.nq + 1) + 256) * 8 + 256 * 4;
+    const size_t fl = ((size_t)CU * (bt.nu + 1) + (size_t)(TC + 2) * (TA + 3) + 3) & ~(size_t)3;
+    return fl * 4 + (size_t)TC * (bt.nu + 1) * 8 + ((size_t)TC * (bt.nq + 1) + 256) * 16 + 256 * 8;
 }
 
 static BoxTile make_tile(int H, int W, int L, bool vert, int TA)
@@ -213,9 +215,23 @@ static BoxTile make_tile(int H, int W, int L, bool vert, int TA)
 
 constexpr int BOXH_TA = 128, BOXH_TC = 8, BOXV_TA = 64, BOXV_TC = 16;
 
+// Tiles for long boxes need more than 64 KB of dynamic LDS (gfx950 has
+// 160 KB per workgroup); the limit is raised once per process.
+static void allow_large_lds()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<false, 128, 8>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<true, 64, 16>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+}
+
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
                          bool vert, const IterParams& p, hipStream_t st)
 {
+    allow_large_lds();
     if (!vert) {
         const BoxTile bt = make_tile(H, W, L, false, BOXH_TA);
         const dim3 g((W + BOXH_TA - 1) / BOXH_TA, (H + BOXH_TC - 1) / BOXH_TC);
