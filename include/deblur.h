@@ -80,6 +80,9 @@ typedef struct {
     int32_t robust;  /* 1: W = Phi'(r_f(u*h)) (eq. (10)); 0: W = 1 (plain RL data term) */
     int32_t boundary;/* deblur_boundary */
     int32_t conv;    /* deblur_conv */
+    int32_t tile;    /* tile shape of the stencil kernels: 0 = library default for the image
+                        size, 1..deblur_tile_variants() = an explicit shape (an autotuner's
+                        choice); all shapes give bitwise-identical results */
 } deblur_params;
 
 /* Text for a status code (static storage). */
@@ -87,6 +90,9 @@ const char* deblur_status_string(int status);
 
 /* Library ABI version (major*10000 + minor*100 + patch). */
 int deblur_version(void);
+
+/* Number of explicit tile shapes selectable through deblur_params.tile. */
+int deblur_tile_variants(void);
 
 /* Workspace bytes needed by an entry point: op 0 = deblur_wiener,
  * 1 = deblur_rrrl_iterate.  Returns 0 for invalid arguments (the matching

@@ -63,10 +63,11 @@ class Params:
     robust: bool = True
     boundary: int = BC_REPLICATE
     conv: int = CONV_AUTO
+    tile: int = 0
 
     def c(self) -> _lib.deblur_params:
         return _lib.deblur_params(self.alpha, self.eps_data, self.eps_tv, self.s_min, int(self.iters),
-                                  int(bool(self.robust)), int(self.boundary), int(self.conv))
+                                  int(bool(self.robust)), int(self.boundary), int(self.conv), int(self.tile))
 
 
 def _stream(t: torch.Tensor) -> int:

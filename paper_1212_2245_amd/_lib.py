@@ -29,7 +29,7 @@ class deblur_psf(ctypes.Structure):
 class deblur_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_float), ("eps_data", ctypes.c_float), ("eps_tv", ctypes.c_float),
                 ("s_min", ctypes.c_float), ("iters", ctypes.c_int32), ("robust", ctypes.c_int32),
-                ("boundary", ctypes.c_int32), ("conv", ctypes.c_int32)]
+                ("boundary", ctypes.c_int32), ("conv", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 # (name, restype, argtypes) of every exported entry point
@@ -38,6 +38,7 @@ _PSF, _PAR = ctypes.POINTER(deblur_psf), ctypes.POINTER(deblur_params)
 SIGNATURES = [
     ("deblur_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("deblur_version", ctypes.c_int, []),
+    ("deblur_tile_variants", ctypes.c_int, []),
     ("deblur_workspace_bytes", _SZ, [_I32, _I32, _I32, _I32, _PSF, _PAR]),
     ("deblur_wiener", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _PSF, ctypes.c_double, ctypes.c_float,
                                      _VP, _SZ, _VP]),

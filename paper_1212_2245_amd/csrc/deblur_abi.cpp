@@ -93,6 +93,7 @@ int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, co
     if (p->boundary != DEBLUR_BC_REPLICATE && p->boundary != DEBLUR_BC_PERIODIC) return DEBLUR_EINVAL;
     if (p->conv < DEBLUR_CONV_AUTO || p->conv > DEBLUR_CONV_STENCIL) return DEBLUR_EINVAL;
     if (p->conv == DEBLUR_CONV_RUNSUM && d->kind == DEBLUR_PSF_TAPS) return DEBLUR_EINVAL;
+    if (p->tile < 0 || p->tile > taps_num_variants()) return DEBLUR_EINVAL;
     const int rad = (d->ph - 1) / 2 > (d->pw - 1) / 2 ? (d->ph - 1) / 2 : (d->pw - 1) / 2;
     if (tap_radius_class(rad) < 0) return DEBLUR_EUNSUPPORTED;
     if ((d->ph - 1) / 2 > H || (d->pw - 1) / 2 > W) return DEBLUR_EINVAL;
@@ -113,6 +114,7 @@ IterParams iter_params(const deblur_params* p)
     q.s_min = p->s_min;
     q.robust = p->robust;
     q.bc = p->boundary;
+    q.tile = p->tile;
     return q;
 }
 
@@ -133,6 +135,8 @@ const char* deblur_status_string(int status)
 }
 
 int deblur_version(void) { return 100; }
+
+int deblur_tile_variants(void) { return taps_num_variants(); }
 
 size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
                               const deblur_params* p)
@@ -215,7 +219,8 @@ int deblur_rrrl_weights(const float* f, const float* u, float* qw, int32_t H, in
     if (s) return s;
     const size_t img = (size_t)H * pitch * sizeof(float), q = (size_t)H * W * 2 * sizeof(float);
     if (overlaps(qw, q, f, img) || overlaps(qw, q, u, img)) return DEBLUR_EINVAL;
-    s = launch_taps_stage1(f, u, qw, H, W, pitch, d, taps, iter_params(p), reinterpret_cast<hipStream_t>(stream));
+    s = launch_taps_stage1(f, u, qw, H, W, pitch, d, taps, iter_params(p), p->tile,
+                           reinterpret_cast<hipStream_t>(stream));
     if (s) return DEBLUR_EUNSUPPORTED;
     return hipGetLastError() == hipSuccess ? DEBLUR_OK : DEBLUR_EDEVICE;
 }
@@ -232,7 +237,7 @@ int deblur_rrrl_update(const float* qw, const float* u, float* u_out, float* u_c
     if (overlaps(u, img, u_out, img) || overlaps(qw, q, u_out, img)) return DEBLUR_EINVAL;
     if (u_copy && (overlaps(u_copy, img, u, img) || overlaps(u_copy, img, u_out, img) || overlaps(u_copy, img, qw, q)))
         return DEBLUR_EINVAL;
-    s = launch_taps_stage2(qw, u, u_out, u_copy, H, W, pitch, d, taps, iter_params(p),
+    s = launch_taps_stage2(qw, u, u_out, u_copy, H, W, pitch, d, taps, iter_params(p), p->tile,
                            reinterpret_cast<hipStream_t>(stream));
     if (s) return DEBLUR_EUNSUPPORTED;
     return hipGetLastError() == hipSuccess ? DEBLUR_OK : DEBLUR_EDEVICE;

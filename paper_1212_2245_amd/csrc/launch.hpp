@@ -14,6 +14,7 @@ namespace deblur {
 struct IterParams {
     float alpha, eps_d2, eps_t2, s_min;
     int robust, bc;
+    int tile;  // tile-shape variant (0 = default)
 };
 
 size_t wiener_ws_bytes(int H, int W, bool rowwise);
@@ -23,10 +24,13 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
 int tap_radius_class(int rad);
 size_t tap_list_bytes(const PsfDev& psf);
 void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st);
+// `variant`: 0 = default tile shape for the image size, 1..taps_num_variants()
+// = an explicit tile shape (all give bitwise-identical results).
+int taps_num_variants();
 int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, int pitch, const PsfDev& psf,
-                       const void* list, const IterParams& p, hipStream_t st);
+                       const void* list, const IterParams& p, int variant, hipStream_t st);
 int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
-                       const PsfDev& psf, const void* list, const IterParams& p, hipStream_t st);
+                       const PsfDev& psf, const void* list, const IterParams& p, int variant, hipStream_t st);
 
 // One fused RRRL iteration for a box PSF of length L along x (vert = false)
 // or y (vert = true).

@@ -49,17 +49,18 @@ __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restri
     if (threadIdx.x == 255) list_count[0] = counts[255];
 }
 
-template <int RAD, int TH>
-__global__ void __launch_bounds__(256) rrrl_taps_stage1(const float* __restrict__ u, const float* __restrict__ f,
-                                                        float2* __restrict__ qw, int H, int W, int pitch,
-                                                        const int4* __restrict__ taps,
-                                                        const int* __restrict__ ntaps, IterParams p)
+template <int RAD, int TH, int NT>
+__global__ void __launch_bounds__(NT) rrrl_taps_stage1(const float* __restrict__ u, const float* __restrict__ f,
+                                                       float2* __restrict__ qw, int H, int W, int pitch,
+                                                       const int4* __restrict__ taps,
+                                                       const int* __restrict__ ntaps, IterParams p)
 {
-    constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / 4;
+    constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (NT / 64);
+    static_assert(R >= 1 && TH % (NT / 64) == 0, "rows per thread");
     __shared__ float tile[LH * LW];
     const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < LH * LW; idx += 256) {
+    for (int idx = tid; idx < LH * LW; idx += NT) {
         const int ly = idx / LW, lx = idx - ly * LW;
         const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
         tile[idx] = u[(size_t)gy * pitch + gx];
@@ -92,31 +93,32 @@ __global__ void __launch_bounds__(256) rrrl_taps_stage1(const float* __restrict_
     }
 }
 
-template <int RAD, int TH>
-__global__ void __launch_bounds__(256) rrrl_taps_stage2(const float2* __restrict__ qw, const float* __restrict__ u,
-                                                        float* __restrict__ u_next, float* __restrict__ ckpt,
-                                                        int H, int W, int pitch, const int4* __restrict__ taps,
-                                                        const int* __restrict__ ntaps, IterParams p)
+template <int RAD, int TH, int NT>
+__global__ void __launch_bounds__(NT) rrrl_taps_stage2(const float2* __restrict__ qw, const float* __restrict__ u,
+                                                       float* __restrict__ u_next, float* __restrict__ ckpt,
+                                                       int H, int W, int pitch, const int4* __restrict__ taps,
+                                                       const int* __restrict__ ntaps, IterParams p)
 {
-    constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / 4;
+    constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (NT / 64);
+    static_assert(R >= 1 && TH % (NT / 64) == 0, "rows per thread");
     constexpr int UW = TW + 4, UH = TH + 4, GW = TW + 2, GH = TH + 2;
     __shared__ float2 qt[LH * LW];
     __shared__ float ut[UH * UW];
     __shared__ float gt[GH * GW];
     const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < LH * LW; idx += 256) {
+    for (int idx = tid; idx < LH * LW; idx += NT) {
         const int ly = idx / LW, lx = idx - ly * LW;
         const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
         qt[idx] = qw[(size_t)gy * W + gx];
     }
-    for (int idx = tid; idx < UH * UW; idx += 256) {
+    for (int idx = tid; idx < UH * UW; idx += NT) {
         const int ly = idx / UW, lx = idx - ly * UW;
         ut[idx] = u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
     }
     __syncthreads();
     // diffusivity g = Psi'(|grad u|^2) by central differences at pixels
-    for (int idx = tid; idx < GH * GW; idx += 256) {
+    for (int idx = tid; idx < GH * GW; idx += NT) {
         const int a = idx / GW, b = idx - a * GW;
         const float gx = 0.5f * (ut[(a + 1) * UW + b + 2] - ut[(a + 1) * UW + b]);
         const float gy = 0.5f * (ut[(a + 2) * UW + b + 1] - ut[a * UW + b + 1]);
@@ -173,23 +175,69 @@ int tap_radius_class(int rad)
     return -1;
 }
 
-template <int RAD>
-static void launch_stage1_t(const float* f, const float* u, float2* qw, int H, int W, int pitch,
-                            const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+// Tile variants (rows per tile TH, threads per workgroup NT); every variant
+// visits the taps of a pixel in the same order, so results are bitwise equal.
+struct TileVariant {
+    int th, nt;
+};
+static constexpr TileVariant kVariants[] = {{64, 1024}, {64, 256}, {32, 256}, {32, 512}, {16, 256}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int taps_num_variants() { return kNumVariants; }
+
+template <int RAD, int TH, int NT>
+static void stage1_inst(const float* f, const float* u, float2* qw, int H, int W, int pitch, const int4* taps,
+                        const int* nt, const IterParams& p, hipStream_t st)
 {
-    constexpr int TH1 = RAD >= 32 ? 32 : 64;
-    const dim3 g1((W + 63) / 64, (H + TH1 - 1) / TH1);
-    hipLaunchKernelGGL((rrrl_taps_stage1<RAD, TH1>), g1, dim3(256), 0, st, u, f, qw, H, W, pitch, taps, nt, p);
+    const dim3 g((W + 63) / 64, (H + TH - 1) / TH);
+    hipLaunchKernelGGL((rrrl_taps_stage1<RAD, TH, NT>), g, dim3(NT), 0, st, u, f, qw, H, W, pitch, taps, nt, p);
+}
+
+template <int RAD, int TH, int NT>
+static void stage2_inst(const float2* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
+                        const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+{
+    const dim3 g((W + 63) / 64, (H + TH - 1) / TH);
+    hipLaunchKernelGGL((rrrl_taps_stage2<RAD, TH, NT>), g, dim3(NT), 0, st, qw, u, un, ckpt, H, W, pitch, taps, nt,
+                       p);
 }
 
 template <int RAD>
-static void launch_stage2_t(const float2* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
+static void launch_stage1_t(int v, const float* f, const float* u, float2* qw, int H, int W, int pitch,
                             const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
-    constexpr int TH2 = 32;
-    const dim3 g2((W + 63) / 64, (H + TH2 - 1) / TH2);
-    hipLaunchKernelGGL((rrrl_taps_stage2<RAD, TH2>), g2, dim3(256), 0, st, qw, u, un, ckpt, H, W, pitch, taps,
-                       nt, p);
+    switch (v) {
+        case 0: stage1_inst<RAD, 64, 1024>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
+        case 1: stage1_inst<RAD, 64, 256>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
+        case 2: stage1_inst<RAD, 32, 256>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
+        case 3: stage1_inst<RAD, 32, 512>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
+        default: stage1_inst<RAD, 16, 256>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
+    }
+}
+
+template <int RAD>
+static void launch_stage2_t(int v, const float2* qw, const float* u, float* un, float* ckpt, int H, int W,
+                            int pitch, const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+{
+    // 64-row tiles of the two-channel plane exceed LDS for the largest radius
+    if (RAD >= 32 && (v == 0 || v == 1)) v = 3;
+    switch (v) {
+        case 0: stage2_inst<RAD, (RAD >= 32 ? 32 : 64), 1024>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 1: stage2_inst<RAD, (RAD >= 32 ? 32 : 64), 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 2: stage2_inst<RAD, 32, 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 3: stage2_inst<RAD, 32, 512>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        default: stage2_inst<RAD, 16, 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+    }
+}
+
+// Default variant when the caller does not choose one: enough tiles to give
+// every CU several workgroups, else the smallest tiles.
+static int default_variant(int H, int W, int stage)
+{
+    const long tiles64 = (long)((W + 63) / 64) * ((H + 63) / 64);
+    if (tiles64 >= 1024) return stage == 1 ? 1 : 2;
+    if (tiles64 >= 256) return stage == 1 ? 0 : 3;
+    return 4;
 }
 
 size_t tap_list_bytes(const PsfDev& psf) { return 256 + 16 * (size_t)psf.ph * psf.pw; }
@@ -207,34 +255,36 @@ static int psf_radius_class(const PsfDev& psf)
 }
 
 int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, int pitch, const PsfDev& psf,
-                       const void* list, const IterParams& p, hipStream_t st)
+                       const void* list, const IterParams& p, int variant, hipStream_t st)
 {
+    const int v = variant > 0 ? variant - 1 : default_variant(H, W, 1);
     const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
     const int* nt = reinterpret_cast<const int*>(w8);
     const int4* taps = reinterpret_cast<const int4*>(w8 + 256);
     float2* q2 = reinterpret_cast<float2*>(qw);
     switch (psf_radius_class(psf)) {
-        case 4: launch_stage1_t<4>(f, u, q2, H, W, pitch, taps, nt, p, st); break;
-        case 8: launch_stage1_t<8>(f, u, q2, H, W, pitch, taps, nt, p, st); break;
-        case 16: launch_stage1_t<16>(f, u, q2, H, W, pitch, taps, nt, p, st); break;
-        case 32: launch_stage1_t<32>(f, u, q2, H, W, pitch, taps, nt, p, st); break;
+        case 4: launch_stage1_t<4>(v, f, u, q2, H, W, pitch, taps, nt, p, st); break;
+        case 8: launch_stage1_t<8>(v, f, u, q2, H, W, pitch, taps, nt, p, st); break;
+        case 16: launch_stage1_t<16>(v, f, u, q2, H, W, pitch, taps, nt, p, st); break;
+        case 32: launch_stage1_t<32>(v, f, u, q2, H, W, pitch, taps, nt, p, st); break;
         default: return -2;
     }
     return 0;
 }
 
 int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
-                       const PsfDev& psf, const void* list, const IterParams& p, hipStream_t st)
+                       const PsfDev& psf, const void* list, const IterParams& p, int variant, hipStream_t st)
 {
+    const int v = variant > 0 ? variant - 1 : default_variant(H, W, 2);
     const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
     const int* nt = reinterpret_cast<const int*>(w8);
     const int4* taps = reinterpret_cast<const int4*>(w8 + 256);
     const float2* q2 = reinterpret_cast<const float2*>(qw);
     switch (psf_radius_class(psf)) {
-        case 4: launch_stage2_t<4>(q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 8: launch_stage2_t<8>(q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 16: launch_stage2_t<16>(q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 32: launch_stage2_t<32>(q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 4: launch_stage2_t<4>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 8: launch_stage2_t<8>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 16: launch_stage2_t<16>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 32: launch_stage2_t<32>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
         default: return -2;
     }
     return 0;

@@ -55,7 +55,7 @@ def taps(ph, pw, ptr=0x60000000):
 
 
 def params(**kw):
-    d = dict(alpha=0.003, eps_data=0.1, eps_tv=0.1, s_min=1e-12, iters=3, robust=1, boundary=0, conv=0)
+    d = dict(alpha=0.003, eps_data=0.1, eps_tv=0.1, s_min=1e-12, iters=3, robust=1, boundary=0, conv=0, tile=0)
     d.update(kw)
     return _lib.deblur_params(*[d[k] for k, _ in _lib.deblur_params._fields_])
 
@@ -120,6 +120,9 @@ def test_iterate_validation(lib):
     assert iterate(lib, p=params(robust=2)) == E
     assert iterate(lib, p=params(boundary=5)) == E
     assert iterate(lib, p=params(conv=9)) == E
+    assert iterate(lib, p=params(tile=-1)) == E
+    assert iterate(lib, p=params(tile=lib.deblur_tile_variants() + 1)) == E
+    assert iterate(lib, p=params(tile=lib.deblur_tile_variants()), psf=taps(5, 5)) == W_
     assert iterate(lib, psf=taps(3, 3), p=params(conv=_lib.CONV_RUNSUM)) == E
     assert iterate(lib, psf=taps(67, 1)) == U_
     assert iterate(lib, uo=F) == E                                # u_out overlaps f

@@ -289,3 +289,26 @@ def test_box_running_sum_matches_stencil_path():
         dbl.deblur_rrrl_iterate(dev(f), dev(u0), out, dbl.Psf.box(21, "v"), dbl.Params(iters=8, conv=conv))
         outs.append(out.cpu().numpy())
     assert report("runsum vs stencil", outs[0], outs[1]) <= 1e-5
+
+
+@pytest.mark.parametrize("H,W,psfname", [(1024, 1024, "line31"), (100, 70, "line9"), (300, 200, "gauss31"),
+                                         (96, 130, "box63")])
+def test_tile_variants_bitwise_identical(H, W, psfname):
+    """Every tile shape of the stencil kernels gives bitwise-identical output
+    (the taps of a pixel are always summed in the same order)."""
+    rng = np.random.default_rng(51)
+    h = {"line31": lambda: synth.line_psf(31, 0.3), "line9": lambda: synth.line_psf(9, 1.9),
+         "gauss31": lambda: synth.gauss_mixture_psf(synth.rng_for(2), 31),
+         "box63": lambda: synth.box_psf(63, "v")}[psfname]().astype(np.float32)
+    f = dev(synth.observe(rng, synth.ground_truth(rng, H, W), h.astype(np.float64), 2.0))
+    psf = gpu_psf(synth.KIND_TAPS, 0, h)
+    u0 = torch.clamp(f, min=1.0)
+    ref = None
+    nvar = dbl._lib.load().deblur_tile_variants()
+    for v in range(0, nvar + 1):
+        out = torch.empty_like(f)
+        dbl.deblur_rrrl_iterate(f, u0, out, psf, dbl.Params(iters=3, tile=v))
+        if ref is None:
+            ref = out
+        else:
+            assert torch.equal(out, ref), f"tile variant {v} differs"
