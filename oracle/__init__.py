@@ -203,3 +203,93 @@ def wr3l(f, h, K: float, p: Params, iters: int, pos_floor: float = 1.0,
     """WR3L (Sec. 3.2): Wiener initialisation followed by `iters` RRRL steps."""
     u0 = wiener_init(f, h, K, pos_floor)
     return rrrl(f, u0, h, p, iters, threads=threads)
+
+
+# ------------------------------------------------------------------ adjoint
+def _load_adjoint():
+    lib = _load()
+    if not hasattr(lib, "_adj_ready"):
+        dp = ctypes.POINTER(ctypes.c_double)
+        i = ctypes.c_int
+        lib.orc_rrrl_step_adjoint.argtypes = [dp, dp, i, i, dp, i, i, ctypes.POINTER(_Params), dp, dp, dp, dp, dp, i]
+        lib.orc_rrrl_step_adjoint.restype = None
+        lib._adj_ready = True
+    return lib
+
+
+def rrrl_step_adjoint(f, u, h, p: Params, lam, threads: int | None = None):
+    """Reverse-mode derivative of one RRRL step at u: given lam = dL/du',
+    returns (dL/du, dL/df, dL/dh, dL/dalpha) of that step."""
+    f, u, h, lam = _f64(f), _f64(u), _f64(h), _f64(lam)
+    du = np.empty_like(u)
+    df = np.zeros_like(u)
+    dh = np.zeros_like(h)
+    da = ctypes.c_double(0.0)
+    pp = p.c()
+    _load_adjoint().orc_rrrl_step_adjoint(_ptr(f), _ptr(u), u.shape[0], u.shape[1], _ptr(h), h.shape[0], h.shape[1],
+                                          ctypes.byref(pp), _ptr(lam), _ptr(du), _ptr(df), _ptr(dh),
+                                          ctypes.byref(da), threads or default_threads())
+    return du, df, dh, da.value
+
+
+def rrrl_adjoint(f, checkpoints, h, p: Params, lam_K, threads: int | None = None):
+    """Backward through the unrolled iterations u^0 -> ... -> u^K given the
+    iterates u^0..u^{K-1} and lam_K = dL/du^K.  Returns (dL/du^0, dL/df,
+    dL/dh, dL/dalpha) with f entering every step."""
+    lam = _f64(lam_K)
+    df = np.zeros_like(lam)
+    dh = np.zeros(np.shape(h))
+    da = 0.0
+    for k in range(len(checkpoints) - 1, -1, -1):
+        lam, dfk, dhk, dak = rrrl_step_adjoint(f, checkpoints[k], h, p, lam, threads)
+        df += dfk
+        dh += dhk
+        da += dak
+    return lam, df, dh, da
+
+
+def wiener_adjoint(f, h, K: float, pos_floor: float, lam0):
+    """Reverse-mode derivative of the WR3L initialisation u0 = max(u_pre,
+    pos_floor), u_pre = Re IDFT(DFT(f) M), M = conj(h^)/(|h^|^2 + K).
+    Returns (dL/df, dL/dh) given lam0 = dL/du0.
+
+    u_pre is linear in f with transpose Re IDFT(DFT(.) conj(M)).  For h:
+    dL = (1/N) sum_k F(k) dM(k) conj(G^(k)) with G = dL/du_pre, and
+    dM/dh(d) = [K e^{+i w.d} - conj(h^)^2 e^{-i w.d}] / (|h^|^2 + K)^2,
+    evaluated tap by tap."""
+    f, h, lam0 = _f64(f), _f64(h), _f64(lam0)
+    H, W = f.shape
+    hh = psf_spectrum(h, H, W)
+    M = np.conj(hh) / (np.abs(hh) ** 2 + K)
+    u_pre = np.real(np.fft.ifft2(np.fft.fft2(f) * M))
+    G = lam0 * (u_pre > pos_floor)
+    Gh = np.fft.fft2(G)
+    df = np.real(np.fft.ifft2(Gh * np.conj(M)))
+    Z = np.fft.fft2(f) * np.conj(Gh) / (H * W)
+    den2 = (np.abs(hh) ** 2 + K) ** 2
+    c1 = K / den2
+    c2 = -np.conj(hh) ** 2 / den2
+    ky = np.arange(H)[:, None] / H
+    kx = np.arange(W)[None, :] / W
+    Py, Px = h.shape
+    cy, cx = (Py - 1) // 2, (Px - 1) // 2
+    dh = np.zeros_like(h)
+    for j in range(Py):
+        for i in range(Px):
+            ph = np.exp(2j * np.pi * (ky * (j - cy) + kx * (i - cx)))
+            dh[j, i] = np.real(np.sum(Z * (c1 * ph + c2 * np.conj(ph))))
+    return df, dh
+
+
+def wr3l_loss_and_grad(f, h, K: float, p: Params, iters: int, g, pos_floor: float = 1.0,
+                       threads: int | None = None):
+    """L = sum (u^K - g)^2 of WR3L and its gradients (dL/df, dL/dh, dL/dalpha)
+    through the Wiener initialisation and the unrolled RRRL iterations."""
+    f = _f64(f)
+    u0 = wiener_init(f, h, K, pos_floor)
+    uK, ck = rrrl(f, u0, h, p, iters, threads=threads, checkpoints=True)
+    r = uK - _f64(g)
+    loss = float(np.sum(r * r))
+    lam0, df, dh, da = rrrl_adjoint(f, ck, h, p, 2.0 * r, threads)
+    dfw, dhw = wiener_adjoint(f, h, K, pos_floor, lam0)
+    return loss, df + dfw, dh + dhw, da

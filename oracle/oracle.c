@@ -189,3 +189,157 @@ void orc_rrrl(const double* f, const double* u0, double* uK, int H, int W,
     free(a);
     free(b);
 }
+
+/* ------------------------------------------------------------------ adjoint
+ * Reverse-mode derivative of one RRRL step u -> u' = step(u; f, h, alpha),
+ * written out term by term from the forward definition above.  Given
+ * lam = dL/du', writes du = dL/du and ACCUMULATES dL/df into df, dL/dh into
+ * dh (Py*Px, every array entry, zero or not) and dL/dalpha into *dalpha.
+ * Derivatives of max/min/clamp are taken as the indicator of the branch
+ * taken (0 at ties); r_f(s) := s for f <= 0 has df = 0 there. */
+
+/* transpose of A: scatter v(x) h(d) onto the continued index of x - d */
+static void blur_T(const double* v, int H, int W, const double* h, int Py, int Px, int bc, double* out)
+{
+    const int cy = (Py - 1) / 2, cx = (Px - 1) / 2;
+    memset(out, 0, sizeof(double) * (size_t)H * W);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int j = 0; j < Py; ++j)
+                for (int i = 0; i < Px; ++i) {
+                    const double w = h[j * Px + i];
+                    if (w == 0.0) continue;
+                    const int dy = j - cy, dx = i - cx;
+                    out[(size_t)ext(y - dy, H, bc) * W + ext(x - dx, W, bc)] += w * v[(size_t)y * W + x];
+                }
+}
+
+/* transpose of B: scatter v(x) h(d) onto the continued index of x + d */
+static void corr_T(const double* v, int H, int W, const double* h, int Py, int Px, int bc, double* out)
+{
+    const int cy = (Py - 1) / 2, cx = (Px - 1) / 2;
+    memset(out, 0, sizeof(double) * (size_t)H * W);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int j = 0; j < Py; ++j)
+                for (int i = 0; i < Px; ++i) {
+                    const double w = h[j * Px + i];
+                    if (w == 0.0) continue;
+                    const int dy = j - cy, dx = i - cx;
+                    out[(size_t)ext(y + dy, H, bc) * W + ext(x + dx, W, bc)] += w * v[(size_t)y * W + x];
+                }
+}
+
+void orc_rrrl_step_adjoint(const double* f, const double* u, int H, int W, const double* h, int Py, int Px,
+                           const orc_params* p, const double* lam, double* du, double* df, double* dh,
+                           double* dalpha, int nthreads)
+{
+    const size_t n = (size_t)H * W;
+    const int cy = (Py - 1) / 2, cx = (Px - 1) / 2;
+    double* buf = (double*)malloc(sizeof(double) * n * 16);
+    double *s = buf, *st = buf + n, *r = buf + 2 * n, *Wt = buf + 3 * n, *q = buf + 4 * n, *N1 = buf + 5 * n,
+           *N2 = buf + 6 * n, *g = buf + 7 * n, *D = buf + 8 * n, *a = buf + 9 * n, *b = buf + 10 * n,
+           *c = buf + 11 * n, *dq = buf + 12 * n, *dW = buf + 13 * n, *ds = buf + 14 * n, *tmp = buf + 15 * n;
+
+    /* forward intermediates */
+    orc_blur(u, H, W, h, Py, Px, p->bc, s, nthreads);
+    for (size_t i = 0; i < n; ++i) {
+        st[i] = s[i] > p->s_min ? s[i] : p->s_min;
+        r[i] = orc_rf(f[i], st[i]);
+        Wt[i] = p->robust ? pen_deriv(r[i] > 0.0 ? r[i] : 0.0, p->eps_data) : 1.0;
+        q[i] = Wt[i] * (f[i] > 0.0 ? f[i] : 0.0) / st[i];
+    }
+    orc_corr(q, H, W, h, Py, Px, p->bc, N1, nthreads);
+    orc_corr(Wt, H, W, h, Py, Px, p->bc, N2, nthreads);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const int xm = ext(x - 1, W, ORC_BC_REPLICATE), xp = ext(x + 1, W, ORC_BC_REPLICATE);
+            const int ym = ext(y - 1, H, ORC_BC_REPLICATE), yp = ext(y + 1, H, ORC_BC_REPLICATE);
+            const double gx = (u[(size_t)y * W + xp] - u[(size_t)y * W + xm]) / 2.0;
+            const double gy = (u[(size_t)yp * W + x] - u[(size_t)ym * W + x]) / 2.0;
+            g[(size_t)y * W + x] = pen_deriv(gx * gx + gy * gy, p->eps_tv);
+        }
+    orc_tv(u, H, W, p->eps_tv, D, nthreads);
+
+    /* update u' = u * Num / Den */
+    for (size_t i = 0; i < n; ++i) {
+        const double dp = D[i] > 0.0 ? D[i] : 0.0, dm = D[i] < 0.0 ? D[i] : 0.0;
+        const double num = N1[i] + p->alpha * dp, den = N2[i] - p->alpha * dm;
+        du[i] = lam[i] * num / den;
+        a[i] = lam[i] * u[i] / den;                 /* dL/dNum = dL/dN1 */
+        b[i] = -lam[i] * u[i] * num / (den * den);  /* dL/dDen = dL/dN2 */
+        *dalpha += a[i] * dp - b[i] * dm;
+        c[i] = p->alpha * (a[i] * (D[i] > 0.0 ? 1.0 : 0.0) - b[i] * (D[i] < 0.0 ? 1.0 : 0.0)); /* dL/dD */
+    }
+    /* N1 = B q, N2 = B W */
+    corr_T(a, H, W, h, Py, Px, p->bc, dq);
+    corr_T(b, H, W, h, Py, Px, p->bc, dW);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int j = 0; j < Py; ++j)
+                for (int i = 0; i < Px; ++i) {
+                    const size_t src = (size_t)ext(y + j - cy, H, p->bc) * W + ext(x + i - cx, W, p->bc);
+                    const size_t o = (size_t)y * W + x;
+                    dh[j * Px + i] += a[o] * q[src] + b[o] * Wt[src];
+                }
+    /* q = W f+ / s~,  W = phi(r),  r = r_f(s~),  s~ = max(s, s_min) */
+    for (size_t i = 0; i < n; ++i) {
+        const double fp = f[i] > 0.0 ? f[i] : 0.0;
+        double dWi = dW[i] + dq[i] * fp / st[i];
+        double dst = -dq[i] * Wt[i] * fp / (st[i] * st[i]);
+        if (f[i] > 0.0) df[i] += dq[i] * Wt[i] / st[i];
+        if (p->robust) {
+            const double dr = r[i] > 0.0 ? dWi * (-0.5) * Wt[i] * Wt[i] * Wt[i] : 0.0;
+            if (f[i] > 0.0) {
+                dst += dr * (1.0 - f[i] / st[i]);
+                df[i] += dr * (-log(st[i] / f[i]));
+            } else {
+                dst += dr;
+            }
+        }
+        ds[i] = s[i] > p->s_min ? dst : 0.0;
+    }
+    /* s = A u */
+    blur_T(ds, H, W, h, Py, Px, p->bc, tmp);
+    for (size_t i = 0; i < n; ++i) du[i] += tmp[i];
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int j = 0; j < Py; ++j)
+                for (int i = 0; i < Px; ++i) {
+                    const size_t src = (size_t)ext(y - (j - cy), H, p->bc) * W + ext(x - (i - cx), W, p->bc);
+                    dh[j * Px + i] += ds[(size_t)y * W + x] * u[src];
+                }
+    /* D = sum_n (g_p + g_n)/2 (u_n - u_p): with g frozen, and through g */
+    double* dg = dq;  /* reuse */
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const size_t pp = (size_t)y * W + x;
+            const int ny[4] = {y - 1, y + 1, y, y};
+            const int nx[4] = {x, x, x - 1, x + 1};
+            double acc = 0.0, accg = 0.0;
+            for (int k = 0; k < 4; ++k) {
+                if (ny[k] < 0 || ny[k] >= H || nx[k] < 0 || nx[k] >= W) continue;
+                const size_t nn = (size_t)ny[k] * W + nx[k];
+                acc += 0.5 * (g[pp] + g[nn]) * (c[nn] - c[pp]);
+                accg += 0.5 * (u[nn] - u[pp]) * (c[pp] - c[nn]);
+            }
+            du[pp] += acc;
+            dg[pp] = accg;
+        }
+    /* g = psi(gx^2 + gy^2), central differences with clamped neighbours */
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const size_t pp = (size_t)y * W + x;
+            const int xm = ext(x - 1, W, ORC_BC_REPLICATE), xp = ext(x + 1, W, ORC_BC_REPLICATE);
+            const int ym = ext(y - 1, H, ORC_BC_REPLICATE), yp = ext(y + 1, H, ORC_BC_REPLICATE);
+            const double gx = (u[(size_t)y * W + xp] - u[(size_t)y * W + xm]) / 2.0;
+            const double gy = (u[(size_t)yp * W + x] - u[(size_t)ym * W + x]) / 2.0;
+            const double g3 = g[pp] * g[pp] * g[pp];
+            const double dgx = dg[pp] * (-g3 * gx), dgy = dg[pp] * (-g3 * gy);
+            du[(size_t)y * W + xp] += 0.5 * dgx;
+            du[(size_t)y * W + xm] -= 0.5 * dgx;
+            du[(size_t)yp * W + x] += 0.5 * dgy;
+            du[(size_t)ym * W + x] -= 0.5 * dgy;
+        }
+    free(buf);
+}

@@ -34,6 +34,10 @@ void orc_rrrl(const double* f, const double* u0, double* uK, int H, int W,
               const double* h, int Py, int Px, const orc_params* p, int iters,
               double* ckpt, int nthreads);
 
+void orc_rrrl_step_adjoint(const double* f, const double* u, int H, int W, const double* h, int Py, int Px,
+                           const orc_params* p, const double* lam, double* du, double* df, double* dh,
+                           double* dalpha, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif
