@@ -17,8 +17,8 @@ included).  The JSON line also carries:
   * cpu_baseline: the FP64 oracle on the host cores for the same workload.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
-       python bench.py --ingest-pmc DIR   (turn rocprofv3 --pmc results into
-                                           profiles/<kernel>_traffic.json)
+       python bench.py --ingest-pmc DIR   (rocprofv3 --pmc databases -> profiles/)
+       python bench.py --summarize-trace DB OUT   (rocprofv3 kernel trace -> markdown)
 """
 from __future__ import annotations
 
@@ -61,58 +61,62 @@ def parse_args():
     ap.add_argument("--cpu-iters", type=int, default=20, help="RRRL iterations in the oracle sample")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--ingest-pmc", metavar="DIR", help="parse rocprofv3 --pmc output and exit")
+    ap.add_argument("--ingest-pmc", metavar="DIR", help="parse rocprofv3 --pmc databases and exit")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT"),
+                    help="write a markdown summary of a rocprofv3 --kernel-trace database and exit")
+    ap.add_argument("--command", default="", help="command line recorded in summaries")
     return ap.parse_args()
 
 
-# ---------------------------------------------------------------- pmc ingest
-def ingest_pmc(d: str) -> None:
-    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the stage kernels
-    and of the calibration copy kernel from rocprofv3 counter_collection CSVs
-    under `d`, scaled by the copy's bytes, into profiles/<kernel>_traffic.json."""
-    import csv
-    rows = []
-    for p in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-        with open(p) as fh:
-            rows += list(csv.DictReader(fh))
-    if not rows:
-        raise SystemExit(f"no counter_collection.csv under {d}")
-    vals: dict[tuple[str, str], list[float]] = {}
-    for r in rows:
-        name = r.get("Kernel_Name", "")
-        ctr = r.get("Counter_Name", "")
-        v = float(r.get("Counter_Value", "nan"))
-        key = None
+# ------------------------------------------------------------- profiles
+def _rocpd_rows(db: str, sql: str):
+    import sqlite3
+    con = sqlite3.connect(db)
+    try:
+        return list(con.execute(sql))
+    finally:
+        con.close()
+
+
+def summarize_trace(db: str, out: str, command: str) -> None:
+    """Per-kernel summary (calls, total, average duration) of a rocprofv3
+    --kernel-trace database, as a short markdown file."""
+    rows = _rocpd_rows(db, "select name, total_calls, total_duration, average, percentage from top_kernels")
+    lines = [f"# rocprofv3 kernel trace: {os.path.basename(out)}", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | total us | avg us | % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in rows:
+        short = name.split("(")[0].replace("void ", "")
+        lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.3f} | {pct:.1f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def ingest_pmc(d: str, command: str = "") -> None:
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the kernels from two
+    rocprofv3 --pmc databases under d/fetch and d/write, scaled by what the
+    same counters read for the largest plain device copy in the same run
+    (bench.py --pmc-calibrate copies 256 MiB), into
+    profiles/stage_kernels_traffic.json."""
+    res = {"source_hash": kernel_source_hash(), "command": command, "kernels": {}}
+    scale = {}
+    for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        dbs = glob.glob(os.path.join(d, sub, "**", "*.db"), recursive=True)
+        if not dbs:
+            raise SystemExit(f"no database under {os.path.join(d, sub)}")
+        rows = _rocpd_rows(dbs[0], "select kernel_name, value, grid_size from counters_collection "
+                                   f"where counter_name = '{ctr}'")
+        copies = [r for r in rows if "copyBuffer" in r[0]]
+        big = max(copies, key=lambda r: r[2])
+        copy_bytes = json.load(open(os.path.join(d, "calib.json")))["copy_bytes"]
+        scale[ctr] = copy_bytes / (big[1] * 1024.0)
         for k, frag in KERNELS.items():
-            if frag in name:
-                key = k
-        if "copy" in name.lower() or "elementwise" in name.lower():
-            key = "copy"
-        if key:
-            vals.setdefault((key, ctr), []).append(v)
-    meta = json.load(open(os.path.join(d, "calib.json"))) if os.path.exists(os.path.join(d, "calib.json")) else {}
-    out = {}
-    for (k, c), v in vals.items():
-        out.setdefault(k, {})[c] = sum(v) / len(v)
-    copy_bytes = meta.get("copy_bytes")
-    res = {"source_hash": kernel_source_hash(), "raw_kib_per_dispatch": out, "copy_bytes": copy_bytes}
-    if copy_bytes and "copy" in out:
-        # a copy of N bytes reads N and writes N: scale = true bytes / counter reading
-        fs = out["copy"].get("FETCH_SIZE")
-        ws = out["copy"].get("WRITE_SIZE")
-        res["fetch_scale"] = copy_bytes / (fs * 1024.0) if fs else None
-        res["write_scale"] = copy_bytes / (ws * 1024.0) if ws else None
-    for k in KERNELS:
-        if k in out:
-            fs, ws = out[k].get("FETCH_SIZE"), out[k].get("WRITE_SIZE")
-            tb = 0.0
-            ok = True
-            for v, sc in ((fs, res.get("fetch_scale")), (ws, res.get("write_scale"))):
-                if v is None or sc is None:
-                    ok = False
-                else:
-                    tb += v * 1024.0 * sc
-            res[k] = {"traffic_bytes": tb if ok else None}
+            vals = [r[1] for r in rows if frag in r[0]]
+            if vals:
+                res["kernels"].setdefault(k, {})[ctr + "_KiB"] = sum(vals) / len(vals)
+    res["scale"] = scale
+    for k, v in res["kernels"].items():
+        v["traffic_bytes"] = (v["FETCH_SIZE_KiB"] * scale["FETCH_SIZE"] + v["WRITE_SIZE_KiB"] * scale["WRITE_SIZE"]) * 1024.0
     os.makedirs(PROFILES, exist_ok=True)
     with open(os.path.join(PROFILES, "stage_kernels_traffic.json"), "w") as fh:
         json.dump(res, fh, indent=1)
@@ -126,14 +130,17 @@ def load_traffic(kernel: str):
     d = json.load(open(p))
     if d.get("source_hash") != kernel_source_hash():
         return None  # kernels changed since the counters were taken
-    return (d.get(kernel) or {}).get("traffic_bytes")
+    return (d.get("kernels", {}).get(kernel) or {}).get("traffic_bytes")
 
 
 # ------------------------------------------------------------------- bench
 def main():
     args = parse_args()
     if args.ingest_pmc:
-        ingest_pmc(args.ingest_pmc)
+        ingest_pmc(args.ingest_pmc, args.command)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
