@@ -95,8 +95,10 @@ int deblur_version(void);
 int deblur_tile_variants(void);
 
 /* Workspace bytes needed by an entry point: op 0 = deblur_wiener,
- * 1 = deblur_rrrl_iterate.  Returns 0 for invalid arguments (the matching
- * call then returns DEBLUR_EINVAL or DEBLUR_EUNSUPPORTED). */
+ * 1 = deblur_rrrl_iterate, 2 = deblur_rrrl_backward without the Wiener step,
+ * 3 = deblur_rrrl_backward through the Wiener step.  Returns 0 for invalid
+ * arguments (the matching call then returns DEBLUR_EINVAL or
+ * DEBLUR_EUNSUPPORTED). */
 size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
                               const deblur_params* p);
 
@@ -122,6 +124,30 @@ int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch
 int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t H, int32_t W, int32_t pitch,
                         const deblur_psf* psf, const deblur_params* p, float* ckpt, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* Reverse-mode derivative of a loss L(u^K) through p->iters unrolled RRRL
+ * iterations (eqs. (9)-(12)) and, if through_wiener, through the Wiener
+ * initialisation with its positivity floor (eq. (2), Sec. 3.2), for the
+ * observed image f, the PSF entries and alpha.
+ *   ckpt:     device, p->iters * H * pitch floats: u^0 .. u^{K-1} as written by
+ *             deblur_rrrl_iterate (may be NULL when p->iters == 0);
+ *   grad_uK:  device H x pitch, dL/du^K;
+ *   grad_f:   device H x pitch, receives dL/df (overwritten);
+ *   grad_taps (nullable): device array of the PSF's ph*pw entries (boxes: the
+ *             1 x P or P x 1 array of the box), receives dL/dh for every entry,
+ *             zero or not (overwritten);
+ *   grad_alpha (nullable): device scalar, receives dL/dalpha;
+ *   grad_u0 (nullable): device H x pitch, receives dL/du^0 (the derivative at
+ *             the Wiener output, before the Wiener adjoint).
+ * K, pos_floor: the Wiener parameters of the forward call (used when
+ * through_wiener; then H and W must be 2^a 3^b <= 2048).  Derivatives of
+ * max/min take the branch taken (0 at ties); d r_f/df is taken as 0 where
+ * f <= 0.  Partial sums are reduced in a fixed order: results are
+ * deterministic.  Output buffers must not overlap the inputs. */
+int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int32_t H, int32_t W,
+                         int32_t pitch, const deblur_psf* psf, const deblur_params* p, int32_t through_wiener,
+                         double K, float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha,
+                         float* grad_u0, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Stage-level entry points of one RRRL iteration (spatial stencil path).
  * deblur_rrrl_iterate chains them; they are exported for callers that

@@ -201,3 +201,84 @@ def deblur_rrrl_update(qw: torch.Tensor, u: torch.Tensor, u_out: torch.Tensor, p
                                 ctypes.byref(cpsf), taps.data_ptr(), ctypes.byref(cpar), _stream(u))
     _lib.check(st, "deblur_rrrl_update")
     return u_out
+
+
+# -------------------------------------------------------------- backward
+__all__ += ["deblur_rrrl_backward", "WR3LFunction", "wr3l_autograd"]
+
+
+def deblur_rrrl_backward(f: torch.Tensor, ckpt: torch.Tensor | None, grad_uK: torch.Tensor, psf: Psf,
+                         params: Params, through_wiener: bool = True, K: float = 0.01, pos_floor: float = 1.0,
+                         grad_taps: bool = True, grad_alpha: bool = True, grad_u0: bool = False,
+                         ws: torch.Tensor | None = None) -> dict:
+    """Gradients of L(u^K) given dL/du^K = grad_uK: returns a dict with
+    'f' (dL/df), 'taps' (dL/dh for every PSF entry), 'alpha', 'u0'."""
+    lib = _lib.load()
+    H, W, pitch = _image(f, "f")
+    _same_layout((H, W, pitch), _image(grad_uK, "grad_uK"), "f", "grad_uK")
+    if params.iters > 0 and (ckpt is None or not ckpt.is_contiguous() or ckpt.numel() < params.iters * H * pitch):
+        raise ValueError("ckpt must hold iters * H * pitch floats")
+    cpsf, cpar = psf.c(), params.c()
+    op = _lib.OP_BACKWARD_WIENER if through_wiener else _lib.OP_BACKWARD
+    need = lib.deblur_workspace_bytes(op, H, W, pitch, ctypes.byref(cpsf), ctypes.byref(cpar))
+    wst = _workspace(need, f, ws)
+    out = {"f": torch.empty_strided((H, W), (pitch, 1), dtype=torch.float32, device=f.device)}
+    ph, pw = (cpsf.ph, cpsf.pw) if psf.kind == PSF_TAPS else (
+        (1, psf.length + (1 - psf.length % 2)) if psf.kind == PSF_BOX_H else (psf.length + (1 - psf.length % 2), 1))
+    if grad_taps:
+        out["taps"] = torch.empty((ph, pw), dtype=torch.float32, device=f.device)
+    if grad_alpha:
+        out["alpha"] = torch.empty((), dtype=torch.float32, device=f.device)
+    if grad_u0:
+        out["u0"] = torch.empty_strided((H, W), (pitch, 1), dtype=torch.float32, device=f.device)
+    st = lib.deblur_rrrl_backward(f.data_ptr(), ckpt.data_ptr() if ckpt is not None else None, grad_uK.data_ptr(),
+                                  H, W, pitch, ctypes.byref(cpsf), ctypes.byref(cpar), int(bool(through_wiener)),
+                                  float(K), float(pos_floor), out["f"].data_ptr(),
+                                  out["taps"].data_ptr() if grad_taps else None,
+                                  out["alpha"].data_ptr() if grad_alpha else None,
+                                  out["u0"].data_ptr() if grad_u0 else None, wst.data_ptr(), wst.numel(), _stream(f))
+    _lib.check(st, "deblur_rrrl_backward")
+    return out
+
+
+class WR3LFunction(torch.autograd.Function):
+    """u = WR3L(f; h, alpha) with the hand-written adjoint as backward.
+
+    forward(f [H,W], taps [ph,pw] (general PSF entries), alpha (0-dim tensor),
+    K, iters, params_template) stores the per-iteration checkpoints u^k and
+    the backward recomputes every other quantity from them."""
+
+    @staticmethod
+    def forward(ctx, f, taps, alpha, K: float, iters: int, template: Params | None = None):
+        base = template or Params()
+        params = Params(alpha=float(alpha), iters=int(iters), eps_data=base.eps_data, eps_tv=base.eps_tv,
+                        s_min=base.s_min, robust=base.robust, boundary=base.boundary, conv=base.conv,
+                        tile=base.tile)
+        f = f.contiguous()
+        psf = Psf.from_taps(taps.detach().contiguous())
+        H, W = f.shape
+        u = torch.empty_like(f)
+        deblur_wiener(f, u, psf, K, 1.0)
+        ck = torch.empty((max(iters, 1), H, W), dtype=torch.float32, device=f.device)
+        deblur_rrrl_iterate(f, u, u, psf, params, ckpt=ck if iters > 0 else None)
+        ctx.save_for_backward(f, psf.taps, ck)
+        ctx.params, ctx.K = params, K
+        ctx.alpha_like = alpha if isinstance(alpha, torch.Tensor) else None
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        f, taps, ck = ctx.saved_tensors
+        g = deblur_rrrl_backward(f, ck if ctx.params.iters > 0 else None, grad_u.contiguous(), Psf.from_taps(taps),
+                                 ctx.params, through_wiener=True, K=ctx.K)
+        ga = g["alpha"]
+        if ctx.alpha_like is not None:
+            ga = ga.to(device=ctx.alpha_like.device, dtype=ctx.alpha_like.dtype)
+        return g["f"], g["taps"], ga, None, None, None
+
+
+def wr3l_autograd(f: torch.Tensor, taps: torch.Tensor, alpha: torch.Tensor, K: float = 0.01, iters: int = 10,
+                  template: Params | None = None) -> torch.Tensor:
+    """Differentiable WR3L (w.r.t. f, taps, alpha) through the library's
+    forward and backward kernels."""
+    return WR3LFunction.apply(f, taps, alpha, K, iters, template)

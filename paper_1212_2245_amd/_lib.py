@@ -18,7 +18,7 @@ PSF_BOX_H, PSF_BOX_V, PSF_TAPS = 0, 1, 2
 BC_REPLICATE, BC_PERIODIC = 0, 1
 CONV_AUTO, CONV_RUNSUM, CONV_STENCIL = 0, 1, 2
 
-OP_WIENER, OP_ITERATE = 0, 1
+OP_WIENER, OP_ITERATE, OP_BACKWARD, OP_BACKWARD_WIENER = 0, 1, 2, 3
 
 
 class deblur_psf(ctypes.Structure):
@@ -43,6 +43,8 @@ SIGNATURES = [
     ("deblur_wiener", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _PSF, ctypes.c_double, ctypes.c_float,
                                      _VP, _SZ, _VP]),
     ("deblur_rrrl_iterate", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP, _SZ, _VP]),
+    ("deblur_rrrl_backward", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _I32, ctypes.c_double,
+                                            ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     ("deblur_taps_bytes", _SZ, [_PSF]),
     ("deblur_compile_taps", ctypes.c_int, [_PSF, _VP, _SZ, _VP]),
     ("deblur_rrrl_weights", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _VP, _PAR, _VP]),

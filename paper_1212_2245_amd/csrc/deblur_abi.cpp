@@ -100,6 +100,16 @@ int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, co
     return DEBLUR_OK;
 }
 
+int check_backward(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, const deblur_params* p,
+                   bool through_wiener, PsfDev* d)
+{
+    int s = check_iterate(H, W, pitch, psf, p, d);
+    if (s) return s;
+    if (through_wiener && (!is_2a3b(H) || !is_2a3b(W) || H > kMaxFft || W > kMaxFft)) return DEBLUR_EUNSUPPORTED;
+    if (through_wiener && (d->ph > H || d->pw > W)) return DEBLUR_EINVAL;
+    return DEBLUR_OK;
+}
+
 bool use_box(const PsfDev& d, const deblur_params* p)
 {
     return d.kind != DEBLUR_PSF_TAPS && p->conv != DEBLUR_CONV_STENCIL;
@@ -150,6 +160,10 @@ size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, c
         if (check_iterate(H, W, pitch, psf, p, &d)) return 0;
         return iterate_ws_bytes(H, W, pitch, d, use_box(d, p));
     }
+    if (op == 2 || op == 3) {
+        if (check_backward(H, W, pitch, psf, p, op == 3, &d)) return 0;
+        return backward_ws_bytes(H, W, d, op == 3);
+    }
     return 0;
 }
 
@@ -189,6 +203,33 @@ int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t
     if (!ws || ws_bytes < need) return DEBLUR_EWORKSPACE;
     s = launch_rrrl_iterate(f, u_in, u_out, H, W, pitch, d, iter_params(p), p->iters, ckpt, box, ws,
                             reinterpret_cast<hipStream_t>(stream));
+    return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EUNSUPPORTED : DEBLUR_EDEVICE);
+}
+
+int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int32_t H, int32_t W,
+                         int32_t pitch, const deblur_psf* psf, const deblur_params* p, int32_t through_wiener,
+                         double K, float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha,
+                         float* grad_u0, void* ws, size_t ws_bytes, void* stream)
+{
+    PsfDev d;
+    if (!f || !grad_uK || !grad_f) return DEBLUR_EINVAL;
+    if (through_wiener != 0 && through_wiener != 1) return DEBLUR_EINVAL;
+    int s = check_backward(H, W, pitch, psf, p, through_wiener == 1, &d);
+    if (s) return s;
+    if (p->iters > 0 && !ckpt) return DEBLUR_EINVAL;
+    if (through_wiener && (!(K > 0.0) || !std::isfinite(K) || !std::isfinite(pos_floor))) return DEBLUR_EINVAL;
+    const size_t img = (size_t)H * pitch * sizeof(float);
+    const size_t ck = img * (size_t)p->iters;
+    if (overlaps(grad_f, img, f, img) || overlaps(grad_f, img, grad_uK, img) || (ckpt && overlaps(grad_f, img, ckpt, ck)))
+        return DEBLUR_EINVAL;
+    if (grad_u0 && (overlaps(grad_u0, img, grad_f, img) || overlaps(grad_u0, img, f, img) ||
+                    overlaps(grad_u0, img, grad_uK, img) || (ckpt && overlaps(grad_u0, img, ckpt, ck))))
+        return DEBLUR_EINVAL;
+    const size_t need = backward_ws_bytes(H, W, d, through_wiener == 1);
+    if (!ws || ws_bytes < need) return DEBLUR_EWORKSPACE;
+    s = launch_rrrl_backward(f, ckpt, grad_uK, H, W, pitch, d, iter_params(p), p->iters, through_wiener == 1, K,
+                             pos_floor, grad_f, grad_taps, grad_alpha, grad_u0, ws,
+                             reinterpret_cast<hipStream_t>(stream));
     return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EUNSUPPORTED : DEBLUR_EDEVICE);
 }
 

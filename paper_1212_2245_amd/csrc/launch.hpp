@@ -21,6 +21,15 @@ size_t wiener_ws_bytes(int H, int W, bool rowwise);
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
                   float pos_floor, void* ws, bool rowwise, hipStream_t st);
 
+// 2D transform building blocks on half spectra H x (W/2+1) (complex64)
+void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st);
+void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st);
+void launch_fft2_inverse(float2* S, int H, int W, float* out, int pitch, float floor_, bool accumulate,
+                         hipStream_t st);
+void launch_spectral_mul(const float2* Sin, const float2* M, bool conjM, float2* Sout, size_t n, hipStream_t st);
+void launch_wiener_dh_prep(const float2* Fh, const float2* Gh, const float2* hh, float2* Y, size_t n, double K,
+                           hipStream_t st);
+
 int tap_radius_class(int rad);
 size_t tap_list_bytes(const PsfDev& psf);
 void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st);
@@ -28,7 +37,7 @@ void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st);
 // = an explicit tile shape (all give bitwise-identical results).
 int taps_num_variants();
 int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, int pitch, const PsfDev& psf,
-                       const void* list, const IterParams& p, int variant, hipStream_t st);
+                       const void* list, const IterParams& p, int variant, hipStream_t st, float* s_out = nullptr);
 int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
                        const PsfDev& psf, const void* list, const IterParams& p, int variant, hipStream_t st);
 
@@ -43,5 +52,13 @@ size_t iterate_ws_bytes(int H, int W, int pitch, const PsfDev& psf, bool use_box
 int launch_rrrl_iterate(const float* f, const float* u_in, float* u_out, int H, int W, int pitch,
                         const PsfDev& psf, const IterParams& p, int iters, float* ckpt, bool use_box, void* ws,
                         hipStream_t st);
+
+// Backward through WR3L (iterations from checkpoints, optionally the Wiener
+// initialisation).
+size_t backward_ws_bytes(int H, int W, const PsfDev& psf, bool through_wiener);
+int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int H, int W, int pitch,
+                         const PsfDev& psf, const IterParams& p, int iters, bool through_wiener, double K,
+                         float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0,
+                         void* ws, hipStream_t st);
 
 }  // namespace deblur

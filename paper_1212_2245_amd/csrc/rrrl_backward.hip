@@ -1,0 +1,657 @@
+// Backward (reverse-mode) pass through WR3L: the unrolled RRRL iterations
+// (Sec. 2.3, eqs. (9)-(12)) and the Wiener initialisation with its positivity
+// floor (Sec. 2.1 eq. (2), Sec. 3.2), for gradients of a loss L(u^K) with
+// respect to the observed image f, the PSF taps h and the weight alpha.
+//
+// Per reversed iteration k (lam = dL/du^{k+1}), from the checkpoint u^k:
+//   recompute  s = A u (raw), W, q                      (stage-1 kernel)
+//   adj_update N1, N2, D, g; a = lam u/Den, b = -lam u Num/Den^2,
+//              c = alpha (a 1[D>0] - b 1[D<0]), du = lam Num/Den, alpha part
+//   dq, dW_B = B^T (a, b)        B^T = zero-extended convolution + border fold
+//   adj_point  W, q, r_f, s chain -> ds; df accumulated
+//   A^T ds                       zero-extended correlation + border fold
+//   adj_tv     lam' = du + A^T ds + diffusion adjoint (frozen g and through g)
+//   adj_dh     per-workgroup partial sums of dL/dh(d) for every PSF entry
+// Under periodic continuation B^T = A and A^T = B (wrapped, no fold).
+// The transpose of a gather from the constant continuation E(v)(x) =
+// v(clamp(x)) is a scatter onto clamp(x): outputs are formed on a grid
+// extended by the PSF radius and the extension is summed onto the border
+// pixels (fold).  Partial sums are reduced in a fixed order (deterministic).
+#include <cmath>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "psf.hpp"
+
+namespace deblur {
+
+constexpr int BW_TW = 64, BW_NT = 256;
+
+// ------------------------------------------------ adjoint of the update step
+template <int RAD, int TH>
+__global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ qw, const float* __restrict__ u,
+                                                    const float* __restrict__ lam, int lam_pitch,
+                                                    float2* __restrict__ ab, float* __restrict__ cpl,
+                                                    float* __restrict__ du, double* __restrict__ alpha_part,
+                                                    int H, int W, int pitch, const int4* __restrict__ taps,
+                                                    const int* __restrict__ ntaps, IterParams p)
+{
+    constexpr int TW = BW_TW, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (BW_NT / 64);
+    constexpr int UW = TW + 4, UH = TH + 4, GW = TW + 2, GH = TH + 2;
+    __shared__ float2 qt[LH * LW];
+    __shared__ float ut[UH * UW];
+    __shared__ float gt[GH * GW];
+    __shared__ double red[BW_NT];
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < LH * LW; idx += BW_NT) {
+        const int ly = idx / LW, lx = idx - ly * LW;
+        const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
+        qt[idx] = qw[(size_t)gy * W + gx];
+    }
+    for (int idx = tid; idx < UH * UW; idx += BW_NT) {
+        const int ly = idx / UW, lx = idx - ly * UW;
+        ut[idx] = u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < GH * GW; idx += BW_NT) {
+        const int a = idx / GW, b = idx - a * GW;
+        const float gx = 0.5f * (ut[(a + 1) * UW + b + 2] - ut[(a + 1) * UW + b]);
+        const float gy = 0.5f * (ut[(a + 2) * UW + b + 1] - ut[a * UW + b + 1]);
+        gt[idx] = pen_deriv(gx * gx + gy * gy, p.eps_t2);
+    }
+    const int tx = tid & 63, ty = tid >> 6;
+    float n1[R], n2[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) n1[i] = n2[i] = 0.0f;
+    const float2* base = qt + (ty * R + RAD) * LW + tx + RAD;
+    const int n = ntaps[0];
+    for (int t = 0; t < n; ++t) {
+        const int4 e = taps[t];
+        const float w = __int_as_float(e.z);
+        const float2* s = base + e.x * LW + e.y;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const float2 v = s[i * LW];
+            n1[i] = fmaf(w, v.x, n1[i]);
+            n2[i] = fmaf(w, v.y, n2[i]);
+        }
+    }
+    __syncthreads();
+    double apart = 0.0;
+    const int x = x0 + tx;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int ry = ty * R + i;
+        const int y = y0 + ry;
+        if (x >= W || y >= H) continue;
+        const int c = (ry + 2) * UW + tx + 2;
+        const int cg = (ry + 1) * GW + tx + 1;
+        const float up = ut[c], gp = gt[cg];
+        const float D = 0.5f * (gp + gt[cg - GW]) * (ut[c - UW] - up) + 0.5f * (gp + gt[cg + GW]) * (ut[c + UW] - up)
+                      + 0.5f * (gp + gt[cg - 1]) * (ut[c - 1] - up) + 0.5f * (gp + gt[cg + 1]) * (ut[c + 1] - up);
+        const float dp = fmaxf(D, 0.0f), dm = fminf(D, 0.0f);
+        const float num = n1[i] + p.alpha * dp, den = n2[i] - p.alpha * dm;
+        const float l = lam[(size_t)y * lam_pitch + x];
+        const float a = l * up / den;
+        const float b = -l * up * num / (den * den);
+        const size_t o = (size_t)y * W + x;
+        ab[o] = make_float2(a, b);
+        cpl[o] = p.alpha * ((D > 0.0f ? a : 0.0f) - (D < 0.0f ? b : 0.0f));
+        du[o] = l * num / den;
+        apart += (double)a * dp - (double)b * dm;
+    }
+    red[tid] = apart;
+    __syncthreads();
+    for (int off = BW_NT / 2; off > 0; off >>= 1) {
+        if (tid < off) red[tid] += red[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) alpha_part[blockIdx.y * gridDim.x + blockIdx.x] += red[0];
+}
+
+// ----------------------------------- transposed blur: stencil on a grid
+// out(z) = sum_t h(d_t) V(z + SIGN d_t) for z on the grid with origin
+// (oy, ox) and size OH x OW; V is the input extended by zero (constant-
+// continuation transposes, before the fold) or wrapped (periodic).
+template <int RAD, int TH, int SIGN, typename T>
+__global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, int vpitch, int H, int W, int wrap,
+                                                     T* __restrict__ out, int opitch, int oy, int ox, int OH, int OW,
+                                                     const int4* __restrict__ taps, const int* __restrict__ ntaps)
+{
+    constexpr int TW = BW_TW, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (BW_NT / 64);
+    __shared__ T vt[LH * LW];
+    const int zx0 = ox + blockIdx.x * TW, zy0 = oy + blockIdx.y * TH;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < LH * LW; idx += BW_NT) {
+        const int ly = idx / LW, lx = idx - ly * LW;
+        int gy = zy0 - RAD + ly, gx = zx0 - RAD + lx;
+        T val{};
+        if (wrap) {
+            gy = ext_index(gy, H, BC_PERIODIC);
+            gx = ext_index(gx, W, BC_PERIODIC);
+            val = v[(size_t)gy * vpitch + gx];
+        } else if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            val = v[(size_t)gy * vpitch + gx];
+        }
+        vt[idx] = val;
+    }
+    __syncthreads();
+    const int tx = tid & 63, ty = tid >> 6;
+    T acc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] = T{};
+    const T* base = vt + (ty * R + RAD) * LW + tx + RAD;
+    const int n = ntaps[0];
+    for (int t = 0; t < n; ++t) {
+        const int4 e = taps[t];
+        const float w = __int_as_float(e.z);
+        const T* s = base + SIGN * (e.x * LW + e.y);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if constexpr (sizeof(T) == 8) {
+                acc[i].x = fmaf(w, s[i * LW].x, acc[i].x);
+                acc[i].y = fmaf(w, s[i * LW].y, acc[i].y);
+            } else {
+                acc[i] = fmaf(w, s[i * LW], acc[i]);
+            }
+        }
+    }
+    const int zx = zx0 + tx;
+    if (zx >= ox + OW) return;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int zy = zy0 + ty * R + i;
+        if (zy >= oy + OH) break;
+        out[(size_t)(zy - oy) * opitch + (zx - ox)] = acc[i];
+    }
+}
+
+// Fold of an output extended by (ry, rx): every image pixel sums the grid
+// points whose clamped position it is.
+template <typename T>
+__global__ void __launch_bounds__(256) adj_fold(const T* __restrict__ ext, int epitch, int ry, int rx, int H, int W,
+                                                T* __restrict__ out, int opitch)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= W) return;
+    const int ylo = y == 0 ? -ry : y, yhi = y == H - 1 ? H - 1 + ry : y;
+    const int xlo = x == 0 ? -rx : x, xhi = x == W - 1 ? W - 1 + rx : x;
+    T acc{};
+    for (int zy = ylo; zy <= yhi; ++zy)
+        for (int zx = xlo; zx <= xhi; ++zx) {
+            const T v = ext[(size_t)(zy + ry) * epitch + (zx + rx)];
+            if constexpr (sizeof(T) == 8) {
+                acc.x += v.x;
+                acc.y += v.y;
+            } else {
+                acc += v;
+            }
+        }
+    out[(size_t)y * opitch + x] = acc;
+}
+
+// ------------------------------- adjoint of W, q = W f / s, r_f and the guard
+__global__ void __launch_bounds__(256) adj_point(const float2* __restrict__ dqw, const float2* __restrict__ qw,
+                                                 const float* __restrict__ s_raw, const float* __restrict__ f,
+                                                 float* __restrict__ grad_f, float* __restrict__ ds, int H, int W,
+                                                 int pitch, IterParams p)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= W) return;
+    const size_t o = (size_t)y * W + x, of = (size_t)y * pitch + x;
+    const float2 d = dqw[o], v = qw[o];
+    const float sr = s_raw[o];
+    const float st = fmaxf(sr, p.s_min);
+    const float fv = f[of];
+    const float fp = fmaxf(fv, 0.0f);
+    const float wt = v.y;
+    const float dW = d.y + d.x * fp / st;
+    float dst = -d.x * wt * fp / (st * st);
+    float df = fv > 0.0f ? d.x * wt / st : 0.0f;
+    if (p.robust) {
+        const float r = info_div(fv, st);
+        const float dr = r > 0.0f ? dW * (-0.5f) * wt * wt * wt : 0.0f;
+        if (fv > 0.0f) {
+            dst += dr * (1.0f - fv / st);
+            df += dr * (-logf(st / fv));
+        } else {
+            dst += dr;
+        }
+    }
+    ds[o] = sr > p.s_min ? dst : 0.0f;
+    grad_f[of] += df;
+}
+
+// ------------------------------------------ adjoint of the diffusion term
+// lam_out = du + aT + (L_g c) + (through g), c = dL/dD, frozen-g operator L_g
+// symmetric; g = Psi'(gx^2 + gy^2) with central differences of clamped u.
+template <int TH>
+__global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int pitch, const float* __restrict__ cpl,
+                                                const float* __restrict__ du, const float* __restrict__ aT,
+                                                float* __restrict__ lam_out, int H, int W, IterParams p)
+{
+    constexpr int TW = BW_TW, UW = TW + 4, UH = TH + 4, GW = TW + 2, GH = TH + 2;
+    __shared__ float ut[UH * UW], ct[UH * UW];
+    __shared__ float gt[GH * GW], dgx[GH * GW], dgy[GH * GW];
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < UH * UW; idx += BW_NT) {
+        const int ly = idx / UW, lx = idx - ly * UW;
+        const int gy = clampi(y0 - 2 + ly, H), gx = clampi(x0 - 2 + lx, W);
+        ut[idx] = u[(size_t)gy * pitch + gx];
+        ct[idx] = cpl[(size_t)gy * W + gx];
+    }
+    __syncthreads();
+    // at grid points (y0-1+a, x0-1+b): g, and dL/dgx, dL/dgy through g
+    for (int idx = tid; idx < GH * GW; idx += BW_NT) {
+        const int a = idx / GW, b = idx - a * GW;
+        const int c = (a + 1) * UW + b + 1;
+        const float up = ut[c], cp = ct[c];
+        const float gx = 0.5f * (ut[c + 1] - ut[c - 1]);
+        const float gy = 0.5f * (ut[c + UW] - ut[c - UW]);
+        const float g = pen_deriv(gx * gx + gy * gy, p.eps_t2);
+        // dL/dg(p) = sum_n (u_n - u_p)(c_p - c_n)/2 (neighbours outside read u_p: 0)
+        const float dg = 0.5f * ((ut[c - UW] - up) * (cp - ct[c - UW]) + (ut[c + UW] - up) * (cp - ct[c + UW])
+                                 + (ut[c - 1] - up) * (cp - ct[c - 1]) + (ut[c + 1] - up) * (cp - ct[c + 1]));
+        const float g3 = -g * g * g * dg;
+        gt[idx] = g;
+        dgx[idx] = g3 * gx;
+        dgy[idx] = g3 * gy;
+    }
+    __syncthreads();
+    constexpr int R = TH / (BW_NT / 64);
+    const int tx = tid & 63, ty = tid >> 6;
+    const int x = x0 + tx;
+    if (x >= W) return;
+    for (int i = 0; i < R; ++i) {
+        const int ry = ty * R + i, y = y0 + ry;
+        if (y >= H) break;
+        const int c = (ry + 2) * UW + tx + 2, k = (ry + 1) * GW + tx + 1;
+        const float gm = gt[k], cm = ct[c];
+        float acc = 0.5f * (gm + gt[k - GW]) * (ct[c - UW] - cm) + 0.5f * (gm + gt[k + GW]) * (ct[c + UW] - cm)
+                  + 0.5f * (gm + gt[k - 1]) * (ct[c - 1] - cm) + 0.5f * (gm + gt[k + 1]) * (ct[c + 1] - cm);
+        // gx(p) = (u(p_x+1 clamped) - u(p_x-1 clamped))/2: gather the scatter
+        if (x > 0) acc += 0.5f * dgx[k - 1];
+        if (x == W - 1) acc += 0.5f * dgx[k];
+        if (x < W - 1) acc -= 0.5f * dgx[k + 1];
+        if (x == 0) acc -= 0.5f * dgx[k];
+        if (y > 0) acc += 0.5f * dgy[k - GW];
+        if (y == H - 1) acc += 0.5f * dgy[k];
+        if (y < H - 1) acc -= 0.5f * dgy[k + GW];
+        if (y == 0) acc -= 0.5f * dgy[k];
+        const size_t o = (size_t)y * W + x;
+        lam_out[o] = du[o] + aT[o] + acc;
+    }
+}
+
+// ------------------------------------------------------ dL/dh partial sums
+// For every entry (j, i) of the PSF array, d = (j - cy, i - cx):
+//   sum over the tile of a(x) q(E(x + d)) + b(x) W(E(x + d)) + ds(x) u(E(x - d))
+// added to this workgroup's slot of `part` (FP64).
+template <int RAD>
+__global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, const float2* __restrict__ qw,
+                                                const float* __restrict__ ds, const float* __restrict__ u,
+                                                int pitch, int H, int W, int ph, int pw, int bc,
+                                                double* __restrict__ part)
+{
+    constexpr int TH = 32, TW = BW_TW, LW = TW + 2 * RAD, LH = TH + 2 * RAD;
+    constexpr int MAXK = ((2 * RAD + 1) * (2 * RAD + 1) + BW_NT - 1) / BW_NT;
+    __shared__ float2 ct[TH * TW];
+    __shared__ float2 ht[LH * LW];
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    const int tid = threadIdx.x;
+    const int PP = ph * pw, cy = (ph - 1) / 2, cx = (pw - 1) / 2;
+    float acc[MAXK];
+    int off[MAXK];
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k) {
+        acc[k] = 0.0f;
+        const int t = tid + k * BW_NT;
+        const int j = t < PP ? t / pw : 0, i = t < PP ? t - j * pw : 0;
+        off[k] = (j - cy) * LW + (i - cx);
+    }
+    // a, b with the (q, W) plane at x + d
+    for (int idx = tid; idx < TH * TW; idx += BW_NT) {
+        const int ly = idx / TW, lx = idx - ly * TW;
+        const int y = y0 + ly, x = x0 + lx;
+        ct[idx] = (y < H && x < W) ? ab[(size_t)y * W + x] : make_float2(0.0f, 0.0f);
+    }
+    for (int idx = tid; idx < LH * LW; idx += BW_NT) {
+        const int ly = idx / LW, lx = idx - ly * LW;
+        const int gy = ext_index(y0 - RAD + ly, H, bc), gx = ext_index(x0 - RAD + lx, W, bc);
+        ht[idx] = qw[(size_t)gy * W + gx];
+    }
+    __syncthreads();
+    for (int ly = 0; ly < TH; ++ly)
+        for (int lx = 0; lx < TW; ++lx) {
+            const float2 c = ct[ly * TW + lx];
+            const float2* h0 = ht + (ly + RAD) * LW + lx + RAD;
+#pragma unroll
+            for (int k = 0; k < MAXK; ++k) {
+                const float2 v = h0[off[k]];
+                acc[k] = fmaf(c.x, v.x, fmaf(c.y, v.y, acc[k]));
+            }
+        }
+    __syncthreads();
+    // ds with u at x - d
+    for (int idx = tid; idx < TH * TW; idx += BW_NT) {
+        const int ly = idx / TW, lx = idx - ly * TW;
+        const int y = y0 + ly, x = x0 + lx;
+        ct[idx] = make_float2((y < H && x < W) ? ds[(size_t)y * W + x] : 0.0f, 0.0f);
+    }
+    float* hs = reinterpret_cast<float*>(ht);
+    for (int idx = tid; idx < LH * LW; idx += BW_NT) {
+        const int ly = idx / LW, lx = idx - ly * LW;
+        const int gy = ext_index(y0 - RAD + ly, H, bc), gx = ext_index(x0 - RAD + lx, W, bc);
+        hs[idx] = u[(size_t)gy * pitch + gx];
+    }
+    __syncthreads();
+    for (int ly = 0; ly < TH; ++ly)
+        for (int lx = 0; lx < TW; ++lx) {
+            const float c = ct[ly * TW + lx].x;
+            const float* h0 = hs + (ly + RAD) * LW + lx + RAD;
+#pragma unroll
+            for (int k = 0; k < MAXK; ++k) acc[k] = fmaf(c, h0[-off[k]], acc[k]);
+        }
+    const size_t b = (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * PP;
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k) {
+        const int t = tid + k * BW_NT;
+        if (t < PP) part[b + t] += (double)acc[k];
+    }
+}
+
+// Fixed-order reduction of the per-workgroup partial sums.
+__global__ void __launch_bounds__(256) adj_reduce(const double* __restrict__ part, int nblocks, int PP,
+                                                  const double* __restrict__ alpha_part, double* __restrict__ dh,
+                                                  double* __restrict__ dalpha)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < PP) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * PP + t];
+        dh[t] = s;
+    }
+    if (t == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += alpha_part[b];
+        dalpha[0] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) fill_zero_f64(double* __restrict__ p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void __launch_bounds__(256) fill_zero_f32(float* __restrict__ p, int W, int H, int pitch)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x < W) p[(size_t)y * pitch + x] = 0.0f;
+}
+
+__global__ void __launch_bounds__(256) copy_plane(const float* __restrict__ src, int spitch, float* __restrict__ dst,
+                                                  int dpitch, int W)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x < W) dst[(size_t)y * dpitch + x] = src[(size_t)y * spitch + x];
+}
+
+// -------------------------------------------------------- Wiener adjoint
+// G = lam0 1[u_pre > floor]
+__global__ void __launch_bounds__(256) wiener_mask(const float* __restrict__ lam0, const float* __restrict__ upre,
+                                                   float* __restrict__ G, int W, float floor_)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x < W) {
+        const size_t o = (size_t)y * W + x;
+        G[o] = upre[o] > floor_ ? lam0[o] : 0.0f;
+    }
+}
+
+// Y = Z c1 + conj(Z c2), Z = F conj(G), c1 = K / (|h^|^2+K)^2,
+// c2 = -conj(h^)^2 / (|h^|^2+K)^2, on the half spectrum (FP64 arithmetic).
+__global__ void __launch_bounds__(256) wiener_dh_spectrum(const float2* __restrict__ Fh, const float2* __restrict__ Gh,
+                                                          const float2* __restrict__ hh, float2* __restrict__ Y,
+                                                          size_t n, double K)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double fr = Fh[i].x, fi = Fh[i].y, gr = Gh[i].x, gi = Gh[i].y;
+    const double zr = fr * gr + fi * gi, zi = fi * gr - fr * gi;   // F conj(G)
+    const double hr = hh[i].x, hi = hh[i].y;
+    const double m2 = hr * hr + hi * hi + K;
+    const double den = m2 * m2;
+    const double c1 = K / den;
+    const double c2r = -(hr * hr - hi * hi) / den, c2i = (2.0 * hr * hi) / den;  // -conj(h)^2/den
+    const double pr = zr * c2r - zi * c2i, pi = zr * c2i + zi * c2r;              // Z c2
+    Y[i] = make_float2((float)(zr * c1 + pr), (float)(zi * c1 - pi));
+}
+
+// dh(j, i) += R((j - cy) mod H, (i - cx) mod W)
+__global__ void __launch_bounds__(256) wiener_dh_gather(const float* __restrict__ R, int H, int W, int ph, int pw,
+                                                        double* __restrict__ dh)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ph * pw) return;
+    const int j = t / pw, i = t - j * pw;
+    const int y = ext_index(j - (ph - 1) / 2, H, BC_PERIODIC), x = ext_index(i - (pw - 1) / 2, W, BC_PERIODIC);
+    dh[t] += (double)R[(size_t)y * W + x];
+}
+
+__global__ void __launch_bounds__(256) write_grads(const double* __restrict__ dh, int PP, const double* __restrict__ da,
+                                                   float* __restrict__ grad_taps, float* __restrict__ grad_alpha)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (grad_taps && t < PP) grad_taps[t] = (float)dh[t];
+    if (grad_alpha && t == 0) grad_alpha[0] = (float)da[0];
+}
+
+// ------------------------------------------------------------ host driver
+static size_t r256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+struct BwdLayout {
+    size_t list, qw, s, ab, c, du, ds, aT, lamA, lamB, dqw, ext, part, apart, dh, da, total;
+    size_t wiener;  // start of the Wiener-adjoint region (reuses the iteration planes)
+};
+
+static int bwd_rad(const PsfDev& psf) { return tap_radius_class(max((psf.ph - 1) / 2, (psf.pw - 1) / 2)); }
+
+static int bwd_th(int rad) { return rad >= 32 ? 16 : 32; }
+
+static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
+{
+    BwdLayout L{};
+    const int rad = bwd_rad(psf);
+    const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
+    const size_t pl = r256((size_t)H * W * 4), pl2 = r256((size_t)H * W * 8);
+    const size_t ext2 = r256((size_t)(H + 2 * cy) * (W + 2 * cx) * 8);
+    const int th = bwd_th(rad);
+    const size_t nb_it = (size_t)((W + 63) / 64) * ((H + th - 1) / th);
+    const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + 31) / 32);
+    size_t o = 0;
+    L.list = o; o += r256(tap_list_bytes(psf));
+    L.qw = o; o += pl2;
+    L.s = o; o += pl;
+    L.ab = o; o += pl2;
+    L.c = o; o += pl;
+    L.du = o; o += pl;
+    L.ds = o; o += pl;
+    L.aT = o; o += pl;
+    L.lamA = o; o += pl;
+    L.lamB = o; o += pl;
+    L.dqw = o; o += pl2;
+    L.ext = o; o += ext2;
+    L.part = o; o += r256(nb_dh * psf.ph * psf.pw * 8);
+    L.apart = o; o += r256(nb_it * 8);
+    L.dh = o; o += r256((size_t)psf.ph * psf.pw * 8);
+    L.da = o; o += 256;
+    L.total = o;
+    L.wiener = L.qw;  // the Wiener adjoint runs after the iterations: reuse from qw on
+    return L;
+}
+
+size_t backward_ws_bytes(int H, int W, const PsfDev& psf, bool through_wiener)
+{
+    BwdLayout L = bwd_layout(H, W, psf);
+    size_t need = L.total;
+    if (through_wiener) {
+        // M, S1, S2, h^ (half planes, complex64) + u_pre, G, R (real planes)
+        const size_t half = r256((size_t)H * (W / 2 + 1) * 8), pl = r256((size_t)H * W * 4);
+        const size_t w = L.wiener + 4 * half + 3 * pl;
+        // the Wiener region must not overlap lamA/lamB (lam0 lives there) or dh/da
+        need = std::max(need, L.total + 4 * half + 3 * pl);
+        (void)w;
+    }
+    return need;
+}
+
+template <int RAD>
+static void launch_bwd_iter(const float* f, const float* u, const float* lam, int lam_pitch, float* lam_out,
+                            float* grad_f, int H, int W, int pitch, const PsfDev& psf, const IterParams& p,
+                            unsigned char* w8, const BwdLayout& L, hipStream_t st)
+{
+    constexpr int TH = RAD >= 32 ? 16 : 32;
+    const int4* taps = reinterpret_cast<const int4*>(w8 + L.list + 256);
+    const int* nt = reinterpret_cast<const int*>(w8 + L.list);
+    float2* qw = reinterpret_cast<float2*>(w8 + L.qw);
+    float* s = reinterpret_cast<float*>(w8 + L.s);
+    float2* ab = reinterpret_cast<float2*>(w8 + L.ab);
+    float* c = reinterpret_cast<float*>(w8 + L.c);
+    float* du = reinterpret_cast<float*>(w8 + L.du);
+    float* ds = reinterpret_cast<float*>(w8 + L.ds);
+    float* aT = reinterpret_cast<float*>(w8 + L.aT);
+    float2* dqw = reinterpret_cast<float2*>(w8 + L.dqw);
+    double* part = reinterpret_cast<double*>(w8 + L.part);
+    double* apart = reinterpret_cast<double*>(w8 + L.apart);
+    const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
+    const bool per = p.bc == BC_PERIODIC;
+
+    launch_taps_stage1(f, u, reinterpret_cast<float*>(qw), H, W, pitch, psf, w8 + L.list, p, 0, st, s);
+    const dim3 gi((W + 63) / 64, (H + TH - 1) / TH);
+    hipLaunchKernelGGL((adj_update<RAD, TH>), gi, dim3(BW_NT), 0, st, (const float2*)qw, u, lam, lam_pitch, ab, c,
+                       du, apart, H, W, pitch, taps, nt, p);
+    // dq, dW = B^T (a, b)
+    if (per) {
+        hipLaunchKernelGGL((adj_stencil<RAD, TH, -1, float2>), gi, dim3(BW_NT), 0, st, (const float2*)ab, W, H, W, 1,
+                           dqw, W, 0, 0, H, W, taps, nt);
+    } else {
+        float2* ext = reinterpret_cast<float2*>(w8 + L.ext);
+        const int EH = H + 2 * cy, EW = W + 2 * cx;
+        const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH);
+        hipLaunchKernelGGL((adj_stencil<RAD, TH, -1, float2>), ge, dim3(BW_NT), 0, st, (const float2*)ab, W, H, W, 0,
+                           ext, EW, -cy, -cx, EH, EW, taps, nt);
+        hipLaunchKernelGGL(adj_fold<float2>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float2*)ext, EW, cy,
+                           cx, H, W, dqw, W);
+    }
+    hipLaunchKernelGGL(adj_point, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float2*)dqw, (const float2*)qw,
+                       (const float*)s, f, grad_f, ds, H, W, pitch, p);
+    // A^T ds
+    if (per) {
+        hipLaunchKernelGGL((adj_stencil<RAD, TH, 1, float>), gi, dim3(BW_NT), 0, st, (const float*)ds, W, H, W, 1, aT,
+                           W, 0, 0, H, W, taps, nt);
+    } else {
+        float* ext = reinterpret_cast<float*>(w8 + L.ext);
+        const int EH = H + 2 * cy, EW = W + 2 * cx;
+        const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH);
+        hipLaunchKernelGGL((adj_stencil<RAD, TH, 1, float>), ge, dim3(BW_NT), 0, st, (const float*)ds, W, H, W, 0, ext,
+                           EW, -cy, -cx, EH, EW, taps, nt);
+        hipLaunchKernelGGL(adj_fold<float>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float*)ext, EW, cy, cx,
+                           H, W, aT, W);
+    }
+    hipLaunchKernelGGL((adj_tv<32>), dim3((W + 63) / 64, (H + 31) / 32), dim3(BW_NT), 0, st, u, pitch,
+                       (const float*)c, (const float*)du, (const float*)aT, lam_out, H, W, p);
+    hipLaunchKernelGGL((adj_dh<RAD>), dim3((W + 63) / 64, (H + 31) / 32), dim3(BW_NT), 0, st, (const float2*)ab,
+                       (const float2*)qw, (const float*)ds, u, pitch, H, W, psf.ph, psf.pw, p.bc, part);
+}
+
+int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int H, int W, int pitch,
+                         const PsfDev& psf, const IterParams& p, int iters, bool through_wiener, double K,
+                         float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0,
+                         void* ws, hipStream_t st)
+{
+    const int rad = bwd_rad(psf);
+    if (rad < 0) return -2;
+    unsigned char* w8 = reinterpret_cast<unsigned char*>(ws);
+    const BwdLayout L = bwd_layout(H, W, psf);
+    const int PP = psf.ph * psf.pw;
+    const int th = bwd_th(rad);
+    const size_t nb_it = (size_t)((W + 63) / 64) * ((H + th - 1) / th);
+    const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + 31) / 32);
+    double* part = reinterpret_cast<double*>(w8 + L.part);
+    double* apart = reinterpret_cast<double*>(w8 + L.apart);
+    double* dh = reinterpret_cast<double*>(w8 + L.dh);
+    double* da = reinterpret_cast<double*>(w8 + L.da);
+    float* lamA = reinterpret_cast<float*>(w8 + L.lamA);
+    float* lamB = reinterpret_cast<float*>(w8 + L.lamB);
+
+    launch_compile_taps(psf, w8 + L.list, st);
+    hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((nb_dh * PP + 255) / 256)), dim3(256), 0, st, part,
+                       nb_dh * PP);
+    hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((nb_it + 255) / 256)), dim3(256), 0, st, apart, nb_it);
+    hipLaunchKernelGGL(fill_zero_f32, dim3((W + 255) / 256, H), dim3(256), 0, st, grad_f, W, H, pitch);
+
+    const float* lam = grad_uK;
+    int lam_pitch = pitch;
+    for (int k = iters - 1; k >= 0; --k) {
+        float* lam_out = (k % 2 == 0) ? lamA : lamB;
+        const float* u = ckpt + (size_t)k * H * pitch;
+        switch (rad) {
+            case 4: launch_bwd_iter<4>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+            case 8: launch_bwd_iter<8>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+            case 16: launch_bwd_iter<16>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+            default: launch_bwd_iter<32>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+        }
+        lam = lam_out;
+        lam_pitch = W;
+    }
+    hipLaunchKernelGGL(adj_reduce, dim3((PP + 255) / 256), dim3(256), 0, st, (const double*)part, (int)nb_dh, PP,
+                       (const double*)apart, dh, da);
+    if (iters == 0) {
+        // no iteration: lam0 = grad_uK, dalpha = 0 (apart zeroed)
+        hipLaunchKernelGGL(copy_plane, dim3((W + 255) / 256, H), dim3(256), 0, st, grad_uK, pitch, lamA, W, W);
+        lam = lamA;
+    }
+    // lam now holds dL/du^0 (dense, pitch W)
+    if (grad_u0)
+        hipLaunchKernelGGL(copy_plane, dim3((W + 255) / 256, H), dim3(256), 0, st, lam, W, grad_u0, pitch, W);
+    if (through_wiener) {
+        const size_t half = r256((size_t)H * (W / 2 + 1) * 8), pl = r256((size_t)H * W * 4);
+        unsigned char* wb = w8 + L.total;
+        float2* Sa = reinterpret_cast<float2*>(wb);
+        float2* Sb = reinterpret_cast<float2*>(wb + half);
+        float2* M = reinterpret_cast<float2*>(wb + 2 * half);
+        float2* hh = reinterpret_cast<float2*>(wb + 3 * half);
+        float* upre = reinterpret_cast<float*>(wb + 4 * half);
+        float* G = reinterpret_cast<float*>(wb + 4 * half + pl);
+        float* R = reinterpret_cast<float*>(wb + 4 * half + 2 * pl);
+        const size_t nh = (size_t)H * (W / 2 + 1);
+        // M, h^; F^ = DFT(f); u_pre = IDFT(F^ M) (no floor); G = lam0 1[u_pre > floor]
+        launch_wiener_mult(psf, H, W, K, M, hh, st);
+        launch_fft2_forward(f, pitch, H, W, Sa, st);
+        launch_spectral_mul(Sa, M, false, Sb, nh, st);
+        launch_fft2_inverse(Sb, H, W, upre, W, -INFINITY, false, st);
+        hipLaunchKernelGGL(wiener_mask, dim3((W + 255) / 256, H), dim3(256), 0, st, lam, (const float*)upre, G, W,
+                           pos_floor);
+        launch_fft2_forward(G, W, H, W, Sb, st);                     // Sb = G^
+        launch_wiener_dh_prep(Sa, Sb, hh, Sa, nh, K, st);            // Sa <- Y
+        launch_spectral_mul(Sb, M, true, Sb, nh, st);                // dL/df += IDFT(G^ conj M)
+        launch_fft2_inverse(Sb, H, W, grad_f, pitch, 0.0f, true, st);
+        launch_fft2_inverse(Sa, H, W, R, W, -INFINITY, false, st);   // R = IDFT(Y)
+        hipLaunchKernelGGL(wiener_dh_gather, dim3((PP + 255) / 256), dim3(256), 0, st, (const float*)R, H, W, psf.ph,
+                           psf.pw, dh);
+    }
+    hipLaunchKernelGGL(write_grads, dim3((PP + 255) / 256), dim3(256), 0, st, (const double*)dh, PP,
+                       (const double*)da, grad_taps, grad_alpha);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+void launch_wiener_dh_prep(const float2* Fh, const float2* Gh, const float2* hh, float2* Y, size_t n, double K,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(wiener_dh_spectrum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Fh, Gh, hh, Y, n, K);
+}
+
+}  // namespace deblur

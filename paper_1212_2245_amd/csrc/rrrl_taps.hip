@@ -51,8 +51,8 @@ __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restri
 
 template <int RAD, int TH, int NT>
 __global__ void __launch_bounds__(NT) rrrl_taps_stage1(const float* __restrict__ u, const float* __restrict__ f,
-                                                       float2* __restrict__ qw, int H, int W, int pitch,
-                                                       const int4* __restrict__ taps,
+                                                       float2* __restrict__ qw, float* __restrict__ s_out, int H,
+                                                       int W, int pitch, const int4* __restrict__ taps,
                                                        const int* __restrict__ ntaps, IterParams p)
 {
     constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (NT / 64);
@@ -85,6 +85,7 @@ __global__ void __launch_bounds__(NT) rrrl_taps_stage1(const float* __restrict__
     for (int i = 0; i < R; ++i) {
         const int y = y0 + ty * R + i;
         if (y >= H) break;
+        if (s_out) s_out[(size_t)y * W + x] = acc[i];   // unclamped A u (backward pass)
         const float s = fmaxf(acc[i], p.s_min);
         const float fv = f[(size_t)y * pitch + x];
         const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
@@ -186,11 +187,12 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 int taps_num_variants() { return kNumVariants; }
 
 template <int RAD, int TH, int NT>
-static void stage1_inst(const float* f, const float* u, float2* qw, int H, int W, int pitch, const int4* taps,
-                        const int* nt, const IterParams& p, hipStream_t st)
+static void stage1_inst(const float* f, const float* u, float2* qw, float* s_out, int H, int W, int pitch,
+                        const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     const dim3 g((W + 63) / 64, (H + TH - 1) / TH);
-    hipLaunchKernelGGL((rrrl_taps_stage1<RAD, TH, NT>), g, dim3(NT), 0, st, u, f, qw, H, W, pitch, taps, nt, p);
+    hipLaunchKernelGGL((rrrl_taps_stage1<RAD, TH, NT>), g, dim3(NT), 0, st, u, f, qw, s_out, H, W, pitch, taps, nt,
+                       p);
 }
 
 template <int RAD, int TH, int NT>
@@ -203,15 +205,15 @@ static void stage2_inst(const float2* qw, const float* u, float* un, float* ckpt
 }
 
 template <int RAD>
-static void launch_stage1_t(int v, const float* f, const float* u, float2* qw, int H, int W, int pitch,
-                            const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+static void launch_stage1_t(int v, const float* f, const float* u, float2* qw, float* s_out, int H, int W,
+                            int pitch, const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     switch (v) {
-        case 0: stage1_inst<RAD, 64, 1024>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
-        case 1: stage1_inst<RAD, 64, 256>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
-        case 2: stage1_inst<RAD, 32, 256>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
-        case 3: stage1_inst<RAD, 32, 512>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
-        default: stage1_inst<RAD, 16, 256>(f, u, qw, H, W, pitch, taps, nt, p, st); break;
+        case 0: stage1_inst<RAD, 64, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 1: stage1_inst<RAD, 64, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 2: stage1_inst<RAD, 32, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 3: stage1_inst<RAD, 32, 512>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
+        default: stage1_inst<RAD, 16, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
     }
 }
 
@@ -255,7 +257,7 @@ static int psf_radius_class(const PsfDev& psf)
 }
 
 int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, int pitch, const PsfDev& psf,
-                       const void* list, const IterParams& p, int variant, hipStream_t st)
+                       const void* list, const IterParams& p, int variant, hipStream_t st, float* s_out)
 {
     const int v = variant > 0 ? variant - 1 : default_variant(H, W, 1);
     const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
@@ -263,10 +265,10 @@ int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, 
     const int4* taps = reinterpret_cast<const int4*>(w8 + 256);
     float2* q2 = reinterpret_cast<float2*>(qw);
     switch (psf_radius_class(psf)) {
-        case 4: launch_stage1_t<4>(v, f, u, q2, H, W, pitch, taps, nt, p, st); break;
-        case 8: launch_stage1_t<8>(v, f, u, q2, H, W, pitch, taps, nt, p, st); break;
-        case 16: launch_stage1_t<16>(v, f, u, q2, H, W, pitch, taps, nt, p, st); break;
-        case 32: launch_stage1_t<32>(v, f, u, q2, H, W, pitch, taps, nt, p, st); break;
+        case 4: launch_stage1_t<4>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 8: launch_stage1_t<8>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 16: launch_stage1_t<16>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 32: launch_stage1_t<32>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
         default: return -2;
     }
     return 0;

@@ -85,7 +85,8 @@ __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict
 // M(ky, kx) for kx <= W/2, stored row-major with row pitch W/2+1.  One
 // workgroup per column kx: G_j(kx) = sum_i h[j][i] w_W^(kx (i-cx)) first,
 // then h^(ky,kx) = sum_j G_j(kx) w_H^(ky (j-cy)) with an FP64 twiddle table.
-__global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, double K, float2* __restrict__ M)
+__global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, double K, float2* __restrict__ M,
+                                                      float2* __restrict__ hh)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double2* twh = reinterpret_cast<double2*>(smem_raw);  // H entries
@@ -124,6 +125,7 @@ __global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, 
         }
         const double den = re * re + im * im + K;
         M[(size_t)ky * Wh + kx] = make_float2((float)(re / den), (float)(-im / den));
+        if (hh) hh[(size_t)ky * Wh + kx] = make_float2((float)re, (float)im);
     }
 }
 
@@ -159,10 +161,11 @@ __global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__
     }
 }
 
-// Column pass: for `cb` consecutive columns kx of S: FFT along y, multiply by
-// M, inverse FFT along y (scaled by 1/H), written back in place.
+// Column pass over `cb` consecutive columns kx of the half spectrum S (in
+// place): mode 0: FFT along y, multiply by M (or conj M), inverse FFT (1/H);
+// mode 1: forward FFT only; mode 2: inverse FFT only (1/H).
 __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const float2* __restrict__ M,
-                                                   int H, int W, int cb, FftPlan plan)
+                                                   int H, int W, int cb, FftPlan plan, int mode, int conjM)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* tw = reinterpret_cast<float2*>(smem_raw);
@@ -173,26 +176,40 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
     const int c0 = blockIdx.x * cb;
     for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
         const int y = idx / cb, c = idx - y * cb;
-        a[c * H + y] = (c0 + c < Wh) ? S[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+        float2 v = (c0 + c < Wh) ? S[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+        a[c * H + y] = mode == 2 ? cconj(v) : v;
     }
     __syncthreads();
     float2* X = fft_rows(a, b, cb, plan, tw);
-    float2* Y = X == a ? b : a;
-    for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
-        const int c = idx / H, y = idx - c * H;
-        const float2 m = (c0 + c < Wh) ? M[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
-        X[idx] = cconj(cmul(X[idx], m));
+    if (mode == 0) {
+        float2* Y = X == a ? b : a;
+        for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
+            const int c = idx / H, y = idx - c * H;
+            float2 m = (c0 + c < Wh) ? M[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+            if (conjM) m = cconj(m);
+            X[idx] = cconj(cmul(X[idx], m));
+        }
+        __syncthreads();
+        X = fft_rows(X, Y, cb, plan, tw);
     }
-    __syncthreads();
-    X = fft_rows(X, Y, cb, plan, tw);
-    const float inv = 1.0f / (float)H;
+    const float inv = mode == 1 ? 1.0f : 1.0f / (float)H;
     for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
         const int y = idx / cb, c = idx - y * cb;
         if (c0 + c < Wh) {
             const float2 z = X[c * H + y];
-            S[(size_t)y * Wh + c0 + c] = make_float2(z.x * inv, -z.y * inv);
+            S[(size_t)y * Wh + c0 + c] = mode == 1 ? z : make_float2(z.x * inv, -z.y * inv);
         }
     }
+}
+
+// S_out = S_in * M (or conj M), elementwise on the half spectrum.
+__global__ void __launch_bounds__(256) spectral_mul(const float2* __restrict__ Sin, const float2* __restrict__ M,
+                                                    int conjM, float2* __restrict__ Sout, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 m = conjM ? cconj(M[i]) : M[i];
+    Sout[i] = cmul(Sin[i], m);
 }
 
 // Inverse row pass: U_a, U_b extended to full length by Hermitian symmetry,
@@ -200,7 +217,7 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
 // non-positive values replaced by pos_floor (Sec. 3.2).
 __global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict__ S, float* __restrict__ u,
                                                        int H, int W, int pitch, int nb, FftPlan plan,
-                                                       float pos_floor)
+                                                       float pos_floor, int accumulate)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* tw = reinterpret_cast<float2*>(smem_raw);
@@ -230,8 +247,13 @@ __global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict_
         const int t = idx / W, x = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
         const float2 z = Z[idx];
-        if (ya < H) u[(size_t)ya * pitch + x] = fmaxf(z.x * inv, pos_floor);
-        if (yb < H) u[(size_t)yb * pitch + x] = fmaxf(-z.y * inv, pos_floor);
+        if (accumulate) {
+            if (ya < H) u[(size_t)ya * pitch + x] += z.x * inv;
+            if (yb < H) u[(size_t)yb * pitch + x] += -z.y * inv;
+        } else {
+            if (ya < H) u[(size_t)ya * pitch + x] = fmaxf(z.x * inv, pos_floor);
+            if (yb < H) u[(size_t)yb * pitch + x] = fmaxf(-z.y * inv, pos_floor);
+        }
     }
 }
 
@@ -277,7 +299,7 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
         float2* M = reinterpret_cast<float2*>(ws);
         float2* S = M + (size_t)H * Wh;
         hipLaunchKernelGGL(wiener_mult_2d, dim3(Wh), dim3(256), (size_t)(H + psf.ph) * sizeof(double2), st,
-                           psf, H, W, K, M);
+                           psf, H, W, K, M, (float2*)nullptr);
         const int pairs = (H + 1) / 2;
         const int nb = W >= 1024 ? 1 : 1024 / W;
         const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(float2);
@@ -286,11 +308,45 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
         const int cb = H >= 2048 ? 1 : (2048 / H > 8 ? 8 : 2048 / H);
         const size_t lds_c = (size_t)(H + 2 * cb * H) * sizeof(float2);
         hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), lds_c, st, S, (const float2*)M,
-                           H, W, cb, make_plan(H));
+                           H, W, cb, make_plan(H), 0, 0);
         hipLaunchKernelGGL(wiener_rows_inv, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st,
-                           (const float2*)S, u, H, W, pitch, nb, make_plan(W), pos_floor);
+                           (const float2*)S, u, H, W, pitch, nb, make_plan(W), pos_floor, 0);
     }
     return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+static int row_batch(int W) { return W >= 1024 ? 1 : 1024 / W; }
+static int col_batch(int H) { return H >= 2048 ? 1 : (2048 / H > 8 ? 8 : 2048 / H); }
+
+void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
+{
+    hipLaunchKernelGGL(wiener_mult_2d, dim3(W / 2 + 1), dim3(256), (size_t)(H + psf.ph) * sizeof(double2), st, psf,
+                       H, W, K, M, hh);
+}
+
+void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st)
+{
+    const int nb = row_batch(W), cb = col_batch(H), Wh = W / 2 + 1, pairs = (H + 1) / 2;
+    hipLaunchKernelGGL(wiener_rows_fwd, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st, x,
+                       S, H, W, pitch, nb, make_plan(W));
+    hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S,
+                       (const float2*)nullptr, H, W, cb, make_plan(H), 1, 0);
+}
+
+void launch_fft2_inverse(float2* S, int H, int W, float* out, int pitch, float floor_, bool accumulate,
+                         hipStream_t st)
+{
+    const int nb = row_batch(W), cb = col_batch(H), Wh = W / 2 + 1, pairs = (H + 1) / 2;
+    hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S,
+                       (const float2*)nullptr, H, W, cb, make_plan(H), 2, 0);
+    hipLaunchKernelGGL(wiener_rows_inv, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st,
+                       (const float2*)S, out, H, W, pitch, nb, make_plan(W), floor_, accumulate ? 1 : 0);
+}
+
+void launch_spectral_mul(const float2* Sin, const float2* M, bool conjM, float2* Sout, size_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(spectral_mul, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Sin, M, conjM ? 1 : 0,
+                       Sout, n);
 }
 
 }  // namespace deblur
