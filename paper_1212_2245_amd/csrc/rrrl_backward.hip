@@ -364,8 +364,8 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
 
 // Fixed-order reduction of the per-workgroup partial sums.
 __global__ void __launch_bounds__(256) adj_reduce(const double* __restrict__ part, int nblocks, int PP,
-                                                  const double* __restrict__ alpha_part, double* __restrict__ dh,
-                                                  double* __restrict__ dalpha)
+                                                  const double* __restrict__ alpha_part, int nalpha,
+                                                  double* __restrict__ dh, double* __restrict__ dalpha)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < PP) {
@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(256) adj_reduce(const double* __restrict__ par
     }
     if (t == 0) {
         double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += alpha_part[b];
+        for (int b = 0; b < nalpha; ++b) s += alpha_part[b];
         dalpha[0] = s;
     }
 }
@@ -413,9 +413,9 @@ __global__ void __launch_bounds__(256) wiener_mask(const float* __restrict__ lam
 
 // Y = Z c1 + conj(Z c2), Z = F conj(G), c1 = K / (|h^|^2+K)^2,
 // c2 = -conj(h^)^2 / (|h^|^2+K)^2, on the half spectrum (FP64 arithmetic).
-__global__ void __launch_bounds__(256) wiener_dh_spectrum(const float2* __restrict__ Fh, const float2* __restrict__ Gh,
-                                                          const float2* __restrict__ hh, float2* __restrict__ Y,
-                                                          size_t n, double K)
+// (Y may alias Fh: each element is read before it is written by the same thread.)
+__global__ void __launch_bounds__(256) wiener_dh_spectrum(const float2* Fh, const float2* __restrict__ Gh,
+                                                          const float2* __restrict__ hh, float2* Y, size_t n, double K)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -608,7 +608,7 @@ int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
         lam_pitch = W;
     }
     hipLaunchKernelGGL(adj_reduce, dim3((PP + 255) / 256), dim3(256), 0, st, (const double*)part, (int)nb_dh, PP,
-                       (const double*)apart, dh, da);
+                       (const double*)apart, (int)nb_it, dh, da);
     if (iters == 0) {
         // no iteration: lam0 = grad_uK, dalpha = 0 (apart zeroed)
         hipLaunchKernelGGL(copy_plane, dim3((W + 255) / 256, H), dim3(256), 0, st, grad_uK, pitch, lamA, W, W);

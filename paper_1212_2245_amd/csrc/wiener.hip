@@ -202,9 +202,10 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
     }
 }
 
-// S_out = S_in * M (or conj M), elementwise on the half spectrum.
-__global__ void __launch_bounds__(256) spectral_mul(const float2* __restrict__ Sin, const float2* __restrict__ M,
-                                                    int conjM, float2* __restrict__ Sout, size_t n)
+// S_out = S_in * M (or conj M), elementwise on the half spectrum (S_out may
+// alias S_in).
+__global__ void __launch_bounds__(256) spectral_mul(const float2* Sin, const float2* __restrict__ M, int conjM,
+                                                    float2* Sout, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
