@@ -149,6 +149,42 @@ int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
                          double K, float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha,
                          float* grad_u0, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Batched form: many images of different sizes, each with its own PSF
+ * and parameters, in one hipGraph launch.
+ * An item binds the device pointers f (input) and u (output, H x pitch), the
+ * PSF, the parameters (all items must have the same p.iters) and the Wiener
+ * K and pos_floor; the computation per item is deblur_wiener followed by
+ * deblur_rrrl_iterate.  deblur_batch_plan_create validates every item (the
+ * status of the first invalid one is returned), then allocates the plan's
+ * device memory (per-image scratch planes, compiled tap lists, tile lists),
+ * compiles the PSFs (their taps are read here: a changed PSF needs a new
+ * plan) and captures the graph; it synchronises the device.  group_size > 0
+ * runs the images in consecutive groups of that many (the latency of an
+ * image is the completion of its group), 0 = one group. */
+typedef struct deblur_batch_plan deblur_batch_plan;
+typedef struct {
+    const float* f;
+    float* u;
+    int32_t H, W, pitch;
+    deblur_psf psf;
+    deblur_params p;
+    double K;
+    float pos_floor;
+} deblur_batch_item;
+
+int deblur_batch_plan_create(const deblur_batch_item* items, int32_t n, int32_t group_size,
+                             deblur_batch_plan** plan);
+/* Enqueues the whole batch (one graph launch) on `stream`. */
+int deblur_batch_run(deblur_batch_plan* plan, void* stream);
+/* Number of items of the plan. */
+int32_t deblur_batch_size(const deblur_batch_plan* plan);
+/* After a run has completed: per-item latency in microseconds from the start
+ * of the graph to the completion of the item's group (device clock).  Host
+ * array of deblur_batch_size(plan) doubles.  Synchronous. */
+int deblur_batch_latencies(deblur_batch_plan* plan, double* us_out);
+/* Frees the plan (NULL is allowed). */
+void deblur_batch_plan_destroy(deblur_batch_plan* plan);
+
 /* ---- Stage-level entry points of one RRRL iteration (spatial stencil path).
  * deblur_rrrl_iterate chains them; they are exported for callers that
  * schedule the iteration themselves, and for per-stage verification and

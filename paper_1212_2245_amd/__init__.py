@@ -282,3 +282,57 @@ def wr3l_autograd(f: torch.Tensor, taps: torch.Tensor, alpha: torch.Tensor, K: f
     """Differentiable WR3L (w.r.t. f, taps, alpha) through the library's
     forward and backward kernels."""
     return WR3LFunction.apply(f, taps, alpha, K, iters, template)
+
+
+# --------------------------------------------------------------- batched
+__all__ += ["BatchPlan"]
+
+
+class BatchPlan:
+    """Many WR3L problems (f_i, psf_i, params_i, K_i) run by one graph launch.
+
+    `items`: sequence of (f, psf, params, K, pos_floor) with f a 2D float32
+    device tensor; outputs are allocated here (self.outputs).  All params
+    must have the same `iters`.  group_size > 0 runs consecutive groups of
+    that many images one after another (per-image latency = completion of its
+    group)."""
+
+    def __init__(self, items, group_size: int = 0):
+        lib = _lib.load()
+        self._keep = []
+        self.outputs = []
+        arr = (_lib.deblur_batch_item * len(items))()
+        for k, (f, psf, params, K, floor) in enumerate(items):
+            H, W, pitch = _image(f, "f")
+            u = torch.empty_strided((H, W), (pitch, 1), dtype=torch.float32, device=f.device)
+            self._keep += [f, psf.taps]
+            self.outputs.append(u)
+            arr[k] = _lib.deblur_batch_item(f.data_ptr(), u.data_ptr(), H, W, pitch, psf.c(), params.c(), float(K),
+                                            float(floor))
+        self._plan = ctypes.c_void_p()
+        st = lib.deblur_batch_plan_create(arr, len(items), int(group_size), ctypes.byref(self._plan))
+        _lib.check(st, "deblur_batch_plan_create")
+        self.n = len(items)
+        self.device = items[0][0].device
+
+    def run(self):
+        st = _lib.load().deblur_batch_run(self._plan, torch.cuda.current_stream(self.device).cuda_stream)
+        _lib.check(st, "deblur_batch_run")
+        return self.outputs
+
+    def latencies_us(self):
+        import numpy as np
+        out = (ctypes.c_double * self.n)()
+        _lib.check(_lib.load().deblur_batch_latencies(self._plan, out), "deblur_batch_latencies")
+        return np.array(out[:])
+
+    def close(self):
+        if getattr(self, "_plan", None) and self._plan.value:
+            _lib.load().deblur_batch_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -32,6 +32,12 @@ class deblur_params(ctypes.Structure):
                 ("boundary", ctypes.c_int32), ("conv", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
+class deblur_batch_item(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p), ("u", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("psf", deblur_psf), ("p", deblur_params), ("K", ctypes.c_double),
+                ("pos_floor", ctypes.c_float)]
+
+
 # (name, restype, argtypes) of every exported entry point
 _VP, _SZ, _I32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
 _PSF, _PAR = ctypes.POINTER(deblur_psf), ctypes.POINTER(deblur_params)
@@ -45,6 +51,12 @@ SIGNATURES = [
     ("deblur_rrrl_iterate", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP, _SZ, _VP]),
     ("deblur_rrrl_backward", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _I32, ctypes.c_double,
                                             ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    ("deblur_batch_plan_create", ctypes.c_int, [ctypes.POINTER(deblur_batch_item), _I32, _I32,
+                                                ctypes.POINTER(ctypes.c_void_p)]),
+    ("deblur_batch_run", ctypes.c_int, [_VP, _VP]),
+    ("deblur_batch_size", _I32, [_VP]),
+    ("deblur_batch_latencies", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    ("deblur_batch_plan_destroy", None, [_VP]),
     ("deblur_taps_bytes", _SZ, [_PSF]),
     ("deblur_compile_taps", ctypes.c_int, [_PSF, _VP, _SZ, _VP]),
     ("deblur_rrrl_weights", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _VP, _PAR, _VP]),

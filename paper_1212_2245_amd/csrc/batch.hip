@@ -1,0 +1,309 @@
+// Batched WR3L: many images of different sizes, each with its own PSF and
+// parameters, run by one hipGraph launch.
+//
+// A plan compiles every image's tap list, lays out per-image ping-pong and
+// (q, W) planes, and builds flat tile lists per kernel class (stencil radius
+// classes 4/8/16/32, horizontal and vertical box) spanning all images of a
+// group.  The captured graph runs, per group: the Wiener step of every image
+// (on several forked capture streams), then for each iteration one launch per
+// class and stage, whose workgroups each take one tile of one image from the
+// list; then a timestamp kernel.  Groups run one after another, so with a
+// group size below the batch the completion time of each image's group is
+// its latency.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "box_tiles.hpp"
+#include "launch.hpp"
+#include "psf.hpp"
+#include "stencil_tiles.hpp"
+
+namespace deblur {
+
+struct BatchImg {
+    const float* f;
+    float* buf[2];          // ping-pong; buf[0] is the caller's output
+    float2* qw;             // (q, W) plane of stencil images
+    const int4* taps;       // compiled tap list (non-zero taps)
+    const int* ntaps;
+    int H, W, pitch, L;     // L: box length (box classes)
+    IterParams p;
+};
+
+struct BatchTile {
+    int img, x0, y0, pad;   // x0/y0: along/across origin for box tiles
+};
+
+constexpr int BT_TH = 32, BT_NT = 256;
+
+template <int RAD>
+__global__ void __launch_bounds__(BT_NT) batch_stage1(const BatchTile* __restrict__ tiles,
+                                                      const BatchImg* __restrict__ imgs, int src)
+{
+    __shared__ float tile[stage1_lds_floats<RAD, BT_TH>()];
+    const BatchTile t = tiles[blockIdx.x];
+    const BatchImg& im = imgs[t.img];
+    stage1_tile<RAD, BT_TH, BT_NT>(tile, im.buf[src], im.f, im.qw, nullptr, im.H, im.W, im.pitch, t.x0, t.y0,
+                                   im.taps, im.ntaps[0], im.p);
+}
+
+template <int RAD>
+__global__ void __launch_bounds__(BT_NT) batch_stage2(const BatchTile* __restrict__ tiles,
+                                                      const BatchImg* __restrict__ imgs, int src)
+{
+    __shared__ Stage2Smem<RAD, BT_TH> sm;
+    const BatchTile t = tiles[blockIdx.x];
+    const BatchImg& im = imgs[t.img];
+    stage2_tile<RAD, BT_TH, BT_NT>(sm, im.qw, im.buf[src], im.buf[1 - src], nullptr, im.H, im.W, im.pitch, t.x0,
+                                   t.y0, im.taps, im.ntaps[0], im.p);
+}
+
+template <bool VERT>
+__global__ void __launch_bounds__(256) batch_box(const BatchTile* __restrict__ tiles, const BatchImg* __restrict__ imgs,
+                                                 int src)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TA = VERT ? BOXV_TA : BOXH_TA, TC = VERT ? BOXV_TC : BOXH_TC;
+    const BatchTile t = tiles[blockIdx.x];
+    const BatchImg& im = imgs[t.img];
+    const BoxTile bt = make_tile(im.H, im.W, im.L, VERT, TA);
+    box_iter_tile<VERT, TA, TC>(smem_raw, im.buf[src], im.f, im.buf[1 - src], nullptr, im.pitch, bt, im.p, t.x0,
+                                t.y0);
+}
+
+__global__ void batch_timestamp(unsigned long long* ts, int slot)
+{
+    if (threadIdx.x == 0) ts[slot] = wall_clock64();
+}
+
+// ---------------------------------------------------------------- host side
+enum { CL_R4 = 0, CL_R8, CL_R16, CL_R32, CL_BOXH, CL_BOXV, NCLASS };
+
+
+struct BatchPlan {
+    int n = 0, groups = 0, iters = 0;
+    std::vector<int> group_of;          // image -> group
+    std::vector<void*> allocs;          // device allocations owned by the plan
+    unsigned long long* ts = nullptr;   // groups + 1 timestamps
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> chains;
+    std::vector<hipEvent_t> events;
+    int clock_khz = 0;
+};
+
+static int class_of(const PsfDev& d, bool stencil)
+{
+    if (!stencil && d.kind == PSF_BOX_H) return CL_BOXH;
+    if (!stencil && d.kind == PSF_BOX_V) return CL_BOXV;
+    switch (tap_radius_class(max((d.ph - 1) / 2, (d.pw - 1) / 2))) {
+        case 4: return CL_R4;
+        case 8: return CL_R8;
+        case 16: return CL_R16;
+        default: return CL_R32;
+    }
+}
+
+static void* dalloc(BatchPlan* P, size_t bytes)
+{
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) return nullptr;
+    P->allocs.push_back(p);
+    return p;
+}
+
+void batch_plan_destroy(BatchPlan* P)
+{
+    if (!P) return;
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
+    for (hipStream_t s : P->chains) (void)hipStreamDestroy(s);
+    if (P->cap) (void)hipStreamDestroy(P->cap);
+    for (void* p : P->allocs) (void)hipFree(p);
+    delete P;
+}
+
+// Builds the plan; items already validated.  Returns 0, -3 (allocation) or -4.
+int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPlan** out)
+{
+    BatchPlan* P = new BatchPlan();
+    P->n = n;
+    P->iters = items[0].iters;
+    const int gs = group_size > 0 ? group_size : n;
+    P->groups = (n + gs - 1) / gs;
+    P->group_of.resize(n);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&P->clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
+        batch_plan_destroy(P);
+        return -4;
+    }
+    const int start = P->iters % 2;  // Wiener writes buf[start]; the last iteration writes buf[0]
+    std::vector<BatchImg> imgs(n);
+    size_t wiener_ws = 0;
+    for (int i = 0; i < n; ++i) {
+        const BatchItemDev& it = items[i];
+        BatchImg& b = imgs[i];
+        b.f = it.f;
+        b.buf[0] = it.u;
+        b.buf[1] = static_cast<float*>(dalloc(P, (size_t)it.H * it.pitch * 4));
+        const int cls = class_of(it.psf, it.stencil);
+        b.qw = cls < CL_BOXH ? static_cast<float2*>(dalloc(P, (size_t)it.H * it.W * 8)) : nullptr;
+        void* list = dalloc(P, tap_list_bytes(it.psf));
+        if (!b.buf[1] || (cls < CL_BOXH && !b.qw) || !list) {
+            batch_plan_destroy(P);
+            return -3;
+        }
+        launch_compile_taps(it.psf, list, nullptr);
+        b.ntaps = reinterpret_cast<const int*>(list);
+        b.taps = reinterpret_cast<const int4*>(static_cast<unsigned char*>(list) + 256);
+        b.H = it.H;
+        b.W = it.W;
+        b.pitch = it.pitch;
+        b.L = it.psf.length;
+        b.p = it.p;
+        wiener_ws = std::max(wiener_ws, wiener_ws_bytes(it.H, it.W, it.psf.ph == 1));
+        P->group_of[i] = i / gs;
+    }
+    BatchImg* dimgs = static_cast<BatchImg*>(dalloc(P, sizeof(BatchImg) * n));
+    P->ts = static_cast<unsigned long long*>(dalloc(P, sizeof(unsigned long long) * (P->groups + 1)));
+    if (!dimgs || !P->ts || hipMemcpy(dimgs, imgs.data(), sizeof(BatchImg) * n, hipMemcpyHostToDevice) != hipSuccess) {
+        batch_plan_destroy(P);
+        return -3;
+    }
+    // tile lists per (group, class)
+    struct ClassList {
+        BatchTile* d = nullptr;
+        int count = 0;
+        size_t lds = 0;
+    };
+    std::vector<std::vector<ClassList>> lists(P->groups, std::vector<ClassList>(NCLASS));
+    for (int g = 0; g < P->groups; ++g) {
+        std::vector<std::vector<BatchTile>> host(NCLASS);
+        for (int i = g * gs; i < std::min(n, (g + 1) * gs); ++i) {
+            const BatchItemDev& it = items[i];
+            const int cls = class_of(it.psf, it.stencil);
+            if (cls < CL_BOXH) {
+                for (int y0 = 0; y0 < it.H; y0 += BT_TH)
+                    for (int x0 = 0; x0 < it.W; x0 += 64) host[cls].push_back({i, x0, y0, 0});
+            } else {
+                const bool vert = cls == CL_BOXV;
+                const int TA = vert ? BOXV_TA : BOXH_TA, TC = vert ? BOXV_TC : BOXH_TC;
+                const int along = vert ? it.H : it.W, across = vert ? it.W : it.H;
+                for (int c0 = 0; c0 < across; c0 += TC)
+                    for (int a0 = 0; a0 < along; a0 += TA) host[cls].push_back({i, a0, c0, 0});
+                const BoxTile bt = make_tile(it.H, it.W, it.psf.length, vert, TA);
+                const size_t lds = vert ? box_lds_bytes<true, BOXV_TA, BOXV_TC>(bt)
+                                        : box_lds_bytes<false, BOXH_TA, BOXH_TC>(bt);
+                lists[g][cls].lds = std::max(lists[g][cls].lds, lds);
+            }
+        }
+        for (int c = 0; c < NCLASS; ++c) {
+            if (host[c].empty()) continue;
+            lists[g][c].count = (int)host[c].size();
+            lists[g][c].d = static_cast<BatchTile*>(dalloc(P, sizeof(BatchTile) * host[c].size()));
+            if (!lists[g][c].d || hipMemcpy(lists[g][c].d, host[c].data(), sizeof(BatchTile) * host[c].size(),
+                                            hipMemcpyHostToDevice) != hipSuccess) {
+                batch_plan_destroy(P);
+                return -3;
+            }
+        }
+    }
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_box<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_box<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    // Wiener workspaces, one per capture chain
+    constexpr int kChains = 4;
+    std::vector<void*> wws(kChains);
+    for (int c = 0; c < kChains; ++c) {
+        wws[c] = dalloc(P, wiener_ws);
+        if (!wws[c]) {
+            batch_plan_destroy(P);
+            return -3;
+        }
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {  // tap lists and copies complete
+        batch_plan_destroy(P);
+        return -4;
+    }
+    // ---- capture
+    bool ok = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) == hipSuccess;
+    P->chains.resize(kChains, nullptr);
+    for (int c = 0; c < kChains && ok; ++c) ok = hipStreamCreateWithFlags(&P->chains[c], hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        batch_plan_destroy(P);
+        return -4;
+    }
+    auto event = [&]() {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return (hipEvent_t) nullptr;
+        P->events.push_back(e);
+        return e;
+    };
+    hipStream_t s = P->cap;
+    ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) hipLaunchKernelGGL(batch_timestamp, dim3(1), dim3(64), 0, s, P->ts, 0);
+    for (int g = 0; g < P->groups && ok; ++g) {
+        // Wiener of the group's images, forked over the chains
+        hipEvent_t fork = event();
+        ok = fork && hipEventRecord(fork, s) == hipSuccess;
+        for (int c = 0; c < kChains && ok; ++c) ok = hipStreamWaitEvent(P->chains[c], fork, 0) == hipSuccess;
+        for (int i = g * gs, k = 0; ok && i < std::min(n, (g + 1) * gs); ++i, ++k) {
+            const BatchItemDev& it = items[i];
+            const int c = k % kChains;
+            ok = launch_wiener(it.f, imgs[i].buf[start], it.H, it.W, it.pitch, it.psf, it.K, it.pos_floor, wws[c],
+                               it.psf.ph == 1, P->chains[c]) == 0;
+        }
+        for (int c = 0; c < kChains && ok; ++c) {
+            hipEvent_t join = event();
+            ok = join && hipEventRecord(join, P->chains[c]) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
+        }
+        for (int k = 0; k < P->iters && ok; ++k) {
+            const int src = (start + k) % 2;
+            const auto& L = lists[g];
+            if (L[CL_R4].count) hipLaunchKernelGGL(batch_stage1<4>, dim3(L[CL_R4].count), dim3(BT_NT), 0, s, L[CL_R4].d, dimgs, src);
+            if (L[CL_R8].count) hipLaunchKernelGGL(batch_stage1<8>, dim3(L[CL_R8].count), dim3(BT_NT), 0, s, L[CL_R8].d, dimgs, src);
+            if (L[CL_R16].count) hipLaunchKernelGGL(batch_stage1<16>, dim3(L[CL_R16].count), dim3(BT_NT), 0, s, L[CL_R16].d, dimgs, src);
+            if (L[CL_R32].count) hipLaunchKernelGGL(batch_stage1<32>, dim3(L[CL_R32].count), dim3(BT_NT), 0, s, L[CL_R32].d, dimgs, src);
+            if (L[CL_BOXH].count) hipLaunchKernelGGL(batch_box<false>, dim3(L[CL_BOXH].count), dim3(256), L[CL_BOXH].lds, s, L[CL_BOXH].d, dimgs, src);
+            if (L[CL_BOXV].count) hipLaunchKernelGGL(batch_box<true>, dim3(L[CL_BOXV].count), dim3(256), L[CL_BOXV].lds, s, L[CL_BOXV].d, dimgs, src);
+            if (L[CL_R4].count) hipLaunchKernelGGL(batch_stage2<4>, dim3(L[CL_R4].count), dim3(BT_NT), 0, s, L[CL_R4].d, dimgs, src);
+            if (L[CL_R8].count) hipLaunchKernelGGL(batch_stage2<8>, dim3(L[CL_R8].count), dim3(BT_NT), 0, s, L[CL_R8].d, dimgs, src);
+            if (L[CL_R16].count) hipLaunchKernelGGL(batch_stage2<16>, dim3(L[CL_R16].count), dim3(BT_NT), 0, s, L[CL_R16].d, dimgs, src);
+            if (L[CL_R32].count) hipLaunchKernelGGL(batch_stage2<32>, dim3(L[CL_R32].count), dim3(BT_NT), 0, s, L[CL_R32].d, dimgs, src);
+        }
+        if (ok) hipLaunchKernelGGL(batch_timestamp, dim3(1), dim3(64), 0, s, P->ts, g + 1);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t end = hipStreamEndCapture(s, &graph);
+    ok = ok && end == hipSuccess && graph;
+    P->graph = graph;
+    if (!ok || hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess) {
+        batch_plan_destroy(P);
+        return -4;
+    }
+    *out = P;
+    return 0;
+}
+
+int batch_run(BatchPlan* P, hipStream_t st) { return hipGraphLaunch(P->exec, st) == hipSuccess ? 0 : -4; }
+
+int batch_latencies(BatchPlan* P, double* us)
+{
+    std::vector<unsigned long long> t(P->groups + 1);
+    if (hipMemcpy(t.data(), P->ts, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return -4;
+    const double per_us = (double)P->clock_khz / 1000.0;  // ticks per microsecond
+    for (int i = 0; i < P->n; ++i) us[i] = (double)(t[P->group_of[i] + 1] - t[0]) / per_us;
+    return 0;
+}
+
+int batch_size(const BatchPlan* P) { return P->n; }
+
+}  // namespace deblur

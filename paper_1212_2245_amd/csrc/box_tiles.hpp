@@ -1,0 +1,218 @@
+// Box tiles of the RRRL iteration (Sec. 2.3, eqs. (9)-(12)) for uniform linear motion blur
+// along a coordinate axis (box PSF of integer length L), one fused kernel per
+// iteration.
+//
+// The paper's fast box filter (Sec. 4.3, uniform linear motion) updates a
+// window sum by one addition and one subtraction per pixel.  Here every
+// workgroup owns a tile and forms inclusive prefix sums of its tile rows
+// along the blur axis in LDS, so a window sum is a difference of two prefix
+// values.  The prefix restarts at every tile (a few hundred terms) and is
+// accumulated in FP64, so a window sum is as accurate as a direct FP32 sum of
+// its L terms even for short windows; window sums of non-negative data are
+// clamped at zero.
+//
+// Per tile (TA outputs along the blur axis x TC across it):
+//   1. u on the tile plus halo L-1 along (for A evaluated on the halo that B
+//      needs) and 2 across (diffusion term); f is read where needed.
+//   2. prefix of u along; diffusivity g on the tile + 1.
+//   3. s = A u, W, q on the TA + L - 1 positions B reads.
+//   4. prefix of (q, W) along.
+//   5. N1 = B q, N2 = B W, D(u), u' = u (N1 + a[D]_+) / (N2 - a[D]_-).
+// A: window [x - floor(L/2), x + floor((L-1)/2)]; B: [x - floor((L-1)/2), x + floor(L/2)].
+// Orientation: VERT = false for horizontal motion (along = x), true for
+// vertical motion (along = y).  LDS rows are "lines" of the tile along the
+// blur axis for horizontal motion and image rows for vertical motion, so that
+// global accesses stay coalesced along x in both cases.
+#pragma once
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace deblur {
+
+
+struct BoxTile {
+    int along_n, across_n;  // image extent along / across the blur axis
+    int L, aL, bL, hA;      // length, floor((L-1)/2), floor(L/2), halo along
+    int nu, nq;             // tile positions along: u (TA + 2hA), q/W (TA + L - 1)
+};
+
+template <bool VERT, int TA, int TC>
+struct BoxLayout {
+    // LDS element (c, j): across index c, along index j, line length n
+    static DEBLUR_DEV int at(int c, int j, int n, int lines)
+    {
+        return VERT ? j * lines + c : c * (n + 1) + j;
+    }
+};
+
+// Inclusive prefix along each of `lines` LDS lines of length n (in place),
+// block-wide.  G threads per line; chunk sums exchanged through `sums`.
+template <bool VERT, int TA, int TC, typename T>
+DEBLUR_DEV void prefix_lines(T* buf, int n, int lines, T* sums)
+{
+    constexpr int G = 256 / TC;
+    const int t = threadIdx.x;
+    const int c = VERT ? t % TC : t / G;
+    const int g = VERT ? t / TC : t % G;
+    const int ch = (n + G - 1) / G;
+    const int j0 = g * ch, j1 = min(n, j0 + ch);
+    T acc = T{};
+    if (c < lines)
+        for (int j = j0; j < j1; ++j) acc = acc + buf[BoxLayout<VERT, TA, TC>::at(c, j, n, lines)];
+    sums[c * G + g] = acc;
+    __syncthreads();
+    T off = T{};
+    if (c < lines) {
+        for (int k = 0; k < g; ++k) off = off + sums[c * G + k];
+        for (int j = j0; j < j1; ++j) {
+            const int i = BoxLayout<VERT, TA, TC>::at(c, j, n, lines);
+            off = off + buf[i];
+            buf[i] = off;
+        }
+    }
+    __syncthreads();
+}
+
+DEBLUR_DEV double2 operator+(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// One box-iteration tile: outputs along [a0, a0+TA), across [c0, c0+TC);
+// smem_raw: dynamic LDS of box_lds_bytes() for this tile geometry.
+template <bool VERT, int TA, int TC>
+DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float* __restrict__ u,
+                              const float* __restrict__ f, float* __restrict__ un, float* __restrict__ ckpt, int pitch,
+                              const BoxTile& bt, const IterParams& p, int a0, int c0)
+{
+    using Lay = BoxLayout<VERT, TA, TC>;
+    constexpr int CU = TC + 4;   // u lines (across halo 2)
+    constexpr int G = 256 / TC;
+    const int nu = bt.nu, nq = bt.nq;
+    float* us = reinterpret_cast<float*>(smem_raw);                 // CU lines of nu (u tile)
+    float* gs = us + CU * (nu + 1);                                  // (TC+2) x (TA+2) diffusivity
+    const int doff = (CU * (nu + 1) + (TC + 2) * (TA + 3) + 3) & ~3;
+    double* ps = reinterpret_cast<double*>(us + doff);               // TC lines of nu: prefix of u
+    double2* qs = reinterpret_cast<double2*>(ps + TC * (nu + 1));    // TC lines of nq: prefix of (q, W)
+    double2* sums2 = qs + TC * (nq + 1);
+    double* sums = reinterpret_cast<double*>(sums2 + 256);
+
+    const int lo = a0 - bt.hA;                               // along index of tile position 0
+    const int t = threadIdx.x;
+    const int H = VERT ? bt.along_n : bt.across_n;
+    const int W = VERT ? bt.across_n : bt.along_n;
+
+    // 1. u tile: along extended by the boundary mode, across clamped
+    for (int i = t; i < CU * nu; i += 256) {
+        int c, j;
+        if (VERT) { j = i / CU; c = i - j * CU; } else { c = i / nu; j = i - c * nu; }
+        const int ga = ext_index(lo + j, bt.along_n, p.bc);
+        const int gc = clampi(c0 - 2 + c, bt.across_n);
+        const int y = VERT ? ga : gc, x = VERT ? gc : ga;
+        us[Lay::at(c, j, nu, CU)] = u[(size_t)y * pitch + x];
+    }
+    __syncthreads();
+    // 2a. copy of the TC center lines for the prefix, 2b. diffusivity
+    for (int i = t; i < TC * nu; i += 256) {
+        int c, j;
+        if (VERT) { j = i / TC; c = i - j * TC; } else { c = i / nu; j = i - c * nu; }
+        ps[Lay::at(c, j, nu, TC)] = (double)us[Lay::at(c + 2, j, nu, CU)];
+    }
+    // tile positions of the first/last image index along (clamping for TV)
+    const int jmin = max(0, -lo), jmax = min(nu - 1, bt.along_n - 1 - lo);
+    constexpr int GA = TA + 2;
+    for (int i = t; i < (TC + 2) * GA; i += 256) {
+        int c, k;
+        if (VERT) { k = i / (TC + 2); c = i - k * (TC + 2); } else { c = i / GA; k = i - c * GA; }
+        // g at across c0 - 1 + c, along a0 - 1 + k (tile j = hA - 1 + k)
+        const int j = bt.hA - 1 + k;
+        const int jm = max(j - 1, jmin), jp = min(j + 1, jmax), jc = min(max(j, jmin), jmax);
+        const float da = 0.5f * (us[Lay::at(c + 1, jp, nu, CU)] - us[Lay::at(c + 1, jm, nu, CU)]);
+        const float dc = 0.5f * (us[Lay::at(c + 2, jc, nu, CU)] - us[Lay::at(c, jc, nu, CU)]);
+        gs[VERT ? k * (TC + 2) + c : c * (GA + 1) + k] = pen_deriv(da * da + dc * dc, p.eps_t2);
+    }
+    __syncthreads();
+    prefix_lines<VERT, TA, TC, double>(ps, nu, TC, sums);
+    // 3. s = A u, W, q on positions m = 0..nq-1 (along a0 - aL + m)
+    const float invL = 1.0f / (float)bt.L;
+    for (int i = t; i < TC * nq; i += 256) {
+        int c, m;
+        if (VERT) { m = i / TC; c = i - m * TC; } else { c = i / nq; m = i - c * nq; }
+        const int gc = c0 + c;
+        double2 qw = make_double2(0.0, 0.0);
+        if (gc < bt.across_n) {
+            // B reads E(q)(x'): q at the continued position.  Periodic: the
+            // tile holds the wrapped u, so x' itself is used; constant
+            // continuation: q(clamp(x')), i.e. A u at the clamped position.
+            const int xa = a0 - bt.aL + m;
+            const int ga = ext_index(xa, bt.along_n, p.bc);
+            const int j = (p.bc == BC_PERIODIC ? xa : ga) - lo;  // tile position of the sample
+            const int hi = j + bt.aL, lo2 = j - bt.bL - 1;          // A window [j - bL, j + aL]
+            const double sum = ps[Lay::at(c, hi, nu, TC)] - (lo2 >= 0 ? ps[Lay::at(c, lo2, nu, TC)] : 0.0);
+            const float s = fmaxf((float)fmax(sum, 0.0) * invL, p.s_min);
+            const int y = VERT ? ga : gc, x = VERT ? gc : ga;
+            const float fv = f[(size_t)y * pitch + x];
+            const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
+            qw = make_double2((double)(wt * fmaxf(fv, 0.0f) / s), (double)wt);
+        }
+        qs[Lay::at(c, m, nq, TC)] = qw;
+    }
+    __syncthreads();
+    prefix_lines<VERT, TA, TC, double2>(qs, nq, TC, sums2);
+    // 5. correlation, diffusion term, update
+    for (int i = t; i < TC * TA; i += 256) {
+        int c, o;
+        if (VERT) { o = i / TC; c = i - o * TC; } else { c = i / TA; o = i - c * TA; }
+        const int gc = c0 + c, ga = a0 + o;
+        if (gc >= bt.across_n || ga >= bt.along_n) continue;
+        // B window [o, o + L - 1] in q positions
+        const double2 hi = qs[Lay::at(c, o + bt.L - 1, nq, TC)];
+        const double2 lw = o > 0 ? qs[Lay::at(c, o - 1, nq, TC)] : make_double2(0.0, 0.0);
+        const float n1 = (float)fmax(hi.x - lw.x, 0.0) * invL, n2 = (float)fmax(hi.y - lw.y, 0.0) * invL;
+        const int j = bt.hA + o;
+        const int jm = max(j - 1, jmin), jp = min(j + 1, jmax);
+        const float up = us[Lay::at(c + 2, j, nu, CU)];
+        const int k = o + 1;
+        auto G_ = [&](int cc, int kk) { return gs[VERT ? kk * (TC + 2) + cc : cc * (GA + 1) + kk]; };
+        const float gp = G_(c + 1, k);
+        // along neighbours beyond the image border read u_p itself (zero flux)
+        const float D = 0.5f * (gp + G_(c + 1, k - 1)) * (us[Lay::at(c + 2, jm, nu, CU)] - up)
+                      + 0.5f * (gp + G_(c + 1, k + 1)) * (us[Lay::at(c + 2, jp, nu, CU)] - up)
+                      + 0.5f * (gp + G_(c, k)) * (us[Lay::at(c + 1, j, nu, CU)] - up)
+                      + 0.5f * (gp + G_(c + 2, k)) * (us[Lay::at(c + 3, j, nu, CU)] - up);
+        const float num = n1 + p.alpha * fmaxf(D, 0.0f);
+        const float den = n2 - p.alpha * fminf(D, 0.0f);
+        const int y = VERT ? ga : gc, x = VERT ? gc : ga;
+        const size_t off = (size_t)y * pitch + x;
+        if (ckpt) ckpt[off] = up;
+        un[off] = up * num / den;
+    }
+    (void)G;
+    (void)H;
+    (void)W;
+}
+
+
+template <bool VERT, int TA, int TC>
+inline size_t box_lds_bytes(const BoxTile& bt)
+{
+    constexpr int CU = TC + 4;
+    const size_t fl = ((size_t)CU * (bt.nu + 1) + (size_t)(TC + 2) * (TA + 3) + 3) & ~(size_t)3;
+    return fl * 4 + (size_t)TC * (bt.nu + 1) * 8 + ((size_t)TC * (bt.nq + 1) + 256) * 16 + 256 * 8;
+}
+
+__host__ __device__ inline BoxTile make_tile(int H, int W, int L, bool vert, int TA)
+{
+    BoxTile bt;
+    bt.along_n = vert ? H : W;
+    bt.across_n = vert ? W : H;
+    bt.L = L;
+    bt.aL = (L - 1) / 2;
+    bt.bL = L / 2;
+    bt.hA = L - 1 > 2 ? L - 1 : 2;
+    bt.nu = TA + 2 * bt.hA;
+    bt.nq = TA + L - 1;
+    return bt;
+}
+
+constexpr int BOXH_TA = 128, BOXH_TC = 8, BOXV_TA = 64, BOXV_TC = 16;
+
+}  // namespace deblur

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "deblur.h"
 #include "psf.hpp"
@@ -130,6 +131,10 @@ IterParams iter_params(const deblur_params* p)
 
 }  // namespace
 
+struct deblur_batch_plan {
+    deblur::BatchPlan* impl;
+};
+
 extern "C" {
 
 const char* deblur_status_string(int status)
@@ -231,6 +236,65 @@ int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
                              pos_floor, grad_f, grad_taps, grad_alpha, grad_u0, ws,
                              reinterpret_cast<hipStream_t>(stream));
     return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EUNSUPPORTED : DEBLUR_EDEVICE);
+}
+
+int deblur_batch_plan_create(const deblur_batch_item* items, int32_t n, int32_t group_size,
+                             deblur_batch_plan** plan)
+{
+    if (!items || n < 1 || !plan || group_size < 0) return DEBLUR_EINVAL;
+    *plan = nullptr;
+    std::vector<BatchItemDev> dev(n);
+    for (int i = 0; i < n; ++i) {
+        const deblur_batch_item& it = items[i];
+        PsfDev d;
+        if (!it.f || !it.u) return DEBLUR_EINVAL;
+        int s = check_wiener(it.H, it.W, it.pitch, &it.psf, &d);
+        if (s) return s;
+        if ((s = check_iterate(it.H, it.W, it.pitch, &it.psf, &it.p, &d))) return s;
+        if (!(it.K > 0.0) || !std::isfinite(it.K) || !(it.pos_floor > 0.0f) || !std::isfinite(it.pos_floor))
+            return DEBLUR_EINVAL;
+        if (it.p.iters != items[0].p.iters) return DEBLUR_EINVAL;
+        const size_t img = (size_t)it.H * it.pitch * sizeof(float);
+        if (overlaps(it.f, img, it.u, img)) return DEBLUR_EINVAL;
+        BatchItemDev& b = dev[i];
+        b.f = it.f;
+        b.u = it.u;
+        b.H = it.H;
+        b.W = it.W;
+        b.pitch = it.pitch;
+        b.psf = d;
+        b.p = iter_params(&it.p);
+        b.iters = it.p.iters;
+        b.K = it.K;
+        b.pos_floor = it.pos_floor;
+        b.stencil = it.p.conv == DEBLUR_CONV_STENCIL;
+    }
+    BatchPlan* impl = nullptr;
+    const int s = batch_plan_create(dev.data(), n, group_size, &impl);
+    if (s) return s == -3 ? DEBLUR_EWORKSPACE : DEBLUR_EDEVICE;
+    *plan = new deblur_batch_plan{impl};
+    return DEBLUR_OK;
+}
+
+int deblur_batch_run(deblur_batch_plan* plan, void* stream)
+{
+    if (!plan) return DEBLUR_EINVAL;
+    return batch_run(plan->impl, reinterpret_cast<hipStream_t>(stream)) == 0 ? DEBLUR_OK : DEBLUR_EDEVICE;
+}
+
+int32_t deblur_batch_size(const deblur_batch_plan* plan) { return plan ? batch_size(plan->impl) : 0; }
+
+int deblur_batch_latencies(deblur_batch_plan* plan, double* us_out)
+{
+    if (!plan || !us_out) return DEBLUR_EINVAL;
+    return batch_latencies(plan->impl, us_out) == 0 ? DEBLUR_OK : DEBLUR_EDEVICE;
+}
+
+void deblur_batch_plan_destroy(deblur_batch_plan* plan)
+{
+    if (!plan) return;
+    batch_plan_destroy(plan->impl);
+    delete plan;
 }
 
 size_t deblur_taps_bytes(const deblur_psf* psf)

@@ -35,15 +35,38 @@ DEBLUR_DEV float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 // multiply by -i
 DEBLUR_DEV float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
 
-// Twiddle table tw[m] = exp(-2 pi i m / n), m < n, computed in FP64.
-DEBLUR_DEV void fft_twiddles(float2* tw, int n)
+// Twiddle table tw[m] = exp(-2 pi i m / n), m < n, from FP64 sincospi rounded
+// once.  For n divisible by 8 only the first octant is evaluated and the rest
+// follows exactly from the symmetries of sin and cos (swaps and sign changes).
+template <typename C>
+DEBLUR_DEV void twiddle_table(C* tw, int n)
 {
-    for (int m = threadIdx.x; m < n; m += blockDim.x) {
-        double s, c;
-        sincospi(2.0 * (double)m / (double)n, &s, &c);
-        tw[m] = make_float2((float)c, (float)-s);
+    using R = decltype(tw[0].x);
+    if (n % 8 == 0) {
+        const int Q = n / 4;
+        for (int m = threadIdx.x; m <= n / 8; m += blockDim.x) {
+            double sd, cd;
+            sincospi(2.0 * (double)m / (double)n, &sd, &cd);
+            const R c = (R)cd, s = (R)sd;
+            tw[m] = C{c, -s};
+            tw[Q - m] = C{s, -c};
+            tw[Q + m] = C{-s, -c};
+            tw[2 * Q - m] = C{-c, -s};
+            tw[2 * Q + m] = C{-c, s};
+            tw[3 * Q - m] = C{-s, c};
+            tw[3 * Q + m] = C{s, c};
+            if (m > 0) tw[4 * Q - m] = C{c, s};
+        }
+    } else {
+        for (int m = threadIdx.x; m < n; m += blockDim.x) {
+            double sd, cd;
+            sincospi(2.0 * (double)m / (double)n, &sd, &cd);
+            tw[m] = C{(R)cd, (R)-sd};
+        }
     }
 }
+
+DEBLUR_DEV void fft_twiddles(float2* tw, int n) { twiddle_table(tw, n); }
 
 template <int R>
 DEBLUR_DEV void dft_small(float2* v)

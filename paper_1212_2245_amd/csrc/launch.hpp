@@ -61,4 +61,24 @@ int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
                          float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0,
                          void* ws, hipStream_t st);
 
+// Batched plans (batch.hip)
+struct BatchPlan;
+struct BatchItemDev {
+    const float* f;
+    float* u;
+    int H, W, pitch;
+    PsfDev psf;
+    IterParams p;
+    int iters;
+    double K;
+    float pos_floor;
+    bool stencil;  // run a box PSF through the stencil classes
+};
+
+int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPlan** out);
+int batch_run(BatchPlan* P, hipStream_t st);
+int batch_latencies(BatchPlan* P, double* us);
+int batch_size(const BatchPlan* P);
+void batch_plan_destroy(BatchPlan* P);
+
 }  // namespace deblur

@@ -89,27 +89,27 @@ __global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, 
                                                       float2* __restrict__ hh)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double2* twh = reinterpret_cast<double2*>(smem_raw);  // H entries
+    double2* twh = reinterpret_cast<double2*>(smem_raw);  // H entries: exp(-2 pi i m / H)
     double2* G = twh + H;                                  // ph entries
+    double2* px = G + psf.ph;                              // pw entries: exp(-2 pi i kx (i - cx) / W)
     const int kx = blockIdx.x;
     const int Wh = W / 2 + 1;
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
-    for (int m = threadIdx.x; m < H; m += blockDim.x) {
+    twiddle_table(twh, H);
+    for (int i = threadIdx.x; i < psf.pw; i += blockDim.x) {
+        long long m = ((long long)kx * (long long)(i - cx)) % W;
+        if (m < 0) m += W;
         double s, c;
-        sincospi(2.0 * (double)m / (double)H, &s, &c);
-        twh[m] = make_double2(c, -s);
+        sincospi(2.0 * (double)m / (double)W, &s, &c);
+        px[i] = make_double2(c, -s);
     }
+    __syncthreads();
     for (int j = threadIdx.x; j < psf.ph; j += blockDim.x) {
         double re = 0.0, im = 0.0;
         for (int i = 0; i < psf.pw; ++i) {
             const double w = (double)psf_weight(psf, j, i);
-            if (w == 0.0) continue;
-            long long m = ((long long)kx * (long long)(i - cx)) % W;
-            if (m < 0) m += W;
-            double s, c;
-            sincospi(2.0 * (double)m / (double)W, &s, &c);
-            re += w * c;
-            im -= w * s;
+            re += w * px[i].x;
+            im += w * px[i].y;
         }
         G[j] = make_double2(re, im);
     }
@@ -299,8 +299,8 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
         const int Wh = W / 2 + 1;
         float2* M = reinterpret_cast<float2*>(ws);
         float2* S = M + (size_t)H * Wh;
-        hipLaunchKernelGGL(wiener_mult_2d, dim3(Wh), dim3(256), (size_t)(H + psf.ph) * sizeof(double2), st,
-                           psf, H, W, K, M, (float2*)nullptr);
+        hipLaunchKernelGGL(wiener_mult_2d, dim3(Wh), dim3(256), (size_t)(H + psf.ph + psf.pw) * sizeof(double2),
+                           st, psf, H, W, K, M, (float2*)nullptr);
         const int pairs = (H + 1) / 2;
         const int nb = W >= 1024 ? 1 : 1024 / W;
         const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(float2);
@@ -321,8 +321,8 @@ static int col_batch(int H) { return H >= 2048 ? 1 : (2048 / H > 8 ? 8 : 2048 / 
 
 void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
 {
-    hipLaunchKernelGGL(wiener_mult_2d, dim3(W / 2 + 1), dim3(256), (size_t)(H + psf.ph) * sizeof(double2), st, psf,
-                       H, W, K, M, hh);
+    hipLaunchKernelGGL(wiener_mult_2d, dim3(W / 2 + 1), dim3(256), (size_t)(H + psf.ph + psf.pw) * sizeof(double2),
+                       st, psf, H, W, K, M, hh);
 }
 
 void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st)

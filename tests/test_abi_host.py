@@ -138,3 +138,49 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         _lib.load()
+
+
+def batch_item(f=F, u=U, H=128, W=128, pitch=128, psf=None, iters=3, K=0.01, floor=1.0):
+    return _lib.deblur_batch_item(f, u, H, W, pitch, psf if psf is not None else box(), params(iters=iters), K, floor)
+
+
+def test_batch_validation(lib):
+    E = _lib.DEBLUR_EINVAL
+    plan = ctypes.c_void_p()
+    arr = (_lib.deblur_batch_item * 2)(batch_item(), batch_item(f=0x70000000, u=0x78000000))
+    assert lib.deblur_batch_plan_create(arr, 0, 0, ctypes.byref(plan)) == E
+    assert lib.deblur_batch_plan_create(arr, 2, -1, ctypes.byref(plan)) == E
+    assert lib.deblur_batch_plan_create(None, 2, 0, ctypes.byref(plan)) == E
+    bad = (_lib.deblur_batch_item * 2)(batch_item(), batch_item(f=0x70000000, u=0x78000000, iters=4))
+    assert lib.deblur_batch_plan_create(bad, 2, 0, ctypes.byref(plan)) == E          # different iters
+    bad = (_lib.deblur_batch_item * 1)(batch_item(u=F + 64))
+    assert lib.deblur_batch_plan_create(bad, 1, 0, ctypes.byref(plan)) == E          # f and u overlap
+    bad = (_lib.deblur_batch_item * 1)(batch_item(W=250, pitch=256))
+    assert lib.deblur_batch_plan_create(bad, 1, 0, ctypes.byref(plan)) == _lib.DEBLUR_EUNSUPPORTED
+    bad = (_lib.deblur_batch_item * 1)(batch_item(K=0.0))
+    assert lib.deblur_batch_plan_create(bad, 1, 0, ctypes.byref(plan)) == E
+    assert lib.deblur_batch_run(None, None) == E
+    assert lib.deblur_batch_latencies(None, None) == E
+    assert lib.deblur_batch_size(None) == 0
+    lib.deblur_batch_plan_destroy(None)
+
+
+def test_backward_validation(lib):
+    E = _lib.DEBLUR_EINVAL
+    p = params(iters=2)
+
+    def bw(f=F, ck=CK, g=V, H=64, W=64, pitch=64, psf=None, tw=1, K=0.01, gf=0x58000000, ws=None, wsb=0, pp=None):
+        psf = psf if psf is not None else taps(5, 5)
+        return lib.deblur_rrrl_backward(f, ck, g, H, W, pitch, ctypes.byref(psf), ctypes.byref(pp or p), tw, K, 1.0,
+                                        gf, None, None, None, ws, wsb, None)
+    assert bw(f=None) == E
+    assert bw(gf=None) == E
+    assert bw(ck=None) == E                      # iters > 0 needs checkpoints
+    assert bw(tw=2) == E
+    assert bw(K=0.0) == E
+    assert bw(gf=F) == E                         # grad_f overlaps f
+    assert bw(H=100) == _lib.DEBLUR_EUNSUPPORTED  # through the Wiener step: 2^a 3^b
+    assert bw(H=100, tw=0) == _lib.DEBLUR_EWORKSPACE
+    assert bw() == _lib.DEBLUR_EWORKSPACE
+    assert lib.deblur_workspace_bytes(3, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p)) > \
+        lib.deblur_workspace_bytes(2, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p)) > 0
