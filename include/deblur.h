@@ -61,8 +61,16 @@ typedef enum { DEBLUR_PSF_BOX_H = 0, DEBLUR_PSF_BOX_V = 1, DEBLUR_PSF_TAPS = 2 }
 
 /* How the RRRL iteration evaluates A and B: AUTO picks the fastest exact
  * spatial method for the PSF kind (running sums for boxes, LDS stencil for
- * taps). */
-typedef enum { DEBLUR_CONV_AUTO = 0, DEBLUR_CONV_RUNSUM = 1, DEBLUR_CONV_STENCIL = 2 } deblur_conv;
+ * taps); FFT evaluates both convolutions in the Fourier domain (Sec. 4.3),
+ * which implies periodic continuation (boundary must be PERIODIC; H, W must
+ * be 2^a 3^b <= 2048) and costs the same for any PSF size.  The stage-level
+ * entry points and the backward pass use the stencil. */
+typedef enum {
+    DEBLUR_CONV_AUTO = 0,
+    DEBLUR_CONV_RUNSUM = 1,
+    DEBLUR_CONV_STENCIL = 2,
+    DEBLUR_CONV_FFT = 3
+} deblur_conv;
 
 typedef struct {
     int32_t kind;       /* deblur_psf_kind */

@@ -16,12 +16,12 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (BC_PERIODIC, BC_REPLICATE, CONV_AUTO, CONV_RUNSUM, CONV_STENCIL, PSF_BOX_H, PSF_BOX_V,
+from ._lib import (BC_PERIODIC, BC_REPLICATE, CONV_AUTO, CONV_FFT, CONV_RUNSUM, CONV_STENCIL, PSF_BOX_H, PSF_BOX_V,
                    PSF_TAPS, DeblurError)
 
 __all__ = ["Psf", "Params", "deblur_workspace_bytes", "deblur_wiener", "deblur_rrrl_iterate", "wr3l",
            "DeblurError", "BC_REPLICATE", "BC_PERIODIC", "PSF_BOX_H", "PSF_BOX_V", "PSF_TAPS",
-           "CONV_AUTO", "CONV_RUNSUM", "CONV_STENCIL", "library_path"]
+           "CONV_AUTO", "CONV_RUNSUM", "CONV_STENCIL", "CONV_FFT", "library_path"]
 
 
 def library_path() -> str:

@@ -16,7 +16,7 @@ DEBLUR_EDEVICE = -4
 
 PSF_BOX_H, PSF_BOX_V, PSF_TAPS = 0, 1, 2
 BC_REPLICATE, BC_PERIODIC = 0, 1
-CONV_AUTO, CONV_RUNSUM, CONV_STENCIL = 0, 1, 2
+CONV_AUTO, CONV_RUNSUM, CONV_STENCIL, CONV_FFT = 0, 1, 2, 3
 
 OP_WIENER, OP_ITERATE, OP_BACKWARD, OP_BACKWARD_WIENER = 0, 1, 2, 3
 

@@ -37,6 +37,9 @@ struct BoxTile {
     int nu, nq;             // tile positions along: u (TA + 2hA), q/W (TA + L - 1)
 };
 
+DEBLUR_DEV double2 operator+(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+DEBLUR_DEV double2 operator-(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
 template <bool VERT, int TA, int TC>
 struct BoxLayout {
     // LDS element (c, j): across index c, along index j, line length n
@@ -47,24 +50,39 @@ struct BoxLayout {
 };
 
 // Inclusive prefix along each of `lines` LDS lines of length n (in place),
-// block-wide.  G threads per line; chunk sums exchanged through `sums`.
+// block-wide.  The G = 256/TC threads of a line are consecutive lanes of one
+// wavefront; each sums a contiguous chunk, the chunk offsets come from a
+// shuffle scan over the G lanes.
+template <typename T>
+DEBLUR_DEV T shfl_up_T(T v, int d, int width);
+template <>
+DEBLUR_DEV double shfl_up_T<double>(double v, int d, int width) { return __shfl_up(v, d, width); }
+template <>
+DEBLUR_DEV double2 shfl_up_T<double2>(double2 v, int d, int width)
+{
+    return make_double2(__shfl_up(v.x, d, width), __shfl_up(v.y, d, width));
+}
+
 template <bool VERT, int TA, int TC, typename T>
-DEBLUR_DEV void prefix_lines(T* buf, int n, int lines, T* sums)
+DEBLUR_DEV void prefix_lines(T* buf, int n, int lines, T* /*sums*/)
 {
     constexpr int G = 256 / TC;
+    static_assert(G <= 64 && (G & (G - 1)) == 0, "line group within a wavefront");
     const int t = threadIdx.x;
-    const int c = VERT ? t % TC : t / G;
-    const int g = VERT ? t / TC : t % G;
+    const int c = t / G, g = t % G;
     const int ch = (n + G - 1) / G;
     const int j0 = g * ch, j1 = min(n, j0 + ch);
     T acc = T{};
     if (c < lines)
         for (int j = j0; j < j1; ++j) acc = acc + buf[BoxLayout<VERT, TA, TC>::at(c, j, n, lines)];
-    sums[c * G + g] = acc;
-    __syncthreads();
-    T off = T{};
+    // inclusive scan of the chunk sums over the G lanes of this line
+    T inc = acc;
+    for (int d = 1; d < G; d <<= 1) {
+        const T v = shfl_up_T(inc, d, G);
+        if (g >= d) inc = inc + v;
+    }
+    T off = inc - acc;
     if (c < lines) {
-        for (int k = 0; k < g; ++k) off = off + sums[c * G + k];
         for (int j = j0; j < j1; ++j) {
             const int i = BoxLayout<VERT, TA, TC>::at(c, j, n, lines);
             off = off + buf[i];
@@ -74,7 +92,7 @@ DEBLUR_DEV void prefix_lines(T* buf, int n, int lines, T* sums)
     __syncthreads();
 }
 
-DEBLUR_DEV double2 operator+(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
 
 // One box-iteration tile: outputs along [a0, a0+TA), across [c0, c0+TC);
 // smem_raw: dynamic LDS of box_lds_bytes() for this tile geometry.

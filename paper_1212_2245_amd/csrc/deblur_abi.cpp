@@ -92,7 +92,14 @@ int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, co
     if (!(p->s_min > 0.0f) || !std::isfinite(p->s_min)) return DEBLUR_EINVAL;
     if (p->iters < 0 || (p->robust != 0 && p->robust != 1)) return DEBLUR_EINVAL;
     if (p->boundary != DEBLUR_BC_REPLICATE && p->boundary != DEBLUR_BC_PERIODIC) return DEBLUR_EINVAL;
-    if (p->conv < DEBLUR_CONV_AUTO || p->conv > DEBLUR_CONV_STENCIL) return DEBLUR_EINVAL;
+    if (p->conv < DEBLUR_CONV_AUTO || p->conv > DEBLUR_CONV_FFT) return DEBLUR_EINVAL;
+    if (p->conv == DEBLUR_CONV_FFT) {
+        if (p->boundary != DEBLUR_BC_PERIODIC) return DEBLUR_EINVAL;  // Fourier domain: periodic only
+        if (!is_2a3b(H) || !is_2a3b(W) || H > kMaxFft || W > kMaxFft) return DEBLUR_EUNSUPPORTED;
+        if (d->ph > H || d->pw > W) return DEBLUR_EINVAL;
+        if (p->tile < 0 || p->tile > taps_num_variants()) return DEBLUR_EINVAL;
+        return DEBLUR_OK;
+    }
     if (p->conv == DEBLUR_CONV_RUNSUM && d->kind == DEBLUR_PSF_TAPS) return DEBLUR_EINVAL;
     if (p->tile < 0 || p->tile > taps_num_variants()) return DEBLUR_EINVAL;
     const int rad = (d->ph - 1) / 2 > (d->pw - 1) / 2 ? (d->ph - 1) / 2 : (d->pw - 1) / 2;
@@ -163,6 +170,7 @@ size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, c
     }
     if (op == 1) {
         if (check_iterate(H, W, pitch, psf, p, &d)) return 0;
+        if (p->conv == DEBLUR_CONV_FFT) return fft_iter_ws_bytes(H, W, pitch);
         return iterate_ws_bytes(H, W, pitch, d, use_box(d, p));
     }
     if (op == 2 || op == 3) {
@@ -202,6 +210,12 @@ int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t
         const size_t ck = img * (size_t)p->iters;
         if (overlaps(ckpt, ck, f, img) || overlaps(ckpt, ck, u_in, img) || overlaps(ckpt, ck, u_out, img))
             return DEBLUR_EINVAL;
+    }
+    if (p->conv == DEBLUR_CONV_FFT) {
+        if (!ws || ws_bytes < fft_iter_ws_bytes(H, W, pitch)) return DEBLUR_EWORKSPACE;
+        s = launch_rrrl_fft(f, u_in, u_out, H, W, pitch, d, iter_params(p), p->iters, ckpt, ws,
+                            reinterpret_cast<hipStream_t>(stream));
+        return s == 0 ? DEBLUR_OK : DEBLUR_EDEVICE;
     }
     const bool box = use_box(d, p);
     const size_t need = iterate_ws_bytes(H, W, pitch, d, box);

@@ -160,4 +160,23 @@ DEBLUR_DEV float2* fft_rows(float2* a, float2* b, int nb, const FftPlan& p, cons
     return a;
 }
 
+// Radix sequence for n = 2^a 3^b: threes first, then eights, then 4 or 2.
+inline FftPlan make_plan(int n)
+{
+    FftPlan p{};
+    p.n = n;
+    int m = n;
+    while (m % 3 == 0) {
+        p.radix[p.npass++] = 3;
+        m /= 3;
+    }
+    while (m % 8 == 0) {
+        p.radix[p.npass++] = 8;
+        m /= 8;
+    }
+    if (m == 4) p.radix[p.npass++] = 4;
+    if (m == 2) p.radix[p.npass++] = 2;
+    return p;
+}
+
 }  // namespace deblur

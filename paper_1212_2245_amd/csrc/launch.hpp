@@ -26,6 +26,9 @@ void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, fl
 void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st);
 void launch_fft2_inverse(float2* S, int H, int W, float* out, int pitch, float floor_, bool accumulate,
                          hipStream_t st);
+void launch_rows_fwd(const float* x, int pitch, int H, int W, float2* S, hipStream_t st);
+void launch_cols(float2* S, const float2* mult, bool conj_mult, int mode, int H, int W, hipStream_t st);
+int fft_row_batch(int W);
 void launch_spectral_mul(const float2* Sin, const float2* M, bool conjM, float2* Sout, size_t n, hipStream_t st);
 void launch_wiener_dh_prep(const float2* Fh, const float2* Gh, const float2* hh, float2* Y, size_t n, double K,
                            hipStream_t st);
@@ -60,6 +63,11 @@ int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
                          const PsfDev& psf, const IterParams& p, int iters, bool through_wiener, double K,
                          float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0,
                          void* ws, hipStream_t st);
+
+// Fourier-domain RRRL iterations (periodic continuation), rrrl_fft.hip
+size_t fft_iter_ws_bytes(int H, int W, int pitch);
+int launch_rrrl_fft(const float* f, const float* u_in, float* u_out, int H, int W, int pitch, const PsfDev& psf,
+                    const IterParams& p, int iters, float* ckpt, void* ws, hipStream_t st);
 
 // Batched plans (batch.hip)
 struct BatchPlan;

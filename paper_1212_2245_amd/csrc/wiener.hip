@@ -259,24 +259,6 @@ __global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict_
 }
 
 // ------------------------------------------------------------ host launchers
-static FftPlan make_plan(int n)
-{
-    FftPlan p{};
-    p.n = n;
-    int m = n;
-    while (m % 3 == 0) {
-        p.radix[p.npass++] = 3;
-        m /= 3;
-    }
-    while (m % 8 == 0) {
-        p.radix[p.npass++] = 8;
-        m /= 8;
-    }
-    if (m == 4) p.radix[p.npass++] = 4;
-    if (m == 2) p.radix[p.npass++] = 2;
-    return p;
-}
-
 size_t wiener_ws_bytes(int H, int W, bool rowwise)
 {
     if (rowwise) return (size_t)W * sizeof(float2);
@@ -317,6 +299,7 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
 }
 
 static int row_batch(int W) { return W >= 1024 ? 1 : 1024 / W; }
+int fft_row_batch(int W) { return row_batch(W); }
 static int col_batch(int H) { return H >= 2048 ? 1 : (2048 / H > 8 ? 8 : 2048 / H); }
 
 void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
@@ -342,6 +325,20 @@ void launch_fft2_inverse(float2* S, int H, int W, float* out, int pitch, float f
                        (const float2*)nullptr, H, W, cb, make_plan(H), 2, 0);
     hipLaunchKernelGGL(wiener_rows_inv, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st,
                        (const float2*)S, out, H, W, pitch, nb, make_plan(W), floor_, accumulate ? 1 : 0);
+}
+
+void launch_rows_fwd(const float* x, int pitch, int H, int W, float2* S, hipStream_t st)
+{
+    const int nb = row_batch(W), pairs = (H + 1) / 2;
+    hipLaunchKernelGGL(wiener_rows_fwd, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st, x,
+                       S, H, W, pitch, nb, make_plan(W));
+}
+
+void launch_cols(float2* S, const float2* mult, bool conj_mult, int mode, int H, int W, hipStream_t st)
+{
+    const int cb = col_batch(H), Wh = W / 2 + 1;
+    hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S, mult, H,
+                       W, cb, make_plan(H), mode, conj_mult ? 1 : 0);
 }
 
 void launch_spectral_mul(const float2* Sin, const float2* M, bool conjM, float2* Sout, size_t n, hipStream_t st)

@@ -312,3 +312,42 @@ def test_tile_variants_bitwise_identical(H, W, psfname):
             ref = out
         else:
             assert torch.equal(out, ref), f"tile variant {v} differs"
+
+
+@pytest.mark.parametrize("name,H,W,mk,iters", [
+    ("line21_96x128", 96, 128, lambda: synth.line_psf(21, 0.9), 6),
+    ("gauss31_128", 128, 128, lambda: synth.gauss_mixture_psf(synth.rng_for(2), 31), 8),
+    ("asym7x5_81x48", 81, 48, lambda: synth.random_psf(np.random.default_rng(9), 7, 5), 5),
+    ("box_v15_192x64", 192, 64, lambda: synth.box_psf(15, "v"), 6),
+])
+def test_fft_path_parity(name, H, W, mk, iters):
+    """Fourier-domain iteration (periodic continuation) against the oracle
+    with periodic continuation."""
+    h = mk().astype(np.float32)
+    got, want = iterate_case(H, W, h, synth.KIND_TAPS, 0, iters, bc=oracle.BC_PERIODIC, seed=H)
+    # iterate_case uses the default convolution; rerun through the FFT path
+    rng = np.random.default_rng(H)
+    g = synth.ground_truth(rng, H, W)
+    f = synth.observe(rng, g, h.astype(np.float64), 2.0)
+    u0 = np.maximum(f, 1.0) + rng.uniform(0, 3, size=f.shape).astype(np.float32)
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    dbl.deblur_rrrl_iterate(dev(f), dev(u0), out, gpu_psf(synth.KIND_TAPS, 0, h),
+                            dbl.Params(iters=iters, boundary=dbl.BC_PERIODIC, conv=dbl.CONV_FFT))
+    assert report(f"fft {name}", out.cpu().numpy(), want) <= RTOL_ITER
+    assert report(f"fft vs stencil {name}", out.cpu().numpy(), got) <= RTOL_ITER
+
+
+def test_fft_vs_stencil_full_size_2d_blur():
+    """The 2D-blur workload at its full size (2048^2, dense 31x31 PSF) with
+    periodic continuation: Fourier-domain path against the direct stencil."""
+    c = synth.make_case(2)
+    f = dev(c.f)
+    psf = gpu_psf(c.kind, c.length, c.psf)
+    u0 = torch.clamp(f, min=1.0)
+    outs = []
+    for conv in (dbl.CONV_FFT, dbl.CONV_STENCIL):
+        out = torch.empty_like(f)
+        dbl.deblur_rrrl_iterate(f, u0, out, psf, dbl.Params(alpha=c.alpha, iters=3, boundary=dbl.BC_PERIODIC,
+                                                             conv=conv))
+        outs.append(out.cpu().numpy())
+    assert report("fft vs stencil 2048 gauss31 k3", outs[0], outs[1]) <= 1e-5
