@@ -58,6 +58,11 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--kernel-reps", type=int, default=50, help="launches per stage kernel for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 512-image measurement")
+    ap.add_argument("--batch-images", type=int, default=512)
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--latency-group", type=int, default=64,
+                    help="group size of the latency plan (images run group after group)")
     ap.add_argument("--cpu-iters", type=int, default=20, help="RRRL iterations in the oracle sample")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
@@ -131,6 +136,64 @@ def load_traffic(kernel: str):
     if d.get("source_hash") != kernel_source_hash():
         return None  # kernels changed since the counters were taken
     return (d.get("kernels", {}).get(kernel) or {}).get("traffic_bytes")
+
+
+# ------------------------------------------------------------------- batched
+def bench_batched(dev, args):
+    """512 images, sides from {128,...,1024}, half uniform axis-aligned motion
+    (L 5..41), half oblique lines (L 9..31), 15 iterations each, in one graph
+    launch (one group); per-image latency from a second plan whose images run
+    in consecutive groups."""
+    import torch
+
+    import paper_1212_2245_amd as dbl
+    import synth
+
+    t0 = time.perf_counter()
+    cases = [synth.make_case(3, image=i) for i in range(args.batch_images)]
+    gen_s = time.perf_counter() - t0
+
+    def gpu_psf(c):
+        if c.kind == synth.KIND_BOX_H:
+            return dbl.Psf.box(c.length, "h")
+        if c.kind == synth.KIND_BOX_V:
+            return dbl.Psf.box(c.length, "v")
+        return dbl.Psf.from_taps(torch.from_numpy(c.psf).to(dev))
+
+    items = [(torch.from_numpy(c.f).to(dev), gpu_psf(c), dbl.Params(alpha=c.alpha, iters=c.iters), c.K, 1.0)
+             for c in cases]
+    iters = cases[0].iters
+    npx = sum(c.f.size for c in cases)
+    t0 = time.perf_counter()
+    plan = dbl.BatchPlan(items)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    plan.run()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.batch_reps):
+        plan.run()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.batch_reps
+    plan.close()
+    lat_plan = dbl.BatchPlan(items, group_size=args.latency_group)
+    lat_plan.run()
+    torch.cuda.synchronize()
+    lat = lat_plan.latencies_us()
+    lat_plan.close()
+    import numpy as np
+    alg = 12.0 * npx * iters + 8.0 * npx
+    return {"images": len(cases), "megapixels": round(npx / 1e6, 2), "iters": iters, "ms_per_batch": round(ms, 3),
+            "images_per_s": round(len(cases) / (ms * 1e-3), 1),
+            "mpx_it_per_s": round(npx * iters / (ms * 1e-3) / 1e6, 1),
+            "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "latency_group": args.latency_group,
+            "latency_p50_us": round(float(np.percentile(lat, 50)), 1),
+            "latency_p99_us": round(float(np.percentile(lat, 99)), 1),
+            "plan_create_ms": round(plan_ms, 1), "generate_s": round(gen_s, 1),
+            "kinds": {"box_h": sum(c.kind == 0 for c in cases), "box_v": sum(c.kind == 1 for c in cases),
+                      "line": sum(c.kind == 2 for c in cases)}}
 
 
 # ------------------------------------------------------------------- bench
@@ -244,6 +307,10 @@ def main():
         "wiener_ms": round(ms_wiener, 5),
         "iteration_us": round((ms_step - ms_wiener) * 1e3 / iters, 3),
     }
+
+    if not args.no_batched:
+        print(f"[bench] batched workload: {args.batch_images} images", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(dev, args)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -351,3 +351,16 @@ def test_fft_vs_stencil_full_size_2d_blur():
                                                              conv=conv))
         outs.append(out.cpu().numpy())
     assert report("fft vs stencil 2048 gauss31 k3", outs[0], outs[1]) <= 1e-5
+
+
+def test_autotune_picks_a_valid_identical_shape(tmp_path, monkeypatch):
+    from paper_1212_2245_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tiles.json"))
+    c = synth.make_case(1, size=512)
+    f = dev(c.f)
+    psf = gpu_psf(c.kind, c.length, c.psf)
+    res = autotune.tune(f, psf, dbl.Params(alpha=c.alpha), iters=2, reps=2)
+    n = dbl._lib.load().deblur_tile_variants()
+    assert 1 <= res["tile"] <= n and len(res["timings_us"]) == n
+    assert autotune.best_tile(512, 512, 31, 31) == res["tile"]
+    print(f"[tune] {res['key']}: {res['timings_us']}", flush=True)
