@@ -27,8 +27,8 @@ struct BatchImg {
     const float* f;
     float* buf[2];          // ping-pong; buf[0] is the caller's output
     float2* qw;             // (q, W) plane of stencil images
-    const int4* taps;       // compiled tap list (non-zero taps)
-    const int* ntaps;
+    const TapGroup* taps;   // column groups of the compiled PSF
+    const int* hdr;         // compiled PSF header (hdr[1] = group count)
     int H, W, pitch, L;     // L: box length (box classes)
     IterParams p;
 };
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(BT_NT) batch_stage1(const BatchTile* __restric
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
     stage1_tile<RAD, BT_TH, BT_NT>(tile, im.buf[src], im.f, im.qw, nullptr, im.H, im.W, im.pitch, t.x0, t.y0,
-                                   im.taps, im.ntaps[0], im.p);
+                                   im.taps, im.hdr[1], im.p);
 }
 
 template <int RAD>
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(BT_NT) batch_stage2(const BatchTile* __restric
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
     stage2_tile<RAD, BT_TH, BT_NT>(sm, im.qw, im.buf[src], im.buf[1 - src], nullptr, im.H, im.W, im.pitch, t.x0,
-                                   t.y0, im.taps, im.ntaps[0], im.p);
+                                   t.y0, im.taps, im.hdr[1], im.p);
 }
 
 template <bool VERT>
@@ -160,8 +160,9 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
             return -3;
         }
         launch_compile_taps(it.psf, list, nullptr);
-        b.ntaps = reinterpret_cast<const int*>(list);
-        b.taps = reinterpret_cast<const int4*>(static_cast<unsigned char*>(list) + 256);
+        b.hdr = reinterpret_cast<const int*>(list);
+        b.taps = reinterpret_cast<const TapGroup*>(static_cast<unsigned char*>(list) +
+                                                   tap_groups_offset(it.psf.ph, it.psf.pw));
         b.H = it.H;
         b.W = it.W;
         b.pitch = it.pitch;

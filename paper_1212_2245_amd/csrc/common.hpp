@@ -21,6 +21,16 @@ DEBLUR_DEV int ext_index(int i, int n, int bc)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b mod 8, each XCD with its own L2).  xcd_group maps block b of n to a work
+// index so that the blocks of one XCD take consecutive indices: neighbours
+// that share cache lines then share an L2.  A bijection on [0, n).
+DEBLUR_DEV int xcd_group(int b, int n)
+{
+    const int x = b & 7, slot = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + slot;
+}
+
 DEBLUR_DEV int clampi(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
 
 // Information divergence r_f(s) = s - f - f ln(s/f) (eq. (7)) in FP32,

@@ -17,6 +17,19 @@ struct IterParams {
     int tile;  // tile-shape variant (0 = default)
 };
 
+// Compiled PSF ("tap list" buffer), built on the device by launch_compile_taps:
+//   bytes [0, 256)        header: int count of non-zero taps, int count of
+//                         column groups (a multiple of 4)
+//   bytes [256, ...)      non-zero taps {dy, dx, weight bits, 0}, row-major
+//   bytes [groups_off..)  column groups: runs of up to 8 vertically adjacent
+//                         non-zero taps of one PSF column, column-major order
+struct TapGroup {
+    int dx, dy0, S, pad;  // taps (dy0 + s, dx), s < S; S = 0 pads the list
+    float w[8];
+};
+constexpr int TAP_GROUP_MAX = 8;
+inline size_t tap_groups_offset(int ph, int pw) { return 256 + 16 * (size_t)ph * pw; }
+
 size_t wiener_ws_bytes(int H, int W, bool rowwise);
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
                   float pos_floor, void* ws, bool rowwise, hipStream_t st);

@@ -4,11 +4,15 @@
 // respect to the observed image f, the PSF taps h and the weight alpha.
 //
 // Per reversed iteration k (lam = dL/du^{k+1}), from the checkpoint u^k:
-//   recompute  s = A u (raw), W, q                      (stage-1 kernel)
-//   adj_update N1, N2, D, g; a = lam u/Den, b = -lam u Num/Den^2,
-//              c = alpha (a 1[D>0] - b 1[D<0]), du = lam Num/Den, alpha part
-//   dq, dW_B = B^T (a, b)        B^T = zero-extended convolution + border fold
-//   adj_point  W, q, r_f, s chain -> ds; df accumulated
+//   recompute  s = A u (raw), W, e = W (f - s)/s = q - W   (stage-1 kernel)
+//   adj_update N2 = B W, N3 = B e = N1 - N2, D, g; rho = Num/Den;
+//              a = lam u/Den (= dL/dN1), b = -a rho (= dL/dN2),
+//              c = alpha (a 1[D>0] - b 1[D<0]), du = lam rho, alpha part;
+//              stored: a and bb = b + a = -a (N3 + alpha D)/Den
+//   dq, dBb = B^T (a, bb)        B^T = zero-extended convolution + border fold
+//   adj_point  dW = B^T b + dq f/s = dq (f - s)/s + dBb; r_f, s chain -> ds
+// Near convergence b ~ -a and f ~ s: the rearranged forms avoid the FP32
+// cancellation of B^T b + (B^T a) f/s.
 //   A^T ds                       zero-extended correlation + border fold
 //   adj_tv     lam' = du + A^T ds + diffusion adjoint (frozen g and through g)
 //   adj_dh     per-workgroup partial sums of dL/dh(d) for every PSF entry
@@ -90,15 +94,18 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
         const float up = ut[c], gp = gt[cg];
         const float D = 0.5f * (gp + gt[cg - GW]) * (ut[c - UW] - up) + 0.5f * (gp + gt[cg + GW]) * (ut[c + UW] - up)
                       + 0.5f * (gp + gt[cg - 1]) * (ut[c - 1] - up) + 0.5f * (gp + gt[cg + 1]) * (ut[c + 1] - up);
+        // n1 holds N3 = B e (e = q - W), n2 holds N2 = B W
         const float dp = fmaxf(D, 0.0f), dm = fminf(D, 0.0f);
-        const float num = n1[i] + p.alpha * dp, den = n2[i] - p.alpha * dm;
+        const float num = n2[i] + n1[i] + p.alpha * dp, den = n2[i] - p.alpha * dm;
+        const float rho = num / den;
         const float l = lam[(size_t)y * lam_pitch + x];
         const float a = l * up / den;
-        const float b = -l * up * num / (den * den);
+        const float b = -a * rho;
+        const float bb = -a * ((n1[i] + p.alpha * D) / den);
         const size_t o = (size_t)y * W + x;
-        ab[o] = make_float2(a, b);
+        ab[o] = make_float2(a, bb);
         cpl[o] = p.alpha * ((D > 0.0f ? a : 0.0f) - (D < 0.0f ? b : 0.0f));
-        du[o] = l * num / den;
+        du[o] = l * rho;
         apart += (double)a * dp - (double)b * dm;
     }
     red[tid] = apart;
@@ -200,13 +207,13 @@ __global__ void __launch_bounds__(256) adj_point(const float2* __restrict__ dqw,
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= W) return;
     const size_t o = (size_t)y * W + x, of = (size_t)y * pitch + x;
-    const float2 d = dqw[o], v = qw[o];
+    const float2 d = dqw[o], v = qw[o];   // d = (B^T a, B^T bb), v = (e, W)
     const float sr = s_raw[o];
     const float st = fmaxf(sr, p.s_min);
     const float fv = f[of];
     const float fp = fmaxf(fv, 0.0f);
     const float wt = v.y;
-    const float dW = d.y + d.x * fp / st;
+    const float dW = d.x * ((fp - st) / st) + d.y;
     float dst = -d.x * wt * fp / (st * st);
     float df = fv > 0.0f ? d.x * wt / st : 0.0f;
     if (p.robust) {
@@ -288,6 +295,8 @@ __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int
 // ------------------------------------------------------ dL/dh partial sums
 // For every entry (j, i) of the PSF array, d = (j - cy, i - cx):
 //   sum over the tile of a(x) q(E(x + d)) + b(x) W(E(x + d)) + ds(x) u(E(x - d))
+// where the first two terms are formed as a e(E(x+d)) + bb W(E(x+d))
+// (q = e + W, bb = a + b).
 // added to this workgroup's slot of `part` (FP64).
 template <int RAD>
 __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, const float2* __restrict__ qw,

@@ -21,9 +21,11 @@
 namespace deblur {
 
 // Compacted list of the non-zero taps, row-major order: {dy, dx, w bits, 0},
-// count stored in list_count[0].  Single workgroup.
+// count in hdr[0]; then the column groups (runs of vertically adjacent
+// non-zero taps, split every TAP_GROUP_MAX rows), count rounded up to a
+// multiple of 4 with empty groups, in hdr[1].  Single workgroup.
 __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restrict__ list,
-                                                      int* __restrict__ list_count)
+                                                      TapGroup* __restrict__ groups, int* __restrict__ hdr)
 {
     __shared__ int counts[256];
     const int n = psf.ph * psf.pw;
@@ -47,7 +49,62 @@ __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restri
         const float w = psf_weight(psf, j, i);
         if (w != 0.0f) list[o++] = make_int4(j - cy, i - cx, __float_as_int(w), 0);
     }
-    if (threadIdx.x == 255) list_count[0] = counts[255];
+    if (threadIdx.x == 255) hdr[0] = counts[255];
+    __syncthreads();
+
+    // column groups: thread i owns PSF column i (pw <= 256)
+    const int col = threadIdx.x;
+    int ng = 0;
+    if (col < psf.pw) {
+        int run = 0;
+        for (int j = 0; j < psf.ph; ++j) {
+            if (psf_weight(psf, j, col) != 0.0f) {
+                if (run == 0 || run == TAP_GROUP_MAX) {
+                    ++ng;
+                    run = 0;
+                }
+                ++run;
+            } else {
+                run = 0;
+            }
+        }
+    }
+    counts[threadIdx.x] = ng;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = threadIdx.x >= off ? counts[threadIdx.x - off] : 0;
+        __syncthreads();
+        counts[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (col < psf.pw) {
+        int g = counts[threadIdx.x] - ng - 1, run = 0;
+        for (int j = 0; j < psf.ph; ++j) {
+            const float w = psf_weight(psf, j, col);
+            if (w != 0.0f) {
+                if (run == 0 || run == TAP_GROUP_MAX) {
+                    ++g;
+                    run = 0;
+                    groups[g].dx = col - cx;
+                    groups[g].dy0 = j - cy;
+                    groups[g].pad = 0;
+                    for (int s = 0; s < TAP_GROUP_MAX; ++s) groups[g].w[s] = 0.0f;
+                }
+                groups[g].w[run++] = w;
+                groups[g].S = run;
+            } else {
+                run = 0;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        const int total = counts[255], padded = (total + 3) & ~3;
+        for (int g = total; g < padded; ++g) {
+            groups[g].dx = groups[g].dy0 = groups[g].S = groups[g].pad = 0;
+            for (int s = 0; s < TAP_GROUP_MAX; ++s) groups[g].w[s] = 0.0f;
+        }
+        hdr[1] = padded;
+    }
 }
 
 // ------------------------------------------------------------ host launchers
@@ -72,7 +129,7 @@ int taps_num_variants() { return kNumVariants; }
 
 template <int RAD, int TH, int NT>
 static void stage1_inst(const float* f, const float* u, float2* qw, float* s_out, int H, int W, int pitch,
-                        const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+                        const TapGroup* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     const dim3 g((W + 63) / 64, (H + TH - 1) / TH);
     hipLaunchKernelGGL((rrrl_taps_stage1<RAD, TH, NT>), g, dim3(NT), 0, st, u, f, qw, s_out, H, W, pitch, taps, nt,
@@ -81,7 +138,7 @@ static void stage1_inst(const float* f, const float* u, float2* qw, float* s_out
 
 template <int RAD, int TH, int NT>
 static void stage2_inst(const float2* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
-                        const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+                        const TapGroup* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     const dim3 g((W + 63) / 64, (H + TH - 1) / TH);
     hipLaunchKernelGGL((rrrl_taps_stage2<RAD, TH, NT>), g, dim3(NT), 0, st, qw, u, un, ckpt, H, W, pitch, taps, nt,
@@ -90,7 +147,7 @@ static void stage2_inst(const float2* qw, const float* u, float* un, float* ckpt
 
 template <int RAD>
 static void launch_stage1_t(int v, const float* f, const float* u, float2* qw, float* s_out, int H, int W,
-                            int pitch, const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+                            int pitch, const TapGroup* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     switch (v) {
         case 0: stage1_inst<RAD, 64, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
@@ -103,7 +160,7 @@ static void launch_stage1_t(int v, const float* f, const float* u, float2* qw, f
 
 template <int RAD>
 static void launch_stage2_t(int v, const float2* qw, const float* u, float* un, float* ckpt, int H, int W,
-                            int pitch, const int4* taps, const int* nt, const IterParams& p, hipStream_t st)
+                            int pitch, const TapGroup* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     // 64-row tiles of the two-channel plane exceed LDS for the largest radius
     if (RAD >= 32 && (v == 0 || v == 1)) v = 3;
@@ -126,12 +183,17 @@ static int default_variant(int H, int W, int stage)
     return 4;
 }
 
-size_t tap_list_bytes(const PsfDev& psf) { return 256 + 16 * (size_t)psf.ph * psf.pw; }
+size_t tap_list_bytes(const PsfDev& psf)
+{
+    const size_t P = (size_t)psf.ph * psf.pw;
+    return tap_groups_offset(psf.ph, psf.pw) + sizeof(TapGroup) * (P + 3);
+}
 
 void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st)
 {
     unsigned char* w8 = reinterpret_cast<unsigned char*>(list);
     hipLaunchKernelGGL(build_tap_list, dim3(1), dim3(256), 0, st, psf, reinterpret_cast<int4*>(w8 + 256),
+                       reinterpret_cast<TapGroup*>(w8 + tap_groups_offset(psf.ph, psf.pw)),
                        reinterpret_cast<int*>(w8));
 }
 
@@ -146,7 +208,7 @@ int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, 
     const int v = variant > 0 ? variant - 1 : default_variant(H, W, 1);
     const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
     const int* nt = reinterpret_cast<const int*>(w8);
-    const int4* taps = reinterpret_cast<const int4*>(w8 + 256);
+    const TapGroup* taps = reinterpret_cast<const TapGroup*>(w8 + tap_groups_offset(psf.ph, psf.pw));
     float2* q2 = reinterpret_cast<float2*>(qw);
     switch (psf_radius_class(psf)) {
         case 4: launch_stage1_t<4>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
@@ -164,7 +226,7 @@ int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, 
     const int v = variant > 0 ? variant - 1 : default_variant(H, W, 2);
     const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
     const int* nt = reinterpret_cast<const int*>(w8);
-    const int4* taps = reinterpret_cast<const int4*>(w8 + 256);
+    const TapGroup* taps = reinterpret_cast<const TapGroup*>(w8 + tap_groups_offset(psf.ph, psf.pw));
     const float2* q2 = reinterpret_cast<const float2*>(qw);
     switch (psf_radius_class(psf)) {
         case 4: launch_stage2_t<4>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;

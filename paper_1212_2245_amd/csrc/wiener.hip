@@ -21,25 +21,46 @@
 
 namespace deblur {
 
+// exp(-2 pi i m / n) for an integer m reduced mod n (exact reduction, FP64).
+DEBLUR_DEV double2 unit_root(long long m, int n)
+{
+    m %= n;
+    if (m < 0) m += n;
+    double s, c;
+    sincospi(2.0 * (double)m / (double)n, &s, &c);
+    return make_double2(c, -s);
+}
+
+DEBLUR_DEV double2 zmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// sum_i h(j, i) exp(-2 pi i k (i - c) / n) over one PSF row j, the phase
+// advanced by the FP64 recurrence t <- t exp(-2 pi i k / n) (at most 65
+// steps: relative drift ~1e-14, far below the FP32 rounding of the result).
+DEBLUR_DEV double2 psf_row_dft(const PsfDev& psf, int j, int k, int n, int c)
+{
+    const double2 w = unit_root(k, n);
+    double2 t = unit_root(-(long long)k * c, n);
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < psf.pw; ++i) {
+        const double h = (double)psf_weight(psf, j, i);
+        re = fma(h, t.x, re);
+        im = fma(h, t.y, im);
+        t = zmul(t, w);
+    }
+    return make_double2(re, im);
+}
+
 // M(k) = conj(h^(k)) / (|h^(k)|^2 + K) for a PSF on one row, k < n.
 __global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double K, float2* __restrict__ M)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const int cx = (psf.pw - 1) / 2;
-    double re = 0.0, im = 0.0;
-    for (int i = 0; i < psf.pw; ++i) {
-        const double w = (double)psf_weight(psf, 0, i);
-        if (w == 0.0) continue;
-        long long m = ((long long)k * (long long)(i - cx)) % n;
-        if (m < 0) m += n;
-        double s, c;
-        sincospi(2.0 * (double)m / (double)n, &s, &c);
-        re += w * c;       // exp(-2 pi i k d / n)
-        im -= w * s;
-    }
-    const double den = re * re + im * im + K;
-    M[k] = make_float2((float)(re / den), (float)(-im / den));
+    const double2 hk = psf_row_dft(psf, 0, k, n, (psf.pw - 1) / 2);
+    const double den = hk.x * hk.x + hk.y * hk.y + K;
+    M[k] = make_float2((float)(hk.x / den), (float)(-hk.y / den));
 }
 
 // One workgroup per `nb` row pairs; LDS: two ping-pong buffers of nb*n
@@ -82,51 +103,47 @@ __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict
     }
 }
 
-// M(ky, kx) for kx <= W/2, stored row-major with row pitch W/2+1.  One
-// workgroup per column kx: G_j(kx) = sum_i h[j][i] w_W^(kx (i-cx)) first,
-// then h^(ky,kx) = sum_j G_j(kx) w_H^(ky (j-cy)) with an FP64 twiddle table.
+// M(ky, kx) for kx <= W/2, stored row-major with row pitch W/2+1 (the
+// layout of the half spectra).  Workgroup = 16 consecutive kx (one 128-byte
+// row segment of M per ky) x MULT_KY rows ky.  The PSF rows are first
+// transformed along x, G(j, kx) = sum_i h(j, i) e^{-2 pi i kx (i - cx)/W}
+// (LDS, FP64), then h^(ky, kx) = sum_j G(j, kx) e^{-2 pi i ky (j - cy)/H}.
+// Optionally also h^ itself (hh, complex64).
+constexpr int MULT_KX = 16, MULT_KY = 64, MULT_MAXP = 65;
 __global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, double K, float2* __restrict__ M,
                                                       float2* __restrict__ hh)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double2* twh = reinterpret_cast<double2*>(smem_raw);  // H entries: exp(-2 pi i m / H)
-    double2* G = twh + H;                                  // ph entries
-    double2* px = G + psf.ph;                              // pw entries: exp(-2 pi i kx (i - cx) / W)
-    const int kx = blockIdx.x;
+    __shared__ double2 G[MULT_MAXP * MULT_KX];
     const int Wh = W / 2 + 1;
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
-    twiddle_table(twh, H);
-    for (int i = threadIdx.x; i < psf.pw; i += blockDim.x) {
-        long long m = ((long long)kx * (long long)(i - cx)) % W;
-        if (m < 0) m += W;
-        double s, c;
-        sincospi(2.0 * (double)m / (double)W, &s, &c);
-        px[i] = make_double2(c, -s);
+    const int kx0 = blockIdx.x * MULT_KX, ky0 = blockIdx.y * MULT_KY;
+    for (int idx = threadIdx.x; idx < psf.ph * MULT_KX; idx += blockDim.x) {
+        const int j = idx / MULT_KX, kx = kx0 + idx % MULT_KX;
+        G[idx] = kx < Wh ? psf_row_dft(psf, j, kx, W, cx) : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < psf.ph; j += blockDim.x) {
-        double re = 0.0, im = 0.0;
-        for (int i = 0; i < psf.pw; ++i) {
-            const double w = (double)psf_weight(psf, j, i);
-            re += w * px[i].x;
-            im += w * px[i].y;
-        }
-        G[j] = make_double2(re, im);
-    }
-    __syncthreads();
-    for (int ky = threadIdx.x; ky < H; ky += blockDim.x) {
+    const int lx = threadIdx.x % MULT_KX, kx = kx0 + lx;
+    if (kx >= Wh) return;
+    for (int ky = ky0 + threadIdx.x / MULT_KX; ky < min(ky0 + MULT_KY, H); ky += 256 / MULT_KX) {
+        const double2 w = unit_root(ky, H);
+        double2 t = unit_root(-(long long)ky * cy, H);
         double re = 0.0, im = 0.0;
         for (int j = 0; j < psf.ph; ++j) {
-            int m = (int)(((long long)ky * (long long)(j - cy)) % H);
-            if (m < 0) m += H;
-            const double2 t = twh[m], g = G[j];
+            const double2 g = G[j * MULT_KX + lx];
             re += g.x * t.x - g.y * t.y;
             im += g.x * t.y + g.y * t.x;
+            t = zmul(t, w);
         }
         const double den = re * re + im * im + K;
         M[(size_t)ky * Wh + kx] = make_float2((float)(re / den), (float)(-im / den));
         if (hh) hh[(size_t)ky * Wh + kx] = make_float2((float)re, (float)im);
     }
+}
+
+static void mult_2d_launch(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
+{
+    const dim3 grid((W / 2 + 1 + MULT_KX - 1) / MULT_KX, (H + MULT_KY - 1) / MULT_KY);
+    hipLaunchKernelGGL(wiener_mult_2d, grid, dim3(256), 0, st, psf, H, W, K, M, hh);
 }
 
 // Row pass: rows (2p, 2p+1) packed as z = f_a + i f_b, FFT along x, unpacked
@@ -173,7 +190,7 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
     float2* b = a + cb * H;
     fft_twiddles(tw, H);
     const int Wh = W / 2 + 1;
-    const int c0 = blockIdx.x * cb;
+    const int c0 = xcd_group(blockIdx.x, gridDim.x) * cb;
     for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
         const int y = idx / cb, c = idx - y * cb;
         float2 v = (c0 + c < Wh) ? S[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
@@ -281,8 +298,7 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
         const int Wh = W / 2 + 1;
         float2* M = reinterpret_cast<float2*>(ws);
         float2* S = M + (size_t)H * Wh;
-        hipLaunchKernelGGL(wiener_mult_2d, dim3(Wh), dim3(256), (size_t)(H + psf.ph + psf.pw) * sizeof(double2),
-                           st, psf, H, W, K, M, (float2*)nullptr);
+        mult_2d_launch(psf, H, W, K, M, nullptr, st);
         const int pairs = (H + 1) / 2;
         const int nb = W >= 1024 ? 1 : 1024 / W;
         const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(float2);
@@ -304,8 +320,7 @@ static int col_batch(int H) { return H >= 2048 ? 1 : (2048 / H > 8 ? 8 : 2048 / 
 
 void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
 {
-    hipLaunchKernelGGL(wiener_mult_2d, dim3(W / 2 + 1), dim3(256), (size_t)(H + psf.ph + psf.pw) * sizeof(double2),
-                       st, psf, H, W, K, M, hh);
+    mult_2d_launch(psf, H, W, K, M, hh, st);
 }
 
 void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st)
