@@ -28,7 +28,7 @@ struct BatchImg {
     float* buf[2];          // ping-pong; buf[0] is the caller's output
     float2* qw;             // (q, W) plane of stencil images
     const TapGroup* taps;   // column groups of the compiled PSF
-    const int* hdr;         // compiled PSF header (hdr[1] = group count)
+    const int* hdr;         // compiled PSF header (group counts per run length)
     int H, W, pitch, L;     // L: box length (box classes)
     IterParams p;
 };
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(BT_NT) batch_stage1(const BatchTile* __restric
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
     stage1_tile<RAD, BT_TH, BT_NT>(tile, im.buf[src], im.f, im.qw, nullptr, im.H, im.W, im.pitch, t.x0, t.y0,
-                                   im.taps, im.hdr[1], im.p);
+                                   im.taps, im.hdr, im.p);
 }
 
 template <int RAD>
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(BT_NT) batch_stage2(const BatchTile* __restric
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
     stage2_tile<RAD, BT_TH, BT_NT>(sm, im.qw, im.buf[src], im.buf[1 - src], nullptr, im.H, im.W, im.pitch, t.x0,
-                                   t.y0, im.taps, im.hdr[1], im.p);
+                                   t.y0, im.taps, im.hdr, im.p);
 }
 
 template <bool VERT>

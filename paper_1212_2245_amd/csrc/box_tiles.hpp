@@ -119,14 +119,21 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
     const int W = VERT ? bt.across_n : bt.along_n;
 
     // 1. u tile: along extended by the boundary mode, across clamped
-    for (int i = t; i < CU * nu; i += 256) {
-        int c, j;
-        if (VERT) { j = i / CU; c = i - j * CU; } else { c = i / nu; j = i - c * nu; }
-        const int ga = ext_index(lo + j, bt.along_n, p.bc);
-        const int gc = clampi(c0 - 2 + c, bt.across_n);
-        const int y = VERT ? ga : gc, x = VERT ? gc : ga;
-        us[Lay::at(c, j, nu, CU)] = u[(size_t)y * pitch + x];
-    }
+    batched_n<8>(
+        CU * nu,
+        [&](int i) {
+            int c, j;
+            if (VERT) { j = i / CU; c = i - j * CU; } else { c = i / nu; j = i - c * nu; }
+            const int ga = ext_index(lo + j, bt.along_n, p.bc);
+            const int gc = clampi(c0 - 2 + c, bt.across_n);
+            const int y = VERT ? ga : gc, x = VERT ? gc : ga;
+            return u[(size_t)y * pitch + x];
+        },
+        [&](int i, float v) {
+            int c, j;
+            if (VERT) { j = i / CU; c = i - j * CU; } else { c = i / nu; j = i - c * nu; }
+            us[Lay::at(c, j, nu, CU)] = v;
+        });
     __syncthreads();
     // 2a. copy of the TC center lines for the prefix, 2b. diffusivity
     for (int i = t; i < TC * nu; i += 256) {
@@ -151,28 +158,38 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
     prefix_lines<VERT, TA, TC, double>(ps, nu, TC, sums);
     // 3. s = A u, W, q on positions m = 0..nq-1 (along a0 - aL + m)
     const float invL = 1.0f / (float)bt.L;
-    for (int i = t; i < TC * nq; i += 256) {
-        int c, m;
-        if (VERT) { m = i / TC; c = i - m * TC; } else { c = i / nq; m = i - c * nq; }
-        const int gc = c0 + c;
-        double2 qw = make_double2(0.0, 0.0);
-        if (gc < bt.across_n) {
-            // B reads E(q)(x'): q at the continued position.  Periodic: the
-            // tile holds the wrapped u, so x' itself is used; constant
-            // continuation: q(clamp(x')), i.e. A u at the clamped position.
-            const int xa = a0 - bt.aL + m;
-            const int ga = ext_index(xa, bt.along_n, p.bc);
-            const int j = (p.bc == BC_PERIODIC ? xa : ga) - lo;  // tile position of the sample
-            const int hi = j + bt.aL, lo2 = j - bt.bL - 1;          // A window [j - bL, j + aL]
-            const double sum = ps[Lay::at(c, hi, nu, TC)] - (lo2 >= 0 ? ps[Lay::at(c, lo2, nu, TC)] : 0.0);
-            const float s = fmaxf((float)fmax(sum, 0.0) * invL, p.s_min);
+    // f is fetched for several positions before any is used
+    batched_n<8>(
+        TC * nq,
+        [&](int i) {
+            int c, m;
+            if (VERT) { m = i / TC; c = i - m * TC; } else { c = i / nq; m = i - c * nq; }
+            const int gc = c0 + c;
+            if (gc >= bt.across_n) return 0.0f;
+            const int ga = ext_index(a0 - bt.aL + m, bt.along_n, p.bc);
             const int y = VERT ? ga : gc, x = VERT ? gc : ga;
-            const float fv = f[(size_t)y * pitch + x];
-            const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
-            qw = make_double2((double)(wt * fmaxf(fv, 0.0f) / s), (double)wt);
-        }
-        qs[Lay::at(c, m, nq, TC)] = qw;
-    }
+            return f[(size_t)y * pitch + x];
+        },
+        [&](int i, float fv) {
+            int c, m;
+            if (VERT) { m = i / TC; c = i - m * TC; } else { c = i / nq; m = i - c * nq; }
+            const int gc = c0 + c;
+            double2 qw = make_double2(0.0, 0.0);
+            if (gc < bt.across_n) {
+                // B reads E(q)(x'): q at the continued position.  Periodic: the
+                // tile holds the wrapped u, so x' itself is used; constant
+                // continuation: q(clamp(x')), i.e. A u at the clamped position.
+                const int xa = a0 - bt.aL + m;
+                const int ga = ext_index(xa, bt.along_n, p.bc);
+                const int j = (p.bc == BC_PERIODIC ? xa : ga) - lo;  // tile position of the sample
+                const int hi = j + bt.aL, lo2 = j - bt.bL - 1;          // A window [j - bL, j + aL]
+                const double sum = ps[Lay::at(c, hi, nu, TC)] - (lo2 >= 0 ? ps[Lay::at(c, lo2, nu, TC)] : 0.0);
+                const float s = fmaxf((float)fmax(sum, 0.0) * invL, p.s_min);
+                const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
+                qw = make_double2((double)(wt * fmaxf(fv, 0.0f) * rcp(s)), (double)wt);
+            }
+            qs[Lay::at(c, m, nq, TC)] = qw;
+        });
     __syncthreads();
     prefix_lines<VERT, TA, TC, double2>(qs, nq, TC, sums2);
     // 5. correlation, diffusion term, update
@@ -201,7 +218,7 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
         const int y = VERT ? ga : gc, x = VERT ? gc : ga;
         const size_t off = (size_t)y * pitch + x;
         if (ckpt) ckpt[off] = up;
-        un[off] = up * num / den;
+        un[off] = up * num * rcp(den);
     }
     (void)G;
     (void)H;

@@ -48,15 +48,15 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
     __shared__ double red[BW_NT];
     const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < LH * LW; idx += BW_NT) {
+    stage_to_lds<BW_NT, LH * LW>(qt, [&](int idx) {
         const int ly = idx / LW, lx = idx - ly * LW;
         const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
-        qt[idx] = qw[(size_t)gy * W + gx];
-    }
-    for (int idx = tid; idx < UH * UW; idx += BW_NT) {
+        return qw[(size_t)gy * W + gx];
+    });
+    stage_to_lds<BW_NT, UH * UW>(ut, [&](int idx) {
         const int ly = idx / UW, lx = idx - ly * UW;
-        ut[idx] = u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
-    }
+        return u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
+    });
     __syncthreads();
     for (int idx = tid; idx < GH * GW; idx += BW_NT) {
         const int a = idx / GW, b = idx - a * GW;
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
     __shared__ T vt[LH * LW];
     const int zx0 = ox + blockIdx.x * TW, zy0 = oy + blockIdx.y * TH;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < LH * LW; idx += BW_NT) {
+    stage_to_lds<BW_NT, LH * LW>(vt, [&](int idx) {
         const int ly = idx / LW, lx = idx - ly * LW;
         int gy = zy0 - RAD + ly, gx = zx0 - RAD + lx;
         T val{};
@@ -141,8 +141,8 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
         } else if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
             val = v[(size_t)gy * vpitch + gx];
         }
-        vt[idx] = val;
-    }
+        return val;
+    });
     __syncthreads();
     const int tx = tid & 63, ty = tid >> 6;
     T acc[R];
@@ -243,12 +243,14 @@ __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int
     __shared__ float gt[GH * GW], dgx[GH * GW], dgy[GH * GW];
     const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < UH * UW; idx += BW_NT) {
+    stage_to_lds<BW_NT, UH * UW>(ut, [&](int idx) {
         const int ly = idx / UW, lx = idx - ly * UW;
-        const int gy = clampi(y0 - 2 + ly, H), gx = clampi(x0 - 2 + lx, W);
-        ut[idx] = u[(size_t)gy * pitch + gx];
-        ct[idx] = cpl[(size_t)gy * W + gx];
-    }
+        return u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
+    });
+    stage_to_lds<BW_NT, UH * UW>(ct, [&](int idx) {
+        const int ly = idx / UW, lx = idx - ly * UW;
+        return cpl[(size_t)clampi(y0 - 2 + ly, H) * W + clampi(x0 - 2 + lx, W)];
+    });
     __syncthreads();
     // at grid points (y0-1+a, x0-1+b): g, and dL/dgx, dL/dgy through g
     for (int idx = tid; idx < GH * GW; idx += BW_NT) {
@@ -321,16 +323,16 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
         off[k] = (j - cy) * LW + (i - cx);
     }
     // a, b with the (q, W) plane at x + d
-    for (int idx = tid; idx < TH * TW; idx += BW_NT) {
+    stage_to_lds<BW_NT, TH * TW>(ct, [&](int idx) {
         const int ly = idx / TW, lx = idx - ly * TW;
         const int y = y0 + ly, x = x0 + lx;
-        ct[idx] = (y < H && x < W) ? ab[(size_t)y * W + x] : make_float2(0.0f, 0.0f);
-    }
-    for (int idx = tid; idx < LH * LW; idx += BW_NT) {
+        return (y < H && x < W) ? ab[(size_t)y * W + x] : make_float2(0.0f, 0.0f);
+    });
+    stage_to_lds<BW_NT, LH * LW>(ht, [&](int idx) {
         const int ly = idx / LW, lx = idx - ly * LW;
         const int gy = ext_index(y0 - RAD + ly, H, bc), gx = ext_index(x0 - RAD + lx, W, bc);
-        ht[idx] = qw[(size_t)gy * W + gx];
-    }
+        return qw[(size_t)gy * W + gx];
+    });
     __syncthreads();
     for (int ly = 0; ly < TH; ++ly)
         for (int lx = 0; lx < TW; ++lx) {
@@ -344,17 +346,17 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
         }
     __syncthreads();
     // ds with u at x - d
-    for (int idx = tid; idx < TH * TW; idx += BW_NT) {
+    stage_to_lds<BW_NT, TH * TW>(ct, [&](int idx) {
         const int ly = idx / TW, lx = idx - ly * TW;
         const int y = y0 + ly, x = x0 + lx;
-        ct[idx] = make_float2((y < H && x < W) ? ds[(size_t)y * W + x] : 0.0f, 0.0f);
-    }
+        return make_float2((y < H && x < W) ? ds[(size_t)y * W + x] : 0.0f, 0.0f);
+    });
     float* hs = reinterpret_cast<float*>(ht);
-    for (int idx = tid; idx < LH * LW; idx += BW_NT) {
+    stage_to_lds<BW_NT, LH * LW>(hs, [&](int idx) {
         const int ly = idx / LW, lx = idx - ly * LW;
         const int gy = ext_index(y0 - RAD + ly, H, bc), gx = ext_index(x0 - RAD + lx, W, bc);
-        hs[idx] = u[(size_t)gy * pitch + gx];
-    }
+        return u[(size_t)gy * pitch + gx];
+    });
     __syncthreads();
     for (int ly = 0; ly < TH; ++ly)
         for (int lx = 0; lx < TW; ++lx) {

@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(256) fftp_rows_inv_weights(const float2* __res
     fft_twiddles(tw, W);
     const int Wh = W / 2 + 1;
     const int pair0 = blockIdx.x * nb;
-    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+    stage_to_lds_n<8>(a, nb * W, [&](int idx) {
         const int t = idx / W, k = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
         const bool lo = k < Wh;
@@ -38,8 +38,8 @@ __global__ void __launch_bounds__(256) fftp_rows_inv_weights(const float2* __res
             ua = cconj(ua);
             ub = cconj(ub);
         }
-        a[idx] = make_float2(ua.x - ub.y, -(ua.y + ub.x));
-    }
+        return make_float2(ua.x - ub.y, -(ua.y + ub.x));
+    });
     __syncthreads();
     const float2* Z = fft_rows(a, b, nb, plan, tw);
     const float inv = 1.0f / (float)W;
@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(256) fftp_rows_inv_weights(const float2* __res
             const float s = fmaxf(h == 0 ? z.x * inv : -z.y * inv, p.s_min);
             const float fv = f[(size_t)y * pitch + x];
             const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
-            qo[(size_t)y * W + x] = wt * fmaxf(fv, 0.0f) / s;
+            qo[(size_t)y * W + x] = wt * fmaxf(fv, 0.0f) * rcp(s);
             wo[(size_t)y * W + x] = wt;
         }
     }
@@ -71,11 +71,11 @@ __global__ void __launch_bounds__(256) fftp_rows_fwd_pair(const float* __restric
     float2* b = a + nb * W;
     fft_twiddles(tw, W);
     const int y0 = blockIdx.x * nb;
-    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+    stage_to_lds_n<8>(a, nb * W, [&](int idx) {
         const int t = idx / W, x = idx - t * W;
         const int y = y0 + t;
-        a[idx] = y < H ? make_float2(qi[(size_t)y * W + x], wi[(size_t)y * W + x]) : make_float2(0.0f, 0.0f);
-    }
+        return y < H ? make_float2(qi[(size_t)y * W + x], wi[(size_t)y * W + x]) : make_float2(0.0f, 0.0f);
+    });
     __syncthreads();
     const float2* Z = fft_rows(a, b, nb, plan, tw);
     const int Wh = W / 2 + 1;
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(256) fftp_rows_inv_pair(const float2* __restri
     fft_twiddles(tw, W);
     const int Wh = W / 2 + 1;
     const int y0 = blockIdx.x * nb;
-    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+    stage_to_lds_n<8>(a, nb * W, [&](int idx) {
         const int t = idx / W, k = idx - t * W;
         const int y = y0 + t;
         const bool lo = k < Wh;
@@ -114,8 +114,8 @@ __global__ void __launch_bounds__(256) fftp_rows_inv_pair(const float2* __restri
             ua = cconj(ua);
             ub = cconj(ub);
         }
-        a[idx] = make_float2(ua.x - ub.y, -(ua.y + ub.x));
-    }
+        return make_float2(ua.x - ub.y, -(ua.y + ub.x));
+    });
     __syncthreads();
     const float2* Z = fft_rows(a, b, nb, plan, tw);
     const float inv = 1.0f / (float)W;
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(256) fftp_update(const float* __restrict__ u, 
         const float den = n2[o] - p.alpha * fminf(D, 0.0f);
         const size_t op = (size_t)y * pitch + x;
         if (ckpt) ckpt[op] = up;
-        u_next[op] = up * num / den;
+        u_next[op] = up * num * rcp(den);
     }
 }
 

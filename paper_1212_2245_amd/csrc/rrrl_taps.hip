@@ -21,13 +21,17 @@
 namespace deblur {
 
 // Compacted list of the non-zero taps, row-major order: {dy, dx, w bits, 0},
-// count in hdr[0]; then the column groups (runs of vertically adjacent
-// non-zero taps, split every TAP_GROUP_MAX rows), count rounded up to a
-// multiple of 4 with empty groups, in hdr[1].  Single workgroup.
+// count in hdr[0].  Then the column groups: runs of vertically adjacent
+// non-zero taps of one PSF column, split every TAP_GROUP_MAX rows, ordered by
+// run length S (longest first) and within one length by column and row;
+// hdr[1] = number of groups, hdr[1 + S] = number of groups of length S.
+// Single workgroup of 256 threads (pw <= 256).
 __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restrict__ list,
                                                       TapGroup* __restrict__ groups, int* __restrict__ hdr)
 {
     __shared__ int counts[256];
+    __shared__ int cls[TAP_GROUP_MAX][256];   // groups of length S+1 in column i, then their offsets
+    __shared__ int cls_base[TAP_GROUP_MAX];
     const int n = psf.ph * psf.pw;
     const int per = (n + 255) / 256;
     const int b = threadIdx.x * per, e = min(n, b + per);
@@ -50,60 +54,67 @@ __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restri
         if (w != 0.0f) list[o++] = make_int4(j - cy, i - cx, __float_as_int(w), 0);
     }
     if (threadIdx.x == 255) hdr[0] = counts[255];
-    __syncthreads();
 
-    // column groups: thread i owns PSF column i (pw <= 256)
+    // column groups: thread `col` walks PSF column col; a run of r adjacent
+    // non-zero taps gives floor(r/8) groups of 8 and one of r mod 8
     const int col = threadIdx.x;
-    int ng = 0;
+    for (int q = 0; q < TAP_GROUP_MAX; ++q) cls[q][col] = 0;
     if (col < psf.pw) {
         int run = 0;
-        for (int j = 0; j < psf.ph; ++j) {
-            if (psf_weight(psf, j, col) != 0.0f) {
-                if (run == 0 || run == TAP_GROUP_MAX) {
-                    ++ng;
-                    run = 0;
-                }
+        for (int j = 0; j <= psf.ph; ++j) {
+            const bool nz = j < psf.ph && psf_weight(psf, j, col) != 0.0f;
+            if (nz && run < TAP_GROUP_MAX) {
                 ++run;
-            } else {
-                run = 0;
+                continue;
             }
+            if (run > 0) ++cls[run - 1][col];
+            run = nz ? 1 : 0;
         }
     }
-    counts[threadIdx.x] = ng;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int v = threadIdx.x >= off ? counts[threadIdx.x - off] : 0;
-        __syncthreads();
-        counts[threadIdx.x] += v;
-        __syncthreads();
-    }
-    if (col < psf.pw) {
-        int g = counts[threadIdx.x] - ng - 1, run = 0;
-        for (int j = 0; j < psf.ph; ++j) {
-            const float w = psf_weight(psf, j, col);
-            if (w != 0.0f) {
-                if (run == 0 || run == TAP_GROUP_MAX) {
-                    ++g;
-                    run = 0;
-                    groups[g].dx = col - cx;
-                    groups[g].dy0 = j - cy;
-                    groups[g].pad = 0;
-                    for (int s = 0; s < TAP_GROUP_MAX; ++s) groups[g].w[s] = 0.0f;
-                }
-                groups[g].w[run++] = w;
-                groups[g].S = run;
-            } else {
-                run = 0;
-            }
+    // exclusive prefix over the columns, one length class per thread
+    if (threadIdx.x < TAP_GROUP_MAX) {
+        int acc = 0;
+        for (int i = 0; i < psf.pw; ++i) {
+            const int v = cls[threadIdx.x][i];
+            cls[threadIdx.x][i] = acc;
+            acc += v;
         }
+        counts[threadIdx.x] = acc;   // total of the class
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const int total = counts[255], padded = (total + 3) & ~3;
-        for (int g = total; g < padded; ++g) {
-            groups[g].dx = groups[g].dy0 = groups[g].S = groups[g].pad = 0;
-            for (int s = 0; s < TAP_GROUP_MAX; ++s) groups[g].w[s] = 0.0f;
+        int base = 0;
+        for (int q = TAP_GROUP_MAX - 1; q >= 0; --q) {
+            cls_base[q] = base;
+            base += counts[q];
+            hdr[2 + q] = counts[q];
         }
-        hdr[1] = padded;
+        hdr[1] = base;
+    }
+    __syncthreads();
+    if (col < psf.pw) {
+        int next[TAP_GROUP_MAX];
+        for (int q = 0; q < TAP_GROUP_MAX; ++q) next[q] = cls_base[q] + cls[q][col];
+        int run = 0, j0 = 0;
+        for (int j = 0; j <= psf.ph; ++j) {
+            const bool nz = j < psf.ph && psf_weight(psf, j, col) != 0.0f;
+            if (nz && run < TAP_GROUP_MAX) {
+                if (run == 0) j0 = j;
+                ++run;
+                continue;
+            }
+            if (run > 0) {
+                TapGroup& g = groups[next[run - 1]++];
+                g.dx = col - cx;
+                g.dy0 = j0 - cy;
+                g.S = run;
+                g.pad = 0;
+                for (int s = 0; s < TAP_GROUP_MAX; ++s) g.w[s] = s < run ? psf_weight(psf, j0 + s, col) : 0.0f;
+            }
+            run = nz ? 1 : 0;
+            j0 = j;
+        }
     }
 }
 
@@ -122,7 +133,8 @@ int tap_radius_class(int rad)
 struct TileVariant {
     int th, nt;
 };
-static constexpr TileVariant kVariants[] = {{64, 1024}, {64, 256}, {32, 256}, {32, 512}, {16, 256}};
+static constexpr TileVariant kVariants[] = {{64, 1024}, {64, 256}, {32, 256}, {32, 512}, {16, 256},
+                                            {16, 512}, {32, 1024}, {16, 1024}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int taps_num_variants() { return kNumVariants; }
@@ -154,7 +166,10 @@ static void launch_stage1_t(int v, const float* f, const float* u, float2* qw, f
         case 1: stage1_inst<RAD, 64, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
         case 2: stage1_inst<RAD, 32, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
         case 3: stage1_inst<RAD, 32, 512>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
-        default: stage1_inst<RAD, 16, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 4: stage1_inst<RAD, 16, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 5: stage1_inst<RAD, 16, 512>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 6: stage1_inst<RAD, 32, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
+        default: stage1_inst<RAD, 16, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
     }
 }
 
@@ -169,7 +184,10 @@ static void launch_stage2_t(int v, const float2* qw, const float* u, float* un, 
         case 1: stage2_inst<RAD, (RAD >= 32 ? 32 : 64), 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
         case 2: stage2_inst<RAD, 32, 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
         case 3: stage2_inst<RAD, 32, 512>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        default: stage2_inst<RAD, 16, 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 4: stage2_inst<RAD, 16, 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 5: stage2_inst<RAD, 16, 512>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 6: stage2_inst<RAD, 32, 1024>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        default: stage2_inst<RAD, 16, 1024>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
     }
 }
 
@@ -186,7 +204,7 @@ static int default_variant(int H, int W, int stage)
 size_t tap_list_bytes(const PsfDev& psf)
 {
     const size_t P = (size_t)psf.ph * psf.pw;
-    return tap_groups_offset(psf.ph, psf.pw) + sizeof(TapGroup) * (P + 3);
+    return tap_groups_offset(psf.ph, psf.pw) + sizeof(TapGroup) * P;
 }
 
 void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st)

@@ -39,54 +39,66 @@ DEBLUR_DEV void group_fma_b(const float2* __restrict__ p, const float* w, float 
         }
 }
 
-// Sum over all column groups, in list order (column-major, dy ascending
-// within a column): the order is the same for every tile shape, so the
-// result of a pixel does not depend on the tiling.  The descriptor of the
-// next group is fetched while the current one is processed.
-template <int R, int LW>
-DEBLUR_DEV void blur_groups(const float* __restrict__ base, const TapGroup* __restrict__ grp, int ng,
-                            float (&acc)[R])
+// Sum over all column groups in list order (by run length, longest first,
+// then column-major): the order is the same for every tile shape, so the
+// result of a pixel does not depend on the tiling.  hdr[1 + S] = number of
+// groups of length S.  Each length has its own loop (no per-group dispatch);
+// the descriptor of the next group is fetched while the current one is
+// processed.
+template <int S, int R, int LW>
+DEBLUR_DEV const TapGroup* blur_class(const float* __restrict__ base, const TapGroup* __restrict__ g, int n,
+                                      float (&acc)[R])
 {
-    TapGroup cur = grp[0];
-    for (int g = 0; g < ng; ++g) {
-        const TapGroup nxt = grp[g + 1 < ng ? g + 1 : g];
-        const float* p = base - (cur.dy0 + cur.S - 1) * LW - cur.dx;
-        switch (cur.S) {
-            case 1: group_fma_a<R, 1, LW>(p, cur.w, acc); break;
-            case 2: group_fma_a<R, 2, LW>(p, cur.w, acc); break;
-            case 3: group_fma_a<R, 3, LW>(p, cur.w, acc); break;
-            case 4: group_fma_a<R, 4, LW>(p, cur.w, acc); break;
-            case 5: group_fma_a<R, 5, LW>(p, cur.w, acc); break;
-            case 6: group_fma_a<R, 6, LW>(p, cur.w, acc); break;
-            case 7: group_fma_a<R, 7, LW>(p, cur.w, acc); break;
-            case 8: group_fma_a<R, 8, LW>(p, cur.w, acc); break;
-            default: break;
-        }
+    if (n <= 0) return g;
+    TapGroup cur = g[0];
+    for (int k = 0; k < n; ++k) {
+        const TapGroup nxt = g[k + 1 < n ? k + 1 : k];
+        group_fma_a<R, S, LW>(base - (cur.dy0 + S - 1) * LW - cur.dx, cur.w, acc);
         cur = nxt;
     }
+    return g + n;
+}
+
+template <int S, int R, int LW>
+DEBLUR_DEV const TapGroup* corr_class(const float2* __restrict__ base, const TapGroup* __restrict__ g, int n,
+                                      float (&n1)[R], float (&n2)[R])
+{
+    if (n <= 0) return g;
+    TapGroup cur = g[0];
+    for (int k = 0; k < n; ++k) {
+        const TapGroup nxt = g[k + 1 < n ? k + 1 : k];
+        group_fma_b<R, S, LW>(base + cur.dy0 * LW + cur.dx, cur.w, n1, n2);
+        cur = nxt;
+    }
+    return g + n;
 }
 
 template <int R, int LW>
-DEBLUR_DEV void corr_groups(const float2* __restrict__ base, const TapGroup* __restrict__ grp, int ng,
-                            float (&n1)[R], float (&n2)[R])
+DEBLUR_DEV void blur_groups(const float* __restrict__ base, const TapGroup* __restrict__ g,
+                            const int* __restrict__ hdr, float (&acc)[R])
 {
-    TapGroup cur = grp[0];
-    for (int g = 0; g < ng; ++g) {
-        const TapGroup nxt = grp[g + 1 < ng ? g + 1 : g];
-        const float2* p = base + cur.dy0 * LW + cur.dx;
-        switch (cur.S) {
-            case 1: group_fma_b<R, 1, LW>(p, cur.w, n1, n2); break;
-            case 2: group_fma_b<R, 2, LW>(p, cur.w, n1, n2); break;
-            case 3: group_fma_b<R, 3, LW>(p, cur.w, n1, n2); break;
-            case 4: group_fma_b<R, 4, LW>(p, cur.w, n1, n2); break;
-            case 5: group_fma_b<R, 5, LW>(p, cur.w, n1, n2); break;
-            case 6: group_fma_b<R, 6, LW>(p, cur.w, n1, n2); break;
-            case 7: group_fma_b<R, 7, LW>(p, cur.w, n1, n2); break;
-            case 8: group_fma_b<R, 8, LW>(p, cur.w, n1, n2); break;
-            default: break;
-        }
-        cur = nxt;
-    }
+    g = blur_class<8, R, LW>(base, g, hdr[9], acc);
+    g = blur_class<7, R, LW>(base, g, hdr[8], acc);
+    g = blur_class<6, R, LW>(base, g, hdr[7], acc);
+    g = blur_class<5, R, LW>(base, g, hdr[6], acc);
+    g = blur_class<4, R, LW>(base, g, hdr[5], acc);
+    g = blur_class<3, R, LW>(base, g, hdr[4], acc);
+    g = blur_class<2, R, LW>(base, g, hdr[3], acc);
+    blur_class<1, R, LW>(base, g, hdr[2], acc);
+}
+
+template <int R, int LW>
+DEBLUR_DEV void corr_groups(const float2* __restrict__ base, const TapGroup* __restrict__ g,
+                            const int* __restrict__ hdr, float (&n1)[R], float (&n2)[R])
+{
+    g = corr_class<8, R, LW>(base, g, hdr[9], n1, n2);
+    g = corr_class<7, R, LW>(base, g, hdr[8], n1, n2);
+    g = corr_class<6, R, LW>(base, g, hdr[7], n1, n2);
+    g = corr_class<5, R, LW>(base, g, hdr[6], n1, n2);
+    g = corr_class<4, R, LW>(base, g, hdr[5], n1, n2);
+    g = corr_class<3, R, LW>(base, g, hdr[4], n1, n2);
+    g = corr_class<2, R, LW>(base, g, hdr[3], n1, n2);
+    corr_class<1, R, LW>(base, g, hdr[2], n1, n2);
 }
 
 template <int RAD, int TH>
@@ -97,25 +109,49 @@ constexpr int stage1_lds_floats() { return (TH + 2 * RAD) * (64 + 2 * RAD); }
 template <int RAD, int TH, int NT>
 DEBLUR_DEV void stage1_tile(float* __restrict__ tile, const float* __restrict__ u, const float* __restrict__ f,
                             float2* __restrict__ qw, float* __restrict__ s_out, int H, int W, int pitch, int x0,
-                            int y0, const TapGroup* __restrict__ grp, int ng, const IterParams& p)
+                            int y0, const TapGroup* __restrict__ grp, const int* __restrict__ hdr, const IterParams& p)
 {
     // With s_out (the backward recompute) the pair written is (e, W) with
     // e = q - W = W (f - s) / s, formed without cancellation, instead of (q, W).
     constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (NT / 64);
     static_assert(R >= 1 && TH % (NT / 64) == 0, "rows per thread");
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < LH * LW; idx += NT) {
-        const int ly = idx / LW, lx = idx - ly * LW;
-        const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
-        tile[idx] = u[(size_t)gy * pitch + gx];
+    const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
+    if (inner && pitch % 4 == 0 && ((uintptr_t)u & 15) == 0) {
+        // rows start at x0 - RAD, a multiple of 4: 16-byte loads
+        copy_rows_f4<NT, LH, LW>(tile, u + (size_t)(y0 - RAD) * pitch + (x0 - RAD), pitch);
+    } else if (inner) {
+        const float* src = u + (size_t)(y0 - RAD) * pitch + (x0 - RAD);
+        stage_to_lds<NT, LH * LW>(tile, [&](int idx) {
+            const int ly = idx / LW;
+            return src[(size_t)ly * pitch + (idx - ly * LW)];
+        });
+    } else if (p.bc == BC_REPLICATE) {
+        stage_to_lds<NT, LH * LW>(tile, [&](int idx) {
+            const int ly = idx / LW, lx = idx - ly * LW;
+            return u[(size_t)clampi(y0 - RAD + ly, H) * pitch + clampi(x0 - RAD + lx, W)];
+        });
+    } else {
+        stage_to_lds<NT, LH * LW>(tile, [&](int idx) {
+            const int ly = idx / LW, lx = idx - ly * LW;
+            const int gy = ext_index(y0 - RAD + ly, H, BC_PERIODIC), gx = ext_index(x0 - RAD + lx, W, BC_PERIODIC);
+            return u[(size_t)gy * pitch + gx];
+        });
     }
     __syncthreads();
     const int tx = tid & 63, ty = tid >> 6;
+    const int x = x0 + tx;
+    // f of the thread's pixels, fetched now so the loads overlap the sums
+    float fr[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int y = y0 + ty * R + i;
+        fr[i] = (x < W && y < H) ? f[(size_t)y * pitch + x] : 0.0f;
+    }
     float acc[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) acc[i] = 0.0f;
-    blur_groups<R, LW>(tile + (ty * R + RAD) * LW + tx + RAD, grp, ng, acc);   // A: E(u)(x - d)
-    const int x = x0 + tx;
+    blur_groups<R, LW>(tile + (ty * R + RAD) * LW + tx + RAD, grp, hdr, acc);   // A: E(u)(x - d)
     if (x >= W) return;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -123,10 +159,10 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, const float* __restrict__ 
         if (y >= H) break;
         if (s_out) s_out[(size_t)y * W + x] = acc[i];   // unclamped A u (backward pass)
         const float s = fmaxf(acc[i], p.s_min);
-        const float fv = f[(size_t)y * pitch + x];
+        const float fv = fr[i];
         const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
         const float fp = fmaxf(fv, 0.0f);
-        const float q = s_out ? wt * (fp - s) / s : wt * fp / s;
+        const float q = (s_out ? wt * (fp - s) : wt * fp) * rcp(s);
         qw[(size_t)y * W + x] = make_float2(q, wt);
     }
 }
@@ -138,7 +174,7 @@ __global__ void __launch_bounds__(NT) rrrl_taps_stage1(const float* __restrict__
                                                        const int* __restrict__ hdr, IterParams p)
 {
     __shared__ float tile[stage1_lds_floats<RAD, TH>()];
-    stage1_tile<RAD, TH, NT>(tile, u, f, qw, s_out, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, grp, hdr[1], p);
+    stage1_tile<RAD, TH, NT>(tile, u, f, qw, s_out, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, grp, hdr, p);
 }
 
 template <int RAD, int TH>
@@ -152,7 +188,7 @@ struct Stage2Smem {
 template <int RAD, int TH, int NT>
 DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ qw, const float* __restrict__ u,
                             float* __restrict__ u_next, float* __restrict__ ckpt, int H, int W, int pitch, int x0,
-                            int y0, const TapGroup* __restrict__ grp, int ng, const IterParams& p)
+                            int y0, const TapGroup* __restrict__ grp, const int* __restrict__ hdr, const IterParams& p)
 {
     constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (NT / 64);
     static_assert(R >= 1 && TH % (NT / 64) == 0, "rows per thread");
@@ -161,15 +197,34 @@ DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ 
     float* __restrict__ ut = sm.ut;
     float* __restrict__ gt = sm.gt;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < LH * LW; idx += NT) {
-        const int ly = idx / LW, lx = idx - ly * LW;
-        const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
-        qt[idx] = qw[(size_t)gy * W + gx];
+    const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
+    if (inner && W % 2 == 0 && ((uintptr_t)qw & 15) == 0) {
+        // (q, W) pairs from an even column: 16-byte loads of two pairs
+        copy_rows_f4<NT, LH, 2 * LW>(reinterpret_cast<float*>(qt),
+                                     reinterpret_cast<const float*>(qw + (size_t)(y0 - RAD) * W + (x0 - RAD)),
+                                     2 * (size_t)W);
+    } else if (inner) {
+        const float2* src = qw + (size_t)(y0 - RAD) * W + (x0 - RAD);
+        stage_to_lds<NT, LH * LW>(qt, [&](int idx) {
+            const int ly = idx / LW;
+            return src[(size_t)ly * W + (idx - ly * LW)];
+        });
+    } else if (p.bc == BC_REPLICATE) {
+        stage_to_lds<NT, LH * LW>(qt, [&](int idx) {
+            const int ly = idx / LW, lx = idx - ly * LW;
+            return qw[(size_t)clampi(y0 - RAD + ly, H) * W + clampi(x0 - RAD + lx, W)];
+        });
+    } else {
+        stage_to_lds<NT, LH * LW>(qt, [&](int idx) {
+            const int ly = idx / LW, lx = idx - ly * LW;
+            const int gy = ext_index(y0 - RAD + ly, H, BC_PERIODIC), gx = ext_index(x0 - RAD + lx, W, BC_PERIODIC);
+            return qw[(size_t)gy * W + gx];
+        });
     }
-    for (int idx = tid; idx < UH * UW; idx += NT) {
+    stage_to_lds<NT, UH * UW>(ut, [&](int idx) {
         const int ly = idx / UW, lx = idx - ly * UW;
-        ut[idx] = u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
-    }
+        return u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
+    });
     __syncthreads();
     // diffusivity g = Psi'(|grad u|^2) by central differences at pixels
     for (int idx = tid; idx < GH * GW; idx += NT) {
@@ -182,7 +237,7 @@ DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ 
     float n1[R], n2[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) n1[i] = n2[i] = 0.0f;
-    corr_groups<R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, grp, ng, n1, n2);   // B: E(q, W)(x + d)
+    corr_groups<R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, grp, hdr, n1, n2);   // B: E(q, W)(x + d)
     __syncthreads();   // gt complete
     const int x = x0 + tx;
     if (x >= W) return;
@@ -203,7 +258,7 @@ DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ 
         const float den = n2[i] - p.alpha * fminf(D, 0.0f);
         const size_t o = (size_t)y * pitch + x;
         if (ckpt) ckpt[o] = up;
-        u_next[o] = up * num / den;
+        u_next[o] = up * num * rcp(den);
     }
 }
 
@@ -214,8 +269,7 @@ __global__ void __launch_bounds__(NT) rrrl_taps_stage2(const float2* __restrict_
                                                        const int* __restrict__ hdr, IterParams p)
 {
     __shared__ Stage2Smem<RAD, TH> sm;
-    stage2_tile<RAD, TH, NT>(sm, qw, u, u_next, ckpt, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, grp, hdr[1],
-                             p);
+    stage2_tile<RAD, TH, NT>(sm, qw, u, u_next, ckpt, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, grp, hdr, p);
 }
 
 }  // namespace deblur

@@ -76,13 +76,13 @@ __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict
     fft_twiddles(tw, W);
 
     const int pair0 = blockIdx.x * nb;
-    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+    stage_to_lds_n<8>(a, nb * W, [&](int idx) {
         const int t = idx / W, x = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
         const float va = ya < H ? f[(size_t)ya * pitch + x] : 0.0f;
         const float vb = yb < H ? f[(size_t)yb * pitch + x] : 0.0f;
-        a[idx] = make_float2(va, vb);
-    }
+        return make_float2(va, vb);
+    });
     __syncthreads();
     float2* X = fft_rows(a, b, nb, plan, tw);
     float2* Y = X == a ? b : a;
@@ -157,13 +157,13 @@ __global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__
     float2* b = a + nb * W;
     fft_twiddles(tw, W);
     const int pair0 = blockIdx.x * nb;
-    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+    stage_to_lds_n<8>(a, nb * W, [&](int idx) {
         const int t = idx / W, x = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
         const float va = ya < H ? f[(size_t)ya * pitch + x] : 0.0f;
         const float vb = yb < H ? f[(size_t)yb * pitch + x] : 0.0f;
-        a[idx] = make_float2(va, vb);
-    }
+        return make_float2(va, vb);
+    });
     __syncthreads();
     const float2* Z = fft_rows(a, b, nb, plan, tw);
     const int Wh = W / 2 + 1;
@@ -191,10 +191,18 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
     fft_twiddles(tw, H);
     const int Wh = W / 2 + 1;
     const int c0 = xcd_group(blockIdx.x, gridDim.x) * cb;
-    for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
-        const int y = idx / cb, c = idx - y * cb;
-        float2 v = (c0 + c < Wh) ? S[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
-        a[c * H + y] = mode == 2 ? cconj(v) : v;
+    for (int base = threadIdx.x; base < cb * H; base += 8 * blockDim.x) {
+        float2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int idx = base + k * blockDim.x, y = idx / cb, c = idx - y * cb;
+            v[k] = (idx < cb * H && c0 + c < Wh) ? S[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int idx = base + k * blockDim.x, y = idx / cb, c = idx - y * cb;
+            if (idx < cb * H) a[c * H + y] = mode == 2 ? cconj(v[k]) : v[k];
+        }
     }
     __syncthreads();
     float2* X = fft_rows(a, b, cb, plan, tw);
@@ -244,7 +252,7 @@ __global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict_
     fft_twiddles(tw, W);
     const int Wh = W / 2 + 1;
     const int pair0 = blockIdx.x * nb;
-    for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+    stage_to_lds_n<8>(a, nb * W, [&](int idx) {
         const int t = idx / W, k = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
         const bool lo = k < Wh;
@@ -256,8 +264,8 @@ __global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict_
             ub = cconj(ub);
         }
         // conj(U_a + i U_b) for the inverse via the forward transform
-        a[idx] = make_float2(ua.x - ub.y, -(ua.y + ub.x));
-    }
+        return make_float2(ua.x - ub.y, -(ua.y + ub.x));
+    });
     __syncthreads();
     const float2* Z = fft_rows(a, b, nb, plan, tw);
     const float inv = 1.0f / (float)W;
