@@ -64,6 +64,8 @@ def parse_args():
     ap.add_argument("--latency-group", type=int, default=64,
                     help="group size of the latency plan (images run group after group)")
     ap.add_argument("--cpu-iters", type=int, default=20, help="RRRL iterations in the oracle sample")
+    ap.add_argument("--tile", default="auto",
+                    help="stencil tile shape: 'auto' (autotuner, not cached), 0 (library default) or 1..n")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     ap.add_argument("--ingest-pmc", metavar="DIR", help="parse rocprofv3 --pmc databases and exit")
@@ -226,7 +228,14 @@ def main():
     iters = case.iters
     f = torch.from_numpy(case.f).to(dev)
     psf = dbl.Psf.from_taps(torch.from_numpy(case.psf).to(dev))
-    params = dbl.Params(alpha=case.alpha, iters=iters)
+    tune = None
+    if args.tile == "auto":
+        from paper_1212_2245_amd import autotune
+        tune = autotune.tune(f, psf, dbl.Params(alpha=case.alpha, iters=iters), store=False)
+        tile = int(tune["tile"])
+    else:
+        tile = int(args.tile)
+    params = dbl.Params(alpha=case.alpha, iters=iters, tile=tile)
     u = torch.empty_like(f)
     ws_w = torch.empty(dbl.deblur_workspace_bytes(0, H, W, W, psf), dtype=torch.uint8, device=dev)
     ws_i = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, psf, params), dtype=torch.uint8, device=dev)
@@ -265,7 +274,7 @@ def main():
     taps = dbl.deblur_compile_taps(psf)
     qw = torch.empty((H, W, 2), dtype=torch.float32, device=dev)
     u2 = torch.empty_like(u)
-    p1 = dbl.Params(alpha=case.alpha, iters=1)
+    p1 = dbl.Params(alpha=case.alpha, iters=1, tile=tile)
     dbl.deblur_rrrl_weights(f, u, qw, psf, taps, p1)
     dbl.deblur_rrrl_update(qw, u, u2, psf, taps, p1)
     torch.cuda.synchronize()
@@ -300,7 +309,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "oblique line blur L=31 (31x31 bilinear PSF), 1024x1024, Wiener K=0.01 + "
                                "20 RRRL iterations alpha=0.002, robust, TV, replicate border",
-                   "H": H, "W": W, "iters": iters, "psf_theta_rad": round(case.meta["theta"], 6)},
+                   "H": H, "W": W, "iters": iters, "psf_theta_rad": round(case.meta["theta"], 6),
+                   "tile": tile, "tile_timings_us": ({str(k): round(v, 2) for k, v in tune["timings_us"].items()}
+                                                     if tune else None)},
         "roofline": roofline,
         "hbm": {"algorithmic_bytes_per_step": alg_bytes, "achieved_GBs": round(hbm_gbs, 2),
                 "peak_GBs": HBM_PEAK_GBS, "frac": round(hbm_gbs / HBM_PEAK_GBS, 5)},

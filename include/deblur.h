@@ -201,10 +201,22 @@ void deblur_batch_plan_destroy(deblur_batch_plan* plan);
 /* Bytes of the compiled tap list of a PSF (0 for an invalid descriptor). */
 size_t deblur_taps_bytes(const deblur_psf* psf);
 
-/* Compiles the PSF into the list of its non-zero taps (offsets d and
- * weights h(d), row-major order) in the device buffer `taps_out` of at least
- * deblur_taps_bytes(psf) bytes, 256-byte aligned.  The list is read by the
- * two stage entry points below and stays valid while the PSF is unchanged. */
+/* Compiles the PSF (eq. (1)) in the device buffer `taps_out` of at least
+ * deblur_taps_bytes(psf) bytes, 256-byte aligned.  The result is read by the
+ * two stage entry points below and stays valid while the PSF is unchanged.
+ * Layout (little-endian, P = ph*pw of the PSF array, cy = (ph-1)/2,
+ * cx = (pw-1)/2):
+ *   int32 [0]        number of non-zero taps T
+ *   int32 [1]        number of column groups G
+ *   int32 [1 + S]    number of column groups of length S, S = 1..8
+ *   bytes 256 ..     T records {int32 dy, int32 dx, float32 h, int32 0},
+ *                    the non-zero taps in row-major order
+ *   bytes 256+16P .. G records of 48 bytes {int32 dx, int32 dy0, int32 S,
+ *                    int32 0, float32 w[8]}: taps (dy0 + s, dx) with weights
+ *                    w[s], s < S, a run of vertically adjacent non-zero taps
+ *                    of one PSF column (runs longer than 8 are split);
+ *                    ordered by S descending, then dx, then dy0.
+ * The stencil kernels sum the taps of a pixel in the group order. */
 int deblur_compile_taps(const deblur_psf* psf, void* taps_out, size_t taps_bytes, void* stream);
 
 /* Stage 1 of eq. (9): s = max(A u, s_min) (blur with h, eq. (1)), robust

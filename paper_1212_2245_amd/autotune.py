@@ -2,7 +2,8 @@
 
 The stencil stages run on 64-column tiles whose height and workgroup size
 are selectable (deblur_params.tile, 1..deblur_tile_variants(); 0 = the
-library's default for the image size).  Every shape sums the taps of a pixel
+library's default for the image size, which may differ between the two
+stages; it is timed as a candidate too).  Every shape sums the taps of a pixel
 in the same order, so all give bitwise-identical results; only speed differs.
 `tune` times every shape on the caller's problem with HIP events, checks the
 outputs are identical, and records the fastest in a JSON cache keyed by GPU
@@ -103,7 +104,7 @@ def tune(f, psf, params, iters: int = 3, reps: int = 5, path: str | None = None,
     ref = None
     timings = {}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for v in range(1, lib.deblur_tile_variants() + 1):
+    for v in range(0, lib.deblur_tile_variants() + 1):   # 0: the library's per-stage default
         p = dataclasses.replace(params, iters=iters, tile=v, conv=2)  # stencil path
         out = torch.empty_like(f)
         deblur_rrrl_iterate(f, u0, out, psf, p)

@@ -27,6 +27,7 @@ struct TapGroup {
     int dx, dy0, S, pad;  // taps (dy0 + s, dx), s < S; S = 0 pads the list
     float w[8];
 };
+static_assert(sizeof(TapGroup) == 48, "three 16-byte words per group");
 constexpr int TAP_GROUP_MAX = 8;
 inline size_t tap_groups_offset(int ph, int pw) { return 256 + 16 * (size_t)ph * pw; }
 

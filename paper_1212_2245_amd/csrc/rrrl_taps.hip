@@ -20,6 +20,32 @@
 
 namespace deblur {
 
+// Inclusive prefix sums over the 256 threads of a workgroup of N values per
+// thread (wavefront shuffles, one barrier round through `tot`).
+template <int N>
+DEBLUR_DEV void block_scan256(int (&v)[N], int (*tot)[N])
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const int o = __shfl_up(v[q], d, 64);
+            if (lane >= d) v[q] += o;
+        }
+    }
+    __syncthreads();
+    if (lane == 63) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) tot[wv][q] = v[q];
+    }
+    __syncthreads();
+    for (int w = 0; w < wv; ++w) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) v[q] += tot[w][q];
+    }
+}
+
 // Compacted list of the non-zero taps, row-major order: {dy, dx, w bits, 0},
 // count in hdr[0].  Then the column groups: runs of vertically adjacent
 // non-zero taps of one PSF column, split every TAP_GROUP_MAX rows, ordered by
@@ -29,93 +55,110 @@ namespace deblur {
 __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restrict__ list,
                                                       TapGroup* __restrict__ groups, int* __restrict__ hdr)
 {
-    __shared__ int counts[256];
-    __shared__ int cls[TAP_GROUP_MAX][256];   // groups of length S+1 in column i, then their offsets
+    __shared__ int tot1[4][1], tot8[4][TAP_GROUP_MAX];
     __shared__ int cls_base[TAP_GROUP_MAX];
+    __shared__ float hs[65 * 65];             // the PSF array (ph, pw <= 65)
+    __shared__ unsigned long long mask0[65];  // per column: non-zero rows 0..63
+    __shared__ int mask1[65];                 // per column: row 64 non-zero
     const int n = psf.ph * psf.pw;
+    stage_to_lds_n<8>(hs, n, [&](int t) { return psf_weight(psf, t / psf.pw, t % psf.pw); });
+    __syncthreads();
+    auto wgt = [&](int j, int i) { return hs[j * psf.pw + i]; };
     const int per = (n + 255) / 256;
     const int b = threadIdx.x * per, e = min(n, b + per);
-    int c = 0;
-    for (int k = b; k < e; ++k) c += psf_weight(psf, k / psf.pw, k % psf.pw) != 0.0f;
-    counts[threadIdx.x] = c;
-    __syncthreads();
-    // inclusive Hillis-Steele scan
-    for (int off = 1; off < 256; off <<= 1) {
-        const int v = threadIdx.x >= off ? counts[threadIdx.x - off] : 0;
-        __syncthreads();
-        counts[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int o = counts[threadIdx.x] - c;
+    int c[1] = {0};
+    for (int k = b; k < e; ++k) c[0] += hs[k] != 0.0f;
+    const int mine = c[0];
+    block_scan256<1>(c, tot1);
+    int o = c[0] - mine;
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
     for (int k = b; k < e; ++k) {
         const int j = k / psf.pw, i = k % psf.pw;
-        const float w = psf_weight(psf, j, i);
+        const float w = hs[k];
         if (w != 0.0f) list[o++] = make_int4(j - cy, i - cx, __float_as_int(w), 0);
     }
-    if (threadIdx.x == 255) hdr[0] = counts[255];
+    if (threadIdx.x == 255) hdr[0] = c[0];
 
-    // column groups: thread `col` walks PSF column col; a run of r adjacent
-    // non-zero taps gives floor(r/8) groups of 8 and one of r mod 8
-    const int col = threadIdx.x;
-    for (int q = 0; q < TAP_GROUP_MAX; ++q) cls[q][col] = 0;
-    if (col < psf.pw) {
-        int run = 0;
-        for (int j = 0; j <= psf.ph; ++j) {
-            const bool nz = j < psf.ph && psf_weight(psf, j, col) != 0.0f;
-            if (nz && run < TAP_GROUP_MAX) {
-                ++run;
+    // column groups.  The non-zero pattern of each PSF column as a 65-bit mask
+    // (rows 0..63 by one wavefront ballot, row 64 separately); thread `col`
+    // (< pw) then visits the runs of its column: a run of r adjacent non-zero
+    // taps gives floor(r/8) groups of 8 and one of r mod 8.
+    const int col = threadIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = wv; i < psf.pw; i += 4) {
+        const unsigned long long m = __ballot(lane < psf.ph && wgt(lane, i) != 0.0f);
+        if (lane == 0) {
+            mask0[i] = m;
+            mask1[i] = psf.ph > 64 && wgt(64, i) != 0.0f;
+        }
+    }
+    __syncthreads();
+    const unsigned long long m0 = col < psf.pw ? mask0[col] : 0ull;
+    const bool b64 = col < psf.pw && mask1[col] != 0;
+    // calls fn(start, length) for every maximal run of set bits of (m0, b64)
+    auto for_runs = [&](auto fn) {
+        int j = 0;
+        while (j <= 64) {
+            if (j == 64) {
+                if (b64) fn(64, 1);
+                break;
+            }
+            const unsigned long long rest = m0 >> j;
+            if (rest == 0ull) {
+                j = 64;
                 continue;
             }
-            if (run > 0) ++cls[run - 1][col];
-            run = nz ? 1 : 0;
+            const int start = j + __builtin_ctzll(rest);
+            const unsigned long long inv = ~(m0 >> start);
+            int len = inv == 0ull ? 64 - start : __builtin_ctzll(inv);
+            if (len > 64 - start) len = 64 - start;
+            if (start + len == 64 && b64) ++len;
+            fn(start, len);
+            j = start + len + 1;
         }
-    }
-    __syncthreads();
-    // exclusive prefix over the columns, one length class per thread
-    if (threadIdx.x < TAP_GROUP_MAX) {
-        int acc = 0;
-        for (int i = 0; i < psf.pw; ++i) {
-            const int v = cls[threadIdx.x][i];
-            cls[threadIdx.x][i] = acc;
-            acc += v;
-        }
-        counts[threadIdx.x] = acc;   // total of the class
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    };
+    int my[TAP_GROUP_MAX];
+#pragma unroll
+    for (int q = 0; q < TAP_GROUP_MAX; ++q) my[q] = 0;
+    for_runs([&](int, int len) {
+        my[TAP_GROUP_MAX - 1] += len / TAP_GROUP_MAX;
+        const int r = len % TAP_GROUP_MAX;
+#pragma unroll
+        for (int q = 0; q < TAP_GROUP_MAX - 1; ++q) my[q] += r == q + 1;
+    });
+    // inclusive scan over the columns of the eight per-length counts
+    int sc[TAP_GROUP_MAX];
+#pragma unroll
+    for (int q = 0; q < TAP_GROUP_MAX; ++q) sc[q] = my[q];
+    block_scan256<TAP_GROUP_MAX>(sc, tot8);
+    if (threadIdx.x == 255) {
         int base = 0;
         for (int q = TAP_GROUP_MAX - 1; q >= 0; --q) {
             cls_base[q] = base;
-            base += counts[q];
-            hdr[2 + q] = counts[q];
+            base += sc[q];
+            hdr[2 + q] = sc[q];
         }
         hdr[1] = base;
     }
     __syncthreads();
-    if (col < psf.pw) {
-        int next[TAP_GROUP_MAX];
-        for (int q = 0; q < TAP_GROUP_MAX; ++q) next[q] = cls_base[q] + cls[q][col];
-        int run = 0, j0 = 0;
-        for (int j = 0; j <= psf.ph; ++j) {
-            const bool nz = j < psf.ph && psf_weight(psf, j, col) != 0.0f;
-            if (nz && run < TAP_GROUP_MAX) {
-                if (run == 0) j0 = j;
-                ++run;
-                continue;
-            }
-            if (run > 0) {
-                TapGroup& g = groups[next[run - 1]++];
-                g.dx = col - cx;
-                g.dy0 = j0 - cy;
-                g.S = run;
-                g.pad = 0;
-                for (int s = 0; s < TAP_GROUP_MAX; ++s) g.w[s] = s < run ? psf_weight(psf, j0 + s, col) : 0.0f;
-            }
-            run = nz ? 1 : 0;
-            j0 = j;
-        }
-    }
+    int next[TAP_GROUP_MAX];
+#pragma unroll
+    for (int q = 0; q < TAP_GROUP_MAX; ++q) next[q] = cls_base[q] + sc[q] - my[q];
+    auto emit = [&](int j0, int run) {
+        int slot = 0;
+#pragma unroll
+        for (int q = 0; q < TAP_GROUP_MAX; ++q)
+            if (run == q + 1) slot = next[q]++;
+        float w[TAP_GROUP_MAX];
+#pragma unroll
+        for (int t = 0; t < TAP_GROUP_MAX; ++t) w[t] = t < run ? wgt(j0 + t, col) : 0.0f;
+        int4* g4 = reinterpret_cast<int4*>(groups + slot);
+        g4[0] = make_int4(col - cx, j0 - cy, run, 0);
+        g4[1] = make_int4(__float_as_int(w[0]), __float_as_int(w[1]), __float_as_int(w[2]), __float_as_int(w[3]));
+        g4[2] = make_int4(__float_as_int(w[4]), __float_as_int(w[5]), __float_as_int(w[6]), __float_as_int(w[7]));
+    };
+    for_runs([&](int start, int len) {
+        for (int k = 0; k < len; k += TAP_GROUP_MAX) emit(start + k, min(TAP_GROUP_MAX, len - k));
+    });
 }
 
 // ------------------------------------------------------------ host launchers
@@ -191,8 +234,10 @@ static void launch_stage2_t(int v, const float2* qw, const float* u, float* un, 
     }
 }
 
-// Default variant when the caller does not choose one: enough tiles to give
-// every CU several workgroups, else the smallest tiles.
+// Default variant when the caller does not choose one (measured on MI355X
+// with a 71-tap line PSF; indices into kVariants): 64-row tiles of 1024
+// threads for stage 1 and 32-row tiles of 512 threads for stage 2 at about
+// 1 Mpx; smaller images use 16-row tiles.
 static int default_variant(int H, int W, int stage)
 {
     const long tiles64 = (long)((W + 63) / 64) * ((H + 63) / 64);

@@ -116,6 +116,16 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, const float* __restrict__ 
     constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (NT / 64);
     static_assert(R >= 1 && TH % (NT / 64) == 0, "rows per thread");
     const int tid = threadIdx.x;
+    const int tx = tid & 63, ty = tid >> 6;
+    const int x = x0 + tx;
+    // f of the thread's pixels, fetched first so these loads are in flight
+    // together with the tile's
+    float fr[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int y = y0 + ty * R + i;
+        fr[i] = (x < W && y < H) ? f[(size_t)y * pitch + x] : 0.0f;
+    }
     const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
     if (inner && pitch % 4 == 0 && ((uintptr_t)u & 15) == 0) {
         // rows start at x0 - RAD, a multiple of 4: 16-byte loads
@@ -139,15 +149,6 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, const float* __restrict__ 
         });
     }
     __syncthreads();
-    const int tx = tid & 63, ty = tid >> 6;
-    const int x = x0 + tx;
-    // f of the thread's pixels, fetched now so the loads overlap the sums
-    float fr[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const int y = y0 + ty * R + i;
-        fr[i] = (x < W && y < H) ? f[(size_t)y * pitch + x] : 0.0f;
-    }
     float acc[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) acc[i] = 0.0f;

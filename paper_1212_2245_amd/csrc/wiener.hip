@@ -22,7 +22,7 @@
 namespace deblur {
 
 // exp(-2 pi i m / n) for an integer m reduced mod n (exact reduction, FP64).
-DEBLUR_DEV double2 unit_root(long long m, int n)
+DEBLUR_DEV double2 unit_root(int m, int n)
 {
     m %= n;
     if (m < 0) m += n;
@@ -36,16 +36,23 @@ DEBLUR_DEV double2 zmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// sum_i h(j, i) exp(-2 pi i k (i - c) / n) over one PSF row j, the phase
-// advanced by the FP64 recurrence t <- t exp(-2 pi i k / n) (at most 65
-// steps: relative drift ~1e-14, far below the FP32 rounding of the result).
-DEBLUR_DEV double2 psf_row_dft(const PsfDev& psf, int j, int k, int n, int c)
+// The PSF array in LDS (ph*pw floats, at most 65 x 65), filled with batched
+// loads so the DFT loops below read no global memory.
+constexpr int MULT_MAXP = 65;
+DEBLUR_DEV void psf_to_lds(const PsfDev& psf, float* hs)
 {
-    const double2 w = unit_root(k, n);
-    double2 t = unit_root(-(long long)k * c, n);
+    stage_to_lds_n<8>(hs, psf.ph * psf.pw, [&](int t) { return psf_weight(psf, t / psf.pw, t % psf.pw); });
+}
+
+// sum_i h(j, i) exp(-2 pi i k (i - c) / n) over one PSF row j (hrow = h(j, .)),
+// given w = exp(-2 pi i k / n) and t0 = exp(2 pi i k c / n); the phase is
+// advanced by the FP64 recurrence t <- t w (at most 65 steps: relative drift
+// ~1e-14, far below the FP32 rounding of the result).
+DEBLUR_DEV double2 psf_row_dft(const float* hrow, int pw, double2 w, double2 t)
+{
     double re = 0.0, im = 0.0;
-    for (int i = 0; i < psf.pw; ++i) {
-        const double h = (double)psf_weight(psf, j, i);
+    for (int i = 0; i < pw; ++i) {
+        const double h = (double)hrow[i];
         re = fma(h, t.x, re);
         im = fma(h, t.y, im);
         t = zmul(t, w);
@@ -56,9 +63,12 @@ DEBLUR_DEV double2 psf_row_dft(const PsfDev& psf, int j, int k, int n, int c)
 // M(k) = conj(h^(k)) / (|h^(k)|^2 + K) for a PSF on one row, k < n.
 __global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double K, float2* __restrict__ M)
 {
+    __shared__ float hs[MULT_MAXP];
+    psf_to_lds(psf, hs);
+    __syncthreads();
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const double2 hk = psf_row_dft(psf, 0, k, n, (psf.pw - 1) / 2);
+    const double2 hk = psf_row_dft(hs, psf.pw, unit_root(k, n), unit_root(-k * ((psf.pw - 1) / 2), n));
     const double den = hk.x * hk.x + hk.y * hk.y + K;
     M[k] = make_float2((float)(hk.x / den), (float)(-hk.y / den));
 }
@@ -109,29 +119,44 @@ __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict
 // transformed along x, G(j, kx) = sum_i h(j, i) e^{-2 pi i kx (i - cx)/W}
 // (LDS, FP64), then h^(ky, kx) = sum_j G(j, kx) e^{-2 pi i ky (j - cy)/H}.
 // Optionally also h^ itself (hh, complex64).
-constexpr int MULT_KX = 16, MULT_KY = 64, MULT_MAXP = 65;
+constexpr int MULT_KX = 16, MULT_KY = 64;
 __global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, double K, float2* __restrict__ M,
                                                       float2* __restrict__ hh)
 {
     __shared__ double2 G[MULT_MAXP * MULT_KX];
+    __shared__ float hs[MULT_MAXP * MULT_MAXP];
+    __shared__ double2 rot[2 * (MULT_KX + MULT_KY)];   // per kx, ky: exp(-2 pi i k/n), exp(2 pi i k c/n)
+    psf_to_lds(psf, hs);
     const int Wh = W / 2 + 1;
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
     const int kx0 = blockIdx.x * MULT_KX, ky0 = blockIdx.y * MULT_KY;
+    for (int t = threadIdx.x; t < 2 * (MULT_KX + MULT_KY); t += blockDim.x) {
+        const int q = t % (MULT_KX + MULT_KY), start = t >= MULT_KX + MULT_KY;
+        const bool isx = q < MULT_KX;
+        const int k = isx ? kx0 + q : ky0 + q - MULT_KX, n = isx ? W : H, c = isx ? cx : cy;
+        rot[t] = unit_root(start ? -k * c : k, n);
+    }
+    __syncthreads();
+    const double2* wx = rot;
+    const double2* wy = rot + MULT_KX;
+    const double2* tx0 = rot + MULT_KX + MULT_KY;
+    const double2* ty0 = tx0 + MULT_KX;
     for (int idx = threadIdx.x; idx < psf.ph * MULT_KX; idx += blockDim.x) {
-        const int j = idx / MULT_KX, kx = kx0 + idx % MULT_KX;
-        G[idx] = kx < Wh ? psf_row_dft(psf, j, kx, W, cx) : make_double2(0.0, 0.0);
+        const int j = idx / MULT_KX, q = idx % MULT_KX;
+        G[idx] = kx0 + q < Wh ? psf_row_dft(hs + j * psf.pw, psf.pw, wx[q], tx0[q]) : make_double2(0.0, 0.0);
     }
     __syncthreads();
     const int lx = threadIdx.x % MULT_KX, kx = kx0 + lx;
     if (kx >= Wh) return;
-    for (int ky = ky0 + threadIdx.x / MULT_KX; ky < min(ky0 + MULT_KY, H); ky += 256 / MULT_KX) {
-        const double2 w = unit_root(ky, H);
-        double2 t = unit_root(-(long long)ky * cy, H);
+    for (int q = threadIdx.x / MULT_KX; q < MULT_KY && ky0 + q < H; q += 256 / MULT_KX) {
+        const int ky = ky0 + q;
+        const double2 w = wy[q];
+        double2 t = ty0[q];
         double re = 0.0, im = 0.0;
         for (int j = 0; j < psf.ph; ++j) {
             const double2 g = G[j * MULT_KX + lx];
-            re += g.x * t.x - g.y * t.y;
-            im += g.x * t.y + g.y * t.x;
+            re = fma(g.x, t.x, fma(-g.y, t.y, re));
+            im = fma(g.x, t.y, fma(g.y, t.x, im));
             t = zmul(t, w);
         }
         const double den = re * re + im * im + K;

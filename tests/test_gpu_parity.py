@@ -361,6 +361,6 @@ def test_autotune_picks_a_valid_identical_shape(tmp_path, monkeypatch):
     psf = gpu_psf(c.kind, c.length, c.psf)
     res = autotune.tune(f, psf, dbl.Params(alpha=c.alpha), iters=2, reps=2)
     n = dbl._lib.load().deblur_tile_variants()
-    assert 1 <= res["tile"] <= n and len(res["timings_us"]) == n
+    assert 0 <= res["tile"] <= n and len(res["timings_us"]) == n + 1   # 0: the library default
     assert autotune.best_tile(512, 512, 31, 31) == res["tile"]
     print(f"[tune] {res['key']}: {res['timings_us']}", flush=True)
