@@ -59,6 +59,10 @@ def parse_args():
     ap.add_argument("--kernel-reps", type=int, default=50, help="launches per stage kernel for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 512-image measurement")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-configuration figures (256^2 box, 2048^2 Gaussian stencil/FFT, "
+                         "64 x 512^2 forward + backward)")
+    ap.add_argument("--grad-images", type=int, default=64, help="images of the differentiation workload")
     ap.add_argument("--batch-images", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--latency-group", type=int, default=64,
@@ -198,6 +202,126 @@ def bench_batched(dev, args):
                       "line": sum(c.kind == 2 for c in cases)}}
 
 
+# ------------------------------------------------------------ other configs
+def _events_ms(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_configs(dev, args):
+    """Per-configuration figures beside the headline: the 256^2 box workload
+    (Wiener + 10 iterations, parity vs the oracle), the 2048^2 Gaussian-mixture
+    workload (30 iterations; stencil with constant and periodic continuation,
+    FFT path periodic) and the differentiation workload (64 x 512^2 line PSF,
+    Wiener + 10 iterations with checkpoints, then the backward through both)."""
+    import numpy as np
+    import torch
+
+    import paper_1212_2245_amd as dbl
+    import synth
+    out = {}
+
+    # config 0: 256^2, horizontal box L=15
+    c = synth.make_case(0)
+    H, W = c.f.shape
+    f = torch.from_numpy(c.f).to(dev)
+    psf = dbl.Psf.box(c.length, "h")
+    p = dbl.Params(alpha=c.alpha, iters=c.iters)
+    u = torch.empty_like(f)
+    wsw = torch.empty(dbl.deblur_workspace_bytes(0, H, W, W, psf), dtype=torch.uint8, device=dev)
+    wsi = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, psf, p), dtype=torch.uint8, device=dev)
+
+    def solve0():
+        dbl.deblur_wiener(f, u, psf, c.K, 1.0, ws=wsw)
+        dbl.deblur_rrrl_iterate(f, u, u, psf, p, ws=wsi)
+    ms = _events_ms(solve0, 50)
+    msw = _events_ms(lambda: dbl.deblur_wiener(f, u, psf, c.K, 1.0, ws=wsw), 50)
+    solve0()
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    e = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        want = oracle.wr3l(c.f, c.psf, c.K, oracle.Params(alpha=c.alpha), c.iters, threads=1)
+        t_cpu = time.perf_counter() - t0
+        e = {"rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+             "max_abs": float(np.abs(got - want).max()), "oracle_ms_1core": round(t_cpu * 1e3, 2)}
+    it_us = (ms - msw) * 1e3 / c.iters
+    out["config0_box256"] = {"us_per_solve": round(ms * 1e3, 2), "wiener_us": round(msw * 1e3, 2),
+                             "iteration_us": round(it_us, 2),
+                             "mpx_it_per_s": round(H * W / it_us, 1),
+                             "hbm_frac": round((8 * H * W + 12 * H * W * c.iters) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                             "parity": e}
+
+    # config 2: 2048^2, 31x31 Gaussian mixture, 30 iterations
+    c = synth.make_case(2)
+    H, W = c.f.shape
+    f = torch.from_numpy(c.f).to(dev)
+    psf = dbl.Psf.from_taps(torch.from_numpy(c.psf).to(dev))
+    u0 = torch.empty_like(f)
+    wsw = torch.empty(dbl.deblur_workspace_bytes(0, H, W, W, psf), dtype=torch.uint8, device=dev)
+    msw = _events_ms(lambda: dbl.deblur_wiener(f, u0, psf, c.K, 1.0, ws=wsw), 5)
+    res = {"wiener_us": round(msw * 1e3, 1), "nonzero_taps": int(np.count_nonzero(c.psf))}
+    outs = {}
+    for name, bc, conv in (("stencil_replicate", dbl.BC_REPLICATE, dbl.CONV_STENCIL),
+                           ("stencil_periodic", dbl.BC_PERIODIC, dbl.CONV_STENCIL),
+                           ("fft_periodic", dbl.BC_PERIODIC, dbl.CONV_FFT)):
+        p = dbl.Params(alpha=c.alpha, iters=c.iters, boundary=bc, conv=conv)
+        ws = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, psf, p), dtype=torch.uint8, device=dev)
+        uo = torch.empty_like(f)
+        ms = _events_ms(lambda: dbl.deblur_rrrl_iterate(f, u0, uo, psf, p, ws=ws), 2)
+        outs[name] = uo.cpu().numpy()
+        it_us = ms * 1e3 / c.iters
+        res[name] = {"iteration_us": round(it_us, 1), "mpx_it_per_s": round(H * W / it_us, 1)}
+    a, b = outs["stencil_periodic"], outs["fft_periodic"]
+    res["fft_vs_stencil_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(a))
+    out["config2_gauss2048"] = res
+
+    # config 4: forward with checkpoints + backward through Wiener and iterations
+    cases = [synth.make_case(4, image=i) for i in range(args.grad_images)]
+    H, W = cases[0].f.shape
+    iters = cases[0].iters
+    data = []
+    for c in cases:
+        fd = torch.from_numpy(c.f).to(dev)
+        psf = dbl.Psf.from_taps(torch.from_numpy(c.psf).to(dev))
+        data.append((fd, psf, torch.from_numpy(c.g).to(dev), dbl.Params(alpha=c.alpha, iters=iters), c.K))
+    p0 = data[0][3]
+    wsw = torch.empty(dbl.deblur_workspace_bytes(0, H, W, W, data[0][1]), dtype=torch.uint8, device=dev)
+    wsi = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, data[0][1], p0), dtype=torch.uint8, device=dev)
+    wsb = torch.empty(dbl.deblur_workspace_bytes(3, H, W, W, data[0][1], p0), dtype=torch.uint8, device=dev)
+    ck = torch.empty((iters, H, W), dtype=torch.float32, device=dev)
+    u = torch.empty((H, W), dtype=torch.float32, device=dev)
+
+    def fwd(i):
+        fd, psf, g, p, K = data[i]
+        dbl.deblur_wiener(fd, u, psf, K, 1.0, ws=wsw)
+        dbl.deblur_rrrl_iterate(fd, u, u, psf, p, ckpt=ck, ws=wsi)
+
+    def fwd_bwd(i):
+        fwd(i)
+        fd, psf, g, p, K = data[i]
+        dbl.deblur_rrrl_backward(fd, ck, 2.0 * (u - g), psf, p, through_wiener=True, K=K, ws=wsb)
+
+    ms_f = _events_ms(lambda: [fwd(i) for i in range(len(data))], 2)
+    ms_fb = _events_ms(lambda: [fwd_bwd(i) for i in range(len(data))], 2)
+    npx = len(data) * H * W
+    out["config4_grad512"] = {"images": len(data), "ms_forward": round(ms_f, 3), "ms_forward_backward": round(ms_fb, 3),
+                              "images_per_s_fwd_bwd": round(len(data) / (ms_fb * 1e-3), 1),
+                              "mpx_it_per_s_fwd_bwd": round(npx * iters / (ms_fb * 1e-3) / 1e6, 1),
+                              "note": "gradient parity: tests/test_gpu_backward.py"}
+    return out
+
+
 # ------------------------------------------------------------------- bench
 def main():
     args = parse_args()
@@ -322,6 +446,10 @@ def main():
     if not args.no_batched:
         print(f"[bench] batched workload: {args.batch_images} images", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(dev, args)
+
+    if not args.no_configs:
+        print("[bench] per-configuration figures", file=sys.stderr, flush=True)
+        out["configs"] = bench_configs(dev, args)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -209,6 +209,7 @@ size_t deblur_taps_bytes(const deblur_psf* psf);
  *   int32 [0]        number of non-zero taps T
  *   int32 [1]        number of column groups G
  *   int32 [1 + S]    number of column groups of length S, S = 1..8
+ *   int32 [10]       number of packed words (G + T)
  *   bytes 256 ..     T records {int32 dy, int32 dx, float32 h, int32 0},
  *                    the non-zero taps in row-major order
  *   bytes 256+16P .. G records of 48 bytes {int32 dx, int32 dy0, int32 S,
@@ -216,6 +217,8 @@ size_t deblur_taps_bytes(const deblur_psf* psf);
  *                    w[s], s < S, a run of vertically adjacent non-zero taps
  *                    of one PSF column (runs longer than 8 are split);
  *                    ordered by S descending, then dx, then dy0.
+ *   bytes 256+64P .. the groups again, packed: per group one int32
+ *                    (dx & 0xffff) | (dy0 << 16) followed by its S weights.
  * The stencil kernels sum the taps of a pixel in the group order. */
 int deblur_compile_taps(const deblur_psf* psf, void* taps_out, size_t taps_bytes, void* stream);
 

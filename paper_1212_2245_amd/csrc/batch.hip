@@ -27,7 +27,7 @@ struct BatchImg {
     const float* f;
     float* buf[2];          // ping-pong; buf[0] is the caller's output
     float2* qw;             // (q, W) plane of stencil images
-    const TapGroup* taps;   // column groups of the compiled PSF
+    const float* taps;      // packed column groups of the compiled PSF
     const int* hdr;         // compiled PSF header (group counts per run length)
     int H, W, pitch, L;     // L: box length (box classes)
     IterParams p;
@@ -44,9 +44,10 @@ __global__ void __launch_bounds__(BT_NT) batch_stage1(const BatchTile* __restric
                                                       const BatchImg* __restrict__ imgs, int src)
 {
     __shared__ float tile[stage1_lds_floats<RAD, BT_TH>()];
+    __shared__ float pk[packed_words_max<RAD>()];
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
-    stage1_tile<RAD, BT_TH, BT_NT>(tile, im.buf[src], im.f, im.qw, nullptr, im.H, im.W, im.pitch, t.x0, t.y0,
+    stage1_tile<RAD, BT_TH, BT_NT>(tile, pk, im.buf[src], im.f, im.qw, nullptr, im.H, im.W, im.pitch, t.x0, t.y0,
                                    im.taps, im.hdr, im.p);
 }
 
@@ -161,8 +162,8 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         }
         launch_compile_taps(it.psf, list, nullptr);
         b.hdr = reinterpret_cast<const int*>(list);
-        b.taps = reinterpret_cast<const TapGroup*>(static_cast<unsigned char*>(list) +
-                                                   tap_groups_offset(it.psf.ph, it.psf.pw));
+        b.taps = reinterpret_cast<const float*>(static_cast<unsigned char*>(list) +
+                                                tap_packed_offset(it.psf.ph, it.psf.pw));
         b.H = it.H;
         b.W = it.W;
         b.pitch = it.pitch;

@@ -18,18 +18,27 @@ struct IterParams {
 };
 
 // Compiled PSF ("tap list" buffer), built on the device by launch_compile_taps:
-//   bytes [0, 256)        header: int count of non-zero taps, int count of
-//                         column groups (a multiple of 4)
+//   bytes [0, 256)        header: int count of non-zero taps T, int count of
+//                         column groups G, counts of groups of length 1..8,
+//                         int count of packed words (G + T)
 //   bytes [256, ...)      non-zero taps {dy, dx, weight bits, 0}, row-major
 //   bytes [groups_off..)  column groups: runs of up to 8 vertically adjacent
-//                         non-zero taps of one PSF column, column-major order
+//                         non-zero taps of one PSF column, ordered by length
+//                         (longest first), then column, then row
+//   bytes [packed_off..)  the same groups packed for the stencil kernels:
+//                         per group one word (dx & 0xffff) | (dy0 << 16),
+//                         then its S weights
 struct TapGroup {
-    int dx, dy0, S, pad;  // taps (dy0 + s, dx), s < S; S = 0 pads the list
+    int dx, dy0, S, pad;  // taps (dy0 + s, dx), s < S
     float w[8];
 };
 static_assert(sizeof(TapGroup) == 48, "three 16-byte words per group");
 constexpr int TAP_GROUP_MAX = 8;
 inline size_t tap_groups_offset(int ph, int pw) { return 256 + 16 * (size_t)ph * pw; }
+inline size_t tap_packed_offset(int ph, int pw) { return tap_groups_offset(ph, pw) + 48 * (size_t)ph * pw; }
+// LDS words for the packed groups of any PSF of radius class RAD
+template <int RAD>
+constexpr int packed_words_max() { return 2 * (2 * RAD + 1) * (2 * RAD + 1); }
 
 size_t wiener_ws_bytes(int H, int W, bool rowwise);
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,

@@ -175,27 +175,48 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
 }
 
 // Fold of an output extended by (ry, rx): every image pixel sums the grid
-// points whose clamped position it is.
+// points whose clamped position it is.  Separable: first along x (every
+// extended row, into tmp of EH x W), then along y.  Border pixels sum up to
+// 2r + 1 values; the loads go out eight at a time.
+DEBLUR_DEV void add_to(float& a, float b) { a += b; }
+DEBLUR_DEV void add_to(float2& a, float2 b)
+{
+    a.x += b.x;
+    a.y += b.y;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) adj_fold(const T* __restrict__ ext, int epitch, int ry, int rx, int H, int W,
-                                                T* __restrict__ out, int opitch)
+DEBLUR_DEV T strided_sum(const T* __restrict__ p, size_t stride, int n)
+{
+    T acc{};
+    for (int b0 = 0; b0 < n; b0 += 8) {
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = b0 + k < n ? p[(size_t)(b0 + k) * stride] : T{};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) add_to(acc, v[k]);
+    }
+    return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) adj_fold_x(const T* __restrict__ ext, int epitch, int rx, int W,
+                                                  T* __restrict__ tmp)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, zy = blockIdx.y;
+    if (x >= W) return;
+    const int lo = x == 0 ? 0 : x + rx, hi = x == W - 1 ? W - 1 + 2 * rx : x + rx;   // extended columns
+    tmp[(size_t)zy * W + x] = strided_sum(ext + (size_t)zy * epitch + lo, 1, hi - lo + 1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) adj_fold_y(const T* __restrict__ tmp, int ry, int H, int W,
+                                                  T* __restrict__ out, int opitch)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= W) return;
-    const int ylo = y == 0 ? -ry : y, yhi = y == H - 1 ? H - 1 + ry : y;
-    const int xlo = x == 0 ? -rx : x, xhi = x == W - 1 ? W - 1 + rx : x;
-    T acc{};
-    for (int zy = ylo; zy <= yhi; ++zy)
-        for (int zx = xlo; zx <= xhi; ++zx) {
-            const T v = ext[(size_t)(zy + ry) * epitch + (zx + rx)];
-            if constexpr (sizeof(T) == 8) {
-                acc.x += v.x;
-                acc.y += v.y;
-            } else {
-                acc += v;
-            }
-        }
-    out[(size_t)y * opitch + x] = acc;
+    const int lo = y == 0 ? 0 : y + ry, hi = y == H - 1 ? H - 1 + 2 * ry : y + ry;   // extended rows
+    out[(size_t)y * opitch + x] = strided_sum(tmp + (size_t)lo * W + x, (size_t)W, hi - lo + 1);
 }
 
 // ------------------------------- adjoint of W, q = W f / s, r_f and the guard
@@ -298,31 +319,42 @@ __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int
 // For every entry (j, i) of the PSF array, d = (j - cy, i - cx):
 //   sum over the tile of a(x) q(E(x + d)) + b(x) W(E(x + d)) + ds(x) u(E(x - d))
 // where the first two terms are formed as a e(E(x+d)) + bb W(E(x+d))
-// (q = e + W, bb = a + b).
-// added to this workgroup's slot of `part` (FP64).
+// (q = e + W, bb = a + b); the result is added to this workgroup's slot of
+// `part` (FP64).
+//
+// Work unit = one lag block (a PSF row dy and 8 adjacent columns dx0..dx0+7)
+// over a share of the tile rows.  Along a tile row the unit takes 8 pixels at
+// a time: their 8 factors and the 15 values at x + dx0 .. x + 7 + dx0 + 7 give
+// 64 products per channel from registers (no per-product LDS read).  The
+// extended tile covers columns x0 - RAD - 8 .. x0 + 64 + RAD + 8 so that the
+// padded lags of the last block stay inside it.
+constexpr int DH_TH = 16;
 template <int RAD>
 __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, const float2* __restrict__ qw,
                                                 const float* __restrict__ ds, const float* __restrict__ u,
                                                 int pitch, int H, int W, int ph, int pw, int bc,
                                                 double* __restrict__ part)
 {
-    constexpr int TH = 32, TW = BW_TW, LW = TW + 2 * RAD, LH = TH + 2 * RAD;
-    constexpr int MAXK = ((2 * RAD + 1) * (2 * RAD + 1) + BW_NT - 1) / BW_NT;
+    // LW odd: rows of the extended tile start in different LDS banks
+    constexpr int TH = DH_TH, TW = 64, XO = RAD + 8, LW = TW + 2 * XO + 1, LH = TH + 2 * RAD;
+    constexpr int MAXB = (2 * RAD + 1) * ((2 * RAD + 1 + 7) / 8);   // lag blocks of the largest PSF
+    constexpr int MAXU = (MAXB + BW_NT - 1) / BW_NT;
     __shared__ float2 ct[TH * TW];
     __shared__ float2 ht[LH * LW];
+    __shared__ float red[BW_NT * 8];
     const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
     const int tid = threadIdx.x;
     const int PP = ph * pw, cy = (ph - 1) / 2, cx = (pw - 1) / 2;
-    float acc[MAXK];
-    int off[MAXK];
+    const int nxb = (pw + 7) / 8, nb = ph * nxb;
+    const int rp = max(1, min(TH, BW_NT / nb));        // row parts per lag block
+    const int rows = (TH + rp - 1) / rp;
+    float acc[MAXU][8];
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k) {
-        acc[k] = 0.0f;
-        const int t = tid + k * BW_NT;
-        const int j = t < PP ? t / pw : 0, i = t < PP ? t - j * pw : 0;
-        off[k] = (j - cy) * LW + (i - cx);
-    }
-    // a, b with the (q, W) plane at x + d
+    for (int k = 0; k < MAXU; ++k)
+#pragma unroll
+        for (int l = 0; l < 8; ++l) acc[k][l] = 0.0f;
+
+    // a, bb on the tile; (e, W) on the extended tile
     stage_to_lds<BW_NT, TH * TW>(ct, [&](int idx) {
         const int ly = idx / TW, lx = idx - ly * TW;
         const int y = y0 + ly, x = x0 + lx;
@@ -330,46 +362,92 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
     });
     stage_to_lds<BW_NT, LH * LW>(ht, [&](int idx) {
         const int ly = idx / LW, lx = idx - ly * LW;
-        const int gy = ext_index(y0 - RAD + ly, H, bc), gx = ext_index(x0 - RAD + lx, W, bc);
+        const int gy = ext_index(y0 - RAD + ly, H, bc), gx = ext_index(x0 - XO + lx, W, bc);
         return qw[(size_t)gy * W + gx];
     });
     __syncthreads();
-    for (int ly = 0; ly < TH; ++ly)
-        for (int lx = 0; lx < TW; ++lx) {
-            const float2 c = ct[ly * TW + lx];
-            const float2* h0 = ht + (ly + RAD) * LW + lx + RAD;
 #pragma unroll
-            for (int k = 0; k < MAXK; ++k) {
-                const float2 v = h0[off[k]];
-                acc[k] = fmaf(c.x, v.x, fmaf(c.y, v.y, acc[k]));
+    for (int k = 0; k < MAXU; ++k) {
+        const int unit = tid + k * BW_NT;
+        if (unit >= nb * rp) break;
+        const int blk = unit % nb, r = unit / nb;
+        const int dy = blk / nxb - cy, dx0 = (blk % nxb) * 8 - cx;
+        const int ya = r * rows, yb = min(TH, ya + rows);
+        for (int y = ya; y < yb; ++y) {
+            const float2* hrow = ht + (y + RAD + dy) * LW + XO + dx0;
+            for (int xc = 0; xc < TW; xc += 8) {
+                float2 c[8], h[15];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) c[q] = ct[y * TW + xc + q];
+#pragma unroll
+                for (int q = 0; q < 15; ++q) h[q] = hrow[xc + q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+#pragma unroll
+                    for (int l = 0; l < 8; ++l) acc[k][l] = fmaf(c[q].x, h[q + l].x, fmaf(c[q].y, h[q + l].y, acc[k][l]));
             }
         }
+    }
     __syncthreads();
-    // ds with u at x - d
-    stage_to_lds<BW_NT, TH * TW>(ct, [&](int idx) {
+    // ds on the tile; u on the extended tile (x - d)
+    float* cs = reinterpret_cast<float*>(ct);
+    float* hs = reinterpret_cast<float*>(ht);
+    stage_to_lds<BW_NT, TH * TW>(cs, [&](int idx) {
         const int ly = idx / TW, lx = idx - ly * TW;
         const int y = y0 + ly, x = x0 + lx;
-        return make_float2((y < H && x < W) ? ds[(size_t)y * W + x] : 0.0f, 0.0f);
+        return (y < H && x < W) ? ds[(size_t)y * W + x] : 0.0f;
     });
-    float* hs = reinterpret_cast<float*>(ht);
     stage_to_lds<BW_NT, LH * LW>(hs, [&](int idx) {
         const int ly = idx / LW, lx = idx - ly * LW;
-        const int gy = ext_index(y0 - RAD + ly, H, bc), gx = ext_index(x0 - RAD + lx, W, bc);
+        const int gy = ext_index(y0 - RAD + ly, H, bc), gx = ext_index(x0 - XO + lx, W, bc);
         return u[(size_t)gy * pitch + gx];
     });
     __syncthreads();
-    for (int ly = 0; ly < TH; ++ly)
-        for (int lx = 0; lx < TW; ++lx) {
-            const float c = ct[ly * TW + lx].x;
-            const float* h0 = hs + (ly + RAD) * LW + lx + RAD;
 #pragma unroll
-            for (int k = 0; k < MAXK; ++k) acc[k] = fmaf(c, h0[-off[k]], acc[k]);
+    for (int k = 0; k < MAXU; ++k) {
+        const int unit = tid + k * BW_NT;
+        if (unit >= nb * rp) break;
+        const int blk = unit % nb, r = unit / nb;
+        const int dy = blk / nxb - cy, dx0 = (blk % nxb) * 8 - cx;
+        const int ya = r * rows, yb = min(TH, ya + rows);
+        for (int y = ya; y < yb; ++y) {
+            // u(x - dx0 - l) for pixel x = xc + q: column xc + XO - dx0 - 7 + (q - l + 7)
+            const float* urow = hs + (y + RAD - dy) * LW + XO - dx0 - 7;
+            for (int xc = 0; xc < TW; xc += 8) {
+                float c[8], h[15];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) c[q] = cs[y * TW + xc + q];
+#pragma unroll
+                for (int q = 0; q < 15; ++q) h[q] = urow[xc + q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+#pragma unroll
+                    for (int l = 0; l < 8; ++l) acc[k][l] = fmaf(c[q], h[q - l + 7], acc[k][l]);
+            }
         }
-    const size_t b = (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * PP;
+    }
+    // combine the row parts of each lag block in a fixed order
+    const size_t base = (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * PP;
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k) {
-        const int t = tid + k * BW_NT;
-        if (t < PP) part[b + t] += (double)acc[k];
+    for (int k = 0; k < MAXU; ++k) {
+        __syncthreads();
+        const int unit = tid + k * BW_NT;
+        const bool live = unit < nb * rp;
+        if (live)
+#pragma unroll
+            for (int l = 0; l < 8; ++l) red[tid * 8 + l] = acc[k][l];
+        __syncthreads();
+        if (live && unit / nb == 0) {
+            const int blk = unit % nb;
+            const int j = blk / nxb, i0 = (blk % nxb) * 8;
+#pragma unroll
+            for (int l = 0; l < 8; ++l) {
+                if (i0 + l >= pw) break;
+                double sum = 0.0;
+                for (int r = 0; r < rp; ++r) sum += (double)red[(tid + r * nb) * 8 + l];
+                part[base + j * pw + i0 + l] += sum;
+            }
+        }
     }
 }
 
@@ -380,8 +458,15 @@ __global__ void __launch_bounds__(256) adj_reduce(const double* __restrict__ par
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < PP) {
+        // fixed order b = 0, 1, ...; eight loads in flight
         double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * PP + t];
+        for (int b0 = 0; b0 < nblocks; b0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = b0 + k < nblocks ? part[(size_t)(b0 + k) * PP + t] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += v[k];
+        }
         dh[t] = s;
     }
     if (t == 0) {
@@ -464,7 +549,7 @@ __global__ void __launch_bounds__(256) write_grads(const double* __restrict__ dh
 static size_t r256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 struct BwdLayout {
-    size_t list, qw, s, ab, c, du, ds, aT, lamA, lamB, dqw, ext, part, apart, dh, da, total;
+    size_t list, qw, s, ab, c, du, ds, aT, lamA, lamB, dqw, ext, fold, part, apart, dh, da, total;
     size_t wiener;  // start of the Wiener-adjoint region (reuses the iteration planes)
 };
 
@@ -481,7 +566,7 @@ static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
     const size_t ext2 = r256((size_t)(H + 2 * cy) * (W + 2 * cx) * 8);
     const int th = bwd_th(rad);
     const size_t nb_it = (size_t)((W + 63) / 64) * ((H + th - 1) / th);
-    const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + 31) / 32);
+    const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + DH_TH - 1) / DH_TH);
     size_t o = 0;
     L.list = o; o += r256(tap_list_bytes(psf));
     L.qw = o; o += pl2;
@@ -495,6 +580,7 @@ static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
     L.lamB = o; o += pl;
     L.dqw = o; o += pl2;
     L.ext = o; o += ext2;
+    L.fold = o; o += r256((size_t)(H + 2 * cy) * W * 8);
     L.part = o; o += r256(nb_dh * psf.ph * psf.pw * 8);
     L.apart = o; o += r256(nb_it * 8);
     L.dh = o; o += r256((size_t)psf.ph * psf.pw * 8);
@@ -554,8 +640,11 @@ static void launch_bwd_iter(const float* f, const float* u, const float* lam, in
         const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH);
         hipLaunchKernelGGL((adj_stencil<RAD, TH, -1, float2>), ge, dim3(BW_NT), 0, st, (const float2*)ab, W, H, W, 0,
                            ext, EW, -cy, -cx, EH, EW, taps, nt);
-        hipLaunchKernelGGL(adj_fold<float2>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float2*)ext, EW, cy,
-                           cx, H, W, dqw, W);
+        float2* tmp = reinterpret_cast<float2*>(w8 + L.fold);
+        hipLaunchKernelGGL(adj_fold_x<float2>, dim3((W + 255) / 256, EH), dim3(256), 0, st, (const float2*)ext, EW, cx,
+                           W, tmp);
+        hipLaunchKernelGGL(adj_fold_y<float2>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float2*)tmp, cy, H,
+                           W, dqw, W);
     }
     hipLaunchKernelGGL(adj_point, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float2*)dqw, (const float2*)qw,
                        (const float*)s, f, grad_f, ds, H, W, pitch, p);
@@ -569,12 +658,15 @@ static void launch_bwd_iter(const float* f, const float* u, const float* lam, in
         const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH);
         hipLaunchKernelGGL((adj_stencil<RAD, TH, 1, float>), ge, dim3(BW_NT), 0, st, (const float*)ds, W, H, W, 0, ext,
                            EW, -cy, -cx, EH, EW, taps, nt);
-        hipLaunchKernelGGL(adj_fold<float>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float*)ext, EW, cy, cx,
-                           H, W, aT, W);
+        float* tmp = reinterpret_cast<float*>(w8 + L.fold);
+        hipLaunchKernelGGL(adj_fold_x<float>, dim3((W + 255) / 256, EH), dim3(256), 0, st, (const float*)ext, EW, cx, W,
+                           tmp);
+        hipLaunchKernelGGL(adj_fold_y<float>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float*)tmp, cy, H, W,
+                           aT, W);
     }
     hipLaunchKernelGGL((adj_tv<32>), dim3((W + 63) / 64, (H + 31) / 32), dim3(BW_NT), 0, st, u, pitch,
                        (const float*)c, (const float*)du, (const float*)aT, lam_out, H, W, p);
-    hipLaunchKernelGGL((adj_dh<RAD>), dim3((W + 63) / 64, (H + 31) / 32), dim3(BW_NT), 0, st, (const float2*)ab,
+    hipLaunchKernelGGL((adj_dh<RAD>), dim3((W + 63) / 64, (H + DH_TH - 1) / DH_TH), dim3(BW_NT), 0, st, (const float2*)ab,
                        (const float2*)qw, (const float*)ds, u, pitch, H, W, psf.ph, psf.pw, p.bc, part);
 }
 
@@ -590,7 +682,7 @@ int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
     const int PP = psf.ph * psf.pw;
     const int th = bwd_th(rad);
     const size_t nb_it = (size_t)((W + 63) / 64) * ((H + th - 1) / th);
-    const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + 31) / 32);
+    const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + DH_TH - 1) / DH_TH);
     double* part = reinterpret_cast<double*>(w8 + L.part);
     double* apart = reinterpret_cast<double*>(w8 + L.apart);
     double* dh = reinterpret_cast<double*>(w8 + L.dh);

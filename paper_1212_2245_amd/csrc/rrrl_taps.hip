@@ -50,13 +50,16 @@ DEBLUR_DEV void block_scan256(int (&v)[N], int (*tot)[N])
 // count in hdr[0].  Then the column groups: runs of vertically adjacent
 // non-zero taps of one PSF column, split every TAP_GROUP_MAX rows, ordered by
 // run length S (longest first) and within one length by column and row;
-// hdr[1] = number of groups, hdr[1 + S] = number of groups of length S.
+// hdr[1] = number of groups, hdr[1 + S] = number of groups of length S;
+// the packed copy (one header word and S weights per group) has hdr[10]
+// words.
 // Single workgroup of 256 threads (pw <= 256).
 __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restrict__ list,
-                                                      TapGroup* __restrict__ groups, int* __restrict__ hdr)
+                                                      TapGroup* __restrict__ groups, float* __restrict__ packed,
+                                                      int* __restrict__ hdr)
 {
     __shared__ int tot1[4][1], tot8[4][TAP_GROUP_MAX];
-    __shared__ int cls_base[TAP_GROUP_MAX];
+    __shared__ int cls_base[TAP_GROUP_MAX], word_base[TAP_GROUP_MAX];
     __shared__ float hs[65 * 65];             // the PSF array (ph, pw <= 65)
     __shared__ unsigned long long mask0[65];  // per column: non-zero rows 0..63
     __shared__ int mask1[65];                 // per column: row 64 non-zero
@@ -131,13 +134,16 @@ __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restri
     for (int q = 0; q < TAP_GROUP_MAX; ++q) sc[q] = my[q];
     block_scan256<TAP_GROUP_MAX>(sc, tot8);
     if (threadIdx.x == 255) {
-        int base = 0;
+        int base = 0, words = 0;
         for (int q = TAP_GROUP_MAX - 1; q >= 0; --q) {
             cls_base[q] = base;
+            word_base[q] = words;
             base += sc[q];
+            words += sc[q] * (q + 2);
             hdr[2 + q] = sc[q];
         }
         hdr[1] = base;
+        hdr[10] = words;
     }
     __syncthreads();
     int next[TAP_GROUP_MAX];
@@ -155,6 +161,11 @@ __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restri
         g4[0] = make_int4(col - cx, j0 - cy, run, 0);
         g4[1] = make_int4(__float_as_int(w[0]), __float_as_int(w[1]), __float_as_int(w[2]), __float_as_int(w[3]));
         g4[2] = make_int4(__float_as_int(w[4]), __float_as_int(w[5]), __float_as_int(w[6]), __float_as_int(w[7]));
+        // packed copy: word offset from the group's rank within its length
+        const int q = run - 1;
+        float* pw_ = packed + word_base[q] + (slot - cls_base[q]) * (run + 1);
+        pw_[0] = __int_as_float((int)(((unsigned)(col - cx) & 0xffffu) | ((unsigned)(j0 - cy) << 16)));
+        for (int t = 0; t < run; ++t) pw_[1 + t] = w[t];
     };
     for_runs([&](int start, int len) {
         for (int k = 0; k < len; k += TAP_GROUP_MAX) emit(start + k, min(TAP_GROUP_MAX, len - k));
@@ -184,7 +195,7 @@ int taps_num_variants() { return kNumVariants; }
 
 template <int RAD, int TH, int NT>
 static void stage1_inst(const float* f, const float* u, float2* qw, float* s_out, int H, int W, int pitch,
-                        const TapGroup* taps, const int* nt, const IterParams& p, hipStream_t st)
+                        const float* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     const dim3 g((W + 63) / 64, (H + TH - 1) / TH);
     hipLaunchKernelGGL((rrrl_taps_stage1<RAD, TH, NT>), g, dim3(NT), 0, st, u, f, qw, s_out, H, W, pitch, taps, nt,
@@ -193,7 +204,7 @@ static void stage1_inst(const float* f, const float* u, float2* qw, float* s_out
 
 template <int RAD, int TH, int NT>
 static void stage2_inst(const float2* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
-                        const TapGroup* taps, const int* nt, const IterParams& p, hipStream_t st)
+                        const float* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     const dim3 g((W + 63) / 64, (H + TH - 1) / TH);
     hipLaunchKernelGGL((rrrl_taps_stage2<RAD, TH, NT>), g, dim3(NT), 0, st, qw, u, un, ckpt, H, W, pitch, taps, nt,
@@ -202,7 +213,7 @@ static void stage2_inst(const float2* qw, const float* u, float* un, float* ckpt
 
 template <int RAD>
 static void launch_stage1_t(int v, const float* f, const float* u, float2* qw, float* s_out, int H, int W,
-                            int pitch, const TapGroup* taps, const int* nt, const IterParams& p, hipStream_t st)
+                            int pitch, const float* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     switch (v) {
         case 0: stage1_inst<RAD, 64, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
@@ -218,7 +229,7 @@ static void launch_stage1_t(int v, const float* f, const float* u, float2* qw, f
 
 template <int RAD>
 static void launch_stage2_t(int v, const float2* qw, const float* u, float* un, float* ckpt, int H, int W,
-                            int pitch, const TapGroup* taps, const int* nt, const IterParams& p, hipStream_t st)
+                            int pitch, const float* taps, const int* nt, const IterParams& p, hipStream_t st)
 {
     // 64-row tiles of the two-channel plane exceed LDS for the largest radius
     if (RAD >= 32 && (v == 0 || v == 1)) v = 3;
@@ -249,7 +260,7 @@ static int default_variant(int H, int W, int stage)
 size_t tap_list_bytes(const PsfDev& psf)
 {
     const size_t P = (size_t)psf.ph * psf.pw;
-    return tap_groups_offset(psf.ph, psf.pw) + sizeof(TapGroup) * P;
+    return tap_packed_offset(psf.ph, psf.pw) + 4 * 2 * P;
 }
 
 void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st)
@@ -257,7 +268,7 @@ void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st)
     unsigned char* w8 = reinterpret_cast<unsigned char*>(list);
     hipLaunchKernelGGL(build_tap_list, dim3(1), dim3(256), 0, st, psf, reinterpret_cast<int4*>(w8 + 256),
                        reinterpret_cast<TapGroup*>(w8 + tap_groups_offset(psf.ph, psf.pw)),
-                       reinterpret_cast<int*>(w8));
+                       reinterpret_cast<float*>(w8 + tap_packed_offset(psf.ph, psf.pw)), reinterpret_cast<int*>(w8));
 }
 
 static int psf_radius_class(const PsfDev& psf)
@@ -271,7 +282,7 @@ int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, 
     const int v = variant > 0 ? variant - 1 : default_variant(H, W, 1);
     const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
     const int* nt = reinterpret_cast<const int*>(w8);
-    const TapGroup* taps = reinterpret_cast<const TapGroup*>(w8 + tap_groups_offset(psf.ph, psf.pw));
+    const float* taps = reinterpret_cast<const float*>(w8 + tap_packed_offset(psf.ph, psf.pw));
     float2* q2 = reinterpret_cast<float2*>(qw);
     switch (psf_radius_class(psf)) {
         case 4: launch_stage1_t<4>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
@@ -289,7 +300,7 @@ int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, 
     const int v = variant > 0 ? variant - 1 : default_variant(H, W, 2);
     const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
     const int* nt = reinterpret_cast<const int*>(w8);
-    const TapGroup* taps = reinterpret_cast<const TapGroup*>(w8 + tap_groups_offset(psf.ph, psf.pw));
+    const float* taps = reinterpret_cast<const float*>(w8 + tap_packed_offset(psf.ph, psf.pw));
     const float2* q2 = reinterpret_cast<const float2*>(qw);
     switch (psf_radius_class(psf)) {
         case 4: launch_stage2_t<4>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;

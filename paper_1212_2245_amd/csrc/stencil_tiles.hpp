@@ -41,64 +41,89 @@ DEBLUR_DEV void group_fma_b(const float2* __restrict__ p, const float* w, float 
 
 // Sum over all column groups in list order (by run length, longest first,
 // then column-major): the order is the same for every tile shape, so the
-// result of a pixel does not depend on the tiling.  hdr[1 + S] = number of
-// groups of length S.  Each length has its own loop (no per-group dispatch);
-// the descriptor of the next group is fetched while the current one is
-// processed.
-template <int S, int R, int LW>
-DEBLUR_DEV const TapGroup* blur_class(const float* __restrict__ base, const TapGroup* __restrict__ g, int n,
-                                      float (&acc)[R])
+// result of a pixel does not depend on the tiling.  The groups are read from
+// the packed copy in LDS (pk: per group one word (dx & 0xffff) | (dy0 << 16)
+// and its S weights); cnt[S - 1] = number of groups of length S.  Each length
+// has its own loop (no per-group dispatch).
+DEBLUR_DEV void unpack_offsets(const float* d, int& dx, int& dy0)
 {
-    if (n <= 0) return g;
-    TapGroup cur = g[0];
-    for (int k = 0; k < n; ++k) {
-        const TapGroup nxt = g[k + 1 < n ? k + 1 : k];
-        group_fma_a<R, S, LW>(base - (cur.dy0 + S - 1) * LW - cur.dx, cur.w, acc);
-        cur = nxt;
-    }
-    return g + n;
+    const int h = __builtin_amdgcn_readfirstlane(__float_as_int(d[0]));
+    dx = (int)(short)(h & 0xffff);
+    dy0 = h >> 16;
 }
 
 template <int S, int R, int LW>
-DEBLUR_DEV const TapGroup* corr_class(const float2* __restrict__ base, const TapGroup* __restrict__ g, int n,
-                                      float (&n1)[R], float (&n2)[R])
+DEBLUR_DEV const float* blur_class(const float* __restrict__ base, const float* __restrict__ pk, int n,
+                                   float (&acc)[R])
 {
-    if (n <= 0) return g;
-    TapGroup cur = g[0];
+#pragma unroll 2
     for (int k = 0; k < n; ++k) {
-        const TapGroup nxt = g[k + 1 < n ? k + 1 : k];
-        group_fma_b<R, S, LW>(base + cur.dy0 * LW + cur.dx, cur.w, n1, n2);
-        cur = nxt;
+        const float* d = pk + k * (S + 1);
+        int dx, dy0;
+        unpack_offsets(d, dx, dy0);
+        float w[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) w[s] = d[1 + s];
+        group_fma_a<R, S, LW>(base - (dy0 + S - 1) * LW - dx, w, acc);
     }
-    return g + n;
+    return pk + n * (S + 1);
+}
+
+template <int S, int R, int LW>
+DEBLUR_DEV const float* corr_class(const float2* __restrict__ base, const float* __restrict__ pk, int n,
+                                   float (&n1)[R], float (&n2)[R])
+{
+#pragma unroll 2
+    for (int k = 0; k < n; ++k) {
+        const float* d = pk + k * (S + 1);
+        int dx, dy0;
+        unpack_offsets(d, dx, dy0);
+        float w[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) w[s] = d[1 + s];
+        group_fma_b<R, S, LW>(base + dy0 * LW + dx, w, n1, n2);
+    }
+    return pk + n * (S + 1);
 }
 
 template <int R, int LW>
-DEBLUR_DEV void blur_groups(const float* __restrict__ base, const TapGroup* __restrict__ g,
-                            const int* __restrict__ hdr, float (&acc)[R])
+DEBLUR_DEV void blur_groups(const float* __restrict__ base, const float* __restrict__ pk, const int* cnt,
+                            float (&acc)[R])
 {
-    g = blur_class<8, R, LW>(base, g, hdr[9], acc);
-    g = blur_class<7, R, LW>(base, g, hdr[8], acc);
-    g = blur_class<6, R, LW>(base, g, hdr[7], acc);
-    g = blur_class<5, R, LW>(base, g, hdr[6], acc);
-    g = blur_class<4, R, LW>(base, g, hdr[5], acc);
-    g = blur_class<3, R, LW>(base, g, hdr[4], acc);
-    g = blur_class<2, R, LW>(base, g, hdr[3], acc);
-    blur_class<1, R, LW>(base, g, hdr[2], acc);
+    pk = blur_class<8, R, LW>(base, pk, cnt[7], acc);
+    pk = blur_class<7, R, LW>(base, pk, cnt[6], acc);
+    pk = blur_class<6, R, LW>(base, pk, cnt[5], acc);
+    pk = blur_class<5, R, LW>(base, pk, cnt[4], acc);
+    pk = blur_class<4, R, LW>(base, pk, cnt[3], acc);
+    pk = blur_class<3, R, LW>(base, pk, cnt[2], acc);
+    pk = blur_class<2, R, LW>(base, pk, cnt[1], acc);
+    blur_class<1, R, LW>(base, pk, cnt[0], acc);
 }
 
 template <int R, int LW>
-DEBLUR_DEV void corr_groups(const float2* __restrict__ base, const TapGroup* __restrict__ g,
-                            const int* __restrict__ hdr, float (&n1)[R], float (&n2)[R])
+DEBLUR_DEV void corr_groups(const float2* __restrict__ base, const float* __restrict__ pk, const int* cnt,
+                            float (&n1)[R], float (&n2)[R])
 {
-    g = corr_class<8, R, LW>(base, g, hdr[9], n1, n2);
-    g = corr_class<7, R, LW>(base, g, hdr[8], n1, n2);
-    g = corr_class<6, R, LW>(base, g, hdr[7], n1, n2);
-    g = corr_class<5, R, LW>(base, g, hdr[6], n1, n2);
-    g = corr_class<4, R, LW>(base, g, hdr[5], n1, n2);
-    g = corr_class<3, R, LW>(base, g, hdr[4], n1, n2);
-    g = corr_class<2, R, LW>(base, g, hdr[3], n1, n2);
-    corr_class<1, R, LW>(base, g, hdr[2], n1, n2);
+    pk = corr_class<8, R, LW>(base, pk, cnt[7], n1, n2);
+    pk = corr_class<7, R, LW>(base, pk, cnt[6], n1, n2);
+    pk = corr_class<6, R, LW>(base, pk, cnt[5], n1, n2);
+    pk = corr_class<5, R, LW>(base, pk, cnt[4], n1, n2);
+    pk = corr_class<4, R, LW>(base, pk, cnt[3], n1, n2);
+    pk = corr_class<3, R, LW>(base, pk, cnt[2], n1, n2);
+    pk = corr_class<2, R, LW>(base, pk, cnt[1], n1, n2);
+    corr_class<1, R, LW>(base, pk, cnt[0], n1, n2);
+}
+
+// Copies the packed groups (hdr[10] words at pkg) into LDS and the eight
+// per-length counts into cnt (registers, uniform).
+template <int RAD>
+DEBLUR_DEV void load_groups(float* __restrict__ pk, const float* __restrict__ pkg, const int* __restrict__ hdr,
+                            int (&cnt)[TAP_GROUP_MAX])
+{
+    const int nw = min(hdr[10], packed_words_max<RAD>());
+#pragma unroll
+    for (int q = 0; q < TAP_GROUP_MAX; ++q) cnt[q] = hdr[2 + q];
+    stage_to_lds_n<4>(pk, nw, [&](int i) { return pkg[i]; });
 }
 
 template <int RAD, int TH>
@@ -107,9 +132,10 @@ constexpr int stage1_lds_floats() { return (TH + 2 * RAD) * (64 + 2 * RAD); }
 // Stage 1 on the tile with top-left output (x0, y0): tile = LDS scratch of
 // stage1_lds_floats() floats.
 template <int RAD, int TH, int NT>
-DEBLUR_DEV void stage1_tile(float* __restrict__ tile, const float* __restrict__ u, const float* __restrict__ f,
-                            float2* __restrict__ qw, float* __restrict__ s_out, int H, int W, int pitch, int x0,
-                            int y0, const TapGroup* __restrict__ grp, const int* __restrict__ hdr, const IterParams& p)
+DEBLUR_DEV void stage1_tile(float* __restrict__ tile, float* __restrict__ pk, const float* __restrict__ u,
+                            const float* __restrict__ f, float2* __restrict__ qw, float* __restrict__ s_out, int H,
+                            int W, int pitch, int x0, int y0, const float* __restrict__ pkg,
+                            const int* __restrict__ hdr, const IterParams& p)
 {
     // With s_out (the backward recompute) the pair written is (e, W) with
     // e = q - W = W (f - s) / s, formed without cancellation, instead of (q, W).
@@ -126,6 +152,8 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, const float* __restrict__ 
         const int y = y0 + ty * R + i;
         fr[i] = (x < W && y < H) ? f[(size_t)y * pitch + x] : 0.0f;
     }
+    int cnt[TAP_GROUP_MAX];
+    load_groups<RAD>(pk, pkg, hdr, cnt);
     const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
     if (inner && pitch % 4 == 0 && ((uintptr_t)u & 15) == 0) {
         // rows start at x0 - RAD, a multiple of 4: 16-byte loads
@@ -152,7 +180,7 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, const float* __restrict__ 
     float acc[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) acc[i] = 0.0f;
-    blur_groups<R, LW>(tile + (ty * R + RAD) * LW + tx + RAD, grp, hdr, acc);   // A: E(u)(x - d)
+    blur_groups<R, LW>(tile + (ty * R + RAD) * LW + tx + RAD, pk, cnt, acc);   // A: E(u)(x - d)
     if (x >= W) return;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -171,11 +199,12 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, const float* __restrict__ 
 template <int RAD, int TH, int NT>
 __global__ void __launch_bounds__(NT) rrrl_taps_stage1(const float* __restrict__ u, const float* __restrict__ f,
                                                        float2* __restrict__ qw, float* __restrict__ s_out, int H,
-                                                       int W, int pitch, const TapGroup* __restrict__ grp,
+                                                       int W, int pitch, const float* __restrict__ pkg,
                                                        const int* __restrict__ hdr, IterParams p)
 {
     __shared__ float tile[stage1_lds_floats<RAD, TH>()];
-    stage1_tile<RAD, TH, NT>(tile, u, f, qw, s_out, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, grp, hdr, p);
+    __shared__ float pk[packed_words_max<RAD>()];
+    stage1_tile<RAD, TH, NT>(tile, pk, u, f, qw, s_out, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, pkg, hdr, p);
 }
 
 template <int RAD, int TH>
@@ -183,13 +212,14 @@ struct Stage2Smem {
     float2 qt[(TH + 2 * RAD) * (64 + 2 * RAD)];
     float ut[(TH + 4) * (64 + 4)];
     float gt[(TH + 2) * (64 + 2)];
+    float pk[packed_words_max<RAD>()];
 };
 
 // Stage 2 on the tile with top-left output (x0, y0).
 template <int RAD, int TH, int NT>
 DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ qw, const float* __restrict__ u,
                             float* __restrict__ u_next, float* __restrict__ ckpt, int H, int W, int pitch, int x0,
-                            int y0, const TapGroup* __restrict__ grp, const int* __restrict__ hdr, const IterParams& p)
+                            int y0, const float* __restrict__ pkg, const int* __restrict__ hdr, const IterParams& p)
 {
     constexpr int TW = 64, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (NT / 64);
     static_assert(R >= 1 && TH % (NT / 64) == 0, "rows per thread");
@@ -198,6 +228,8 @@ DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ 
     float* __restrict__ ut = sm.ut;
     float* __restrict__ gt = sm.gt;
     const int tid = threadIdx.x;
+    int cnt[TAP_GROUP_MAX];
+    load_groups<RAD>(sm.pk, pkg, hdr, cnt);
     const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
     if (inner && W % 2 == 0 && ((uintptr_t)qw & 15) == 0) {
         // (q, W) pairs from an even column: 16-byte loads of two pairs
@@ -238,7 +270,7 @@ DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ 
     float n1[R], n2[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) n1[i] = n2[i] = 0.0f;
-    corr_groups<R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, grp, hdr, n1, n2);   // B: E(q, W)(x + d)
+    corr_groups<R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, sm.pk, cnt, n1, n2);   // B: E(q, W)(x + d)
     __syncthreads();   // gt complete
     const int x = x0 + tx;
     if (x >= W) return;
@@ -266,11 +298,11 @@ DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ 
 template <int RAD, int TH, int NT>
 __global__ void __launch_bounds__(NT) rrrl_taps_stage2(const float2* __restrict__ qw, const float* __restrict__ u,
                                                        float* __restrict__ u_next, float* __restrict__ ckpt,
-                                                       int H, int W, int pitch, const TapGroup* __restrict__ grp,
+                                                       int H, int W, int pitch, const float* __restrict__ pkg,
                                                        const int* __restrict__ hdr, IterParams p)
 {
     __shared__ Stage2Smem<RAD, TH> sm;
-    stage2_tile<RAD, TH, NT>(sm, qw, u, u_next, ckpt, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, grp, hdr, p);
+    stage2_tile<RAD, TH, NT>(sm, qw, u, u_next, ckpt, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, pkg, hdr, p);
 }
 
 }  // namespace deblur

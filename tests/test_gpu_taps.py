@@ -1,5 +1,6 @@
-"""Device PSF compiler (deblur_compile_taps): bit-exact check of the tap list
-and of the column groups against the layout documented in deblur.h, for
+"""Device PSF compiler (deblur_compile_taps): bit-exact check of the tap list,
+the column groups and their packed copy against the layout documented in
+deblur.h, for
 sparse, dense, gapped and boundary-size PSFs."""
 import numpy as np
 import pytest
@@ -34,7 +35,7 @@ def expected_groups(h):
 
 def decode(buf, ph, pw):
     b = buf.cpu().numpy().tobytes()
-    hdr = np.frombuffer(b[:40], dtype=np.int32)
+    hdr = np.frombuffer(b[:44], dtype=np.int32)
     T, G = int(hdr[0]), int(hdr[1])
     taps = np.frombuffer(b[256:256 + 16 * T], dtype=np.int32).reshape(T, 4)
     goff = 256 + 16 * ph * pw
@@ -44,7 +45,17 @@ def decode(buf, ph, pw):
         dx, dy0, S, _ = np.frombuffer(rec[:16], dtype=np.int32)
         w = np.frombuffer(rec[16:48], dtype=np.float32)
         groups.append((int(S), int(dx), int(dy0), [float(v) for v in w[:S]]))
-    return hdr, taps, groups
+    poff = goff + 48 * ph * pw
+    words = np.frombuffer(b[poff:poff + 4 * int(hdr[10])], dtype=np.int32)
+    packed, k = [], 0
+    while k < len(words):
+        h = int(words[k])
+        dx, dy0 = ((h & 0xFFFF) ^ 0x8000) - 0x8000, h >> 16
+        S = next(g[0] for g in groups if g[1] == dx and g[2] == dy0)
+        w = words[k + 1:k + 1 + S].view(np.float32)
+        packed.append((S, dx, dy0, [float(v) for v in w]))
+        k += 1 + S
+    return hdr, taps, groups, packed
 
 
 def psfs():
@@ -72,7 +83,7 @@ def test_compiled_taps_bit_exact(name, h):
     psf = dbl.Psf.from_taps(torch.from_numpy(h).cuda())
     buf = dbl.deblur_compile_taps(psf)
     torch.cuda.synchronize()
-    hdr, taps, groups = decode(buf, ph, pw)
+    hdr, taps, groups, packed = decode(buf, ph, pw)
     nz = np.argwhere(h != 0)
     assert int(hdr[0]) == len(nz)
     cy, cx = (ph - 1) // 2, (pw - 1) // 2
@@ -83,4 +94,5 @@ def test_compiled_taps_bit_exact(name, h):
     for S in range(1, 9):
         assert int(hdr[1 + S]) == sum(g[0] == S for g in want)
     assert int(hdr[1]) == len(want)
+    assert int(hdr[10]) == len(want) + len(nz) and packed == want
     print(f"[taps] {name}: {len(nz)} taps, {len(want)} groups", flush=True)
