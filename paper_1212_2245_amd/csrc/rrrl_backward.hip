@@ -26,6 +26,7 @@
 #include "common.hpp"
 #include "launch.hpp"
 #include "psf.hpp"
+#include "stencil_tiles.hpp"
 
 namespace deblur {
 
@@ -37,8 +38,8 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
                                                     const float* __restrict__ lam, int lam_pitch,
                                                     float2* __restrict__ ab, float* __restrict__ cpl,
                                                     float* __restrict__ du, double* __restrict__ alpha_part,
-                                                    int H, int W, int pitch, const int4* __restrict__ taps,
-                                                    const int* __restrict__ ntaps, IterParams p)
+                                                    int H, int W, int pitch, const float* __restrict__ pkg,
+                                                    const int* __restrict__ hdr, IterParams p)
 {
     constexpr int TW = BW_TW, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (BW_NT / 64);
     constexpr int UW = TW + 4, UH = TH + 4, GW = TW + 2, GH = TH + 2;
@@ -46,8 +47,11 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
     __shared__ float ut[UH * UW];
     __shared__ float gt[GH * GW];
     __shared__ double red[BW_NT];
+    __shared__ float pk[packed_words_max<RAD>()];
     const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
     const int tid = threadIdx.x;
+    int cnt[TAP_GROUP_MAX];
+    load_groups<RAD>(pk, pkg, hdr, cnt);
     stage_to_lds<BW_NT, LH * LW>(qt, [&](int idx) {
         const int ly = idx / LW, lx = idx - ly * LW;
         const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
@@ -65,22 +69,10 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
         gt[idx] = pen_deriv(gx * gx + gy * gy, p.eps_t2);
     }
     const int tx = tid & 63, ty = tid >> 6;
-    float n1[R], n2[R];
+    float2 nn[R];   // (N3, N2) = B (e, W)
 #pragma unroll
-    for (int i = 0; i < R; ++i) n1[i] = n2[i] = 0.0f;
-    const float2* base = qt + (ty * R + RAD) * LW + tx + RAD;
-    const int n = ntaps[0];
-    for (int t = 0; t < n; ++t) {
-        const int4 e = taps[t];
-        const float w = __int_as_float(e.z);
-        const float2* s = base + e.x * LW + e.y;
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const float2 v = s[i * LW];
-            n1[i] = fmaf(w, v.x, n1[i]);
-            n2[i] = fmaf(w, v.y, n2[i]);
-        }
-    }
+    for (int i = 0; i < R; ++i) nn[i] = make_float2(0.0f, 0.0f);
+    stencil_groups<1, R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, pk, cnt, nn);
     __syncthreads();
     double apart = 0.0;
     const int x = x0 + tx;
@@ -94,14 +86,15 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
         const float up = ut[c], gp = gt[cg];
         const float D = 0.5f * (gp + gt[cg - GW]) * (ut[c - UW] - up) + 0.5f * (gp + gt[cg + GW]) * (ut[c + UW] - up)
                       + 0.5f * (gp + gt[cg - 1]) * (ut[c - 1] - up) + 0.5f * (gp + gt[cg + 1]) * (ut[c + 1] - up);
-        // n1 holds N3 = B e (e = q - W), n2 holds N2 = B W
+        // nn.x = N3 = B e (e = q - W), nn.y = N2 = B W
+        const float n1 = nn[i].x, n2 = nn[i].y;
         const float dp = fmaxf(D, 0.0f), dm = fminf(D, 0.0f);
-        const float num = n2[i] + n1[i] + p.alpha * dp, den = n2[i] - p.alpha * dm;
+        const float num = n2 + n1 + p.alpha * dp, den = n2 - p.alpha * dm;
         const float rho = num / den;
         const float l = lam[(size_t)y * lam_pitch + x];
         const float a = l * up / den;
         const float b = -a * rho;
-        const float bb = -a * ((n1[i] + p.alpha * D) / den);
+        const float bb = -a * ((n1 + p.alpha * D) / den);
         const size_t o = (size_t)y * W + x;
         ab[o] = make_float2(a, bb);
         cpl[o] = p.alpha * ((D > 0.0f ? a : 0.0f) - (D < 0.0f ? b : 0.0f));
@@ -124,12 +117,15 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
 template <int RAD, int TH, int SIGN, typename T>
 __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, int vpitch, int H, int W, int wrap,
                                                      T* __restrict__ out, int opitch, int oy, int ox, int OH, int OW,
-                                                     const int4* __restrict__ taps, const int* __restrict__ ntaps)
+                                                     const float* __restrict__ pkg, const int* __restrict__ hdr)
 {
     constexpr int TW = BW_TW, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (BW_NT / 64);
     __shared__ T vt[LH * LW];
+    __shared__ float pk[packed_words_max<RAD>()];
     const int zx0 = ox + blockIdx.x * TW, zy0 = oy + blockIdx.y * TH;
     const int tid = threadIdx.x;
+    int cnt[TAP_GROUP_MAX];
+    load_groups<RAD>(pk, pkg, hdr, cnt);
     stage_to_lds<BW_NT, LH * LW>(vt, [&](int idx) {
         const int ly = idx / LW, lx = idx - ly * LW;
         int gy = zy0 - RAD + ly, gx = zx0 - RAD + lx;
@@ -148,22 +144,7 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
     T acc[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) acc[i] = T{};
-    const T* base = vt + (ty * R + RAD) * LW + tx + RAD;
-    const int n = ntaps[0];
-    for (int t = 0; t < n; ++t) {
-        const int4 e = taps[t];
-        const float w = __int_as_float(e.z);
-        const T* s = base + SIGN * (e.x * LW + e.y);
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            if constexpr (sizeof(T) == 8) {
-                acc[i].x = fmaf(w, s[i * LW].x, acc[i].x);
-                acc[i].y = fmaf(w, s[i * LW].y, acc[i].y);
-            } else {
-                acc[i] = fmaf(w, s[i * LW], acc[i]);
-            }
-        }
-    }
+    stencil_groups<SIGN, R, LW>(vt + (ty * R + RAD) * LW + tx + RAD, pk, cnt, acc);
     const int zx = zx0 + tx;
     if (zx >= ox + OW) return;
 #pragma unroll
@@ -611,7 +592,7 @@ static void launch_bwd_iter(const float* f, const float* u, const float* lam, in
                             unsigned char* w8, const BwdLayout& L, hipStream_t st)
 {
     constexpr int TH = RAD >= 32 ? 16 : 32;
-    const int4* taps = reinterpret_cast<const int4*>(w8 + L.list + 256);
+    const float* taps = reinterpret_cast<const float*>(w8 + L.list + tap_packed_offset(psf.ph, psf.pw));
     const int* nt = reinterpret_cast<const int*>(w8 + L.list);
     float2* qw = reinterpret_cast<float2*>(w8 + L.qw);
     float* s = reinterpret_cast<float*>(w8 + L.s);

@@ -126,6 +126,51 @@ DEBLUR_DEV void load_groups(float* __restrict__ pk, const float* __restrict__ pk
     stage_to_lds_n<4>(pk, nw, [&](int i) { return pkg[i]; });
 }
 
+// Generic form for one or two channels (T = float or float2), used by the
+// adjoint stencils.  DIR = +1: out(z) = sum h(d) V(z + d) (taps visited as in
+// B); DIR = -1: out(z) = sum h(d) V(z - d) (as in A).
+DEBLUR_DEV void fma_t(float w, float v, float& a) { a = fmaf(w, v, a); }
+DEBLUR_DEV void fma_t(float w, float2 v, float2& a)
+{
+    a.x = fmaf(w, v.x, a.x);
+    a.y = fmaf(w, v.y, a.y);
+}
+
+template <int DIR, int S, int R, int LW, typename T>
+DEBLUR_DEV const float* stencil_class(const T* __restrict__ base, const float* __restrict__ pk, int n, T (&acc)[R])
+{
+    for (int k = 0; k < n; ++k) {
+        const float* d = pk + k * (S + 1);
+        int dx, dy0;
+        unpack_offsets(d, dx, dy0);
+        float w[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) w[s] = d[1 + s];
+        const T* p = DIR > 0 ? base + dy0 * LW + dx : base - (dy0 + S - 1) * LW - dx;
+        T v[R + S - 1];
+#pragma unroll
+        for (int q = 0; q < R + S - 1; ++q) v[q] = p[q * LW];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < R; ++i) fma_t(w[s], v[DIR > 0 ? i + s : i + S - 1 - s], acc[i]);
+    }
+    return pk + n * (S + 1);
+}
+
+template <int DIR, int R, int LW, typename T>
+DEBLUR_DEV void stencil_groups(const T* __restrict__ base, const float* __restrict__ pk, const int* cnt, T (&acc)[R])
+{
+    pk = stencil_class<DIR, 8, R, LW>(base, pk, cnt[7], acc);
+    pk = stencil_class<DIR, 7, R, LW>(base, pk, cnt[6], acc);
+    pk = stencil_class<DIR, 6, R, LW>(base, pk, cnt[5], acc);
+    pk = stencil_class<DIR, 5, R, LW>(base, pk, cnt[4], acc);
+    pk = stencil_class<DIR, 4, R, LW>(base, pk, cnt[3], acc);
+    pk = stencil_class<DIR, 3, R, LW>(base, pk, cnt[2], acc);
+    pk = stencil_class<DIR, 2, R, LW>(base, pk, cnt[1], acc);
+    stencil_class<DIR, 1, R, LW>(base, pk, cnt[0], acc);
+}
+
 template <int RAD, int TH>
 constexpr int stage1_lds_floats() { return (TH + 2 * RAD) * (64 + 2 * RAD); }
 
