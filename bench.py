@@ -75,6 +75,8 @@ def parse_args():
     ap.add_argument("--ingest-pmc", metavar="DIR", help="parse rocprofv3 --pmc databases and exit")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT"),
                     help="write a markdown summary of a rocprofv3 --kernel-trace database and exit")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DB_OR_OUT",
+                    help="rocprofv3 --pmc databases of the stencil stages, then the output markdown file")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     return ap.parse_args()
 
@@ -98,6 +100,32 @@ def summarize_trace(db: str, out: str, command: str) -> None:
     for name, calls, tot, avg, pct in rows:
         short = name.split("(")[0].replace("void ", "")
         lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.3f} | {pct:.1f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_counters(dbs, out: str, command: str) -> None:
+    """Per-wavefront figures of the stencil stage kernels from rocprofv3 --pmc
+    databases (SQ_* counters; cycle counters in units of 4 cycles)."""
+    vals: dict = {}
+    for db in dbs:
+        for kname, ctr, v in _rocpd_rows(db, "select kernel_name, counter_name, avg(value) from counters_collection "
+                                             "group by kernel_name, counter_name"):
+            for k, frag in KERNELS.items():
+                if frag in kname:
+                    vals.setdefault(k, {"name": kname.split("(")[0].replace("void ", "")})[ctr] = v
+    lines = [f"# rocprofv3 counters: {os.path.basename(out)}", "", "Command (one pass per counter set):", "",
+             "```", command, "```", "",
+             "Per dispatch, divided by SQ_WAVES (cycle counters are in units of 4 cycles).", ""]
+    for k, c in sorted(vals.items()):
+        w = c.get("SQ_WAVES", 0.0) or 1.0
+        lines += [f"## {k}: `{c['name']}`", "", "| counter | per dispatch | per wavefront |", "|---|---|---|"]
+        for n in sorted(c):
+            if n == "name":
+                continue
+            lines.append(f"| {n} | {c[n]:.0f} | {c[n] / w:.1f} |")
+        lines.append("")
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -327,6 +355,9 @@ def main():
     args = parse_args()
     if args.ingest_pmc:
         ingest_pmc(args.ingest_pmc, args.command)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[:-1], args.summarize_counters[-1], args.command)
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)

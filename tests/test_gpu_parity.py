@@ -291,6 +291,22 @@ def test_box_running_sum_matches_stencil_path():
     assert report("runsum vs stencil", outs[0], outs[1]) <= 1e-5
 
 
+@pytest.mark.parametrize("L,bc", [(15, 0), (8, 1), (33, 0)])
+def test_box_vertical_is_transposed_horizontal(L, bc):
+    """Box-V on f equals the transpose of box-H on f^T (separate kernels for
+    the two axes; agreement to rounding)."""
+    rng = np.random.default_rng(L)
+    H, W = 144, 200
+    f = synth.observe(rng, synth.ground_truth(rng, H, W), synth.box_psf(L, "v"), 2.0)
+    u0 = np.maximum(f, 1.0)
+    p = dbl.Params(iters=6, boundary=bc)
+    v = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    dbl.deblur_rrrl_iterate(dev(f), dev(u0), v, dbl.Psf.box(L, "v"), p)
+    h = torch.empty((W, H), dtype=torch.float32, device="cuda")
+    dbl.deblur_rrrl_iterate(dev(f.T), dev(u0.T), h, dbl.Psf.box(L, "h"), p)
+    assert report(f"box V vs H^T L={L} bc={bc}", v.cpu().numpy(), h.cpu().numpy().T) <= 1e-6
+
+
 @pytest.mark.parametrize("H,W,psfname", [(1024, 1024, "line31"), (100, 70, "line9"), (300, 200, "gauss31"),
                                          (96, 130, "box63")])
 def test_tile_variants_bitwise_identical(H, W, psfname):
