@@ -49,6 +49,54 @@ struct BoxLayout {
     }
 };
 
+// Visits every (line c < LINES, position j < n) of a tile: value = load(c, j)
+// then store(c, j, value), with the loads of up to U positions of every line
+// a thread owns issued before the first store.  Horizontal tiles: wavefront
+// w takes lines w, w + 4, ...; its lanes run along j (coalesced along x).
+// Vertical tiles: flat index i = j LINES + c (coalesced along x = c).  No
+// division by a run-time value.
+template <bool VERT, int LINES, int U, typename L, typename S>
+DEBLUR_DEV void tile_pass(int n, L load, S store)
+{
+    using T = decltype(load(0, 0));
+    if constexpr (VERT) {
+        const int total = n * LINES;
+        for (int base = threadIdx.x; base < total; base += U * 256) {
+            T v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int i = base + k * 256, j = i / LINES, c = i - j * LINES;
+                if (i < total) v[k] = load(c, j);
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int i = base + k * 256, j = i / LINES, c = i - j * LINES;
+                if (i < total) store(c, j, v[k]);
+            }
+        }
+    } else {
+        constexpr int NC = (LINES + 3) / 4;
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int j0 = lane; j0 < n; j0 += U * 64) {
+            T v[NC][U];
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int c = w + 4 * q, j = j0 + 64 * k;
+                    if (c < LINES && j < n) v[q][k] = load(c, j);
+                }
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int c = w + 4 * q, j = j0 + 64 * k;
+                    if (c < LINES && j < n) store(c, j, v[q][k]);
+                }
+        }
+    }
+}
+
 // Inclusive prefix along each of `lines` LDS lines of length n (in place),
 // block-wide.  The G = 256/TC threads of a line are consecutive lanes of one
 // wavefront; each sums a contiguous chunk, the chunk offsets come from a
@@ -119,28 +167,20 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
     const int W = VERT ? bt.across_n : bt.along_n;
 
     // 1. u tile: along extended by the boundary mode, across clamped
-    batched_n<8>(
-        CU * nu,
-        [&](int i) {
-            int c, j;
-            if (VERT) { j = i / CU; c = i - j * CU; } else { c = i / nu; j = i - c * nu; }
+    tile_pass<VERT, CU, 4>(
+        nu,
+        [&](int c, int j) {
             const int ga = ext_index(lo + j, bt.along_n, p.bc);
             const int gc = clampi(c0 - 2 + c, bt.across_n);
             const int y = VERT ? ga : gc, x = VERT ? gc : ga;
             return u[(size_t)y * pitch + x];
         },
-        [&](int i, float v) {
-            int c, j;
-            if (VERT) { j = i / CU; c = i - j * CU; } else { c = i / nu; j = i - c * nu; }
-            us[Lay::at(c, j, nu, CU)] = v;
-        });
+        [&](int c, int j, float v) { us[Lay::at(c, j, nu, CU)] = v; });
     __syncthreads();
     // 2a. copy of the TC center lines for the prefix, 2b. diffusivity
-    for (int i = t; i < TC * nu; i += 256) {
-        int c, j;
-        if (VERT) { j = i / TC; c = i - j * TC; } else { c = i / nu; j = i - c * nu; }
-        ps[Lay::at(c, j, nu, TC)] = (double)us[Lay::at(c + 2, j, nu, CU)];
-    }
+    tile_pass<VERT, TC, 1>(
+        nu, [&](int c, int j) { return us[Lay::at(c + 2, j, nu, CU)]; },
+        [&](int c, int j, float v) { ps[Lay::at(c, j, nu, TC)] = (double)v; });
     // tile positions of the first/last image index along (clamping for TV)
     const int jmin = max(0, -lo), jmax = min(nu - 1, bt.along_n - 1 - lo);
     constexpr int GA = TA + 2;
@@ -159,20 +199,16 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
     // 3. s = A u, W, q on positions m = 0..nq-1 (along a0 - aL + m)
     const float invL = 1.0f / (float)bt.L;
     // f is fetched for several positions before any is used
-    batched_n<8>(
-        TC * nq,
-        [&](int i) {
-            int c, m;
-            if (VERT) { m = i / TC; c = i - m * TC; } else { c = i / nq; m = i - c * nq; }
+    tile_pass<VERT, TC, 4>(
+        nq,
+        [&](int c, int m) {
             const int gc = c0 + c;
             if (gc >= bt.across_n) return 0.0f;
             const int ga = ext_index(a0 - bt.aL + m, bt.along_n, p.bc);
             const int y = VERT ? ga : gc, x = VERT ? gc : ga;
             return f[(size_t)y * pitch + x];
         },
-        [&](int i, float fv) {
-            int c, m;
-            if (VERT) { m = i / TC; c = i - m * TC; } else { c = i / nq; m = i - c * nq; }
+        [&](int c, int m, float fv) {
             const int gc = c0 + c;
             double2 qw = make_double2(0.0, 0.0);
             if (gc < bt.across_n) {

@@ -15,6 +15,9 @@ enum { BC_REPLICATE = 0, BC_PERIODIC = 1 };
 DEBLUR_DEV int ext_index(int i, int n, int bc)
 {
     if (bc == BC_PERIODIC) {
+        if (i >= 0 && i < n) return i;
+        if (i < 0 && i >= -n) return i + n;   // halos shorter than the image: no division
+        if (i >= n && i < 2 * n) return i - n;
         const int m = i % n;
         return m < 0 ? m + n : m;
     }

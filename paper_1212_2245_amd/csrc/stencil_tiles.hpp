@@ -56,7 +56,6 @@ template <int S, int R, int LW>
 DEBLUR_DEV const float* blur_class(const float* __restrict__ base, const float* __restrict__ pk, int n,
                                    float (&acc)[R])
 {
-#pragma unroll 2
     for (int k = 0; k < n; ++k) {
         const float* d = pk + k * (S + 1);
         int dx, dy0;
@@ -73,7 +72,6 @@ template <int S, int R, int LW>
 DEBLUR_DEV const float* corr_class(const float2* __restrict__ base, const float* __restrict__ pk, int n,
                                    float (&n1)[R], float (&n2)[R])
 {
-#pragma unroll 2
     for (int k = 0; k < n; ++k) {
         const float* d = pk + k * (S + 1);
         int dx, dy0;
