@@ -23,6 +23,7 @@ struct FftPlan {
     int n;
     int npass;
     int radix[16];
+    unsigned mag[16];   // ceil(2^32 / Ns) of pass q (Ns = product of the earlier radices)
 };
 
 DEBLUR_DEV float2 cmul(float2 a, float2 b)
@@ -113,7 +114,7 @@ DEBLUR_DEV void dft_small(float2* v)
 
 template <int R>
 DEBLUR_DEV void fft_pass(const float2* __restrict__ src, float2* __restrict__ dst, int nb,
-                         int n, int Ns, const float2* __restrict__ tw)
+                         int n, int Ns, unsigned mag, const float2* __restrict__ tw)
 {
     const int m = n / R;
     const int tstride = n / (Ns * R);
@@ -121,7 +122,8 @@ DEBLUR_DEV void fft_pass(const float2* __restrict__ src, float2* __restrict__ ds
         const float2* s = src + t * n;
         float2* d = dst + t * n;
         for (int j = threadIdx.x; j < m; j += blockDim.x) {
-            const int k = j % Ns;
+            // k = j mod Ns by a multiply-high (exact for j < 2^21, Ns < 2^11)
+            const int k = Ns == 1 ? 0 : j - (int)__umulhi((unsigned)j, mag) * Ns;
             float2 v[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) v[r] = s[j + r * m];
@@ -146,10 +148,10 @@ DEBLUR_DEV float2* fft_rows(float2* a, float2* b, int nb, const FftPlan& p, cons
     for (int q = 0; q < p.npass; ++q) {
         const int R = p.radix[q];
         switch (R) {
-            case 2: fft_pass<2>(a, b, nb, p.n, Ns, tw); break;
-            case 3: fft_pass<3>(a, b, nb, p.n, Ns, tw); break;
-            case 4: fft_pass<4>(a, b, nb, p.n, Ns, tw); break;
-            default: fft_pass<8>(a, b, nb, p.n, Ns, tw); break;
+            case 2: fft_pass<2>(a, b, nb, p.n, Ns, p.mag[q], tw); break;
+            case 3: fft_pass<3>(a, b, nb, p.n, Ns, p.mag[q], tw); break;
+            case 4: fft_pass<4>(a, b, nb, p.n, Ns, p.mag[q], tw); break;
+            default: fft_pass<8>(a, b, nb, p.n, Ns, p.mag[q], tw); break;
         }
         __syncthreads();
         float2* t = a;
@@ -176,6 +178,11 @@ inline FftPlan make_plan(int n)
     }
     if (m == 4) p.radix[p.npass++] = 4;
     if (m == 2) p.radix[p.npass++] = 2;
+    unsigned long long ns = 1;
+    for (int q = 0; q < p.npass; ++q) {
+        p.mag[q] = ns > 1 ? (unsigned)(((1ull << 32) + ns - 1) / ns) : 0u;
+        ns *= (unsigned long long)p.radix[q];
+    }
     return p;
 }
 
