@@ -310,6 +310,11 @@ def bench_configs(dev, args):
         outs[name] = uo.cpu().numpy()
         it_us = ms * 1e3 / c.iters
         res[name] = {"iteration_us": round(it_us, 1), "mpx_it_per_s": round(H * W / it_us, 1)}
+        if conv == dbl.CONV_STENCIL:
+            # both stencil stages: A (2T flops) and B on two channels (4T), plus ~80 per pixel
+            tflops = (6 * res["nonzero_taps"] + 80) * H * W / (it_us * 1e-6) / 1e12
+            res[name]["roofline"] = {"bound": "alu", "achieved_tflops": round(tflops, 2),
+                                     "peak": FP32_VECTOR_PEAK_TFLOPS, "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
     a, b = outs["stencil_periodic"], outs["fft_periodic"]
     res["fft_vs_stencil_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(a))
     out["config2_gauss2048"] = res
