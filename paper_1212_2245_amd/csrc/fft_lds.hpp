@@ -118,24 +118,27 @@ DEBLUR_DEV void fft_pass(const float2* __restrict__ src, float2* __restrict__ ds
 {
     const int m = n / R;
     const int tstride = n / (Ns * R);
-    for (int t = 0; t < nb; ++t) {
+    // butterflies of all nb rows in one index range, so that every thread has
+    // work when n / R is smaller than the workgroup
+    const int lm = 31 - __clz(m);
+    const bool pow2 = (m & (m - 1)) == 0;
+    for (int bj = threadIdx.x; bj < nb * m; bj += blockDim.x) {
+        const int t = pow2 ? bj >> lm : bj / m, j = bj - t * m;
         const float2* s = src + t * n;
         float2* d = dst + t * n;
-        for (int j = threadIdx.x; j < m; j += blockDim.x) {
-            // k = j mod Ns by a multiply-high (exact for j < 2^21, Ns < 2^11)
-            const int k = Ns == 1 ? 0 : j - (int)__umulhi((unsigned)j, mag) * Ns;
-            float2 v[R];
+        // k = j mod Ns by a multiply-high (exact for j < 2^21, Ns < 2^11)
+        const int k = Ns == 1 ? 0 : j - (int)__umulhi((unsigned)j, mag) * Ns;
+        float2 v[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = s[j + r * m];
-            if (Ns > 1) {
+        for (int r = 0; r < R; ++r) v[r] = s[j + r * m];
+        if (Ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * tstride]);
-            }
-            dft_small<R>(v);
-            const int base = (j - k) * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) d[base + r * Ns] = v[r];
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * tstride]);
         }
+        dft_small<R>(v);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[base + r * Ns] = v[r];
     }
 }
 

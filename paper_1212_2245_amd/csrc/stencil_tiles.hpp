@@ -84,10 +84,24 @@ DEBLUR_DEV const float* corr_class(const float2* __restrict__ base, const float*
     return pk + n * (S + 1);
 }
 
+// The per-thread tile address, hidden from constant folding: the compiler
+// would otherwise fold the tile's LDS offset into the immediate offsets of the
+// group loads, and re-materialise the large offsets with a VALU add for
+// every paired LDS read inside the group loops.
+template <typename T>
+DEBLUR_DEV const T* opaque_lds(const T* p)
+{
+    using LT = __attribute__((address_space(3))) const T;
+    LT* q = (LT*)p;
+    asm("" : "+v"(q));
+    return (const T*)q;
+}
+
 template <int R, int LW>
 DEBLUR_DEV void blur_groups(const float* __restrict__ base, const float* __restrict__ pk, const int* cnt,
                             float (&acc)[R])
 {
+    base = opaque_lds(base);
     pk = blur_class<8, R, LW>(base, pk, cnt[7], acc);
     pk = blur_class<7, R, LW>(base, pk, cnt[6], acc);
     pk = blur_class<6, R, LW>(base, pk, cnt[5], acc);
@@ -102,6 +116,7 @@ template <int R, int LW>
 DEBLUR_DEV void corr_groups(const float2* __restrict__ base, const float* __restrict__ pk, const int* cnt,
                             float (&n1)[R], float (&n2)[R])
 {
+    base = opaque_lds(base);
     pk = corr_class<8, R, LW>(base, pk, cnt[7], n1, n2);
     pk = corr_class<7, R, LW>(base, pk, cnt[6], n1, n2);
     pk = corr_class<6, R, LW>(base, pk, cnt[5], n1, n2);
@@ -159,6 +174,7 @@ DEBLUR_DEV const float* stencil_class(const T* __restrict__ base, const float* _
 template <int DIR, int R, int LW, typename T>
 DEBLUR_DEV void stencil_groups(const T* __restrict__ base, const float* __restrict__ pk, const int* cnt, T (&acc)[R])
 {
+    base = opaque_lds(base);
     pk = stencil_class<DIR, 8, R, LW>(base, pk, cnt[7], acc);
     pk = stencil_class<DIR, 7, R, LW>(base, pk, cnt[6], acc);
     pk = stencil_class<DIR, 6, R, LW>(base, pk, cnt[5], acc);

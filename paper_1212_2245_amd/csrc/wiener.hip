@@ -115,53 +115,95 @@ __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict
 
 // M(ky, kx) for kx <= W/2, stored row-major with row pitch W/2+1 (the
 // layout of the half spectra).  Workgroup = 16 consecutive kx (one 128-byte
-// row segment of M per ky) x MULT_KY rows ky.  The PSF rows are first
-// transformed along x, G(j, kx) = sum_i h(j, i) e^{-2 pi i kx (i - cx)/W}
-// (LDS, FP64), then h^(ky, kx) = sum_j G(j, kx) e^{-2 pi i ky (j - cy)/H}.
-// Optionally also h^ itself (hh, complex64).
+// row segment of M per ky) x MULT_KY rows ky.  The PSF sides are odd, so the
+// taps at offsets +d and -d from the centre pair up under one cosine and one
+// sine: with phi = 2 pi kx / W,
+//   G(j, kx) = h(j, cx) + sum_{e>=1} [(h(j,cx+e) + h(j,cx-e)) cos(phi e)
+//                                  - i (h(j,cx+e) - h(j,cx-e)) sin(phi e)]
+// and with theta = 2 pi ky / H, P_d = G(cy+d) + G(cy-d), Q_d = G(cy+d) - G(cy-d),
+//   h^(ky, kx) = G(cy, kx) + sum_{d>=1} [P_d cos(theta d) - i Q_d sin(theta d)],
+// in FP64, the cosines and sines advanced by the rotation recurrence from
+// the exact first root (at most 32 steps).  Optionally also h^ itself (hh).
 constexpr int MULT_KX = 16, MULT_KY = 64;
+constexpr int MULT_HALF = (MULT_MAXP - 1) / 2;
 __global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, double K, float2* __restrict__ M,
                                                       float2* __restrict__ hh)
 {
     __shared__ double2 G[MULT_MAXP * MULT_KX];
+    __shared__ double2 PQ[2 * MULT_HALF * MULT_KX];
     __shared__ float hs[MULT_MAXP * MULT_MAXP];
-    __shared__ double2 rot[2 * (MULT_KX + MULT_KY)];   // per kx, ky: exp(-2 pi i k/n), exp(2 pi i k c/n)
+    __shared__ double2 rot[MULT_KX + MULT_KY];   // exp(-2 pi i k / n) per kx, then per ky
     psf_to_lds(psf, hs);
     const int Wh = W / 2 + 1;
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
     const int kx0 = blockIdx.x * MULT_KX, ky0 = blockIdx.y * MULT_KY;
-    for (int t = threadIdx.x; t < 2 * (MULT_KX + MULT_KY); t += blockDim.x) {
-        const int q = t % (MULT_KX + MULT_KY), start = t >= MULT_KX + MULT_KY;
-        const bool isx = q < MULT_KX;
-        const int k = isx ? kx0 + q : ky0 + q - MULT_KX, n = isx ? W : H, c = isx ? cx : cy;
-        rot[t] = unit_root(start ? -k * c : k, n);
+    for (int t = threadIdx.x; t < MULT_KX + MULT_KY; t += blockDim.x)
+        rot[t] = t < MULT_KX ? unit_root(kx0 + t, W) : unit_root(ky0 + t - MULT_KX, H);
+    __syncthreads();
+    // G(j, kx): two PSF rows per thread, their sums interleaved
+    for (int idx = threadIdx.x; idx < psf.ph * MULT_KX; idx += 2 * blockDim.x) {
+        const int q = idx % MULT_KX, j0 = idx / MULT_KX, j1 = j0 + (int)blockDim.x / MULT_KX;
+        const bool two = j1 < psf.ph;
+        const float* h0 = hs + j0 * psf.pw + cx;
+        const float* h1 = hs + (two ? j1 : j0) * psf.pw + cx;
+        const double c1 = rot[q].x, s1 = -rot[q].y;
+        double c = c1, s = s1;
+        double r0 = (double)h0[0], i0 = 0.0, r1 = (double)h1[0], i1 = 0.0;
+        for (int e = 1; e <= cx; ++e) {
+            r0 = fma((double)h0[e] + (double)h0[-e], c, r0);
+            i0 = fma((double)h0[-e] - (double)h0[e], s, i0);
+            r1 = fma((double)h1[e] + (double)h1[-e], c, r1);
+            i1 = fma((double)h1[-e] - (double)h1[e], s, i1);
+            const double cn = fma(c, c1, -s * s1);
+            s = fma(s, c1, c * s1);
+            c = cn;
+        }
+        const bool on = kx0 + q < Wh;
+        G[idx] = on ? make_double2(r0, i0) : make_double2(0.0, 0.0);
+        if (two) G[j1 * MULT_KX + q] = on ? make_double2(r1, i1) : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const double2* wx = rot;
-    const double2* wy = rot + MULT_KX;
-    const double2* tx0 = rot + MULT_KX + MULT_KY;
-    const double2* ty0 = tx0 + MULT_KX;
-    for (int idx = threadIdx.x; idx < psf.ph * MULT_KX; idx += blockDim.x) {
-        const int j = idx / MULT_KX, q = idx % MULT_KX;
-        G[idx] = kx0 + q < Wh ? psf_row_dft(hs + j * psf.pw, psf.pw, wx[q], tx0[q]) : make_double2(0.0, 0.0);
+    for (int idx = threadIdx.x; idx < cy * MULT_KX; idx += blockDim.x) {
+        const int d = idx / MULT_KX + 1, q = idx % MULT_KX;
+        const double2 gp = G[(cy + d) * MULT_KX + q], gm = G[(cy - d) * MULT_KX + q];
+        PQ[2 * idx] = make_double2(gp.x + gm.x, gp.y + gm.y);
+        PQ[2 * idx + 1] = make_double2(gp.x - gm.x, gp.y - gm.y);
     }
     __syncthreads();
     const int lx = threadIdx.x % MULT_KX, kx = kx0 + lx;
     if (kx >= Wh) return;
-    for (int q = threadIdx.x / MULT_KX; q < MULT_KY && ky0 + q < H; q += 256 / MULT_KX) {
-        const int ky = ky0 + q;
-        const double2 w = wy[q];
-        double2 t = ty0[q];
-        double re = 0.0, im = 0.0;
-        for (int j = 0; j < psf.ph; ++j) {
-            const double2 g = G[j * MULT_KX + lx];
-            re = fma(g.x, t.x, fma(-g.y, t.y, re));
-            im = fma(g.x, t.y, fma(g.y, t.x, im));
-            t = zmul(t, w);
+    // NQ rows ky per thread (ky0 + q0 + r * 16), their sums interleaved;
+    // P_d, Q_d are read once for all NQ
+    constexpr int NQ = MULT_KY / (256 / MULT_KX);
+    const int q0 = threadIdx.x / MULT_KX;
+    const double2 g0 = G[cy * MULT_KX + lx];
+    double c1[NQ], s1[NQ], c[NQ], s[NQ], re[NQ], im[NQ];
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+        const double2 w = rot[MULT_KX + q0 + r * (256 / MULT_KX)];
+        c1[r] = c[r] = w.x;
+        s1[r] = s[r] = -w.y;
+        re[r] = g0.x;
+        im[r] = g0.y;
+    }
+    for (int d = 1; d <= cy; ++d) {
+        const double2 P = PQ[2 * ((d - 1) * MULT_KX + lx)], Q = PQ[2 * ((d - 1) * MULT_KX + lx) + 1];
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+            re[r] = fma(P.x, c[r], fma(Q.y, s[r], re[r]));
+            im[r] = fma(P.y, c[r], fma(-Q.x, s[r], im[r]));
+            const double cn = fma(c[r], c1[r], -s[r] * s1[r]);
+            s[r] = fma(s[r], c1[r], c[r] * s1[r]);
+            c[r] = cn;
         }
-        const double den = re * re + im * im + K;
-        M[(size_t)ky * Wh + kx] = make_float2((float)(re / den), (float)(-im / den));
-        if (hh) hh[(size_t)ky * Wh + kx] = make_float2((float)re, (float)im);
+    }
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+        const int ky = ky0 + q0 + r * (256 / MULT_KX);
+        if (ky >= H) break;
+        const double inv = 1.0 / (re[r] * re[r] + im[r] * im[r] + K);
+        M[(size_t)ky * Wh + kx] = make_float2((float)(re[r] * inv), (float)(-im[r] * inv));
+        if (hh) hh[(size_t)ky * Wh + kx] = make_float2((float)re[r], (float)im[r]);
     }
 }
 
@@ -216,12 +258,19 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
     fft_twiddles(tw, H);
     const int Wh = W / 2 + 1;
     const int c0 = xcd_group(blockIdx.x, gridDim.x) * cb;
+    // With at most 8 elements per thread, the multiplier M of the thread's
+    // elements is fetched together with S, so its latency is not paid after
+    // the forward transform.
+    const bool pre = mode == 0 && cb * H <= 8 * (int)blockDim.x;
+    float2 mv[8];
     for (int base = threadIdx.x; base < cb * H; base += 8 * blockDim.x) {
         float2 v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int idx = base + k * blockDim.x, y = idx / cb, c = idx - y * cb;
-            v[k] = (idx < cb * H && c0 + c < Wh) ? S[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+            const bool ok = idx < cb * H && c0 + c < Wh;
+            v[k] = ok ? S[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+            if (pre) mv[k] = ok ? M[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -233,11 +282,19 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
     float2* X = fft_rows(a, b, cb, plan, tw);
     if (mode == 0) {
         float2* Y = X == a ? b : a;
-        for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
-            const int c = idx / H, y = idx - c * H;
-            float2 m = (c0 + c < Wh) ? M[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
-            if (conjM) m = cconj(m);
-            X[idx] = cconj(cmul(X[idx], m));
+        if (pre) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int idx = threadIdx.x + k * blockDim.x, y = idx / cb, c = idx - y * cb;
+                if (idx < cb * H) X[c * H + y] = cconj(cmul(X[c * H + y], conjM ? cconj(mv[k]) : mv[k]));
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
+                const int c = idx / H, y = idx - c * H;
+                float2 m = (c0 + c < Wh) ? M[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+                if (conjM) m = cconj(m);
+                X[idx] = cconj(cmul(X[idx], m));
+            }
         }
         __syncthreads();
         X = fft_rows(X, Y, cb, plan, tw);
