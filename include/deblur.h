@@ -54,9 +54,13 @@ typedef enum {
 typedef enum { DEBLUR_BC_REPLICATE = 0, DEBLUR_BC_PERIODIC = 1 } deblur_boundary;
 
 /* PSF kinds (Sec. 4.3).  Offsets d = (dy, dx) are relative to the centre of
- * an odd-sized array.  BOX_H / BOX_V: uniform linear motion of integer length
- * L >= 1 along x / y, taps 1/L at d in [-floor((L-1)/2), floor(L/2)] (array
- * length L + (L even)).  TAPS: a general ph x pw array (ph, pw odd). */
+ * an odd-sized array.  BOX_H / BOX_V: uniform linear motion of length
+ * L = n + frac along x / y (n = length >= 1, 0 <= frac < 1).  Integer L: taps
+ * 1/L at d in [-floor((n-1)/2), floor(n/2)], array length n + (n even).  A
+ * non-integer length adds one pixel of smaller weight at each end (Sec. 4.3,
+ * uniform linear motion): taps (frac/2)/L at d = -floor((n-1)/2) - 1 and
+ * d = floor(n/2) + 1, the n inner taps 1/L; array length n + (n even) + 2.
+ * TAPS: a general ph x pw array (ph, pw odd). */
 typedef enum { DEBLUR_PSF_BOX_H = 0, DEBLUR_PSF_BOX_V = 1, DEBLUR_PSF_TAPS = 2 } deblur_psf_kind;
 
 /* How the RRRL iteration evaluates A and B: AUTO picks the fastest exact
@@ -77,6 +81,8 @@ typedef struct {
     int32_t length;     /* box length L (BOX_H, BOX_V); ignored for TAPS */
     int32_t ph, pw;     /* TAPS: odd array dims, 1..65 each; ignored for boxes */
     const float* taps;  /* TAPS: device array ph*pw, row-major; may be NULL for boxes */
+    float frac;         /* boxes: fractional part of the length, 0 <= frac < 1 (else
+                           DEBLUR_EINVAL); ignored for TAPS */
 } deblur_psf;
 
 typedef struct {

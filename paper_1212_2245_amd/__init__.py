@@ -11,6 +11,7 @@ functions carry the C names (deblur_wiener, deblur_rrrl_iterate, ...);
 from __future__ import annotations
 
 import ctypes
+import math
 from dataclasses import dataclass
 
 import torch
@@ -30,15 +31,27 @@ def library_path() -> str:
 
 @dataclass
 class Psf:
-    """Point-spread function: a box of integer length along x or y, or a
-    general odd-sized tap array (device float32, row-major, normalised)."""
+    """Point-spread function: a box along x or y (uniform linear motion of
+    length n + frac, Sec. 4.3), or a general odd-sized tap array (device
+    float32, row-major, normalised)."""
     kind: int
     length: int = 0
     taps: torch.Tensor | None = None
+    frac: float = 0.0
 
     @staticmethod
-    def box(length: int, axis: str = "h") -> "Psf":
-        return Psf(PSF_BOX_H if axis == "h" else PSF_BOX_V, int(length), None)
+    def box(length: float, axis: str = "h") -> "Psf":
+        """Box of length L >= 1; a non-integer L adds one pixel of weight
+        (frac/2)/L at each end of the floor(L) pixels of weight 1/L."""
+        n = int(math.floor(length))
+        return Psf(PSF_BOX_H if axis == "h" else PSF_BOX_V, n, None, float(length) - n)
+
+    def array_shape(self) -> tuple[int, int]:
+        """(ph, pw) of the PSF array (for boxes: the odd array holding the taps)."""
+        if self.kind == PSF_TAPS:
+            return (int(self.taps.shape[0]), int(self.taps.shape[1]))
+        P = self.length + (1 - self.length % 2) + (2 if self.frac > 0.0 else 0)
+        return (1, P) if self.kind == PSF_BOX_H else (P, 1)
 
     @staticmethod
     def from_taps(taps: torch.Tensor) -> "Psf":
@@ -49,7 +62,7 @@ class Psf:
     def c(self) -> _lib.deblur_psf:
         if self.kind == PSF_TAPS:
             return _lib.deblur_psf(PSF_TAPS, 0, self.taps.shape[0], self.taps.shape[1], self.taps.data_ptr())
-        return _lib.deblur_psf(self.kind, self.length, 0, 0, None)
+        return _lib.deblur_psf(self.kind, self.length, 0, 0, None, self.frac)
 
 
 @dataclass
@@ -223,8 +236,7 @@ def deblur_rrrl_backward(f: torch.Tensor, ckpt: torch.Tensor | None, grad_uK: to
     need = lib.deblur_workspace_bytes(op, H, W, pitch, ctypes.byref(cpsf), ctypes.byref(cpar))
     wst = _workspace(need, f, ws)
     out = {"f": torch.empty_strided((H, W), (pitch, 1), dtype=torch.float32, device=f.device)}
-    ph, pw = (cpsf.ph, cpsf.pw) if psf.kind == PSF_TAPS else (
-        (1, psf.length + (1 - psf.length % 2)) if psf.kind == PSF_BOX_H else (psf.length + (1 - psf.length % 2), 1))
+    ph, pw = psf.array_shape()
     if grad_taps:
         out["taps"] = torch.empty((ph, pw), dtype=torch.float32, device=f.device)
     if grad_alpha:

@@ -23,7 +23,7 @@ OP_WIENER, OP_ITERATE, OP_BACKWARD, OP_BACKWARD_WIENER = 0, 1, 2, 3
 
 class deblur_psf(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("length", ctypes.c_int32), ("ph", ctypes.c_int32),
-                ("pw", ctypes.c_int32), ("taps", ctypes.c_void_p)]
+                ("pw", ctypes.c_int32), ("taps", ctypes.c_void_p), ("frac", ctypes.c_float)]
 
 
 class deblur_params(ctypes.Structure):

@@ -97,9 +97,7 @@ def tune(f, psf, params, iters: int = 3, reps: int = 5, path: str | None = None,
 
     lib = _lib.load()
     H, W = f.shape
-    taps = psf.taps if psf.taps is not None else None
-    ph, pw = (taps.shape[0], taps.shape[1]) if taps is not None else (
-        (1, psf.length + (1 - psf.length % 2)) if psf.kind == 0 else (psf.length + (1 - psf.length % 2), 1))
+    ph, pw = psf.array_shape()
     u0 = torch.clamp(f, min=1.0)
     ref = None
     timings = {}

@@ -29,7 +29,8 @@ struct BatchImg {
     float2* qw;             // (q, W) plane of stencil images
     const float* taps;      // packed column groups of the compiled PSF
     const int* hdr;         // compiled PSF header (group counts per run length)
-    int H, W, pitch, L;     // L: box length (box classes)
+    int H, W, pitch, L;     // L: integer part of the box length (box classes)
+    float frac;             // fractional part of the box length
     IterParams p;
 };
 
@@ -70,7 +71,7 @@ __global__ void __launch_bounds__(256) batch_box(const BatchTile* __restrict__ t
     constexpr int TA = VERT ? BOXV_TA : BOXH_TA, TC = VERT ? BOXV_TC : BOXH_TC;
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
-    const BoxTile bt = make_tile(im.H, im.W, im.L, VERT, TA);
+    const BoxTile bt = make_tile(im.H, im.W, im.L, im.frac, VERT, TA);
     box_iter_tile<VERT, TA, TC>(smem_raw, im.buf[src], im.f, im.buf[1 - src], nullptr, im.pitch, bt, im.p, t.x0,
                                 t.y0);
 }
@@ -168,6 +169,7 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         b.W = it.W;
         b.pitch = it.pitch;
         b.L = it.psf.length;
+        b.frac = it.psf.frac;
         b.p = it.p;
         wiener_ws = std::max(wiener_ws, wiener_ws_bytes(it.H, it.W, it.psf.ph == 1));
         P->group_of[i] = i / gs;
@@ -199,7 +201,7 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
                 const int along = vert ? it.H : it.W, across = vert ? it.W : it.H;
                 for (int c0 = 0; c0 < across; c0 += TC)
                     for (int a0 = 0; a0 < along; a0 += TA) host[cls].push_back({i, a0, c0, 0});
-                const BoxTile bt = make_tile(it.H, it.W, it.psf.length, vert, TA);
+                const BoxTile bt = make_tile(it.H, it.W, it.psf.length, it.psf.frac, vert, TA);
                 const size_t lds = vert ? box_lds_bytes<true, BOXV_TA, BOXV_TC>(bt)
                                         : box_lds_bytes<false, BOXH_TA, BOXH_TC>(bt);
                 lists[g][cls].lds = std::max(lists[g][cls].lds, lds);

@@ -1,5 +1,5 @@
 // Box tiles of the RRRL iteration (Sec. 2.3, eqs. (9)-(12)) for uniform linear motion blur
-// along a coordinate axis (box PSF of integer length L), one fused kernel per
+// along a coordinate axis (box PSF of length L = n + frac), one fused kernel per
 // iteration.
 //
 // The paper's fast box filter (Sec. 4.3, uniform linear motion) updates a
@@ -18,7 +18,11 @@
 //   3. s = A u, W, q on the TA + L - 1 positions B reads.
 //   4. prefix of (q, W) along.
 //   5. N1 = B q, N2 = B W, D(u), u' = u (N1 + a[D]_+) / (N2 - a[D]_-).
-// A: window [x - floor(L/2), x + floor((L-1)/2)]; B: [x - floor((L-1)/2), x + floor(L/2)].
+// A: window [x - floor(n/2), x + floor((n-1)/2)]; B: [x - floor((n-1)/2), x + floor(n/2)],
+// weight 1/L.  A non-integer length adds the two pixels just outside each
+// window with weight (frac/2)/L (Sec. 4.3): the window sums gain two end
+// terms, read from the u tile (A) or as differences of the (q, W) prefix (B);
+// the halo along and the q/W span grow by one position on each side.
 // Orientation: VERT = false for horizontal motion (along = x), true for
 // vertical motion (along = y).  LDS rows are "lines" of the tile along the
 // blur axis for horizontal motion and image rows for vertical motion, so that
@@ -33,8 +37,10 @@ namespace deblur {
 
 struct BoxTile {
     int along_n, across_n;  // image extent along / across the blur axis
-    int L, aL, bL, hA;      // length, floor((L-1)/2), floor(L/2), halo along
-    int nu, nq;             // tile positions along: u (TA + 2hA), q/W (TA + L - 1)
+    int L, aL, bL, hA;      // integer length n, floor((n-1)/2), floor(n/2), halo along
+    int fr;                 // 1 for a non-integer length (end pixels), else 0
+    float ew, invL;         // end weight frac/2 (relative to the inner weight), 1/(n + frac)
+    int nu, nq;             // tile positions along: u (TA + 2hA), q/W (TA + n - 1 + 2fr)
 };
 
 DEBLUR_DEV double2 operator+(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -196,15 +202,15 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
     }
     __syncthreads();
     prefix_lines<VERT, TA, TC, double>(ps, nu, TC, sums);
-    // 3. s = A u, W, q on positions m = 0..nq-1 (along a0 - aL + m)
-    const float invL = 1.0f / (float)bt.L;
+    // 3. s = A u, W, q on positions m = 0..nq-1 (along a0 - aL - fr + m)
+    const float invL = bt.invL;
     // f is fetched for several positions before any is used
     tile_pass<VERT, TC, 4>(
         nq,
         [&](int c, int m) {
             const int gc = c0 + c;
             if (gc >= bt.across_n) return 0.0f;
-            const int ga = ext_index(a0 - bt.aL + m, bt.along_n, p.bc);
+            const int ga = ext_index(a0 - bt.aL - bt.fr + m, bt.along_n, p.bc);
             const int y = VERT ? ga : gc, x = VERT ? gc : ga;
             return f[(size_t)y * pitch + x];
         },
@@ -215,11 +221,14 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
                 // B reads E(q)(x'): q at the continued position.  Periodic: the
                 // tile holds the wrapped u, so x' itself is used; constant
                 // continuation: q(clamp(x')), i.e. A u at the clamped position.
-                const int xa = a0 - bt.aL + m;
+                const int xa = a0 - bt.aL - bt.fr + m;
                 const int ga = ext_index(xa, bt.along_n, p.bc);
                 const int j = (p.bc == BC_PERIODIC ? xa : ga) - lo;  // tile position of the sample
                 const int hi = j + bt.aL, lo2 = j - bt.bL - 1;          // A window [j - bL, j + aL]
-                const double sum = ps[Lay::at(c, hi, nu, TC)] - (lo2 >= 0 ? ps[Lay::at(c, lo2, nu, TC)] : 0.0);
+                double sum = ps[Lay::at(c, hi, nu, TC)] - (lo2 >= 0 ? ps[Lay::at(c, lo2, nu, TC)] : 0.0);
+                if (bt.fr)   // end pixels j - bL - 1 and j + aL + 1
+                    sum += (double)bt.ew * ((double)us[Lay::at(c + 2, lo2, nu, CU)] +
+                                            (double)us[Lay::at(c + 2, hi + 1, nu, CU)]);
                 const float s = fmaxf((float)fmax(sum, 0.0) * invL, p.s_min);
                 const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
                 qw = make_double2((double)(wt * fmaxf(fv, 0.0f) * rcp(s)), (double)wt);
@@ -234,10 +243,19 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
         if (VERT) { o = i / TC; c = i - o * TC; } else { c = i / TA; o = i - c * TA; }
         const int gc = c0 + c, ga = a0 + o;
         if (gc >= bt.across_n || ga >= bt.along_n) continue;
-        // B window [o, o + L - 1] in q positions
-        const double2 hi = qs[Lay::at(c, o + bt.L - 1, nq, TC)];
-        const double2 lw = o > 0 ? qs[Lay::at(c, o - 1, nq, TC)] : make_double2(0.0, 0.0);
-        const float n1 = (float)fmax(hi.x - lw.x, 0.0) * invL, n2 = (float)fmax(hi.y - lw.y, 0.0) * invL;
+        // B window [o + fr, o + fr + n - 1] in q positions; end pixels o and
+        // o + n + 1 (non-integer length) as differences of the prefix
+        const int w0 = o + bt.fr;
+        const double2 hi = qs[Lay::at(c, w0 + bt.L - 1, nq, TC)];
+        const double2 lw = w0 > 0 ? qs[Lay::at(c, w0 - 1, nq, TC)] : make_double2(0.0, 0.0);
+        double2 sum = hi - lw;
+        if (bt.fr) {
+            const double2 e0 = qs[Lay::at(c, o, nq, TC)] - (o > 0 ? qs[Lay::at(c, o - 1, nq, TC)] : make_double2(0.0, 0.0));
+            const double2 e1 = qs[Lay::at(c, o + bt.L + 1, nq, TC)] - hi;
+            const double ew = (double)bt.ew;
+            sum = sum + make_double2(ew * (e0.x + e1.x), ew * (e0.y + e1.y));
+        }
+        const float n1 = (float)fmax(sum.x, 0.0) * invL, n2 = (float)fmax(sum.y, 0.0) * invL;
         const int j = bt.hA + o;
         const int jm = max(j - 1, jmin), jp = min(j + 1, jmax);
         const float up = us[Lay::at(c + 2, j, nu, CU)];
@@ -270,7 +288,7 @@ inline size_t box_lds_bytes(const BoxTile& bt)
     return fl * 4 + (size_t)TC * (bt.nu + 1) * 8 + ((size_t)TC * (bt.nq + 1) + 256) * 16 + 256 * 8;
 }
 
-__host__ __device__ inline BoxTile make_tile(int H, int W, int L, bool vert, int TA)
+__host__ __device__ inline BoxTile make_tile(int H, int W, int L, float frac, bool vert, int TA)
 {
     BoxTile bt;
     bt.along_n = vert ? H : W;
@@ -278,9 +296,13 @@ __host__ __device__ inline BoxTile make_tile(int H, int W, int L, bool vert, int
     bt.L = L;
     bt.aL = (L - 1) / 2;
     bt.bL = L / 2;
-    bt.hA = L - 1 > 2 ? L - 1 : 2;
+    bt.fr = frac > 0.0f ? 1 : 0;
+    bt.ew = 0.5f * frac;
+    bt.invL = 1.0f / ((float)L + frac);
+    const int h = L - 1 + 2 * bt.fr;
+    bt.hA = h > 2 ? h : 2;
     bt.nu = TA + 2 * bt.hA;
-    bt.nq = TA + L - 1;
+    bt.nq = TA + L - 1 + 2 * bt.fr;
     return bt;
 }
 

@@ -35,9 +35,11 @@ int convert_psf(const deblur_psf* psf, PsfDev* out)
     d.taps = psf->taps;
     if (psf->kind == DEBLUR_PSF_BOX_H || psf->kind == DEBLUR_PSF_BOX_V) {
         if (psf->length < 1) return DEBLUR_EINVAL;
-        const int P = psf->length + (psf->length % 2 == 0 ? 1 : 0);
+        if (!(psf->frac >= 0.0f && psf->frac < 1.0f)) return DEBLUR_EINVAL;   // also rejects NaN
+        const int P = psf->length + (psf->length % 2 == 0 ? 1 : 0) + (psf->frac > 0.0f ? 2 : 0);
         if (P > kMaxTapDim) return DEBLUR_EUNSUPPORTED;
         d.length = psf->length;
+        d.frac = psf->frac;
         d.ph = psf->kind == DEBLUR_PSF_BOX_H ? 1 : P;
         d.pw = psf->kind == DEBLUR_PSF_BOX_H ? P : 1;
     } else if (psf->kind == DEBLUR_PSF_TAPS) {
@@ -45,6 +47,7 @@ int convert_psf(const deblur_psf* psf, PsfDev* out)
             return DEBLUR_EINVAL;
         if (psf->ph > kMaxTapDim || psf->pw > kMaxTapDim) return DEBLUR_EUNSUPPORTED;
         d.length = 0;
+        d.frac = 0.0f;
         d.ph = psf->ph;
         d.pw = psf->pw;
     } else {

@@ -48,7 +48,7 @@ int launch_rrrl_iterate(const float* f, const float* u_in, float* u_out, int H, 
         float* ck = ckpt ? ckpt + (size_t)k * H * pitch : nullptr;
         int s;
         if (use_box) {
-            s = launch_rrrl_box_iter(f, src, dst, ck, H, W, pitch, psf.length, psf.kind == PSF_BOX_V, p, st);
+            s = launch_rrrl_box_iter(f, src, dst, ck, H, W, pitch, psf.length, psf.frac, psf.kind == PSF_BOX_V, p, st);
         } else {
             s = launch_taps_stage1(f, src, qw, H, W, pitch, psf, list, p, p.tile, st);
             if (!s) s = launch_taps_stage2(qw, src, dst, ck, H, W, pitch, psf, list, p, p.tile, st);

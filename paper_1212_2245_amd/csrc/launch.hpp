@@ -70,7 +70,7 @@ int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, 
 // One fused RRRL iteration for a box PSF of length L along x (vert = false)
 // or y (vert = true).
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
-                         bool vert, const IterParams& p, hipStream_t st);
+                         float frac, bool vert, const IterParams& p, hipStream_t st);
 
 // Iteration driver: `iters` iterations u_in -> u_out with ping-pong buffers
 // in the workspace; box kinds use the fused running-sum kernel when use_box.

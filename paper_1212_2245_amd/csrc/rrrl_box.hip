@@ -31,17 +31,17 @@ static void allow_large_lds()
 }
 
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
-                         bool vert, const IterParams& p, hipStream_t st)
+                         float frac, bool vert, const IterParams& p, hipStream_t st)
 {
     allow_large_lds();
     if (!vert) {
-        const BoxTile bt = make_tile(H, W, L, false, BOXH_TA);
+        const BoxTile bt = make_tile(H, W, L, frac, false, BOXH_TA);
         const dim3 g((W + BOXH_TA - 1) / BOXH_TA, (H + BOXH_TC - 1) / BOXH_TC);
         const size_t lds = box_lds_bytes<false, BOXH_TA, BOXH_TC>(bt);
         hipLaunchKernelGGL((rrrl_box_iter<false, BOXH_TA, BOXH_TC>), g, dim3(256), lds, st, u, f, un, ckpt, pitch,
                            bt, p);
     } else {
-        const BoxTile bt = make_tile(H, W, L, true, BOXV_TA);
+        const BoxTile bt = make_tile(H, W, L, frac, true, BOXV_TA);
         const dim3 g((W + BOXV_TC - 1) / BOXV_TC, (H + BOXV_TA - 1) / BOXV_TA);
         const size_t lds = box_lds_bytes<true, BOXV_TA, BOXV_TC>(bt);
         hipLaunchKernelGGL((rrrl_box_iter<true, BOXV_TA, BOXV_TC>), g, dim3(256), lds, st, u, f, un, ckpt, pitch,
@@ -50,10 +50,10 @@ int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt,
     return 0;
 }
 
-size_t box_lds_bytes_for(int H, int W, int L, bool vert)
+size_t box_lds_bytes_for(int H, int W, int L, float frac, bool vert)
 {
-    return vert ? box_lds_bytes<true, BOXV_TA, BOXV_TC>(make_tile(H, W, L, true, BOXV_TA))
-                : box_lds_bytes<false, BOXH_TA, BOXH_TC>(make_tile(H, W, L, false, BOXH_TA));
+    return vert ? box_lds_bytes<true, BOXV_TA, BOXV_TC>(make_tile(H, W, L, frac, true, BOXV_TA))
+                : box_lds_bytes<false, BOXH_TA, BOXH_TC>(make_tile(H, W, L, frac, false, BOXH_TA));
 }
 
 }  // namespace deblur

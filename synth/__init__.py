@@ -72,20 +72,25 @@ def ground_truth(rng: np.random.Generator, H: int, W: int,
 # --------------------------------------------------------------------------
 # point-spread functions (odd-sized arrays, centre at ((Py-1)/2, (Px-1)/2))
 # --------------------------------------------------------------------------
-def box_psf(L: int, axis: str = "h") -> np.ndarray:
-    """Uniform linear motion of integer length L along a coordinate axis.
+def box_psf(L: float, axis: str = "h") -> np.ndarray:
+    """Uniform linear motion of length L >= 1 along a coordinate axis.
 
-    Taps at offsets d in [-floor((L-1)/2), floor(L/2)], weight 1/L each (one
-    extra tap on the + side for even L), stored in an odd-length array of
-    P = L + (L even) entries.
+    n = floor(L) taps at offsets d in [-floor((n-1)/2), floor(n/2)], weight
+    1/L each (one extra tap on the + side for even n), stored in an odd-length
+    array of n + (n even) entries.  A non-integer L adds one tap of weight
+    (frac/2)/L, frac = L - n, just outside each end (two more entries).
     """
-    if L < 1:
+    n = int(math.floor(L))
+    if n < 1:
         raise ValueError("box length must be >= 1")
-    P = L + (1 - L % 2)
+    frac = float(L) - n
+    P = n + (1 - n % 2) + (2 if frac > 0.0 else 0)
     c = (P - 1) // 2
     row = np.zeros(P, dtype=np.float64)
-    lo, hi = -((L - 1) // 2), L // 2
+    lo, hi = -((n - 1) // 2), n // 2
     row[c + lo:c + hi + 1] = 1.0 / L
+    if frac > 0.0:
+        row[c + lo - 1] = row[c + hi + 1] = 0.5 * frac / L
     return row[None, :] if axis == "h" else row[:, None]
 
 

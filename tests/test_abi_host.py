@@ -46,8 +46,8 @@ def test_status_strings(lib):
     assert lib.deblur_version() >= 100
 
 
-def box(L=15, kind=_lib.PSF_BOX_H):
-    return _lib.deblur_psf(kind, L, 0, 0, None)
+def box(L=15, kind=_lib.PSF_BOX_H, frac=0.0):
+    return _lib.deblur_psf(kind, L, 0, 0, None, frac)
 
 
 def taps(ph, pw, ptr=0x60000000):
@@ -75,6 +75,8 @@ def iterate(lib, f=F, ui=U, uo=V, H=64, W=64, pitch=64, psf=None, p=None, ck=Non
 def test_workspace_bytes(lib):
     p = params()
     assert lib.deblur_workspace_bytes(0, 256, 256, 256, ctypes.byref(box()), None) > 0
+    assert lib.deblur_workspace_bytes(1, 256, 256, 256, ctypes.byref(box(14, frac=0.5)), ctypes.byref(p)) > 0
+    assert lib.deblur_workspace_bytes(1, 256, 256, 256, ctypes.byref(box(14, frac=1.5)), ctypes.byref(p)) == 0
     assert lib.deblur_workspace_bytes(0, 256, 256, 256, ctypes.byref(taps(31, 31)), None) > 0
     assert lib.deblur_workspace_bytes(1, 100, 77, 80, ctypes.byref(taps(31, 31)), ctypes.byref(p)) > 0
     assert lib.deblur_workspace_bytes(0, 256, 250, 256, ctypes.byref(box()), None) == 0   # 250 = 2 * 5^3
@@ -92,6 +94,11 @@ def test_wiener_validation(lib):
     assert wiener(lib, K=float("nan")) == E
     assert wiener(lib, floor=0.0) == E
     assert wiener(lib, psf=box(0)) == E
+    assert wiener(lib, psf=box(0, frac=0.5)) == E                # length 0.5 < 1
+    for bad in (-0.25, 1.0, 1.5, float("nan"), float("inf")):
+        assert wiener(lib, psf=box(14, frac=bad)) == E           # fractional part outside [0, 1)
+    assert wiener(lib, psf=box(63, _lib.PSF_BOX_V, frac=0.5)) == W_  # 65 entries: supported
+    assert wiener(lib, psf=box(64, _lib.PSF_BOX_V, frac=0.5)) == U_  # 67 entries: beyond the tap limit
     assert wiener(lib, psf=_lib.deblur_psf(9, 3, 0, 0, None)) == E
     assert wiener(lib, psf=taps(4, 5)) == E                      # even dims
     assert wiener(lib, psf=_lib.deblur_psf(_lib.PSF_TAPS, 0, 3, 3, None)) == E

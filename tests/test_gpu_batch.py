@@ -71,3 +71,26 @@ def test_batch_against_oracle_and_groups():
     assert lat[0] == lat[1] and lat[2] == lat[3] and lat[4] == lat[5]
     assert lat[0] < lat[2] < lat[4]
     plan.close()
+
+
+def test_batch_fractional_boxes():
+    """Boxes of non-integer length in the batched graph: bitwise equal to the
+    single-image calls and within the parity bar of the oracle."""
+    rng = np.random.default_rng(77)
+    specs = [(96, 128, 14.5, "h"), (128, 96, 7.25, "v"), (64, 144, 1.5, "h"), (162, 64, 30.75, "v")]
+    items, want = [], []
+    for H, W, L, axis in specs:
+        h = synth.box_psf(L, axis)
+        f = synth.observe(rng, synth.ground_truth(rng, H, W), h, 2.0).astype(np.float32)
+        p = dbl.Params(alpha=0.003, iters=4)
+        items.append((dev(f), dbl.Psf.box(L, axis), p, 0.01, 1.0))
+        want.append(oracle.wr3l(f, h.astype(np.float32), 0.01, oracle.Params(alpha=0.003), 4))
+    plan = dbl.BatchPlan(items)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for (f, psf, p, K, fl), out, w, spec in zip(items, outs, want, specs):
+        assert torch.equal(out, dbl.wr3l(f, psf, K, p, fl)), spec
+        e = float(np.linalg.norm(out.cpu().numpy() - w) / np.linalg.norm(w))
+        print(f"[parity] batch fractional box {spec}: rel_l2={e:.3e}", flush=True)
+        assert e <= 1e-4
+    plan.close()

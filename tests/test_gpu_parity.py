@@ -56,6 +56,8 @@ WIENER_CASES = [
     ("box_h_15_256", 256, 256, lambda: synth.box_psf(15, "h"), synth.KIND_BOX_H, 15),
     ("box_h_16_192x384", 192, 384, lambda: synth.box_psf(16, "h"), synth.KIND_BOX_H, 16),
     ("box_v_9_128", 128, 128, lambda: synth.box_psf(9, "v"), synth.KIND_BOX_V, 9),
+    ("box_h_12.5_256", 256, 256, lambda: synth.box_psf(12.5, "h"), synth.KIND_BOX_H, 12.5),
+    ("box_v_7.25_128x96", 128, 96, lambda: synth.box_psf(7.25, "v"), synth.KIND_BOX_V, 7.25),
     ("line31_256", 256, 256, lambda: synth.line_psf(31, 0.7), synth.KIND_TAPS, 0),
     ("line17_96x144", 96, 144, lambda: synth.line_psf(17, 2.0), synth.KIND_TAPS, 0),
     ("gauss31_512", 512, 512, lambda: synth.gauss_mixture_psf(synth.rng_for(2), 31), synth.KIND_TAPS, 0),
@@ -115,6 +117,8 @@ def iterate_case(H, W, h, kind, L, iters, alpha=0.003, robust=True, bc=oracle.BC
 ITER_CASES = [
     ("box_h15_256_k10", 256, 256, lambda: synth.box_psf(15, "h"), synth.KIND_BOX_H, 15, 10, {}),
     ("box_v8_ragged", 77, 129, lambda: synth.box_psf(8, "v"), synth.KIND_BOX_V, 8, 5, {}),
+    ("box_h14.5_256_k10", 256, 256, lambda: synth.box_psf(14.5, "h"), synth.KIND_BOX_H, 14.5, 10, {}),
+    ("box_v8.3_ragged", 77, 129, lambda: synth.box_psf(8.3, "v"), synth.KIND_BOX_V, 8.3, 5, {}),
     ("line31_192_k20", 192, 192, lambda: synth.line_psf(31, 0.4), synth.KIND_TAPS, 0, 20, dict(alpha=0.002)),
     ("line9_ragged_periodic", 100, 70, lambda: synth.line_psf(9, 2.5), synth.KIND_TAPS, 0, 6,
      dict(bc=oracle.BC_PERIODIC)),
@@ -262,40 +266,42 @@ def test_stage_parity(robust, bc):
     assert report("stage2 u'", out.cpu().numpy(), want_u) <= 1e-5
 
 
-@pytest.mark.parametrize("L", [1, 2, 3, 4, 8, 15, 16, 27, 40, 41, 64])
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 8, 15, 16, 27, 40, 41, 64, 1.5, 2.25, 8.75, 15.5, 40.9, 63.5])
 @pytest.mark.parametrize("axis", ["h", "v"])
 @pytest.mark.parametrize("bc", [oracle.BC_REPLICATE, oracle.BC_PERIODIC])
 def test_box_running_sum_lengths(L, axis, bc):
-    """Running-sum box path (every length, odd and even, both continuations)
-    against the oracle's direct summation."""
+    """Running-sum box path (every length, odd and even, integer and with
+    fractional end pixels, both continuations) against the oracle's direct
+    summation."""
     H, W = (70, 150) if axis == "h" else (150, 70)
     if bc == oracle.BC_PERIODIC and L > min(H, W):
         pytest.skip("PSF longer than the image")
     h = synth.box_psf(L, axis).astype(np.float32)
     kind = synth.KIND_BOX_H if axis == "h" else synth.KIND_BOX_V
-    got, want = iterate_case(H, W, h, kind, L, 3, alpha=0.003, bc=bc, seed=L)
+    got, want = iterate_case(H, W, h, kind, L, 3, alpha=0.003, bc=bc, seed=int(L * 4))
     assert report(f"box {axis} L={L} bc={bc}", got, want) <= RTOL_ITER
 
 
-def test_box_running_sum_matches_stencil_path():
+@pytest.mark.parametrize("L,axis", [(21, "v"), (20.5, "v"), (9.75, "h")])
+def test_box_running_sum_matches_stencil_path(L, axis):
     """The same box PSF through the running-sum kernel and the tap stencil."""
     rng = np.random.default_rng(41)
     H, W = 200, 256
-    f = synth.observe(rng, synth.ground_truth(rng, H, W), synth.box_psf(21, "v"), 2.0)
+    f = synth.observe(rng, synth.ground_truth(rng, H, W), synth.box_psf(L, axis), 2.0)
     u0 = np.maximum(f, 1.0)
     outs = []
     for conv in (dbl.CONV_RUNSUM, dbl.CONV_STENCIL):
         out = torch.empty((H, W), dtype=torch.float32, device="cuda")
-        dbl.deblur_rrrl_iterate(dev(f), dev(u0), out, dbl.Psf.box(21, "v"), dbl.Params(iters=8, conv=conv))
+        dbl.deblur_rrrl_iterate(dev(f), dev(u0), out, dbl.Psf.box(L, axis), dbl.Params(iters=8, conv=conv))
         outs.append(out.cpu().numpy())
-    assert report("runsum vs stencil", outs[0], outs[1]) <= 1e-5
+    assert report(f"runsum vs stencil L={L}", outs[0], outs[1]) <= 1e-5
 
 
-@pytest.mark.parametrize("L,bc", [(15, 0), (8, 1), (33, 0)])
+@pytest.mark.parametrize("L,bc", [(15, 0), (8, 1), (33, 0), (14.5, 0), (7.25, 1)])
 def test_box_vertical_is_transposed_horizontal(L, bc):
     """Box-V on f equals the transpose of box-H on f^T (separate kernels for
     the two axes; agreement to rounding)."""
-    rng = np.random.default_rng(L)
+    rng = np.random.default_rng(int(L * 4))
     H, W = 144, 200
     f = synth.observe(rng, synth.ground_truth(rng, H, W), synth.box_psf(L, "v"), 2.0)
     u0 = np.maximum(f, 1.0)

@@ -59,6 +59,47 @@ def test_box_blur_is_window_mean(L, axis):
     np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-11)
 
 
+@pytest.mark.parametrize("L", [1.5, 2.25, 4.5, 7.75, 14.5, 15.25, 40.9])
+@pytest.mark.parametrize("axis", ["h", "v"])
+def test_fractional_box_blur(L, axis):
+    """Uniform motion of non-integer length L = n + frac (Sec. 4.3): the
+    integer window of n pixels with weight 1/L plus one pixel of weight
+    (frac/2)/L at each end (brute force); and successive window values differ
+    by two additions and two subtractions, as the paper states for its box
+    filter update."""
+    r = rng(int(L * 8))
+    v = r.uniform(0, 255, size=(7, 80) if axis == "h" else (80, 7))
+    h = synth.box_psf(L, axis)
+    got = oracle.blur(v, h, oracle.BC_REPLICATE)
+    vv = v if axis == "h" else v.T
+    gg = got if axis == "h" else got.T
+    n, frac = int(math.floor(L)), L - math.floor(L)
+    e = 0.5 * frac
+    N = vv.shape[1]
+    cl = lambda j: min(max(j, 0), N - 1)  # noqa: E731
+    for x in range(N):
+        inner = sum(vv[:, cl(j)] for j in range(x - n // 2, x + (n - 1) // 2 + 1))
+        ends = vv[:, cl(x - n // 2 - 1)] + vv[:, cl(x + (n - 1) // 2 + 1)]
+        np.testing.assert_allclose(gg[:, x], (inner + e * ends) / L, rtol=1e-13, atol=1e-11)
+    lo, hi = n // 2 + 2, N - (n - 1) // 2 - 3   # interior: no clamping
+    for x in range(lo, hi):
+        upd = ((1 - e) * vv[:, x + 1 + (n - 1) // 2] + e * vv[:, x + 2 + (n - 1) // 2]
+               - (1 - e) * vv[:, x - n // 2] - e * vv[:, x - n // 2 - 1]) / L
+        np.testing.assert_allclose(gg[:, x + 1] - gg[:, x], upd, rtol=1e-9, atol=1e-9)
+
+
+def test_fractional_box_limits():
+    """frac -> 0 gives the integer box (continuity in L); weights sum to one."""
+    for n in (1, 2, 5, 16, 31):
+        a = synth.box_psf(n + 1e-12, "h")[0]
+        b = np.pad(synth.box_psf(n, "h")[0], 1)
+        np.testing.assert_allclose(a, b, atol=1e-12)
+        for frac in (0.1, 0.5, 0.9):
+            h = synth.box_psf(n + frac, "v")
+            assert h.shape == (n + (1 - n % 2) + 2, 1)
+            assert abs(h.sum() - 1.0) < 1e-14
+
+
 def test_blur_preserves_mass_periodic():
     """Normalised PSF: periodic blur preserves total mass (sum_d h(d) = 1)."""
     r = rng(5)
