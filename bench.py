@@ -289,6 +289,14 @@ def bench_configs(dev, args):
                              "mpx_it_per_s": round(H * W / it_us, 1),
                              "hbm_frac": round((8 * H * W + 12 * H * W * c.iters) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
                              "parity": e}
+    # the same image with a box of non-integer length (fractional end pixels)
+    # and the integer length next to it, iterations only
+    it = {}
+    for L in (c.length, c.length - 0.5):
+        pL = dbl.Psf.box(L, "h")
+        wsL = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, pL, p), dtype=torch.uint8, device=dev)
+        it[str(L)] = round(_events_ms(lambda: dbl.deblur_rrrl_iterate(f, f, u, pL, p, ws=wsL), 50) * 1e3 / c.iters, 2)
+    out["config0_box256"]["iteration_us_by_length"] = it
 
     # config 2: 2048^2, 31x31 Gaussian mixture, 30 iterations
     c = synth.make_case(2)

@@ -88,7 +88,8 @@ typedef struct {
 typedef struct {
     float alpha;     /* regulariser weight alpha >= 0 (eq. (9)) */
     float eps_data;  /* epsilon > 0 of the data penaliser Phi(z) = sqrt(z + eps^2) (Sec. 2.3) */
-    float eps_tv;    /* epsilon > 0 of the TV penaliser Psi (Sec. 2.3) */
+    float eps_tv;    /* > 0: epsilon of the TV penaliser Psi (Sec. 2.3), or the contrast
+                        parameter lambda of the Perona-Malik penaliser (psi = 1) */
     float s_min;     /* > 0: the blurred iterate is bounded below by s_min before dividing */
     int32_t iters;   /* number of RRRL iterations, >= 0 */
     int32_t robust;  /* 1: W = Phi'(r_f(u*h)) (eq. (10)); 0: W = 1 (plain RL data term) */
@@ -97,6 +98,9 @@ typedef struct {
     int32_t tile;    /* tile shape of the stencil kernels: 0 = library default for the image
                         size, 1..deblur_tile_variants() = an explicit shape (an autotuner's
                         choice); all shapes give bitwise-identical results */
+    int32_t psi;     /* regulariser Psi (Sec. 2.3): 0 = regularised TV, Psi(z) = sqrt(z + eps^2);
+                        1 = Perona-Malik, Psi(z) = (lambda^2/2) ln(1 + z/lambda^2), non-convex in
+                        |grad u| (diffusivity lambda^2 / (lambda^2 + z)); else DEBLUR_EINVAL */
 } deblur_params;
 
 /* Text for a status code (static storage). */
@@ -125,6 +129,17 @@ size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, c
  * division is done in FP64, the transforms in FP32. */
 int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
                   double K, float pos_floor, void* ws, size_t ws_bytes, void* stream);
+
+/* Starting image for RRRL without the Wiener step (Sec. 2.3; the RRRL columns
+ * of Table 1 start from an image the paper does not state):
+ *   DEBLUR_START_FLAT:     u0 = max(mean(f), pos_floor) at every pixel (the mean
+ *                          summed in FP64 in a fixed order: deterministic);
+ *   DEBLUR_START_OBSERVED: u0 = max(f, pos_floor).
+ * f, u0: device H x W, pitch `pitch`, must not overlap; pos_floor > 0 (the
+ * multiplicative update needs a positive start, Sec. 3.2).  No workspace. */
+typedef enum { DEBLUR_START_FLAT = 0, DEBLUR_START_OBSERVED = 1 } deblur_start;
+int deblur_rrrl_start(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, int32_t mode,
+                      float pos_floor, void* stream);
 
 /* p->iters RRRL iterations (Sec. 2.3 eq. (9)-(12)) from u_in:
  *   s = max(A u, s_min),  W = Phi'(r_f(s)) (or 1),  q = W max(f,0) / s,

@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("eps_data", ctypes.c_double),
                 ("eps_tv", ctypes.c_double), ("s_min", ctypes.c_double),
-                ("robust", ctypes.c_int), ("bc", ctypes.c_int)]
+                ("robust", ctypes.c_int), ("bc", ctypes.c_int), ("psi", ctypes.c_int)]
 
 
 _lib = None
@@ -62,7 +62,7 @@ def _load():
             fn.restype = None
         lib.orc_rf.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.orc_rf.restype = ctypes.c_double
-        lib.orc_tv.argtypes = [dp, i, i, ctypes.c_double, dp, i]
+        lib.orc_tv.argtypes = [dp, i, i, ctypes.c_double, i, dp, i]
         lib.orc_tv.restype = None
         lib.orc_rrrl_step.argtypes = [dp, dp, dp, i, i, dp, i, i, ctypes.POINTER(_Params), dp, i]
         lib.orc_rrrl_step.restype = None
@@ -96,10 +96,11 @@ class Params:
     s_min: float = 1e-12
     robust: bool = True
     bc: int = BC_REPLICATE
+    psi: int = 0   # regulariser: 0 regularised TV, 1 Perona-Malik (lambda = eps_tv)
 
     def c(self) -> _Params:
         return _Params(self.alpha, self.eps_data, self.eps_tv, self.s_min,
-                       int(bool(self.robust)), int(self.bc))
+                       int(bool(self.robust)), int(self.bc), int(self.psi))
 
 
 # ---------------------------------------------------------------- operators
@@ -126,11 +127,12 @@ def rf(f: float, s: float) -> float:
     return _load().orc_rf(float(f), float(s))
 
 
-def tv(u, eps_tv: float, threads: int | None = None) -> np.ndarray:
-    """D(u) = div(Psi'(|grad u|^2) grad u) by central differences (eq. (11), Sec. 4.1)."""
+def tv(u, eps_tv: float, threads: int | None = None, psi: int = 0) -> np.ndarray:
+    """D(u) = div(Psi'(|grad u|^2) grad u) by central differences (eq. (11), Sec. 4.1);
+    psi = 1 selects the non-convex Perona-Malik penaliser with lambda = eps_tv."""
     u = _f64(u)
     out = np.empty_like(u)
-    _load().orc_tv(_ptr(u), u.shape[0], u.shape[1], float(eps_tv), _ptr(out),
+    _load().orc_tv(_ptr(u), u.shape[0], u.shape[1], float(eps_tv), int(psi), _ptr(out),
                    threads or default_threads())
     return out
 
@@ -196,6 +198,16 @@ def wiener_init(f, h, K: float, pos_floor: float) -> np.ndarray:
     """WR3L initialisation (Sec. 3.2): Wiener output with values below the
     positive floor replaced, u^0 = max(u_pre, pos_floor)."""
     return np.maximum(wiener(f, h, K), pos_floor)
+
+
+def rrrl_start(f, mode: int, pos_floor: float) -> np.ndarray:
+    """Starting image of RRRL without the Wiener step (the paper does not
+    state one): mode 0 (flat) max(mean f, pos_floor) everywhere, mode 1
+    (observed) max(f, pos_floor); positive as the multiplicative update needs."""
+    f = _f64(f)
+    if mode == 0:
+        return np.full_like(f, max(float(f.mean()), pos_floor))
+    return np.maximum(f, pos_floor)
 
 
 def wr3l(f, h, K: float, p: Params, iters: int, pos_floor: float = 1.0,

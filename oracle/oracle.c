@@ -93,6 +93,22 @@ static double pen_deriv(double z, double eps)
     return 1.0 / sqrt(z + eps * eps);
 }
 
+/* Diffusivity g = 2 Psi'(z) of the regulariser (same scaling as pen_deriv):
+ *   psi = 0: regularised TV, Psi(z) = sqrt(z + eps^2)      -> (z + eps^2)^(-1/2)
+ *   psi = 1: a penaliser non-convex in |grad u| (Sec. 2.3, "non-convex
+ *            w.r.t. s"), Perona-Malik Psi(z) = (lam^2/2) ln(1 + z/lam^2)
+ *            -> lam^2 / (lam^2 + z), lam = eps. */
+static double diffusivity(double z, double eps, int psi)
+{
+    return psi ? eps * eps / (eps * eps + z) : pen_deriv(z, eps);
+}
+
+/* -2 dg/dz expressed through g: g^3 (TV) or 2 g^2 / lam^2 (Perona-Malik). */
+static double diffusivity_slope(double g, double eps, int psi)
+{
+    return psi ? 2.0 * g * g / (eps * eps) : g * g * g;
+}
+
 /* Nonlinear diffusion term D(u) = div(Psi'(|grad u|^2) grad u), eq. (11),
  * by central differences (Sec. 4.1):
  *   g(p)  = psi(gx^2 + gy^2), gx = (u(y,x+1) - u(y,x-1))/2,
@@ -101,7 +117,7 @@ static double pen_deriv(double z, double eps)
  *           (g(p) + g(n))/2 * (u(n) - u(p))
  * (fluxes between pixel centres with averaged diffusivity, zero flux across
  * the image border). */
-void orc_tv(const double* u, int H, int W, double eps_t, double* D, int nthreads)
+void orc_tv(const double* u, int H, int W, double eps_t, int psi, double* D, int nthreads)
 {
     double* g = (double*)malloc(sizeof(double) * (size_t)H * W);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
@@ -111,7 +127,7 @@ void orc_tv(const double* u, int H, int W, double eps_t, double* D, int nthreads
             const int ym = ext(y - 1, H, ORC_BC_REPLICATE), yp = ext(y + 1, H, ORC_BC_REPLICATE);
             const double gx = (u[(size_t)y * W + xp] - u[(size_t)y * W + xm]) / 2.0;
             const double gy = (u[(size_t)yp * W + x] - u[(size_t)ym * W + x]) / 2.0;
-            g[(size_t)y * W + x] = pen_deriv(gx * gx + gy * gy, eps_t);
+            g[(size_t)y * W + x] = diffusivity(gx * gx + gy * gy, eps_t, psi);
         }
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (int y = 0; y < H; ++y)
@@ -161,7 +177,7 @@ void orc_rrrl_step(const double* f, const double* u, double* u_next, int H, int 
     }
     orc_corr(q, H, W, h, Py, Px, p->bc, N1, nthreads);
     orc_corr(Wt, H, W, h, Py, Px, p->bc, N2, nthreads);
-    orc_tv(u, H, W, p->eps_tv, D, nthreads);
+    orc_tv(u, H, W, p->eps_tv, p->psi, D, nthreads);
     for (size_t i = 0; i < n; ++i) {
         const double dp = D[i] > 0.0 ? D[i] : 0.0;
         const double dm = D[i] < 0.0 ? D[i] : 0.0;
@@ -257,9 +273,9 @@ void orc_rrrl_step_adjoint(const double* f, const double* u, int H, int W, const
             const int ym = ext(y - 1, H, ORC_BC_REPLICATE), yp = ext(y + 1, H, ORC_BC_REPLICATE);
             const double gx = (u[(size_t)y * W + xp] - u[(size_t)y * W + xm]) / 2.0;
             const double gy = (u[(size_t)yp * W + x] - u[(size_t)ym * W + x]) / 2.0;
-            g[(size_t)y * W + x] = pen_deriv(gx * gx + gy * gy, p->eps_tv);
+            g[(size_t)y * W + x] = diffusivity(gx * gx + gy * gy, p->eps_tv, p->psi);
         }
-    orc_tv(u, H, W, p->eps_tv, D, nthreads);
+    orc_tv(u, H, W, p->eps_tv, p->psi, D, nthreads);
 
     /* update u' = u * Num / Den */
     for (size_t i = 0; i < n; ++i) {
@@ -334,7 +350,7 @@ void orc_rrrl_step_adjoint(const double* f, const double* u, int H, int W, const
             const int ym = ext(y - 1, H, ORC_BC_REPLICATE), yp = ext(y + 1, H, ORC_BC_REPLICATE);
             const double gx = (u[(size_t)y * W + xp] - u[(size_t)y * W + xm]) / 2.0;
             const double gy = (u[(size_t)yp * W + x] - u[(size_t)ym * W + x]) / 2.0;
-            const double g3 = g[pp] * g[pp] * g[pp];
+            const double g3 = diffusivity_slope(g[pp], p->eps_tv, p->psi);
             const double dgx = dg[pp] * (-g3 * gx), dgy = dg[pp] * (-g3 * gy);
             du[(size_t)y * W + xp] += 0.5 * dgx;
             du[(size_t)y * W + xm] -= 0.5 * dgx;

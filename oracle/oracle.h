@@ -19,6 +19,7 @@ typedef struct {
     double s_min;     /* lower guard on the blurred iterate u*h */
     int robust;       /* 1: W = Phi'(r_f(u*h)); 0: W = 1 (plain RL data term) */
     int bc;           /* ORC_BC_* for the convolutions A and B */
+    int psi;          /* regulariser: 0 regularised TV, 1 Perona-Malik (non-convex), lambda = eps_tv */
 } orc_params;
 
 void orc_blur(const double* v, int H, int W, const double* h, int Py, int Px,
@@ -26,7 +27,7 @@ void orc_blur(const double* v, int H, int W, const double* h, int Py, int Px,
 void orc_corr(const double* v, int H, int W, const double* h, int Py, int Px,
               int bc, double* out, int nthreads);
 double orc_rf(double f, double s);
-void orc_tv(const double* u, int H, int W, double eps_t, double* D, int nthreads);
+void orc_tv(const double* u, int H, int W, double eps_t, int psi, double* D, int nthreads);
 void orc_rrrl_step(const double* f, const double* u, double* u_next, int H, int W,
                    const double* h, int Py, int Px, const orc_params* p,
                    double* parts, int nthreads);

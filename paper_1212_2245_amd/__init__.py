@@ -18,11 +18,12 @@ import torch
 
 from . import _lib
 from ._lib import (BC_PERIODIC, BC_REPLICATE, CONV_AUTO, CONV_FFT, CONV_RUNSUM, CONV_STENCIL, PSF_BOX_H, PSF_BOX_V,
-                   PSF_TAPS, DeblurError)
+                   PSF_TAPS, PSI_PERONA_MALIK, PSI_TV, START_FLAT, START_OBSERVED, DeblurError)
 
 __all__ = ["Psf", "Params", "deblur_workspace_bytes", "deblur_wiener", "deblur_rrrl_iterate", "wr3l",
            "DeblurError", "BC_REPLICATE", "BC_PERIODIC", "PSF_BOX_H", "PSF_BOX_V", "PSF_TAPS",
-           "CONV_AUTO", "CONV_RUNSUM", "CONV_STENCIL", "CONV_FFT", "library_path"]
+           "CONV_AUTO", "CONV_RUNSUM", "CONV_STENCIL", "CONV_FFT", "PSI_TV", "PSI_PERONA_MALIK", "START_FLAT",
+           "START_OBSERVED", "deblur_rrrl_start", "rrrl", "library_path"]
 
 
 def library_path() -> str:
@@ -77,10 +78,12 @@ class Params:
     boundary: int = BC_REPLICATE
     conv: int = CONV_AUTO
     tile: int = 0
+    psi: int = PSI_TV   # regulariser: PSI_TV, or PSI_PERONA_MALIK (non-convex, lambda = eps_tv)
 
     def c(self) -> _lib.deblur_params:
         return _lib.deblur_params(self.alpha, self.eps_data, self.eps_tv, self.s_min, int(self.iters),
-                                  int(bool(self.robust)), int(self.boundary), int(self.conv), int(self.tile))
+                                  int(bool(self.robust)), int(self.boundary), int(self.conv), int(self.tile),
+                                  int(self.psi))
 
 
 def _stream(t: torch.Tensor) -> int:
@@ -126,6 +129,29 @@ def deblur_wiener(f: torch.Tensor, u0: torch.Tensor, psf: Psf, K: float = 0.01, 
                            float(pos_floor), wst.data_ptr(), wst.numel(), _stream(f))
     _lib.check(st, "deblur_wiener")
     return u0
+
+
+def deblur_rrrl_start(f: torch.Tensor, u0: torch.Tensor, mode: int = _lib.START_FLAT,
+                      pos_floor: float = 1.0) -> torch.Tensor:
+    """Starting image of RRRL without the Wiener step: START_FLAT gives
+    max(mean(f), pos_floor) everywhere, START_OBSERVED max(f, pos_floor)."""
+    lib = _lib.load()
+    H, W, pitch = _image(f, "f")
+    _same_layout((H, W, pitch), _image(u0, "u0"), "f", "u0")
+    st = lib.deblur_rrrl_start(f.data_ptr(), u0.data_ptr(), H, W, pitch, int(mode), float(pos_floor), _stream(f))
+    _lib.check(st, "deblur_rrrl_start")
+    return u0
+
+
+def rrrl(f: torch.Tensor, psf: Psf, params: Params | None = None, start: int = _lib.START_FLAT,
+         pos_floor: float = 1.0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """RRRL alone (Sec. 2.3, the RRRL columns of Table 1): a flat or observed
+    start, then params.iters iterations.  With params.alpha = 0 and
+    robust = False this is Richardson-Lucy."""
+    params = params or Params()
+    u = out if out is not None else torch.empty_like(f)
+    deblur_rrrl_start(f, u, start, pos_floor)
+    return deblur_rrrl_iterate(f, u, u, psf, params)
 
 
 def deblur_rrrl_iterate(f: torch.Tensor, u_in: torch.Tensor, u_out: torch.Tensor, psf: Psf, params: Params,

@@ -17,6 +17,8 @@ DEBLUR_EDEVICE = -4
 PSF_BOX_H, PSF_BOX_V, PSF_TAPS = 0, 1, 2
 BC_REPLICATE, BC_PERIODIC = 0, 1
 CONV_AUTO, CONV_RUNSUM, CONV_STENCIL, CONV_FFT = 0, 1, 2, 3
+PSI_TV, PSI_PERONA_MALIK = 0, 1
+START_FLAT, START_OBSERVED = 0, 1
 
 OP_WIENER, OP_ITERATE, OP_BACKWARD, OP_BACKWARD_WIENER = 0, 1, 2, 3
 
@@ -29,7 +31,8 @@ class deblur_psf(ctypes.Structure):
 class deblur_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_float), ("eps_data", ctypes.c_float), ("eps_tv", ctypes.c_float),
                 ("s_min", ctypes.c_float), ("iters", ctypes.c_int32), ("robust", ctypes.c_int32),
-                ("boundary", ctypes.c_int32), ("conv", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("boundary", ctypes.c_int32), ("conv", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("psi", ctypes.c_int32)]
 
 
 class deblur_batch_item(ctypes.Structure):
@@ -48,6 +51,7 @@ SIGNATURES = [
     ("deblur_workspace_bytes", _SZ, [_I32, _I32, _I32, _I32, _PSF, _PAR]),
     ("deblur_wiener", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _PSF, ctypes.c_double, ctypes.c_float,
                                      _VP, _SZ, _VP]),
+    ("deblur_rrrl_start", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _I32, ctypes.c_float, _VP]),
     ("deblur_rrrl_iterate", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP, _SZ, _VP]),
     ("deblur_rrrl_backward", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _I32, ctypes.c_double,
                                             ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),

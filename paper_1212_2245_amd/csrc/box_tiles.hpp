@@ -198,7 +198,7 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
         const int jm = max(j - 1, jmin), jp = min(j + 1, jmax), jc = min(max(j, jmin), jmax);
         const float da = 0.5f * (us[Lay::at(c + 1, jp, nu, CU)] - us[Lay::at(c + 1, jm, nu, CU)]);
         const float dc = 0.5f * (us[Lay::at(c + 2, jc, nu, CU)] - us[Lay::at(c, jc, nu, CU)]);
-        gs[VERT ? k * (TC + 2) + c : c * (GA + 1) + k] = pen_deriv(da * da + dc * dc, p.eps_t2);
+        gs[VERT ? k * (TC + 2) + c : c * (GA + 1) + k] = tv_diffusivity(da * da + dc * dc, p);
     }
     __syncthreads();
     prefix_lines<VERT, TA, TC, double>(ps, nu, TC, sums);

@@ -94,6 +94,7 @@ int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, co
     if (!(p->eps_tv > 0.0f) || !std::isfinite(p->eps_tv)) return DEBLUR_EINVAL;
     if (!(p->s_min > 0.0f) || !std::isfinite(p->s_min)) return DEBLUR_EINVAL;
     if (p->iters < 0 || (p->robust != 0 && p->robust != 1)) return DEBLUR_EINVAL;
+    if (p->psi != 0 && p->psi != 1) return DEBLUR_EINVAL;
     if (p->boundary != DEBLUR_BC_REPLICATE && p->boundary != DEBLUR_BC_PERIODIC) return DEBLUR_EINVAL;
     if (p->conv < DEBLUR_CONV_AUTO || p->conv > DEBLUR_CONV_FFT) return DEBLUR_EINVAL;
     if (p->conv == DEBLUR_CONV_FFT) {
@@ -134,6 +135,7 @@ IterParams iter_params(const deblur_params* p)
     q.eps_t2 = p->eps_tv * p->eps_tv;
     q.s_min = p->s_min;
     q.robust = p->robust;
+    q.psi = p->psi;
     q.bc = p->boundary;
     q.tile = p->tile;
     return q;
@@ -197,6 +199,21 @@ int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch
     if (!ws || ws_bytes < need) return DEBLUR_EWORKSPACE;
     return launch_wiener(f, u0, H, W, pitch, d, K, pos_floor, ws, wiener_rowwise(d),
                          reinterpret_cast<hipStream_t>(stream));
+}
+
+int deblur_rrrl_start(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, int32_t mode,
+                      float pos_floor, void* stream)
+{
+    if (!f || !u0) return DEBLUR_EINVAL;
+    int s = check_image(H, W, pitch);
+    if (s) return s;
+    if (mode != DEBLUR_START_FLAT && mode != DEBLUR_START_OBSERVED) return DEBLUR_EINVAL;
+    if (!(pos_floor > 0.0f) || !std::isfinite(pos_floor)) return DEBLUR_EINVAL;
+    const size_t img = (size_t)H * pitch * sizeof(float);
+    if (overlaps(f, img, u0, img)) return DEBLUR_EINVAL;
+    return launch_rrrl_start(f, u0, H, W, pitch, mode, pos_floor, reinterpret_cast<hipStream_t>(stream)) == 0
+               ? DEBLUR_OK
+               : DEBLUR_EDEVICE;
 }
 
 int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t H, int32_t W, int32_t pitch,

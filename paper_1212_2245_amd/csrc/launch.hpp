@@ -15,7 +15,23 @@ struct IterParams {
     float alpha, eps_d2, eps_t2, s_min;
     int robust, bc;
     int tile;  // tile-shape variant (0 = default)
+    int psi;   // regulariser: 0 regularised TV, 1 Perona-Malik (lambda^2 = eps_t2)
 };
+
+// Diffusivity g = 2 Psi'(z), z = |grad u|^2, in the scaling of the data
+// weight (the factor 1/2 cancels in the quotient of eq. (9)): regularised TV
+// (z + eps^2)^(-1/2), or the non-convex Perona-Malik penaliser
+// (Sec. 2.3) lambda^2 / (lambda^2 + z).
+DEBLUR_DEV float tv_diffusivity(float z, const IterParams& p)
+{
+    return p.psi ? p.eps_t2 * rcp(p.eps_t2 + z) : pen_deriv(z, p.eps_t2);
+}
+
+// -2 dg/dz through g (backward): g^3 (TV) or 2 g^2 / lambda^2 (Perona-Malik).
+DEBLUR_DEV float tv_slope(float g, const IterParams& p)
+{
+    return p.psi ? 2.0f * g * g * rcp(p.eps_t2) : g * g * g;
+}
 
 // Compiled PSF ("tap list" buffer), built on the device by launch_compile_taps:
 //   bytes [0, 256)        header: int count of non-zero taps T, int count of
@@ -69,6 +85,10 @@ int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, 
 
 // One fused RRRL iteration for a box PSF of length L along x (vert = false)
 // or y (vert = true).
+// Starting image of RRRL without the Wiener step: mode 0 flat (mean of f),
+// 1 the observed image; both floored at pos_floor.
+int launch_rrrl_start(const float* f, float* u0, int H, int W, int pitch, int mode, float pos_floor, hipStream_t st);
+
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
                          float frac, bool vert, const IterParams& p, hipStream_t st);
 

@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
         const int a = idx / GW, b = idx - a * GW;
         const float gx = 0.5f * (ut[(a + 1) * UW + b + 2] - ut[(a + 1) * UW + b]);
         const float gy = 0.5f * (ut[(a + 2) * UW + b + 1] - ut[a * UW + b + 1]);
-        gt[idx] = pen_deriv(gx * gx + gy * gy, p.eps_t2);
+        gt[idx] = tv_diffusivity(gx * gx + gy * gy, p);
     }
     const int tx = tid & 63, ty = tid >> 6;
     float2 nn[R];   // (N3, N2) = B (e, W)
@@ -261,11 +261,11 @@ __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int
         const float up = ut[c], cp = ct[c];
         const float gx = 0.5f * (ut[c + 1] - ut[c - 1]);
         const float gy = 0.5f * (ut[c + UW] - ut[c - UW]);
-        const float g = pen_deriv(gx * gx + gy * gy, p.eps_t2);
+        const float g = tv_diffusivity(gx * gx + gy * gy, p);
         // dL/dg(p) = sum_n (u_n - u_p)(c_p - c_n)/2 (neighbours outside read u_p: 0)
         const float dg = 0.5f * ((ut[c - UW] - up) * (cp - ct[c - UW]) + (ut[c + UW] - up) * (cp - ct[c + UW])
                                  + (ut[c - 1] - up) * (cp - ct[c - 1]) + (ut[c + 1] - up) * (cp - ct[c + 1]));
-        const float g3 = -g * g * g * dg;
+        const float g3 = -tv_slope(g, p) * dg;
         gt[idx] = g;
         dgx[idx] = g3 * gx;
         dgy[idx] = g3 * gy;

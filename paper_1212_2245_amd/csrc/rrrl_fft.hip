@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(256) fftp_update(const float* __restrict__ u, 
         const int a = idx / GW, b = idx - a * GW;
         const float gx = 0.5f * (ut[(a + 1) * UW + b + 2] - ut[(a + 1) * UW + b]);
         const float gy = 0.5f * (ut[(a + 2) * UW + b + 1] - ut[a * UW + b + 1]);
-        gt[idx] = pen_deriv(gx * gx + gy * gy, p.eps_t2);
+        gt[idx] = tv_diffusivity(gx * gx + gy * gy, p);
     }
     __syncthreads();
     const int tx = tid & 63, ty = tid >> 6;

@@ -323,7 +323,7 @@ DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ 
         const int a = idx / GW, b = idx - a * GW;
         const float gx = 0.5f * (ut[(a + 1) * UW + b + 2] - ut[(a + 1) * UW + b]);
         const float gy = 0.5f * (ut[(a + 2) * UW + b + 1] - ut[a * UW + b + 1]);
-        gt[idx] = pen_deriv(gx * gx + gy * gy, p.eps_t2);
+        gt[idx] = tv_diffusivity(gx * gx + gy * gy, p);
     }
     const int tx = tid & 63, ty = tid >> 6;
     float n1[R], n2[R];

@@ -212,3 +212,19 @@ def test_gpu_finite_difference_in_f():
     print(f"[grad] GPU FD {fd:.6e}  oracle FD {fd64:.6e}  GPU adjoint {gv:.6e}", flush=True)
     assert abs(fd - fd64) <= 2e-3 * abs(fd64)
     assert abs(fd - gv) <= 2e-2 * abs(gv)
+
+
+def test_backward_perona_malik():
+    """The non-convex Perona-Malik regulariser (lambda = 20 grey levels) in the
+    backward pass: derivative of the diffusivity g = lambda^2/(lambda^2 + z)."""
+    H, W = 48, 64
+    rng = np.random.default_rng(99)
+    g = synth.ground_truth(rng, H, W)
+    h = synth.line_psf(9, 1.2).astype(np.float32)
+    f = synth.observe(rng, g, h.astype(np.float64), 2.0)
+    K, alpha, iters = 0.01, 0.02, 3
+    p = oracle.Params(alpha=alpha, eps_tv=20.0, psi=1)
+    (df, dh, da, lam0), floor = oracle_floor(f, h, g.astype(np.float32), K, p, iters, True)
+    gp = dbl.Params(alpha=alpha, iters=iters, eps_tv=20.0, psi=dbl.PSI_PERONA_MALIK)
+    got = gpu_grads(f, dbl.Psf.from_taps(dev(h)), g.astype(np.float32), K, gp, True)
+    check("perona_malik", got, df, dh, da, lam0, floor)

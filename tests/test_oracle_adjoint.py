@@ -30,11 +30,13 @@ def t_blur(v, h, bc, adjoint=False):
     return F.conv2d(vp, k[None, None])[0, 0]
 
 
-def t_tv(u, eps):
+def t_tv(u, eps, psi=0):
     up = F.pad(u[None, None], (1, 1, 1, 1), mode="replicate")[0, 0]
     gx = 0.5 * (up[1:-1, 2:] - up[1:-1, :-2])
     gy = 0.5 * (up[2:, 1:-1] - up[:-2, 1:-1])
-    g = 1.0 / torch.sqrt(gx * gx + gy * gy + eps * eps)
+    z = gx * gx + gy * gy
+    # regularised TV, or the non-convex Perona-Malik penaliser (lambda = eps)
+    g = eps * eps / (eps * eps + z) if psi else 1.0 / torch.sqrt(z + eps * eps)
     D = torch.zeros_like(u)
     # vertical fluxes between rows y and y+1, horizontal between x and x+1
     fy = 0.5 * (g[:-1] + g[1:]) * (u[1:] - u[:-1])
@@ -57,7 +59,7 @@ def t_step(f, u, h, alpha, p: oracle.Params):
     q = W * torch.where(fpos, f, torch.zeros_like(f)) / s
     N1 = t_blur(q, h, p.bc, adjoint=True)
     N2 = t_blur(W, h, p.bc, adjoint=True)
-    D = t_tv(u, p.eps_tv)
+    D = t_tv(u, p.eps_tv, p.psi)
     return u * (N1 + alpha * torch.clamp(D, min=0.0)) / (N2 - alpha * torch.clamp(D, max=0.0))
 
 
@@ -77,19 +79,25 @@ def t_wiener_init(f, h, K, floor):
 
 
 # ----------------------------------------------------------------- tests
-CASES = [(oracle.BC_REPLICATE, True), (oracle.BC_PERIODIC, True), (oracle.BC_REPLICATE, False)]
+CASES = [(oracle.BC_REPLICATE, True, 0), (oracle.BC_PERIODIC, True, 0), (oracle.BC_REPLICATE, False, 0),
+         (oracle.BC_REPLICATE, True, 1)]
 
 
-@pytest.mark.parametrize("bc,robust", CASES)
-def test_step_adjoint_matches_torch_autograd(bc, robust):
-    r = rng(bc * 2 + robust)
+def case_params(alpha, robust, bc, psi):
+    # Perona-Malik with lambda = 20 grey levels: both diffusion regimes occur
+    return oracle.Params(alpha=alpha, robust=robust, bc=bc, psi=psi, eps_tv=20.0 if psi else 0.1)
+
+
+@pytest.mark.parametrize("bc,robust,psi", CASES)
+def test_step_adjoint_matches_torch_autograd(bc, robust, psi):
+    r = rng(bc * 2 + robust + 5 * psi)
     H, W = 11, 13
     h = synth.random_psf(r, 5, 3, density=0.7)
     f = r.uniform(0, 255, (H, W))
     f[2, 3:6] = 0.0
     u = r.uniform(3, 255, (H, W))
     lam = r.normal(size=(H, W))
-    p = oracle.Params(alpha=0.07, robust=robust, bc=bc)
+    p = case_params(0.07, robust, bc, psi)
     du, df, dh, da = oracle.rrrl_step_adjoint(f, u, h, p, lam)
 
     tf, tu, th = (torch.tensor(x, requires_grad=True) for x in (f, u, h))
@@ -103,22 +111,22 @@ def test_step_adjoint_matches_torch_autograd(bc, robust):
     assert abs(da - ta.grad.item()) <= 1e-9 * abs(da) + 1e-12
 
 
-@pytest.mark.parametrize("bc,robust", CASES)
-def test_step_adjoint_finite_differences(bc, robust):
+@pytest.mark.parametrize("bc,robust,psi", CASES)
+def test_step_adjoint_finite_differences(bc, robust, psi):
     """Central differences of the oracle forward along random directions, for
     u, f (directions on pixels with f >= 1), every tap (zero or not) and alpha."""
-    r = rng(10 + bc * 2 + robust)
+    r = rng(10 + bc * 2 + robust + 5 * psi)
     H, W = 10, 12
     h = synth.line_psf(5, 0.6)
     f = r.uniform(0, 255, (H, W))
     f[0, :4] = 0.0
     u = r.uniform(3, 255, (H, W))
     lam = r.normal(size=(H, W))
-    p = oracle.Params(alpha=0.05, robust=robust, bc=bc)
+    p = case_params(0.05, robust, bc, psi)
     du, df, dh, da = oracle.rrrl_step_adjoint(f, u, h, p, lam)
 
     def L(ff=f, uu=u, hh=h, a=0.05):
-        q = oracle.Params(alpha=a, robust=robust, bc=bc)
+        q = case_params(a, robust, bc, psi)
         return float((oracle.rrrl_step(ff, uu, hh, q) * lam).sum())
 
     e = 1e-6

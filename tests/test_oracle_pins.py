@@ -152,6 +152,32 @@ def test_tv_hand_worked_profile():
                                rtol=1e-14, atol=1e-14)
 
 
+def test_perona_malik_hand_worked_profile():
+    """Non-convex Perona-Malik regulariser (lambda = 2) on a hand-worked 1x5
+    profile; as a row and as a column."""
+    rows = np.loadtxt(os.path.join(GOLD, "tv_perona_malik_1x5.txt"))
+    np.testing.assert_allclose(oracle.tv(rows[:, 0][None, :], 2.0, psi=1)[0], rows[:, 1], rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(oracle.tv(rows[:, 0][:, None], 2.0, psi=1)[:, 0], rows[:, 1], rtol=1e-14,
+                               atol=1e-14)
+
+
+def test_perona_malik_limits():
+    """lambda -> infinity: diffusivity 1, D = the zero-flux 5-point Laplacian;
+    small lambda: edges (|grad u| >> lambda) stop diffusing; fluxes still
+    telescope to zero."""
+    u = rng(18).uniform(0, 255, size=(13, 17))
+    np.testing.assert_allclose(oracle.tv(u, 1e9, psi=1), ndimage.laplace(u, mode="nearest"), rtol=1e-9, atol=1e-7)
+    step = np.zeros((6, 12))
+    step[:, 6:] = 100.0
+    D = oracle.tv(step, 1.0, psi=1)
+    # only the two columns at the jump have a flux: (g + g)/2 * 100 with g = 1/(1 + 50^2)
+    g = 1.0 / (1.0 + 50.0 ** 2)
+    np.testing.assert_allclose(D[:, 5], g * 100.0, rtol=1e-12)
+    np.testing.assert_allclose(D[:, 6], -g * 100.0, rtol=1e-12)
+    assert np.all(D[:, :5] == 0.0) and np.all(D[:, 7:] == 0.0)
+    assert abs(oracle.tv(u, 30.0, psi=1).sum()) < 1e-9 * np.abs(u).sum()
+
+
 def test_tv_constant_diffusivity_is_neumann_laplacian():
     """With Psi' constant (eps_tv huge), eps_tv * D is the 5-point Laplacian
     with reflecting (zero-flux) boundary: scipy.ndimage.laplace, mode nearest."""
