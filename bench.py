@@ -486,6 +486,21 @@ def main():
         "wiener_ms": round(ms_wiener, 5),
         "iteration_us": round((ms_step - ms_wiener) * 1e3 / iters, 3),
     }
+    # the same iterations with r_f through the lookup table of Sec. 4.1
+    # (speed only; its accuracy cost is measured by the parity tests)
+    p_lut = dbl.Params(alpha=case.alpha, iters=iters, tile=tile, rf_lut=True)
+    ws_l = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, psf, p_lut), dtype=torch.uint8, device=dev)
+    us_it = {}
+    u_it = torch.empty_like(u)
+    for name, pp, wsx in (("exact", params, ws_i), ("lookup", p_lut, ws_l)):
+        dbl.deblur_rrrl_iterate(f, u, u_it, psf, pp, ws=wsx)
+        ev0.record()
+        for _ in range(max(1, args.kernel_reps // 4)):
+            dbl.deblur_rrrl_iterate(f, u, u_it, psf, pp, ws=wsx)
+        ev1.record()
+        torch.cuda.synchronize()
+        us_it[name] = round(ev0.elapsed_time(ev1) / max(1, args.kernel_reps // 4) * 1e3 / iters, 3)
+    out["rf_iteration_us"] = us_it
 
     if not args.no_batched:
         print(f"[bench] batched workload: {args.batch_images} images", file=sys.stderr, flush=True)

@@ -101,6 +101,11 @@ typedef struct {
     int32_t psi;     /* regulariser Psi (Sec. 2.3): 0 = regularised TV, Psi(z) = sqrt(z + eps^2);
                         1 = Perona-Malik, Psi(z) = (lambda^2/2) ln(1 + z/lambda^2), non-convex in
                         |grad u| (diffusivity lambda^2 / (lambda^2 + z)); else DEBLUR_EINVAL */
+    int32_t rf_lut;  /* 0: exact r_f (eq. (7)); 1: the lookup mode of Sec. 4.1, r_f(s) = f r_1(s/f)
+                        with r_1(x) = x - 1 - ln x tabulated at x = k/64 up to 65, linear
+                        interpolation, the tangent at 65 beyond.  The first call with rf_lut = 1 on a
+                        device allocates and uploads the 16 KB table (keep that call out of graph
+                        capture); the backward pass rejects it (DEBLUR_EUNSUPPORTED). */
 } deblur_params;
 
 /* Text for a status code (static storage). */

@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("eps_data", ctypes.c_double),
                 ("eps_tv", ctypes.c_double), ("s_min", ctypes.c_double),
-                ("robust", ctypes.c_int), ("bc", ctypes.c_int), ("psi", ctypes.c_int)]
+                ("robust", ctypes.c_int), ("bc", ctypes.c_int), ("psi", ctypes.c_int), ("rf_lut", ctypes.c_int)]
 
 
 _lib = None
@@ -62,6 +62,8 @@ def _load():
             fn.restype = None
         lib.orc_rf.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.orc_rf.restype = ctypes.c_double
+        lib.orc_rf_lut.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_rf_lut.restype = ctypes.c_double
         lib.orc_tv.argtypes = [dp, i, i, ctypes.c_double, i, dp, i]
         lib.orc_tv.restype = None
         lib.orc_rrrl_step.argtypes = [dp, dp, dp, i, i, dp, i, i, ctypes.POINTER(_Params), dp, i]
@@ -97,10 +99,11 @@ class Params:
     robust: bool = True
     bc: int = BC_REPLICATE
     psi: int = 0   # regulariser: 0 regularised TV, 1 Perona-Malik (lambda = eps_tv)
+    rf_lut: bool = False   # r_f by the lookup of Sec. 4.1 (forward only)
 
     def c(self) -> _Params:
         return _Params(self.alpha, self.eps_data, self.eps_tv, self.s_min,
-                       int(bool(self.robust)), int(self.bc), int(self.psi))
+                       int(bool(self.robust)), int(self.bc), int(self.psi), int(bool(self.rf_lut)))
 
 
 # ---------------------------------------------------------------- operators
@@ -125,6 +128,12 @@ def corr(v, h, bc: int = BC_REPLICATE, threads: int | None = None) -> np.ndarray
 def rf(f: float, s: float) -> float:
     """Information divergence r_f(s) = s - f - f ln(s/f) (eq. (7)); r_0(s) = s."""
     return _load().orc_rf(float(f), float(s))
+
+
+def rf_lut(f: float, s: float) -> float:
+    """r_f(s) by the lookup of Sec. 4.1 (r_1 sampled at k/64 up to 65, linear
+    interpolation, tangent beyond 65)."""
+    return _load().orc_rf_lut(float(f), float(s))
 
 
 def tv(u, eps_tv: float, threads: int | None = None, psi: int = 0) -> np.ndarray:

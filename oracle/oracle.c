@@ -85,6 +85,25 @@ double orc_rf(double f, double s)
     return s - f - f * log(s / f);
 }
 
+/* The lookup mode of Sec. 4.1: r_1(x) = x - 1 - ln x known at the samples
+ * x_k = k/64, k = 1..65*64, linearly interpolated between them; below the
+ * first sample the first sample; beyond 65 the tangent of r_1 at 65; and
+ * r_f(s) = f r_1(s/f) (r_0(s) = s). */
+static double r1_exact(double x) { return x - 1.0 - log(x); }
+
+double orc_rf_lut(double f, double s)
+{
+    if (f <= 0.0) return s;
+    const double x = s / f;
+    if (x > 65.0) return f * (r1_exact(65.0) + (1.0 - 1.0 / 65.0) * (x - 65.0));
+    double t = x * 64.0;
+    if (t < 1.0) t = 1.0;
+    int k = (int)t;
+    if (k > 65 * 64 - 1) k = 65 * 64 - 1;
+    const double a = r1_exact(k / 64.0), b = r1_exact((k + 1) / 64.0);
+    return f * (a + (t - k) * (b - a));
+}
+
 /* Diffusivity of the regularised L1 / TV penaliser, up to the constant
  * factor 1/2 that cancels in the quotient of eq. (9):
  *   phi(z) = (z + eps^2)^(-1/2). */
@@ -168,7 +187,7 @@ void orc_rrrl_step(const double* f, const double* u, double* u_next, int H, int 
         const double si = s[i] > p->s_min ? s[i] : p->s_min;
         s[i] = si;
         if (p->robust) {
-            const double r = orc_rf(f[i], si);
+            const double r = p->rf_lut ? orc_rf_lut(f[i], si) : orc_rf(f[i], si);
             Wt[i] = pen_deriv(r > 0.0 ? r : 0.0, p->eps_data);
         } else {
             Wt[i] = 1.0;

@@ -20,6 +20,7 @@ typedef struct {
     int robust;       /* 1: W = Phi'(r_f(u*h)); 0: W = 1 (plain RL data term) */
     int bc;           /* ORC_BC_* for the convolutions A and B */
     int psi;          /* regulariser: 0 regularised TV, 1 Perona-Malik (non-convex), lambda = eps_tv */
+    int rf_lut;       /* 1: r_f through the lookup of Sec. 4.1 (orc_rf_lut); forward only */
 } orc_params;
 
 void orc_blur(const double* v, int H, int W, const double* h, int Py, int Px,
@@ -27,6 +28,7 @@ void orc_blur(const double* v, int H, int W, const double* h, int Py, int Px,
 void orc_corr(const double* v, int H, int W, const double* h, int Py, int Px,
               int bc, double* out, int nthreads);
 double orc_rf(double f, double s);
+double orc_rf_lut(double f, double s);
 void orc_tv(const double* u, int H, int W, double eps_t, int psi, double* D, int nthreads);
 void orc_rrrl_step(const double* f, const double* u, double* u_next, int H, int W,
                    const double* h, int Py, int Px, const orc_params* p,

@@ -79,11 +79,12 @@ class Params:
     conv: int = CONV_AUTO
     tile: int = 0
     psi: int = PSI_TV   # regulariser: PSI_TV, or PSI_PERONA_MALIK (non-convex, lambda = eps_tv)
+    rf_lut: bool = False  # r_f through the lookup table of Sec. 4.1 instead of exactly
 
     def c(self) -> _lib.deblur_params:
         return _lib.deblur_params(self.alpha, self.eps_data, self.eps_tv, self.s_min, int(self.iters),
                                   int(bool(self.robust)), int(self.boundary), int(self.conv), int(self.tile),
-                                  int(self.psi))
+                                  int(self.psi), int(bool(self.rf_lut)))
 
 
 def _stream(t: torch.Tensor) -> int:

@@ -32,7 +32,7 @@ class deblur_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_float), ("eps_data", ctypes.c_float), ("eps_tv", ctypes.c_float),
                 ("s_min", ctypes.c_float), ("iters", ctypes.c_int32), ("robust", ctypes.c_int32),
                 ("boundary", ctypes.c_int32), ("conv", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("psi", ctypes.c_int32)]
+                ("psi", ctypes.c_int32), ("rf_lut", ctypes.c_int32)]
 
 
 class deblur_batch_item(ctypes.Structure):

@@ -230,7 +230,7 @@ DEBLUR_DEV void box_iter_tile(unsigned char* __restrict__ smem_raw, const float*
                     sum += (double)bt.ew * ((double)us[Lay::at(c + 2, lo2, nu, CU)] +
                                             (double)us[Lay::at(c + 2, hi + 1, nu, CU)]);
                 const float s = fmaxf((float)fmax(sum, 0.0) * invL, p.s_min);
-                const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
+                const float wt = p.robust ? pen_deriv(fmaxf(rf_eval(fv, s, p), 0.0f), p.eps_d2) : 1.0f;
                 qw = make_double2((double)(wt * fmaxf(fv, 0.0f) * rcp(s)), (double)wt);
             }
             qs[Lay::at(c, m, nq, TC)] = qw;

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "deblur.h"
@@ -83,6 +84,34 @@ int check_wiener(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, Psf
     return DEBLUR_OK;
 }
 
+// Device table of r_1 for the lookup mode of r_f, built on first use on
+// each device (host FP64, rounded once) and kept until the process ends.
+const float* r1_table()
+{
+    static std::mutex mu;
+    static std::vector<float*> tables;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)tables.size() <= dev) tables.resize(dev + 1, nullptr);
+    if (tables[dev]) return tables[dev];
+    std::vector<float> h(RF_LUT_WORDS);
+    for (int k = 1; k <= RF_LUT_N; ++k) {
+        const double x = (double)k / RF_LUT_PER_UNIT;
+        h[k] = (float)((x - 1.0) - std::log(x));
+    }
+    h[0] = h[1];
+    h[RF_LUT_N + 1] = (float)(1.0 - 1.0 / 65.0);
+    float* d = nullptr;
+    if (hipMalloc(&d, sizeof(float) * RF_LUT_WORDS) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, h.data(), sizeof(float) * RF_LUT_WORDS, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return nullptr;
+    }
+    tables[dev] = d;
+    return d;
+}
+
 int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, const deblur_params* p, PsfDev* d)
 {
     int s = check_image(H, W, pitch);
@@ -95,6 +124,8 @@ int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, co
     if (!(p->s_min > 0.0f) || !std::isfinite(p->s_min)) return DEBLUR_EINVAL;
     if (p->iters < 0 || (p->robust != 0 && p->robust != 1)) return DEBLUR_EINVAL;
     if (p->psi != 0 && p->psi != 1) return DEBLUR_EINVAL;
+    if (p->rf_lut != 0 && p->rf_lut != 1) return DEBLUR_EINVAL;
+    if (p->rf_lut && !r1_table()) return DEBLUR_EDEVICE;
     if (p->boundary != DEBLUR_BC_REPLICATE && p->boundary != DEBLUR_BC_PERIODIC) return DEBLUR_EINVAL;
     if (p->conv < DEBLUR_CONV_AUTO || p->conv > DEBLUR_CONV_FFT) return DEBLUR_EINVAL;
     if (p->conv == DEBLUR_CONV_FFT) {
@@ -117,6 +148,7 @@ int check_backward(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, c
 {
     int s = check_iterate(H, W, pitch, psf, p, d);
     if (s) return s;
+    if (p->rf_lut) return DEBLUR_EUNSUPPORTED;   // the adjoint differentiates the exact r_f
     if (through_wiener && (!is_2a3b(H) || !is_2a3b(W) || H > kMaxFft || W > kMaxFft)) return DEBLUR_EUNSUPPORTED;
     if (through_wiener && (d->ph > H || d->pw > W)) return DEBLUR_EINVAL;
     return DEBLUR_OK;
@@ -136,6 +168,7 @@ IterParams iter_params(const deblur_params* p)
     q.s_min = p->s_min;
     q.robust = p->robust;
     q.psi = p->psi;
+    q.r1_lut = p->rf_lut ? r1_table() : nullptr;
     q.bc = p->boundary;
     q.tile = p->tile;
     return q;

@@ -16,7 +16,37 @@ struct IterParams {
     int robust, bc;
     int tile;  // tile-shape variant (0 = default)
     int psi;   // regulariser: 0 regularised TV, 1 Perona-Malik (lambda^2 = eps_t2)
+    const float* r1_lut;   // device table of r_1 (lookup mode of r_f), or null: exact r_f
 };
+
+// Lookup mode of the information divergence (Sec. 4.1): r_1(x) = x - 1 - ln x
+// tabulated at x = k / RF_LUT_PER_UNIT, k = 1 .. RF_LUT_N (x up to 65), read
+// with linear interpolation; r_f(s) = f r_1(s/f); beyond 65 the tangent of
+// r_1 at 65; below the first sample the first sample.  Table layout:
+// [0] unused (= [1]), [1..RF_LUT_N] samples, [RF_LUT_N + 1] the slope
+// r_1'(65) = 1 - 1/65.
+constexpr int RF_LUT_PER_UNIT = 64;
+constexpr int RF_LUT_N = 65 * RF_LUT_PER_UNIT;
+constexpr int RF_LUT_WORDS = RF_LUT_N + 2;
+
+DEBLUR_DEV float rf_lookup(float f, float s, const float* __restrict__ lut)
+{
+    if (!(f > 0.0f)) return s;   // r_0(s) = s
+    const float x = s * rcp(f);
+    const float t = fminf(fmaxf(x * (float)RF_LUT_PER_UNIT, 1.0f), (float)RF_LUT_N);
+    const int k = min((int)t, RF_LUT_N - 1);
+    const float a = lut[k], b = lut[k + 1];
+    float r1 = fmaf(t - (float)k, b - a, a);
+    if (x > 65.0f) r1 = fmaf(x - 65.0f, lut[RF_LUT_N + 1], lut[RF_LUT_N]);
+    return f * r1;
+}
+
+// r_f(s) (eq. (7)) as the iteration's data weight uses it: exact, or the
+// lookup mode.
+DEBLUR_DEV float rf_eval(float f, float s, const IterParams& p)
+{
+    return p.r1_lut ? rf_lookup(f, s, p.r1_lut) : info_div(f, s);
+}
 
 // Diffusivity g = 2 Psi'(z), z = |grad u|^2, in the scaling of the data
 // weight (the factor 1/2 cancels in the quotient of eq. (9)): regularised TV

@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) fftp_rows_inv_weights(const float2* __res
             if (y >= H) break;
             const float s = fmaxf(h == 0 ? z.x * inv : -z.y * inv, p.s_min);
             const float fv = f[(size_t)y * pitch + x];
-            const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
+            const float wt = p.robust ? pen_deriv(fmaxf(rf_eval(fv, s, p), 0.0f), p.eps_d2) : 1.0f;
             qo[(size_t)y * W + x] = wt * fmaxf(fv, 0.0f) * rcp(s);
             wo[(size_t)y * W + x] = wt;
         }

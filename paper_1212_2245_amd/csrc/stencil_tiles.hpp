@@ -248,7 +248,7 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, float* __restrict__ pk, co
         if (s_out) s_out[(size_t)y * W + x] = acc[i];   // unclamped A u (backward pass)
         const float s = fmaxf(acc[i], p.s_min);
         const float fv = fr[i];
-        const float wt = p.robust ? pen_deriv(fmaxf(info_div(fv, s), 0.0f), p.eps_d2) : 1.0f;
+        const float wt = p.robust ? pen_deriv(fmaxf(rf_eval(fv, s, p), 0.0f), p.eps_d2) : 1.0f;
         const float fp = fmaxf(fv, 0.0f);
         const float q = (s_out ? wt * (fp - s) : wt * fp) * rcp(s);
         qw[(size_t)y * W + x] = make_float2(q, wt);

@@ -56,7 +56,7 @@ def taps(ph, pw, ptr=0x60000000):
 
 def params(**kw):
     d = dict(alpha=0.003, eps_data=0.1, eps_tv=0.1, s_min=1e-12, iters=3, robust=1, boundary=0, conv=0, tile=0,
-             psi=0)
+             psi=0, rf_lut=0)
     d.update(kw)
     return _lib.deblur_params(*[d[k] for k, _ in _lib.deblur_params._fields_])
 
@@ -129,6 +129,7 @@ def test_iterate_validation(lib):
     assert iterate(lib, p=params(psi=2)) == E
     assert iterate(lib, p=params(psi=-1)) == E
     assert iterate(lib, p=params(psi=1)) == W_                      # Perona-Malik: valid
+    assert iterate(lib, p=params(rf_lut=2)) == E
     assert iterate(lib, p=params(boundary=5)) == E
     assert iterate(lib, p=params(conv=9)) == E
     assert iterate(lib, p=params(tile=-1)) == E

@@ -97,3 +97,40 @@ def test_perona_malik_differs_from_tv():
             outs[alpha, psi] = dbl.rrrl(f, psf, dbl.Params(alpha=alpha, iters=4, psi=psi, eps_tv=10.0))
     assert torch.equal(outs[0.0, 0], outs[0.0, 1])
     assert not torch.equal(outs[0.05, 0], outs[0.05, 1])
+
+
+@pytest.mark.parametrize("name,H,W,mk,kind,L,kw", [
+    ("lut_line17_stencil", 96, 128, lambda: synth.line_psf(17, 0.8), synth.KIND_TAPS, 0, {}),
+    ("lut_box_v13", 128, 80, lambda: synth.box_psf(13, "v"), synth.KIND_BOX_V, 13, {}),
+    ("lut_line9_fft", 96, 96, lambda: synth.line_psf(9, 2.4), synth.KIND_TAPS, 0,
+     dict(bc=oracle.BC_PERIODIC, conv=dbl.CONV_FFT)),
+])
+def test_rf_lookup_mode_parity(name, H, W, mk, kind, L, kw):
+    """r_f by the lookup table of Sec. 4.1 on every iteration path, against the
+    oracle's lookup mode; and the lookup's own cost: its distance from the
+    exact iteration, on the GPU and in the oracle."""
+    h = mk().astype(np.float32)
+    f = observed(H, W, h, H * 3 + W)
+    bc = kw.get("bc", oracle.BC_REPLICATE)
+    u0 = oracle.rrrl_start(f, 1, 1.0)
+    want_lut = oracle.rrrl(f, u0, h, oracle.Params(alpha=0.003, bc=bc, rf_lut=True), 10)
+    want_exact = oracle.rrrl(f, u0, h, oracle.Params(alpha=0.003, bc=bc), 10)
+    psf = dbl.Psf.from_taps(dev(h)) if kind == synth.KIND_TAPS else dbl.Psf.box(L, "v")
+    outs = {}
+    for lut in (True, False):
+        gp = dbl.Params(alpha=0.003, iters=10, boundary=bc, conv=kw.get("conv", dbl.CONV_AUTO), rf_lut=lut)
+        outs[lut] = dbl.rrrl(dev(f), psf, gp, start=dbl.START_OBSERVED).cpu().numpy()
+    assert report(name + " lut vs oracle lut", outs[True], want_lut) <= RTOL_ITER
+    cost_oracle = rel_l2(want_lut, want_exact)
+    cost_gpu = report(name + " lut vs exact (gpu)", outs[True], outs[False])
+    print(f"[lut] {name}: lookup vs exact: oracle {cost_oracle:.3e}, gpu {cost_gpu:.3e}", flush=True)
+    assert cost_oracle > 0.0
+    assert abs(cost_gpu - cost_oracle) <= 0.1 * cost_oracle + 2 * RTOL_ITER
+
+
+def test_rf_lookup_mode_rejected_by_backward():
+    h = synth.line_psf(5, 0.3).astype(np.float32)
+    f = dev(observed(32, 32, h, 1))
+    ck = torch.empty((2, 32, 32), dtype=torch.float32, device="cuda")
+    with pytest.raises(dbl.DeblurError):
+        dbl.deblur_rrrl_backward(f, ck, f, dbl.Psf.from_taps(dev(h)), dbl.Params(iters=2, rf_lut=True))

@@ -142,6 +142,29 @@ def test_rf_closed_forms():
     assert math.isclose(oracle.rf(f, f + e), e * e / (2 * f), rel_tol=1e-4)
 
 
+def test_rf_lookup_mode():
+    """The lookup mode of Sec. 4.1 against the exact r_f: equal at the table
+    samples s = f k/64; between samples above it by at most the linear
+    interpolation bound f h^2/8 max r_1'' (h = 1/64, r_1''(x) = 1/x^2, convex);
+    beyond x = 65 the tangent, below r_f by at most f (x-65)^2 / (2 65^2);
+    r_0(s) = s."""
+    r = rng(17)
+    for f in (0.5, 7.0, 100.0, 240.0):
+        for k in (1, 2, 63, 64, 65, 100, 1000, 4159, 4160):
+            s = f * k / 64.0
+            assert math.isclose(oracle.rf_lut(f, s), oracle.rf(f, s), rel_tol=1e-12, abs_tol=1e-12 * f)
+        for x in r.uniform(1.0 / 64.0, 65.0, 300):
+            lo = math.floor(x * 64.0) / 64.0
+            bound = f * (1.0 / 64.0) ** 2 / 8.0 / lo ** 2
+            d = oracle.rf_lut(f, f * x) - oracle.rf(f, f * x)
+            assert -1e-12 * f <= d <= bound * (1 + 1e-9) + 1e-12 * f, (f, x, d, bound)
+        for x in (65.5, 80.0, 200.0):
+            d = oracle.rf(f, f * x) - oracle.rf_lut(f, f * x)
+            assert -1e-9 * f <= d <= f * (x - 65.0) ** 2 / (2 * 65.0 ** 2) * (1 + 1e-9)
+    assert oracle.rf_lut(0.0, 3.5) == 3.5
+    assert math.isclose(oracle.rf_lut(10.0, 0.01), 10.0 * (1 / 64 - 1 - math.log(1 / 64)), rel_tol=1e-12)
+
+
 # ----------------------------------------------------------------------- TV
 def test_tv_hand_worked_profile():
     rows = np.loadtxt(os.path.join(GOLD, "tv_profile_1x5.txt"))
