@@ -78,6 +78,8 @@ def parse_args():
     ap.add_argument("--summarize-counters", nargs="+", metavar="DB_OR_OUT",
                     help="rocprofv3 --pmc databases of the stencil stages, then the output markdown file")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
+    ap.add_argument("--quality", action="store_true",
+                    help="print the SNR table of the methods on the Table 1 stand-ins (one JSON line) and exit")
     return ap.parse_args()
 
 
@@ -374,6 +376,17 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
+        return
+    if args.quality:
+        import synth
+        from paper_1212_2245_amd import quality
+        rows = {}
+        for sc in synth.table1_scenarios(256, 0):
+            rows[sc["name"]] = {
+                "full": {k: round(v, 2) for k, v in quality.method_snrs(sc["f"], sc["g"], sc["psf"], sc["K"]).items()},
+                "interior24": {k: round(v, 2) for k, v in
+                               quality.method_snrs(sc["f"], sc["g"], sc["psf"], sc["K"], border=24).items()}}
+        print(json.dumps({"snr_db": rows, "data": "synthetic stand-ins, 256x256, seed 0"}), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -147,6 +147,64 @@ def gauss_mixture_psf(rng: np.random.Generator, P: int = 31, n: int = 3) -> np.n
     return h / h.sum()
 
 
+def camera_shake_psf(rng: np.random.Generator, P: int = 25, steps: int = 60, step_len: float = 0.45) -> np.ndarray:
+    """Irregular "camera-shake" PSF (the kind of Fig. 1(a)): a random walk with
+    momentum from the centre (`steps` steps of `step_len` px, heading turning
+    by N(0, 0.35) rad per step), recentred on its mean, each visited point
+    bilinearly splatted with equal weight; PxP array, normalised to 1."""
+    pts = np.zeros((steps + 1, 2))
+    heading = rng.uniform(0.0, 2.0 * math.pi)
+    for k in range(steps):
+        heading += rng.normal(0.0, 0.35)
+        pts[k + 1] = pts[k] + step_len * np.array([math.sin(heading), math.cos(heading)])
+    pts -= pts.mean(axis=0)
+    R = (P - 1) // 2
+    if np.abs(pts).max() > R - 1:
+        pts *= (R - 1) / np.abs(pts).max()
+    h = np.zeros((P, P))
+    for py, px in pts:
+        iy, ix = math.floor(py), math.floor(px)
+        fy, fx = py - iy, px - ix
+        for oy, wy in ((0, 1.0 - fy), (1, fy)):
+            for ox, wx in ((0, 1.0 - fx), (1, fx)):
+                h[R + iy + oy, R + ix + ox] += wy * wx
+    return h / h.sum()
+
+
+def add_impulse_noise(rng: np.random.Generator, f: np.ndarray, density: float) -> np.ndarray:
+    """Replaces a fraction `density` of the pixels by values uniform on [0, 255]
+    (the impulse noise of Fig. 2(i)); float32."""
+    out = np.array(f, dtype=np.float32, copy=True)
+    mask = rng.uniform(size=f.shape) < density
+    out[mask] = rng.uniform(0.0, 255.0, size=int(mask.sum())).astype(np.float32)
+    return out
+
+
+def table1_scenarios(size: int = 256, seed: int = 0) -> list[dict]:
+    """Synthetic stand-ins for the four test images of Table 1 (the
+    cameraman image is not available): one seeded ground truth with texture,
+    degraded as (a) camera shake, no noise beyond 8-bit quantisation;
+    (b) 21 px motion at 45 degrees; (c) (a) plus Gaussian noise sigma 5;
+    (d) (a) with 15 % impulse noise.  Blur with constant continuation (no
+    inverse crime).  Each: name, f, g, psf, Wiener K of Table 1."""
+    rng = rng_for(10, seed)
+    g = ground_truth(rng, size, size, texture_std=10.0)
+    shake = camera_shake_psf(rng)
+    motion = line_psf(21, math.pi / 4)
+    blurred = np.round(np.clip(blur_replicate(g, shake), 0.0, 255.0))
+    out = [
+        dict(name="camera_shake", f=blurred.astype(np.float32), psf=shake, K=0.006),
+        dict(name="motion21_45deg", f=np.round(np.clip(blur_replicate(g, motion), 0.0, 255.0)).astype(np.float32),
+             psf=motion, K=0.006),
+        dict(name="shake_gauss5", f=np.clip(blurred + rng.normal(0.0, 5.0, size=g.shape), 0.0, 255.0)
+             .astype(np.float32), psf=shake, K=0.06),
+        dict(name="shake_impulse15", f=add_impulse_noise(rng, blurred, 0.15), psf=shake, K=0.16),
+    ]
+    for d in out:
+        d["g"] = g.astype(np.float32)
+    return out
+
+
 # --------------------------------------------------------------------------
 # forward model used to make observations (data generation only)
 # --------------------------------------------------------------------------
