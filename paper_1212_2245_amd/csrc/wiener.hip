@@ -366,6 +366,11 @@ __global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict_
 }
 
 // ------------------------------------------------------------ host launchers
+// Rows (pairs) and columns per workgroup of the transform passes: as few as
+// keep a workgroup's threads busy, so that small images still spread over
+// many workgroups (the passes are latency bound at these sizes).
+static int row_batch(int W) { return W >= 256 ? 1 : 256 / W; }
+static int col_batch(int H) { return H >= 512 ? 1 : (512 / H > 8 ? 8 : 512 / H); }
 size_t wiener_ws_bytes(int H, int W, bool rowwise)
 {
     if (rowwise) return (size_t)W * sizeof(float2);
@@ -380,7 +385,7 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
         float2* M = reinterpret_cast<float2*>(ws);
         hipLaunchKernelGGL(wiener_mult_1d, dim3((W + 255) / 256), dim3(256), 0, st, psf, W, K, M);
         const int pairs = (H + 1) / 2;
-        const int nb = W >= 1024 ? 1 : 1024 / W;
+        const int nb = row_batch(W);
         const size_t lds = (size_t)(W + 2 * nb * W) * sizeof(float2);
         hipLaunchKernelGGL(wiener_rows_fused, dim3((pairs + nb - 1) / nb), dim3(256), lds, st, f, u, H, W,
                            pitch, nb, make_plan(W), (const float2*)M, pos_floor);
@@ -390,11 +395,11 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
         float2* S = M + (size_t)H * Wh;
         mult_2d_launch(psf, H, W, K, M, nullptr, st);
         const int pairs = (H + 1) / 2;
-        const int nb = W >= 1024 ? 1 : 1024 / W;
+        const int nb = row_batch(W);
         const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(float2);
         hipLaunchKernelGGL(wiener_rows_fwd, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st, f, S, H, W,
                            pitch, nb, make_plan(W));
-        const int cb = H >= 2048 ? 1 : (2048 / H > 8 ? 8 : 2048 / H);
+        const int cb = col_batch(H);
         const size_t lds_c = (size_t)(H + 2 * cb * H) * sizeof(float2);
         hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), lds_c, st, S, (const float2*)M,
                            H, W, cb, make_plan(H), 0, 0);
@@ -404,9 +409,7 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
-static int row_batch(int W) { return W >= 1024 ? 1 : 1024 / W; }
 int fft_row_batch(int W) { return row_batch(W); }
-static int col_batch(int H) { return H >= 2048 ? 1 : (2048 / H > 8 ? 8 : 2048 / H); }
 
 void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
 {
