@@ -255,6 +255,18 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, float* __restrict__ pk, co
     }
 }
 
+// Tile (column, row) of this workgroup on a 2D grid of tiles, remapped so
+// that the workgroups of one XCD take a contiguous range of tiles in raster
+// order: vertically adjacent tiles, which share halo rows, then mostly share
+// an L2.
+DEBLUR_DEV int2 xcd_tile()
+{
+    const int n = gridDim.x * gridDim.y;
+    const int w = xcd_group(blockIdx.y * gridDim.x + blockIdx.x, n);
+    const int ty = w / gridDim.x;
+    return make_int2(w - ty * gridDim.x, ty);
+}
+
 template <int RAD, int TH, int NT>
 __global__ void __launch_bounds__(NT) rrrl_taps_stage1(const float* __restrict__ u, const float* __restrict__ f,
                                                        float2* __restrict__ qw, float* __restrict__ s_out, int H,
@@ -263,7 +275,8 @@ __global__ void __launch_bounds__(NT) rrrl_taps_stage1(const float* __restrict__
 {
     __shared__ float tile[stage1_lds_floats<RAD, TH>()];
     __shared__ float pk[packed_words_max<RAD>()];
-    stage1_tile<RAD, TH, NT>(tile, pk, u, f, qw, s_out, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, pkg, hdr, p);
+    const int2 t = xcd_tile();
+    stage1_tile<RAD, TH, NT>(tile, pk, u, f, qw, s_out, H, W, pitch, t.x * 64, t.y * TH, pkg, hdr, p);
 }
 
 template <int RAD, int TH>
@@ -361,7 +374,8 @@ __global__ void __launch_bounds__(NT) rrrl_taps_stage2(const float2* __restrict_
                                                        const int* __restrict__ hdr, IterParams p)
 {
     __shared__ Stage2Smem<RAD, TH> sm;
-    stage2_tile<RAD, TH, NT>(sm, qw, u, u_next, ckpt, H, W, pitch, blockIdx.x * 64, blockIdx.y * TH, pkg, hdr, p);
+    const int2 t = xcd_tile();
+    stage2_tile<RAD, TH, NT>(sm, qw, u, u_next, ckpt, H, W, pitch, t.x * 64, t.y * TH, pkg, hdr, p);
 }
 
 }  // namespace deblur
