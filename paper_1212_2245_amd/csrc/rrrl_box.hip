@@ -12,8 +12,14 @@ __global__ void __launch_bounds__(256) rrrl_box_iter(const float* __restrict__ u
                                                      BoxTile bt, IterParams p)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    box_iter_tile<VERT, TA, TC>(smem_raw, u, f, un, ckpt, pitch, bt, p, (VERT ? blockIdx.y : blockIdx.x) * TA,
-                                (VERT ? blockIdx.x : blockIdx.y) * TC);
+    // vertical blur: tiles in raster order, a contiguous range per XCD, so the
+    // tiles above and below (which share halo rows) mostly share an L2 (for
+    // horizontal blur the neighbours along the axis are adjacent blocks and
+    // the default order measured as fast)
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    const int w = VERT ? xcd_group(b, gridDim.x * gridDim.y) : b;
+    const int by = w / gridDim.x, bx = w - by * gridDim.x;
+    box_iter_tile<VERT, TA, TC>(smem_raw, u, f, un, ckpt, pitch, bt, p, (VERT ? by : bx) * TA, (VERT ? bx : by) * TC);
 }
 
 // ------------------------------------------------------------ host launchers
