@@ -359,6 +359,31 @@ def test_fft_path_parity(name, H, W, mk, iters):
     assert report(f"fft vs stencil {name}", out.cpu().numpy(), got) <= RTOL_ITER
 
 
+def test_dense_gaussian_full_size_sampled():
+    """The 2D-blur workload at its full size (2048^2, dense 31x31 PSF, constant
+    continuation, the benchmarked stencil path): one iteration, compared with
+    the oracle on 16x16 windows at the corners, edges and centre.  One step
+    of a pixel depends on u within 15 (A) + 15 (B) + 2 (diffusion) pixels, so
+    the oracle runs its step on crops with a 40 px margin (aligned with the
+    image border where the window touches it) and only the windows count."""
+    c = synth.make_case(2)
+    H, W = c.f.shape
+    u0 = np.maximum(c.f, 1.0).astype(np.float32) + np.random.default_rng(7).uniform(0, 2, c.f.shape).astype(np.float32)
+    gp = dbl.Params(alpha=c.alpha, iters=1)
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    dbl.deblur_rrrl_iterate(dev(c.f), dev(u0), out, gpu_psf(c.kind, c.length, c.psf), gp)
+    got = out.cpu().numpy()
+    p = oracle.Params(alpha=c.alpha)
+    M, S = 40, 16
+    for (y, x) in ((0, 0), (0, W - S), (H - S, 0), (H - S, W - S), (0, 1000), (1000, 0), (H - S, 777),
+                   (1500, W - S), (1017, 1031)):
+        y0, x0 = max(0, y - M), max(0, x - M)
+        y1, x1 = min(H, y + S + M), min(W, x + S + M)
+        step = oracle.rrrl_step(c.f[y0:y1, x0:x1], u0[y0:y1, x0:x1], c.psf, p)
+        want = step[y - y0:y - y0 + S, x - x0:x - x0 + S]
+        assert report(f"dense 2048 one step window ({y},{x})", got[y:y + S, x:x + S], want) <= 1e-5
+
+
 def test_fft_vs_stencil_full_size_2d_blur():
     """The 2D-blur workload at its full size (2048^2, dense 31x31 PSF) with
     periodic continuation: Fourier-domain path against the direct stencil."""
