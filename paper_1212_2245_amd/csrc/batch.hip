@@ -38,7 +38,7 @@ struct BatchTile {
     int img, x0, y0, pad;   // x0/y0: along/across origin for box tiles
 };
 
-constexpr int BT_TH = 32, BT_NT = 256;
+constexpr int BT_TH = 32, BT_NT = 512;
 
 template <int RAD>
 __global__ void __launch_bounds__(BT_NT) batch_stage1(const BatchTile* __restrict__ tiles,
