@@ -124,7 +124,8 @@ void batch_plan_destroy(BatchPlan* P)
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     for (hipEvent_t e : P->events) (void)hipEventDestroy(e);
-    for (hipStream_t s : P->chains) (void)hipStreamDestroy(s);
+    for (hipStream_t s : P->chains)
+        if (s) (void)hipStreamDestroy(s);
     if (P->cap) (void)hipStreamDestroy(P->cap);
     for (void* p : P->allocs) (void)hipFree(p);
     delete P;
@@ -238,8 +239,10 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
     }
     // ---- capture
     bool ok = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) == hipSuccess;
-    P->chains.resize(kChains, nullptr);
-    for (int c = 0; c < kChains && ok; ++c) ok = hipStreamCreateWithFlags(&P->chains[c], hipStreamNonBlocking) == hipSuccess;
+    // chains 0..kChains-1: the Wiener steps; kChains + class: the iterations of one tile class
+    P->chains.resize(kChains + NCLASS, nullptr);
+    for (int c = 0; c < kChains + NCLASS && ok; ++c)
+        ok = hipStreamCreateWithFlags(&P->chains[c], hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         batch_plan_destroy(P);
         return -4;
@@ -268,19 +271,48 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
             hipEvent_t join = event();
             ok = join && hipEventRecord(join, P->chains[c]) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
         }
-        for (int k = 0; k < P->iters && ok; ++k) {
-            const int src = (start + k) % 2;
-            const auto& L = lists[g];
-            if (L[CL_R4].count) hipLaunchKernelGGL(batch_stage1<4>, dim3(L[CL_R4].count), dim3(BT_NT), 0, s, L[CL_R4].d, dimgs, src);
-            if (L[CL_R8].count) hipLaunchKernelGGL(batch_stage1<8>, dim3(L[CL_R8].count), dim3(BT_NT), 0, s, L[CL_R8].d, dimgs, src);
-            if (L[CL_R16].count) hipLaunchKernelGGL(batch_stage1<16>, dim3(L[CL_R16].count), dim3(BT_NT), 0, s, L[CL_R16].d, dimgs, src);
-            if (L[CL_R32].count) hipLaunchKernelGGL(batch_stage1<32>, dim3(L[CL_R32].count), dim3(BT_NT), 0, s, L[CL_R32].d, dimgs, src);
-            if (L[CL_BOXH].count) hipLaunchKernelGGL(batch_box<false>, dim3(L[CL_BOXH].count), dim3(256), L[CL_BOXH].lds, s, L[CL_BOXH].d, dimgs, src);
-            if (L[CL_BOXV].count) hipLaunchKernelGGL(batch_box<true>, dim3(L[CL_BOXV].count), dim3(256), L[CL_BOXV].lds, s, L[CL_BOXV].d, dimgs, src);
-            if (L[CL_R4].count) hipLaunchKernelGGL(batch_stage2<4>, dim3(L[CL_R4].count), dim3(BT_NT), 0, s, L[CL_R4].d, dimgs, src);
-            if (L[CL_R8].count) hipLaunchKernelGGL(batch_stage2<8>, dim3(L[CL_R8].count), dim3(BT_NT), 0, s, L[CL_R8].d, dimgs, src);
-            if (L[CL_R16].count) hipLaunchKernelGGL(batch_stage2<16>, dim3(L[CL_R16].count), dim3(BT_NT), 0, s, L[CL_R16].d, dimgs, src);
-            if (L[CL_R32].count) hipLaunchKernelGGL(batch_stage2<32>, dim3(L[CL_R32].count), dim3(BT_NT), 0, s, L[CL_R32].d, dimgs, src);
+        // the iterations: every tile class (stencil radius, box axis) covers
+        // its own images, which depend only on themselves, so each class is
+        // an independent chain over all iterations, forked once after the
+        // Wiener step and joined at the end of the group
+        const auto& L = lists[g];
+        auto launch_class = [&](int cls, int src, hipStream_t cs) {
+            const BatchTile* d = L[cls].d;
+            const dim3 grid(L[cls].count);
+            switch (cls) {
+                case CL_R4:
+                    hipLaunchKernelGGL(batch_stage1<4>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_stage2<4>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    break;
+                case CL_R8:
+                    hipLaunchKernelGGL(batch_stage1<8>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_stage2<8>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    break;
+                case CL_R16:
+                    hipLaunchKernelGGL(batch_stage1<16>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_stage2<16>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    break;
+                case CL_R32:
+                    hipLaunchKernelGGL(batch_stage1<32>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_stage2<32>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    break;
+                case CL_BOXH:
+                    hipLaunchKernelGGL(batch_box<false>, grid, dim3(256), L[cls].lds, cs, d, dimgs, src);
+                    break;
+                default:
+                    hipLaunchKernelGGL(batch_box<true>, grid, dim3(256), L[cls].lds, cs, d, dimgs, src);
+                    break;
+            }
+        };
+        hipEvent_t fork_it = ok ? event() : nullptr;
+        ok = ok && fork_it && hipEventRecord(fork_it, s) == hipSuccess;
+        for (int cls = 0; cls < NCLASS && ok; ++cls) {
+            if (!L[cls].count) continue;
+            hipStream_t cs = P->chains[kChains + cls];
+            ok = hipStreamWaitEvent(cs, fork_it, 0) == hipSuccess;
+            for (int k = 0; k < P->iters && ok; ++k) launch_class(cls, (start + k) % 2, cs);
+            hipEvent_t join = ok ? event() : nullptr;
+            ok = ok && join && hipEventRecord(join, cs) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
         }
         if (ok) hipLaunchKernelGGL(batch_timestamp, dim3(1), dim3(64), 0, s, P->ts, g + 1);
     }
