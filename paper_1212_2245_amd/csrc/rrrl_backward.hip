@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int
 // 64 products per channel from registers (no per-product LDS read).  The
 // extended tile covers columns x0 - RAD - 8 .. x0 + 64 + RAD + 8 so that the
 // padded lags of the last block stay inside it.
-constexpr int DH_TH = 16;
+constexpr int DH_TH = 8;
 template <int RAD>
 __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, const float2* __restrict__ qw,
                                                 const float* __restrict__ ds, const float* __restrict__ u,
