@@ -536,7 +536,10 @@ struct BwdLayout {
 
 static int bwd_rad(const PsfDev& psf) { return tap_radius_class(max((psf.ph - 1) / 2, (psf.pw - 1) / 2)); }
 
-static int bwd_th(int rad) { return rad >= 32 ? 16 : 32; }
+// Rows per tile of the backward iteration kernels: 8 (at 512^2, 512
+// workgroups, two per CU; taller tiles leave CUs idle or one wave per SIMD).
+constexpr int BWD_TH = 8;
+static int bwd_th(int) { return BWD_TH; }
 
 static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
 {
@@ -591,7 +594,7 @@ static void launch_bwd_iter(const float* f, const float* u, const float* lam, in
                             float* grad_f, int H, int W, int pitch, const PsfDev& psf, const IterParams& p,
                             unsigned char* w8, const BwdLayout& L, hipStream_t st)
 {
-    constexpr int TH = RAD >= 32 ? 16 : 32;
+    constexpr int TH = BWD_TH;
     const float* taps = reinterpret_cast<const float*>(w8 + L.list + tap_packed_offset(psf.ph, psf.pw));
     const int* nt = reinterpret_cast<const int*>(w8 + L.list);
     float2* qw = reinterpret_cast<float2*>(w8 + L.qw);
@@ -645,7 +648,7 @@ static void launch_bwd_iter(const float* f, const float* u, const float* lam, in
         hipLaunchKernelGGL(adj_fold_y<float>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float*)tmp, cy, H, W,
                            aT, W);
     }
-    hipLaunchKernelGGL((adj_tv<32>), dim3((W + 63) / 64, (H + 31) / 32), dim3(BW_NT), 0, st, u, pitch,
+    hipLaunchKernelGGL((adj_tv<BWD_TH>), dim3((W + 63) / 64, (H + BWD_TH - 1) / BWD_TH), dim3(BW_NT), 0, st, u, pitch,
                        (const float*)c, (const float*)du, (const float*)aT, lam_out, H, W, p);
     hipLaunchKernelGGL((adj_dh<RAD>), dim3((W + 63) / 64, (H + DH_TH - 1) / DH_TH), dim3(BW_NT), 0, st, (const float2*)ab,
                        (const float2*)qw, (const float*)ds, u, pitch, H, W, psf.ph, psf.pw, p.bc, part);
