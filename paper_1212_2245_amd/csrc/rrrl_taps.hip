@@ -249,12 +249,17 @@ static void launch_stage2_t(int v, const float2* qw, const float* u, float* un, 
 // with a 71-tap line PSF; indices into kVariants): 64-row tiles of 1024
 // threads for stage 1 and 32-row tiles of 512 threads for stage 2 at about
 // 1 Mpx; smaller images use 16-row tiles.
-static int default_variant(int H, int W, int stage)
+// Default tile shape (index into kVariants) by image size, from a sweep of
+// every shape with a sparse (31-px line) and a dense (31x31) PSF at 256^2 ..
+// 2048^2: small images want many workgroups (16 rows x 512 threads, 2 rows
+// per thread), large ones more rows per thread for reuse of the loaded
+// column values (32 x 512, then 32 x 256).  Both stages use the same shape.
+static int default_variant(int H, int W, int /*stage*/)
 {
     const long tiles64 = (long)((W + 63) / 64) * ((H + 63) / 64);
-    if (tiles64 >= 1024) return stage == 1 ? 1 : 2;
-    if (tiles64 >= 256) return stage == 1 ? 0 : 3;
-    return 4;
+    if (tiles64 >= 1024) return 2;
+    if (tiles64 >= 256) return 3;
+    return 5;
 }
 
 size_t tap_list_bytes(const PsfDev& psf)
