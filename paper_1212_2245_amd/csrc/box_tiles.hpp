@@ -306,6 +306,10 @@ __host__ __device__ inline BoxTile make_tile(int H, int W, int L, float frac, bo
     return bt;
 }
 
-constexpr int BOXH_TA = 128, BOXH_TC = 8, BOXV_TA = 64, BOXV_TC = 16;
+// Tile shapes (positions along the blur axis x lines across): the narrow
+// shapes serve vertical blur, small images and the batched graph; the wide
+// horizontal shape serves single images above 512^2, where it measured faster.
+constexpr int BOXH_TA = 64, BOXH_TC = 4, BOXV_TA = 64, BOXV_TC = 8;
+constexpr int BOXH_WIDE_TA = 128, BOXH_WIDE_TC = 8;
 
 }  // namespace deblur

@@ -29,11 +29,11 @@ static void allow_large_lds()
 {
     static std::once_flag once;
     std::call_once(once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<false, 128, 8>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<false, BOXH_WIDE_TA, BOXH_WIDE_TC>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<false, 64, 4>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<false, BOXH_TA, BOXH_TC>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<true, 64, 8>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<true, BOXV_TA, BOXV_TC>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     });
 }
@@ -42,25 +42,27 @@ int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt,
                          float frac, bool vert, const IterParams& p, hipStream_t st)
 {
     allow_large_lds();
-    // tile shapes (along x across): vertical blur 64 x 8 at every size
-    // measured (256^2 .. 2048^2); horizontal blur 64 x 4 up to 512^2 (a
-    // 256^2 image gives only 64 workgroups with wide tiles), 128 x 8 above
+    // tile shapes: vertical blur BOXV at every size measured (256^2 ..
+    // 2048^2); horizontal blur BOXH up to 512^2 (a 256^2 image gives only 64
+    // workgroups with wide tiles), BOXH_WIDE above
     if (vert) {
-        const BoxTile bt = make_tile(H, W, L, frac, true, 64);
-        const dim3 g((W + 7) / 8, (H + 63) / 64);
-        const size_t lds = box_lds_bytes<true, 64, 8>(bt);
-        hipLaunchKernelGGL((rrrl_box_iter<true, 64, 8>), g, dim3(256), lds, st, u, f, un, ckpt, pitch, bt, p);
+        const BoxTile bt = make_tile(H, W, L, frac, true, BOXV_TA);
+        const dim3 g((W + BOXV_TC - 1) / BOXV_TC, (H + BOXV_TA - 1) / BOXV_TA);
+        const size_t lds = box_lds_bytes<true, BOXV_TA, BOXV_TC>(bt);
+        hipLaunchKernelGGL((rrrl_box_iter<true, BOXV_TA, BOXV_TC>), g, dim3(256), lds, st, u, f, un, ckpt, pitch,
+                           bt, p);
     } else if ((long)H * W <= 512L * 512L) {
-        const BoxTile bt = make_tile(H, W, L, frac, false, 64);
-        const dim3 g((W + 63) / 64, (H + 3) / 4);
-        const size_t lds = box_lds_bytes<false, 64, 4>(bt);
-        hipLaunchKernelGGL((rrrl_box_iter<false, 64, 4>), g, dim3(256), lds, st, u, f, un, ckpt, pitch, bt, p);
-    } else {
         const BoxTile bt = make_tile(H, W, L, frac, false, BOXH_TA);
         const dim3 g((W + BOXH_TA - 1) / BOXH_TA, (H + BOXH_TC - 1) / BOXH_TC);
         const size_t lds = box_lds_bytes<false, BOXH_TA, BOXH_TC>(bt);
         hipLaunchKernelGGL((rrrl_box_iter<false, BOXH_TA, BOXH_TC>), g, dim3(256), lds, st, u, f, un, ckpt, pitch,
                            bt, p);
+    } else {
+        const BoxTile bt = make_tile(H, W, L, frac, false, BOXH_WIDE_TA);
+        const dim3 g((W + BOXH_WIDE_TA - 1) / BOXH_WIDE_TA, (H + BOXH_WIDE_TC - 1) / BOXH_WIDE_TC);
+        const size_t lds = box_lds_bytes<false, BOXH_WIDE_TA, BOXH_WIDE_TC>(bt);
+        hipLaunchKernelGGL((rrrl_box_iter<false, BOXH_WIDE_TA, BOXH_WIDE_TC>), g, dim3(256), lds, st, u, f, un,
+                           ckpt, pitch, bt, p);
     }
     return 0;
 }
