@@ -228,3 +228,18 @@ def test_backward_perona_malik():
     gp = dbl.Params(alpha=alpha, iters=iters, eps_tv=20.0, psi=dbl.PSI_PERONA_MALIK)
     got = gpu_grads(f, dbl.Psf.from_taps(dev(h)), g.astype(np.float32), K, gp, True)
     check("perona_malik", got, df, dh, da, lam0, floor)
+
+
+def test_backward_fractional_box():
+    """A vertical box of non-integer length (fractional end pixels): dL/dh for
+    every entry of its array, including the two end taps."""
+    rng = np.random.default_rng(17)
+    H, W = 72, 48
+    g = synth.ground_truth(rng, H, W)
+    h = synth.box_psf(8.5, "v").astype(np.float32)
+    f = synth.observe(rng, g, h.astype(np.float64), 2.0)
+    p = oracle.Params(alpha=0.003)
+    (df, dh, da, lam0), floor = oracle_floor(f, h, g.astype(np.float32), 0.01, p, 3, True)
+    got = gpu_grads(f, dbl.Psf.box(8.5, "v"), g.astype(np.float32), 0.01, dbl.Params(alpha=0.003, iters=3), True)
+    assert got["taps"].shape == h.shape
+    check("box8.5v", got, df, dh, da, lam0, floor)
