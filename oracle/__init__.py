@@ -11,7 +11,11 @@ Passages followed (Welk et al., "Fast and Robust Linear Motion Deblurring"):
   * replacement of non-positive Wiener values by a small positive value
     before RRRL: Sec. 3.2 (WR3L);
   * RRRL iteration: Sec. 2.3, eqs. (6)-(12), multiplicative in u^k;
-  * diffusion term by central differences: Sec. 4.1.
+  * diffusion term by central differences: Sec. 4.1; the non-convex
+    (Perona-Malik) penaliser as the variant Sec. 2.3 mentions;
+  * the lookup-table evaluation of r_f: Sec. 4.1;
+  * starting images of RRRL without the Wiener step (Table 1's RRRL
+    columns): flat or observed.
 """
 from __future__ import annotations
 

@@ -165,6 +165,19 @@ def test_rf_lookup_mode():
     assert math.isclose(oracle.rf_lut(10.0, 0.01), 10.0 * (1 / 64 - 1 - math.log(1 / 64)), rel_tol=1e-12)
 
 
+def test_rrrl_start_images():
+    """Starting images of RRRL without the Wiener step: flat = the mean,
+    floored; observed = the image, floored."""
+    c = np.full((5, 7), 42.5)
+    np.testing.assert_array_equal(oracle.rrrl_start(c, 0, 1.0), c)
+    H, W = 6, 9
+    ramp = np.add.outer(np.arange(H, dtype=np.float64), 10.0 * np.arange(W))
+    np.testing.assert_allclose(oracle.rrrl_start(ramp, 0, 1.0), np.full((H, W), (H - 1) / 2 + 10 * (W - 1) / 2))
+    np.testing.assert_array_equal(oracle.rrrl_start(np.zeros((3, 3)), 0, 1.5), np.full((3, 3), 1.5))
+    f = np.array([[0.0, 0.5, 3.0], [-2.0, 1.0, 7.0]])
+    np.testing.assert_array_equal(oracle.rrrl_start(f, 1, 1.0), [[1.0, 1.0, 3.0], [1.0, 1.0, 7.0]])
+
+
 # ----------------------------------------------------------------------- TV
 def test_tv_hand_worked_profile():
     rows = np.loadtxt(os.path.join(GOLD, "tv_profile_1x5.txt"))
