@@ -48,7 +48,8 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
     __shared__ float gt[GH * GW];
     __shared__ double red[BW_NT];
     __shared__ float pk[packed_words_max<RAD>()];
-    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
+    const int x0 = tile_xy.x * TW, y0 = tile_xy.y * TH;
     const int tid = threadIdx.x;
     int cnt[TAP_GROUP_MAX];
     load_groups<RAD>(pk, pkg, hdr, cnt);
@@ -122,7 +123,8 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
     constexpr int TW = BW_TW, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (BW_NT / 64);
     __shared__ T vt[LH * LW];
     __shared__ float pk[packed_words_max<RAD>()];
-    const int zx0 = ox + blockIdx.x * TW, zy0 = oy + blockIdx.y * TH;
+    const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
+    const int zx0 = ox + tile_xy.x * TW, zy0 = oy + tile_xy.y * TH;
     const int tid = threadIdx.x;
     int cnt[TAP_GROUP_MAX];
     load_groups<RAD>(pk, pkg, hdr, cnt);
@@ -243,7 +245,8 @@ __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int
     constexpr int TW = BW_TW, UW = TW + 4, UH = TH + 4, GW = TW + 2, GH = TH + 2;
     __shared__ float ut[UH * UW], ct[UH * UW];
     __shared__ float gt[GH * GW], dgx[GH * GW], dgy[GH * GW];
-    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
+    const int x0 = tile_xy.x * TW, y0 = tile_xy.y * TH;
     const int tid = threadIdx.x;
     stage_to_lds<BW_NT, UH * UW>(ut, [&](int idx) {
         const int ly = idx / UW, lx = idx - ly * UW;
@@ -323,7 +326,8 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
     __shared__ float2 ct[TH * TW];
     __shared__ float2 ht[LH * LW];
     __shared__ float red[BW_NT * 8];
-    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
+    const int x0 = tile_xy.x * TW, y0 = tile_xy.y * TH;
     const int tid = threadIdx.x;
     const int PP = ph * pw, cy = (ph - 1) / 2, cx = (pw - 1) / 2;
     const int nxb = (pw + 7) / 8, nb = ph * nxb;
