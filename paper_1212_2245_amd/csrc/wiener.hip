@@ -15,6 +15,8 @@
 //    as one complex row, unpacked to two half spectra), column pass (FFT,
 //    multiply by M, inverse FFT), inverse row pass (Hermitian extension,
 //    rows packed again, inverse FFT, floor).
+#include <algorithm>
+
 #include "fft_lds.hpp"
 #include "launch.hpp"
 #include "psf.hpp"
@@ -126,17 +128,24 @@ __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict
 // the exact first root (at most 32 steps).  Optionally also h^ itself (hh).
 constexpr int MULT_KX = 16, MULT_KY = 64;
 constexpr int MULT_HALF = (MULT_MAXP - 1) / 2;
-__global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, double K, float2* __restrict__ M,
-                                                      float2* __restrict__ hh)
+// LDS of one multiplier block: G, P/Q, the PSF, the roots (16-byte aligned parts)
+constexpr size_t MULT_G_OFF = 0, MULT_PQ_OFF = MULT_G_OFF + sizeof(double2) * MULT_MAXP * MULT_KX,
+                 MULT_HS_OFF = MULT_PQ_OFF + sizeof(double2) * 2 * MULT_HALF * MULT_KX,
+                 MULT_ROT_OFF = (MULT_HS_OFF + sizeof(float) * MULT_MAXP * MULT_MAXP + 15) & ~(size_t)15,
+                 MULT_SMEM = MULT_ROT_OFF + sizeof(double2) * (MULT_KX + MULT_KY);
+
+// One block (bx, by) of M: kx in [16 bx, 16 bx + 16), ky in [64 by, 64 by + 64).
+DEBLUR_DEV void mult_2d_block(const PsfDev& psf, int H, int W, double K, float2* __restrict__ M,
+                              float2* __restrict__ hh, int bx, int by, unsigned char* smem)
 {
-    __shared__ double2 G[MULT_MAXP * MULT_KX];
-    __shared__ double2 PQ[2 * MULT_HALF * MULT_KX];
-    __shared__ float hs[MULT_MAXP * MULT_MAXP];
-    __shared__ double2 rot[MULT_KX + MULT_KY];   // exp(-2 pi i k / n) per kx, then per ky
+    double2* G = reinterpret_cast<double2*>(smem + MULT_G_OFF);
+    double2* PQ = reinterpret_cast<double2*>(smem + MULT_PQ_OFF);
+    float* hs = reinterpret_cast<float*>(smem + MULT_HS_OFF);
+    double2* rot = reinterpret_cast<double2*>(smem + MULT_ROT_OFF);   // exp(-2 pi i k / n) per kx, then per ky
     psf_to_lds(psf, hs);
     const int Wh = W / 2 + 1;
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
-    const int kx0 = blockIdx.x * MULT_KX, ky0 = blockIdx.y * MULT_KY;
+    const int kx0 = bx * MULT_KX, ky0 = by * MULT_KY;
     for (int t = threadIdx.x; t < MULT_KX + MULT_KY; t += blockDim.x)
         rot[t] = t < MULT_KX ? unit_root(kx0 + t, W) : unit_root(ky0 + t - MULT_KX, H);
     __syncthreads();
@@ -207,23 +216,29 @@ __global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, 
     }
 }
 
+__global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, double K, float2* __restrict__ M,
+                                                      float2* __restrict__ hh)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    mult_2d_block(psf, H, W, K, M, hh, blockIdx.x, blockIdx.y, smem_raw);
+}
+
 static void mult_2d_launch(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
 {
     const dim3 grid((W / 2 + 1 + MULT_KX - 1) / MULT_KX, (H + MULT_KY - 1) / MULT_KY);
-    hipLaunchKernelGGL(wiener_mult_2d, grid, dim3(256), 0, st, psf, H, W, K, M, hh);
+    hipLaunchKernelGGL(wiener_mult_2d, grid, dim3(256), MULT_SMEM, st, psf, H, W, K, M, hh);
 }
 
 // Row pass: rows (2p, 2p+1) packed as z = f_a + i f_b, FFT along x, unpacked
 // into the half spectra F_a(k), F_b(k), k <= W/2, written to S (row pitch W/2+1).
-__global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__ f, float2* __restrict__ S,
-                                                       int H, int W, int pitch, int nb, FftPlan plan)
+DEBLUR_DEV void rows_fwd_block(const float* __restrict__ f, float2* __restrict__ S, int H, int W, int pitch, int nb,
+                               const FftPlan& plan, int blk, unsigned char* smem_raw)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* tw = reinterpret_cast<float2*>(smem_raw);
     float2* a = tw + W;
     float2* b = a + nb * W;
     fft_twiddles(tw, W);
-    const int pair0 = blockIdx.x * nb;
+    const int pair0 = blk * nb;
     stage_to_lds_n<8>(a, nb * W, [&](int idx) {
         const int t = idx / W, x = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
@@ -242,6 +257,29 @@ __global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__
         // F_a = (Z(k) + conj Z(-k))/2,  F_b = (Z(k) - conj Z(-k))/(2i)
         if (ya < H) S[(size_t)ya * Wh + k] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
         if (yb < H) S[(size_t)yb * Wh + k] = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+    }
+}
+
+__global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__ f, float2* __restrict__ S,
+                                                       int H, int W, int pitch, int nb, FftPlan plan)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    rows_fwd_block(f, S, H, W, pitch, nb, plan, blockIdx.x, smem_raw);
+}
+
+// The row pass of f and the multiplier M in one launch: they are independent,
+// and as one grid (row blocks first, then the M blocks) they overlap without
+// a second stream.  LDS: the larger of the two needs.
+__global__ void __launch_bounds__(256) wiener_rows_fwd_mult(const float* __restrict__ f, float2* __restrict__ S,
+                                                            int H, int W, int pitch, int nb, FftPlan plan, int nrow,
+                                                            PsfDev psf, double K, float2* __restrict__ M, int gxm)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if ((int)blockIdx.x < nrow) {
+        rows_fwd_block(f, S, H, W, pitch, nb, plan, blockIdx.x, smem_raw);
+    } else {
+        const int b = blockIdx.x - nrow, by = b / gxm;
+        mult_2d_block(psf, H, W, K, M, nullptr, b - by * gxm, by, smem_raw);
     }
 }
 
@@ -393,12 +431,13 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
         const int Wh = W / 2 + 1;
         float2* M = reinterpret_cast<float2*>(ws);
         float2* S = M + (size_t)H * Wh;
-        mult_2d_launch(psf, H, W, K, M, nullptr, st);
         const int pairs = (H + 1) / 2;
         const int nb = row_batch(W);
         const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(float2);
-        hipLaunchKernelGGL(wiener_rows_fwd, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st, f, S, H, W,
-                           pitch, nb, make_plan(W));
+        const int nrow = (pairs + nb - 1) / nb;
+        const int gxm = (Wh + MULT_KX - 1) / MULT_KX, gym = (H + MULT_KY - 1) / MULT_KY;
+        hipLaunchKernelGGL(wiener_rows_fwd_mult, dim3(nrow + gxm * gym), dim3(256), std::max(lds_r, MULT_SMEM), st,
+                           f, S, H, W, pitch, nb, make_plan(W), nrow, psf, K, M, gxm);
         const int cb = col_batch(H);
         const size_t lds_c = (size_t)(H + 2 * cb * H) * sizeof(float2);
         hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), lds_c, st, S, (const float2*)M,
