@@ -384,6 +384,41 @@ def test_dense_gaussian_full_size_sampled():
         assert report(f"dense 2048 one step window ({y},{x})", got[y:y + S, x:x + S], want) <= 1e-5
 
 
+def test_largest_image_sampled():
+    """The largest image the boundary accepts, H x pitch = 2^31 pixels (32768 x
+    65536, 8 GiB per plane), through one stencil iteration with the oblique
+    31-px line PSF: every global offset of the stage kernels is past 32 bits
+    here.  Inputs are seeded uniform noise made on the device (a blurred
+    image of this size would take minutes to synthesise on the host); the
+    oracle's step runs on crops with a 40 px margin around 16x16 windows at
+    the corners, the edges and the last rows."""
+    H, W = 32768, 65536
+    g = torch.Generator(device="cuda").manual_seed(2245)
+    f = torch.rand((H, W), generator=g, device="cuda") * 255.0
+    u0 = torch.clamp(f, min=1.0) + torch.rand((H, W), generator=g, device="cuda")
+    out = torch.empty_like(f)
+    h = synth.line_psf(31, 1.1)
+    gp = dbl.Params(alpha=0.002, iters=1)
+    try:
+        dbl.deblur_rrrl_iterate(f, u0, out, gpu_psf(synth.KIND_TAPS, 0, h), gp)
+        torch.cuda.synchronize()
+        p = oracle.Params(alpha=0.002)
+        M, S = 40, 16
+        for (y, x) in ((0, 0), (0, W - S), (H - S, 0), (H - S, W - S), (H // 2, W // 2), (H - S, 40000),
+                       (20000, W - S), (H - 1 - S, W - 1 - S)):
+            y0, x0 = max(0, y - M), max(0, x - M)
+            y1, x1 = min(H, y + S + M), min(W, x + S + M)
+            fc = f[y0:y1, x0:x1].cpu().numpy()
+            uc = u0[y0:y1, x0:x1].cpu().numpy()
+            step = oracle.rrrl_step(fc, uc, h, p)
+            want = step[y - y0:y - y0 + S, x - x0:x - x0 + S]
+            got = out[y:y + S, x:x + S].cpu().numpy()
+            assert report(f"2^31 px one step window ({y},{x})", got, want) <= 1e-5
+    finally:
+        del f, u0, out
+        torch.cuda.empty_cache()
+
+
 def test_fft_vs_stencil_full_size_2d_blur():
     """The 2D-blur workload at its full size (2048^2, dense 31x31 PSF) with
     periodic continuation: Fourier-domain path against the direct stencil."""
