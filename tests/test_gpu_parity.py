@@ -384,23 +384,29 @@ def test_dense_gaussian_full_size_sampled():
         assert report(f"dense 2048 one step window ({y},{x})", got[y:y + S, x:x + S], want) <= 1e-5
 
 
-def test_largest_image_sampled():
+@pytest.mark.parametrize("name,kind,length,mk", [
+    ("line31", synth.KIND_TAPS, 0, lambda: synth.line_psf(31, 1.1)),
+    ("box_h15", synth.KIND_BOX_H, 15, lambda: synth.box_psf(15, "h")),
+    ("box_v9", synth.KIND_BOX_V, 9, lambda: synth.box_psf(9, "v")),
+])
+def test_largest_image_sampled(name, kind, length, mk):
     """The largest image the boundary accepts, H x pitch = 2^31 pixels (32768 x
-    65536, 8 GiB per plane), through one stencil iteration with the oblique
-    31-px line PSF: every global offset of the stage kernels is past 32 bits
-    here.  Inputs are seeded uniform noise made on the device (a blurred
-    image of this size would take minutes to synthesise on the host); the
-    oracle's step runs on crops with a 40 px margin around 16x16 windows at
-    the corners, the edges and the last rows."""
+    65536, 8 GiB per plane), through one iteration of the stencil path (oblique
+    31-px line) and of the running-sum path (horizontal and vertical boxes):
+    every global offset of these kernels is past 32 bits here.  Inputs are
+    seeded uniform noise made on the device (a blurred image of this size
+    would take minutes to synthesise on the host); the oracle's step runs on
+    crops with a 40 px margin around 16x16 windows at the corners, the edges
+    and the last rows."""
     H, W = 32768, 65536
     g = torch.Generator(device="cuda").manual_seed(2245)
     f = torch.rand((H, W), generator=g, device="cuda") * 255.0
     u0 = torch.clamp(f, min=1.0) + torch.rand((H, W), generator=g, device="cuda")
     out = torch.empty_like(f)
-    h = synth.line_psf(31, 1.1)
+    h = mk()
     gp = dbl.Params(alpha=0.002, iters=1)
     try:
-        dbl.deblur_rrrl_iterate(f, u0, out, gpu_psf(synth.KIND_TAPS, 0, h), gp)
+        dbl.deblur_rrrl_iterate(f, u0, out, gpu_psf(kind, length, h), gp)
         torch.cuda.synchronize()
         p = oracle.Params(alpha=0.002)
         M, S = 40, 16
@@ -413,7 +419,7 @@ def test_largest_image_sampled():
             step = oracle.rrrl_step(fc, uc, h, p)
             want = step[y - y0:y - y0 + S, x - x0:x - x0 + S]
             got = out[y:y + S, x:x + S].cpu().numpy()
-            assert report(f"2^31 px one step window ({y},{x})", got, want) <= 1e-5
+            assert report(f"2^31 px {name} one step window ({y},{x})", got, want) <= 1e-5
     finally:
         del f, u0, out
         torch.cuda.empty_cache()
