@@ -550,7 +550,6 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
         out["pmc_calibration_copy_bytes"] = nbytes
     print(json.dumps(out), flush=True)
 
