@@ -400,8 +400,9 @@ def test_largest_image_sampled(name, kind, length, mk):
     and the last rows."""
     H, W = 32768, 65536
     g = torch.Generator(device="cuda").manual_seed(2245)
-    f = torch.rand((H, W), generator=g, device="cuda") * 255.0
-    u0 = torch.clamp(f, min=1.0) + torch.rand((H, W), generator=g, device="cuda")
+    # explicit dtype: another test module sets torch's default dtype to float64
+    f = torch.rand((H, W), generator=g, device="cuda", dtype=torch.float32) * 255.0
+    u0 = torch.clamp(f, min=1.0) + torch.rand((H, W), generator=g, device="cuda", dtype=torch.float32)
     out = torch.empty_like(f)
     h = mk()
     gp = dbl.Params(alpha=0.002, iters=1)
