@@ -186,7 +186,7 @@ def test_gpu_finite_difference_in_f():
     far below the step's own error."""
     c = synth.make_case(4, size=128)
     taps = dev(c.psf)
-    alpha = torch.tensor(c.alpha)
+    alpha = torch.tensor(c.alpha, dtype=torch.float64)
     rng = np.random.default_rng(9)
     vn = rng.normal(size=c.f.shape) * (c.f >= 1)
     v = dev(vn)

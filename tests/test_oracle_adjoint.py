@@ -11,7 +11,14 @@ import torch.nn.functional as F
 import oracle
 import synth
 
-torch.set_default_dtype(torch.float64)
+
+@pytest.fixture(autouse=True)
+def _float64_default():
+    """FP64 as torch's default dtype for this module's tests only."""
+    prev = torch.get_default_dtype()
+    torch.set_default_dtype(torch.float64)
+    yield
+    torch.set_default_dtype(prev)
 
 
 def rng(i):
