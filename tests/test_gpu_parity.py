@@ -134,6 +134,13 @@ ITER_CASES = [
     ("tiny_5x3", 5, 3, lambda: synth.random_psf(np.random.default_rng(6), 3, 3), synth.KIND_TAPS, 0, 3, {}),
     ("single_row", 1, 40, lambda: synth.box_psf(5, "h"), synth.KIND_BOX_H, 5, 4, {}),
     ("pitch_160", 100, 130, lambda: synth.line_psf(15, 0.2), synth.KIND_TAPS, 0, 5, dict(pitch=160)),
+    # PSF reach comparable to the image: halos clamp (or wrap) on both sides of every tile
+    ("line31_on_20x24", 20, 24, lambda: synth.line_psf(31, 0.9), synth.KIND_TAPS, 0, 4, {}),
+    ("line31_on_20x24_periodic", 20, 24, lambda: synth.line_psf(31, 0.9), synth.KIND_TAPS, 0, 4,
+     dict(bc=oracle.BC_PERIODIC)),
+    ("box_h41_on_16x30", 16, 30, lambda: synth.box_psf(41, "h"), synth.KIND_BOX_H, 41, 4, {}),
+    ("box_v9_on_12x20_periodic", 12, 20, lambda: synth.box_psf(9, "v"), synth.KIND_BOX_V, 9, 4,
+     dict(bc=oracle.BC_PERIODIC)),
 ]
 
 
