@@ -110,6 +110,9 @@ CASES = [
     ("no_wiener", 48, 72, lambda: synth.line_psf(7, 1.0), oracle.BC_REPLICATE, True, 4, False),
     ("iters0", 32, 32, lambda: synth.random_psf(np.random.default_rng(3), 3, 3), oracle.BC_REPLICATE, True, 0, True),
     ("gauss31_64", 64, 64, lambda: synth.gauss_mixture_psf(synth.rng_for(2), 31), oracle.BC_REPLICATE, True, 2, True),
+    # PSF reach comparable to the image: the transposes' border folds span most of a row or column
+    ("line31_on_32", 32, 32, lambda: synth.line_psf(31, 0.9), oracle.BC_REPLICATE, True, 2, True),
+    ("line31_on_32x36_periodic", 32, 36, lambda: synth.line_psf(31, 0.9), oracle.BC_PERIODIC, True, 2, False),
 ]
 
 
