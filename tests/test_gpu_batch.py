@@ -117,3 +117,28 @@ def test_batch_method_variants():
     for (f, psf, p, K, fl), out in zip(items, outs):
         assert torch.equal(out, dbl.wr3l(f, psf, K, p, fl))
     plan.close()
+
+
+def test_batch_small_images_large_psfs():
+    """Images barely larger than their PSFs (halos clamp on both sides of
+    every tile) in one graph with a larger image: bitwise equal to the
+    single-image calls, for every stencil radius class and both box axes."""
+    rng = np.random.default_rng(11)
+    specs = [(32, 32, synth.line_psf(31, 0.9)), (36, 48, synth.line_psf(17, 2.3)), (16, 24, synth.line_psf(9, 0.2)),
+             (24, 16, synth.random_psf(np.random.default_rng(4), 7, 5)), (16, 48, None), (48, 16, "v"),
+             (256, 256, synth.line_psf(31, 1.7))]
+    items = []
+    for H, W, h in specs:
+        if h is None or isinstance(h, str):
+            axis = "v" if h == "v" else "h"
+            psf_arr, psf = synth.box_psf(13, axis), dbl.Psf.box(13, axis)
+        else:
+            psf_arr, psf = h, dbl.Psf.from_taps(dev(h))
+        f = synth.observe(rng, synth.ground_truth(rng, H, W), psf_arr, 2.0)
+        items.append((dev(f), psf, dbl.Params(alpha=0.003, iters=5), 0.01, 1.0))
+    plan = dbl.BatchPlan(items)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for (f, psf, p, K, fl), out in zip(items, outs):
+        assert torch.equal(out, dbl.wr3l(f, psf, K, p, fl))
+    plan.close()
