@@ -348,6 +348,7 @@ def test_tile_variants_bitwise_identical(H, W, psfname):
     ("gauss31_128", 128, 128, lambda: synth.gauss_mixture_psf(synth.rng_for(2), 31), 8),
     ("asym7x5_81x48", 81, 48, lambda: synth.random_psf(np.random.default_rng(9), 7, 5), 5),
     ("box_v15_192x64", 192, 64, lambda: synth.box_psf(15, "v"), 6),
+    ("line31_32x36", 32, 36, lambda: synth.line_psf(31, 0.9), 4),   # PSF nearly as large as the image
 ])
 def test_fft_path_parity(name, H, W, mk, iters):
     """Fourier-domain iteration (periodic continuation) against the oracle
