@@ -152,6 +152,24 @@ def test_iterate_parity(name, H, W, mk, kind, L, iters, kw):
     assert report("iterate " + name, got, want) <= RTOL_ITER
 
 
+def test_iterate_zero_and_negative_observations():
+    """Observations that are exactly zero over a block and negative at some
+    pixels (the f <= 0 branch: r_f(s) = s, q from max(f, 0)), with a
+    one-tap PSF and with a line PSF, against the oracle."""
+    rng = np.random.default_rng(21)
+    H, W = 72, 88
+    for h in (np.ones((1, 1)), synth.line_psf(13, 0.6)):
+        f = synth.observe(rng, synth.ground_truth(rng, H, W), h, 2.0).astype(np.float64)
+        f[10:30, 20:50] = 0.0
+        f[50:54, 60:70] = -3.0
+        f = f.astype(np.float32)
+        u0 = (np.maximum(f, 1.0) + rng.uniform(0, 3, size=f.shape)).astype(np.float32)
+        want = oracle.rrrl(f, u0, h, oracle.Params(alpha=0.003), 5)
+        out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        dbl.deblur_rrrl_iterate(dev(f), dev(u0), out, gpu_psf(synth.KIND_TAPS, 0, h), dbl.Params(alpha=0.003, iters=5))
+        assert report(f"zero/negative f, psf {h.shape}", out.cpu().numpy(), want) <= RTOL_ITER
+
+
 def test_iterate_edge_counts_and_aliasing():
     rng = np.random.default_rng(21)
     H, W = 48, 72
