@@ -15,7 +15,9 @@
  *    (deblur_psf, deblur_params) are HOST pointers read during the call.
  *  - The caller owns all memory.  The library allocates nothing on these
  *    calls; scratch space is the caller's workspace of at least
- *    deblur_workspace_bytes(...) bytes, 256-byte aligned.
+ *    deblur_workspace_bytes(...) bytes, 256-byte aligned.  One exception:
+ *    the first call with deblur_params.rf_lut = 1 on a device uploads a
+ *    16 KB table that the library keeps until the process ends.
  *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
  *    null stream) and the call returns without synchronising.  Inputs must
  *    stay valid until the stream reaches the work.  Calls on distinct streams
