@@ -46,7 +46,9 @@ typedef enum {
     DEBLUR_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad enum, ...) */
     DEBLUR_EUNSUPPORTED = -2, /* valid but not implemented (FFT length, PSF radius, ...) */
     DEBLUR_EWORKSPACE = -3,   /* workspace missing or smaller than required */
-    DEBLUR_EDEVICE = -4       /* HIP launch or runtime failure */
+    DEBLUR_EDEVICE = -4,      /* HIP launch or runtime failure */
+    DEBLUR_ESCRATCH = -5      /* the problem needs more than the static scratch of
+                                 deblur_rrrl_iterate_noalloc (DEBLUR_NOALLOC_SCRATCH_BYTES) */
 } deblur_status;
 
 /* Boundary continuation of the blur A and adjoint blur B (Sec. 4.2): the
@@ -160,6 +162,28 @@ int deblur_rrrl_start(const float* f, float* u0, int32_t H, int32_t W, int32_t p
 int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t H, int32_t W, int32_t pitch,
                         const deblur_psf* psf, const deblur_params* p, float* ckpt, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* Variant of deblur_rrrl_iterate for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, hosts that forbid
+ * hipMalloc): the same arguments without the workspace, the same kernels and
+ * results bit for bit.  Its scratch is a static device array of
+ * DEBLUR_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU the library runs on
+ * holds from library load until the process ends; the call allocates nothing
+ * (no hipMalloc, no library allocation).
+ *  - A problem whose workspace, deblur_workspace_bytes(1, ...), exceeds the
+ *    scratch returns DEBLUR_ESCRATCH before anything is enqueued (e.g. the
+ *    stencil path holds 16 bytes per pixel: up to about 4 Mpx).
+ *  - rf_lut = 1 returns DEBLUR_EUNSUPPORTED (that mode allocates its table on
+ *    first use).
+ *  - Every call on a GPU shares that GPU's one scratch array, which keeps the
+ *    last call's contents: calls that overlap in time on one GPU (different
+ *    streams, or host threads) race and give undefined results.  Serialise
+ *    them, e.g. by issuing them on one stream.
+ * Other arguments, layouts, ownership and errors: as deblur_rrrl_iterate. */
+#define DEBLUR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int deblur_rrrl_iterate_noalloc(const float* f, const float* u_in, float* u_out, int32_t H, int32_t W,
+                                int32_t pitch, const deblur_psf* psf, const deblur_params* p, float* ckpt,
+                                void* stream);
 
 /* Reverse-mode derivative of a loss L(u^K) through p->iters unrolled RRRL
  * iterations (eqs. (9)-(12)) and, if through_wiener, through the Wiener

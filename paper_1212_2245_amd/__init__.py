@@ -23,7 +23,7 @@ from ._lib import (BC_PERIODIC, BC_REPLICATE, CONV_AUTO, CONV_FFT, CONV_RUNSUM, 
 __all__ = ["Psf", "Params", "deblur_workspace_bytes", "deblur_wiener", "deblur_rrrl_iterate", "wr3l",
            "DeblurError", "BC_REPLICATE", "BC_PERIODIC", "PSF_BOX_H", "PSF_BOX_V", "PSF_TAPS",
            "CONV_AUTO", "CONV_RUNSUM", "CONV_STENCIL", "CONV_FFT", "PSI_TV", "PSI_PERONA_MALIK", "START_FLAT",
-           "START_OBSERVED", "deblur_rrrl_start", "rrrl", "library_path"]
+           "START_OBSERVED", "deblur_rrrl_start", "rrrl", "library_path", "deblur_rrrl_iterate_noalloc"]
 
 
 def library_path() -> str:
@@ -175,6 +175,27 @@ def deblur_rrrl_iterate(f: torch.Tensor, u_in: torch.Tensor, u_out: torch.Tensor
                                  ckpt.data_ptr() if ckpt is not None else None,
                                  wst.data_ptr(), wst.numel(), _stream(f))
     _lib.check(st, "deblur_rrrl_iterate")
+    return u_out
+
+
+def deblur_rrrl_iterate_noalloc(f: torch.Tensor, u_in: torch.Tensor, u_out: torch.Tensor, psf: Psf,
+                                params: Params, ckpt: torch.Tensor | None = None) -> torch.Tensor:
+    """deblur_rrrl_iterate on the library's static device scratch: allocates
+    nothing.  Calls that overlap in time on one GPU share that scratch and
+    race; problems needing more than 64 MiB of workspace raise DeblurError."""
+    lib = _lib.load()
+    H, W, pitch = _image(f, "f")
+    _same_layout((H, W, pitch), _image(u_in, "u_in"), "f", "u_in")
+    _same_layout((H, W, pitch), _image(u_out, "u_out"), "f", "u_out")
+    if ckpt is not None:
+        if (not ckpt.is_cuda or ckpt.dtype != torch.float32 or not ckpt.is_contiguous()
+                or ckpt.numel() < params.iters * H * pitch):
+            raise ValueError("ckpt must be a contiguous float32 device tensor of iters*H*pitch elements")
+    cpsf, cpar = psf.c(), params.c()
+    st = lib.deblur_rrrl_iterate_noalloc(f.data_ptr(), u_in.data_ptr(), u_out.data_ptr(), H, W, pitch,
+                                         ctypes.byref(cpsf), ctypes.byref(cpar),
+                                         ckpt.data_ptr() if ckpt is not None else None, _stream(f))
+    _lib.check(st, "deblur_rrrl_iterate_noalloc")
     return u_out
 
 

@@ -13,6 +13,8 @@ DEBLUR_EINVAL = -1
 DEBLUR_EUNSUPPORTED = -2
 DEBLUR_EWORKSPACE = -3
 DEBLUR_EDEVICE = -4
+DEBLUR_ESCRATCH = -5
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 PSF_BOX_H, PSF_BOX_V, PSF_TAPS = 0, 1, 2
 BC_REPLICATE, BC_PERIODIC = 0, 1
@@ -53,6 +55,7 @@ SIGNATURES = [
                                      _VP, _SZ, _VP]),
     ("deblur_rrrl_start", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _I32, ctypes.c_float, _VP]),
     ("deblur_rrrl_iterate", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP, _SZ, _VP]),
+    ("deblur_rrrl_iterate_noalloc", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP]),
     ("deblur_rrrl_backward", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _I32, ctypes.c_double,
                                             ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     ("deblur_batch_plan_create", ctypes.c_int, [ctypes.POINTER(deblur_batch_item), _I32, _I32,

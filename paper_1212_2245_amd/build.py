@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdeblur.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["wiener.hip", "rrrl_taps.hip", "rrrl_box.hip", "rrrl_backward.hip", "rrrl_fft.hip", "batch.hip", "start.hip",
+SOURCES = ["wiener.hip", "rrrl_taps.hip", "rrrl_box.hip", "rrrl_backward.hip", "rrrl_fft.hip", "batch.hip", "start.hip", "noalloc.hip",
            "driver.cpp", "deblur_abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -174,6 +174,44 @@ IterParams iter_params(const deblur_params* p)
     return q;
 }
 
+// deblur_rrrl_iterate and its no-allocation variant: validation, then the
+// iteration driver on the caller's workspace or, when use_static, on the
+// library's static scratch (after checking that the need fits in it).
+int iterate_impl(const float* f, const float* u_in, float* u_out, int32_t H, int32_t W, int32_t pitch,
+                 const deblur_psf* psf, const deblur_params* p, float* ckpt, void* ws, size_t ws_bytes,
+                 bool use_static, void* stream)
+{
+    PsfDev d;
+    if (!f || !u_in || !u_out) return DEBLUR_EINVAL;
+    int s = check_iterate(H, W, pitch, psf, p, &d);
+    if (s) return s;
+    const size_t img = (size_t)H * pitch * sizeof(float);
+    if (overlaps(f, img, u_out, img) || (u_in != u_out && overlaps(u_in, img, u_out, img))) return DEBLUR_EINVAL;
+    if (ckpt) {
+        const size_t ck = img * (size_t)p->iters;
+        if (overlaps(ckpt, ck, f, img) || overlaps(ckpt, ck, u_in, img) || overlaps(ckpt, ck, u_out, img))
+            return DEBLUR_EINVAL;
+    }
+    const bool fft = p->conv == DEBLUR_CONV_FFT;
+    const bool box = !fft && use_box(d, p);
+    const size_t need = fft ? fft_iter_ws_bytes(H, W, pitch) : iterate_ws_bytes(H, W, pitch, d, box);
+    if (use_static) {
+        if (need > NOALLOC_SCRATCH_BYTES) return DEBLUR_ESCRATCH;
+        hipError_t e = hipSuccess;
+        ws = noalloc_scratch(&e);
+        if (!ws) return DEBLUR_EDEVICE;
+        ws_bytes = NOALLOC_SCRATCH_BYTES;
+    }
+    if (!ws || ws_bytes < need) return DEBLUR_EWORKSPACE;
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (fft) {
+        s = launch_rrrl_fft(f, u_in, u_out, H, W, pitch, d, iter_params(p), p->iters, ckpt, ws, st);
+        return s == 0 ? DEBLUR_OK : DEBLUR_EDEVICE;
+    }
+    s = launch_rrrl_iterate(f, u_in, u_out, H, W, pitch, d, iter_params(p), p->iters, ckpt, box, ws, st);
+    return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EUNSUPPORTED : DEBLUR_EDEVICE);
+}
+
 }  // namespace
 
 struct deblur_batch_plan {
@@ -190,6 +228,7 @@ const char* deblur_status_string(int status)
         case DEBLUR_EUNSUPPORTED: return "unsupported configuration";
         case DEBLUR_EWORKSPACE: return "workspace missing or too small";
         case DEBLUR_EDEVICE: return "HIP device or launch failure";
+        case DEBLUR_ESCRATCH: return "problem exceeds the static scratch of the no-allocation entry point";
         default: return "unknown status";
     }
 }
@@ -253,29 +292,16 @@ int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t
                         const deblur_psf* psf, const deblur_params* p, float* ckpt, void* ws, size_t ws_bytes,
                         void* stream)
 {
-    PsfDev d;
-    if (!f || !u_in || !u_out) return DEBLUR_EINVAL;
-    int s = check_iterate(H, W, pitch, psf, p, &d);
-    if (s) return s;
-    const size_t img = (size_t)H * pitch * sizeof(float);
-    if (overlaps(f, img, u_out, img) || (u_in != u_out && overlaps(u_in, img, u_out, img))) return DEBLUR_EINVAL;
-    if (ckpt) {
-        const size_t ck = img * (size_t)p->iters;
-        if (overlaps(ckpt, ck, f, img) || overlaps(ckpt, ck, u_in, img) || overlaps(ckpt, ck, u_out, img))
-            return DEBLUR_EINVAL;
-    }
-    if (p->conv == DEBLUR_CONV_FFT) {
-        if (!ws || ws_bytes < fft_iter_ws_bytes(H, W, pitch)) return DEBLUR_EWORKSPACE;
-        s = launch_rrrl_fft(f, u_in, u_out, H, W, pitch, d, iter_params(p), p->iters, ckpt, ws,
-                            reinterpret_cast<hipStream_t>(stream));
-        return s == 0 ? DEBLUR_OK : DEBLUR_EDEVICE;
-    }
-    const bool box = use_box(d, p);
-    const size_t need = iterate_ws_bytes(H, W, pitch, d, box);
-    if (!ws || ws_bytes < need) return DEBLUR_EWORKSPACE;
-    s = launch_rrrl_iterate(f, u_in, u_out, H, W, pitch, d, iter_params(p), p->iters, ckpt, box, ws,
-                            reinterpret_cast<hipStream_t>(stream));
-    return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EUNSUPPORTED : DEBLUR_EDEVICE);
+    return iterate_impl(f, u_in, u_out, H, W, pitch, psf, p, ckpt, ws, ws_bytes, false, stream);
+}
+
+int deblur_rrrl_iterate_noalloc(const float* f, const float* u_in, float* u_out, int32_t H, int32_t W,
+                                int32_t pitch, const deblur_psf* psf, const deblur_params* p, float* ckpt,
+                                void* stream)
+{
+    // the lookup mode would allocate its table on first use
+    if (p && p->rf_lut) return DEBLUR_EUNSUPPORTED;
+    return iterate_impl(f, u_in, u_out, H, W, pitch, psf, p, ckpt, nullptr, 0, true, stream);
 }
 
 int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int32_t H, int32_t W,

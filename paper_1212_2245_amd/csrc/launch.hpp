@@ -142,6 +142,12 @@ size_t fft_iter_ws_bytes(int H, int W, int pitch);
 int launch_rrrl_fft(const float* f, const float* u_in, float* u_out, int H, int W, int pitch, const PsfDev& psf,
                     const IterParams& p, int iters, float* ckpt, void* ws, hipStream_t st);
 
+// Static scratch of the no-allocation iterate entry point (noalloc.hip): its
+// size, and the device address of the calling device's copy (looked up once
+// per device; nullptr and *err set on failure).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+void* noalloc_scratch(hipError_t* err);
+
 // Batched plans (batch.hip)
 struct BatchPlan;
 struct BatchItemDev {

@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_status_strings(lib):
-    for s in (0, -1, -2, -3, -4):
+    for s in (0, -1, -2, -3, -4, -5):
         assert lib.deblur_status_string(s)
     assert lib.deblur_status_string(7) == b"unknown status"
     assert lib.deblur_version() >= 100
@@ -143,6 +143,29 @@ def test_iterate_validation(lib):
     assert iterate(lib, ui=V) == W_                               # u_in == u_out is allowed
     assert iterate(lib) == W_
     assert iterate(lib, ws=WS, wsb=64) == W_
+
+
+def test_iterate_noalloc_validation(lib):
+    """Error paths of the no-allocation variant: rejected before the static
+    scratch is looked up or anything is enqueued."""
+    E, U_, S_ = _lib.DEBLUR_EINVAL, _lib.DEBLUR_EUNSUPPORTED, _lib.DEBLUR_ESCRATCH
+
+    def call(f=F, ui=U, uo=V, H=64, W=64, pitch=64, psf=None, p=None, ck=None):
+        psf = psf if psf is not None else box()
+        p = p if p is not None else params()
+        return lib.deblur_rrrl_iterate_noalloc(f, ui, uo, H, W, pitch, ctypes.byref(psf), ctypes.byref(p), ck, None)
+
+    assert call(f=None) == E
+    assert call(uo=F) == E
+    assert call(p=params(alpha=-1.0)) == E
+    assert call(p=params(rf_lut=1)) == U_                        # the lookup mode would allocate its table
+    assert lib.deblur_rrrl_iterate_noalloc(F, U, V, 64, 64, 64, ctypes.byref(box()), None, None, None) == E
+    # stencil path at 2048 x 2048: 16 B/px of workspace plus the tap list > 64 MiB
+    need = lib.deblur_workspace_bytes(1, 2048, 2048, 2048, ctypes.byref(taps(5, 5)), ctypes.byref(params()))
+    assert need > _lib.NOALLOC_SCRATCH_BYTES
+    far = 0x1000000000
+    assert call(f=far, ui=2 * far, uo=3 * far, H=2048, W=2048, pitch=2048, psf=taps(5, 5)) == S_
+    assert lib.deblur_status_string(S_) and b"scratch" in lib.deblur_status_string(S_)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
