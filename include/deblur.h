@@ -99,9 +99,10 @@ typedef struct {
     int32_t robust;  /* 1: W = Phi'(r_f(u*h)) (eq. (10)); 0: W = 1 (plain RL data term) */
     int32_t boundary;/* deblur_boundary */
     int32_t conv;    /* deblur_conv */
-    int32_t tile;    /* tile shape of the stencil kernels: 0 = library default for the image
-                        size, 1..deblur_tile_variants() = an explicit shape (an autotuner's
-                        choice); all shapes give bitwise-identical results */
+    int32_t tile;    /* tile shape: 0 = library default for the image size, else an explicit
+                        shape (an autotuner's choice), 1..deblur_tile_variants() for the stencil
+                        kernels, 1..deblur_box_tile_variants() for the running-sum kernel (boxes
+                        with conv AUTO or RUNSUM); all shapes give bitwise-identical results */
     int32_t psi;     /* regulariser Psi (Sec. 2.3): 0 = regularised TV, Psi(z) = sqrt(z + eps^2);
                         1 = Perona-Malik, Psi(z) = (lambda^2/2) ln(1 + z/lambda^2), non-convex in
                         |grad u| (diffusivity lambda^2 / (lambda^2 + z)); else DEBLUR_EINVAL */
@@ -118,8 +119,11 @@ const char* deblur_status_string(int status);
 /* Library ABI version (major*10000 + minor*100 + patch). */
 int deblur_version(void);
 
-/* Number of explicit tile shapes selectable through deblur_params.tile. */
+/* Number of explicit tile shapes selectable through deblur_params.tile:
+ * of the stencil kernels (TAPS PSFs, or boxes with conv = STENCIL) and of the
+ * running-sum kernel (boxes otherwise). */
 int deblur_tile_variants(void);
+int deblur_box_tile_variants(void);
 
 /* Workspace bytes needed by an entry point: op 0 = deblur_wiener,
  * 1 = deblur_rrrl_iterate, 2 = deblur_rrrl_backward without the Wiener step,

@@ -50,6 +50,7 @@ SIGNATURES = [
     ("deblur_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("deblur_version", ctypes.c_int, []),
     ("deblur_tile_variants", ctypes.c_int, []),
+    ("deblur_box_tile_variants", ctypes.c_int, []),
     ("deblur_workspace_bytes", _SZ, [_I32, _I32, _I32, _I32, _PSF, _PAR]),
     ("deblur_wiener", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _PSF, ctypes.c_double, ctypes.c_float,
                                      _VP, _SZ, _VP]),

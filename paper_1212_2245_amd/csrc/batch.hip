@@ -16,7 +16,7 @@
 #include <cstdint>
 #include <vector>
 
-#include "box_tiles.hpp"
+#include "box_seg.hpp"
 #include "launch.hpp"
 #include "psf.hpp"
 #include "stencil_tiles.hpp"
@@ -63,17 +63,19 @@ __global__ void __launch_bounds__(BT_NT) batch_stage2(const BatchTile* __restric
                                    t.y0, im.taps, im.hdr, im.p);
 }
 
+// Box tiles of the batch: one tile shape per orientation for all sizes.
+constexpr int BBH_TA = 64, BBH_TC = 8, BBV_TA = 64, BBV_TC = 8;
+
 template <bool VERT>
-__global__ void __launch_bounds__(256) batch_box(const BatchTile* __restrict__ tiles, const BatchImg* __restrict__ imgs,
-                                                 int src)
+__global__ void __launch_bounds__(BOX_NT) batch_box(const BatchTile* __restrict__ tiles,
+                                                    const BatchImg* __restrict__ imgs, int src)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int TA = VERT ? BOXV_TA : BOXH_TA, TC = VERT ? BOXV_TC : BOXH_TC;
+    extern __shared__ __align__(16) float box_lds[];
+    constexpr int TA = VERT ? BBV_TA : BBH_TA, TC = VERT ? BBV_TC : BBH_TC;
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
-    const BoxTile bt = make_tile(im.H, im.W, im.L, im.frac, VERT, TA);
-    box_iter_tile<VERT, TA, TC>(smem_raw, im.buf[src], im.f, im.buf[1 - src], nullptr, im.pitch, bt, im.p, t.x0,
-                                t.y0);
+    const BoxGeom g = box_geom<VERT, TA, TC>(im.H, im.W, im.L, im.frac);
+    box_seg_tile<VERT, TA, TC>(box_lds, im.buf[src], im.f, im.buf[1 - src], nullptr, im.pitch, g, im.p, t.x0, t.y0);
 }
 
 __global__ void batch_timestamp(unsigned long long* ts, int slot)
@@ -198,13 +200,15 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
                     for (int x0 = 0; x0 < it.W; x0 += 64) host[cls].push_back({i, x0, y0, 0});
             } else {
                 const bool vert = cls == CL_BOXV;
-                const int TA = vert ? BOXV_TA : BOXH_TA, TC = vert ? BOXV_TC : BOXH_TC;
+                const int TA = vert ? BBV_TA : BBH_TA, TC = vert ? BBV_TC : BBH_TC;
                 const int along = vert ? it.H : it.W, across = vert ? it.W : it.H;
                 for (int c0 = 0; c0 < across; c0 += TC)
                     for (int a0 = 0; a0 < along; a0 += TA) host[cls].push_back({i, a0, c0, 0});
-                const BoxTile bt = make_tile(it.H, it.W, it.psf.length, it.psf.frac, vert, TA);
-                const size_t lds = vert ? box_lds_bytes<true, BOXV_TA, BOXV_TC>(bt)
-                                        : box_lds_bytes<false, BOXH_TA, BOXH_TC>(bt);
+                const size_t lds =
+                    4 * (size_t)(vert ? box_lds_words<true, BBV_TA, BBV_TC>(
+                                            box_geom<true, BBV_TA, BBV_TC>(it.H, it.W, it.psf.length, it.psf.frac))
+                                      : box_lds_words<false, BBH_TA, BBH_TC>(
+                                            box_geom<false, BBH_TA, BBH_TC>(it.H, it.W, it.psf.length, it.psf.frac)));
                 lists[g][cls].lds = std::max(lists[g][cls].lds, lds);
             }
         }
@@ -297,10 +301,10 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
                     hipLaunchKernelGGL(batch_stage2<32>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
                     break;
                 case CL_BOXH:
-                    hipLaunchKernelGGL(batch_box<false>, grid, dim3(256), L[cls].lds, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_box<false>, grid, dim3(BOX_NT), L[cls].lds, cs, d, dimgs, src);
                     break;
                 default:
-                    hipLaunchKernelGGL(batch_box<true>, grid, dim3(256), L[cls].lds, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_box<true>, grid, dim3(BOX_NT), L[cls].lds, cs, d, dimgs, src);
                     break;
             }
         };

@@ -137,6 +137,8 @@ int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, co
     }
     if (p->conv == DEBLUR_CONV_RUNSUM && d->kind == DEBLUR_PSF_TAPS) return DEBLUR_EINVAL;
     if (p->tile < 0 || p->tile > taps_num_variants()) return DEBLUR_EINVAL;
+    if (d->kind != DEBLUR_PSF_TAPS && p->conv != DEBLUR_CONV_STENCIL && p->tile > box_num_variants())
+        return DEBLUR_EINVAL;
     const int rad = (d->ph - 1) / 2 > (d->pw - 1) / 2 ? (d->ph - 1) / 2 : (d->pw - 1) / 2;
     if (tap_radius_class(rad) < 0) return DEBLUR_EUNSUPPORTED;
     if ((d->ph - 1) / 2 > H || (d->pw - 1) / 2 > W) return DEBLUR_EINVAL;
@@ -236,6 +238,8 @@ const char* deblur_status_string(int status)
 int deblur_version(void) { return 100; }
 
 int deblur_tile_variants(void) { return taps_num_variants(); }
+
+int deblur_box_tile_variants(void) { return box_num_variants(); }
 
 size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
                               const deblur_params* p)

@@ -119,6 +119,10 @@ int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, 
 // 1 the observed image; both floored at pos_floor.
 int launch_rrrl_start(const float* f, float* u0, int H, int W, int pitch, int mode, float pos_floor, hipStream_t st);
 
+// Box tile shapes: count of explicit variants (deblur_params.tile for the
+// running-sum path) and the default for an image.
+int box_num_variants();
+int box_default_variant(int H, int W, bool vert);
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
                          float frac, bool vert, const IterParams& p, hipStream_t st);
 

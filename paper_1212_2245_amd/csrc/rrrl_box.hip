@@ -1,71 +1,74 @@
-// Single-image launcher of the fused box-iteration kernel (tiles in
-// box_tiles.hpp).
+// Single-image launcher of the fused box-iteration kernel (tile body in
+// box_seg.hpp).  Three tile shapes per orientation; every shape gives
+// bitwise-identical results (re-basing points are image coordinates).
 #include <mutex>
 
-#include "box_tiles.hpp"
+#include "box_seg.hpp"
 
 namespace deblur {
 
+// Tiles in raster order (along the blur axis fastest), remapped so that the
+// workgroups of one XCD take a contiguous range: tiles that share halos then
+// mostly share an L2.
 template <bool VERT, int TA, int TC>
-__global__ void __launch_bounds__(256) rrrl_box_iter(const float* __restrict__ u, const float* __restrict__ f,
-                                                     float* __restrict__ un, float* __restrict__ ckpt, int pitch,
-                                                     BoxTile bt, IterParams p)
+__global__ void __launch_bounds__(BOX_NT) rrrl_box_iter(const float* __restrict__ u, const float* __restrict__ f,
+                                                        float* __restrict__ un, float* __restrict__ ckpt, int pitch,
+                                                        BoxGeom g, IterParams p, int tiles_along)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    // vertical blur: tiles in raster order, a contiguous range per XCD, so the
-    // tiles above and below (which share halo rows) mostly share an L2 (for
-    // horizontal blur the neighbours along the axis are adjacent blocks and
-    // the default order measured as fast)
-    const int b = blockIdx.y * gridDim.x + blockIdx.x;
-    const int w = VERT ? xcd_group(b, gridDim.x * gridDim.y) : b;
-    const int by = w / gridDim.x, bx = w - by * gridDim.x;
-    box_iter_tile<VERT, TA, TC>(smem_raw, u, f, un, ckpt, pitch, bt, p, (VERT ? by : bx) * TA, (VERT ? bx : by) * TC);
+    extern __shared__ __align__(16) float box_lds[];
+    const int w = xcd_group(blockIdx.x, gridDim.x);
+    const int tc = w / tiles_along, ta = w - tc * tiles_along;
+    box_seg_tile<VERT, TA, TC>(box_lds, u, f, un, ckpt, pitch, g, p, ta * TA, tc * TC);
 }
 
-// ------------------------------------------------------------ host launchers
-// Tiles for long boxes need more than 64 KB of dynamic LDS (gfx950 has
-// 160 KB per workgroup); the limit is raised once per process.
-static void allow_large_lds()
+template <bool VERT, int TA, int TC>
+static void launch_box(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
+                       float frac, const IterParams& p, hipStream_t st)
 {
     static std::once_flag once;
     std::call_once(once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<false, BOXH_WIDE_TA, BOXH_WIDE_TC>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<false, BOXH_TA, BOXH_TC>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<true, BOXV_TA, BOXV_TC>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rrrl_box_iter<VERT, TA, TC>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     });
+    const BoxGeom g = box_geom<VERT, TA, TC>(H, W, L, frac);
+    const int ta = (g.N + TA - 1) / TA, tc = (g.M + TC - 1) / TC;
+    const size_t lds = (size_t)box_lds_words<VERT, TA, TC>(g) * sizeof(float);
+    hipLaunchKernelGGL((rrrl_box_iter<VERT, TA, TC>), dim3(ta * tc), dim3(BOX_NT), lds, st, u, f, un, ckpt, pitch, g,
+                       p, ta);
+}
+
+int box_num_variants() { return 4; }
+
+// Default shape per orientation and size (variant 0); 1..4 explicit.  Small
+// images take the small tiles (2 outputs per thread), which spread them over
+// more compute units.
+int box_default_variant(int H, int W, bool vert)
+{
+    if ((long)H * W <= 512L * 512L) return 4;
+    return vert ? 1 : 1;
 }
 
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
                          float frac, bool vert, const IterParams& p, hipStream_t st)
 {
-    allow_large_lds();
-    // tile shapes: vertical blur BOXV at every size measured (256^2 ..
-    // 2048^2); horizontal blur BOXH up to 512^2 (a 256^2 image gives only 64
-    // workgroups with wide tiles), BOXH_WIDE above
+    int v = p.tile > 0 ? p.tile : box_default_variant(H, W, vert);
+    if (v > box_num_variants()) return -2;
     if (vert) {
-        const BoxTile bt = make_tile(H, W, L, frac, true, BOXV_TA);
-        const dim3 g((W + BOXV_TC - 1) / BOXV_TC, (H + BOXV_TA - 1) / BOXV_TA);
-        const size_t lds = box_lds_bytes<true, BOXV_TA, BOXV_TC>(bt);
-        hipLaunchKernelGGL((rrrl_box_iter<true, BOXV_TA, BOXV_TC>), g, dim3(256), lds, st, u, f, un, ckpt, pitch,
-                           bt, p);
-    } else if ((long)H * W <= 512L * 512L) {
-        const BoxTile bt = make_tile(H, W, L, frac, false, BOXH_TA);
-        const dim3 g((W + BOXH_TA - 1) / BOXH_TA, (H + BOXH_TC - 1) / BOXH_TC);
-        const size_t lds = box_lds_bytes<false, BOXH_TA, BOXH_TC>(bt);
-        hipLaunchKernelGGL((rrrl_box_iter<false, BOXH_TA, BOXH_TC>), g, dim3(256), lds, st, u, f, un, ckpt, pitch,
-                           bt, p);
+        switch (v) {
+            case 1: launch_box<true, 128, 16>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            case 2: launch_box<true, 256, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            case 3: launch_box<true, 64, 32>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            default: launch_box<true, 64, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+        }
     } else {
-        const BoxTile bt = make_tile(H, W, L, frac, false, BOXH_WIDE_TA);
-        const dim3 g((W + BOXH_WIDE_TA - 1) / BOXH_WIDE_TA, (H + BOXH_WIDE_TC - 1) / BOXH_WIDE_TC);
-        const size_t lds = box_lds_bytes<false, BOXH_WIDE_TA, BOXH_WIDE_TC>(bt);
-        hipLaunchKernelGGL((rrrl_box_iter<false, BOXH_WIDE_TA, BOXH_WIDE_TC>), g, dim3(256), lds, st, u, f, un,
-                           ckpt, pitch, bt, p);
+        switch (v) {
+            case 1: launch_box<false, 256, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            case 2: launch_box<false, 128, 16>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            case 3: launch_box<false, 64, 32>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            default: launch_box<false, 64, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+        }
     }
     return 0;
 }
-
 
 }  // namespace deblur
