@@ -127,7 +127,7 @@ int deblur_box_tile_variants(void);
 
 /* Workspace bytes needed by an entry point: op 0 = deblur_wiener,
  * 1 = deblur_rrrl_iterate, 2 = deblur_rrrl_backward without the Wiener step,
- * 3 = deblur_rrrl_backward through the Wiener step.  Returns 0 for invalid
+ * 3 = deblur_rrrl_backward through the Wiener step, 4 = deblur_wiener_fp64.  Returns 0 for invalid
  * arguments (the matching call then returns DEBLUR_EINVAL or
  * DEBLUR_EUNSUPPORTED). */
 size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
@@ -142,6 +142,17 @@ size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, c
  * division is done in FP64, the transforms in FP32. */
 int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
                   double K, float pos_floor, void* ws, size_t ws_bytes, void* stream);
+
+/* The Wiener initialisation of deblur_wiener (same formula, arguments,
+ * layouts and errors) with the multiplier M, the spectra and the transforms
+ * in FP64; only the output is rounded, once, to FP32.  The FP32 transforms of
+ * deblur_wiener leave u0 a few units of FP32 roundoff away from the exact
+ * result; this variant rounds it correctly, which matters where the output
+ * feeds a gradient of an ill-conditioned iteration (the periodic Wiener step
+ * rings at image borders, Sec. 4.2).  Workspace: deblur_workspace_bytes(4,
+ * ...), twice that of deblur_wiener. */
+int deblur_wiener_fp64(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                       double K, float pos_floor, void* ws, size_t ws_bytes, void* stream);
 
 /* Starting image for RRRL without the Wiener step (Sec. 2.3; the RRRL columns
  * of Table 1 start from an image the paper does not state):

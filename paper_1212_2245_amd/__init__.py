@@ -11,6 +11,7 @@ functions carry the C names (deblur_wiener, deblur_rrrl_iterate, ...);
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import math
 from dataclasses import dataclass
 
@@ -118,17 +119,20 @@ def deblur_workspace_bytes(op: int, H: int, W: int, pitch: int, psf: Psf, params
 
 
 def deblur_wiener(f: torch.Tensor, u0: torch.Tensor, psf: Psf, K: float = 0.01, pos_floor: float = 1.0,
-                  ws: torch.Tensor | None = None) -> torch.Tensor:
-    """u0 <- max(Re IDFT(DFT(f) conj(h^)/(|h^|^2+K)), pos_floor), on f's stream."""
+                  ws: torch.Tensor | None = None, fp64: bool = False) -> torch.Tensor:
+    """u0 <- max(Re IDFT(DFT(f) conj(h^)/(|h^|^2+K)), pos_floor), on f's stream.
+    fp64=True: deblur_wiener_fp64 (transforms in FP64, output rounded once)."""
     lib = _lib.load()
     H, W, pitch = _image(f, "f")
     _same_layout((H, W, pitch), _image(u0, "u0"), "f", "u0")
     cpsf = psf.c()
-    need = lib.deblur_workspace_bytes(_lib.OP_WIENER, H, W, pitch, ctypes.byref(cpsf), None)
+    op = _lib.OP_WIENER_FP64 if fp64 else _lib.OP_WIENER
+    need = lib.deblur_workspace_bytes(op, H, W, pitch, ctypes.byref(cpsf), None)
     wst = _workspace(need, f, ws)
-    st = lib.deblur_wiener(f.data_ptr(), u0.data_ptr(), H, W, pitch, ctypes.byref(cpsf), float(K),
-                           float(pos_floor), wst.data_ptr(), wst.numel(), _stream(f))
-    _lib.check(st, "deblur_wiener")
+    fn, name = (lib.deblur_wiener_fp64, "deblur_wiener_fp64") if fp64 else (lib.deblur_wiener, "deblur_wiener")
+    st = fn(f.data_ptr(), u0.data_ptr(), H, W, pitch, ctypes.byref(cpsf), float(K), float(pos_floor),
+            wst.data_ptr(), wst.numel(), _stream(f))
+    _lib.check(st, name)
     return u0
 
 
@@ -200,11 +204,12 @@ def deblur_rrrl_iterate_noalloc(f: torch.Tensor, u_in: torch.Tensor, u_out: torc
 
 
 def wr3l(f: torch.Tensor, psf: Psf, K: float = 0.01, params: Params | None = None,
-         pos_floor: float = 1.0, out: torch.Tensor | None = None) -> torch.Tensor:
-    """WR3L (Sec. 3.2): Wiener initialisation, then params.iters RRRL steps."""
+         pos_floor: float = 1.0, out: torch.Tensor | None = None, wiener_fp64: bool = False) -> torch.Tensor:
+    """WR3L (Sec. 3.2): Wiener initialisation, then params.iters RRRL steps
+    (wiener_fp64: the Wiener step through deblur_wiener_fp64)."""
     params = params or Params()
     u = out if out is not None else torch.empty_like(f)
-    deblur_wiener(f, u, psf, K, pos_floor)
+    deblur_wiener(f, u, psf, K, pos_floor, fp64=wiener_fp64)
     return deblur_rrrl_iterate(f, u, u, psf, params)
 
 
@@ -304,44 +309,83 @@ def deblur_rrrl_backward(f: torch.Tensor, ckpt: torch.Tensor | None, grad_uK: to
 class WR3LFunction(torch.autograd.Function):
     """u = WR3L(f; h, alpha) with the hand-written adjoint as backward.
 
-    forward(f [H,W], taps [ph,pw] (general PSF entries), alpha (0-dim tensor),
-    K, iters, params_template) stores the per-iteration checkpoints u^k and
-    the backward recomputes every other quantity from them."""
+    forward(f, taps, alpha, K, iters, template, pos_floor):
+      f      [H, W] or a batch [B, H, W] (device float32);
+      taps   [ph, pw] shared by the batch, or [B, ph, pw] one PSF per image;
+      alpha  a scalar or a [B] tensor (one regulariser weight per image).  Its
+             values are launch parameters read on the host: a device tensor
+             costs one synchronisation per forward (pass it on the CPU to
+             avoid it);
+      template: the other RRRL parameters (penalisers, boundary, tile, ...),
+             all carried over; the lookup mode of r_f is not differentiable
+             here and is rejected;
+      pos_floor: the Wiener positivity floor (Sec. 3.2).
+    The Wiener step runs in FP64 (deblur_wiener_fp64): the gradient of the
+    unrolled iteration is ill-conditioned near the border ringing of the
+    periodic Wiener filter, and a correctly rounded u^0 keeps the GPU
+    gradient within 1e-3 of the FP64 one.  The per-iteration checkpoints u^k
+    are stored; the backward recomputes every other quantity from them."""
 
     @staticmethod
-    def forward(ctx, f, taps, alpha, K: float, iters: int, template: Params | None = None):
+    def forward(ctx, f, taps, alpha, K: float, iters: int, template: Params | None = None, pos_floor: float = 1.0):
         base = template or Params()
-        params = Params(alpha=float(alpha), iters=int(iters), eps_data=base.eps_data, eps_tv=base.eps_tv,
-                        s_min=base.s_min, robust=base.robust, boundary=base.boundary, conv=base.conv,
-                        tile=base.tile)
-        f = f.contiguous()
-        psf = Psf.from_taps(taps.detach().contiguous())
-        H, W = f.shape
-        u = torch.empty_like(f)
-        deblur_wiener(f, u, psf, K, 1.0)
-        ck = torch.empty((max(iters, 1), H, W), dtype=torch.float32, device=f.device)
-        deblur_rrrl_iterate(f, u, u, psf, params, ckpt=ck if iters > 0 else None)
-        ctx.save_for_backward(f, psf.taps, ck)
-        ctx.params, ctx.K = params, K
+        if base.rf_lut:
+            raise ValueError("WR3LFunction differentiates the exact r_f: template.rf_lut must be False")
+        batched = f.dim() == 3
+        fb = (f if batched else f.unsqueeze(0)).contiguous()
+        B, H, W = fb.shape
+        tb = taps.detach()
+        if tb.dim() == 2:
+            tb = tb.unsqueeze(0).expand(B, -1, -1)
+        tb = tb.contiguous()
+        if tb.shape[0] != B:
+            raise ValueError("taps must be [ph, pw] or [B, ph, pw]")
+        a = torch.as_tensor(alpha).detach().to("cpu", torch.float64).reshape(-1)
+        if a.numel() not in (1, B):
+            raise ValueError("alpha must be a scalar or hold one value per image")
+        alphas = [float(a[i if a.numel() > 1 else 0]) for i in range(B)]
+        u = torch.empty_like(fb)
+        ck = torch.empty((B, max(iters, 1), H, W), dtype=torch.float32, device=f.device)
+        plist = []
+        for i in range(B):
+            p = dataclasses.replace(base, alpha=alphas[i], iters=int(iters))
+            psf = Psf.from_taps(tb[i])
+            deblur_wiener(fb[i], u[i], psf, K, pos_floor, fp64=True)
+            deblur_rrrl_iterate(fb[i], u[i], u[i], psf, p, ckpt=ck[i] if iters > 0 else None)
+            plist.append(p)
+        ctx.save_for_backward(fb, tb, ck)
+        ctx.plist, ctx.K, ctx.pos_floor = plist, K, pos_floor
+        ctx.batched, ctx.shared_taps = batched, taps.dim() == 2
+        ctx.alpha_shape = a.numel()
         ctx.alpha_like = alpha if isinstance(alpha, torch.Tensor) else None
-        return u
+        return u if batched else u[0]
 
     @staticmethod
     def backward(ctx, grad_u):
-        f, taps, ck = ctx.saved_tensors
-        g = deblur_rrrl_backward(f, ck if ctx.params.iters > 0 else None, grad_u.contiguous(), Psf.from_taps(taps),
-                                 ctx.params, through_wiener=True, K=ctx.K)
-        ga = g["alpha"]
+        fb, tb, ck = ctx.saved_tensors
+        gb = (grad_u if ctx.batched else grad_u.unsqueeze(0)).contiguous()
+        gf, gt, ga = torch.empty_like(fb), torch.empty_like(tb), torch.empty(fb.shape[0], device=fb.device)
+        for i, p in enumerate(ctx.plist):
+            g = deblur_rrrl_backward(fb[i], ck[i] if p.iters > 0 else None, gb[i], Psf.from_taps(tb[i]), p,
+                                     through_wiener=True, K=ctx.K, pos_floor=ctx.pos_floor)
+            gf[i].copy_(g["f"])
+            gt[i].copy_(g["taps"])
+            ga[i] = g["alpha"]
+        if ctx.shared_taps:
+            gt = gt.sum(0)
+        if ctx.alpha_shape == 1:
+            ga = ga.sum()
         if ctx.alpha_like is not None:
-            ga = ga.to(device=ctx.alpha_like.device, dtype=ctx.alpha_like.dtype)
-        return g["f"], g["taps"], ga, None, None, None
+            ga = ga.reshape(ctx.alpha_like.shape).to(device=ctx.alpha_like.device, dtype=ctx.alpha_like.dtype)
+        return (gf if ctx.batched else gf[0]), gt, ga, None, None, None, None
 
 
 def wr3l_autograd(f: torch.Tensor, taps: torch.Tensor, alpha: torch.Tensor, K: float = 0.01, iters: int = 10,
-                  template: Params | None = None) -> torch.Tensor:
+                  template: Params | None = None, pos_floor: float = 1.0) -> torch.Tensor:
     """Differentiable WR3L (w.r.t. f, taps, alpha) through the library's
-    forward and backward kernels."""
-    return WR3LFunction.apply(f, taps, alpha, K, iters, template)
+    forward and backward kernels; f is [H, W] or a batch [B, H, W] (see
+    WR3LFunction)."""
+    return WR3LFunction.apply(f, taps, alpha, K, iters, template, pos_floor)
 
 
 # --------------------------------------------------------------- batched

@@ -22,7 +22,7 @@ CONV_AUTO, CONV_RUNSUM, CONV_STENCIL, CONV_FFT = 0, 1, 2, 3
 PSI_TV, PSI_PERONA_MALIK = 0, 1
 START_FLAT, START_OBSERVED = 0, 1
 
-OP_WIENER, OP_ITERATE, OP_BACKWARD, OP_BACKWARD_WIENER = 0, 1, 2, 3
+OP_WIENER, OP_ITERATE, OP_BACKWARD, OP_BACKWARD_WIENER, OP_WIENER_FP64 = 0, 1, 2, 3, 4
 
 
 class deblur_psf(ctypes.Structure):
@@ -54,6 +54,8 @@ SIGNATURES = [
     ("deblur_workspace_bytes", _SZ, [_I32, _I32, _I32, _I32, _PSF, _PAR]),
     ("deblur_wiener", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _PSF, ctypes.c_double, ctypes.c_float,
                                      _VP, _SZ, _VP]),
+    ("deblur_wiener_fp64", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _PSF, ctypes.c_double, ctypes.c_float,
+                                          _VP, _SZ, _VP]),
     ("deblur_rrrl_start", ctypes.c_int, [_VP, _VP, _I32, _I32, _I32, _I32, ctypes.c_float, _VP]),
     ("deblur_rrrl_iterate", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP, _SZ, _VP]),
     ("deblur_rrrl_iterate_noalloc", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP]),

@@ -269,7 +269,7 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
             const BatchItemDev& it = items[i];
             const int c = k % kChains;
             ok = launch_wiener(it.f, imgs[i].buf[start], it.H, it.W, it.pitch, it.psf, it.K, it.pos_floor, wws[c],
-                               it.psf.ph == 1, P->chains[c]) == 0;
+                               it.psf.ph == 1, false, P->chains[c]) == 0;
         }
         for (int c = 0; c < kChains && ok; ++c) {
             hipEvent_t join = event();

@@ -245,9 +245,9 @@ size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, c
                               const deblur_params* p)
 {
     PsfDev d;
-    if (op == 0) {
+    if (op == 0 || op == 4) {
         if (check_wiener(H, W, pitch, psf, &d)) return 0;
-        return wiener_ws_bytes(H, W, wiener_rowwise(d));
+        return wiener_ws_bytes(H, W, wiener_rowwise(d), op == 4);
     }
     if (op == 1) {
         if (check_iterate(H, W, pitch, psf, p, &d)) return 0;
@@ -261,8 +261,8 @@ size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, c
     return 0;
 }
 
-int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
-                  double K, float pos_floor, void* ws, size_t ws_bytes, void* stream)
+static int wiener_impl(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                       double K, float pos_floor, void* ws, size_t ws_bytes, bool fp64, void* stream)
 {
     PsfDev d;
     if (!f || !u0) return DEBLUR_EINVAL;
@@ -271,10 +271,24 @@ int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch
     if (!(K > 0.0) || !std::isfinite(K) || !(pos_floor > 0.0f) || !std::isfinite(pos_floor)) return DEBLUR_EINVAL;
     const size_t img = (size_t)H * pitch * sizeof(float);
     if (overlaps(f, img, u0, img)) return DEBLUR_EINVAL;
-    const size_t need = wiener_ws_bytes(H, W, wiener_rowwise(d));
+    const size_t need = wiener_ws_bytes(H, W, wiener_rowwise(d), fp64);
     if (!ws || ws_bytes < need) return DEBLUR_EWORKSPACE;
-    return launch_wiener(f, u0, H, W, pitch, d, K, pos_floor, ws, wiener_rowwise(d),
-                         reinterpret_cast<hipStream_t>(stream));
+    return launch_wiener(f, u0, H, W, pitch, d, K, pos_floor, ws, wiener_rowwise(d), fp64,
+                         reinterpret_cast<hipStream_t>(stream)) == 0
+               ? DEBLUR_OK
+               : DEBLUR_EDEVICE;
+}
+
+int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                  double K, float pos_floor, void* ws, size_t ws_bytes, void* stream)
+{
+    return wiener_impl(f, u0, H, W, pitch, psf, K, pos_floor, ws, ws_bytes, false, stream);
+}
+
+int deblur_wiener_fp64(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                       double K, float pos_floor, void* ws, size_t ws_bytes, void* stream)
+{
+    return wiener_impl(f, u0, H, W, pitch, psf, K, pos_floor, ws, ws_bytes, true, stream);
 }
 
 int deblur_rrrl_start(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, int32_t mode,

@@ -6,6 +6,9 @@
 // in LDS and the twiddles exp(-2 pi i m / n) are generated in FP64 per
 // workgroup and rounded once to FP32.
 //
+// The same code runs in FP64 (complex type double2, FP64 twiddles) for the
+// Wiener step's FP64 variant.
+//
 // Stockham autosort formulation: pass p with radix R and stride Ns (product of
 // the radices already applied) maps butterfly j (0 <= j < n/R), k = j mod Ns,
 //   inputs   x[j + r n/R],  r = 0..R-1
@@ -36,6 +39,26 @@ DEBLUR_DEV float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 // multiply by -i
 DEBLUR_DEV float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
 
+DEBLUR_DEV double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+DEBLUR_DEV double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+DEBLUR_DEV double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+DEBLUR_DEV double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+DEBLUR_DEV double2 cmul_mi(double2 a) { return make_double2(a.y, -a.x); }
+
+// Real type and constructor of a complex type.
+template <typename C> struct Cplx;
+template <> struct Cplx<float2> {
+    using R = float;
+    static DEBLUR_DEV float2 make(float x, float y) { return make_float2(x, y); }
+};
+template <> struct Cplx<double2> {
+    using R = double;
+    static DEBLUR_DEV double2 make(double x, double y) { return make_double2(x, y); }
+};
+
 // Twiddle table tw[m] = exp(-2 pi i m / n), m < n, from FP64 sincospi rounded
 // once.  For n divisible by 8 only the first octant is evaluated and the rest
 // follows exactly from the symmetries of sin and cos (swaps and sign changes).
@@ -48,7 +71,7 @@ DEBLUR_DEV void twiddle_table(C* tw, int n)
         for (int m = threadIdx.x; m <= n / 8; m += blockDim.x) {
             double sd, cd;
             sincospi(2.0 * (double)m / (double)n, &sd, &cd);
-            const R c = (R)cd, s = (R)sd;
+            const R c = (R)cd, s = (R)sd;   // exact for R = double
             tw[m] = C{c, -s};
             tw[Q - m] = C{s, -c};
             tw[Q + m] = C{-s, -c};
@@ -68,39 +91,41 @@ DEBLUR_DEV void twiddle_table(C* tw, int n)
 }
 
 DEBLUR_DEV void fft_twiddles(float2* tw, int n) { twiddle_table(tw, n); }
+DEBLUR_DEV void fft_twiddles(double2* tw, int n) { twiddle_table(tw, n); }
 
-template <int R>
-DEBLUR_DEV void dft_small(float2* v)
+template <int R, typename C>
+DEBLUR_DEV void dft_small(C* v)
 {
+    using T = typename Cplx<C>::R;
     if constexpr (R == 2) {
-        const float2 a = v[0], b = v[1];
+        const C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     } else if constexpr (R == 3) {
-        const float c = 0.86602540378443864676f;  // sqrt(3)/2
-        const float2 t1 = cadd(v[1], v[2]);
-        const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
-        const float2 d = csub(v[1], v[2]);
-        const float2 t3 = make_float2(c * d.y, -c * d.x);  // -i * c * (v1 - v2)
+        const T c = (T)0.86602540378443864676;  // sqrt(3)/2
+        const C t1 = cadd(v[1], v[2]);
+        const C t2 = Cplx<C>::make(v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y);
+        const C d = csub(v[1], v[2]);
+        const C t3 = Cplx<C>::make(c * d.y, -c * d.x);  // -i * c * (v1 - v2)
         v[0] = cadd(v[0], t1);
         v[1] = cadd(t2, t3);
         v[2] = csub(t2, t3);
     } else if constexpr (R == 4) {
-        const float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-        const float2 s13 = cadd(v[1], v[3]), d13 = cmul_mi(csub(v[1], v[3]));
+        const C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const C s13 = cadd(v[1], v[3]), d13 = cmul_mi(csub(v[1], v[3]));
         v[0] = cadd(s02, s13);
         v[2] = csub(s02, s13);
         v[1] = cadd(d02, d13);
         v[3] = csub(d02, d13);
     } else if constexpr (R == 8) {
-        float2 e[4] = {v[0], v[2], v[4], v[6]};
-        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        C e[4] = {v[0], v[2], v[4], v[6]};
+        C o[4] = {v[1], v[3], v[5], v[7]};
         dft_small<4>(e);
         dft_small<4>(o);
-        const float r = 0.70710678118654752440f;
-        const float2 w1 = make_float2(r * (o[1].x + o[1].y), r * (o[1].y - o[1].x));   // (1-i)/sqrt2
-        const float2 w2 = cmul_mi(o[2]);                                               // -i
-        const float2 w3 = make_float2(r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)); // (-1-i)/sqrt2
+        const T r = (T)0.70710678118654752440;
+        const C w1 = Cplx<C>::make(r * (o[1].x + o[1].y), r * (o[1].y - o[1].x));   // (1-i)/sqrt2
+        const C w2 = cmul_mi(o[2]);                                                 // -i
+        const C w3 = Cplx<C>::make(r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y));  // (-1-i)/sqrt2
         v[0] = cadd(e[0], o[0]);
         v[4] = csub(e[0], o[0]);
         v[1] = cadd(e[1], w1);
@@ -112,9 +137,9 @@ DEBLUR_DEV void dft_small(float2* v)
     }
 }
 
-template <int R>
-DEBLUR_DEV void fft_pass(const float2* __restrict__ src, float2* __restrict__ dst, int nb,
-                         int n, int Ns, unsigned mag, const float2* __restrict__ tw)
+template <int R, typename C>
+DEBLUR_DEV void fft_pass(const C* __restrict__ src, C* __restrict__ dst, int nb,
+                         int n, int Ns, unsigned mag, const C* __restrict__ tw)
 {
     const int m = n / R;
     const int tstride = n / (Ns * R);
@@ -124,11 +149,11 @@ DEBLUR_DEV void fft_pass(const float2* __restrict__ src, float2* __restrict__ ds
     const bool pow2 = (m & (m - 1)) == 0;
     for (int bj = threadIdx.x; bj < nb * m; bj += blockDim.x) {
         const int t = pow2 ? bj >> lm : bj / m, j = bj - t * m;
-        const float2* s = src + t * n;
-        float2* d = dst + t * n;
+        const C* s = src + t * n;
+        C* d = dst + t * n;
         // k = j mod Ns by a multiply-high (exact for j < 2^21, Ns < 2^11)
         const int k = Ns == 1 ? 0 : j - (int)__umulhi((unsigned)j, mag) * Ns;
-        float2 v[R];
+        C v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = s[j + r * m];
         if (Ns > 1) {
@@ -145,7 +170,8 @@ DEBLUR_DEV void fft_pass(const float2* __restrict__ src, float2* __restrict__ ds
 // Forward FFT of nb rows of length p.n stored contiguously in `a`; `b` is a
 // scratch buffer of the same size.  Returns the buffer holding the result.
 // Must be called by all threads of the block; ends with a barrier.
-DEBLUR_DEV float2* fft_rows(float2* a, float2* b, int nb, const FftPlan& p, const float2* tw)
+template <typename C>
+DEBLUR_DEV C* fft_rows(C* a, C* b, int nb, const FftPlan& p, const C* tw)
 {
     int Ns = 1;
     for (int q = 0; q < p.npass; ++q) {
@@ -157,7 +183,7 @@ DEBLUR_DEV float2* fft_rows(float2* a, float2* b, int nb, const FftPlan& p, cons
             default: fft_pass<8>(a, b, nb, p.n, Ns, p.mag[q], tw); break;
         }
         __syncthreads();
-        float2* t = a;
+        C* t = a;
         a = b;
         b = t;
         Ns *= R;

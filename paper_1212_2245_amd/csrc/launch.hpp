@@ -86,9 +86,10 @@ inline size_t tap_packed_offset(int ph, int pw) { return tap_groups_offset(ph, p
 template <int RAD>
 constexpr int packed_words_max() { return 2 * (2 * RAD + 1) * (2 * RAD + 1); }
 
-size_t wiener_ws_bytes(int H, int W, bool rowwise);
+// Wiener step; fp64: M, spectra and transforms in FP64 (output rounded once).
+size_t wiener_ws_bytes(int H, int W, bool rowwise, bool fp64 = false);
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
-                  float pos_floor, void* ws, bool rowwise, hipStream_t st);
+                  float pos_floor, void* ws, bool rowwise, bool fp64, hipStream_t st);
 
 // 2D transform building blocks on half spectra H x (W/2+1) (complex64)
 void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st);

@@ -10,16 +10,35 @@ namespace deblur {
 // One column group applied to R consecutive output rows of one column.
 // A (blur, E(u)(x - d)): p points at tile row (first output row - dy0 - S + 1),
 // column (x - dx); v[k] = p[k LW] serves output i, tap s at k = i + S - 1 - s.
+// Column groups of at least GROUP_PARTIAL taps are summed into a partial of
+// their own that is then added to the pixel's total: a dense PSF's total then
+// takes one rounded addition per group instead of one per tap (the 961 taps of
+// a 31 x 31 PSF: 124 additions), which bounds its rounding error ~7x lower.
+// Shorter groups (sparse line PSFs) accumulate directly.
+constexpr int GROUP_PARTIAL = 4;
+
 template <int R, int S, int LW>
 DEBLUR_DEV void group_fma_a(const float* __restrict__ p, const float* w, float (&acc)[R])
 {
     float v[R + S - 1];
 #pragma unroll
     for (int k = 0; k < R + S - 1; ++k) v[k] = p[k * LW];
+    if constexpr (S >= GROUP_PARTIAL) {
+        float part[R];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
+        for (int i = 0; i < R; ++i) part[i] = w[0] * v[i + S - 1];
 #pragma unroll
-        for (int i = 0; i < R; ++i) acc[i] = fmaf(w[s], v[i + S - 1 - s], acc[i]);
+        for (int s = 1; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < R; ++i) part[i] = fmaf(w[s], v[i + S - 1 - s], part[i]);
+#pragma unroll
+        for (int i = 0; i < R; ++i) acc[i] += part[i];
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < R; ++i) acc[i] = fmaf(w[s], v[i + S - 1 - s], acc[i]);
+    }
 }
 
 // B (correlation, E(q, W)(x + d)) on the two-channel tile: p points at tile
@@ -30,13 +49,34 @@ DEBLUR_DEV void group_fma_b(const float2* __restrict__ p, const float* w, float 
     float2 v[R + S - 1];
 #pragma unroll
     for (int k = 0; k < R + S - 1; ++k) v[k] = p[k * LW];
-#pragma unroll
-    for (int s = 0; s < S; ++s)
+    if constexpr (S >= GROUP_PARTIAL) {
+        float p1[R], p2[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            n1[i] = fmaf(w[s], v[i + s].x, n1[i]);
-            n2[i] = fmaf(w[s], v[i + s].y, n2[i]);
+            p1[i] = w[0] * v[i].x;
+            p2[i] = w[0] * v[i].y;
         }
+#pragma unroll
+        for (int s = 1; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                p1[i] = fmaf(w[s], v[i + s].x, p1[i]);
+                p2[i] = fmaf(w[s], v[i + s].y, p2[i]);
+            }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            n1[i] += p1[i];
+            n2[i] += p2[i];
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                n1[i] = fmaf(w[s], v[i + s].x, n1[i]);
+                n2[i] = fmaf(w[s], v[i + s].y, n2[i]);
+            }
+    }
 }
 
 // Sum over all column groups in list order (by run length, longest first,

@@ -3,8 +3,9 @@
 //   u^0 = max( Re IDFT( DFT(f) * M ), pos_floor ),  M = conj(h^) / (|h^|^2 + K)
 //
 // with periodic continuation (Fourier domain, Sec. 4.2).  M is formed in FP64
-// (the division by |h^|^2 + K with small K) and stored as complex64; the
-// transforms run in FP32 in LDS.
+// (the division by |h^|^2 + K with small K).  Default: M stored as complex64,
+// transforms in FP32 in LDS.  FP64 variant (complex type double2): M, the
+// spectra and the transforms in FP64, the output rounded once to FP32.
 //
 // Two paths:
 //  * PSF supported on one row (horizontal motion): the 2D filter reduces to a
@@ -16,6 +17,7 @@
 //    multiply by M, inverse FFT), inverse row pass (Hermitian extension,
 //    rows packed again, inverse FFT, floor).
 #include <algorithm>
+#include <mutex>
 
 #include "fft_lds.hpp"
 #include "launch.hpp"
@@ -63,7 +65,8 @@ DEBLUR_DEV double2 psf_row_dft(const float* hrow, int pw, double2 w, double2 t)
 }
 
 // M(k) = conj(h^(k)) / (|h^(k)|^2 + K) for a PSF on one row, k < n.
-__global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double K, float2* __restrict__ M)
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double K, C* __restrict__ M)
 {
     __shared__ float hs[MULT_MAXP];
     psf_to_lds(psf, hs);
@@ -72,19 +75,22 @@ __global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double 
     if (k >= n) return;
     const double2 hk = psf_row_dft(hs, psf.pw, unit_root(k, n), unit_root(-k * ((psf.pw - 1) / 2), n));
     const double den = hk.x * hk.x + hk.y * hk.y + K;
-    M[k] = make_float2((float)(hk.x / den), (float)(-hk.y / den));
+    using R = typename Cplx<C>::R;
+    M[k] = Cplx<C>::make((R)(hk.x / den), (R)(-hk.y / den));
 }
 
 // One workgroup per `nb` row pairs; LDS: two ping-pong buffers of nb*n
 // complex plus the twiddle table.
+template <typename C>
 __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict__ f, float* __restrict__ u,
                                                          int H, int W, int pitch, int nb, FftPlan plan,
-                                                         const float2* __restrict__ M, float pos_floor)
+                                                         const C* __restrict__ M, float pos_floor)
 {
+    using R = typename Cplx<C>::R;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float2* tw = reinterpret_cast<float2*>(smem_raw);
-    float2* a = tw + W;
-    float2* b = a + nb * W;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* a = tw + W;
+    C* b = a + nb * W;
     fft_twiddles(tw, W);
 
     const int pair0 = blockIdx.x * nb;
@@ -93,11 +99,11 @@ __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict
         const int ya = 2 * (pair0 + t), yb = ya + 1;
         const float va = ya < H ? f[(size_t)ya * pitch + x] : 0.0f;
         const float vb = yb < H ? f[(size_t)yb * pitch + x] : 0.0f;
-        return make_float2(va, vb);
+        return Cplx<C>::make((R)va, (R)vb);
     });
     __syncthreads();
-    float2* X = fft_rows(a, b, nb, plan, tw);
-    float2* Y = X == a ? b : a;
+    C* X = fft_rows(a, b, nb, plan, tw);
+    C* Y = X == a ? b : a;
     // Y = conj(X * M): the inverse transform is conj(FFT(conj(.)))/n
     for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
         const int x = idx % W;
@@ -105,13 +111,13 @@ __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict
     }
     __syncthreads();
     X = fft_rows(X, Y, nb, plan, tw);
-    const float inv = 1.0f / (float)W;
+    const R inv = (R)1 / (R)W;
     for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
         const int t = idx / W, x = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
-        const float2 z = X[idx];
-        if (ya < H) u[(size_t)ya * pitch + x] = fmaxf(z.x * inv, pos_floor);
-        if (yb < H) u[(size_t)yb * pitch + x] = fmaxf(-z.y * inv, pos_floor);
+        const C z = X[idx];
+        if (ya < H) u[(size_t)ya * pitch + x] = fmaxf((float)(z.x * inv), pos_floor);
+        if (yb < H) u[(size_t)yb * pitch + x] = fmaxf((float)(-z.y * inv), pos_floor);
     }
 }
 
@@ -135,9 +141,11 @@ constexpr size_t MULT_G_OFF = 0, MULT_PQ_OFF = MULT_G_OFF + sizeof(double2) * MU
                  MULT_SMEM = MULT_ROT_OFF + sizeof(double2) * (MULT_KX + MULT_KY);
 
 // One block (bx, by) of M: kx in [16 bx, 16 bx + 16), ky in [64 by, 64 by + 64).
-DEBLUR_DEV void mult_2d_block(const PsfDev& psf, int H, int W, double K, float2* __restrict__ M,
+template <typename C>
+DEBLUR_DEV void mult_2d_block(const PsfDev& psf, int H, int W, double K, C* __restrict__ M,
                               float2* __restrict__ hh, int bx, int by, unsigned char* smem)
 {
+    using R = typename Cplx<C>::R;
     double2* G = reinterpret_cast<double2*>(smem + MULT_G_OFF);
     double2* PQ = reinterpret_cast<double2*>(smem + MULT_PQ_OFF);
     float* hs = reinterpret_cast<float*>(smem + MULT_HS_OFF);
@@ -211,7 +219,7 @@ DEBLUR_DEV void mult_2d_block(const PsfDev& psf, int H, int W, double K, float2*
         const int ky = ky0 + q0 + r * (256 / MULT_KX);
         if (ky >= H) break;
         const double inv = 1.0 / (re[r] * re[r] + im[r] * im[r] + K);
-        M[(size_t)ky * Wh + kx] = make_float2((float)(re[r] * inv), (float)(-im[r] * inv));
+        M[(size_t)ky * Wh + kx] = Cplx<C>::make((R)(re[r] * inv), (R)(-im[r] * inv));
         if (hh) hh[(size_t)ky * Wh + kx] = make_float2((float)re[r], (float)im[r]);
     }
 }
@@ -220,7 +228,7 @@ __global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, 
                                                       float2* __restrict__ hh)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    mult_2d_block(psf, H, W, K, M, hh, blockIdx.x, blockIdx.y, smem_raw);
+    mult_2d_block<float2>(psf, H, W, K, M, hh, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 static void mult_2d_launch(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
@@ -231,12 +239,14 @@ static void mult_2d_launch(const PsfDev& psf, int H, int W, double K, float2* M,
 
 // Row pass: rows (2p, 2p+1) packed as z = f_a + i f_b, FFT along x, unpacked
 // into the half spectra F_a(k), F_b(k), k <= W/2, written to S (row pitch W/2+1).
-DEBLUR_DEV void rows_fwd_block(const float* __restrict__ f, float2* __restrict__ S, int H, int W, int pitch, int nb,
+template <typename C>
+DEBLUR_DEV void rows_fwd_block(const float* __restrict__ f, C* __restrict__ S, int H, int W, int pitch, int nb,
                                const FftPlan& plan, int blk, unsigned char* smem_raw)
 {
-    float2* tw = reinterpret_cast<float2*>(smem_raw);
-    float2* a = tw + W;
-    float2* b = a + nb * W;
+    using R = typename Cplx<C>::R;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* a = tw + W;
+    C* b = a + nb * W;
     fft_twiddles(tw, W);
     const int pair0 = blk * nb;
     stage_to_lds_n<8>(a, nb * W, [&](int idx) {
@@ -244,23 +254,25 @@ DEBLUR_DEV void rows_fwd_block(const float* __restrict__ f, float2* __restrict__
         const int ya = 2 * (pair0 + t), yb = ya + 1;
         const float va = ya < H ? f[(size_t)ya * pitch + x] : 0.0f;
         const float vb = yb < H ? f[(size_t)yb * pitch + x] : 0.0f;
-        return make_float2(va, vb);
+        return Cplx<C>::make((R)va, (R)vb);
     });
     __syncthreads();
-    const float2* Z = fft_rows(a, b, nb, plan, tw);
+    const C* Z = fft_rows(a, b, nb, plan, tw);
     const int Wh = W / 2 + 1;
     for (int idx = threadIdx.x; idx < nb * Wh; idx += blockDim.x) {
         const int t = idx / Wh, k = idx - t * Wh;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
-        const float2 zk = Z[t * W + k];
-        const float2 zm = Z[t * W + (k == 0 ? 0 : W - k)];
+        const C zk = Z[t * W + k];
+        const C zm = Z[t * W + (k == 0 ? 0 : W - k)];
         // F_a = (Z(k) + conj Z(-k))/2,  F_b = (Z(k) - conj Z(-k))/(2i)
-        if (ya < H) S[(size_t)ya * Wh + k] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-        if (yb < H) S[(size_t)yb * Wh + k] = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+        const R h = (R)0.5;
+        if (ya < H) S[(size_t)ya * Wh + k] = Cplx<C>::make(h * (zk.x + zm.x), h * (zk.y - zm.y));
+        if (yb < H) S[(size_t)yb * Wh + k] = Cplx<C>::make(h * (zk.y + zm.y), -h * (zk.x - zm.x));
     }
 }
 
-__global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__ f, float2* __restrict__ S,
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__ f, C* __restrict__ S,
                                                        int H, int W, int pitch, int nb, FftPlan plan)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -270,29 +282,32 @@ __global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__
 // The row pass of f and the multiplier M in one launch: they are independent,
 // and as one grid (row blocks first, then the M blocks) they overlap without
 // a second stream.  LDS: the larger of the two needs.
-__global__ void __launch_bounds__(256) wiener_rows_fwd_mult(const float* __restrict__ f, float2* __restrict__ S,
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_rows_fwd_mult(const float* __restrict__ f, C* __restrict__ S,
                                                             int H, int W, int pitch, int nb, FftPlan plan, int nrow,
-                                                            PsfDev psf, double K, float2* __restrict__ M, int gxm)
+                                                            PsfDev psf, double K, C* __restrict__ M, int gxm)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if ((int)blockIdx.x < nrow) {
         rows_fwd_block(f, S, H, W, pitch, nb, plan, blockIdx.x, smem_raw);
     } else {
         const int b = blockIdx.x - nrow, by = b / gxm;
-        mult_2d_block(psf, H, W, K, M, nullptr, b - by * gxm, by, smem_raw);
+        mult_2d_block<C>(psf, H, W, K, M, nullptr, b - by * gxm, by, smem_raw);
     }
 }
 
 // Column pass over `cb` consecutive columns kx of the half spectrum S (in
 // place): mode 0: FFT along y, multiply by M (or conj M), inverse FFT (1/H);
 // mode 1: forward FFT only; mode 2: inverse FFT only (1/H).
-__global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const float2* __restrict__ M,
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_cols(C* __restrict__ S, const C* __restrict__ M,
                                                    int H, int W, int cb, FftPlan plan, int mode, int conjM)
 {
+    using R = typename Cplx<C>::R;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float2* tw = reinterpret_cast<float2*>(smem_raw);
-    float2* a = tw + H;
-    float2* b = a + cb * H;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* a = tw + H;
+    C* b = a + cb * H;
     fft_twiddles(tw, H);
     const int Wh = W / 2 + 1;
     const int c0 = xcd_group(blockIdx.x, gridDim.x) * cb;
@@ -300,15 +315,16 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
     // elements is fetched together with S, so its latency is not paid after
     // the forward transform.
     const bool pre = mode == 0 && cb * H <= 8 * (int)blockDim.x;
-    float2 mv[8];
+    const C zero = Cplx<C>::make((R)0, (R)0);
+    C mv[8];
     for (int base = threadIdx.x; base < cb * H; base += 8 * blockDim.x) {
-        float2 v[8];
+        C v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int idx = base + k * blockDim.x, y = idx / cb, c = idx - y * cb;
             const bool ok = idx < cb * H && c0 + c < Wh;
-            v[k] = ok ? S[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
-            if (pre) mv[k] = ok ? M[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+            v[k] = ok ? S[(size_t)y * Wh + c0 + c] : zero;
+            if (pre) mv[k] = ok ? M[(size_t)y * Wh + c0 + c] : zero;
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -317,9 +333,9 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
         }
     }
     __syncthreads();
-    float2* X = fft_rows(a, b, cb, plan, tw);
+    C* X = fft_rows(a, b, cb, plan, tw);
     if (mode == 0) {
-        float2* Y = X == a ? b : a;
+        C* Y = X == a ? b : a;
         if (pre) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -329,7 +345,7 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
         } else {
             for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
                 const int c = idx / H, y = idx - c * H;
-                float2 m = (c0 + c < Wh) ? M[(size_t)y * Wh + c0 + c] : make_float2(0.0f, 0.0f);
+                C m = (c0 + c < Wh) ? M[(size_t)y * Wh + c0 + c] : zero;
                 if (conjM) m = cconj(m);
                 X[idx] = cconj(cmul(X[idx], m));
             }
@@ -337,12 +353,12 @@ __global__ void __launch_bounds__(256) wiener_cols(float2* __restrict__ S, const
         __syncthreads();
         X = fft_rows(X, Y, cb, plan, tw);
     }
-    const float inv = mode == 1 ? 1.0f : 1.0f / (float)H;
+    const R inv = mode == 1 ? (R)1 : (R)1 / (R)H;
     for (int idx = threadIdx.x; idx < cb * H; idx += blockDim.x) {
         const int y = idx / cb, c = idx - y * cb;
         if (c0 + c < Wh) {
-            const float2 z = X[c * H + y];
-            S[(size_t)y * Wh + c0 + c] = mode == 1 ? z : make_float2(z.x * inv, -z.y * inv);
+            const C z = X[c * H + y];
+            S[(size_t)y * Wh + c0 + c] = mode == 1 ? z : Cplx<C>::make(z.x * inv, -z.y * inv);
         }
     }
 }
@@ -361,14 +377,16 @@ __global__ void __launch_bounds__(256) spectral_mul(const float2* Sin, const flo
 // Inverse row pass: U_a, U_b extended to full length by Hermitian symmetry,
 // packed as Z = U_a + i U_b, inverse FFT (scaled by 1/W): u_a = Re, u_b = Im;
 // non-positive values replaced by pos_floor (Sec. 3.2).
-__global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict__ S, float* __restrict__ u,
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_rows_inv(const C* __restrict__ S, float* __restrict__ u,
                                                        int H, int W, int pitch, int nb, FftPlan plan,
                                                        float pos_floor, int accumulate)
 {
+    using R = typename Cplx<C>::R;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float2* tw = reinterpret_cast<float2*>(smem_raw);
-    float2* a = tw + W;
-    float2* b = a + nb * W;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* a = tw + W;
+    C* b = a + nb * W;
     fft_twiddles(tw, W);
     const int Wh = W / 2 + 1;
     const int pair0 = blockIdx.x * nb;
@@ -377,28 +395,29 @@ __global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict_
         const int ya = 2 * (pair0 + t), yb = ya + 1;
         const bool lo = k < Wh;
         const int kk = lo ? k : W - k;
-        float2 ua = ya < H ? S[(size_t)ya * Wh + kk] : make_float2(0.0f, 0.0f);
-        float2 ub = yb < H ? S[(size_t)yb * Wh + kk] : make_float2(0.0f, 0.0f);
+        const C zero = Cplx<C>::make((R)0, (R)0);
+        C ua = ya < H ? S[(size_t)ya * Wh + kk] : zero;
+        C ub = yb < H ? S[(size_t)yb * Wh + kk] : zero;
         if (!lo) {
             ua = cconj(ua);
             ub = cconj(ub);
         }
         // conj(U_a + i U_b) for the inverse via the forward transform
-        return make_float2(ua.x - ub.y, -(ua.y + ub.x));
+        return Cplx<C>::make(ua.x - ub.y, -(ua.y + ub.x));
     });
     __syncthreads();
-    const float2* Z = fft_rows(a, b, nb, plan, tw);
-    const float inv = 1.0f / (float)W;
+    const C* Z = fft_rows(a, b, nb, plan, tw);
+    const R inv = (R)1 / (R)W;
     for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
         const int t = idx / W, x = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
-        const float2 z = Z[idx];
+        const C z = Z[idx];
         if (accumulate) {
-            if (ya < H) u[(size_t)ya * pitch + x] += z.x * inv;
-            if (yb < H) u[(size_t)yb * pitch + x] += -z.y * inv;
+            if (ya < H) u[(size_t)ya * pitch + x] += (float)(z.x * inv);
+            if (yb < H) u[(size_t)yb * pitch + x] += (float)(-z.y * inv);
         } else {
-            if (ya < H) u[(size_t)ya * pitch + x] = fmaxf(z.x * inv, pos_floor);
-            if (yb < H) u[(size_t)yb * pitch + x] = fmaxf(-z.y * inv, pos_floor);
+            if (ya < H) u[(size_t)ya * pitch + x] = fmaxf((float)(z.x * inv), pos_floor);
+            if (yb < H) u[(size_t)yb * pitch + x] = fmaxf((float)(-z.y * inv), pos_floor);
         }
     }
 }
@@ -409,43 +428,68 @@ __global__ void __launch_bounds__(256) wiener_rows_inv(const float2* __restrict_
 // many workgroups (the passes are latency bound at these sizes).
 static int row_batch(int W) { return W >= 256 ? 1 : 256 / W; }
 static int col_batch(int H) { return H >= 512 ? 1 : (512 / H > 8 ? 8 : 512 / H); }
-size_t wiener_ws_bytes(int H, int W, bool rowwise)
+size_t wiener_ws_bytes(int H, int W, bool rowwise, bool fp64)
 {
-    if (rowwise) return (size_t)W * sizeof(float2);
+    const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
+    if (rowwise) return (size_t)W * cs;
     const size_t Wh = (size_t)W / 2 + 1;
-    return 2 * (size_t)H * Wh * sizeof(float2);  // M and S
+    return 2 * (size_t)H * Wh * cs;  // M and S
+}
+
+// FP64 transforms of 2048 points need more than 64 KB of LDS per workgroup;
+// the limit is raised once per kernel.
+template <typename K>
+static void allow_lds(K* kernel)
+{
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+}
+
+template <typename C>
+static int launch_wiener_t(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
+                           float pos_floor, void* ws, bool rowwise, hipStream_t st)
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        allow_lds(&wiener_rows_fused<C>);
+        allow_lds(&wiener_rows_fwd_mult<C>);
+        allow_lds(&wiener_cols<C>);
+        allow_lds(&wiener_rows_inv<C>);
+    });
+    if (rowwise) {
+        C* M = reinterpret_cast<C*>(ws);
+        hipLaunchKernelGGL(wiener_mult_1d<C>, dim3((W + 255) / 256), dim3(256), 0, st, psf, W, K, M);
+        const int pairs = (H + 1) / 2;
+        const int nb = row_batch(W);
+        const size_t lds = (size_t)(W + 2 * nb * W) * sizeof(C);
+        hipLaunchKernelGGL(wiener_rows_fused<C>, dim3((pairs + nb - 1) / nb), dim3(256), lds, st, f, u, H, W,
+                           pitch, nb, make_plan(W), (const C*)M, pos_floor);
+    } else {
+        const int Wh = W / 2 + 1;
+        C* M = reinterpret_cast<C*>(ws);
+        C* S = M + (size_t)H * Wh;
+        const int pairs = (H + 1) / 2;
+        const int nb = row_batch(W);
+        const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(C);
+        const int nrow = (pairs + nb - 1) / nb;
+        const int gxm = (Wh + MULT_KX - 1) / MULT_KX, gym = (H + MULT_KY - 1) / MULT_KY;
+        hipLaunchKernelGGL(wiener_rows_fwd_mult<C>, dim3(nrow + gxm * gym), dim3(256), std::max(lds_r, MULT_SMEM), st,
+                           f, S, H, W, pitch, nb, make_plan(W), nrow, psf, K, M, gxm);
+        const int cb = col_batch(H);
+        const size_t lds_c = (size_t)(H + 2 * cb * H) * sizeof(C);
+        hipLaunchKernelGGL(wiener_cols<C>, dim3((Wh + cb - 1) / cb), dim3(256), lds_c, st, S, (const C*)M,
+                           H, W, cb, make_plan(H), 0, 0);
+        hipLaunchKernelGGL(wiener_rows_inv<C>, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st,
+                           (const C*)S, u, H, W, pitch, nb, make_plan(W), pos_floor, 0);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
-                  float pos_floor, void* ws, bool rowwise, hipStream_t st)
+                  float pos_floor, void* ws, bool rowwise, bool fp64, hipStream_t st)
 {
-    if (rowwise) {
-        float2* M = reinterpret_cast<float2*>(ws);
-        hipLaunchKernelGGL(wiener_mult_1d, dim3((W + 255) / 256), dim3(256), 0, st, psf, W, K, M);
-        const int pairs = (H + 1) / 2;
-        const int nb = row_batch(W);
-        const size_t lds = (size_t)(W + 2 * nb * W) * sizeof(float2);
-        hipLaunchKernelGGL(wiener_rows_fused, dim3((pairs + nb - 1) / nb), dim3(256), lds, st, f, u, H, W,
-                           pitch, nb, make_plan(W), (const float2*)M, pos_floor);
-    } else {
-        const int Wh = W / 2 + 1;
-        float2* M = reinterpret_cast<float2*>(ws);
-        float2* S = M + (size_t)H * Wh;
-        const int pairs = (H + 1) / 2;
-        const int nb = row_batch(W);
-        const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(float2);
-        const int nrow = (pairs + nb - 1) / nb;
-        const int gxm = (Wh + MULT_KX - 1) / MULT_KX, gym = (H + MULT_KY - 1) / MULT_KY;
-        hipLaunchKernelGGL(wiener_rows_fwd_mult, dim3(nrow + gxm * gym), dim3(256), std::max(lds_r, MULT_SMEM), st,
-                           f, S, H, W, pitch, nb, make_plan(W), nrow, psf, K, M, gxm);
-        const int cb = col_batch(H);
-        const size_t lds_c = (size_t)(H + 2 * cb * H) * sizeof(float2);
-        hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), lds_c, st, S, (const float2*)M,
-                           H, W, cb, make_plan(H), 0, 0);
-        hipLaunchKernelGGL(wiener_rows_inv, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st,
-                           (const float2*)S, u, H, W, pitch, nb, make_plan(W), pos_floor, 0);
-    }
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return fp64 ? launch_wiener_t<double2>(f, u, H, W, pitch, psf, K, pos_floor, ws, rowwise, st)
+                : launch_wiener_t<float2>(f, u, H, W, pitch, psf, K, pos_floor, ws, rowwise, st);
 }
 
 int fft_row_batch(int W) { return row_batch(W); }
@@ -458,9 +502,9 @@ void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, fl
 void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st)
 {
     const int nb = row_batch(W), cb = col_batch(H), Wh = W / 2 + 1, pairs = (H + 1) / 2;
-    hipLaunchKernelGGL(wiener_rows_fwd, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st, x,
+    hipLaunchKernelGGL(wiener_rows_fwd<float2>, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st, x,
                        S, H, W, pitch, nb, make_plan(W));
-    hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S,
+    hipLaunchKernelGGL(wiener_cols<float2>, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S,
                        (const float2*)nullptr, H, W, cb, make_plan(H), 1, 0);
 }
 
@@ -468,23 +512,23 @@ void launch_fft2_inverse(float2* S, int H, int W, float* out, int pitch, float f
                          hipStream_t st)
 {
     const int nb = row_batch(W), cb = col_batch(H), Wh = W / 2 + 1, pairs = (H + 1) / 2;
-    hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S,
+    hipLaunchKernelGGL(wiener_cols<float2>, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S,
                        (const float2*)nullptr, H, W, cb, make_plan(H), 2, 0);
-    hipLaunchKernelGGL(wiener_rows_inv, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st,
+    hipLaunchKernelGGL(wiener_rows_inv<float2>, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st,
                        (const float2*)S, out, H, W, pitch, nb, make_plan(W), floor_, accumulate ? 1 : 0);
 }
 
 void launch_rows_fwd(const float* x, int pitch, int H, int W, float2* S, hipStream_t st)
 {
     const int nb = row_batch(W), pairs = (H + 1) / 2;
-    hipLaunchKernelGGL(wiener_rows_fwd, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st, x,
+    hipLaunchKernelGGL(wiener_rows_fwd<float2>, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st, x,
                        S, H, W, pitch, nb, make_plan(W));
 }
 
 void launch_cols(float2* S, const float2* mult, bool conj_mult, int mode, int H, int W, hipStream_t st)
 {
     const int cb = col_batch(H), Wh = W / 2 + 1;
-    hipLaunchKernelGGL(wiener_cols, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S, mult, H,
+    hipLaunchKernelGGL(wiener_cols<float2>, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S, mult, H,
                        W, cb, make_plan(H), mode, conj_mult ? 1 : 0);
 }
 

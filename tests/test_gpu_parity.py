@@ -43,10 +43,21 @@ def pitched(a, pitch):
     return buf[:, :W]
 
 
-def report(name, got, want):
+# Per-pixel bar beside the relative L2 one: the largest pixel error, relative
+# to the largest reference value, within twice the L2 bar.
+RTOL_PIXEL = 2e-4
+
+
+def report(name, got, want, px_tol=RTOL_PIXEL):
+    """Prints rel-L2 and the largest pixel error; asserts the per-pixel bar
+    (px_tol=None: print only) and returns rel-L2 for the caller's L2 bar."""
     e = rel_l2(got, want)
-    m = float(np.abs(np.asarray(got, np.float64) - want).max())
-    print(f"[parity] {name}: rel_l2={e:.3e} max_abs={m:.3e}", flush=True)
+    d = np.abs(np.asarray(got, np.float64) - want)
+    m = float(d.max())
+    px = m / float(np.abs(want).max())
+    print(f"[parity] {name}: rel_l2={e:.3e} max_abs={m:.3e} max_abs/max|ref|={px:.3e}", flush=True)
+    if px_tol is not None:
+        assert px <= px_tol, f"{name}: largest pixel error {px:.3e} of the reference maximum"
     return e
 
 
@@ -96,13 +107,35 @@ def test_wiener_pitch_and_small_K():
         assert torch.all(buf[:, 96:] == -7.0)   # padding untouched
 
 
+@pytest.mark.parametrize("name,H,W,mk,kind,L", [c for c in WIENER_CASES if c[1] <= 512],
+                         ids=[c[0] for c in WIENER_CASES if c[1] <= 512])
+def test_wiener_fp64_correctly_rounded(name, H, W, mk, kind, L):
+    """deblur_wiener_fp64: transforms in FP64, output rounded once, so every
+    pixel is the FP64 oracle value rounded to FP32 (an FP64 error of ~1e-15
+    can flip a rounding only when the exact value sits that close to a
+    rounding boundary: at most 1 ulp, and rarely)."""
+    rng = np.random.default_rng(H * 7 + W)
+    g = synth.ground_truth(rng, H, W)
+    h = mk().astype(np.float32)
+    f = synth.observe(rng, g, h.astype(np.float64), 2.0)
+    want = oracle.wiener_init(f, h, 0.01, 1.0)
+    u = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    dbl.deblur_wiener(dev(f), u, gpu_psf(kind, L, h), 0.01, 1.0, fp64=True)
+    got = u.cpu().numpy()
+    want32 = want.astype(np.float32)
+    ulp = np.abs(got.view(np.int32).astype(np.int64) - want32.view(np.int32).astype(np.int64))
+    print(f"[parity] wiener fp64 {name}: exact {np.mean(ulp == 0) * 100:.4f}% max {ulp.max()} ulp", flush=True)
+    assert ulp.max() <= 1 and np.mean(ulp == 0) >= 0.999
+
+
 # ------------------------------------------------------------- iterations
 def iterate_case(H, W, h, kind, L, iters, alpha=0.003, robust=True, bc=oracle.BC_REPLICATE, seed=0,
                  eps_d=0.1, eps_t=0.1, pitch=None):
     rng = np.random.default_rng(seed)
     g = synth.ground_truth(rng, H, W)
     f = synth.observe(rng, g, h.astype(np.float64), 2.0)
-    u0 = np.maximum(f, 1.0) + rng.uniform(0, 3, size=f.shape).astype(np.float32)
+    # the start is rounded to FP32 before either side sees it: both run from the same state
+    u0 = (np.maximum(f, 1.0) + rng.uniform(0, 3, size=f.shape)).astype(np.float32).astype(np.float64)
     p = oracle.Params(alpha=alpha, eps_data=eps_d, eps_tv=eps_t, robust=robust, bc=bc)
     want = oracle.rrrl(f, u0, h, p, iters)
     gp = dbl.Params(alpha=alpha, iters=iters, eps_data=eps_d, eps_tv=eps_t, robust=robust, boundary=bc)
@@ -124,9 +157,9 @@ ITER_CASES = [
      dict(bc=oracle.BC_PERIODIC)),
     ("gauss31_128_k10", 128, 128, lambda: synth.gauss_mixture_psf(synth.rng_for(2), 31), synth.KIND_TAPS, 0, 10,
      {}),
-    ("asym5x3_strong_tv", 64, 80, lambda: synth.random_psf(np.random.default_rng(5), 5, 3), synth.KIND_TAPS, 0, 5,
+    ("asym5x3_tv_a0.02", 64, 80, lambda: synth.random_psf(np.random.default_rng(5), 5, 3), synth.KIND_TAPS, 0, 5,
      dict(alpha=0.02)),
-    ("line21_nonrobust", 96, 96, lambda: synth.line_psf(21, 0.785), synth.KIND_TAPS, 0, 4, dict(robust=False)),
+    ("line21_nonrobust_k4", 96, 96, lambda: synth.line_psf(21, 0.785), synth.KIND_TAPS, 0, 4, dict(robust=False)),
     ("eps_small", 64, 64, lambda: synth.line_psf(11, 1.3), synth.KIND_TAPS, 0, 5, dict(eps_d=0.01, eps_t=0.01)),
     ("eps_large", 64, 64, lambda: synth.line_psf(11, 1.3), synth.KIND_TAPS, 0, 5, dict(eps_d=1.0, eps_t=1.0)),
     ("taps_63x1_periodic", 70, 90, lambda: synth.box_psf(63, "v"), synth.KIND_TAPS, 0, 4,
@@ -150,6 +183,52 @@ def test_iterate_parity(name, H, W, mk, kind, L, iters, kw):
     got, want = iterate_case(H, W, h, kind, L, iters, **kw)
     assert np.all(np.isfinite(got))
     assert report("iterate " + name, got, want) <= RTOL_ITER
+
+
+def fp32_floor(H, W, h, iters, alpha=0.003, robust=True, bc=oracle.BC_REPLICATE, seed=0, eps_d=0.1, eps_t=0.1,
+               pitch=None):
+    """Oracle only, on the inputs of iterate_case: (a) the FP64 iteration
+    with its state rounded to FP32 after every step, and (b) the FP64
+    iteration from a start perturbed by one unit of FP32 roundoff at random,
+    each against the plain FP64 result (rel-L2)."""
+    rng = np.random.default_rng(seed)
+    g = synth.ground_truth(rng, H, W)
+    f = synth.observe(rng, g, h.astype(np.float64), 2.0)
+    u0 = (np.maximum(f, 1.0) + rng.uniform(0, 3, size=f.shape)).astype(np.float32).astype(np.float64)
+    p = oracle.Params(alpha=alpha, eps_data=eps_d, eps_tv=eps_t, robust=robust, bc=bc)
+    want = oracle.rrrl(f, u0, h, p, iters)
+    u = u0.copy()
+    for _ in range(iters):
+        u = oracle.rrrl(f, u, h, p, 1).astype(np.float32).astype(np.float64)
+    up = u0 * (1.0 + np.random.default_rng(1).uniform(-2.0 ** -24, 2.0 ** -24, u0.shape))
+    return rel_l2(u, want), rel_l2(oracle.rrrl(f, up, h, p, iters), want)
+
+
+# Settings far from the workloads' (alpha 0.5 on a 3-tap-wide PSF, plain RL
+# for 10 iterations from a noisy start, 30 iterations of a dense 31 x 31 PSF):
+# the oracle alone shows that the 1e-4 bar lies below what FP32 state can
+# hold there.  Held to the bar and expected to fail; the test prints the
+# measured error next to the two oracle-only figures of fp32_floor.
+STRESS_CASES = [
+    # (name, H, W, psf, iters, kw, oracle-only figures measured: FP32-state floor; 1-roundoff start response)
+    ("gauss31_128_k30", 128, 128, lambda: synth.gauss_mixture_psf(synth.rng_for(2), 31), 30, {},
+     "floor 6.5e-5; the GPU's 961-term FP32 sums measured 2.6e-4"),
+    ("asym5x3_strong_tv", 64, 80, lambda: synth.random_psf(np.random.default_rng(5), 5, 3), 8, dict(alpha=0.5),
+     "values grow to 1e18; a 1-roundoff start perturbation moves the FP64 result by 6.7e-4; GPU 1.9e-4"),
+    ("line21_nonrobust_k10", 96, 96, lambda: synth.line_psf(21, 0.785), 10, dict(robust=False),
+     "floor 1.3e-4; a 1-roundoff start perturbation moves the FP64 result by 8.6e-4; GPU 1.3e-3"),
+]
+
+
+@pytest.mark.xfail(strict=False, reason="below the FP32 conditioning floor of the setting (figures in STRESS_CASES)")
+@pytest.mark.parametrize("name,H,W,mk,iters,kw,measured", STRESS_CASES, ids=[c[0] for c in STRESS_CASES])
+def test_iterate_parity_stress(name, H, W, mk, iters, kw, measured):
+    h = mk().astype(np.float32)
+    got, want = iterate_case(H, W, h, synth.KIND_TAPS, 0, iters, **kw)
+    floor, chaos = fp32_floor(H, W, h, iters, **kw)
+    print(f"[parity] stress {name}: oracle FP32-state floor {floor:.2e}, 1-roundoff start response {chaos:.2e}"
+          f" (recorded: {measured})", flush=True)
+    assert report("iterate stress " + name, got, want, px_tol=None) <= RTOL_ITER
 
 
 def test_iterate_zero_and_negative_observations():
@@ -236,22 +315,23 @@ def test_wr3l_workload_parity(config, size):
     assert report(f"wr3l config {config} size {size}", got.cpu().numpy(), want) <= RTOL_ITER
 
 
+@pytest.mark.xfail(strict=False, reason="the oracle alone moves 1.9e-4 (rel-L2) when its Wiener output is rounded "
+                   "to FP32, so no FP32-state run can meet 1e-4 here; GPU measured 6.9e-4 (FP64 Wiener)")
 def test_wr3l_dense_gaussian_30_iterations():
     """Dense 31x31 Gaussian-mixture PSF, Wiener + 30 iterations (the 2D-blur
-    workload at 256^2).  This iteration amplifies perturbations strongly: an
-    FP64 run from the FP32-rounded Wiener output already differs from the
-    FP64 run by `floor` (oracle only).  Any FP32-state implementation carries
-    that representation error, so the bar is max(1e-4, 4 * floor)."""
+    workload at 256^2), held to the 1e-4 bar.  This iteration amplifies
+    perturbations strongly: the FP64 run from the FP32-rounded Wiener output
+    already differs from the FP64 run by `floor` (oracle only, printed)."""
     c = synth.make_case(2, size=256)
     p = oracle.Params(alpha=c.alpha)
     u0 = oracle.wiener_init(c.f, c.psf, c.K, 1.0)
     want = oracle.rrrl(c.f, u0, c.psf, p, c.iters)
     rounded = oracle.rrrl(c.f, u0.astype(np.float32).astype(np.float64), c.psf, p, c.iters)
     floor = rel_l2(rounded, want)
-    got = dbl.wr3l(dev(c.f), gpu_psf(c.kind, c.length, c.psf), c.K, dbl.Params(alpha=c.alpha, iters=c.iters))
-    err = report("wr3l dense gaussian 256 k30", got.cpu().numpy(), want)
+    got = dbl.wr3l(dev(c.f), gpu_psf(c.kind, c.length, c.psf), c.K, dbl.Params(alpha=c.alpha, iters=c.iters),
+                   wiener_fp64=True)
     print(f"[parity] FP32 representation floor {floor:.3e}", flush=True)
-    assert err <= max(RTOL_ITER, 4.0 * floor)
+    assert report("wr3l dense gaussian 256 k30 (FP64 Wiener)", got.cpu().numpy(), want, px_tol=None) <= RTOL_ITER
 
 
 def test_wr3l_full_size_workload_1():
@@ -297,7 +377,8 @@ def test_stage_parity(robust, bc):
 def test_box_running_sum_lengths(L, axis, bc):
     """Running-sum box path (every length, odd and even, integer and with
     fractional end pixels, both continuations) against the oracle's direct
-    summation."""
+    summation, at the workloads' alpha (0.003); alpha = 0.05: the stress
+    test below."""
     H, W = (70, 150) if axis == "h" else (150, 70)
     if bc == oracle.BC_PERIODIC and L > min(H, W):
         pytest.skip("PSF longer than the image")
@@ -305,6 +386,23 @@ def test_box_running_sum_lengths(L, axis, bc):
     kind = synth.KIND_BOX_H if axis == "h" else synth.KIND_BOX_V
     got, want = iterate_case(H, W, h, kind, L, 3, alpha=0.003, bc=bc, seed=int(L * 4))
     assert report(f"box {axis} L={L} bc={bc}", got, want) <= RTOL_ITER
+
+
+@pytest.mark.xfail(strict=False, reason="alpha = 0.05 makes the box iteration amplify a 1-roundoff perturbation "
+                   "of its start ~300x more than at 0.003 (per pixel 4e-5 .. 1.7e-4, oracle only); GPU per-pixel "
+                   "errors measured 2e-4 .. 4.7e-4")
+@pytest.mark.parametrize("L,axis", [(2, "h"), (3, "h"), (27, "h"), (64, "v")])
+def test_box_running_sum_stress(L, axis):
+    """The box lengths at alpha = 0.05 (17x the workloads' value), held to the
+    same bars; the oracle-only sensitivity is printed beside the error."""
+    H, W = (70, 150) if axis == "h" else (150, 70)
+    h = synth.box_psf(L, axis).astype(np.float32)
+    kind = synth.KIND_BOX_H if axis == "h" else synth.KIND_BOX_V
+    got, want = iterate_case(H, W, h, kind, L, 3, alpha=0.05, seed=int(L * 4))
+    floor, chaos = fp32_floor(H, W, h, 3, alpha=0.05, seed=int(L * 4))
+    print(f"[parity] box stress {axis} L={L}: oracle FP32-state floor {floor:.2e}, 1-roundoff start response "
+          f"{chaos:.2e}", flush=True)
+    assert report(f"box stress {axis} L={L}", got, want) <= RTOL_ITER
 
 
 @pytest.mark.parametrize("L,axis", [(21, "v"), (20.5, "v"), (9.75, "h")])
@@ -377,11 +475,13 @@ def test_fft_path_parity(name, H, W, mk, iters):
     rng = np.random.default_rng(H)
     g = synth.ground_truth(rng, H, W)
     f = synth.observe(rng, g, h.astype(np.float64), 2.0)
-    u0 = np.maximum(f, 1.0) + rng.uniform(0, 3, size=f.shape).astype(np.float32)
+    # the start is rounded to FP32 before either side sees it: both run from the same state
+    u0 = (np.maximum(f, 1.0) + rng.uniform(0, 3, size=f.shape)).astype(np.float32).astype(np.float64)
     out = torch.empty((H, W), dtype=torch.float32, device="cuda")
     dbl.deblur_rrrl_iterate(dev(f), dev(u0), out, gpu_psf(synth.KIND_TAPS, 0, h),
                             dbl.Params(iters=iters, boundary=dbl.BC_PERIODIC, conv=dbl.CONV_FFT))
     assert report(f"fft {name}", out.cpu().numpy(), want) <= RTOL_ITER
+    assert report(f"stencil periodic {name}", got, want) <= RTOL_ITER
     assert report(f"fft vs stencil {name}", out.cpu().numpy(), got) <= RTOL_ITER
 
 
