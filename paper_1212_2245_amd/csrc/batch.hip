@@ -7,9 +7,10 @@
 // group.  The captured graph runs, per group: the Wiener step of every image
 // (on several forked capture streams), then for each iteration one launch per
 // class and stage, whose workgroups each take one tile of one image from the
-// list; then a timestamp kernel.  Groups run one after another, so with a
-// group size below the batch the completion time of each image's group is
-// its latency.
+// list; then a timestamp kernel.  Groups run one after another.  In the
+// launches of the last iteration every tile counts itself done for its image
+// (an atomic counter) and the image's last tile writes the image's
+// completion time: per-image latencies, no waiting inside any kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,8 +32,21 @@ struct BatchImg {
     const int* hdr;         // compiled PSF header (group counts per run length)
     int H, W, pitch, L;     // L: integer part of the box length (box classes)
     float frac;             // fractional part of the box length
+    int ntiles;             // tiles of one launch of the image's class
     IterParams p;
 };
+
+// Completion of the image of tile t in a launch of the last iteration: the
+// launch's last tile of the image stamps the time (all threads call).
+DEBLUR_DEV void count_tile(const BatchImg& im, int img, unsigned* cnt, unsigned long long* ts)
+{
+    if (!cnt) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned old = atomicAdd(&cnt[img], 1u);
+        if (old + 1 == (unsigned)im.ntiles) ts[img] = wall_clock64();
+    }
+}
 
 struct BatchTile {
     int img, x0, y0, pad;   // x0/y0: along/across origin for box tiles
@@ -54,13 +68,15 @@ __global__ void __launch_bounds__(BT_NT) batch_stage1(const BatchTile* __restric
 
 template <int RAD>
 __global__ void __launch_bounds__(BT_NT) batch_stage2(const BatchTile* __restrict__ tiles,
-                                                      const BatchImg* __restrict__ imgs, int src)
+                                                      const BatchImg* __restrict__ imgs, int src, unsigned* cnt,
+                                                      unsigned long long* ts)
 {
     __shared__ Stage2Smem<RAD, BT_TH> sm;
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
     stage2_tile<RAD, BT_TH, BT_NT>(sm, im.qw, im.buf[src], im.buf[1 - src], nullptr, im.H, im.W, im.pitch, t.x0,
                                    t.y0, im.taps, im.hdr, im.p);
+    count_tile(im, t.img, cnt, ts);
 }
 
 // Box tiles of the batch: one tile shape per orientation for all sizes.
@@ -68,7 +84,8 @@ constexpr int BBH_TA = 64, BBH_TC = 8, BBV_TA = 64, BBV_TC = 8;
 
 template <bool VERT>
 __global__ void __launch_bounds__(BOX_NT) batch_box(const BatchTile* __restrict__ tiles,
-                                                    const BatchImg* __restrict__ imgs, int src)
+                                                    const BatchImg* __restrict__ imgs, int src, unsigned* cnt,
+                                                    unsigned long long* ts)
 {
     extern __shared__ __align__(16) float box_lds[];
     constexpr int TA = VERT ? BBV_TA : BBH_TA, TC = VERT ? BBV_TC : BBH_TC;
@@ -76,11 +93,18 @@ __global__ void __launch_bounds__(BOX_NT) batch_box(const BatchTile* __restrict_
     const BatchImg& im = imgs[t.img];
     const BoxGeom g = box_geom<VERT, TA, TC>(im.H, im.W, im.L, im.frac);
     box_seg_tile<VERT, TA, TC>(box_lds, im.buf[src], im.f, im.buf[1 - src], nullptr, im.pitch, g, im.p, t.x0, t.y0);
+    count_tile(im, t.img, cnt, ts);
 }
 
 __global__ void batch_timestamp(unsigned long long* ts, int slot)
 {
     if (threadIdx.x == 0) ts[slot] = wall_clock64();
+}
+
+// Clears the per-image tile counters (a fill kernel inside the graph).
+__global__ void batch_clear(unsigned* cnt, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) cnt[i] = 0u;
 }
 
 // ---------------------------------------------------------------- host side
@@ -92,6 +116,8 @@ struct BatchPlan {
     std::vector<int> group_of;          // image -> group
     std::vector<void*> allocs;          // device allocations owned by the plan
     unsigned long long* ts = nullptr;   // groups + 1 timestamps
+    unsigned* img_cnt = nullptr;        // per image: tiles of the last iteration done
+    unsigned long long* img_ts = nullptr;   // per image: completion time
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
@@ -173,13 +199,24 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         b.pitch = it.pitch;
         b.L = it.psf.length;
         b.frac = it.psf.frac;
+        if (cls < CL_BOXH) {
+            b.ntiles = ((it.W + 63) / 64) * ((it.H + BT_TH - 1) / BT_TH);
+        } else {
+            const bool vert = cls == CL_BOXV;
+            const int TA = vert ? BBV_TA : BBH_TA, TC = vert ? BBV_TC : BBH_TC;
+            const int along = vert ? it.H : it.W, across = vert ? it.W : it.H;
+            b.ntiles = ((along + TA - 1) / TA) * ((across + TC - 1) / TC);
+        }
         b.p = it.p;
         wiener_ws = std::max(wiener_ws, wiener_ws_bytes(it.H, it.W, it.psf.ph == 1));
         P->group_of[i] = i / gs;
     }
     BatchImg* dimgs = static_cast<BatchImg*>(dalloc(P, sizeof(BatchImg) * n));
     P->ts = static_cast<unsigned long long*>(dalloc(P, sizeof(unsigned long long) * (P->groups + 1)));
-    if (!dimgs || !P->ts || hipMemcpy(dimgs, imgs.data(), sizeof(BatchImg) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    P->img_cnt = static_cast<unsigned*>(dalloc(P, sizeof(unsigned) * n));
+    P->img_ts = static_cast<unsigned long long*>(dalloc(P, sizeof(unsigned long long) * n));
+    if (!dimgs || !P->ts || !P->img_cnt || !P->img_ts ||
+        hipMemcpy(dimgs, imgs.data(), sizeof(BatchImg) * n, hipMemcpyHostToDevice) != hipSuccess) {
         batch_plan_destroy(P);
         return -3;
     }
@@ -237,6 +274,7 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
             return -3;
         }
     }
+    prepare_wiener_kernels();   // runtime attribute calls stay out of the capture
     if (hipDeviceSynchronize() != hipSuccess) {  // tap lists and copies complete
         batch_plan_destroy(P);
         return -4;
@@ -259,7 +297,10 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
     };
     hipStream_t s = P->cap;
     ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) hipLaunchKernelGGL(batch_timestamp, dim3(1), dim3(64), 0, s, P->ts, 0);
+    if (ok) {
+        hipLaunchKernelGGL(batch_clear, dim3((n + 255) / 256), dim3(256), 0, s, P->img_cnt, n);
+        hipLaunchKernelGGL(batch_timestamp, dim3(1), dim3(64), 0, s, P->ts, 0);
+    }
     for (int g = 0; g < P->groups && ok; ++g) {
         // Wiener of the group's images, forked over the chains
         hipEvent_t fork = event();
@@ -280,31 +321,33 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         // an independent chain over all iterations, forked once after the
         // Wiener step and joined at the end of the group
         const auto& L = lists[g];
-        auto launch_class = [&](int cls, int src, hipStream_t cs) {
+        auto launch_class = [&](int cls, int src, hipStream_t cs, bool last) {
             const BatchTile* d = L[cls].d;
             const dim3 grid(L[cls].count);
+            unsigned* cnt = last ? P->img_cnt : nullptr;   // the last iteration stamps completions
+            unsigned long long* its = P->img_ts;
             switch (cls) {
                 case CL_R4:
                     hipLaunchKernelGGL(batch_stage1<4>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
-                    hipLaunchKernelGGL(batch_stage2<4>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_stage2<4>, grid, dim3(BT_NT), 0, cs, d, dimgs, src, cnt, its);
                     break;
                 case CL_R8:
                     hipLaunchKernelGGL(batch_stage1<8>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
-                    hipLaunchKernelGGL(batch_stage2<8>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_stage2<8>, grid, dim3(BT_NT), 0, cs, d, dimgs, src, cnt, its);
                     break;
                 case CL_R16:
                     hipLaunchKernelGGL(batch_stage1<16>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
-                    hipLaunchKernelGGL(batch_stage2<16>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_stage2<16>, grid, dim3(BT_NT), 0, cs, d, dimgs, src, cnt, its);
                     break;
                 case CL_R32:
                     hipLaunchKernelGGL(batch_stage1<32>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
-                    hipLaunchKernelGGL(batch_stage2<32>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_stage2<32>, grid, dim3(BT_NT), 0, cs, d, dimgs, src, cnt, its);
                     break;
                 case CL_BOXH:
-                    hipLaunchKernelGGL(batch_box<false>, grid, dim3(BOX_NT), L[cls].lds, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_box<false>, grid, dim3(BOX_NT), L[cls].lds, cs, d, dimgs, src, cnt, its);
                     break;
                 default:
-                    hipLaunchKernelGGL(batch_box<true>, grid, dim3(BOX_NT), L[cls].lds, cs, d, dimgs, src);
+                    hipLaunchKernelGGL(batch_box<true>, grid, dim3(BOX_NT), L[cls].lds, cs, d, dimgs, src, cnt, its);
                     break;
             }
         };
@@ -314,7 +357,7 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
             if (!L[cls].count) continue;
             hipStream_t cs = P->chains[kChains + cls];
             ok = hipStreamWaitEvent(cs, fork_it, 0) == hipSuccess;
-            for (int k = 0; k < P->iters && ok; ++k) launch_class(cls, (start + k) % 2, cs);
+            for (int k = 0; k < P->iters && ok; ++k) launch_class(cls, (start + k) % 2, cs, k == P->iters - 1);
             hipEvent_t join = ok ? event() : nullptr;
             ok = ok && join && hipEventRecord(join, cs) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
         }
@@ -334,13 +377,19 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
 
 int batch_run(BatchPlan* P, hipStream_t st) { return hipGraphLaunch(P->exec, st) == hipSuccess ? 0 : -4; }
 
+// Per-image latency: from the start of the graph to the completion of the
+// image's last tile (written by that tile; 0 iterations: its group's end).
 int batch_latencies(BatchPlan* P, double* us)
 {
-    std::vector<unsigned long long> t(P->groups + 1);
-    if (hipMemcpy(t.data(), P->ts, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    std::vector<unsigned long long> t(P->groups + 1), ti(P->n);
+    if (hipMemcpy(t.data(), P->ts, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(ti.data(), P->img_ts, sizeof(unsigned long long) * ti.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return -4;
     const double per_us = (double)P->clock_khz / 1000.0;  // ticks per microsecond
-    for (int i = 0; i < P->n; ++i) us[i] = (double)(t[P->group_of[i] + 1] - t[0]) / per_us;
+    for (int i = 0; i < P->n; ++i) {
+        const unsigned long long end = P->iters > 0 ? ti[i] : t[P->group_of[i] + 1];
+        us[i] = (double)(end - t[0]) / per_us;
+    }
     return 0;
 }
 

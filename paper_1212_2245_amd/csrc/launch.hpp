@@ -88,6 +88,9 @@ constexpr int packed_words_max() { return 2 * (2 * RAD + 1) * (2 * RAD + 1); }
 
 // Wiener step; fp64: M, spectra and transforms in FP64 (output rounded once).
 size_t wiener_ws_bytes(int H, int W, bool rowwise, bool fp64 = false);
+// Raises the LDS limit of the Wiener kernels (once per process; a plan calls
+// it before capturing a graph).
+void prepare_wiener_kernels();
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
                   float pos_floor, void* ws, bool rowwise, bool fp64, hipStream_t st);
 

@@ -446,8 +446,7 @@ static void allow_lds(K* kernel)
 }
 
 template <typename C>
-static int launch_wiener_t(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
-                           float pos_floor, void* ws, bool rowwise, hipStream_t st)
+static void allow_wiener_lds()
 {
     static std::once_flag once;
     std::call_once(once, [] {
@@ -456,6 +455,19 @@ static int launch_wiener_t(const float* f, float* u, int H, int W, int pitch, co
         allow_lds(&wiener_cols<C>);
         allow_lds(&wiener_rows_inv<C>);
     });
+}
+
+void prepare_wiener_kernels()
+{
+    allow_wiener_lds<float2>();
+    allow_wiener_lds<double2>();
+}
+
+template <typename C>
+static int launch_wiener_t(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
+                           float pos_floor, void* ws, bool rowwise, hipStream_t st)
+{
+    allow_wiener_lds<C>();
     if (rowwise) {
         C* M = reinterpret_cast<C*>(ws);
         hipLaunchKernelGGL(wiener_mult_1d<C>, dim3((W + 255) / 256), dim3(256), 0, st, psf, W, K, M);
