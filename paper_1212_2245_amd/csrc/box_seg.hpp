@@ -8,7 +8,9 @@
 // every BOX_SEG positions of the blur axis: at every position whose
 // coordinate is a multiple of BOX_SEG the window sum is formed afresh by a
 // direct sum of its n terms, and between two such positions it slides
-// (windows of at most BOX_SEG terms are always summed directly).  The
+// (windows of at most BOX_SEG terms are always summed directly, and so is
+// every window of an image of at most 512 x 512 pixels: such images are bound
+// by the latency of a tile, and direct sums have no serial chain).  The
 // re-basing points are absolute image coordinates, so the value at a pixel
 // does not depend on the tile that computes it: every tile shape gives
 // bitwise-identical results.  A non-integer length adds the two end pixels
@@ -45,6 +47,7 @@ struct BoxGeom {
     int hl, hr;          // u halo before / after the tile along the axis
     int nu, nq;          // u positions (TA + hl + hr), q positions (TA + n - 1 + 2 fr)
     int pu, pq, pg;      // LDS pitches: of u, q/W and g lines (horizontal) or rows (vertical)
+    int slide;           // 1: windows slide between re-basing points; 0: every window summed directly
 };
 
 // LDS pitch of an array whose lines are read by the threads (line c = t % TC,
@@ -75,6 +78,7 @@ __host__ __device__ inline BoxGeom box_geom(int H, int W, int n, float frac)
     g.hr = h > 2 ? h : 2;
     g.nu = TA + g.hl + g.hr;
     g.nq = TA + n - 1 + 2 * g.fr;
+    g.slide = n > BOX_SEG && (long)H * W > 512L * 512L;
     if (VERT) {
         g.pu = box_pitch(TC + 4, true, TC);
         g.pq = box_pitch(TC, true, TC);
@@ -256,6 +260,9 @@ struct BoxTileOps {
     // Phase B1: s = A u at the q positions (into the W array); B2: g.
     static DEBLUR_DEV void sums(int t, float* __restrict__ lds, const BoxGeom& g, const IterParams& p, int a0, int c0)
     {
+        // explicit fmaf only: no multiply-add fused by the compiler, so that every
+        // tile shape (every instantiation) rounds the same operations
+#pragma clang fp contract(off)
         float* U = lds;
         float* Q = U + (VERT ? g.nu * g.pu : (TC + 4) * g.pu);
         float* Wt = Q + (VERT ? g.nq * g.pq : TC * g.pq);
@@ -283,7 +290,7 @@ struct BoxTileOps {
                         const int n = g.n;
 #pragma unroll
                         for (int i = 0; i < BOX_SEG; ++i) {
-                            if (n > BOX_SEG && i > 0) {
+                            if (g.slide && i > 0) {
                                 S = (S + ub[(i + g.aL) * su]) - ub[(i - g.bL - 1) * su];
                             } else {
                                 S = seq_sum(ub + (i - g.bL) * su, su, n);
@@ -301,7 +308,7 @@ struct BoxTileOps {
                         // u position of the sample: the clamped position under constant
                         // continuation, x itself (the tile holds the wrapped u) if periodic
                         const int js = (p.bc == BC_PERIODIC ? x : xc) - ulo;
-                        const int r = g.n > BOX_SEG ? xc % BOX_SEG : 0;
+                        const int r = g.slide ? xc % BOX_SEG : 0;
                         if (js == jprev) {
                             // same sample as the previous position (clamped border run)
                         } else if (js == jprev + 1 && r != 0) {
@@ -341,6 +348,9 @@ struct BoxTileOps {
     static DEBLUR_DEV void diffusivity(int t, const float* __restrict__ U, float* __restrict__ G, const BoxGeom& g,
                                        const IterParams& p, int jmin, int jmax)
     {
+        // explicit fmaf only: no multiply-add fused by the compiler, so that every
+        // tile shape (every instantiation) rounds the same operations
+#pragma clang fp contract(off)
         constexpr int GW = TA + 2, GL = TC + 2;
         const int su = VERT ? g.pu : 1, lu = VERT ? 1 : g.pu;
         auto one = [&](int cc, int k) {
@@ -377,6 +387,9 @@ struct BoxTileOps {
     // array), in place, one position per thread and step.
     static DEBLUR_DEV void weights(int t, float* __restrict__ lds, const BoxGeom& g, const IterParams& p, int c0)
     {
+        // explicit fmaf only: no multiply-add fused by the compiler, so that every
+        // tile shape (every instantiation) rounds the same operations
+#pragma clang fp contract(off)
         float* Q = lds + (VERT ? g.nu * g.pu : (TC + 4) * g.pu);
         float* Wt = Q + (VERT ? g.nq * g.pq : TC * g.pq);
         auto one = [&](int iq, float sv, float fv) {
@@ -430,6 +443,9 @@ struct BoxTileOps {
                                         float* __restrict__ un, float* __restrict__ ckpt, int pitch,
                                         const BoxGeom& g, const IterParams& p, int x0, int gc)
     {
+        // explicit fmaf only: no multiply-add fused by the compiler, so that every
+        // tile shape (every instantiation) rounds the same operations
+#pragma clang fp contract(off)
         const int sq = VERT ? g.pq : 1, su = VERT ? g.pu : 1, sg = VERT ? g.pg : 1;
         const int lu = VERT ? 1 : g.pu, lg = VERT ? 1 : g.pg;   // next line
         const float* qb = Q + (VERT ? c : c * g.pq) + (o0 + g.fr) * sq;   // B window start of output o0
@@ -440,13 +456,13 @@ struct BoxTileOps {
         float N1 = 0.0f, N2 = 0.0f;
 #pragma unroll
         for (int i = 0; i < OPT; ++i) {
-            if (n > BOX_SEG && ((OPT % BOX_SEG == 0 && i % BOX_SEG != 0) || (OPT % BOX_SEG != 0 && i > 0 && (x0 + i) % BOX_SEG != 0))) {
+            if (g.slide && ((OPT % BOX_SEG == 0 && i % BOX_SEG != 0) || (OPT % BOX_SEG != 0 && i > 0 && (x0 + i) % BOX_SEG != 0))) {
                 N1 = (N1 + qb[(i + n - 1) * sq]) - qb[(i - 1) * sq];
                 N2 = (N2 + wb[(i + n - 1) * sq]) - wb[(i - 1) * sq];
             } else {
                 // re-base at the last multiple of BOX_SEG (chunks shorter than
                 // BOX_SEG may start after it), then slide to output i
-                const int r = n > BOX_SEG && OPT % BOX_SEG != 0 ? (x0 + i) % BOX_SEG : 0;
+                const int r = g.slide && OPT % BOX_SEG != 0 ? (x0 + i) % BOX_SEG : 0;
                 seq_sum2(qb + (i - r) * sq, wb + (i - r) * sq, sq, n, N1, N2);
                 for (int d = 1; d <= r; ++d) {
                     N1 = (N1 + qb[(i - r + d + n - 1) * sq]) - qb[(i - r + d - 1) * sq];
@@ -479,6 +495,9 @@ struct BoxTileOps {
                                   float* __restrict__ ckpt, int pitch, const BoxGeom& g, const IterParams& p, int a0,
                                   int c0)
     {
+        // explicit fmaf only: no multiply-add fused by the compiler, so that every
+        // tile shape (every instantiation) rounds the same operations
+#pragma clang fp contract(off)
         const float* U = lds;
         const float* Q = U + (VERT ? g.nu * g.pu : (TC + 4) * g.pu);
         const float* Wt = Q + (VERT ? g.nq * g.pq : TC * g.pq);
@@ -498,9 +517,9 @@ struct BoxTileOps {
             if (x >= g.N) break;
             // B window [x - aL, x + bL] at q positions [o + fr, o + fr + n - 1]
             const int w0 = o + g.fr;
-            if (x % BOX_SEG == 0 || o == o0 || g.n <= BOX_SEG) {
-                // re-base at the last multiple of BOX_SEG (o0 is one); short windows: direct sums
-                const int r = g.n > BOX_SEG ? x % BOX_SEG : 0;
+            if (x % BOX_SEG == 0 || o == o0 || !g.slide) {
+                // re-base at the last multiple of BOX_SEG (o0 is one); no sliding: direct sums
+                const int r = g.slide ? x % BOX_SEG : 0;
                 const int i0 = box_at<VERT>(c, w0 - r, g.pq);
                 seq_sum2(Q + i0, Wt + i0, VERT ? g.pq : 1, g.n, N1, N2);
                 for (int d = 1; d <= r; ++d) {

@@ -1,6 +1,7 @@
 // Single-image launcher of the fused box-iteration kernel (tile body in
-// box_seg.hpp).  Three tile shapes per orientation; every shape gives
-// bitwise-identical results (re-basing points are image coordinates).
+// box_seg.hpp).  Five tile shapes per orientation; every shape gives
+// bitwise-identical results (re-basing points are image coordinates and the
+// tile arithmetic is compiled without multiply-add contraction).
 #include <mutex>
 
 #include "box_seg.hpp"
@@ -37,15 +38,16 @@ static void launch_box(const float* f, const float* u, float* un, float* ckpt, i
                        p, ta);
 }
 
-int box_num_variants() { return 4; }
+int box_num_variants() { return 5; }
 
-// Default shape per orientation and size (variant 0); 1..4 explicit.  Small
-// images take the small tiles (2 outputs per thread), which spread them over
-// more compute units.
+// Default shape per orientation and size (variant 0); 1..5 explicit.  Images
+// up to 512^2 take the 64x4 tiles (one output per thread), which spread them
+// over more compute units.
 int box_default_variant(int H, int W, bool vert)
 {
-    if ((long)H * W <= 512L * 512L) return 4;
-    return vert ? 1 : 1;
+    (void)vert;
+    if ((long)H * W <= 512L * 512L) return 5;
+    return 1;
 }
 
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
@@ -58,14 +60,16 @@ int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt,
             case 1: launch_box<true, 128, 16>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
             case 2: launch_box<true, 256, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
             case 3: launch_box<true, 64, 32>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            default: launch_box<true, 64, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            case 4: launch_box<true, 64, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            default: launch_box<true, 64, 4>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
         }
     } else {
         switch (v) {
             case 1: launch_box<false, 256, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
             case 2: launch_box<false, 128, 16>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
             case 3: launch_box<false, 64, 32>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            default: launch_box<false, 64, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            case 4: launch_box<false, 64, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
+            default: launch_box<false, 64, 4>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
         }
     }
     return 0;
