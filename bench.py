@@ -1,28 +1,37 @@
 #!/usr/bin/env python3
 """WR3L benchmark on one MI355X.
 
-Workload (default): one 1024x1024 float32 image (rectangles on a gradient plus
-band-limited texture), oblique linear motion blur of length 31 px at a seeded
-random angle (31x31 bilinear line PSF), noise sigma 3; Wiener initialisation
-(K = 0.01) followed by 20 RRRL iterations with alpha = 0.002.
-
-One step = the whole hot path on that image: deblur_wiener + 20 iterations of
-deblur_rrrl_iterate, inputs resident in HBM.  value = RRRL megapixel-
-iterations per second of the whole step (H*W*iters / step time, Wiener time
-included).  The JSON line also carries:
-  * roofline: the dominant kernel's algorithmic rate (timed alone with HIP
-    events on its launch stream) against the MI355X peak for its bound;
-  * hbm: the iteration's algorithmic bytes (12 B per pixel-iteration read u, f,
-    write u; 8 B per pixel for Wiener) per second against 8 TB/s;
-  * cpu_baseline: the FP64 oracle on the host cores for the same workload.
+Headline workload: the batched form, 512 float32 images with sides drawn from
+{128, 192, 256, 384, 512, 768, 1024}, each with its own PSF (half uniform
+axis-aligned motion blur of length 5..41, half oblique line blur of length
+9..31), noise sigma 1..4, Wiener initialisation then 15 RRRL iterations each.
+One step = one launch of the batch plan (one hipGraph: every image's Wiener
+step and all iterations), inputs resident in HBM.  value = RRRL megapixel-
+iterations per second over the whole batch (sum of H*W*iters / step time,
+Wiener time included).  The JSON line also carries:
+  * batched: images/s, per-image latency p50/p99 (completion time stamped by
+    each image's last tile), for the one-group plan and for 64-image groups;
+  * roofline: the batch's dominant kernel (largest time per batch), each
+    class kernel timed alone with HIP events on its launch stream, against
+    the MI355X peak for its bound (ALU for the stencil classes, HBM for the
+    running-sum classes); roofline_classes: every class;
+  * ceilings: the HBM fraction each path could reach if it ran at its ALU
+    roofline (the paths are ALU-bound per the instruction counts);
+  * cpu_baseline: the FP64 oracle on the host cores on a sample of the batch's
+    images, with the GPU's error against it on those images;
+  * configs: the single-image workloads (256^2 box, 1024^2 oblique line,
+    2048^2 Gaussian mixture against the full-size oracle on both
+    continuations, the 64 x 512^2 differentiation workload).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
-       python bench.py --ingest-pmc DIR   (rocprofv3 --pmc databases -> profiles/)
-       python bench.py --summarize-trace DB OUT   (rocprofv3 kernel trace -> markdown)
+       python bench.py --ingest-pmc DIR --kernels FRAG...   (rocprofv3 --pmc CSVs -> profiles/kernel_traffic.json)
+       python bench.py --summarize-trace CSV OUT [--solo-calls N]   (rocprofv3 kernel trace -> markdown + JSON)
+       python bench.py --summarize-counters CSV... OUT --kernels FRAG...
 """
 from __future__ import annotations
 
 import argparse
+import csv
 import glob
 import hashlib
 import json
@@ -33,24 +42,33 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (packed FMA), TFLOP/s
+FP32_UNPACKED_TFLOPS = 78.6      # the same without packed FP32 (the code is built without it)
 CSRC = os.path.join(ROOT, "paper_1212_2245_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 METRIC = "RRRL megapixel-iterations/s + % HBM peak at ≤1e-4 rel-L2 vs FP64; batched images/s"
 
-# kernel name fragments as they appear in rocprofv3 traces
-KERNELS = {"stage1": "rrrl_taps_stage1", "stage2": "rrrl_taps_stage2"}
+# the sources each kernel family is compiled from (its include closure):
+# counter figures stay valid while these are unchanged
+KERNEL_SOURCES = {
+    "stencil": ("rrrl_taps.hip", "stencil_tiles.hpp", "launch.hpp", "psf.hpp", "common.hpp"),
+    "box": ("rrrl_box.hip", "box_seg.hpp", "launch.hpp", "common.hpp"),
+    "batch": ("batch.hip", "box_seg.hpp", "stencil_tiles.hpp", "launch.hpp", "psf.hpp", "common.hpp"),
+}
 
 
-# the sources the two stage kernels are compiled from (their include closure):
-# the HBM-traffic counters stay valid while these are unchanged
-STAGE_SOURCES = ("rrrl_taps.hip", "stencil_tiles.hpp", "launch.hpp", "psf.hpp", "common.hpp")
+def family_of(kernel: str) -> str:
+    if "batch_" in kernel:
+        return "batch"
+    if "rrrl_box_iter" in kernel:
+        return "box"
+    return "stencil"
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(family: str) -> str:
     h = hashlib.sha256()
-    for name in STAGE_SOURCES:
+    for name in KERNEL_SOURCES[family]:
         with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -61,27 +79,28 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--kernel-reps", type=int, default=50, help="launches per stage kernel for the roofline")
+    ap.add_argument("--kernel-reps", type=int, default=50, help="solo launches per class kernel for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched 512-image measurement")
-    ap.add_argument("--no-configs", action="store_true",
-                    help="skip the per-configuration figures (256^2 box, 2048^2 Gaussian stencil/FFT, "
-                         "64 x 512^2 forward + backward)")
+    ap.add_argument("--no-configs", action="store_true", help="skip the single-image and differentiation figures")
+    ap.add_argument("--no-config2-oracle", action="store_true",
+                    help="skip the full-size FP64 oracle of the 2048^2 workload (about a minute of host time)")
     ap.add_argument("--grad-images", type=int, default=64, help="images of the differentiation workload")
     ap.add_argument("--batch-images", type=int, default=512)
-    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--latency-group", type=int, default=64,
-                    help="group size of the latency plan (images run group after group)")
-    ap.add_argument("--cpu-iters", type=int, default=20, help="RRRL iterations in the oracle sample")
+                    help="group size of the second plan whose per-image latencies are reported")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="host time budget of the oracle sample")
     ap.add_argument("--tile", default="auto",
-                    help="stencil tile shape: 'auto' (autotuner, not cached), 0 (library default) or 1..n")
+                    help="batch tile shapes: auto (tuned here), default, or S,BH,BV variants")
     ap.add_argument("--pmc-calibrate", action="store_true",
-                    help="also run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--ingest-pmc", metavar="DIR", help="parse rocprofv3 --pmc databases and exit")
-    ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT"),
-                    help="write a markdown summary of a rocprofv3 --kernel-trace database and exit")
-    ap.add_argument("--summarize-counters", nargs="+", metavar="DB_OR_OUT",
-                    help="rocprofv3 --pmc databases of the stencil stages, then the output markdown file")
+                    help="also copy 256 MiB device-to-device (the scale of the HBM byte counters)")
+    ap.add_argument("--ingest-pmc", metavar="DIR", help="parse rocprofv3 --pmc CSVs (DIR/fetch, DIR/write) and exit")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("CSV", "OUT"),
+                    help="summarize a rocprofv3 kernel-trace CSV into OUT (.md) and OUT's .json, then exit")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="CSV_OR_OUT",
+                    help="per-wavefront SQ counters of --kernels from rocprofv3 --pmc CSVs; last argument = OUT")
+    ap.add_argument("--kernels", nargs="+", default=[], help="kernel name fragments for --ingest-pmc / counters")
+    ap.add_argument("--solo-calls", type=int, default=0,
+                    help="with --summarize-trace: launches per class kernel on the bench's timing stream")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
     ap.add_argument("--quality", action="store_true",
                     help="print the SNR table of the methods on the Table 1 stand-ins (one JSON line) and exit")
@@ -89,48 +108,84 @@ def parse_args():
 
 
 # ------------------------------------------------------------- profiles
-def _rocpd_rows(db: str, sql: str):
-    import sqlite3
-    con = sqlite3.connect(db)
-    try:
-        return list(con.execute(sql))
-    finally:
-        con.close()
+def _short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").replace("deblur::", "")
 
 
-def summarize_trace(db: str, out: str, command: str) -> None:
-    """Per-kernel summary (calls, total, average duration) of a rocprofv3
-    --kernel-trace database, as a short markdown file."""
-    rows = _rocpd_rows(db, "select name, total_calls, total_duration, average, percentage from top_kernels")
+def _csv_rows(path: str):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_trace(path: str, out: str, command: str, solo_calls: int = 0) -> None:
+    """Per-kernel, per-stream summary (calls, total, average duration) of a
+    rocprofv3 --kernel-trace CSV as markdown (OUT) and JSON (OUT with .json).
+    Rows on a stream where a kernel has exactly solo_calls launches are the
+    bench's solo timing launches (marked solo)."""
+    agg: dict = {}
+    for r in _csv_rows(path):
+        k = (_short(r["Kernel_Name"]), r.get("Stream_Id", "?"))
+        d = agg.setdefault(k, [0, 0.0])
+        d[0] += 1
+        d[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+    total = sum(v[1] for v in agg.values()) or 1.0
+    rows = sorted(agg.items(), key=lambda kv: -kv[1][1])
     lines = [f"# rocprofv3 kernel trace: {os.path.basename(out)}", "", "Command:", "", "```", command, "```", "",
-             "| kernel | calls | total us | avg us | % |", "|---|---|---|---|---|"]
-    for name, calls, tot, avg, pct in rows:
-        short = name.split("(")[0].replace("void ", "")
-        lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.3f} | {pct:.1f} |")
+             "Durations per kernel and stream" + (f"; solo = the {solo_calls} launches per class kernel of the "
+                                                   "bench's timing stream" if solo_calls else "") + ".", "",
+             "| kernel | stream | calls | total us | avg us | % |", "|---|---|---|---|---|---|"]
+    js = {"command": command, "solo_calls": solo_calls,
+          "source_hash": {f: kernel_source_hash(f) for f in KERNEL_SOURCES}, "kernels": []}
+    for (name, stream), (calls, tot) in rows:
+        solo = bool(solo_calls) and calls == solo_calls
+        lines.append(f"| `{name}` | {stream}{' (solo)' if solo else ''} | {calls} | {tot:.1f} | {tot / calls:.3f} | "
+                     f"{100 * tot / total:.1f} |")
+        js["kernels"].append({"kernel": name, "stream": stream, "calls": calls, "total_us": round(tot, 3),
+                              "avg_us": round(tot / calls, 3), "solo": solo})
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    with open(os.path.splitext(out)[0] + ".json", "w") as fh:
+        json.dump(js, fh, indent=1)
     print("\n".join(lines))
 
 
-def summarize_counters(dbs, out: str, command: str) -> None:
-    """Per-wavefront figures of the stencil stage kernels from rocprofv3 --pmc
-    databases (SQ_* counters; cycle counters in units of 4 cycles)."""
+def rocprof_solo_avg(kernel: str, trace_json: str):
+    """Average duration (us) of a kernel's solo launches in a committed trace
+    summary, or None (no summary, or the kernel's sources changed since)."""
+    try:
+        d = json.load(open(trace_json))
+    except (OSError, ValueError):
+        return None
+    fam = family_of(kernel)
+    if d.get("source_hash", {}).get(fam) != kernel_source_hash(fam):
+        return None
+    for r in d.get("kernels", []):
+        if r["solo"] and r["kernel"] == kernel:
+            return r["avg_us"]
+    return None
+
+
+def summarize_counters(paths, out: str, command: str, frags) -> None:
+    """Per-wavefront figures of the kernels matching `frags` from rocprofv3
+    --pmc CSVs (SQ_* counters, averaged over dispatches; cycle counters in
+    units of 4 cycles)."""
     vals: dict = {}
-    for db in dbs:
-        for kname, ctr, v in _rocpd_rows(db, "select kernel_name, counter_name, avg(value) from counters_collection "
-                                             "group by kernel_name, counter_name"):
-            for k, frag in KERNELS.items():
-                if frag in kname:
-                    vals.setdefault(k, {"name": kname.split("(")[0].replace("void ", "")})[ctr] = v
+    for path in paths:
+        acc: dict = {}
+        for r in _csv_rows(path):
+            name = _short(r["Kernel_Name"])
+            if not any(f in name for f in frags):
+                continue
+            acc.setdefault((name, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+        for (name, ctr), v in acc.items():
+            vals.setdefault(name, {})[ctr] = sum(v) / len(v)
     lines = [f"# rocprofv3 counters: {os.path.basename(out)}", "", "Command (one pass per counter set):", "",
              "```", command, "```", "",
              "Per dispatch, divided by SQ_WAVES (cycle counters are in units of 4 cycles).", ""]
-    for k, c in sorted(vals.items()):
+    for name, c in sorted(vals.items()):
         w = c.get("SQ_WAVES", 0.0) or 1.0
-        lines += [f"## {k}: `{c['name']}`", "", "| counter | per dispatch | per wavefront |", "|---|---|---|"]
+        lines += [f"## `{name}`", "", "| counter | per dispatch | per wavefront |", "|---|---|---|"]
         for n in sorted(c):
-            if n == "name":
-                continue
             lines.append(f"| {n} | {c[n]:.0f} | {c[n] / w:.1f} |")
         lines.append("")
     with open(out, "w") as fh:
@@ -138,61 +193,90 @@ def summarize_counters(dbs, out: str, command: str) -> None:
     print("\n".join(lines))
 
 
-def ingest_pmc(d: str, command: str = "") -> None:
-    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the kernels from two
-    rocprofv3 --pmc databases under d/fetch and d/write, scaled by what the
-    same counters read for the largest plain device copy in the same run
-    (bench.py --pmc-calibrate copies 256 MiB), into
-    profiles/stage_kernels_traffic.json."""
-    res = {"source_hash": kernel_source_hash(), "command": command, "kernels": {}}
-    scale = {}
+TRAFFIC_JSON = os.path.join(PROFILES, "kernel_traffic.json")
+
+
+def ingest_pmc(d: str, command: str, frags) -> None:
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the kernels matching
+    `frags`, from two rocprofv3 --pmc CSVs under d/fetch and d/write, scaled
+    by what the same counters read for the largest plain device copy of the
+    run (bench.py --pmc-calibrate copies 256 MiB); merged into
+    profiles/kernel_traffic.json with each kernel's source hash."""
+    try:
+        res = json.load(open(TRAFFIC_JSON))
+    except (OSError, ValueError):
+        res = {"kernels": {}}
+    scale, per = {}, {}
     for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
-        dbs = glob.glob(os.path.join(d, sub, "**", "*.db"), recursive=True)
-        if not dbs:
-            raise SystemExit(f"no database under {os.path.join(d, sub)}")
-        rows = _rocpd_rows(dbs[0], "select kernel_name, value, grid_size from counters_collection "
-                                   f"where counter_name = '{ctr}'")
-        copies = [r for r in rows if "copyBuffer" in r[0]]
-        big = max(copies, key=lambda r: r[2])
+        paths = glob.glob(os.path.join(d, sub, "**", "*counter_collection.csv"), recursive=True)
+        if not paths:
+            raise SystemExit(f"no counter CSV under {os.path.join(d, sub)}")
+        rows = [r for r in _csv_rows(paths[0]) if r["Counter_Name"] == ctr]
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        big = max(copies, key=lambda r: int(r["Grid_Size"]))
         copy_bytes = json.load(open(os.path.join(d, "calib.json")))["copy_bytes"]
-        scale[ctr] = copy_bytes / (big[1] * 1024.0)
-        for k, frag in KERNELS.items():
-            vals = [r[1] for r in rows if frag in r[0]]
-            if vals:
-                res["kernels"].setdefault(k, {})[ctr + "_KiB"] = sum(vals) / len(vals)
-    res["scale"] = scale
-    for k, v in res["kernels"].items():
-        v["traffic_bytes"] = (v["FETCH_SIZE_KiB"] * scale["FETCH_SIZE"] + v["WRITE_SIZE_KiB"] * scale["WRITE_SIZE"]) * 1024.0
+        scale[ctr] = copy_bytes / (float(big["Counter_Value"]) * 1024.0)
+        for r in rows:
+            name = _short(r["Kernel_Name"])
+            if any(f in name for f in frags):
+                per.setdefault(name, {}).setdefault(ctr, []).append(float(r["Counter_Value"]))
+    for name, c in per.items():
+        e = {k + "_KiB": sum(v) / len(v) for k, v in c.items()}
+        e["traffic_bytes"] = (e["FETCH_SIZE_KiB"] * scale["FETCH_SIZE"] + e["WRITE_SIZE_KiB"] * scale["WRITE_SIZE"]) * 1024.0
+        e["scale"] = scale
+        e["source_hash"] = kernel_source_hash(family_of(name))
+        e["command"] = command
+        res["kernels"][name] = e
     os.makedirs(PROFILES, exist_ok=True)
-    with open(os.path.join(PROFILES, "stage_kernels_traffic.json"), "w") as fh:
+    with open(TRAFFIC_JSON, "w") as fh:
         json.dump(res, fh, indent=1)
     print(json.dumps(res, indent=1))
 
 
 def load_traffic(kernel: str):
-    p = os.path.join(PROFILES, "stage_kernels_traffic.json")
-    if not os.path.exists(p):
+    """Counted HBM bytes per launch of a kernel, or None (not counted, or its
+    sources changed since the counters were taken)."""
+    try:
+        e = json.load(open(TRAFFIC_JSON))["kernels"].get(kernel)
+    except (OSError, ValueError, KeyError):
         return None
-    d = json.load(open(p))
-    if d.get("source_hash") != kernel_source_hash():
-        return None  # kernels changed since the counters were taken
-    return (d.get("kernels", {}).get(kernel) or {}).get("traffic_bytes")
+    if not e or e.get("source_hash") != kernel_source_hash(family_of(kernel)):
+        return None
+    return e["traffic_bytes"]
 
 
 # ------------------------------------------------------------------- batched
-def bench_batched(dev, args):
-    """512 images, sides from {128,...,1024}, half uniform axis-aligned motion
-    (L 5..41), half oblique lines (L 9..31), 15 iterations each, in one graph
-    launch (one group); per-image latency from a second plan whose images run
-    in consecutive groups."""
+CLASS_NAMES = ("stencil_r4", "stencil_r8", "stencil_r16", "stencil_r32", "box_h", "box_v")
+STENCIL_SHAPES = {1: (32, 512), 2: (16, 256), 3: (32, 256)}           # batch stencil variants (rows, threads)
+BOX_SHAPES = {False: {1: (256, 8), 2: (128, 16), 3: (64, 32), 4: (64, 8), 5: (64, 4)},   # (along, across)
+              True: {1: (128, 16), 2: (256, 8), 3: (64, 32), 4: (64, 8), 5: (64, 4)}}
+BATCH_DEFAULT_TILES = (1, 4, 4)
+# algorithmic operations per pixel-iteration beyond the blur taps: the
+# robust weight and quotient (~20), the diffusivity (~12) and the diffusion
+# term and update (~20) of eqs. (9)-(12), plus the two window sums of each
+# running-sum pass (~8 with re-basing) for a box
+STENCIL_EXTRA_FLOPS = 40       # per stage, as counted for the roofline (1 FMA = 2 flops)
+BOX_OPS_PER_PX = 80            # VALU operations per pixel-iteration of the fused box iteration
+BYTES_PER_PX_IT = 12.0         # read u and f, write u'
+
+
+def class_kernel(cls: int, stage: int, tiles) -> str:
+    """The class kernel's name as the kernel trace prints it."""
+    if cls >= 4:
+        vert = cls == 5
+        ta, tc = BOX_SHAPES[vert][tiles[2] if vert else tiles[1]]
+        return f"batch_box<{'true' if vert else 'false'}, {ta}, {tc}>"
+    th, nt = STENCIL_SHAPES[tiles[0]]
+    return f"batch_stage{stage}<{4 << cls}, {th}, {nt}>"
+
+
+def batch_workload(dev, n):
     import torch
 
     import paper_1212_2245_amd as dbl
     import synth
 
-    t0 = time.perf_counter()
-    cases = [synth.make_case(3, image=i) for i in range(args.batch_images)]
-    gen_s = time.perf_counter() - t0
+    cases = [synth.make_case(3, image=i) for i in range(n)]
 
     def gpu_psf(c):
         if c.kind == synth.KIND_BOX_H:
@@ -203,38 +287,77 @@ def bench_batched(dev, args):
 
     items = [(torch.from_numpy(c.f).to(dev), gpu_psf(c), dbl.Params(alpha=c.alpha, iters=c.iters), c.K, 1.0)
              for c in cases]
-    iters = cases[0].iters
-    npx = sum(c.f.size for c in cases)
-    t0 = time.perf_counter()
-    plan = dbl.BatchPlan(items)
-    plan_ms = (time.perf_counter() - t0) * 1e3
-    plan.run()
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.batch_reps):
-        plan.run()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.batch_reps
-    plan.close()
-    lat_plan = dbl.BatchPlan(items, group_size=args.latency_group)
-    lat_plan.run()
-    torch.cuda.synchronize()
-    lat = lat_plan.latencies_us()
-    lat_plan.close()
+    return cases, items
+
+
+def time_classes(plan, cases, tiles, reps: int):
+    """Every class kernel of the plan launched alone reps times (after one
+    warm launch) on a dedicated stream, timed with HIP events on that stream;
+    algorithmic work per launch and the rate against the class's roofline."""
     import numpy as np
-    alg = 12.0 * npx * iters + 8.0 * npx
-    return {"images": len(cases), "megapixels": round(npx / 1e6, 2), "iters": iters, "ms_per_batch": round(ms, 3),
-            "images_per_s": round(len(cases) / (ms * 1e-3), 1),
-            "mpx_it_per_s": round(npx * iters / (ms * 1e-3) / 1e6, 1),
-            "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "latency_group": args.latency_group,
-            "latency_p50_us": round(float(np.percentile(lat, 50)), 1),
-            "latency_p99_us": round(float(np.percentile(lat, 99)), 1),
-            "plan_create_ms": round(plan_ms, 1), "generate_s": round(gen_s, 1),
-            "kinds": {"box_h": sum(c.kind == 0 for c in cases), "box_v": sum(c.kind == 1 for c in cases),
-                      "line": sum(c.kind == 2 for c in cases)}}
+    import torch
+
+    iters = cases[0].iters
+    solo = torch.cuda.Stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cls_of = [plan.class_of(i) for i in range(plan.n)]
+    out = []
+    for cls in sorted(set(cls_of)):
+        imgs = [i for i in range(plan.n) if cls_of[i] == cls]
+        px = float(sum(cases[i].f.size for i in imgs))
+        for stage in ((1, 2) if cls < 4 else (1,)):
+            plan.launch_class(cls, stage, solo)
+            ev0.record(solo)
+            for _ in range(reps):
+                plan.launch_class(cls, stage, solo)
+            ev1.record(solo)
+            solo.synchronize()
+            us = ev0.elapsed_time(ev1) * 1e3 / reps
+            name = class_kernel(cls, stage, tiles)
+            e = {"class": CLASS_NAMES[cls], "kernel": name, "images": len(imgs), "megapixels": round(px / 1e6, 3),
+                 "tiles": plan.class_tiles(cls), "avg_launch_us": round(us, 3), "launches_per_batch": iters,
+                 "time_per_batch_us": round(us * iters, 1)}
+            if cls < 4:
+                taps = [int(np.count_nonzero(cases[i].psf)) for i in imgs]
+                per_tap = 2 if stage == 1 else 4        # A: T FMA; B on two channels: 2T FMA
+                flops = float(sum((per_tap * t + STENCIL_EXTRA_FLOPS) * cases[i].f.size for t, i in zip(taps, imgs)))
+                ach = flops / (us * 1e-6) / 1e12
+                e.update({"bound": "alu", "flops_per_launch": flops, "achieved": round(ach, 3), "unit": "TFLOP/s",
+                          "peak": FP32_VECTOR_PEAK_TFLOPS, "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
+                          "frac_of_unpacked": round(ach / FP32_UNPACKED_TFLOPS, 4),
+                          "mean_taps": round(float(np.mean(taps)), 1)})
+            else:
+                nbytes = BYTES_PER_PX_IT * px
+                ach = nbytes / (us * 1e-6) / 1e9
+                e.update({"bound": "hbm", "bytes_per_launch": nbytes, "achieved": round(ach, 1), "unit": "GB/s",
+                          "peak": HBM_PEAK_GBS, "frac": round(ach / HBM_PEAK_GBS, 4)})
+            out.append(e)
+    return out
+
+
+def hbm_ceilings(classes):
+    """HBM fraction each class could reach at its ALU roofline: the time of
+    its algorithmic operations at the unpacked FP32 rate (78.6 TFLOP/s, i.e.
+    39.3 T lane-operations/s) against the time of its 12 B per
+    pixel-iteration at 8 TB/s."""
+    t_hbm = BYTES_PER_PX_IT / (HBM_PEAK_GBS * 1e9)
+    ops_rate = FP32_UNPACKED_TFLOPS * 1e12 / 2
+    out = {}
+    for e in classes:
+        if e["bound"] == "alu":
+            if not e["kernel"].startswith("batch_stage1"):
+                continue
+            # both stages: 3T FMA + 2 x 40 extra flops, each extra flop one operation
+            ops = 3 * e["mean_taps"] + 2 * STENCIL_EXTRA_FLOPS
+        else:
+            ops = BOX_OPS_PER_PX
+        out[e["class"]] = {"ops_per_px_it": round(ops, 1), "hbm_frac_ceiling": round(min(1.0, t_hbm / (ops / ops_rate)), 3)}
+    return out
+
+
+def percentiles(lat):
+    import numpy as np
+    return round(float(np.percentile(lat, 50)), 1), round(float(np.percentile(lat, 99)), 1)
 
 
 # ------------------------------------------------------------ other configs
@@ -251,20 +374,20 @@ def _events_ms(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def bench_configs(dev, args):
-    """Per-configuration figures beside the headline: the 256^2 box workload
-    (Wiener + 10 iterations, parity vs the oracle), the 2048^2 Gaussian-mixture
-    workload (30 iterations; stencil with constant and periodic continuation,
-    FFT path periodic) and the differentiation workload (64 x 512^2 line PSF,
-    Wiener + 10 iterations with checkpoints, then the backward through both)."""
+def _err(got, want):
     import numpy as np
+    got = got.astype(np.float64)
+    return {"rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+            "max_abs": float(np.abs(got - want).max()),
+            "max_abs_rel_to_max": float(np.abs(got - want).max() / np.abs(want).max())}
+
+
+def config0(dev, args):
+    """256^2, horizontal box L=15: Wiener + 10 iterations per solve."""
     import torch
 
     import paper_1212_2245_amd as dbl
     import synth
-    out = {}
-
-    # config 0: 256^2, horizontal box L=15
     c = synth.make_case(0)
     H, W = c.f.shape
     f = torch.from_numpy(c.f).to(dev)
@@ -285,27 +408,91 @@ def bench_configs(dev, args):
     e = None
     if not args.no_cpu_baseline:
         import oracle
-        t0 = time.perf_counter()
-        want = oracle.wr3l(c.f, c.psf, c.K, oracle.Params(alpha=c.alpha), c.iters, threads=1)
-        t_cpu = time.perf_counter() - t0
-        e = {"rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
-             "max_abs": float(np.abs(got - want).max()), "oracle_ms_1core": round(t_cpu * 1e3, 2)}
+        e = _err(got, oracle.wr3l(c.f, c.psf, c.K, oracle.Params(alpha=c.alpha), c.iters))
     it_us = (ms - msw) * 1e3 / c.iters
-    out["config0_box256"] = {"us_per_solve": round(ms * 1e3, 2), "wiener_us": round(msw * 1e3, 2),
-                             "iteration_us": round(it_us, 2),
-                             "mpx_it_per_s": round(H * W / it_us, 1),
-                             "hbm_frac": round((8 * H * W + 12 * H * W * c.iters) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-                             "parity": e}
-    # the same image with a box of non-integer length (fractional end pixels)
-    # and the integer length next to it, iterations only
+    res = {"workload": "256x256, horizontal box L=15, Wiener K=0.01 + 10 RRRL iterations alpha=0.003",
+           "us_per_solve": round(ms * 1e3, 2), "wiener_us": round(msw * 1e3, 2), "iteration_us": round(it_us, 2),
+           "mpx_it_per_s": round(H * W / it_us, 1),
+           "hbm_frac": round((8 * H * W + 12 * H * W * c.iters) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+           "parity": e}
     it = {}
-    for L in (c.length, c.length - 0.5):
+    for L in (c.length, c.length - 0.5):     # and a non-integer length (fractional end pixels)
         pL = dbl.Psf.box(L, "h")
         wsL = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, pL, p), dtype=torch.uint8, device=dev)
         it[str(L)] = round(_events_ms(lambda: dbl.deblur_rrrl_iterate(f, f, u, pL, p, ws=wsL), 50) * 1e3 / c.iters, 2)
-    out["config0_box256"]["iteration_us_by_length"] = it
+    res["iteration_us_by_length"] = it
+    return res
 
-    # config 2: 2048^2, 31x31 Gaussian mixture, 30 iterations
+
+def config1(dev, args):
+    """1024^2, oblique line L=31 (31x31 bilinear PSF): Wiener + 20 iterations,
+    the stencil path with autotuned tiles; both stage kernels timed alone."""
+    import numpy as np
+    import torch
+
+    import paper_1212_2245_amd as dbl
+    import synth
+    from paper_1212_2245_amd import autotune
+    case = synth.make_case(1)
+    H, W = case.f.shape
+    iters = case.iters
+    f = torch.from_numpy(case.f).to(dev)
+    psf = dbl.Psf.from_taps(torch.from_numpy(case.psf).to(dev))
+    tune = autotune.tune(f, psf, dbl.Params(alpha=case.alpha, iters=iters), store=False)
+    tile = int(tune["tile"])
+    params = dbl.Params(alpha=case.alpha, iters=iters, tile=tile)
+    u = torch.empty_like(f)
+    ws_w = torch.empty(dbl.deblur_workspace_bytes(0, H, W, W, psf), dtype=torch.uint8, device=dev)
+    ws_i = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, psf, params), dtype=torch.uint8, device=dev)
+
+    def step():
+        dbl.deblur_wiener(f, u, psf, case.K, 1.0, ws=ws_w)
+        dbl.deblur_rrrl_iterate(f, u, u, psf, params, ws=ws_i)
+    ms = _events_ms(step, 20)
+    step()
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    ms_w = _events_ms(lambda: dbl.deblur_wiener(f, u, psf, case.K, 1.0, ws=ws_w), 20)
+    taps = dbl.deblur_compile_taps(psf)
+    qw = torch.empty((H, W, 2), dtype=torch.float32, device=dev)
+    u2 = torch.empty_like(u)
+    p1 = dbl.Params(alpha=case.alpha, iters=1, tile=tile)
+    T = int(np.count_nonzero(case.psf))
+    kt = {}
+    for name, fn, per_tap in (("stage1", lambda: dbl.deblur_rrrl_weights(f, u, qw, psf, taps, p1), 2),
+                              ("stage2", lambda: dbl.deblur_rrrl_update(qw, u, u2, psf, taps, p1), 4)):
+        us = _events_ms(fn, args.kernel_reps) * 1e3
+        fl = (per_tap * T + STENCIL_EXTRA_FLOPS) * H * W
+        kt[name] = {"avg_launch_us": round(us, 3), "flops_per_launch": fl,
+                    "achieved_tflops": round(fl / (us * 1e-6) / 1e12, 3),
+                    "frac": round(fl / (us * 1e-6) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)}
+    res = {"workload": "1024x1024, oblique line blur L=31 (31x31 bilinear PSF, %d taps), Wiener K=0.01 + "
+                       "20 RRRL iterations alpha=0.002, replicate border" % T,
+           "ms_per_solve": round(ms, 4), "wiener_ms": round(ms_w, 4),
+           "iteration_us": round((ms - ms_w) * 1e3 / iters, 3),
+           "mpx_it_per_s": round(H * W * iters / (ms * 1e-3) / 1e6, 1),
+           "hbm_frac": round((12.0 * H * W * iters + 8.0 * H * W) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+           "tile": tile, "tile_timings_us": {str(k): round(v, 2) for k, v in tune["timings_us"].items()},
+           "stage_kernels": kt}
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        want = oracle.wr3l(case.f, case.psf, case.K, oracle.Params(alpha=case.alpha), iters,
+                           threads=oracle.default_threads())
+        res["parity"] = _err(got, want)
+        res["parity"]["oracle_s"] = round(time.perf_counter() - t0, 2)
+    return res
+
+
+def config2(dev, args):
+    """2048^2, 31x31 Gaussian mixture, Wiener + 30 iterations: the stencil path
+    on both continuations and the FFT path (periodic), each against the
+    full-size FP64 oracle on its continuation (Sec. 4.2)."""
+    import numpy as np
+    import torch
+
+    import paper_1212_2245_amd as dbl
+    import synth
     c = synth.make_case(2)
     H, W = c.f.shape
     f = torch.from_numpy(c.f).to(dev)
@@ -313,7 +500,9 @@ def bench_configs(dev, args):
     u0 = torch.empty_like(f)
     wsw = torch.empty(dbl.deblur_workspace_bytes(0, H, W, W, psf), dtype=torch.uint8, device=dev)
     msw = _events_ms(lambda: dbl.deblur_wiener(f, u0, psf, c.K, 1.0, ws=wsw), 5)
-    res = {"wiener_us": round(msw * 1e3, 1), "nonzero_taps": int(np.count_nonzero(c.psf))}
+    T = int(np.count_nonzero(c.psf))
+    res = {"workload": "2048x2048, 31x31 Gaussian-mixture PSF (%d taps), Wiener K=0.01 + 30 RRRL iterations "
+                       "alpha=0.002" % T, "wiener_us": round(msw * 1e3, 1)}
     outs = {}
     for name, bc, conv in (("stencil_replicate", dbl.BC_REPLICATE, dbl.CONV_STENCIL),
                            ("stencil_periodic", dbl.BC_PERIODIC, dbl.CONV_STENCIL),
@@ -326,15 +515,36 @@ def bench_configs(dev, args):
         it_us = ms * 1e3 / c.iters
         res[name] = {"iteration_us": round(it_us, 1), "mpx_it_per_s": round(H * W / it_us, 1)}
         if conv == dbl.CONV_STENCIL:
-            # both stencil stages: A (2T flops) and B on two channels (4T), plus ~80 per pixel
-            tflops = (6 * res["nonzero_taps"] + 80) * H * W / (it_us * 1e-6) / 1e12
+            tflops = (6 * T + 2 * STENCIL_EXTRA_FLOPS) * H * W / (it_us * 1e-6) / 1e12
             res[name]["roofline"] = {"bound": "alu", "achieved_tflops": round(tflops, 2),
                                      "peak": FP32_VECTOR_PEAK_TFLOPS, "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
     a, b = outs["stencil_periodic"], outs["fft_periodic"]
-    res["fft_vs_stencil_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(a))
-    out["config2_gauss2048"] = res
+    res["fft_vs_stencil_periodic_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(a))
+    if not (args.no_cpu_baseline or args.no_config2_oracle):
+        import oracle
+        threads = oracle.default_threads()
+        for bc, names in ((oracle.BC_REPLICATE, ("stencil_replicate",)),
+                          (oracle.BC_PERIODIC, ("stencil_periodic", "fft_periodic"))):
+            print(f"[bench] 2048^2 FP64 oracle, {'periodic' if bc else 'replicate'} continuation", file=sys.stderr,
+                  flush=True)
+            t0 = time.perf_counter()
+            want = oracle.wr3l(c.f, c.psf, c.K, oracle.Params(alpha=c.alpha, bc=bc), c.iters, threads=threads)
+            dt = time.perf_counter() - t0
+            for n in names:
+                res[n]["vs_oracle"] = _err(outs[n], want)
+                res[n]["vs_oracle"]["oracle_s"] = round(dt, 1)
+                res[n]["vs_oracle"]["oracle_threads"] = threads
+    return res
 
-    # config 4: forward with checkpoints + backward through Wiener and iterations
+
+def config4(dev, args):
+    """64 x 512^2 oblique lines (31-tap PSFs): Wiener + 10 iterations with
+    per-iteration checkpoints, then the backward pass through the iterations
+    and the Wiener step (dL/df, dL/dh, dL/dalpha)."""
+    import torch
+
+    import paper_1212_2245_amd as dbl
+    import synth
     cases = [synth.make_case(4, image=i) for i in range(args.grad_images)]
     H, W = cases[0].f.shape
     iters = cases[0].iters
@@ -344,7 +554,7 @@ def bench_configs(dev, args):
         psf = dbl.Psf.from_taps(torch.from_numpy(c.psf).to(dev))
         data.append((fd, psf, torch.from_numpy(c.g).to(dev), dbl.Params(alpha=c.alpha, iters=iters), c.K))
     p0 = data[0][3]
-    wsw = torch.empty(dbl.deblur_workspace_bytes(0, H, W, W, data[0][1]), dtype=torch.uint8, device=dev)
+    wsw = torch.empty(dbl.deblur_workspace_bytes(4, H, W, W, data[0][1]), dtype=torch.uint8, device=dev)  # FP64 Wiener
     wsi = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, data[0][1], p0), dtype=torch.uint8, device=dev)
     wsb = torch.empty(dbl.deblur_workspace_bytes(3, H, W, W, data[0][1], p0), dtype=torch.uint8, device=dev)
     ck = torch.empty((iters, H, W), dtype=torch.float32, device=dev)
@@ -352,7 +562,7 @@ def bench_configs(dev, args):
 
     def fwd(i):
         fd, psf, g, p, K = data[i]
-        dbl.deblur_wiener(fd, u, psf, K, 1.0, ws=wsw)
+        dbl.deblur_wiener(fd, u, psf, K, 1.0, ws=wsw, fp64=True)
         dbl.deblur_rrrl_iterate(fd, u, u, psf, p, ckpt=ck, ws=wsi)
 
     def fwd_bwd(i):
@@ -363,24 +573,53 @@ def bench_configs(dev, args):
     ms_f = _events_ms(lambda: [fwd(i) for i in range(len(data))], 2)
     ms_fb = _events_ms(lambda: [fwd_bwd(i) for i in range(len(data))], 2)
     npx = len(data) * H * W
-    out["config4_grad512"] = {"images": len(data), "ms_forward": round(ms_f, 3), "ms_forward_backward": round(ms_fb, 3),
-                              "images_per_s_fwd_bwd": round(len(data) / (ms_fb * 1e-3), 1),
-                              "mpx_it_per_s_fwd_bwd": round(npx * iters / (ms_fb * 1e-3) / 1e6, 1),
-                              "note": "gradient parity: tests/test_gpu_backward.py"}
-    return out
+    return {"workload": f"{len(data)} x 512x512, oblique line PSFs (31x31), Wiener (FP64 transforms) + 10 RRRL "
+                        "iterations with checkpoints, backward through both",
+            "images": len(data), "ms_forward": round(ms_f, 3), "ms_forward_backward": round(ms_fb, 3),
+            "images_per_s_fwd_bwd": round(len(data) / (ms_fb * 1e-3), 1),
+            "mpx_it_per_s_fwd_bwd": round(npx * iters / (ms_fb * 1e-3) / 1e6, 1),
+            "note": "gradient parity: tests/test_gpu_backward.py"}
+
+
+def cpu_sample(cases, outputs, budget_s: float):
+    """The FP64 oracle on the batch's images in order until budget_s of host
+    time is spent (at least one image); throughput and the GPU's error on
+    those images."""
+    import numpy as np
+
+    import oracle
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    done, errs = [], []
+    for i, c in enumerate(cases):
+        want = oracle.wr3l(c.f, c.psf, c.K, oracle.Params(alpha=c.alpha), c.iters, threads=threads)
+        errs.append(_err(outputs[i], want))
+        done.append(i)
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    pxit = sum(cases[i].f.size * cases[i].iters for i in done)
+    sizes = sorted({cases[i].f.shape[0] for i in done})
+    base = {"value": round(pxit / dt / 1e6, 4), "unit": "Mpx-it/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {len(done)} images of the batch (sides {sizes}, {pxit / 1e6:.1f} Mpx-it), "
+                      f"FP64 oracle Wiener + 15 RRRL iterations each, {dt:.1f} s wall on {threads} threads"}
+    parity = {"images": len(done), "max_rel_l2": max(e["rel_l2"] for e in errs),
+              "max_abs_rel_to_max": max(e["max_abs_rel_to_max"] for e in errs),
+              "median_rel_l2": float(np.median([e["rel_l2"] for e in errs])), "tol_rel_l2": 1e-4}
+    return base, parity
 
 
 # ------------------------------------------------------------------- bench
 def main():
     args = parse_args()
     if args.ingest_pmc:
-        ingest_pmc(args.ingest_pmc, args.command)
+        ingest_pmc(args.ingest_pmc, args.command, args.kernels)
         return
     if args.summarize_counters:
-        summarize_counters(args.summarize_counters[:-1], args.summarize_counters[-1], args.command)
+        summarize_counters(args.summarize_counters[:-1], args.summarize_counters[-1], args.command, args.kernels)
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
+        summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command, args.solo_calls)
         return
     if args.quality:
         import synth
@@ -400,150 +639,100 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1212_2245_amd as dbl
-    import synth
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    case = synth.make_case(1)
-    H, W = case.f.shape
-    iters = case.iters
-    f = torch.from_numpy(case.f).to(dev)
-    psf = dbl.Psf.from_taps(torch.from_numpy(case.psf).to(dev))
+
+    t0 = time.perf_counter()
+    cases, items = batch_workload(dev, args.batch_images)
+    gen_s = time.perf_counter() - t0
+    iters = cases[0].iters
+    npx = sum(c.f.size for c in cases)
     tune = None
     if args.tile == "auto":
         from paper_1212_2245_amd import autotune
-        tune = autotune.tune(f, psf, dbl.Params(alpha=case.alpha, iters=iters), store=False)
-        tile = int(tune["tile"])
+        print("[bench] tuning the batch tile shapes", file=sys.stderr, flush=True)
+        tune = autotune.tune_batch(items, store=False)
+        tiles = tuple(tune["tiles"])
+    elif args.tile == "default":
+        tiles = (0, 0, 0)
     else:
-        tile = int(args.tile)
-    params = dbl.Params(alpha=case.alpha, iters=iters, tile=tile)
-    u = torch.empty_like(f)
-    ws_w = torch.empty(dbl.deblur_workspace_bytes(0, H, W, W, psf), dtype=torch.uint8, device=dev)
-    ws_i = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, psf, params), dtype=torch.uint8, device=dev)
-
-    def step():
-        dbl.deblur_wiener(f, u, psf, case.K, 1.0, ws=ws_w)
-        dbl.deblur_rrrl_iterate(f, u, u, psf, params, ws=ws_i)
-
+        tiles = tuple(int(t) for t in args.tile.split(","))
+    resolved = tuple(t if t > 0 else d for t, d in zip(tiles, BATCH_DEFAULT_TILES))
+    t0 = time.perf_counter()
+    plan = dbl.BatchPlan(items, tiles=tiles)
+    plan_ms = (time.perf_counter() - t0) * 1e3
     for _ in range(args.warmup):
-        step()
+        plan.run()
     torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps), timing {args.steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] warmup done ({args.warmup} steps), timing {args.steps} steps of {len(cases)} images",
+          file=sys.stderr, flush=True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
     for _ in range(args.steps):
-        step()
+        plan.run()
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    ms_step = max(ms_step, 1e3 * wall / args.steps)
-    mpxit = H * W * iters / (ms_step * 1e-3) / 1e6
-    result_gpu = u.cpu().numpy()
+    ms_step = max(ev0.elapsed_time(ev1) / args.steps, 1e3 * wall / args.steps)
+    lat1 = plan.latencies_us()
+    outputs = [o.cpu().numpy() for o in plan.outputs]
 
-    # Wiener alone and one iteration alone (context)
-    ev0.record()
-    for _ in range(args.kernel_reps):
-        dbl.deblur_wiener(f, u, psf, case.K, 1.0, ws=ws_w)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_wiener = ev0.elapsed_time(ev1) / args.kernel_reps
+    print("[bench] class kernels alone", file=sys.stderr, flush=True)
+    classes = time_classes(plan, cases, resolved, args.kernel_reps)
+    plan.close()
+    dom = max(classes, key=lambda e: e["time_per_batch_us"])
+    rp = rocprof_solo_avg(dom["kernel"], os.path.join(PROFILES, "batched_512_kernel_trace.json"))
+    roofline = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"], "unit": dom["unit"],
+                "frac": dom["frac"], "traffic": load_traffic(dom["kernel"]), "kernel": dom["kernel"],
+                "class": dom["class"], "avg_launch_us": dom["avg_launch_us"],
+                "work_per_launch": dom.get("flops_per_launch", dom.get("bytes_per_launch")),
+                "rocprof_avg_us": rp,
+                "frac_rocprof": (round(dom["frac"] * dom["avg_launch_us"] / rp, 4) if rp else None)}
 
-    # per-kernel timing of the two stage kernels, each launched alone
-    taps = dbl.deblur_compile_taps(psf)
-    qw = torch.empty((H, W, 2), dtype=torch.float32, device=dev)
-    u2 = torch.empty_like(u)
-    p1 = dbl.Params(alpha=case.alpha, iters=1, tile=tile)
-    dbl.deblur_rrrl_weights(f, u, qw, psf, taps, p1)
-    dbl.deblur_rrrl_update(qw, u, u2, psf, taps, p1)
+    lat_plan = dbl.BatchPlan(items, group_size=args.latency_group, tiles=tiles)
+    lat_plan.run()
     torch.cuda.synchronize()
-    kt = {}
-    for name, fn in (("stage1", lambda: dbl.deblur_rrrl_weights(f, u, qw, psf, taps, p1)),
-                     ("stage2", lambda: dbl.deblur_rrrl_update(qw, u, u2, psf, taps, p1))):
-        ev0.record()
-        for _ in range(args.kernel_reps):
-            fn()
-        ev1.record()
-        torch.cuda.synchronize()
-        kt[name] = ev0.elapsed_time(ev1) / args.kernel_reps * 1e-3   # seconds per launch
-    T = int(np.count_nonzero(case.psf))
-    # algorithmic flops per pixel: stage 1 = A (T FMA) + robust weight and
-    # quotient (~40); stage 2 = B on two channels (2T FMA) + diffusion term and
-    # update (~40).  One FMA = 2 flops.
-    flops = {"stage1": (2 * T + 40) * H * W, "stage2": (4 * T + 40) * H * W}
-    dom = max(kt, key=lambda k: kt[k])
-    ach = flops[dom] / kt[dom] / 1e12
-    traffic = load_traffic(dom)
-    roofline = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": KERNELS[dom], "avg_launch_us": round(kt[dom] * 1e6, 3),
-                "flops_per_launch": flops[dom], "nonzero_taps": T,
-                "other_kernel": {"name": KERNELS["stage1" if dom == "stage2" else "stage2"],
-                                 "avg_launch_us": round(kt["stage1" if dom == "stage2" else "stage2"] * 1e6, 3)}}
-    alg_bytes = 12.0 * H * W * iters + 8.0 * H * W
-    hbm_gbs = alg_bytes / (ms_step * 1e-3) / 1e9
+    lat64 = lat_plan.latencies_us()
+    lat_plan.close()
+    p50, p99 = percentiles(lat1)
+    g50, g99 = percentiles(lat64)
+    alg = BYTES_PER_PX_IT * npx * iters + 8.0 * npx
     out = {
-        "metric": METRIC, "value": round(mpxit, 3), "unit": "Mpx-it/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "oblique line blur L=31 (31x31 bilinear PSF), 1024x1024, Wiener K=0.01 + "
-                               "20 RRRL iterations alpha=0.002, robust, TV, replicate border",
-                   "H": H, "W": W, "iters": iters, "psf_theta_rad": round(case.meta["theta"], 6),
-                   "tile": tile, "tile_timings_us": ({str(k): round(v, 2) for k, v in tune["timings_us"].items()}
-                                                     if tune else None)},
+        "metric": METRIC, "value": round(npx * iters / (ms_step * 1e-3) / 1e6, 1), "unit": "Mpx-it/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched RRRL: {len(cases)} images, sides from {{128,...,1024}}, half uniform "
+                               "axis-aligned motion blur L 5..41, half oblique line blur L 9..31, noise sigma 1..4, "
+                               "Wiener + 15 RRRL iterations each, one hipGraph launch per batch",
+                   "images": len(cases), "megapixels": round(npx / 1e6, 2), "iters": iters,
+                   "tiles": list(resolved), "tile_timings_us": tune["timings_us"] if tune else None},
         "roofline": roofline,
-        "hbm": {"algorithmic_bytes_per_step": alg_bytes, "achieved_GBs": round(hbm_gbs, 2),
-                "peak_GBs": HBM_PEAK_GBS, "frac": round(hbm_gbs / HBM_PEAK_GBS, 5)},
-        "wiener_ms": round(ms_wiener, 5),
-        "iteration_us": round((ms_step - ms_wiener) * 1e3 / iters, 3),
+        "batched": {"images_per_s": round(len(cases) / (ms_step * 1e-3), 1),
+                    "latency_p50_us": p50, "latency_p99_us": p99,
+                    "latency_group": args.latency_group, "group_latency_p50_us": g50, "group_latency_p99_us": g99,
+                    "plan_create_ms": round(plan_ms, 1), "generate_s": round(gen_s, 1),
+                    "kinds": {"box_h": sum(c.kind == 0 for c in cases), "box_v": sum(c.kind == 1 for c in cases),
+                              "line": sum(c.kind == 2 for c in cases)}},
+        "hbm": {"algorithmic_bytes_per_step": alg, "achieved_GBs": round(alg / (ms_step * 1e-3) / 1e9, 1),
+                "peak_GBs": HBM_PEAK_GBS, "frac": round(alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline_classes": classes,
+        "ceilings": hbm_ceilings(classes),
     }
-    # the same iterations with r_f through the lookup table of Sec. 4.1
-    # (speed only; its accuracy cost is measured by the parity tests)
-    p_lut = dbl.Params(alpha=case.alpha, iters=iters, tile=tile, rf_lut=True)
-    ws_l = torch.empty(dbl.deblur_workspace_bytes(1, H, W, W, psf, p_lut), dtype=torch.uint8, device=dev)
-    us_it = {}
-    u_it = torch.empty_like(u)
-    for name, pp, wsx in (("exact", params, ws_i), ("lookup", p_lut, ws_l)):
-        dbl.deblur_rrrl_iterate(f, u, u_it, psf, pp, ws=wsx)
-        ev0.record()
-        for _ in range(max(1, args.kernel_reps // 4)):
-            dbl.deblur_rrrl_iterate(f, u, u_it, psf, pp, ws=wsx)
-        ev1.record()
-        torch.cuda.synchronize()
-        us_it[name] = round(ev0.elapsed_time(ev1) / max(1, args.kernel_reps // 4) * 1e3 / iters, 3)
-    out["rf_iteration_us"] = us_it
-
-    if not args.no_batched:
-        print(f"[bench] batched workload: {args.batch_images} images", file=sys.stderr, flush=True)
-        out["batched"] = bench_batched(dev, args)
-
     if not args.no_configs:
-        print("[bench] per-configuration figures", file=sys.stderr, flush=True)
-        out["configs"] = bench_configs(dev, args)
-
+        print("[bench] single-image and differentiation workloads", file=sys.stderr, flush=True)
+        out["configs"] = {"box256": config0(dev, args), "line1024": config1(dev, args),
+                          "gauss2048": config2(dev, args), "grad512x64": config4(dev, args)}
     if not args.no_cpu_baseline:
-        import oracle
-        threads = oracle.default_threads()
-        t0 = time.perf_counter()
-        want = oracle.wr3l(case.f, case.psf, case.K, oracle.Params(alpha=case.alpha), args.cpu_iters,
-                           threads=threads)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(H * W * args.cpu_iters / dt / 1e6, 4), "unit": "Mpx-it/s",
-                               "cores": threads, "kind": "oracle",
-                               "sample": f"the full workload image (1024x1024), FP64 oracle Wiener + "
-                                         f"{args.cpu_iters} RRRL iterations, {dt:.2f} s wall"}
-        if args.cpu_iters == iters:
-            e = float(np.linalg.norm(result_gpu.astype(np.float64) - want) / np.linalg.norm(want))
-            out["parity"] = {"rel_l2": e, "max_abs": float(np.abs(result_gpu - want).max()), "tol": 1e-4}
-
+        print("[bench] FP64 oracle on a sample of the batch", file=sys.stderr, flush=True)
+        out["cpu_baseline"], out["parity"] = cpu_sample(cases, outputs, args.cpu_seconds)
     if args.pmc_calibrate:
         nbytes = 256 << 20
         a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)

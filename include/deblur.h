@@ -234,8 +234,8 @@ int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
  * device memory (per-image scratch planes, compiled tap lists, tile lists),
  * compiles the PSFs (their taps are read here: a changed PSF needs a new
  * plan) and captures the graph; it synchronises the device.  group_size > 0
- * runs the images in consecutive groups of that many (the latency of an
- * image is the completion of its group), 0 = one group. */
+ * runs the images in consecutive groups of that many (a group starts when
+ * the previous one has ended), 0 = one group. */
 typedef struct deblur_batch_plan deblur_batch_plan;
 typedef struct {
     const float* f;
@@ -249,12 +249,47 @@ typedef struct {
 
 int deblur_batch_plan_create(const deblur_batch_item* items, int32_t n, int32_t group_size,
                              deblur_batch_plan** plan);
+
+/* Tile shapes of a plan.  Family DEBLUR_BATCH_STENCIL: the 64-column tiles
+ * of the stencil classes (1: 32 rows / 512 threads, 2: 16 / 256, 3: 32 /
+ * 256); DEBLUR_BATCH_BOX: the box tile variants of deblur_box_tile_variants,
+ * per orientation.  Every shape gives bitwise-identical results. */
+#define DEBLUR_BATCH_STENCIL 0
+#define DEBLUR_BATCH_BOX 1
+/* Number of shapes of a family (0 for an unknown family). */
+int32_t deblur_batch_tile_variants(int32_t family);
+/* deblur_batch_plan_create with chosen tile shapes: tiles (host, 3 entries,
+ * or NULL for the defaults) = {stencil variant, horizontal box variant,
+ * vertical box variant}, each 0 (default: 1, 4, 4) .. the family's count,
+ * else DEBLUR_EINVAL.  Items with p.conv == DEBLUR_CONV_FFT are rejected
+ * with DEBLUR_EUNSUPPORTED by both create calls: a plan runs the direct
+ * paths (stencil, running sums) only. */
+int deblur_batch_plan_create_tiled(const deblur_batch_item* items, int32_t n, int32_t group_size,
+                                   const int32_t* tiles, deblur_batch_plan** plan);
+
+/* Tile classes of a plan: 0..3 stencil radius classes 4, 8, 16, 32; 4
+ * horizontal box; 5 vertical box. */
+#define DEBLUR_BATCH_NCLASS 6
+/* Class of an item (>= 0), or DEBLUR_EINVAL. */
+int32_t deblur_batch_class_of(const deblur_batch_plan* plan, int32_t image);
+/* Tiles of one launch of a class in the plan's first group (0 if none), or
+ * DEBLUR_EINVAL. */
+int32_t deblur_batch_class_tiles(const deblur_batch_plan* plan, int32_t cls);
+/* For per-kernel timing: enqueues on `stream`, outside the graph, one launch
+ * of one kernel of a class over the first group's tiles (stage 1 or 2 of a
+ * stencil class; stage 1 = the box kernel of a box class), reading the
+ * items' outputs and writing the plan's own scratch planes.  The outputs are
+ * left unchanged and the next deblur_batch_run recomputes everything.  It
+ * must not overlap a run of the same plan.  DEBLUR_EINVAL: no such class
+ * tiles or stage. */
+int deblur_batch_launch_class(deblur_batch_plan* plan, int32_t cls, int32_t stage, void* stream);
 /* Enqueues the whole batch (one graph launch) on `stream`. */
 int deblur_batch_run(deblur_batch_plan* plan, void* stream);
 /* Number of items of the plan. */
 int32_t deblur_batch_size(const deblur_batch_plan* plan);
 /* After a run has completed: per-item latency in microseconds from the start
- * of the graph to the completion of the item's group (device clock).  Host
+ * of the graph to the completion of the item's last tile in its last
+ * iteration (device clock; items with 0 iterations: their group's end).  Host
  * array of deblur_batch_size(plan) doubles.  Synchronous. */
 int deblur_batch_latencies(deblur_batch_plan* plan, double* us_out);
 /* Frees the plan (NULL is allowed). */

@@ -398,10 +398,14 @@ class BatchPlan:
     `items`: sequence of (f, psf, params, K, pos_floor) with f a 2D float32
     device tensor; outputs are allocated here (self.outputs).  All params
     must have the same `iters`.  group_size > 0 runs consecutive groups of
-    that many images one after another (per-image latency = completion of its
-    group)."""
+    that many images one after another.  `tiles`: None (library defaults),
+    "auto" (the tuned shapes of autotune.best_batch_tiles for this batch, the
+    defaults when none are cached) or (stencil, box_h, box_v) variants."""
 
-    def __init__(self, items, group_size: int = 0):
+    STENCIL, BOX = 0, 1                 # tile families
+    CLASS_NAMES = ("stencil_r4", "stencil_r8", "stencil_r16", "stencil_r32", "box_h", "box_v")
+
+    def __init__(self, items, group_size: int = 0, tiles=None):
         lib = _lib.load()
         self._keep = []
         self.outputs = []
@@ -413,11 +417,41 @@ class BatchPlan:
             self.outputs.append(u)
             arr[k] = _lib.deblur_batch_item(f.data_ptr(), u.data_ptr(), H, W, pitch, psf.c(), params.c(), float(K),
                                             float(floor))
+        if isinstance(tiles, str):
+            if tiles != "auto":
+                raise ValueError("tiles: None, 'auto' or three variants")
+            from . import autotune
+            tiles = autotune.best_batch_tiles(items)
+        self.tiles = tuple(int(t) for t in tiles) if tiles is not None else (0, 0, 0)
+        if len(self.tiles) != 3:
+            raise ValueError("tiles: (stencil, box_h, box_v)")
         self._plan = ctypes.c_void_p()
-        st = lib.deblur_batch_plan_create(arr, len(items), int(group_size), ctypes.byref(self._plan))
-        _lib.check(st, "deblur_batch_plan_create")
+        t3 = (ctypes.c_int32 * 3)(*self.tiles)
+        st = lib.deblur_batch_plan_create_tiled(arr, len(items), int(group_size), t3, ctypes.byref(self._plan))
+        _lib.check(st, "deblur_batch_plan_create_tiled")
         self.n = len(items)
         self.device = items[0][0].device
+
+    @staticmethod
+    def tile_variants(family: int) -> int:
+        return int(_lib.load().deblur_batch_tile_variants(int(family)))
+
+    def class_of(self, image: int) -> int:
+        c = _lib.load().deblur_batch_class_of(self._plan, int(image))
+        _lib.check(min(c, 0), "deblur_batch_class_of")
+        return int(c)
+
+    def class_tiles(self, cls: int) -> int:
+        c = _lib.load().deblur_batch_class_tiles(self._plan, int(cls))
+        _lib.check(min(c, 0), "deblur_batch_class_tiles")
+        return int(c)
+
+    def launch_class(self, cls: int, stage: int = 1, stream=None):
+        """One launch of one class kernel over the first group's tiles,
+        outside the graph (for per-kernel timing); outputs unchanged."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _lib.check(_lib.load().deblur_batch_launch_class(self._plan, int(cls), int(stage), s.cuda_stream),
+                   "deblur_batch_launch_class")
 
     def run(self):
         st = _lib.load().deblur_batch_run(self._plan, torch.cuda.current_stream(self.device).cuda_stream)

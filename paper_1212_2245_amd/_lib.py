@@ -63,6 +63,12 @@ SIGNATURES = [
                                             ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     ("deblur_batch_plan_create", ctypes.c_int, [ctypes.POINTER(deblur_batch_item), _I32, _I32,
                                                 ctypes.POINTER(ctypes.c_void_p)]),
+    ("deblur_batch_plan_create_tiled", ctypes.c_int, [ctypes.POINTER(deblur_batch_item), _I32, _I32,
+                                                      ctypes.POINTER(_I32), ctypes.POINTER(_VP)]),
+    ("deblur_batch_tile_variants", _I32, [_I32]),
+    ("deblur_batch_class_of", _I32, [_VP, _I32]),
+    ("deblur_batch_class_tiles", _I32, [_VP, _I32]),
+    ("deblur_batch_launch_class", ctypes.c_int, [_VP, _I32, _I32, _VP]),
     ("deblur_batch_run", ctypes.c_int, [_VP, _VP]),
     ("deblur_batch_size", _I32, [_VP]),
     ("deblur_batch_latencies", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),

@@ -1,14 +1,21 @@
-"""Tile-shape autotuner for the stencil kernels of the RRRL iteration.
+"""Tile-shape autotuner of the RRRL kernels.
 
-The stencil stages run on 64-column tiles whose height and workgroup size
-are selectable (deblur_params.tile, 1..deblur_tile_variants(); 0 = the
-library's default for the image size, which may differ between the two
-stages; it is timed as a candidate too).  Every shape sums the taps of a pixel
-in the same order, so all give bitwise-identical results; only speed differs.
-`tune` times every shape on the caller's problem with HIP events, checks the
-outputs are identical, and records the fastest in a JSON cache keyed by GPU
-architecture, ROCm version, image size class and PSF radius class.
-`best_tile` looks a key up (0 when unknown).
+Three families of kernels have selectable tile shapes, and within a family
+every shape gives bitwise-identical results (the shapes only change which
+workgroup computes a pixel, never the order of its arithmetic):
+
+* "stencil": the single-image stencil stages (deblur_params.tile,
+  1..deblur_tile_variants(); 0 = the library's per-size default);
+* "box_h" / "box_v": the single-image running-sum kernel of a horizontal or
+  vertical box (deblur_params.tile, 1..deblur_box_tile_variants());
+* "batch": the tile shapes of a batch plan, (stencil, box_h, box_v) variants
+  of deblur_batch_plan_create_tiled.
+
+Each `tune_*` times every shape of its family on the caller's problem with
+HIP events, checks that the outputs are bitwise identical (AssertionError
+otherwise), and records the fastest in a JSON cache keyed by family, GPU
+architecture, ROCm version, an image-size class and a PSF-radius class;
+`best_*` looks a key up (the library default when the key is unknown).
 
 Cache file: $DEBLUR_TUNE_CACHE, else ~/.cache/deblur_mi355x/tiles.json.
 """
@@ -46,7 +53,36 @@ def size_class(H: int, W: int) -> int:
 
 
 def key(arch: str, rocm: str, H: int, W: int, ph: int, pw: int) -> str:
+    """Key of the stencil family (the family name is implicit)."""
     return f"{arch}|{rocm}|px{size_class(H, W)}|r{radius_class(ph, pw)}"
+
+
+def length_class(L: float) -> int:
+    """Box length rounded up to a power of two, at least 8 (the halo of a box
+    tile grows with the length)."""
+    c = 8
+    while c < L:
+        c <<= 1
+    return c
+
+
+def family_key(family: str, arch: str, rocm: str, size: int, radius: int) -> str:
+    return f"{family}|{arch}|{rocm}|px{size}|r{radius}"
+
+
+def batch_class(items) -> tuple[int, int]:
+    """(total pixels, largest PSF radius or box length) classes of a batch."""
+    from . import PSF_BOX_H, PSF_BOX_V
+    px = sum(int(it[0].shape[0]) * int(it[0].shape[1]) for it in items)
+    rad = 1
+    for it in items:
+        psf = it[1]
+        if psf.kind in (PSF_BOX_H, PSF_BOX_V):
+            rad = max(rad, length_class(psf.length + psf.frac))
+        else:
+            ph, pw = psf.array_shape()
+            rad = max(rad, radius_class(ph, pw))
+    return size_class(px, 1), rad
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -125,3 +161,124 @@ def tune(f, psf, params, iters: int = 3, reps: int = 5, path: str | None = None,
         d[k] = {"tile": best, "timings_us": {str(a): round(b, 3) for a, b in timings.items()}}
         save_cache(d, path)
     return {"tile": best, "timings_us": timings, "key": k}
+
+
+def _time(fn, reps):
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) * 1e3 / reps
+
+
+def _store(family_k: str, entry: dict, path: str | None) -> None:
+    d = load_cache(path)
+    d[family_k] = entry
+    save_cache(d, path)
+
+
+def best_box_tile(H: int, W: int, length: float, axis: str, path: str | None = None) -> int:
+    arch, rocm = _device_ids()
+    k = family_key(f"box_{axis}", arch, rocm, size_class(H, W), length_class(length))
+    entry = load_cache(path).get(k)
+    return int(entry["tile"]) if entry else 0
+
+
+def tune_box(f, psf, params, iters: int = 3, reps: int = 5, path: str | None = None, store: bool = True) -> dict:
+    """Time every running-sum tile shape on (f, box psf, params), bitwise
+    check, record the fastest under the box_h / box_v family."""
+    import dataclasses
+
+    import torch
+
+    from . import PSF_BOX_H, PSF_BOX_V, _lib, deblur_rrrl_iterate
+
+    if psf.kind not in (PSF_BOX_H, PSF_BOX_V):
+        raise ValueError("tune_box needs a box PSF")
+    axis = "h" if psf.kind == PSF_BOX_H else "v"
+    lib = _lib.load()
+    H, W = f.shape
+    u0 = torch.clamp(f, min=1.0)
+    ref, timings = None, {}
+    for v in range(0, lib.deblur_box_tile_variants() + 1):
+        p = dataclasses.replace(params, iters=iters, tile=v, conv=1)   # running sums
+        out = torch.empty_like(f)
+        deblur_rrrl_iterate(f, u0, out, psf, p)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(out, ref):
+            raise AssertionError(f"box tile shape {v} changed the result")
+        timings[v] = _time(lambda: deblur_rrrl_iterate(f, u0, out, psf, p), reps) / iters
+    arch, rocm = _device_ids()
+    k = family_key(f"box_{axis}", arch, rocm, size_class(H, W), length_class(psf.length + psf.frac))
+    best = choose(timings)
+    if store:
+        _store(k, {"tile": best, "timings_us": {str(a): round(b, 3) for a, b in timings.items()}}, path)
+    return {"tile": best, "timings_us": timings, "key": k}
+
+
+def best_batch_tiles(items, path: str | None = None):
+    """Cached (stencil, box_h, box_v) variants for a batch like `items`, or
+    None (library defaults)."""
+    arch, rocm = _device_ids()
+    px, rad = batch_class(items)
+    entry = load_cache(path).get(family_key("batch", arch, rocm, px, rad))
+    return tuple(int(t) for t in entry["tiles"]) if entry else None
+
+
+def tune_batch(items, reps: int = 5, path: str | None = None, store: bool = True) -> dict:
+    """Tile shapes of a batch plan over `items`: every variant of one family
+    is tried with the other two at their defaults, each plan's outputs must
+    equal the default plan's bitwise, and each family is timed by launching
+    its classes' kernels alone (the plan's per-class launch hook)."""
+    import torch
+
+    from . import BatchPlan
+
+    def class_time(plan, classes):
+        t = 0.0
+        for c in classes:
+            for stage in ((1, 2) if c < 4 else (1,)):
+                plan.launch_class(c, stage)
+                torch.cuda.synchronize()
+                t += _time(lambda: plan.launch_class(c, stage), reps)
+        return t
+
+    ref_plan = BatchPlan(items, tiles=(0, 0, 0))
+    ref = [o.clone() for o in ref_plan.run()]
+    torch.cuda.synchronize()
+    classes = sorted({ref_plan.class_of(i) for i in range(ref_plan.n)})
+    ref_plan.close()
+    fams = {0: [c for c in classes if c < 4], 1: [c for c in classes if c == 4], 2: [c for c in classes if c == 5]}
+    nvar = {0: BatchPlan.tile_variants(BatchPlan.STENCIL), 1: BatchPlan.tile_variants(BatchPlan.BOX),
+            2: BatchPlan.tile_variants(BatchPlan.BOX)}
+    best, timings = [0, 0, 0], {}
+    for fam in (0, 1, 2):
+        if not fams[fam]:
+            continue
+        tf = {}
+        for v in range(1, nvar[fam] + 1):
+            tiles = [0, 0, 0]
+            tiles[fam] = v
+            plan = BatchPlan(items, tiles=tuple(tiles))
+            outs = plan.run()
+            torch.cuda.synchronize()
+            for i, (a, b) in enumerate(zip(outs, ref)):
+                if not torch.equal(a, b):
+                    plan.close()
+                    raise AssertionError(f"batch tiles {tiles} changed image {i}")
+            tf[v] = class_time(plan, fams[fam])
+            plan.close()
+        best[fam] = choose(tf)
+        timings[("stencil", "box_h", "box_v")[fam]] = tf
+    arch, rocm = _device_ids()
+    px, rad = batch_class(items)
+    k = family_key("batch", arch, rocm, px, rad)
+    if store:
+        _store(k, {"tiles": best, "timings_us": {f: {str(a): round(b, 3) for a, b in t.items()}
+                                                 for f, t in timings.items()}}, path)
+    return {"tiles": tuple(best), "timings_us": timings, "key": k}

@@ -52,49 +52,64 @@ struct BatchTile {
     int img, x0, y0, pad;   // x0/y0: along/across origin for box tiles
 };
 
-constexpr int BT_TH = 32, BT_NT = 512;
+// Stencil tile shapes of the batch (rows TH of a 64-column tile, NT threads),
+// variant 1..3 (0: variant 1).  Every shape sums a pixel's taps in the same
+// order: the results do not depend on the choice.
+constexpr int BATCH_STENCIL_VARIANTS = 3;
 
-template <int RAD>
-__global__ void __launch_bounds__(BT_NT) batch_stage1(const BatchTile* __restrict__ tiles,
-                                                      const BatchImg* __restrict__ imgs, int src)
+template <typename F>
+inline void with_batch_stencil_shape(int v, F&& f)
 {
-    __shared__ float tile[stage1_lds_floats<RAD, BT_TH>()];
+    using std::integral_constant;
+    switch (v) {
+        case 2: f(integral_constant<int, 16>{}, integral_constant<int, 256>{}); break;
+        case 3: f(integral_constant<int, 32>{}, integral_constant<int, 256>{}); break;
+        default: f(integral_constant<int, 32>{}, integral_constant<int, 512>{}); break;
+    }
+}
+
+template <int RAD, int TH, int NT>
+__global__ void __launch_bounds__(NT) batch_stage1(const BatchTile* __restrict__ tiles,
+                                                   const BatchImg* __restrict__ imgs, int src)
+{
+    __shared__ float tile[stage1_lds_floats<RAD, TH>()];
     __shared__ float pk[packed_words_max<RAD>()];
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
-    stage1_tile<RAD, BT_TH, BT_NT>(tile, pk, im.buf[src], im.f, im.qw, nullptr, im.H, im.W, im.pitch, t.x0, t.y0,
-                                   im.taps, im.hdr, im.p);
+    stage1_tile<RAD, TH, NT>(tile, pk, im.buf[src], im.f, im.qw, nullptr, im.H, im.W, im.pitch, t.x0, t.y0, im.taps,
+                             im.hdr, im.p);
 }
 
-template <int RAD>
-__global__ void __launch_bounds__(BT_NT) batch_stage2(const BatchTile* __restrict__ tiles,
-                                                      const BatchImg* __restrict__ imgs, int src, unsigned* cnt,
-                                                      unsigned long long* ts)
+template <int RAD, int TH, int NT>
+__global__ void __launch_bounds__(NT) batch_stage2(const BatchTile* __restrict__ tiles,
+                                                   const BatchImg* __restrict__ imgs, int src, unsigned* cnt,
+                                                   unsigned long long* ts)
 {
-    __shared__ Stage2Smem<RAD, BT_TH> sm;
+    __shared__ Stage2Smem<RAD, TH> sm;
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
-    stage2_tile<RAD, BT_TH, BT_NT>(sm, im.qw, im.buf[src], im.buf[1 - src], nullptr, im.H, im.W, im.pitch, t.x0,
-                                   t.y0, im.taps, im.hdr, im.p);
+    stage2_tile<RAD, TH, NT>(sm, im.qw, im.buf[src], im.buf[1 - src], nullptr, im.H, im.W, im.pitch, t.x0, t.y0,
+                             im.taps, im.hdr, im.p);
     count_tile(im, t.img, cnt, ts);
 }
 
-// Box tiles of the batch: one tile shape per orientation for all sizes.
-constexpr int BBH_TA = 64, BBH_TC = 8, BBV_TA = 64, BBV_TC = 8;
-
-template <bool VERT>
+// Box tiles of the batch: one tile shape per orientation (a box variant of
+// the single-image kernel) for all sizes.
+template <bool VERT, int TA, int TC>
 __global__ void __launch_bounds__(BOX_NT) batch_box(const BatchTile* __restrict__ tiles,
                                                     const BatchImg* __restrict__ imgs, int src, unsigned* cnt,
                                                     unsigned long long* ts)
 {
     extern __shared__ __align__(16) float box_lds[];
-    constexpr int TA = VERT ? BBV_TA : BBH_TA, TC = VERT ? BBV_TC : BBH_TC;
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
     const BoxGeom g = box_geom<VERT, TA, TC>(im.H, im.W, im.L, im.frac);
     box_seg_tile<VERT, TA, TC>(box_lds, im.buf[src], im.f, im.buf[1 - src], nullptr, im.pitch, g, im.p, t.x0, t.y0);
     count_tile(im, t.img, cnt, ts);
 }
+
+// The batch's default box shapes: variant 4 (64 x 8) for both orientations.
+constexpr int BATCH_BOX_DEFAULT = 4;
 
 __global__ void batch_timestamp(unsigned long long* ts, int slot)
 {
@@ -111,8 +126,18 @@ __global__ void batch_clear(unsigned* cnt, int n)
 enum { CL_R4 = 0, CL_R8, CL_R16, CL_R32, CL_BOXH, CL_BOXV, NCLASS };
 
 
+struct ClassList {
+    BatchTile* d = nullptr;   // device tile list
+    int count = 0;
+    size_t lds = 0;           // dynamic LDS bytes (box classes)
+};
+
 struct BatchPlan {
-    int n = 0, groups = 0, iters = 0;
+    int n = 0, groups = 0, iters = 0, start = 0;
+    int st_var = 1, box_var[2] = {BATCH_BOX_DEFAULT, BATCH_BOX_DEFAULT};   // tile shapes
+    std::vector<int> class_of_img;      // image -> tile class
+    std::vector<std::vector<ClassList>> lists;   // [group][class]
+    BatchImg* dimgs = nullptr;
     std::vector<int> group_of;          // image -> group
     std::vector<void*> allocs;          // device allocations owned by the plan
     unsigned long long* ts = nullptr;   // groups + 1 timestamps
@@ -159,12 +184,73 @@ void batch_plan_destroy(BatchPlan* P)
     delete P;
 }
 
-// Builds the plan; items already validated.  Returns 0, -3 (allocation) or -4.
-int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPlan** out)
+template <bool VERT>
+static void set_box_attr(int v)
+{
+    with_box_shape<VERT>(v, [](auto ta, auto tc) {
+        (void)hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&batch_box<VERT, decltype(ta)::value, decltype(tc)::value>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+}
+
+// One launch of one class over the tiles of list L: stage 1 and/or 2 of a
+// stencil class (stages & 1, & 2), the box kernel of a box class.  The
+// launches of an image's last iteration count tiles into cnt (else null).
+static void launch_class(const BatchPlan* P, const ClassList& L, int cls, int stages, int src, unsigned* cnt,
+                         hipStream_t cs)
+{
+    const BatchTile* d = L.d;
+    const dim3 grid(L.count);
+    unsigned long long* its = P->img_ts;
+    const BatchImg* dimgs = P->dimgs;
+    if (cls == CL_BOXH || cls == CL_BOXV) {
+        auto box = [&](auto vert) {
+            constexpr bool V = decltype(vert)::value;
+            with_box_shape<V>(P->box_var[V ? 1 : 0], [&](auto ta, auto tc) {
+                hipLaunchKernelGGL((batch_box<V, decltype(ta)::value, decltype(tc)::value>), grid, dim3(BOX_NT), L.lds,
+                                   cs, d, dimgs, src, cnt, its);
+            });
+        };
+        if (cls == CL_BOXV) box(std::true_type{});
+        else box(std::false_type{});
+        return;
+    }
+    with_batch_stencil_shape(P->st_var, [&](auto th, auto nt) {
+        constexpr int TH = decltype(th)::value, NT = decltype(nt)::value;
+        auto both = [&](auto rad) {
+            constexpr int R = decltype(rad)::value;
+            if (stages & 1) hipLaunchKernelGGL((batch_stage1<R, TH, NT>), grid, dim3(NT), 0, cs, d, dimgs, src);
+            if (stages & 2)
+                hipLaunchKernelGGL((batch_stage2<R, TH, NT>), grid, dim3(NT), 0, cs, d, dimgs, src, cnt, its);
+        };
+        switch (cls) {
+            case CL_R4: both(std::integral_constant<int, 4>{}); break;
+            case CL_R8: both(std::integral_constant<int, 8>{}); break;
+            case CL_R16: both(std::integral_constant<int, 16>{}); break;
+            default: both(std::integral_constant<int, 32>{}); break;
+        }
+    });
+}
+
+// Builds the plan; items already validated, tiles (3 entries or null: stencil
+// variant, horizontal and vertical box variant; 0 = default) in range.
+// Returns 0, -3 (allocation) or -4.
+int batch_plan_create(const BatchItemDev* items, int n, int group_size, const int* tiles, BatchPlan** out)
 {
     BatchPlan* P = new BatchPlan();
     P->n = n;
     P->iters = items[0].iters;
+    if (tiles) {
+        if (tiles[0] > 0) P->st_var = tiles[0];
+        if (tiles[1] > 0) P->box_var[0] = tiles[1];
+        if (tiles[2] > 0) P->box_var[1] = tiles[2];
+    }
+    int st_th = 32;
+    with_batch_stencil_shape(P->st_var, [&](auto th, auto) { st_th = decltype(th)::value; });
+    int box_ta[2], box_tc[2];
+    with_box_shape<false>(P->box_var[0], [&](auto ta, auto tc) { box_ta[0] = ta; box_tc[0] = tc; });
+    with_box_shape<true>(P->box_var[1], [&](auto ta, auto tc) { box_ta[1] = ta; box_tc[1] = tc; });
     const int gs = group_size > 0 ? group_size : n;
     P->groups = (n + gs - 1) / gs;
     P->group_of.resize(n);
@@ -175,6 +261,8 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         return -4;
     }
     const int start = P->iters % 2;  // Wiener writes buf[start]; the last iteration writes buf[0]
+    P->start = start;
+    P->class_of_img.resize(n);
     std::vector<BatchImg> imgs(n);
     size_t wiener_ws = 0;
     for (int i = 0; i < n; ++i) {
@@ -184,6 +272,7 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         b.buf[0] = it.u;
         b.buf[1] = static_cast<float*>(dalloc(P, (size_t)it.H * it.pitch * 4));
         const int cls = class_of(it.psf, it.stencil);
+        P->class_of_img[i] = cls;
         b.qw = cls < CL_BOXH ? static_cast<float2*>(dalloc(P, (size_t)it.H * it.W * 8)) : nullptr;
         void* list = dalloc(P, tap_list_bytes(it.psf));
         if (!b.buf[1] || (cls < CL_BOXH && !b.qw) || !list) {
@@ -200,10 +289,10 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         b.L = it.psf.length;
         b.frac = it.psf.frac;
         if (cls < CL_BOXH) {
-            b.ntiles = ((it.W + 63) / 64) * ((it.H + BT_TH - 1) / BT_TH);
+            b.ntiles = ((it.W + 63) / 64) * ((it.H + st_th - 1) / st_th);
         } else {
             const bool vert = cls == CL_BOXV;
-            const int TA = vert ? BBV_TA : BBH_TA, TC = vert ? BBV_TC : BBH_TC;
+            const int TA = box_ta[vert], TC = box_tc[vert];
             const int along = vert ? it.H : it.W, across = vert ? it.W : it.H;
             b.ntiles = ((along + TA - 1) / TA) * ((across + TC - 1) / TC);
         }
@@ -212,6 +301,7 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         P->group_of[i] = i / gs;
     }
     BatchImg* dimgs = static_cast<BatchImg*>(dalloc(P, sizeof(BatchImg) * n));
+    P->dimgs = dimgs;
     P->ts = static_cast<unsigned long long*>(dalloc(P, sizeof(unsigned long long) * (P->groups + 1)));
     P->img_cnt = static_cast<unsigned*>(dalloc(P, sizeof(unsigned) * n));
     P->img_ts = static_cast<unsigned long long*>(dalloc(P, sizeof(unsigned long long) * n));
@@ -221,31 +311,33 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         return -3;
     }
     // tile lists per (group, class)
-    struct ClassList {
-        BatchTile* d = nullptr;
-        int count = 0;
-        size_t lds = 0;
-    };
-    std::vector<std::vector<ClassList>> lists(P->groups, std::vector<ClassList>(NCLASS));
+    P->lists.assign(P->groups, std::vector<ClassList>(NCLASS));
+    auto& lists = P->lists;
     for (int g = 0; g < P->groups; ++g) {
         std::vector<std::vector<BatchTile>> host(NCLASS);
         for (int i = g * gs; i < std::min(n, (g + 1) * gs); ++i) {
             const BatchItemDev& it = items[i];
             const int cls = class_of(it.psf, it.stencil);
             if (cls < CL_BOXH) {
-                for (int y0 = 0; y0 < it.H; y0 += BT_TH)
+                for (int y0 = 0; y0 < it.H; y0 += st_th)
                     for (int x0 = 0; x0 < it.W; x0 += 64) host[cls].push_back({i, x0, y0, 0});
             } else {
                 const bool vert = cls == CL_BOXV;
-                const int TA = vert ? BBV_TA : BBH_TA, TC = vert ? BBV_TC : BBH_TC;
+                const int TA = box_ta[vert], TC = box_tc[vert];
                 const int along = vert ? it.H : it.W, across = vert ? it.W : it.H;
                 for (int c0 = 0; c0 < across; c0 += TC)
                     for (int a0 = 0; a0 < along; a0 += TA) host[cls].push_back({i, a0, c0, 0});
-                const size_t lds =
-                    4 * (size_t)(vert ? box_lds_words<true, BBV_TA, BBV_TC>(
-                                            box_geom<true, BBV_TA, BBV_TC>(it.H, it.W, it.psf.length, it.psf.frac))
-                                      : box_lds_words<false, BBH_TA, BBH_TC>(
-                                            box_geom<false, BBH_TA, BBH_TC>(it.H, it.W, it.psf.length, it.psf.frac)));
+                size_t lds = 0;
+                auto words = [&](auto v) {
+                    constexpr bool V = decltype(v)::value;
+                    with_box_shape<V>(P->box_var[V ? 1 : 0], [&](auto ta, auto tc) {
+                        constexpr int A = decltype(ta)::value, C = decltype(tc)::value;
+                        lds = 4 * (size_t)box_lds_words<V, A, C>(box_geom<V, A, C>(it.H, it.W, it.psf.length,
+                                                                                    it.psf.frac));
+                    });
+                };
+                if (vert) words(std::true_type{});
+                else words(std::false_type{});
                 lists[g][cls].lds = std::max(lists[g][cls].lds, lds);
             }
         }
@@ -260,10 +352,8 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
             }
         }
     }
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_box<false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_box<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    set_box_attr<false>(P->box_var[0]);
+    set_box_attr<true>(P->box_var[1]);
     // Wiener workspaces, one per capture chain
     constexpr int kChains = 4;
     std::vector<void*> wws(kChains);
@@ -321,43 +411,14 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPla
         // an independent chain over all iterations, forked once after the
         // Wiener step and joined at the end of the group
         const auto& L = lists[g];
-        auto launch_class = [&](int cls, int src, hipStream_t cs, bool last) {
-            const BatchTile* d = L[cls].d;
-            const dim3 grid(L[cls].count);
-            unsigned* cnt = last ? P->img_cnt : nullptr;   // the last iteration stamps completions
-            unsigned long long* its = P->img_ts;
-            switch (cls) {
-                case CL_R4:
-                    hipLaunchKernelGGL(batch_stage1<4>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
-                    hipLaunchKernelGGL(batch_stage2<4>, grid, dim3(BT_NT), 0, cs, d, dimgs, src, cnt, its);
-                    break;
-                case CL_R8:
-                    hipLaunchKernelGGL(batch_stage1<8>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
-                    hipLaunchKernelGGL(batch_stage2<8>, grid, dim3(BT_NT), 0, cs, d, dimgs, src, cnt, its);
-                    break;
-                case CL_R16:
-                    hipLaunchKernelGGL(batch_stage1<16>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
-                    hipLaunchKernelGGL(batch_stage2<16>, grid, dim3(BT_NT), 0, cs, d, dimgs, src, cnt, its);
-                    break;
-                case CL_R32:
-                    hipLaunchKernelGGL(batch_stage1<32>, grid, dim3(BT_NT), 0, cs, d, dimgs, src);
-                    hipLaunchKernelGGL(batch_stage2<32>, grid, dim3(BT_NT), 0, cs, d, dimgs, src, cnt, its);
-                    break;
-                case CL_BOXH:
-                    hipLaunchKernelGGL(batch_box<false>, grid, dim3(BOX_NT), L[cls].lds, cs, d, dimgs, src, cnt, its);
-                    break;
-                default:
-                    hipLaunchKernelGGL(batch_box<true>, grid, dim3(BOX_NT), L[cls].lds, cs, d, dimgs, src, cnt, its);
-                    break;
-            }
-        };
         hipEvent_t fork_it = ok ? event() : nullptr;
         ok = ok && fork_it && hipEventRecord(fork_it, s) == hipSuccess;
         for (int cls = 0; cls < NCLASS && ok; ++cls) {
             if (!L[cls].count) continue;
             hipStream_t cs = P->chains[kChains + cls];
             ok = hipStreamWaitEvent(cs, fork_it, 0) == hipSuccess;
-            for (int k = 0; k < P->iters && ok; ++k) launch_class(cls, (start + k) % 2, cs, k == P->iters - 1);
+            for (int k = 0; k < P->iters && ok; ++k)
+                launch_class(P, L[cls], cls, 3, (start + k) % 2, k == P->iters - 1 ? P->img_cnt : nullptr, cs);
             hipEvent_t join = ok ? event() : nullptr;
             ok = ok && join && hipEventRecord(join, cs) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
         }
@@ -394,5 +455,25 @@ int batch_latencies(BatchPlan* P, double* us)
 }
 
 int batch_size(const BatchPlan* P) { return P->n; }
+
+int batch_class_of(const BatchPlan* P, int img) { return P->class_of_img[img]; }
+
+int batch_class_tiles(const BatchPlan* P, int cls) { return P->lists[0][cls].count; }
+
+// One launch of one class's kernel over the first group's tiles, outside the
+// graph, on st: reads buffer 0 (the outputs), writes buffer 1 and the (q, W)
+// planes.  -2: no tiles of that class in the first group, or a stage the
+// class does not have.
+int batch_launch_class(const BatchPlan* P, int cls, int stage, hipStream_t st)
+{
+    const ClassList& L = P->lists[0][cls];
+    if (!L.count) return -2;
+    const bool box = cls == CL_BOXH || cls == CL_BOXV;
+    if ((box && stage != 1) || (!box && stage != 1 && stage != 2)) return -2;
+    launch_class(P, L, cls, box ? 1 : stage, 0, nullptr, st);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int batch_num_variants(int family) { return family == 0 ? BATCH_STENCIL_VARIANTS : BOX_VARIANTS; }
 
 }  // namespace deblur

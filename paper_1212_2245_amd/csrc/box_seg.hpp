@@ -32,6 +32,8 @@
 // so that global accesses stay coalesced along x).
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -557,6 +559,30 @@ struct BoxTileOps {
         }
     }
 };
+
+// Tile shape (TA along, TC across) of box tile variant v = 1..5: calls
+// f(TA, TC) with both as std::integral_constant.  Variants 1 and 2 swap
+// between the orientations so that variant 1 is the wide-along shape for
+// horizontal and the tall-across one for vertical motion.
+template <bool VERT, typename F>
+inline void with_box_shape(int v, F&& f)
+{
+    using std::integral_constant;
+    switch (v) {
+        case 1:
+            if constexpr (VERT) f(integral_constant<int, 128>{}, integral_constant<int, 16>{});
+            else f(integral_constant<int, 256>{}, integral_constant<int, 8>{});
+            break;
+        case 2:
+            if constexpr (VERT) f(integral_constant<int, 256>{}, integral_constant<int, 8>{});
+            else f(integral_constant<int, 128>{}, integral_constant<int, 16>{});
+            break;
+        case 3: f(integral_constant<int, 64>{}, integral_constant<int, 32>{}); break;
+        case 4: f(integral_constant<int, 64>{}, integral_constant<int, 8>{}); break;
+        default: f(integral_constant<int, 64>{}, integral_constant<int, 4>{}); break;
+    }
+}
+constexpr int BOX_VARIANTS = 5;
 
 template <bool VERT, int TA, int TC>
 DEBLUR_DEV void box_seg_tile(float* __restrict__ lds, const float* __restrict__ u, const float* __restrict__ f,

@@ -352,8 +352,27 @@ int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
 int deblur_batch_plan_create(const deblur_batch_item* items, int32_t n, int32_t group_size,
                              deblur_batch_plan** plan)
 {
+    return deblur_batch_plan_create_tiled(items, n, group_size, nullptr, plan);
+}
+
+int32_t deblur_batch_tile_variants(int32_t family)
+{
+    return family == DEBLUR_BATCH_STENCIL || family == DEBLUR_BATCH_BOX ? batch_num_variants(family) : 0;
+}
+
+int deblur_batch_plan_create_tiled(const deblur_batch_item* items, int32_t n, int32_t group_size,
+                                   const int32_t* tiles, deblur_batch_plan** plan)
+{
     if (!items || n < 1 || !plan || group_size < 0) return DEBLUR_EINVAL;
     *plan = nullptr;
+    int t3[3] = {0, 0, 0};
+    if (tiles) {
+        for (int k = 0; k < 3; ++k) {
+            const int lim = batch_num_variants(k == 0 ? DEBLUR_BATCH_STENCIL : DEBLUR_BATCH_BOX);
+            if (tiles[k] < 0 || tiles[k] > lim) return DEBLUR_EINVAL;
+            t3[k] = tiles[k];
+        }
+    }
     std::vector<BatchItemDev> dev(n);
     for (int i = 0; i < n; ++i) {
         const deblur_batch_item& it = items[i];
@@ -365,6 +384,7 @@ int deblur_batch_plan_create(const deblur_batch_item* items, int32_t n, int32_t 
         if (!(it.K > 0.0) || !std::isfinite(it.K) || !(it.pos_floor > 0.0f) || !std::isfinite(it.pos_floor))
             return DEBLUR_EINVAL;
         if (it.p.iters != items[0].p.iters) return DEBLUR_EINVAL;
+        if (it.p.conv == DEBLUR_CONV_FFT) return DEBLUR_EUNSUPPORTED;   // plans run the direct paths only
         const size_t img = (size_t)it.H * it.pitch * sizeof(float);
         if (overlaps(it.f, img, it.u, img)) return DEBLUR_EINVAL;
         BatchItemDev& b = dev[i];
@@ -381,7 +401,7 @@ int deblur_batch_plan_create(const deblur_batch_item* items, int32_t n, int32_t 
         b.stencil = it.p.conv == DEBLUR_CONV_STENCIL;
     }
     BatchPlan* impl = nullptr;
-    const int s = batch_plan_create(dev.data(), n, group_size, &impl);
+    const int s = batch_plan_create(dev.data(), n, group_size, t3, &impl);
     if (s) return s == -3 ? DEBLUR_EWORKSPACE : DEBLUR_EDEVICE;
     *plan = new deblur_batch_plan{impl};
     return DEBLUR_OK;
@@ -394,6 +414,25 @@ int deblur_batch_run(deblur_batch_plan* plan, void* stream)
 }
 
 int32_t deblur_batch_size(const deblur_batch_plan* plan) { return plan ? batch_size(plan->impl) : 0; }
+
+int32_t deblur_batch_class_of(const deblur_batch_plan* plan, int32_t image)
+{
+    if (!plan || image < 0 || image >= batch_size(plan->impl)) return DEBLUR_EINVAL;
+    return batch_class_of(plan->impl, image);
+}
+
+int32_t deblur_batch_class_tiles(const deblur_batch_plan* plan, int32_t cls)
+{
+    if (!plan || cls < 0 || cls >= DEBLUR_BATCH_NCLASS) return DEBLUR_EINVAL;
+    return batch_class_tiles(plan->impl, cls);
+}
+
+int deblur_batch_launch_class(deblur_batch_plan* plan, int32_t cls, int32_t stage, void* stream)
+{
+    if (!plan || cls < 0 || cls >= DEBLUR_BATCH_NCLASS) return DEBLUR_EINVAL;
+    const int s = batch_launch_class(plan->impl, cls, stage, reinterpret_cast<hipStream_t>(stream));
+    return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EINVAL : DEBLUR_EDEVICE);
+}
 
 int deblur_batch_latencies(deblur_batch_plan* plan, double* us_out)
 {

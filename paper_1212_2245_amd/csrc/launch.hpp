@@ -170,7 +170,11 @@ struct BatchItemDev {
     bool stencil;  // run a box PSF through the stencil classes
 };
 
-int batch_plan_create(const BatchItemDev* items, int n, int group_size, BatchPlan** out);
+int batch_plan_create(const BatchItemDev* items, int n, int group_size, const int* tiles, BatchPlan** out);
+int batch_class_of(const BatchPlan* P, int img);
+int batch_class_tiles(const BatchPlan* P, int cls);
+int batch_launch_class(const BatchPlan* P, int cls, int stage, hipStream_t st);
+int batch_num_variants(int family);
 int batch_run(BatchPlan* P, hipStream_t st);
 int batch_latencies(BatchPlan* P, double* us);
 int batch_size(const BatchPlan* P);

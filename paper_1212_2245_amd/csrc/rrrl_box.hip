@@ -38,7 +38,7 @@ static void launch_box(const float* f, const float* u, float* un, float* ckpt, i
                        p, ta);
 }
 
-int box_num_variants() { return 5; }
+int box_num_variants() { return BOX_VARIANTS; }
 
 // Default shape per orientation and size (variant 0); 1..5 explicit.  Images
 // up to 512^2 take the 64x4 tiles (one output per thread), which spread them
@@ -53,25 +53,16 @@ int box_default_variant(int H, int W, bool vert)
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
                          float frac, bool vert, const IterParams& p, hipStream_t st)
 {
-    int v = p.tile > 0 ? p.tile : box_default_variant(H, W, vert);
+    const int v = p.tile > 0 ? p.tile : box_default_variant(H, W, vert);
     if (v > box_num_variants()) return -2;
-    if (vert) {
-        switch (v) {
-            case 1: launch_box<true, 128, 16>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            case 2: launch_box<true, 256, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            case 3: launch_box<true, 64, 32>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            case 4: launch_box<true, 64, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            default: launch_box<true, 64, 4>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-        }
-    } else {
-        switch (v) {
-            case 1: launch_box<false, 256, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            case 2: launch_box<false, 128, 16>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            case 3: launch_box<false, 64, 32>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            case 4: launch_box<false, 64, 8>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-            default: launch_box<false, 64, 4>(f, u, un, ckpt, H, W, pitch, L, frac, p, st); break;
-        }
-    }
+    if (vert)
+        with_box_shape<true>(v, [&](auto ta, auto tc) {
+            launch_box<true, decltype(ta)::value, decltype(tc)::value>(f, u, un, ckpt, H, W, pitch, L, frac, p, st);
+        });
+    else
+        with_box_shape<false>(v, [&](auto ta, auto tc) {
+            launch_box<false, decltype(ta)::value, decltype(tc)::value>(f, u, un, ckpt, H, W, pitch, L, frac, p, st);
+        });
     return 0;
 }
 

@@ -200,6 +200,30 @@ def test_batch_validation(lib):
     lib.deblur_batch_plan_destroy(None)
 
 
+def test_batch_tiles_validation(lib):
+    """Tile shapes of a plan: variant counts per family; out-of-range shapes
+    and FFT-path items are rejected before any device work."""
+    E = _lib.DEBLUR_EINVAL
+    assert lib.deblur_batch_tile_variants(0) == 3
+    assert lib.deblur_batch_tile_variants(1) == lib.deblur_box_tile_variants() == 5
+    assert lib.deblur_batch_tile_variants(2) == 0
+    plan = ctypes.c_void_p()
+    arr = (_lib.deblur_batch_item * 1)(batch_item())
+    for t in ((4, 0, 0), (0, 6, 0), (0, 0, 6), (-1, 0, 0)):
+        t3 = (ctypes.c_int32 * 3)(*t)
+        assert lib.deblur_batch_plan_create_tiled(arr, 1, 0, t3, ctypes.byref(plan)) == E
+    fft = batch_item()
+    fft.p.conv = _lib.CONV_FFT
+    fft.p.boundary = _lib.BC_PERIODIC
+    arr = (_lib.deblur_batch_item * 1)(fft)
+    assert lib.deblur_batch_plan_create(arr, 1, 0, ctypes.byref(plan)) == _lib.DEBLUR_EUNSUPPORTED
+    t3 = (ctypes.c_int32 * 3)(1, 2, 3)
+    assert lib.deblur_batch_plan_create_tiled(arr, 1, 0, t3, ctypes.byref(plan)) == _lib.DEBLUR_EUNSUPPORTED
+    assert lib.deblur_batch_class_of(None, 0) == E
+    assert lib.deblur_batch_class_tiles(None, 0) == E
+    assert lib.deblur_batch_launch_class(None, 0, 1, None) == E
+
+
 def test_backward_validation(lib):
     E = _lib.DEBLUR_EINVAL
     p = params(iters=2)

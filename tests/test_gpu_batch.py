@@ -1,7 +1,8 @@
-"""Batched WR3L (one graph launch: the Wiener steps, then one persistent
-tile-queue kernel per tile class over many images of mixed sizes and PSFs):
-bitwise equal to the single-image entry points, within the parity bar of the
-FP64 oracle, with per-image completion times."""
+"""Batched WR3L (one graph launch: the Wiener steps, then per iteration one
+launch per tile class, each over a flat tile list of many images of mixed
+sizes and PSFs): bitwise equal to the single-image entry points whatever the
+tile shapes, within the parity bar of the FP64 oracle, with per-image
+completion times."""
 import numpy as np
 import pytest
 
@@ -55,6 +56,67 @@ def test_batch_equals_single_image_calls():
     lat = plan.latencies_us()
     # one completion time per image, stamped by its last tile
     assert lat.shape == (14,) and np.all(lat > 0) and len(set(lat.tolist())) > 1
+    plan.close()
+
+
+def test_batch_tile_shapes_bitwise_and_class_launches():
+    """Every tile shape of every family gives the default plan's outputs bit
+    for bit; the per-class launches (for kernel timing) run each class's
+    kernels alone and leave the outputs unchanged."""
+    cases = batch_cases(14)
+    items = [(dev(c.f), gpu_psf(c), dbl.Params(alpha=c.alpha, iters=c.iters), c.K, 1.0) for c in cases]
+    ref_plan = dbl.BatchPlan(items)
+    ref = [o.clone() for o in ref_plan.run()]
+    torch.cuda.synchronize()
+    classes = {ref_plan.class_of(i) for i in range(ref_plan.n)}
+    assert {4, 5} <= classes and any(c < 4 for c in classes)
+    for c in sorted(classes):
+        assert ref_plan.class_tiles(c) > 0
+        for stage in ((1, 2) if c < 4 else (1,)):
+            ref_plan.launch_class(c, stage)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, ref_plan.outputs):
+        assert torch.equal(a, b)
+    with pytest.raises(dbl.DeblurError):
+        ref_plan.launch_class(4, 2)            # a box class has one kernel
+    for c in range(6):
+        if c not in classes:
+            assert ref_plan.class_tiles(c) == 0
+            with pytest.raises(dbl.DeblurError):
+                ref_plan.launch_class(c, 1)
+    with pytest.raises(dbl.DeblurError):
+        ref_plan.class_of(len(items))
+    ref_plan.close()
+    for fam, nv in ((0, dbl.BatchPlan.tile_variants(0)), (1, dbl.BatchPlan.tile_variants(1)),
+                    (2, dbl.BatchPlan.tile_variants(1))):
+        for v in range(1, nv + 1):
+            t = [0, 0, 0]
+            t[fam] = v
+            print(f"[batch] tiles {t}", flush=True)
+            plan = dbl.BatchPlan(items, tiles=tuple(t))
+            outs = plan.run()
+            torch.cuda.synchronize()
+            for i, (a, b) in enumerate(zip(outs, ref)):
+                assert torch.equal(a, b), (t, i)
+            plan.close()
+
+
+def test_autotune_box_and_batch_families(tmp_path, monkeypatch):
+    """The box and batch families of the autotuner: bitwise-checked timings,
+    the choice cached and read back (a plan built with tiles='auto' takes it)."""
+    from paper_1212_2245_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tiles.json"))
+    c = synth.make_case(0)
+    res = autotune.tune_box(dev(c.f), dbl.Psf.box(c.length, "h"), dbl.Params(alpha=c.alpha), iters=2, reps=2)
+    assert 0 <= res["tile"] <= 5 and len(res["timings_us"]) == 6
+    assert autotune.best_box_tile(256, 256, c.length, "h") == res["tile"]
+    assert autotune.best_box_tile(256, 256, c.length, "v") == 0          # not tuned
+    cases = batch_cases(8)
+    items = [(dev(c.f), gpu_psf(c), dbl.Params(alpha=c.alpha, iters=c.iters), c.K, 1.0) for c in cases]
+    r = autotune.tune_batch(items, reps=2)
+    assert autotune.best_batch_tiles(items) == r["tiles"]
+    plan = dbl.BatchPlan(items, tiles="auto")
+    assert plan.tiles == r["tiles"]
     plan.close()
 
 
