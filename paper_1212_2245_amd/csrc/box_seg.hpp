@@ -20,9 +20,10 @@
 //   A. u on the tile plus a halo along (the A window of every q position B
 //      reads, and the re-basing lead-in) and 2 lines across (diffusion term);
 //      f at the q positions.
-//   B. s = A u at the TA + n - 1 (+2) positions B reads (each thread aligned
-//      blocks of BOX_SEG positions of one line); diffusivity g on the tile
-//      + 1; then W and q at those positions (one position per thread).
+//   B. s = A u at the TA + n - 1 (+2) positions B reads (sliding: each thread
+//      aligned blocks of BOX_SEG positions of one line; direct sums: one
+//      position per thread and step); diffusivity g on the tile + 1; then W
+//      and q at those positions (one position per thread and step).
 //   C. N1 = B q, N2 = B W (re-based every BOX_SEG outputs), D(u), and the
 //      update u' = u (N1 + a[D]_+) / (N2 - a[D]_-).
 // A: window [x - floor(n/2), x + floor((n-1)/2)]; B: [x - floor((n-1)/2),
@@ -271,8 +272,35 @@ struct BoxTileOps {
         float* G = Wt + (VERT ? g.nq * g.pq : TC * g.pq);
         const int qlo = a0 - g.aL - g.fr;
         const int ulo = a0 - g.hl;
-        // B1: thread t takes line t % TC and the aligned blocks of BOX_SEG q positions t / TC + k NB
-        {
+        if (!g.slide) {
+            // B1 without sliding: every window summed directly, one q position
+            // per thread and step (the positions are spread over all threads,
+            // as in the weights phase, so the tile has no long serial chain)
+            auto direct = [&](int c, int m) {
+                const int x = qlo + m;
+                const int xc = ext_index(x, g.N, p.bc);
+                const int js = (p.bc == BC_PERIODIC ? x : xc) - ulo;
+                const int cu = c + 2;
+                float sum = seq_sum(U + box_at<VERT>(cu, js - g.bL, g.pu), VERT ? g.pu : 1, g.n);
+                if (g.fr)
+                    sum = fmaf(g.ew,
+                               U[box_at<VERT>(cu, js - g.bL - 1, g.pu)] + U[box_at<VERT>(cu, js + g.aL + 1, g.pu)],
+                               sum);
+                Wt[box_at<VERT>(c, m, g.pq)] = fmaxf(sum, 0.0f) * g.invL;
+            };
+            if (VERT) {
+                constexpr int QPP = BOX_NT / TC;
+                const int c = t % TC;
+                if (c0 + c < g.M)
+                    for (int m = t / TC; m < g.nq; m += QPP) direct(c, m);
+            } else {
+                const int w = t >> 6, lane = t & 63;
+                for (int c = w; c < TC && c0 + c < g.M; c += 4)
+                    for (int m = lane; m < g.nq; m += 64) direct(c, m);
+            }
+        } else {
+            // B1 with sliding: thread t takes line t % TC and the aligned blocks
+            // of BOX_SEG q positions t / TC + k NB
             constexpr int NB = BOX_NT / TC;
             const int c = t % TC;
             const int kfirst = seg_floor(qlo), klast = seg_floor(qlo + g.nq - 1);
@@ -289,17 +317,17 @@ struct BoxTileOps {
                         // of the loop below (re-base at xb, then slide)
                         const float* ub = Ul + (xb - ulo) * su;   // u at the block's first sample
                         float* wo = Wl + (xb - qlo) * sq;
-                        const int n = g.n;
-#pragma unroll
-                        for (int i = 0; i < BOX_SEG; ++i) {
-                            if (g.slide && i > 0) {
-                                S = (S + ub[(i + g.aL) * su]) - ub[(i - g.bL - 1) * su];
-                            } else {
-                                S = seq_sum(ub + (i - g.bL) * su, su, n);
-                            }
+                        auto emit = [&](int i) {
                             float sum = S;
                             if (g.fr) sum = fmaf(g.ew, ub[(i - g.bL - 1) * su] + ub[(i + g.aL + 1) * su], sum);
                             wo[i * sq] = fmaxf(sum, 0.0f) * g.invL;
+                        };
+                        S = seq_sum(ub - g.bL * su, su, g.n);
+                        emit(0);
+#pragma unroll
+                        for (int i = 1; i < BOX_SEG; ++i) {
+                            S = (S + ub[(i + g.aL) * su]) - ub[(i - g.bL - 1) * su];
+                            emit(i);
                         }
                         continue;
                     }
@@ -310,7 +338,7 @@ struct BoxTileOps {
                         // u position of the sample: the clamped position under constant
                         // continuation, x itself (the tile holds the wrapped u) if periodic
                         const int js = (p.bc == BC_PERIODIC ? x : xc) - ulo;
-                        const int r = g.slide ? xc % BOX_SEG : 0;
+                        const int r = xc % BOX_SEG;
                         if (js == jprev) {
                             // same sample as the previous position (clamped border run)
                         } else if (js == jprev + 1 && r != 0) {
@@ -439,7 +467,9 @@ struct BoxTileOps {
 
     // Phase C for a chunk of OPT outputs x0 .. x0 + OPT - 1 whose along
     // neighbours all lie inside the image (x0 >= 1, x0 + OPT < N): the same
-    // arithmetic as the general loop below, in straight-line form.
+    // arithmetic as the general loop below, in straight-line form.  x0 is a
+    // multiple of OPT, and OPT divides BOX_SEG or is a multiple of it, so the
+    // re-basing points inside a chunk are the multiples of BOX_SEG of i.
     static DEBLUR_DEV void update_inner(int c, int o0, const float* __restrict__ U, const float* __restrict__ Q,
                                         const float* __restrict__ Wt, const float* __restrict__ G,
                                         float* __restrict__ un, float* __restrict__ ckpt, int pitch,
@@ -448,6 +478,7 @@ struct BoxTileOps {
         // explicit fmaf only: no multiply-add fused by the compiler, so that every
         // tile shape (every instantiation) rounds the same operations
 #pragma clang fp contract(off)
+        static_assert(OPT % BOX_SEG == 0 || BOX_SEG % OPT == 0, "chunks aligned to the re-basing period");
         const int sq = VERT ? g.pq : 1, su = VERT ? g.pu : 1, sg = VERT ? g.pg : 1;
         const int lu = VERT ? 1 : g.pu, lg = VERT ? 1 : g.pg;   // next line
         const float* qb = Q + (VERT ? c : c * g.pq) + (o0 + g.fr) * sq;   // B window start of output o0
@@ -455,22 +486,7 @@ struct BoxTileOps {
         const float* U2 = U + (c + 2) * lu + (g.hl + o0) * su;
         const float* G1 = G + (c + 1) * lg + (o0 + 1) * sg;
         const int n = g.n;
-        float N1 = 0.0f, N2 = 0.0f;
-#pragma unroll
-        for (int i = 0; i < OPT; ++i) {
-            if (g.slide && ((OPT % BOX_SEG == 0 && i % BOX_SEG != 0) || (OPT % BOX_SEG != 0 && i > 0 && (x0 + i) % BOX_SEG != 0))) {
-                N1 = (N1 + qb[(i + n - 1) * sq]) - qb[(i - 1) * sq];
-                N2 = (N2 + wb[(i + n - 1) * sq]) - wb[(i - 1) * sq];
-            } else {
-                // re-base at the last multiple of BOX_SEG (chunks shorter than
-                // BOX_SEG may start after it), then slide to output i
-                const int r = g.slide && OPT % BOX_SEG != 0 ? (x0 + i) % BOX_SEG : 0;
-                seq_sum2(qb + (i - r) * sq, wb + (i - r) * sq, sq, n, N1, N2);
-                for (int d = 1; d <= r; ++d) {
-                    N1 = (N1 + qb[(i - r + d + n - 1) * sq]) - qb[(i - r + d - 1) * sq];
-                    N2 = (N2 + wb[(i - r + d + n - 1) * sq]) - wb[(i - r + d - 1) * sq];
-                }
-            }
+        auto finish = [&](int i, float N1, float N2) {
             float s1 = N1, s2 = N2;
             if (g.fr) {
                 s1 = fmaf(g.ew, qb[(i - 1) * sq] + qb[(i + n) * sq], s1);
@@ -488,6 +504,37 @@ struct BoxTileOps {
             const size_t off = VERT ? (size_t)(x0 + i) * pitch + gc : (size_t)gc * pitch + x0 + i;
             if (ckpt) ckpt[off] = up;
             un[off] = up * num * rcp(den);
+        };
+        float N1, N2;
+        if (!g.slide) {
+            // every window summed directly, in a rolled loop (one copy of the code)
+#pragma unroll 1
+            for (int i = 0; i < OPT; ++i) {
+                seq_sum2(qb + i * sq, wb + i * sq, sq, n, N1, N2);
+                finish(i, N1, N2);
+            }
+            return;
+        }
+        {
+            // re-base at the last multiple of BOX_SEG (a chunk shorter than
+            // BOX_SEG may start after it), then slide to output 0
+            const int r = OPT % BOX_SEG != 0 ? x0 % BOX_SEG : 0;
+            seq_sum2(qb - r * sq, wb - r * sq, sq, n, N1, N2);
+            for (int d = 1; d <= r; ++d) {
+                N1 = (N1 + qb[(d - r + n - 1) * sq]) - qb[(d - r - 1) * sq];
+                N2 = (N2 + wb[(d - r + n - 1) * sq]) - wb[(d - r - 1) * sq];
+            }
+        }
+        finish(0, N1, N2);
+#pragma unroll
+        for (int i = 1; i < OPT; ++i) {
+            if (i % BOX_SEG == 0) {
+                seq_sum2(qb + i * sq, wb + i * sq, sq, n, N1, N2);
+            } else {
+                N1 = (N1 + qb[(i + n - 1) * sq]) - qb[(i - 1) * sq];
+                N2 = (N2 + wb[(i + n - 1) * sq]) - wb[(i - 1) * sq];
+            }
+            finish(i, N1, N2);
         }
     }
 
