@@ -111,6 +111,10 @@ typedef struct {
                         interpolation, the tangent at 65 beyond.  The first call with rf_lut = 1 on a
                         device allocates and uploads the 16 KB table (keep that call out of graph
                         capture); the backward pass rejects it (DEBLUR_EUNSUPPORTED). */
+    int32_t bwd_tile;/* tile rows of deblur_rrrl_backward's iteration kernels: 0 = default (8),
+                        1 = 8, 2 = 4, 3 = 16 rows of 64 columns (an autotuner's choice; all give
+                        bitwise-identical gradients); ignored by the forward entry points; else
+                        DEBLUR_EINVAL */
 } deblur_params;
 
 /* Text for a status code (static storage). */
@@ -124,6 +128,9 @@ int deblur_version(void);
  * running-sum kernel (boxes otherwise). */
 int deblur_tile_variants(void);
 int deblur_box_tile_variants(void);
+/* Number of explicit tile-row shapes of the backward (deblur_params.bwd_tile,
+ * 1..n; 0 = default). */
+int deblur_backward_tile_variants(void);
 
 /* Workspace bytes needed by an entry point: op 0 = deblur_wiener,
  * 1 = deblur_rrrl_iterate, 2 = deblur_rrrl_backward without the Wiener step,

@@ -81,11 +81,12 @@ class Params:
     tile: int = 0
     psi: int = PSI_TV   # regulariser: PSI_TV, or PSI_PERONA_MALIK (non-convex, lambda = eps_tv)
     rf_lut: bool = False  # r_f through the lookup table of Sec. 4.1 instead of exactly
+    bwd_tile: int = 0   # tile rows of the backward kernels: 0 default (8), 1: 8, 2: 4, 3: 16
 
     def c(self) -> _lib.deblur_params:
         return _lib.deblur_params(self.alpha, self.eps_data, self.eps_tv, self.s_min, int(self.iters),
                                   int(bool(self.robust)), int(self.boundary), int(self.conv), int(self.tile),
-                                  int(self.psi), int(bool(self.rf_lut)))
+                                  int(self.psi), int(bool(self.rf_lut)), int(self.bwd_tile))
 
 
 def _stream(t: torch.Tensor) -> int:
@@ -306,6 +307,39 @@ def deblur_rrrl_backward(f: torch.Tensor, ckpt: torch.Tensor | None, grad_uK: to
     return out
 
 
+_SIDE_STREAMS: dict = {}
+
+
+def _on_streams(n: int, fn, device, width: int = 4) -> None:
+    """fn(i) for i < n, spread round-robin over up to `width` side streams
+    forked from the current stream and joined back into it: the images of a
+    batch are independent, and their launches (a few hundred workgroups each
+    at 512^2) overlap instead of running one after another.  Tensors made
+    before the call are ordered before the fork; temporaries made inside fn
+    belong to its side stream."""
+    main = torch.cuda.current_stream(device)
+    k = min(n, width)
+    if k <= 1:
+        for i in range(n):
+            fn(i)
+        return
+    key = (str(device), k)
+    if key not in _SIDE_STREAMS:
+        _SIDE_STREAMS[key] = [torch.cuda.Stream(device=device) for _ in range(k)]   # default priority
+    side = _SIDE_STREAMS[key]
+    fork = torch.cuda.Event()
+    fork.record(main)
+    for s in side:
+        s.wait_event(fork)
+    for i in range(n):
+        with torch.cuda.stream(side[i % k]):
+            fn(i)
+    for s in side:
+        join = torch.cuda.Event()
+        join.record(s)
+        main.wait_event(join)
+
+
 class WR3LFunction(torch.autograd.Function):
     """u = WR3L(f; h, alpha) with the hand-written adjoint as backward.
 
@@ -324,7 +358,8 @@ class WR3LFunction(torch.autograd.Function):
     unrolled iteration is ill-conditioned near the border ringing of the
     periodic Wiener filter, and a correctly rounded u^0 keeps the GPU
     gradient within 1e-3 of the FP64 one.  The per-iteration checkpoints u^k
-    are stored; the backward recomputes every other quantity from them."""
+    are stored; the backward recomputes every other quantity from them.  The
+    images of a batch run concurrently on up to four side streams."""
 
     @staticmethod
     def forward(ctx, f, taps, alpha, K: float, iters: int, template: Params | None = None, pos_floor: float = 1.0):
@@ -346,13 +381,13 @@ class WR3LFunction(torch.autograd.Function):
         alphas = [float(a[i if a.numel() > 1 else 0]) for i in range(B)]
         u = torch.empty_like(fb)
         ck = torch.empty((B, max(iters, 1), H, W), dtype=torch.float32, device=f.device)
-        plist = []
-        for i in range(B):
-            p = dataclasses.replace(base, alpha=alphas[i], iters=int(iters))
+        plist = [dataclasses.replace(base, alpha=alphas[i], iters=int(iters)) for i in range(B)]
+
+        def one(i):
             psf = Psf.from_taps(tb[i])
             deblur_wiener(fb[i], u[i], psf, K, pos_floor, fp64=True)
-            deblur_rrrl_iterate(fb[i], u[i], u[i], psf, p, ckpt=ck[i] if iters > 0 else None)
-            plist.append(p)
+            deblur_rrrl_iterate(fb[i], u[i], u[i], psf, plist[i], ckpt=ck[i] if iters > 0 else None)
+        _on_streams(B, one, f.device)
         ctx.save_for_backward(fb, tb, ck)
         ctx.plist, ctx.K, ctx.pos_floor = plist, K, pos_floor
         ctx.batched, ctx.shared_taps = batched, taps.dim() == 2
@@ -365,12 +400,15 @@ class WR3LFunction(torch.autograd.Function):
         fb, tb, ck = ctx.saved_tensors
         gb = (grad_u if ctx.batched else grad_u.unsqueeze(0)).contiguous()
         gf, gt, ga = torch.empty_like(fb), torch.empty_like(tb), torch.empty(fb.shape[0], device=fb.device)
-        for i, p in enumerate(ctx.plist):
+
+        def one(i):
+            p = ctx.plist[i]
             g = deblur_rrrl_backward(fb[i], ck[i] if p.iters > 0 else None, gb[i], Psf.from_taps(tb[i]), p,
                                      through_wiener=True, K=ctx.K, pos_floor=ctx.pos_floor)
             gf[i].copy_(g["f"])
             gt[i].copy_(g["taps"])
-            ga[i] = g["alpha"]
+            ga[i].copy_(g["alpha"].reshape(()))
+        _on_streams(len(ctx.plist), one, fb.device)
         if ctx.shared_taps:
             gt = gt.sum(0)
         if ctx.alpha_shape == 1:

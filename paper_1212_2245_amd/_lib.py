@@ -34,7 +34,7 @@ class deblur_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_float), ("eps_data", ctypes.c_float), ("eps_tv", ctypes.c_float),
                 ("s_min", ctypes.c_float), ("iters", ctypes.c_int32), ("robust", ctypes.c_int32),
                 ("boundary", ctypes.c_int32), ("conv", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("psi", ctypes.c_int32), ("rf_lut", ctypes.c_int32)]
+                ("psi", ctypes.c_int32), ("rf_lut", ctypes.c_int32), ("bwd_tile", ctypes.c_int32)]
 
 
 class deblur_batch_item(ctypes.Structure):
@@ -66,6 +66,7 @@ SIGNATURES = [
     ("deblur_batch_plan_create_tiled", ctypes.c_int, [ctypes.POINTER(deblur_batch_item), _I32, _I32,
                                                       ctypes.POINTER(_I32), ctypes.POINTER(_VP)]),
     ("deblur_batch_tile_variants", _I32, [_I32]),
+    ("deblur_backward_tile_variants", ctypes.c_int, []),
     ("deblur_batch_class_of", _I32, [_VP, _I32]),
     ("deblur_batch_class_tiles", _I32, [_VP, _I32]),
     ("deblur_batch_launch_class", ctypes.c_int, [_VP, _I32, _I32, _VP]),

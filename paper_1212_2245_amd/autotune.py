@@ -9,7 +9,9 @@ workgroup computes a pixel, never the order of its arithmetic):
 * "box_h" / "box_v": the single-image running-sum kernel of a horizontal or
   vertical box (deblur_params.tile, 1..deblur_box_tile_variants());
 * "batch": the tile shapes of a batch plan, (stencil, box_h, box_v) variants
-  of deblur_batch_plan_create_tiled.
+  of deblur_batch_plan_create_tiled;
+* "backward": the tile rows of the backward's iteration kernels
+  (deblur_params.bwd_tile, 1..deblur_backward_tile_variants()).
 
 Each `tune_*` times every shape of its family on the caller's problem with
 HIP events, checks that the outputs are bitwise identical (AssertionError
@@ -282,3 +284,50 @@ def tune_batch(items, reps: int = 5, path: str | None = None, store: bool = True
         _store(k, {"tiles": best, "timings_us": {f: {str(a): round(b, 3) for a, b in t.items()}
                                                  for f, t in timings.items()}}, path)
     return {"tiles": tuple(best), "timings_us": timings, "key": k}
+
+
+def best_backward_tile(H: int, W: int, ph: int, pw: int, path: str | None = None) -> int:
+    arch, rocm = _device_ids()
+    entry = load_cache(path).get(family_key("backward", arch, rocm, size_class(H, W), radius_class(ph, pw)))
+    return int(entry["tile"]) if entry else 0
+
+
+def tune_backward(f, psf, params, reps: int = 3, path: str | None = None, store: bool = True,
+                  through_wiener: bool = True, K: float = 0.01) -> dict:
+    """Time every backward tile-row shape on a checkpointed forward of
+    (f, psf, params); every shape must give the same gradients bit for bit."""
+    import dataclasses
+
+    import torch
+
+    from . import _lib, deblur_rrrl_backward, deblur_rrrl_iterate, deblur_wiener
+
+    lib = _lib.load()
+    H, W = f.shape
+    ph, pw = psf.array_shape()
+    iters = max(int(params.iters), 1)
+    u = torch.empty_like(f)
+    ck = torch.empty((iters, H, W), dtype=torch.float32, device=f.device)
+    p0 = dataclasses.replace(params, iters=iters)
+    deblur_wiener(f, u, psf, K, 1.0, fp64=True)
+    deblur_rrrl_iterate(f, u, u, psf, p0, ckpt=ck)
+    gu = torch.clamp(u, max=1.0) - 0.5
+    ref, timings = None, {}
+    for v in range(0, lib.deblur_backward_tile_variants() + 1):
+        p = dataclasses.replace(p0, bwd_tile=v)
+
+        def run():
+            return deblur_rrrl_backward(f, ck, gu, psf, p, through_wiener=through_wiener, K=K)
+        g = run()
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = {k: t.clone() for k, t in g.items()}
+        elif any(not torch.equal(g[k], ref[k]) for k in ref):
+            raise AssertionError(f"backward tile shape {v} changed the gradients")
+        timings[v] = _time(run, reps)
+    arch, rocm = _device_ids()
+    k = family_key("backward", arch, rocm, size_class(H, W), radius_class(ph, pw))
+    best = choose(timings)
+    if store:
+        _store(k, {"tile": best, "timings_us": {str(a): round(b, 3) for a, b in timings.items()}}, path)
+    return {"tile": best, "timings_us": timings, "key": k}

@@ -125,6 +125,7 @@ int check_iterate(int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf, co
     if (p->iters < 0 || (p->robust != 0 && p->robust != 1)) return DEBLUR_EINVAL;
     if (p->psi != 0 && p->psi != 1) return DEBLUR_EINVAL;
     if (p->rf_lut != 0 && p->rf_lut != 1) return DEBLUR_EINVAL;
+    if (p->bwd_tile < 0 || p->bwd_tile > backward_tile_variants()) return DEBLUR_EINVAL;
     if (p->rf_lut && !r1_table()) return DEBLUR_EDEVICE;
     if (p->boundary != DEBLUR_BC_REPLICATE && p->boundary != DEBLUR_BC_PERIODIC) return DEBLUR_EINVAL;
     if (p->conv < DEBLUR_CONV_AUTO || p->conv > DEBLUR_CONV_FFT) return DEBLUR_EINVAL;
@@ -170,6 +171,7 @@ IterParams iter_params(const deblur_params* p)
     q.s_min = p->s_min;
     q.robust = p->robust;
     q.psi = p->psi;
+    q.bwd_tile = p->bwd_tile;
     q.r1_lut = p->rf_lut ? r1_table() : nullptr;
     q.bc = p->boundary;
     q.tile = p->tile;
@@ -240,6 +242,8 @@ int deblur_version(void) { return 100; }
 int deblur_tile_variants(void) { return taps_num_variants(); }
 
 int deblur_box_tile_variants(void) { return box_num_variants(); }
+
+int deblur_backward_tile_variants(void) { return backward_tile_variants(); }
 
 size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
                               const deblur_params* p)

@@ -15,6 +15,7 @@ struct IterParams {
     float alpha, eps_d2, eps_t2, s_min;
     int robust, bc;
     int tile;  // tile-shape variant (0 = default)
+    int bwd_tile;   // backward tile rows variant (0 = default)
     int psi;   // regulariser: 0 regularised TV, 1 Perona-Malik (lambda^2 = eps_t2)
     const float* r1_lut;   // device table of r_1 (lookup mode of r_f), or null: exact r_f
 };
@@ -126,6 +127,7 @@ int launch_rrrl_start(const float* f, float* u0, int H, int W, int pitch, int mo
 // Box tile shapes: count of explicit variants (deblur_params.tile for the
 // running-sum path) and the default for an image.
 int box_num_variants();
+int backward_tile_variants();
 int box_default_variant(int H, int W, bool vert);
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
                          float frac, bool vert, const IterParams& p, hipStream_t st);

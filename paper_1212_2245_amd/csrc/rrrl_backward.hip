@@ -46,7 +46,6 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
     __shared__ float2 qt[LH * LW];
     __shared__ float ut[UH * UW];
     __shared__ float gt[GH * GW];
-    __shared__ double red[BW_NT];
     __shared__ float pk[packed_words_max<RAD>()];
     const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
     const int x0 = tile_xy.x * TW, y0 = tile_xy.y * TH;
@@ -75,13 +74,17 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
     for (int i = 0; i < R; ++i) nn[i] = make_float2(0.0f, 0.0f);
     stencil_groups<1, R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, pk, cnt, nn);
     __syncthreads();
-    double apart = 0.0;
     const int x = x0 + tx;
+    const int ntx = (W + TW - 1) / TW;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int ry = ty * R + i;
         const int y = y0 + ry;
-        if (x >= W || y >= H) continue;
+        // dL/dalpha of this image row's 64 columns: one wave holds the row,
+        // summed by a fixed shuffle tree into the row's own slot (the same
+        // grouping whatever the tile height)
+        double apart = 0.0;
+        if (x < W && y < H) {
         const int c = (ry + 2) * UW + tx + 2;
         const int cg = (ry + 1) * GW + tx + 1;
         const float up = ut[c], gp = gt[cg];
@@ -100,15 +103,12 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
         ab[o] = make_float2(a, bb);
         cpl[o] = p.alpha * ((D > 0.0f ? a : 0.0f) - (D < 0.0f ? b : 0.0f));
         du[o] = l * rho;
-        apart += (double)a * dp - (double)b * dm;
+        apart = (double)a * dp - (double)b * dm;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) apart += __shfl_xor(apart, off, 64);
+        if (tx == 0 && y < H) alpha_part[(size_t)y * ntx + tile_xy.x] += apart;
     }
-    red[tid] = apart;
-    __syncthreads();
-    for (int off = BW_NT / 2; off > 0; off >>= 1) {
-        if (tid < off) red[tid] += red[tid + off];
-        __syncthreads();
-    }
-    if (tid == 0) alpha_part[blockIdx.y * gridDim.x + blockIdx.x] += red[0];
 }
 
 // ----------------------------------- transposed blur: stencil on a grid
@@ -454,10 +454,20 @@ __global__ void __launch_bounds__(256) adj_reduce(const double* __restrict__ par
         }
         dh[t] = s;
     }
-    if (t == 0) {
+    if (blockIdx.x == 0) {
+        // dL/dalpha: thread k sums the contiguous chunk k of the row slots in
+        // order, then a fixed tree over the 256 chunk sums
+        __shared__ double red[256];
+        const int k = threadIdx.x, chunk = (nalpha + 255) / 256;
         double s = 0.0;
-        for (int b = 0; b < nalpha; ++b) s += alpha_part[b];
-        dalpha[0] = s;
+        for (int b = k * chunk; b < min(nalpha, (k + 1) * chunk); ++b) s += alpha_part[b];
+        red[k] = s;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (k < off) red[k] += red[k + off];
+            __syncthreads();
+        }
+        if (k == 0) dalpha[0] = red[0];
     }
 }
 
@@ -540,10 +550,13 @@ struct BwdLayout {
 
 static int bwd_rad(const PsfDev& psf) { return tap_radius_class(max((psf.ph - 1) / 2, (psf.pw - 1) / 2)); }
 
-// Rows per tile of the backward iteration kernels: 8 (at 512^2, 512
-// workgroups, two per CU; taller tiles leave CUs idle or one wave per SIMD).
-constexpr int BWD_TH = 8;
-static int bwd_th(int) { return BWD_TH; }
+// Rows per tile of the backward iteration kernels, by bwd_tile variant:
+// 0/1: 8 (the default: at 512^2, 512 workgroups, two per CU), 2: 4, 3: 16.
+// The results do not depend on it (per-pixel sums in tap order; the
+// dL/dalpha partial sums are per image row).
+constexpr int BWD_VARIANTS = 3;
+static int bwd_th(const IterParams& p) { return p.bwd_tile == 2 ? 4 : (p.bwd_tile == 3 ? 16 : 8); }
+int backward_tile_variants() { return BWD_VARIANTS; }
 
 static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
 {
@@ -552,8 +565,7 @@ static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
     const size_t pl = r256((size_t)H * W * 4), pl2 = r256((size_t)H * W * 8);
     const size_t ext2 = r256((size_t)(H + 2 * cy) * (W + 2 * cx) * 8);
-    const int th = bwd_th(rad);
-    const size_t nb_it = (size_t)((W + 63) / 64) * ((H + th - 1) / th);
+    const size_t nb_it = (size_t)((W + 63) / 64) * H;      // dL/dalpha slots: per image row and 64 columns
     const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + DH_TH - 1) / DH_TH);
     size_t o = 0;
     L.list = o; o += r256(tap_list_bytes(psf));
@@ -593,12 +605,11 @@ size_t backward_ws_bytes(int H, int W, const PsfDev& psf, bool through_wiener)
     return need;
 }
 
-template <int RAD>
+template <int RAD, int TH>
 static void launch_bwd_iter(const float* f, const float* u, const float* lam, int lam_pitch, float* lam_out,
                             float* grad_f, int H, int W, int pitch, const PsfDev& psf, const IterParams& p,
                             unsigned char* w8, const BwdLayout& L, hipStream_t st)
 {
-    constexpr int TH = BWD_TH;
     const float* taps = reinterpret_cast<const float*>(w8 + L.list + tap_packed_offset(psf.ph, psf.pw));
     const int* nt = reinterpret_cast<const int*>(w8 + L.list);
     float2* qw = reinterpret_cast<float2*>(w8 + L.qw);
@@ -652,10 +663,22 @@ static void launch_bwd_iter(const float* f, const float* u, const float* lam, in
         hipLaunchKernelGGL(adj_fold_y<float>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float*)tmp, cy, H, W,
                            aT, W);
     }
-    hipLaunchKernelGGL((adj_tv<BWD_TH>), dim3((W + 63) / 64, (H + BWD_TH - 1) / BWD_TH), dim3(BW_NT), 0, st, u, pitch,
+    hipLaunchKernelGGL((adj_tv<TH>), dim3((W + 63) / 64, (H + TH - 1) / TH), dim3(BW_NT), 0, st, u, pitch,
                        (const float*)c, (const float*)du, (const float*)aT, lam_out, H, W, p);
     hipLaunchKernelGGL((adj_dh<RAD>), dim3((W + 63) / 64, (H + DH_TH - 1) / DH_TH), dim3(BW_NT), 0, st, (const float2*)ab,
                        (const float2*)qw, (const float*)ds, u, pitch, H, W, psf.ph, psf.pw, p.bc, part);
+}
+
+template <int RAD>
+static void launch_bwd_iter_th(int th, const float* f, const float* u, const float* lam, int lam_pitch,
+                               float* lam_out, float* grad_f, int H, int W, int pitch, const PsfDev& psf,
+                               const IterParams& p, unsigned char* w8, const BwdLayout& L, hipStream_t st)
+{
+    switch (th) {
+        case 4: launch_bwd_iter<RAD, 4>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+        case 16: launch_bwd_iter<RAD, 16>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+        default: launch_bwd_iter<RAD, 8>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+    }
 }
 
 int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int H, int W, int pitch,
@@ -668,8 +691,8 @@ int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
     unsigned char* w8 = reinterpret_cast<unsigned char*>(ws);
     const BwdLayout L = bwd_layout(H, W, psf);
     const int PP = psf.ph * psf.pw;
-    const int th = bwd_th(rad);
-    const size_t nb_it = (size_t)((W + 63) / 64) * ((H + th - 1) / th);
+    const int th = bwd_th(p);
+    const size_t nb_it = (size_t)((W + 63) / 64) * H;
     const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + DH_TH - 1) / DH_TH);
     double* part = reinterpret_cast<double*>(w8 + L.part);
     double* apart = reinterpret_cast<double*>(w8 + L.apart);
@@ -690,10 +713,10 @@ int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
         float* lam_out = (k % 2 == 0) ? lamA : lamB;
         const float* u = ckpt + (size_t)k * H * pitch;
         switch (rad) {
-            case 4: launch_bwd_iter<4>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
-            case 8: launch_bwd_iter<8>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
-            case 16: launch_bwd_iter<16>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
-            default: launch_bwd_iter<32>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+            case 4: launch_bwd_iter_th<4>(th, f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+            case 8: launch_bwd_iter_th<8>(th, f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+            case 16: launch_bwd_iter_th<16>(th, f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+            default: launch_bwd_iter_th<32>(th, f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
         }
         lam = lam_out;
         lam_pitch = W;

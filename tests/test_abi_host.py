@@ -56,7 +56,7 @@ def taps(ph, pw, ptr=0x60000000):
 
 def params(**kw):
     d = dict(alpha=0.003, eps_data=0.1, eps_tv=0.1, s_min=1e-12, iters=3, robust=1, boundary=0, conv=0, tile=0,
-             psi=0, rf_lut=0)
+             psi=0, rf_lut=0, bwd_tile=0)
     d.update(kw)
     return _lib.deblur_params(*[d[k] for k, _ in _lib.deblur_params._fields_])
 
@@ -198,6 +198,12 @@ def test_batch_validation(lib):
     assert lib.deblur_batch_latencies(None, None) == E
     assert lib.deblur_batch_size(None) == 0
     lib.deblur_batch_plan_destroy(None)
+
+
+def test_backward_tile_validation(lib):
+    assert lib.deblur_backward_tile_variants() == 3
+    assert iterate(lib, p=params(bwd_tile=4)) == _lib.DEBLUR_EINVAL
+    assert iterate(lib, p=params(bwd_tile=-1)) == _lib.DEBLUR_EINVAL
 
 
 def test_batch_tiles_validation(lib):

@@ -350,3 +350,38 @@ def test_gpu_finite_difference_in_parameters(which):
         adj = float(taps.grad[j])
     print(f"[grad] FD {which}: {fd:.6e}  adjoint {adj:.6e}  rel {abs(fd - adj) / abs(adj):.2e}", flush=True)
     assert abs(fd - adj) <= 2e-2 * abs(adj)
+
+
+@pytest.mark.parametrize("bc", [oracle.BC_REPLICATE, oracle.BC_PERIODIC], ids=["replicate", "periodic"])
+def test_backward_tile_rows_bitwise(bc):
+    """Every tile-row shape of the backward kernels gives the same gradients
+    bit for bit: a 36 x 72 image (partial tiles both ways; the gradient stops
+    at u^0) and a 48 x 96 one through the Wiener step with a long line PSF
+    (radius class 16)."""
+    rng = np.random.default_rng(7)
+    n = dbl._lib.load().deblur_backward_tile_variants()
+    assert n == 3
+    for H, W, h, tw in ((36, 72, synth.random_psf(rng, 5, 7), False), (48, 96, synth.line_psf(21, 0.4), True)):
+        f = rng.uniform(0.0, 255.0, (H, W))
+        g = rng.uniform(0.0, 255.0, (H, W))
+        psf = dbl.Psf.from_taps(dev(h))
+        ref = None
+        for v in range(n + 1):
+            gp = dbl.Params(alpha=0.01, iters=3, boundary=bc, bwd_tile=v)
+            got = gpu_grads(f, psf, g, 0.01, gp, tw)
+            if ref is None:
+                ref = got
+            else:
+                for k in ref:
+                    assert np.array_equal(got[k], ref[k]), (H, W, v, k)
+
+
+def test_autotune_backward_family(tmp_path, monkeypatch):
+    from paper_1212_2245_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tiles.json"))
+    c = synth.make_case(4, image=0)
+    psf = dbl.Psf.from_taps(dev(c.psf))
+    res = autotune.tune_backward(dev(c.f), psf, dbl.Params(alpha=c.alpha, iters=2), reps=1)
+    assert 0 <= res["tile"] <= 3 and len(res["timings_us"]) == 4
+    assert autotune.best_backward_tile(512, 512, 31, 31) == res["tile"]
+    print(f"[tune] {res['key']}: {res['timings_us']}", flush=True)
