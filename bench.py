@@ -167,21 +167,28 @@ def rocprof_solo_avg(kernel: str, trace_json: str):
 
 def summarize_counters(paths, out: str, command: str, frags) -> None:
     """Per-wavefront figures of the kernels matching `frags` from rocprofv3
-    --pmc CSVs (SQ_* counters, averaged over dispatches; cycle counters in
-    units of 4 cycles)."""
+    --pmc CSVs (SQ_* counters, averaged over each kernel's dispatches of its
+    largest grid; cycle counters in units of 4 cycles)."""
     vals: dict = {}
     for path in paths:
         acc: dict = {}
-        for r in _csv_rows(path):
+        rows = _csv_rows(path)
+        top: dict = {}      # per kernel, the dispatches of its largest grid
+        for r in rows:
             name = _short(r["Kernel_Name"])
-            if not any(f in name for f in frags):
+            if any(f in name for f in frags):
+                top[name] = max(top.get(name, 0), int(r["Grid_Size"]))
+        for r in rows:
+            name = _short(r["Kernel_Name"])
+            if name not in top or int(r["Grid_Size"]) != top[name]:
                 continue
             acc.setdefault((name, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
         for (name, ctr), v in acc.items():
             vals.setdefault(name, {})[ctr] = sum(v) / len(v)
     lines = [f"# rocprofv3 counters: {os.path.basename(out)}", "", "Command (one pass per counter set):", "",
              "```", command, "```", "",
-             "Per dispatch, divided by SQ_WAVES (cycle counters are in units of 4 cycles).", ""]
+             "Per dispatch (each kernel's dispatches of its largest grid), divided by SQ_WAVES (cycle counters "
+             "are in units of 4 cycles).", ""]
     for name, c in sorted(vals.items()):
         w = c.get("SQ_WAVES", 0.0) or 1.0
         lines += [f"## `{name}`", "", "| counter | per dispatch | per wavefront |", "|---|---|---|"]
@@ -194,6 +201,7 @@ def summarize_counters(paths, out: str, command: str, frags) -> None:
 
 
 TRAFFIC_JSON = os.path.join(PROFILES, "kernel_traffic.json")
+PMC_COPY_BYTES = 256 << 20      # the device copy of --pmc-calibrate
 
 
 def ingest_pmc(d: str, command: str, frags) -> None:
@@ -206,24 +214,33 @@ def ingest_pmc(d: str, command: str, frags) -> None:
         res = json.load(open(TRAFFIC_JSON))
     except (OSError, ValueError):
         res = {"kernels": {}}
-    scale, per = {}, {}
+    scale, per, calib = {}, {}, {}
     for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         paths = glob.glob(os.path.join(d, sub, "**", "*counter_collection.csv"), recursive=True)
         if not paths:
             raise SystemExit(f"no counter CSV under {os.path.join(d, sub)}")
         rows = [r for r in _csv_rows(paths[0]) if r["Counter_Name"] == ctr]
         copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        big = max(copies, key=lambda r: int(r["Grid_Size"]))
-        copy_bytes = json.load(open(os.path.join(d, "calib.json")))["copy_bytes"]
-        scale[ctr] = copy_bytes / (float(big["Counter_Value"]) * 1024.0)
+        # the calibration copy is the run's last device operation
+        last = max(copies, key=lambda r: int(r["Dispatch_Id"]))
+        scale[ctr] = PMC_COPY_BYTES / (float(last["Counter_Value"]) * 1024.0)
+        calib[ctr] = {"dispatch": int(last["Dispatch_Id"]), "KiB": float(last["Counter_Value"])}
+        # per kernel, the dispatches of its largest grid (a batch kernel also
+        # runs over the smaller tile lists of 64-image groups)
+        top: dict = {}
         for r in rows:
             name = _short(r["Kernel_Name"])
             if any(f in name for f in frags):
+                top[name] = max(top.get(name, 0), int(r["Grid_Size"]))
+        for r in rows:
+            name = _short(r["Kernel_Name"])
+            if name in top and int(r["Grid_Size"]) == top[name]:
                 per.setdefault(name, {}).setdefault(ctr, []).append(float(r["Counter_Value"]))
     for name, c in per.items():
         e = {k + "_KiB": sum(v) / len(v) for k, v in c.items()}
         e["traffic_bytes"] = (e["FETCH_SIZE_KiB"] * scale["FETCH_SIZE"] + e["WRITE_SIZE_KiB"] * scale["WRITE_SIZE"]) * 1024.0
         e["scale"] = scale
+        e["calibration"] = calib
         e["source_hash"] = kernel_source_hash(family_of(name))
         e["command"] = command
         res["kernels"][name] = e
@@ -685,7 +702,7 @@ def main():
     classes = time_classes(plan, cases, resolved, args.kernel_reps)
     plan.close()
     dom = max(classes, key=lambda e: e["time_per_batch_us"])
-    rp = rocprof_solo_avg(dom["kernel"], os.path.join(PROFILES, "batched_512_kernel_trace.json"))
+    rp = rocprof_solo_avg(dom["kernel"], os.path.join(PROFILES, "bench_default_kernel_trace.json"))
     roofline = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"], "unit": dom["unit"],
                 "frac": dom["frac"], "traffic": load_traffic(dom["kernel"]), "kernel": dom["kernel"],
                 "class": dom["class"], "avg_launch_us": dom["avg_launch_us"],
@@ -730,7 +747,7 @@ def main():
         print("[bench] FP64 oracle on a sample of the batch", file=sys.stderr, flush=True)
         out["cpu_baseline"], out["parity"] = cpu_sample(cases, outputs, args.cpu_seconds)
     if args.pmc_calibrate:
-        nbytes = 256 << 20
+        nbytes = PMC_COPY_BYTES
         a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
