@@ -90,7 +90,7 @@ def parse_args():
                     help="group size of the second plan whose per-image latencies are reported")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="host time budget of the oracle sample")
     ap.add_argument("--tile", default="auto",
-                    help="batch tile shapes: auto (tuned here), default, or S,BH,BV variants")
+                    help="batch tile shapes: auto (tuned here), default, or five variants S,BH,BV,BHL,BVL")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="also copy 256 MiB device-to-device (the scale of the HBM byte counters)")
     ap.add_argument("--ingest-pmc", metavar="DIR", help="parse rocprofv3 --pmc CSVs (DIR/fetch, DIR/write) and exit")
@@ -263,11 +263,12 @@ def load_traffic(kernel: str):
 
 
 # ------------------------------------------------------------------- batched
-CLASS_NAMES = ("stencil_r4", "stencil_r8", "stencil_r16", "stencil_r32", "box_h", "box_v")
+CLASS_NAMES = ("stencil_r4", "stencil_r8", "stencil_r16", "stencil_r32", "box_h", "box_v", "box_h_large",
+               "box_v_large")
 STENCIL_SHAPES = {1: (32, 512), 2: (16, 256), 3: (32, 256)}           # batch stencil variants (rows, threads)
 BOX_SHAPES = {False: {1: (256, 8), 2: (128, 16), 3: (64, 32), 4: (64, 8), 5: (64, 4)},   # (along, across)
               True: {1: (128, 16), 2: (256, 8), 3: (64, 32), 4: (64, 8), 5: (64, 4)}}
-BATCH_DEFAULT_TILES = (1, 4, 4)
+BATCH_DEFAULT_TILES = (1, 5, 5, 1, 1)   # stencil; box h, v up to 512^2; box h, v above
 # algorithmic operations per pixel-iteration beyond the blur taps: the
 # robust weight and quotient (~20), the diffusivity (~12) and the diffusion
 # term and update (~20) of eqs. (9)-(12), plus the two window sums of each
@@ -280,8 +281,8 @@ BYTES_PER_PX_IT = 12.0         # read u and f, write u'
 def class_kernel(cls: int, stage: int, tiles) -> str:
     """The class kernel's name as the kernel trace prints it."""
     if cls >= 4:
-        vert = cls == 5
-        ta, tc = BOX_SHAPES[vert][tiles[2] if vert else tiles[1]]
+        vert = cls in (5, 7)
+        ta, tc = BOX_SHAPES[vert][tiles[cls - 3]]
         return f"batch_box<{'true' if vert else 'false'}, {ta}, {tc}>"
     th, nt = STENCIL_SHAPES[tiles[0]]
     return f"batch_stage{stage}<{4 << cls}, {th}, {nt}>"
@@ -673,7 +674,7 @@ def main():
         tune = autotune.tune_batch(items, store=False)
         tiles = tuple(tune["tiles"])
     elif args.tile == "default":
-        tiles = (0, 0, 0)
+        tiles = (0,) * len(BATCH_DEFAULT_TILES)
     else:
         tiles = tuple(int(t) for t in args.tile.split(","))
     resolved = tuple(t if t > 0 else d for t, d in zip(tiles, BATCH_DEFAULT_TILES))

@@ -263,20 +263,23 @@ int deblur_batch_plan_create(const deblur_batch_item* items, int32_t n, int32_t 
  * per orientation.  Every shape gives bitwise-identical results. */
 #define DEBLUR_BATCH_STENCIL 0
 #define DEBLUR_BATCH_BOX 1
+#define DEBLUR_BATCH_NTILES 5
 /* Number of shapes of a family (0 for an unknown family). */
 int32_t deblur_batch_tile_variants(int32_t family);
-/* deblur_batch_plan_create with chosen tile shapes: tiles (host, 3 entries,
- * or NULL for the defaults) = {stencil variant, horizontal box variant,
- * vertical box variant}, each 0 (default: 1, 4, 4) .. the family's count,
- * else DEBLUR_EINVAL.  Items with p.conv == DEBLUR_CONV_FFT are rejected
+/* deblur_batch_plan_create with chosen tile shapes: tiles (host,
+ * DEBLUR_BATCH_NTILES entries, or NULL for the defaults) = {stencil variant,
+ * box variant of horizontal images up to 512 x 512 pixels, of vertical ones
+ * up to 512 x 512, of larger horizontal ones, of larger vertical ones}, each
+ * 0 (default: 1, 5, 5, 1, 1) .. the family's count, else DEBLUR_EINVAL.  Items with p.conv == DEBLUR_CONV_FFT are rejected
  * with DEBLUR_EUNSUPPORTED by both create calls: a plan runs the direct
  * paths (stencil, running sums) only. */
 int deblur_batch_plan_create_tiled(const deblur_batch_item* items, int32_t n, int32_t group_size,
                                    const int32_t* tiles, deblur_batch_plan** plan);
 
 /* Tile classes of a plan: 0..3 stencil radius classes 4, 8, 16, 32; 4
- * horizontal box; 5 vertical box. */
-#define DEBLUR_BATCH_NCLASS 6
+ * horizontal and 5 vertical box images up to 512 x 512 pixels; 6 horizontal
+ * and 7 vertical box images above. */
+#define DEBLUR_BATCH_NCLASS 8
 /* Class of an item (>= 0), or DEBLUR_EINVAL. */
 int32_t deblur_batch_class_of(const deblur_batch_plan* plan, int32_t image);
 /* Tiles of one launch of a class in the plan's first group (0 if none), or

@@ -438,10 +438,15 @@ class BatchPlan:
     must have the same `iters`.  group_size > 0 runs consecutive groups of
     that many images one after another.  `tiles`: None (library defaults),
     "auto" (the tuned shapes of autotune.best_batch_tiles for this batch, the
-    defaults when none are cached) or (stencil, box_h, box_v) variants."""
+    defaults when none are cached) or the five variants (stencil, box_h,
+    box_v, box_h_large, box_v_large): box images up to 512 x 512 pixels and
+    larger ones have their own tile classes."""
 
     STENCIL, BOX = 0, 1                 # tile families
-    CLASS_NAMES = ("stencil_r4", "stencil_r8", "stencil_r16", "stencil_r32", "box_h", "box_v")
+    NTILES = 5
+    TILE_NAMES = ("stencil", "box_h", "box_v", "box_h_large", "box_v_large")
+    CLASS_NAMES = ("stencil_r4", "stencil_r8", "stencil_r16", "stencil_r32", "box_h", "box_v", "box_h_large",
+                   "box_v_large")
 
     def __init__(self, items, group_size: int = 0, tiles=None):
         lib = _lib.load()
@@ -457,15 +462,15 @@ class BatchPlan:
                                             float(floor))
         if isinstance(tiles, str):
             if tiles != "auto":
-                raise ValueError("tiles: None, 'auto' or three variants")
+                raise ValueError("tiles: None, 'auto' or five variants")
             from . import autotune
             tiles = autotune.best_batch_tiles(items)
-        self.tiles = tuple(int(t) for t in tiles) if tiles is not None else (0, 0, 0)
-        if len(self.tiles) != 3:
-            raise ValueError("tiles: (stencil, box_h, box_v)")
+        self.tiles = tuple(int(t) for t in tiles) if tiles is not None else (0,) * self.NTILES
+        if len(self.tiles) != self.NTILES:
+            raise ValueError("tiles: " + ", ".join(self.TILE_NAMES))
         self._plan = ctypes.c_void_p()
-        t3 = (ctypes.c_int32 * 3)(*self.tiles)
-        st = lib.deblur_batch_plan_create_tiled(arr, len(items), int(group_size), t3, ctypes.byref(self._plan))
+        tt = (ctypes.c_int32 * self.NTILES)(*self.tiles)
+        st = lib.deblur_batch_plan_create_tiled(arr, len(items), int(group_size), tt, ctypes.byref(self._plan))
         _lib.check(st, "deblur_batch_plan_create_tiled")
         self.n = len(items)
         self.device = items[0][0].device

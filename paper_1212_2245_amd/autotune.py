@@ -8,8 +8,8 @@ workgroup computes a pixel, never the order of its arithmetic):
   1..deblur_tile_variants(); 0 = the library's per-size default);
 * "box_h" / "box_v": the single-image running-sum kernel of a horizontal or
   vertical box (deblur_params.tile, 1..deblur_box_tile_variants());
-* "batch": the tile shapes of a batch plan, (stencil, box_h, box_v) variants
-  of deblur_batch_plan_create_tiled;
+* "batch": the tile shapes of a batch plan, the (stencil, box_h, box_v,
+  box_h_large, box_v_large) variants of deblur_batch_plan_create_tiled;
 * "backward": the tile rows of the backward's iteration kernels
   (deblur_params.bwd_tile, 1..deblur_backward_tile_variants()).
 
@@ -223,20 +223,27 @@ def tune_box(f, psf, params, iters: int = 3, reps: int = 5, path: str | None = N
     return {"tile": best, "timings_us": timings, "key": k}
 
 
+BatchPlan_NTILES = 5     # tile entries of a batch plan
+
+
 def best_batch_tiles(items, path: str | None = None):
-    """Cached (stencil, box_h, box_v) variants for a batch like `items`, or
-    None (library defaults)."""
+    """Cached tile variants (BatchPlan.TILE_NAMES order) for a batch like
+    `items`, or None (library defaults)."""
     arch, rocm = _device_ids()
     px, rad = batch_class(items)
     entry = load_cache(path).get(family_key("batch", arch, rocm, px, rad))
-    return tuple(int(t) for t in entry["tiles"]) if entry else None
+    if not entry or len(entry["tiles"]) != BatchPlan_NTILES:
+        return None
+    return tuple(int(t) for t in entry["tiles"])
 
 
 def tune_batch(items, reps: int = 5, path: str | None = None, store: bool = True) -> dict:
-    """Tile shapes of a batch plan over `items`: every variant of one family
-    is tried with the other two at their defaults, each plan's outputs must
-    equal the default plan's bitwise, and each family is timed by launching
-    its classes' kernels alone (the plan's per-class launch hook)."""
+    """Tile shapes of a batch plan over `items`: every variant of one tile
+    entry (stencil, box_h, box_v, box_h_large, box_v_large) is tried with the
+    others at their defaults, each plan's outputs must equal the default
+    plan's bitwise, and each entry is timed by launching its classes' kernels
+    alone (the plan's per-class launch hook).  Entries whose classes hold no
+    image keep the default (0)."""
     import torch
 
     from . import BatchPlan
@@ -250,21 +257,23 @@ def tune_batch(items, reps: int = 5, path: str | None = None, store: bool = True
                 t += _time(lambda: plan.launch_class(c, stage), reps)
         return t
 
-    ref_plan = BatchPlan(items, tiles=(0, 0, 0))
+    n = BatchPlan.NTILES
+    ref_plan = BatchPlan(items, tiles=(0,) * n)
     ref = [o.clone() for o in ref_plan.run()]
     torch.cuda.synchronize()
     classes = sorted({ref_plan.class_of(i) for i in range(ref_plan.n)})
     ref_plan.close()
-    fams = {0: [c for c in classes if c < 4], 1: [c for c in classes if c == 4], 2: [c for c in classes if c == 5]}
-    nvar = {0: BatchPlan.tile_variants(BatchPlan.STENCIL), 1: BatchPlan.tile_variants(BatchPlan.BOX),
-            2: BatchPlan.tile_variants(BatchPlan.BOX)}
-    best, timings = [0, 0, 0], {}
-    for fam in (0, 1, 2):
+    # tile entry -> its classes: 0 the stencil classes 0..3, 1..4 the box classes 4..7
+    fams = {0: [c for c in classes if c < 4]}
+    for e in range(1, n):
+        fams[e] = [c for c in classes if c == e + 3]
+    best, timings = [0] * n, {}
+    for fam in range(n):
         if not fams[fam]:
             continue
         tf = {}
-        for v in range(1, nvar[fam] + 1):
-            tiles = [0, 0, 0]
+        for v in range(1, BatchPlan.tile_variants(BatchPlan.STENCIL if fam == 0 else BatchPlan.BOX) + 1):
+            tiles = [0] * n
             tiles[fam] = v
             plan = BatchPlan(items, tiles=tuple(tiles))
             outs = plan.run()
@@ -276,7 +285,7 @@ def tune_batch(items, reps: int = 5, path: str | None = None, store: bool = True
             tf[v] = class_time(plan, fams[fam])
             plan.close()
         best[fam] = choose(tf)
-        timings[("stencil", "box_h", "box_v")[fam]] = tf
+        timings[BatchPlan.TILE_NAMES[fam]] = tf
     arch, rocm = _device_ids()
     px, rad = batch_class(items)
     k = family_key("batch", arch, rocm, px, rad)

@@ -3,11 +3,13 @@
 //
 // A plan compiles every image's tap list, lays out per-image ping-pong and
 // (q, W) planes, and builds flat tile lists per kernel class (stencil radius
-// classes 4/8/16/32, horizontal and vertical box) spanning all images of a
-// group.  The captured graph runs, per group: the Wiener step of every image
-// (on several forked capture streams), then for each iteration one launch per
-// class and stage, whose workgroups each take one tile of one image from the
-// list; then a timestamp kernel.  Groups run one after another.  In the
+// classes 4/8/16/32; horizontal and vertical box, each split at 512 x 512
+// pixels) spanning all images of a group.  The captured graph runs, per
+// group: the Wiener step of every image (on several forked capture streams),
+// then one chain per class with, for each iteration, one launch per stage,
+// whose workgroups each take one tile of one image from the list; the class
+// chains are independent, and a timestamp kernel follows their join.  Groups
+// run one after another.  In the
 // launches of the last iteration every tile counts itself done for its image
 // (an atomic counter) and the image's last tile writes the image's
 // completion time: per-image latencies, no waiting inside any kernel.
@@ -108,8 +110,9 @@ __global__ void __launch_bounds__(BOX_NT) batch_box(const BatchTile* __restrict_
     count_tile(im, t.img, cnt, ts);
 }
 
-// The batch's default box shapes: variant 4 (64 x 8) for both orientations.
-constexpr int BATCH_BOX_DEFAULT = 4;
+// The batch's default box shapes per (orientation, size class): 64 x 4
+// tiles (variant 5) for images up to 512 x 512, variant 1 above.
+constexpr int BATCH_BOX_DEFAULT_SMALL = 5, BATCH_BOX_DEFAULT_LARGE = 1;
 
 __global__ void batch_timestamp(unsigned long long* ts, int slot)
 {
@@ -123,7 +126,11 @@ __global__ void batch_clear(unsigned* cnt, int n)
 }
 
 // ---------------------------------------------------------------- host side
-enum { CL_R4 = 0, CL_R8, CL_R16, CL_R32, CL_BOXH, CL_BOXV, NCLASS };
+// Tile classes: stencil radius classes, then box classes by orientation and
+// image size (up to 512 x 512 / above: different tile shapes suit them).
+enum { CL_R4 = 0, CL_R8, CL_R16, CL_R32, CL_BOXH, CL_BOXV, CL_BOXH_L, CL_BOXV_L, NCLASS };
+constexpr bool is_box(int cls) { return cls >= CL_BOXH; }
+constexpr bool box_vert(int cls) { return cls == CL_BOXV || cls == CL_BOXV_L; }
 
 
 struct ClassList {
@@ -134,7 +141,9 @@ struct ClassList {
 
 struct BatchPlan {
     int n = 0, groups = 0, iters = 0, start = 0;
-    int st_var = 1, box_var[2] = {BATCH_BOX_DEFAULT, BATCH_BOX_DEFAULT};   // tile shapes
+    int st_var = 1;     // tile shapes: stencil; box per class (CL_BOXH + b)
+    int box_var[4] = {BATCH_BOX_DEFAULT_SMALL, BATCH_BOX_DEFAULT_SMALL, BATCH_BOX_DEFAULT_LARGE,
+                      BATCH_BOX_DEFAULT_LARGE};
     std::vector<int> class_of_img;      // image -> tile class
     std::vector<std::vector<ClassList>> lists;   // [group][class]
     BatchImg* dimgs = nullptr;
@@ -151,10 +160,11 @@ struct BatchPlan {
     int clock_khz = 0;
 };
 
-static int class_of(const PsfDev& d, bool stencil)
+static int class_of(const PsfDev& d, bool stencil, int H, int W)
 {
-    if (!stencil && d.kind == PSF_BOX_H) return CL_BOXH;
-    if (!stencil && d.kind == PSF_BOX_V) return CL_BOXV;
+    const bool large = (long)H * W > 512L * 512L;
+    if (!stencil && d.kind == PSF_BOX_H) return large ? CL_BOXH_L : CL_BOXH;
+    if (!stencil && d.kind == PSF_BOX_V) return large ? CL_BOXV_L : CL_BOXV;
     switch (tap_radius_class(max((d.ph - 1) / 2, (d.pw - 1) / 2))) {
         case 4: return CL_R4;
         case 8: return CL_R8;
@@ -204,15 +214,15 @@ static void launch_class(const BatchPlan* P, const ClassList& L, int cls, int st
     const dim3 grid(L.count);
     unsigned long long* its = P->img_ts;
     const BatchImg* dimgs = P->dimgs;
-    if (cls == CL_BOXH || cls == CL_BOXV) {
+    if (is_box(cls)) {
         auto box = [&](auto vert) {
             constexpr bool V = decltype(vert)::value;
-            with_box_shape<V>(P->box_var[V ? 1 : 0], [&](auto ta, auto tc) {
+            with_box_shape<V>(P->box_var[cls - CL_BOXH], [&](auto ta, auto tc) {
                 hipLaunchKernelGGL((batch_box<V, decltype(ta)::value, decltype(tc)::value>), grid, dim3(BOX_NT), L.lds,
                                    cs, d, dimgs, src, cnt, its);
             });
         };
-        if (cls == CL_BOXV) box(std::true_type{});
+        if (box_vert(cls)) box(std::true_type{});
         else box(std::false_type{});
         return;
     }
@@ -233,8 +243,9 @@ static void launch_class(const BatchPlan* P, const ClassList& L, int cls, int st
     });
 }
 
-// Builds the plan; items already validated, tiles (3 entries or null: stencil
-// variant, horizontal and vertical box variant; 0 = default) in range.
+// Builds the plan; items already validated, tiles (5 entries or null: stencil
+// variant; box variants of horizontal and vertical images up to 512^2, then
+// of larger ones; 0 = default) in range.
 // Returns 0, -3 (allocation) or -4.
 int batch_plan_create(const BatchItemDev* items, int n, int group_size, const int* tiles, BatchPlan** out)
 {
@@ -243,14 +254,21 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
     P->iters = items[0].iters;
     if (tiles) {
         if (tiles[0] > 0) P->st_var = tiles[0];
-        if (tiles[1] > 0) P->box_var[0] = tiles[1];
-        if (tiles[2] > 0) P->box_var[1] = tiles[2];
+        for (int b = 0; b < 4; ++b)
+            if (tiles[1 + b] > 0) P->box_var[b] = tiles[1 + b];
     }
     int st_th = 32;
     with_batch_stencil_shape(P->st_var, [&](auto th, auto) { st_th = decltype(th)::value; });
-    int box_ta[2], box_tc[2];
-    with_box_shape<false>(P->box_var[0], [&](auto ta, auto tc) { box_ta[0] = ta; box_tc[0] = tc; });
-    with_box_shape<true>(P->box_var[1], [&](auto ta, auto tc) { box_ta[1] = ta; box_tc[1] = tc; });
+    int box_ta[4], box_tc[4];   // per box class CL_BOXH + b
+    for (int b = 0; b < 4; ++b) {
+        auto get = [&](int& ta_out, int& tc_out) {
+            if (box_vert(CL_BOXH + b))
+                with_box_shape<true>(P->box_var[b], [&](auto ta, auto tc) { ta_out = ta; tc_out = tc; });
+            else
+                with_box_shape<false>(P->box_var[b], [&](auto ta, auto tc) { ta_out = ta; tc_out = tc; });
+        };
+        get(box_ta[b], box_tc[b]);
+    }
     const int gs = group_size > 0 ? group_size : n;
     P->groups = (n + gs - 1) / gs;
     P->group_of.resize(n);
@@ -271,7 +289,7 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
         b.f = it.f;
         b.buf[0] = it.u;
         b.buf[1] = static_cast<float*>(dalloc(P, (size_t)it.H * it.pitch * 4));
-        const int cls = class_of(it.psf, it.stencil);
+        const int cls = class_of(it.psf, it.stencil, it.H, it.W);
         P->class_of_img[i] = cls;
         b.qw = cls < CL_BOXH ? static_cast<float2*>(dalloc(P, (size_t)it.H * it.W * 8)) : nullptr;
         void* list = dalloc(P, tap_list_bytes(it.psf));
@@ -291,8 +309,8 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
         if (cls < CL_BOXH) {
             b.ntiles = ((it.W + 63) / 64) * ((it.H + st_th - 1) / st_th);
         } else {
-            const bool vert = cls == CL_BOXV;
-            const int TA = box_ta[vert], TC = box_tc[vert];
+            const bool vert = box_vert(cls);
+            const int TA = box_ta[cls - CL_BOXH], TC = box_tc[cls - CL_BOXH];
             const int along = vert ? it.H : it.W, across = vert ? it.W : it.H;
             b.ntiles = ((along + TA - 1) / TA) * ((across + TC - 1) / TC);
         }
@@ -317,20 +335,20 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
         std::vector<std::vector<BatchTile>> host(NCLASS);
         for (int i = g * gs; i < std::min(n, (g + 1) * gs); ++i) {
             const BatchItemDev& it = items[i];
-            const int cls = class_of(it.psf, it.stencil);
+            const int cls = P->class_of_img[i];
             if (cls < CL_BOXH) {
                 for (int y0 = 0; y0 < it.H; y0 += st_th)
                     for (int x0 = 0; x0 < it.W; x0 += 64) host[cls].push_back({i, x0, y0, 0});
             } else {
-                const bool vert = cls == CL_BOXV;
-                const int TA = box_ta[vert], TC = box_tc[vert];
+                const bool vert = box_vert(cls);
+                const int TA = box_ta[cls - CL_BOXH], TC = box_tc[cls - CL_BOXH];
                 const int along = vert ? it.H : it.W, across = vert ? it.W : it.H;
                 for (int c0 = 0; c0 < across; c0 += TC)
                     for (int a0 = 0; a0 < along; a0 += TA) host[cls].push_back({i, a0, c0, 0});
                 size_t lds = 0;
                 auto words = [&](auto v) {
                     constexpr bool V = decltype(v)::value;
-                    with_box_shape<V>(P->box_var[V ? 1 : 0], [&](auto ta, auto tc) {
+                    with_box_shape<V>(P->box_var[cls - CL_BOXH], [&](auto ta, auto tc) {
                         constexpr int A = decltype(ta)::value, C = decltype(tc)::value;
                         lds = 4 * (size_t)box_lds_words<V, A, C>(box_geom<V, A, C>(it.H, it.W, it.psf.length,
                                                                                     it.psf.frac));
@@ -352,8 +370,10 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
             }
         }
     }
-    set_box_attr<false>(P->box_var[0]);
-    set_box_attr<true>(P->box_var[1]);
+    for (int b = 0; b < 4; ++b) {
+        if (box_vert(CL_BOXH + b)) set_box_attr<true>(P->box_var[b]);
+        else set_box_attr<false>(P->box_var[b]);
+    }
     // Wiener workspaces, one per capture chain
     constexpr int kChains = 4;
     std::vector<void*> wws(kChains);
@@ -468,7 +488,7 @@ int batch_launch_class(const BatchPlan* P, int cls, int stage, hipStream_t st)
 {
     const ClassList& L = P->lists[0][cls];
     if (!L.count) return -2;
-    const bool box = cls == CL_BOXH || cls == CL_BOXV;
+    const bool box = is_box(cls);
     if ((box && stage != 1) || (!box && stage != 1 && stage != 2)) return -2;
     launch_class(P, L, cls, box ? 1 : stage, 0, nullptr, st);
     return hipGetLastError() == hipSuccess ? 0 : -4;

@@ -369,12 +369,12 @@ int deblur_batch_plan_create_tiled(const deblur_batch_item* items, int32_t n, in
 {
     if (!items || n < 1 || !plan || group_size < 0) return DEBLUR_EINVAL;
     *plan = nullptr;
-    int t3[3] = {0, 0, 0};
+    int t5[DEBLUR_BATCH_NTILES] = {0, 0, 0, 0, 0};
     if (tiles) {
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < DEBLUR_BATCH_NTILES; ++k) {
             const int lim = batch_num_variants(k == 0 ? DEBLUR_BATCH_STENCIL : DEBLUR_BATCH_BOX);
             if (tiles[k] < 0 || tiles[k] > lim) return DEBLUR_EINVAL;
-            t3[k] = tiles[k];
+            t5[k] = tiles[k];
         }
     }
     std::vector<BatchItemDev> dev(n);
@@ -405,7 +405,7 @@ int deblur_batch_plan_create_tiled(const deblur_batch_item* items, int32_t n, in
         b.stencil = it.p.conv == DEBLUR_CONV_STENCIL;
     }
     BatchPlan* impl = nullptr;
-    const int s = batch_plan_create(dev.data(), n, group_size, t3, &impl);
+    const int s = batch_plan_create(dev.data(), n, group_size, t5, &impl);
     if (s) return s == -3 ? DEBLUR_EWORKSPACE : DEBLUR_EDEVICE;
     *plan = new deblur_batch_plan{impl};
     return DEBLUR_OK;

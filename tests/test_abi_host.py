@@ -215,16 +215,16 @@ def test_batch_tiles_validation(lib):
     assert lib.deblur_batch_tile_variants(2) == 0
     plan = ctypes.c_void_p()
     arr = (_lib.deblur_batch_item * 1)(batch_item())
-    for t in ((4, 0, 0), (0, 6, 0), (0, 0, 6), (-1, 0, 0)):
-        t3 = (ctypes.c_int32 * 3)(*t)
-        assert lib.deblur_batch_plan_create_tiled(arr, 1, 0, t3, ctypes.byref(plan)) == E
+    for t in ((4, 0, 0, 0, 0), (0, 6, 0, 0, 0), (0, 0, 6, 0, 0), (0, 0, 0, 6, 0), (0, 0, 0, 0, 6), (-1, 0, 0, 0, 0)):
+        t5 = (ctypes.c_int32 * 5)(*t)
+        assert lib.deblur_batch_plan_create_tiled(arr, 1, 0, t5, ctypes.byref(plan)) == E
     fft = batch_item()
     fft.p.conv = _lib.CONV_FFT
     fft.p.boundary = _lib.BC_PERIODIC
     arr = (_lib.deblur_batch_item * 1)(fft)
     assert lib.deblur_batch_plan_create(arr, 1, 0, ctypes.byref(plan)) == _lib.DEBLUR_EUNSUPPORTED
-    t3 = (ctypes.c_int32 * 3)(1, 2, 3)
-    assert lib.deblur_batch_plan_create_tiled(arr, 1, 0, t3, ctypes.byref(plan)) == _lib.DEBLUR_EUNSUPPORTED
+    t5 = (ctypes.c_int32 * 5)(1, 2, 3, 4, 5)
+    assert lib.deblur_batch_plan_create_tiled(arr, 1, 0, t5, ctypes.byref(plan)) == _lib.DEBLUR_EUNSUPPORTED
     assert lib.deblur_batch_class_of(None, 0) == E
     assert lib.deblur_batch_class_tiles(None, 0) == E
     assert lib.deblur_batch_launch_class(None, 0, 1, None) == E

@@ -63,13 +63,13 @@ def test_batch_tile_shapes_bitwise_and_class_launches():
     """Every tile shape of every family gives the default plan's outputs bit
     for bit; the per-class launches (for kernel timing) run each class's
     kernels alone and leave the outputs unchanged."""
-    cases = batch_cases(14)
+    cases = batch_cases(14) + batch_cases(4, sizes=(768,))     # box images up to 512^2 and above
     items = [(dev(c.f), gpu_psf(c), dbl.Params(alpha=c.alpha, iters=c.iters), c.K, 1.0) for c in cases]
     ref_plan = dbl.BatchPlan(items)
     ref = [o.clone() for o in ref_plan.run()]
     torch.cuda.synchronize()
     classes = {ref_plan.class_of(i) for i in range(ref_plan.n)}
-    assert {4, 5} <= classes and any(c < 4 for c in classes)
+    assert {4, 5, 6, 7} <= classes and any(c < 4 for c in classes)
     for c in sorted(classes):
         assert ref_plan.class_tiles(c) > 0
         for stage in ((1, 2) if c < 4 else (1,)):
@@ -79,7 +79,7 @@ def test_batch_tile_shapes_bitwise_and_class_launches():
         assert torch.equal(a, b)
     with pytest.raises(dbl.DeblurError):
         ref_plan.launch_class(4, 2)            # a box class has one kernel
-    for c in range(6):
+    for c in range(8):
         if c not in classes:
             assert ref_plan.class_tiles(c) == 0
             with pytest.raises(dbl.DeblurError):
@@ -87,10 +87,10 @@ def test_batch_tile_shapes_bitwise_and_class_launches():
     with pytest.raises(dbl.DeblurError):
         ref_plan.class_of(len(items))
     ref_plan.close()
-    for fam, nv in ((0, dbl.BatchPlan.tile_variants(0)), (1, dbl.BatchPlan.tile_variants(1)),
-                    (2, dbl.BatchPlan.tile_variants(1))):
+    for fam in range(dbl.BatchPlan.NTILES):
+        nv = dbl.BatchPlan.tile_variants(dbl.BatchPlan.STENCIL if fam == 0 else dbl.BatchPlan.BOX)
         for v in range(1, nv + 1):
-            t = [0, 0, 0]
+            t = [0] * dbl.BatchPlan.NTILES
             t[fam] = v
             print(f"[batch] tiles {t}", flush=True)
             plan = dbl.BatchPlan(items, tiles=tuple(t))
