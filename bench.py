@@ -281,9 +281,9 @@ BYTES_PER_PX_IT = 12.0         # read u and f, write u'
 def class_kernel(cls: int, stage: int, tiles) -> str:
     """The class kernel's name as the kernel trace prints it."""
     if cls >= 4:
-        vert = cls in (5, 7)
+        vert, large = cls in (5, 7), cls >= 6
         ta, tc = BOX_SHAPES[vert][tiles[cls - 3]]
-        return f"batch_box<{'true' if vert else 'false'}, {ta}, {tc}>"
+        return f"batch_box<{'true' if vert else 'false'}, {ta}, {tc}, {'true' if large else 'false'}>"
     th, nt = STENCIL_SHAPES[tiles[0]]
     return f"batch_stage{stage}<{4 << cls}, {th}, {nt}>"
 

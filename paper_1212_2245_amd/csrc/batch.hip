@@ -95,9 +95,12 @@ __global__ void __launch_bounds__(NT) batch_stage2(const BatchTile* __restrict__
     count_tile(im, t.img, cnt, ts);
 }
 
-// Box tiles of the batch: one tile shape per orientation (a box variant of
-// the single-image kernel) for all sizes.
-template <bool VERT, int TA, int TC>
+// Box tiles of the batch: one tile shape per class (a box variant of the
+// single-image kernel).  LARGE (the class of images above 512 x 512 pixels)
+// does not change the code; it gives the two size classes' launches their
+// own kernel names even when they take the same tile shape, so that a
+// profile attributes each launch to its class.
+template <bool VERT, int TA, int TC, bool LARGE>
 __global__ void __launch_bounds__(BOX_NT) batch_box(const BatchTile* __restrict__ tiles,
                                                     const BatchImg* __restrict__ imgs, int src, unsigned* cnt,
                                                     unsigned long long* ts)
@@ -194,12 +197,12 @@ void batch_plan_destroy(BatchPlan* P)
     delete P;
 }
 
-template <bool VERT>
+template <bool VERT, bool LARGE>
 static void set_box_attr(int v)
 {
     with_box_shape<VERT>(v, [](auto ta, auto tc) {
         (void)hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&batch_box<VERT, decltype(ta)::value, decltype(tc)::value>),
+            reinterpret_cast<const void*>(&batch_box<VERT, decltype(ta)::value, decltype(tc)::value, LARGE>),
             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     });
 }
@@ -215,15 +218,19 @@ static void launch_class(const BatchPlan* P, const ClassList& L, int cls, int st
     unsigned long long* its = P->img_ts;
     const BatchImg* dimgs = P->dimgs;
     if (is_box(cls)) {
-        auto box = [&](auto vert) {
-            constexpr bool V = decltype(vert)::value;
+        auto box = [&](auto vert, auto large) {
+            constexpr bool V = decltype(vert)::value, BIG = decltype(large)::value;
             with_box_shape<V>(P->box_var[cls - CL_BOXH], [&](auto ta, auto tc) {
-                hipLaunchKernelGGL((batch_box<V, decltype(ta)::value, decltype(tc)::value>), grid, dim3(BOX_NT), L.lds,
-                                   cs, d, dimgs, src, cnt, its);
+                hipLaunchKernelGGL((batch_box<V, decltype(ta)::value, decltype(tc)::value, BIG>), grid, dim3(BOX_NT),
+                                   L.lds, cs, d, dimgs, src, cnt, its);
             });
         };
-        if (box_vert(cls)) box(std::true_type{});
-        else box(std::false_type{});
+        switch (cls) {
+            case CL_BOXH: box(std::false_type{}, std::false_type{}); break;
+            case CL_BOXV: box(std::true_type{}, std::false_type{}); break;
+            case CL_BOXH_L: box(std::false_type{}, std::true_type{}); break;
+            default: box(std::true_type{}, std::true_type{}); break;
+        }
         return;
     }
     with_batch_stencil_shape(P->st_var, [&](auto th, auto nt) {
@@ -370,10 +377,10 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
             }
         }
     }
-    for (int b = 0; b < 4; ++b) {
-        if (box_vert(CL_BOXH + b)) set_box_attr<true>(P->box_var[b]);
-        else set_box_attr<false>(P->box_var[b]);
-    }
+    set_box_attr<false, false>(P->box_var[CL_BOXH - CL_BOXH]);
+    set_box_attr<true, false>(P->box_var[CL_BOXV - CL_BOXH]);
+    set_box_attr<false, true>(P->box_var[CL_BOXH_L - CL_BOXH]);
+    set_box_attr<true, true>(P->box_var[CL_BOXV_L - CL_BOXH]);
     // Wiener workspaces, one per capture chain
     constexpr int kChains = 4;
     std::vector<void*> wws(kChains);
