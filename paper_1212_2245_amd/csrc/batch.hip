@@ -289,7 +289,6 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
     P->start = start;
     P->class_of_img.resize(n);
     std::vector<BatchImg> imgs(n);
-    size_t wiener_ws = 0;
     for (int i = 0; i < n; ++i) {
         const BatchItemDev& it = items[i];
         BatchImg& b = imgs[i];
@@ -322,7 +321,6 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
             b.ntiles = ((along + TA - 1) / TA) * ((across + TC - 1) / TC);
         }
         b.p = it.p;
-        wiener_ws = std::max(wiener_ws, wiener_ws_bytes(it.H, it.W, it.psf.ph == 1));
         P->group_of[i] = i / gs;
     }
     BatchImg* dimgs = static_cast<BatchImg*>(dalloc(P, sizeof(BatchImg) * n));
@@ -381,14 +379,52 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
     set_box_attr<true, false>(P->box_var[CL_BOXV - CL_BOXH]);
     set_box_attr<false, true>(P->box_var[CL_BOXH_L - CL_BOXH]);
     set_box_attr<true, true>(P->box_var[CL_BOXV_L - CL_BOXH]);
-    // Wiener workspaces, one per capture chain
+    // Wiener steps: per group, the images of one size and one path (one-row
+    // PSF or general) form one job list, run by one batched launch per
+    // kernel; every image has its own workspace.
     constexpr int kChains = 4;
-    std::vector<void*> wws(kChains);
-    for (int c = 0; c < kChains; ++c) {
-        wws[c] = dalloc(P, wiener_ws);
-        if (!wws[c]) {
-            batch_plan_destroy(P);
-            return -3;
+    struct JobSet {
+        WienerJob* d = nullptr;
+        int count = 0, H = 0, W = 0;
+        bool rowwise = false;
+    };
+    std::vector<std::vector<JobSet>> jobsets(P->groups);
+    for (int g = 0; g < P->groups; ++g) {
+        std::vector<std::pair<long, std::vector<WienerJob>>> sets;   // key: (H, W, rowwise)
+        for (int i = g * gs; i < std::min(n, (g + 1) * gs); ++i) {
+            const BatchItemDev& it = items[i];
+            const bool rowwise = it.psf.ph == 1;
+            const long key = ((long)it.H << 33) | ((long)it.W << 1) | (rowwise ? 1 : 0);
+            void* w = dalloc(P, wiener_ws_bytes(it.H, it.W, rowwise));
+            if (!w) {
+                batch_plan_destroy(P);
+                return -3;
+            }
+            WienerJob j;
+            j.f = it.f;
+            j.u = imgs[i].buf[start];
+            j.pitch = it.pitch;
+            j.pos_floor = it.pos_floor;
+            j.K = it.K;
+            j.psf = it.psf;
+            j.ws = w;
+            auto e = std::find_if(sets.begin(), sets.end(), [&](const auto& x) { return x.first == key; });
+            if (e == sets.end()) sets.push_back({key, {j}});
+            else e->second.push_back(j);
+        }
+        for (auto& kv : sets) {
+            JobSet js;
+            js.count = (int)kv.second.size();
+            js.H = (int)(kv.first >> 33);
+            js.W = (int)((kv.first >> 1) & 0xffffffffL);
+            js.rowwise = kv.first & 1;
+            js.d = static_cast<WienerJob*>(dalloc(P, sizeof(WienerJob) * kv.second.size()));
+            if (!js.d || hipMemcpy(js.d, kv.second.data(), sizeof(WienerJob) * kv.second.size(),
+                                   hipMemcpyHostToDevice) != hipSuccess) {
+                batch_plan_destroy(P);
+                return -3;
+            }
+            jobsets[g].push_back(js);
         }
     }
     prepare_wiener_kernels();   // runtime attribute calls stay out of the capture
@@ -423,11 +459,18 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
         hipEvent_t fork = event();
         ok = fork && hipEventRecord(fork, s) == hipSuccess;
         for (int c = 0; c < kChains && ok; ++c) ok = hipStreamWaitEvent(P->chains[c], fork, 0) == hipSuccess;
-        for (int i = g * gs, k = 0; ok && i < std::min(n, (g + 1) * gs); ++i, ++k) {
-            const BatchItemDev& it = items[i];
-            const int c = k % kChains;
-            ok = launch_wiener(it.f, imgs[i].buf[start], it.H, it.W, it.pitch, it.psf, it.K, it.pos_floor, wws[c],
-                               it.psf.ph == 1, false, P->chains[c]) == 0;
+        // the job sets spread over the chains, largest first onto the least loaded
+        std::vector<const JobSet*> order;
+        for (const JobSet& js : jobsets[g]) order.push_back(&js);
+        std::sort(order.begin(), order.end(), [](const JobSet* a, const JobSet* b) {
+            return (long)a->H * a->W * a->count > (long)b->H * b->W * b->count;
+        });
+        long load[kChains] = {0, 0, 0, 0};
+        for (size_t k = 0; ok && k < order.size(); ++k) {
+            const JobSet& js = *order[k];
+            const int c = (int)(std::min_element(load, load + kChains) - load);
+            load[c] += (long)js.H * js.W * js.count;
+            ok = launch_wiener_batch(js.d, js.count, js.H, js.W, js.rowwise, P->chains[c]) == 0;
         }
         for (int c = 0; c < kChains && ok; ++c) {
             hipEvent_t join = event();

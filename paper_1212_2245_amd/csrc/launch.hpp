@@ -92,6 +92,18 @@ size_t wiener_ws_bytes(int H, int W, bool rowwise, bool fp64 = false);
 // Raises the LDS limit of the Wiener kernels (once per process; a plan calls
 // it before capturing a graph).
 void prepare_wiener_kernels();
+// One image's Wiener step in a batched launch: input, output (H x pitch),
+// PSF, K, positivity floor and its own workspace (wiener_ws_bytes, FP32).
+struct WienerJob {
+    const float* f;
+    float* u;
+    int pitch;
+    float pos_floor;
+    double K;
+    PsfDev psf;
+    void* ws;
+};
+int launch_wiener_batch(const WienerJob* jobs, int n, int H, int W, bool rowwise, hipStream_t st);
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
                   float pos_floor, void* ws, bool rowwise, bool fp64, hipStream_t st);
 

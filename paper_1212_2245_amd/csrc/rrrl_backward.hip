@@ -561,7 +561,6 @@ int backward_tile_variants() { return BWD_VARIANTS; }
 static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
 {
     BwdLayout L{};
-    const int rad = bwd_rad(psf);
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
     const size_t pl = r256((size_t)H * W * 4), pl2 = r256((size_t)H * W * 8);
     const size_t ext2 = r256((size_t)(H + 2 * cy) * (W + 2 * cx) * 8);

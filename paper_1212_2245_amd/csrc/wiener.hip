@@ -64,14 +64,14 @@ DEBLUR_DEV double2 psf_row_dft(const float* hrow, int pw, double2 w, double2 t)
     return make_double2(re, im);
 }
 
-// M(k) = conj(h^(k)) / (|h^(k)|^2 + K) for a PSF on one row, k < n.
+// M(k) = conj(h^(k)) / (|h^(k)|^2 + K) for a PSF on one row, k < n; one
+// workgroup of 256 frequencies (block blk).
 template <typename C>
-__global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double K, C* __restrict__ M)
+DEBLUR_DEV void mult_1d_block(const PsfDev& psf, int n, double K, C* __restrict__ M, int blk, float* hs)
 {
-    __shared__ float hs[MULT_MAXP];
     psf_to_lds(psf, hs);
     __syncthreads();
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blk * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const double2 hk = psf_row_dft(hs, psf.pw, unit_root(k, n), unit_root(-k * ((psf.pw - 1) / 2), n));
     const double den = hk.x * hk.x + hk.y * hk.y + K;
@@ -79,21 +79,27 @@ __global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double 
     M[k] = Cplx<C>::make((R)(hk.x / den), (R)(-hk.y / den));
 }
 
-// One workgroup per `nb` row pairs; LDS: two ping-pong buffers of nb*n
-// complex plus the twiddle table.
 template <typename C>
-__global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict__ f, float* __restrict__ u,
-                                                         int H, int W, int pitch, int nb, FftPlan plan,
-                                                         const C* __restrict__ M, float pos_floor)
+__global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double K, C* __restrict__ M)
+{
+    __shared__ float hs[MULT_MAXP];
+    mult_1d_block<C>(psf, n, K, M, blockIdx.x, hs);
+}
+
+// One workgroup per `nb` row pairs (block blk); LDS: two ping-pong buffers
+// of nb*n complex plus the twiddle table.
+template <typename C>
+DEBLUR_DEV void rows_fused_block(const float* __restrict__ f, float* __restrict__ u, int H, int W, int pitch, int nb,
+                                 const FftPlan& plan, const C* __restrict__ M, float pos_floor, int blk,
+                                 unsigned char* smem_raw)
 {
     using R = typename Cplx<C>::R;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     C* tw = reinterpret_cast<C*>(smem_raw);
     C* a = tw + W;
     C* b = a + nb * W;
     fft_twiddles(tw, W);
 
-    const int pair0 = blockIdx.x * nb;
+    const int pair0 = blk * nb;
     stage_to_lds_n<8>(a, nb * W, [&](int idx) {
         const int t = idx / W, x = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
@@ -119,6 +125,15 @@ __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict
         if (ya < H) u[(size_t)ya * pitch + x] = fmaxf((float)(z.x * inv), pos_floor);
         if (yb < H) u[(size_t)yb * pitch + x] = fmaxf((float)(-z.y * inv), pos_floor);
     }
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict__ f, float* __restrict__ u,
+                                                         int H, int W, int pitch, int nb, FftPlan plan,
+                                                         const C* __restrict__ M, float pos_floor)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    rows_fused_block<C>(f, u, H, W, pitch, nb, plan, M, pos_floor, blockIdx.x, smem_raw);
 }
 
 // M(ky, kx) for kx <= W/2, stored row-major with row pitch W/2+1 (the
@@ -300,17 +315,16 @@ __global__ void __launch_bounds__(256) wiener_rows_fwd_mult(const float* __restr
 // place): mode 0: FFT along y, multiply by M (or conj M), inverse FFT (1/H);
 // mode 1: forward FFT only; mode 2: inverse FFT only (1/H).
 template <typename C>
-__global__ void __launch_bounds__(256) wiener_cols(C* __restrict__ S, const C* __restrict__ M,
-                                                   int H, int W, int cb, FftPlan plan, int mode, int conjM)
+DEBLUR_DEV void cols_block(C* __restrict__ S, const C* __restrict__ M, int H, int W, int cb, const FftPlan& plan,
+                           int mode, int conjM, int blk, unsigned char* smem_raw)
 {
     using R = typename Cplx<C>::R;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     C* tw = reinterpret_cast<C*>(smem_raw);
     C* a = tw + H;
     C* b = a + cb * H;
     fft_twiddles(tw, H);
     const int Wh = W / 2 + 1;
-    const int c0 = xcd_group(blockIdx.x, gridDim.x) * cb;
+    const int c0 = blk * cb;
     // With at most 8 elements per thread, the multiplier M of the thread's
     // elements is fetched together with S, so its latency is not paid after
     // the forward transform.
@@ -363,6 +377,16 @@ __global__ void __launch_bounds__(256) wiener_cols(C* __restrict__ S, const C* _
     }
 }
 
+// Column blocks in an XCD-aware order (the blocks of one XCD take adjacent
+// columns, which share cache lines of S).
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_cols(C* __restrict__ S, const C* __restrict__ M,
+                                                   int H, int W, int cb, FftPlan plan, int mode, int conjM)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cols_block<C>(S, M, H, W, cb, plan, mode, conjM, xcd_group(blockIdx.x, gridDim.x), smem_raw);
+}
+
 // S_out = S_in * M (or conj M), elementwise on the half spectrum (S_out may
 // alias S_in).
 __global__ void __launch_bounds__(256) spectral_mul(const float2* Sin, const float2* __restrict__ M, int conjM,
@@ -378,18 +402,16 @@ __global__ void __launch_bounds__(256) spectral_mul(const float2* Sin, const flo
 // packed as Z = U_a + i U_b, inverse FFT (scaled by 1/W): u_a = Re, u_b = Im;
 // non-positive values replaced by pos_floor (Sec. 3.2).
 template <typename C>
-__global__ void __launch_bounds__(256) wiener_rows_inv(const C* __restrict__ S, float* __restrict__ u,
-                                                       int H, int W, int pitch, int nb, FftPlan plan,
-                                                       float pos_floor, int accumulate)
+DEBLUR_DEV void rows_inv_block(const C* __restrict__ S, float* __restrict__ u, int H, int W, int pitch, int nb,
+                               const FftPlan& plan, float pos_floor, int accumulate, int blk, unsigned char* smem_raw)
 {
     using R = typename Cplx<C>::R;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     C* tw = reinterpret_cast<C*>(smem_raw);
     C* a = tw + W;
     C* b = a + nb * W;
     fft_twiddles(tw, W);
     const int Wh = W / 2 + 1;
-    const int pair0 = blockIdx.x * nb;
+    const int pair0 = blk * nb;
     stage_to_lds_n<8>(a, nb * W, [&](int idx) {
         const int t = idx / W, k = idx - t * W;
         const int ya = 2 * (pair0 + t), yb = ya + 1;
@@ -420,6 +442,74 @@ __global__ void __launch_bounds__(256) wiener_rows_inv(const C* __restrict__ S, 
             if (yb < H) u[(size_t)yb * pitch + x] = fmaxf((float)(-z.y * inv), pos_floor);
         }
     }
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_rows_inv(const C* __restrict__ S, float* __restrict__ u,
+                                                       int H, int W, int pitch, int nb, FftPlan plan,
+                                                       float pos_floor, int accumulate)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    rows_inv_block<C>(S, u, H, W, pitch, nb, plan, pos_floor, accumulate, blockIdx.x, smem_raw);
+}
+
+// ------------------------------------------------- batched form (FP32)
+// Many images of one size and one path in one launch: blockIdx.y selects the
+// image's job, blockIdx.x the block within the image, as in the one-image
+// kernels (the same block bodies, so the results are the same bit for bit).
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_mult_1d_b(const WienerJob* __restrict__ jobs, int n)
+{
+    __shared__ float hs[MULT_MAXP];
+    const WienerJob& j = jobs[blockIdx.y];
+    mult_1d_block<C>(j.psf, n, j.K, reinterpret_cast<C*>(j.ws), blockIdx.x, hs);
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_rows_fused_b(const WienerJob* __restrict__ jobs, int H, int W, int nb,
+                                                           FftPlan plan)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const WienerJob& j = jobs[blockIdx.y];
+    rows_fused_block<C>(j.f, j.u, H, W, j.pitch, nb, plan, reinterpret_cast<const C*>(j.ws), j.pos_floor, blockIdx.x,
+                        smem_raw);
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_rows_fwd_mult_b(const WienerJob* __restrict__ jobs, int H, int W,
+                                                              int nb, FftPlan plan, int nrow, int gxm)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const WienerJob& j = jobs[blockIdx.y];
+    C* M = reinterpret_cast<C*>(j.ws);
+    C* S = M + (size_t)H * (W / 2 + 1);
+    if ((int)blockIdx.x < nrow) {
+        rows_fwd_block(j.f, S, H, W, j.pitch, nb, plan, blockIdx.x, smem_raw);
+    } else {
+        const int b = blockIdx.x - nrow, by = b / gxm;
+        mult_2d_block<C>(j.psf, H, W, j.K, M, nullptr, b - by * gxm, by, smem_raw);
+    }
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_cols_b(const WienerJob* __restrict__ jobs, int H, int W, int cb,
+                                                     FftPlan plan)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const WienerJob& j = jobs[blockIdx.y];
+    C* M = reinterpret_cast<C*>(j.ws);
+    C* S = M + (size_t)H * (W / 2 + 1);
+    cols_block<C>(S, M, H, W, cb, plan, 0, 0, xcd_group(blockIdx.x, gridDim.x), smem_raw);
+}
+
+template <typename C>
+__global__ void __launch_bounds__(256) wiener_rows_inv_b(const WienerJob* __restrict__ jobs, int H, int W, int nb,
+                                                         FftPlan plan)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const WienerJob& j = jobs[blockIdx.y];
+    const C* S = reinterpret_cast<const C*>(j.ws) + (size_t)H * (W / 2 + 1);
+    rows_inv_block<C>(S, j.u, H, W, j.pitch, nb, plan, j.pos_floor, 0, blockIdx.x, smem_raw);
 }
 
 // ------------------------------------------------------------ host launchers
@@ -454,6 +544,10 @@ static void allow_wiener_lds()
         allow_lds(&wiener_rows_fwd_mult<C>);
         allow_lds(&wiener_cols<C>);
         allow_lds(&wiener_rows_inv<C>);
+        allow_lds(&wiener_rows_fused_b<C>);
+        allow_lds(&wiener_rows_fwd_mult_b<C>);
+        allow_lds(&wiener_cols_b<C>);
+        allow_lds(&wiener_rows_inv_b<C>);
     });
 }
 
@@ -493,6 +587,34 @@ static int launch_wiener_t(const float* f, float* u, int H, int W, int pitch, co
                            H, W, cb, make_plan(H), 0, 0);
         hipLaunchKernelGGL(wiener_rows_inv<C>, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st,
                            (const C*)S, u, H, W, pitch, nb, make_plan(W), pos_floor, 0);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+// The Wiener steps of n images of one size H x W and one path (jobs: device
+// array of n descriptors, each with its own workspace of wiener_ws_bytes),
+// FP32 transforms: one launch per kernel of the one-image form.
+int launch_wiener_batch(const WienerJob* jobs, int n, int H, int W, bool rowwise, hipStream_t st)
+{
+    using C = float2;
+    allow_wiener_lds<C>();
+    const int pairs = (H + 1) / 2, nb = row_batch(W);
+    const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(C);
+    if (rowwise) {
+        hipLaunchKernelGGL(wiener_mult_1d_b<C>, dim3((W + 255) / 256, n), dim3(256), 0, st, jobs, W);
+        hipLaunchKernelGGL(wiener_rows_fused_b<C>, dim3((pairs + nb - 1) / nb, n), dim3(256), lds_r, st, jobs, H, W,
+                           nb, make_plan(W));
+    } else {
+        const int Wh = W / 2 + 1;
+        const int nrow = (pairs + nb - 1) / nb;
+        const int gxm = (Wh + MULT_KX - 1) / MULT_KX, gym = (H + MULT_KY - 1) / MULT_KY;
+        hipLaunchKernelGGL(wiener_rows_fwd_mult_b<C>, dim3(nrow + gxm * gym, n), dim3(256), std::max(lds_r, MULT_SMEM),
+                           st, jobs, H, W, nb, make_plan(W), nrow, gxm);
+        const int cb = col_batch(H);
+        hipLaunchKernelGGL(wiener_cols_b<C>, dim3((Wh + cb - 1) / cb, n), dim3(256), (size_t)(H + 2 * cb * H) * sizeof(C),
+                           st, jobs, H, W, cb, make_plan(H));
+        hipLaunchKernelGGL(wiener_rows_inv_b<C>, dim3((pairs + nb - 1) / nb, n), dim3(256), lds_r, st, jobs, H, W, nb,
+                           make_plan(W));
     }
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
