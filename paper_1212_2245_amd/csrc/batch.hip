@@ -5,10 +5,10 @@
 // (q, W) planes, and builds flat tile lists per kernel class (stencil radius
 // classes 4/8/16/32; horizontal and vertical box, each split at 512 x 512
 // pixels) spanning all images of a group.  The captured graph runs, per
-// group: the Wiener step of every image (on several forked capture streams),
-// then one chain per class with, for each iteration, one launch per stage,
-// whose workgroups each take one tile of one image from the list; the class
-// chains are independent, and a timestamp kernel follows their join.  Groups
+// group, one independent chain per class: the Wiener steps of the class's
+// images (one batched launch per kernel for each image size), then for each
+// iteration one launch per stage, whose workgroups each take one tile of one
+// image from the list; a timestamp kernel follows the chains' join.  Groups
 // run one after another.  In the
 // launches of the last iteration every tile counts itself done for its image
 // (an atomic counter) and the image's last tile writes the image's
@@ -379,22 +379,23 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
     set_box_attr<true, false>(P->box_var[CL_BOXV - CL_BOXH]);
     set_box_attr<false, true>(P->box_var[CL_BOXH_L - CL_BOXH]);
     set_box_attr<true, true>(P->box_var[CL_BOXV_L - CL_BOXH]);
-    // Wiener steps: per group, the images of one size and one path (one-row
-    // PSF or general) form one job list, run by one batched launch per
-    // kernel; every image has its own workspace.
-    constexpr int kChains = 4;
+    // Wiener steps: per group and tile class, the images of one size and one
+    // path (one-row PSF or general) form one job list, run by one batched
+    // launch per kernel at the head of the class's chain; every image has its
+    // own workspace.
     struct JobSet {
         WienerJob* d = nullptr;
-        int count = 0, H = 0, W = 0;
+        int count = 0, H = 0, W = 0, cls = 0;
         bool rowwise = false;
     };
     std::vector<std::vector<JobSet>> jobsets(P->groups);
     for (int g = 0; g < P->groups; ++g) {
-        std::vector<std::pair<long, std::vector<WienerJob>>> sets;   // key: (H, W, rowwise)
+        std::vector<std::pair<long, std::vector<WienerJob>>> sets;   // key: (class, H, W, rowwise)
         for (int i = g * gs; i < std::min(n, (g + 1) * gs); ++i) {
             const BatchItemDev& it = items[i];
             const bool rowwise = it.psf.ph == 1;
-            const long key = ((long)it.H << 33) | ((long)it.W << 1) | (rowwise ? 1 : 0);
+            const long key = ((long)P->class_of_img[i] << 56) | ((long)it.H << 28) | ((long)it.W << 1) |
+                             (rowwise ? 1 : 0);
             void* w = dalloc(P, wiener_ws_bytes(it.H, it.W, rowwise));
             if (!w) {
                 batch_plan_destroy(P);
@@ -415,8 +416,9 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
         for (auto& kv : sets) {
             JobSet js;
             js.count = (int)kv.second.size();
-            js.H = (int)(kv.first >> 33);
-            js.W = (int)((kv.first >> 1) & 0xffffffffL);
+            js.cls = (int)(kv.first >> 56);
+            js.H = (int)((kv.first >> 28) & 0xfffffffL);
+            js.W = (int)((kv.first >> 1) & 0x7ffffffL);
             js.rowwise = kv.first & 1;
             js.d = static_cast<WienerJob*>(dalloc(P, sizeof(WienerJob) * kv.second.size()));
             if (!js.d || hipMemcpy(js.d, kv.second.data(), sizeof(WienerJob) * kv.second.size(),
@@ -434,9 +436,9 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
     }
     // ---- capture
     bool ok = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) == hipSuccess;
-    // chains 0..kChains-1: the Wiener steps; kChains + class: the iterations of one tile class
-    P->chains.resize(kChains + NCLASS, nullptr);
-    for (int c = 0; c < kChains + NCLASS && ok; ++c)
+    // one chain per tile class
+    P->chains.resize(NCLASS, nullptr);
+    for (int c = 0; c < NCLASS && ok; ++c)
         ok = hipStreamCreateWithFlags(&P->chains[c], hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         batch_plan_destroy(P);
@@ -455,38 +457,21 @@ int batch_plan_create(const BatchItemDev* items, int n, int group_size, const in
         hipLaunchKernelGGL(batch_timestamp, dim3(1), dim3(64), 0, s, P->ts, 0);
     }
     for (int g = 0; g < P->groups && ok; ++g) {
-        // Wiener of the group's images, forked over the chains
+        // every tile class (stencil radius, box axis and size) covers its own
+        // images, which depend only on themselves, so each class is an
+        // independent chain, forked once per group and joined at its end:
+        // the batched Wiener steps of its images, then all iterations
+        const auto& L = lists[g];
         hipEvent_t fork = event();
         ok = fork && hipEventRecord(fork, s) == hipSuccess;
-        for (int c = 0; c < kChains && ok; ++c) ok = hipStreamWaitEvent(P->chains[c], fork, 0) == hipSuccess;
-        // the job sets spread over the chains, largest first onto the least loaded
-        std::vector<const JobSet*> order;
-        for (const JobSet& js : jobsets[g]) order.push_back(&js);
-        std::sort(order.begin(), order.end(), [](const JobSet* a, const JobSet* b) {
-            return (long)a->H * a->W * a->count > (long)b->H * b->W * b->count;
-        });
-        long load[kChains] = {0, 0, 0, 0};
-        for (size_t k = 0; ok && k < order.size(); ++k) {
-            const JobSet& js = *order[k];
-            const int c = (int)(std::min_element(load, load + kChains) - load);
-            load[c] += (long)js.H * js.W * js.count;
-            ok = launch_wiener_batch(js.d, js.count, js.H, js.W, js.rowwise, P->chains[c]) == 0;
-        }
-        for (int c = 0; c < kChains && ok; ++c) {
-            hipEvent_t join = event();
-            ok = join && hipEventRecord(join, P->chains[c]) == hipSuccess && hipStreamWaitEvent(s, join, 0) == hipSuccess;
-        }
-        // the iterations: every tile class (stencil radius, box axis) covers
-        // its own images, which depend only on themselves, so each class is
-        // an independent chain over all iterations, forked once after the
-        // Wiener step and joined at the end of the group
-        const auto& L = lists[g];
-        hipEvent_t fork_it = ok ? event() : nullptr;
-        ok = ok && fork_it && hipEventRecord(fork_it, s) == hipSuccess;
         for (int cls = 0; cls < NCLASS && ok; ++cls) {
             if (!L[cls].count) continue;
-            hipStream_t cs = P->chains[kChains + cls];
-            ok = hipStreamWaitEvent(cs, fork_it, 0) == hipSuccess;
+            hipStream_t cs = P->chains[cls];
+            ok = hipStreamWaitEvent(cs, fork, 0) == hipSuccess;
+            for (size_t k = 0; ok && k < jobsets[g].size(); ++k) {
+                const JobSet& js = jobsets[g][k];
+                if (js.cls == cls) ok = launch_wiener_batch(js.d, js.count, js.H, js.W, js.rowwise, cs) == 0;
+            }
             for (int k = 0; k < P->iters && ok; ++k)
                 launch_class(P, L[cls], cls, 3, (start + k) % 2, k == P->iters - 1 ? P->img_cnt : nullptr, cs);
             hipEvent_t join = ok ? event() : nullptr;
