@@ -237,13 +237,14 @@ def best_batch_tiles(items, path: str | None = None):
     return tuple(int(t) for t in entry["tiles"])
 
 
-def tune_batch(items, reps: int = 5, path: str | None = None, store: bool = True) -> dict:
+def tune_batch(items, reps: int = 10, path: str | None = None, store: bool = True) -> dict:
     """Tile shapes of a batch plan over `items`: every variant of one tile
     entry (stencil, box_h, box_v, box_h_large, box_v_large) is tried with the
     others at their defaults, each plan's outputs must equal the default
     plan's bitwise, and each entry is timed by launching its classes' kernels
-    alone (the plan's per-class launch hook).  Entries whose classes hold no
-    image keep the default (0)."""
+    alone (the plan's per-class launch hook): after one full run of the plan,
+    the best of three rounds of `reps` launches.  Entries whose classes hold
+    no image keep the default (0)."""
     import torch
 
     from . import BatchPlan
@@ -282,7 +283,7 @@ def tune_batch(items, reps: int = 5, path: str | None = None, store: bool = True
                 if not torch.equal(a, b):
                     plan.close()
                     raise AssertionError(f"batch tiles {tiles} changed image {i}")
-            tf[v] = class_time(plan, fams[fam])
+            tf[v] = min(class_time(plan, fams[fam]) for _ in range(3))
             plan.close()
         best[fam] = choose(tf)
         timings[BatchPlan.TILE_NAMES[fam]] = tf
