@@ -255,10 +255,10 @@ def test_autograd_batch_per_image_alpha():
     every image's output and gradients equal those of its single-image call
     bit for bit; a PSF shared by the batch gets the sum of the images' dL/dh,
     a scalar alpha the sum of their dL/dalpha."""
-    B = 3
+    B = 6          # more images than side streams: two images share a stream
     cases = [synth.make_case(4, image=i, size=96) for i in range(B)]
     g = torch.stack([dev(c.g) for c in cases]).double()
-    alpha = torch.tensor([0.002, 0.004, 0.001], dtype=torch.float32)
+    alpha = torch.tensor([0.002, 0.004, 0.001, 0.003, 0.0015, 0.0025], dtype=torch.float32)
     f = torch.stack([dev(c.f) for c in cases]).requires_grad_(True)
     taps = torch.stack([dev(c.psf) for c in cases]).requires_grad_(True)
     a = alpha.clone().requires_grad_(True)
