@@ -238,7 +238,8 @@ int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
  * K and pos_floor; the computation per item is deblur_wiener followed by
  * deblur_rrrl_iterate.  deblur_batch_plan_create validates every item (the
  * status of the first invalid one is returned), then allocates the plan's
- * device memory (per-image scratch planes, compiled tap lists, tile lists),
+ * device memory (per-image scratch planes and Wiener workspaces, compiled
+ * tap lists, tile lists, the Wiener job lists),
  * compiles the PSFs (their taps are read here: a changed PSF needs a new
  * plan) and captures the graph; it synchronises the device.  group_size > 0
  * runs the images in consecutive groups of that many (a group starts when
@@ -270,9 +271,10 @@ int32_t deblur_batch_tile_variants(int32_t family);
  * DEBLUR_BATCH_NTILES entries, or NULL for the defaults) = {stencil variant,
  * box variant of horizontal images up to 512 x 512 pixels, of vertical ones
  * up to 512 x 512, of larger horizontal ones, of larger vertical ones}, each
- * 0 (default: 1, 5, 5, 1, 1) .. the family's count, else DEBLUR_EINVAL.  Items with p.conv == DEBLUR_CONV_FFT are rejected
- * with DEBLUR_EUNSUPPORTED by both create calls: a plan runs the direct
- * paths (stencil, running sums) only. */
+ * 0 (default: 1, 5, 5, 1, 1) .. the family's count, else DEBLUR_EINVAL.
+ * Items with p.conv == DEBLUR_CONV_FFT are rejected with
+ * DEBLUR_EUNSUPPORTED by both create calls: a plan runs the direct paths
+ * (stencil, running sums) only. */
 int deblur_batch_plan_create_tiled(const deblur_batch_item* items, int32_t n, int32_t group_size,
                                    const int32_t* tiles, deblur_batch_plan** plan);
 
