@@ -231,6 +231,37 @@ int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
                          double K, float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha,
                          float* grad_u0, void* ws, size_t ws_bytes, void* stream);
 
+/* deblur_rrrl_backward for B images at once (the same derivatives, eqs.
+ * (9)-(12), eq. (2)): one launch per kernel covers every image, so a batch of
+ * small images fills the GPU.  All images share H, W, pitch, the PSF array
+ * dimensions, *p except alpha, through_wiener, K and pos_floor; each has its
+ * own f, checkpoints, dL/du^K, PSF taps and alpha.  Image b (0 <= b < B):
+ *   f + b img_stride, grad_uK + b img_stride, grad_f + b img_stride,
+ *   grad_u0 + b img_stride (each H x pitch floats);
+ *   ckpt + b ckpt_stride (p->iters * H * pitch floats);
+ *   PSF: psf->taps + b taps_stride for DEBLUR_PSF_TAPS (taps_stride 0: one
+ *   PSF shared by the batch); box kinds are shared and need taps_stride 0;
+ *   grad_taps + b ph pw (nullable; B ph pw floats), grad_alpha + b
+ *   (nullable; B floats);
+ *   alpha: device array of B floats, image b's regulariser weight; NULL uses
+ *   p->alpha for every image.  Its values are read by the kernels and are not
+ *   validated (they must be finite and >= 0).
+ * Strides are in floats: img_stride >= H pitch, ckpt_stride >= p->iters H
+ * pitch, taps_stride >= ph pw (or 0).  1 <= B <= 65535.  Each image's results
+ * equal deblur_rrrl_backward's for that image bit for bit.  ws: at least
+ * deblur_backward_batch_workspace_bytes(...) bytes (B per-image workspaces).
+ * Output ranges (over the whole batch) must not overlap the inputs'.
+ * Errors as deblur_rrrl_backward; DEBLUR_EINVAL for B or a stride out of
+ * range. */
+size_t deblur_backward_batch_workspace_bytes(int32_t B, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                                             const deblur_params* p, int32_t through_wiener);
+int deblur_rrrl_backward_batch(int32_t B, const float* f, const float* ckpt, const float* grad_uK, int32_t H,
+                               int32_t W, int32_t pitch, int64_t img_stride, int64_t ckpt_stride,
+                               const deblur_psf* psf, int64_t taps_stride, const float* alpha,
+                               const deblur_params* p, int32_t through_wiener, double K, float pos_floor,
+                               float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0, void* ws,
+                               size_t ws_bytes, void* stream);
+
 /* ---- Batched form: many images of different sizes, each with its own PSF
  * and parameters, in one hipGraph launch.
  * An item binds the device pointers f (input) and u (output, H x pitch), the

@@ -307,6 +307,83 @@ def deblur_rrrl_backward(f: torch.Tensor, ckpt: torch.Tensor | None, grad_uK: to
     return out
 
 
+__all__ += ["deblur_rrrl_backward_batch"]
+
+
+def _batch_images(t: torch.Tensor, name: str) -> tuple[int, int, int, int, int]:
+    """(B, H, W, pitch, image stride) of a [B, H, W] float32 device tensor."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 3:
+        raise ValueError(f"{name} must be a [B, H, W] float32 device tensor")
+    if t.stride(2) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    return t.shape[0], t.shape[1], t.shape[2], t.stride(1), t.stride(0)
+
+
+def deblur_rrrl_backward_batch(f: torch.Tensor, ckpt: torch.Tensor | None, grad_uK: torch.Tensor,
+                               taps, params: Params, alpha: torch.Tensor | None = None,
+                               through_wiener: bool = True, K: float = 0.01, pos_floor: float = 1.0,
+                               grad_taps: bool = True, grad_alpha: bool = True, grad_u0: bool = False,
+                               ws: torch.Tensor | None = None) -> dict:
+    """deblur_rrrl_backward for a batch of B equally sized images in one
+    launch per kernel.  f, grad_uK: [B, H, W] (same layout); ckpt:
+    [B, iters, H, W] (contiguous per image, None when iters == 0); taps:
+    [B, ph, pw] one PSF per image, [ph, pw] or a Psf (any kind) shared by
+    the batch; alpha: [B] device
+    float32 weights (None: params.alpha for all).  Returns a dict of batched
+    gradients: 'f' [B, H, W], 'taps' [B, ph, pw], 'alpha' [B], 'u0'."""
+    lib = _lib.load()
+    B, H, W, pitch, istride = _batch_images(f, "f")
+    if _batch_images(grad_uK, "grad_uK") != (B, H, W, pitch, istride):
+        raise ValueError("f and grad_uK must have the same shape and strides")
+    cstride = 0
+    if params.iters > 0:
+        if ckpt is None or ckpt.dim() != 4 or tuple(ckpt.shape) != (B, params.iters, H, W) or ckpt.dtype != torch.float32:
+            raise ValueError("ckpt must be a [B, iters, H, W] float32 tensor")
+        if ckpt.stride(3) != 1 or ckpt.stride(2) != pitch or ckpt.stride(1) != H * pitch:
+            raise ValueError("ckpt must hold each image's iterates as consecutive H x pitch planes")
+        cstride = ckpt.stride(0)
+    if isinstance(taps, Psf):
+        cpsf, tstride = taps.c(), 0
+        ph, pw = taps.array_shape()
+    else:
+        if taps.dim() == 2:
+            tb, tstride = taps.contiguous(), 0
+        elif taps.dim() == 3 and taps.shape[0] == B:
+            tb = taps.contiguous()
+            tstride = tb.stride(0)
+        else:
+            raise ValueError("taps must be [ph, pw], [B, ph, pw] or a Psf")
+        ph, pw = int(tb.shape[-2]), int(tb.shape[-1])
+        cpsf = Psf.from_taps(tb if tb.dim() == 2 else tb[0]).c()
+    cpar = params.c()
+    if alpha is not None:
+        if not alpha.is_cuda or alpha.dtype != torch.float32 or alpha.numel() != B:
+            raise ValueError("alpha must be a [B] float32 device tensor")
+        alpha = alpha.contiguous()
+    need = lib.deblur_backward_batch_workspace_bytes(B, H, W, pitch, ctypes.byref(cpsf), ctypes.byref(cpar),
+                                                     int(bool(through_wiener)))
+    if need == 0:
+        raise ValueError("invalid backward batch arguments")
+    wst = _workspace(need, f, ws)
+    out = {"f": torch.empty_strided((B, H, W), (istride, pitch, 1), dtype=torch.float32, device=f.device)}
+    if grad_taps:
+        out["taps"] = torch.empty((B, ph, pw), dtype=torch.float32, device=f.device)
+    if grad_alpha:
+        out["alpha"] = torch.empty((B,), dtype=torch.float32, device=f.device)
+    if grad_u0:
+        out["u0"] = torch.empty_strided((B, H, W), (istride, pitch, 1), dtype=torch.float32, device=f.device)
+    st = lib.deblur_rrrl_backward_batch(B, f.data_ptr(), ckpt.data_ptr() if ckpt is not None else None,
+                                        grad_uK.data_ptr(), H, W, pitch, istride, cstride, ctypes.byref(cpsf),
+                                        tstride, alpha.data_ptr() if alpha is not None else None,
+                                        ctypes.byref(cpar), int(bool(through_wiener)), float(K), float(pos_floor),
+                                        out["f"].data_ptr(), out["taps"].data_ptr() if grad_taps else None,
+                                        out["alpha"].data_ptr() if grad_alpha else None,
+                                        out["u0"].data_ptr() if grad_u0 else None, wst.data_ptr(), wst.numel(),
+                                        _stream(f))
+    _lib.check(st, "deblur_rrrl_backward_batch")
+    return out
+
+
 _SIDE_STREAMS: dict = {}
 
 
@@ -359,7 +436,9 @@ class WR3LFunction(torch.autograd.Function):
     periodic Wiener filter, and a correctly rounded u^0 keeps the GPU
     gradient within 1e-3 of the FP64 one.  The per-iteration checkpoints u^k
     are stored; the backward recomputes every other quantity from them.  The
-    images of a batch run concurrently on up to four side streams."""
+    forward runs the images of a batch concurrently on up to four side
+    streams; the backward covers the whole batch with one launch per kernel
+    (deblur_rrrl_backward_batch)."""
 
     @staticmethod
     def forward(ctx, f, taps, alpha, K: float, iters: int, template: Params | None = None, pos_floor: float = 1.0):
@@ -399,16 +478,11 @@ class WR3LFunction(torch.autograd.Function):
     def backward(ctx, grad_u):
         fb, tb, ck = ctx.saved_tensors
         gb = (grad_u if ctx.batched else grad_u.unsqueeze(0)).contiguous()
-        gf, gt, ga = torch.empty_like(fb), torch.empty_like(tb), torch.empty(fb.shape[0], device=fb.device)
-
-        def one(i):
-            p = ctx.plist[i]
-            g = deblur_rrrl_backward(fb[i], ck[i] if p.iters > 0 else None, gb[i], Psf.from_taps(tb[i]), p,
-                                     through_wiener=True, K=ctx.K, pos_floor=ctx.pos_floor)
-            gf[i].copy_(g["f"])
-            gt[i].copy_(g["taps"])
-            ga[i].copy_(g["alpha"].reshape(()))
-        _on_streams(len(ctx.plist), one, fb.device)
+        p0 = ctx.plist[0]
+        alphas = torch.tensor([p.alpha for p in ctx.plist], dtype=torch.float32).to(fb.device, non_blocking=True)
+        g = deblur_rrrl_backward_batch(fb, ck if p0.iters > 0 else None, gb, tb, p0, alpha=alphas,
+                                       through_wiener=True, K=ctx.K, pos_floor=ctx.pos_floor)
+        gf, gt, ga = g["f"], g["taps"], g["alpha"]
         if ctx.shared_taps:
             gt = gt.sum(0)
         if ctx.alpha_shape == 1:

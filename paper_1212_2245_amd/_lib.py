@@ -61,6 +61,11 @@ SIGNATURES = [
     ("deblur_rrrl_iterate_noalloc", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP]),
     ("deblur_rrrl_backward", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _I32, ctypes.c_double,
                                             ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    ("deblur_backward_batch_workspace_bytes", _SZ, [_I32, _I32, _I32, _I32, _PSF, _PAR, _I32]),
+    ("deblur_rrrl_backward_batch", ctypes.c_int, [_I32, _VP, _VP, _VP, _I32, _I32, _I32, ctypes.c_int64,
+                                                  ctypes.c_int64, _PSF, ctypes.c_int64, _VP, _PAR, _I32,
+                                                  ctypes.c_double, ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _SZ,
+                                                  _VP]),
     ("deblur_batch_plan_create", ctypes.c_int, [ctypes.POINTER(deblur_batch_item), _I32, _I32,
                                                 ctypes.POINTER(ctypes.c_void_p)]),
     ("deblur_batch_plan_create_tiled", ctypes.c_int, [ctypes.POINTER(deblur_batch_item), _I32, _I32,

@@ -36,6 +36,15 @@ DEBLUR_DEV int xcd_group(int b, int n)
 
 DEBLUR_DEV int clampi(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
 
+// Launches over a batch of equally shaped images take the image index from
+// blockIdx.z: image z's plane is the first image's advanced by z times a
+// byte stride (stride 0: one plane shared by the batch).
+template <typename T>
+DEBLUR_DEV T* zadv(T* p, size_t stride)
+{
+    return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (size_t)blockIdx.z * stride);
+}
+
 // Cooperative copy of N elements into LDS: lds[idx] = fetch(idx), idx < N,
 // by NT threads.  All global loads of a thread are issued before the first
 // LDS store, so their latencies overlap (a plain strided loop would wait for

@@ -353,6 +353,70 @@ int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
     return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EUNSUPPORTED : DEBLUR_EDEVICE);
 }
 
+namespace {
+
+// Validates the shared arguments of a backward batch; DEBLUR_OK or an error.
+int check_backward_batch(int32_t B, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                         const deblur_params* p, int32_t through_wiener, int64_t img_stride, int64_t ckpt_stride,
+                         int64_t taps_stride, PsfDev* d)
+{
+    if (B < 1 || B > 65535) return DEBLUR_EINVAL;
+    if (through_wiener != 0 && through_wiener != 1) return DEBLUR_EINVAL;
+    int s = check_backward(H, W, pitch, psf, p, through_wiener == 1, d);
+    if (s) return s;
+    const int64_t img = (int64_t)H * pitch;
+    if (img_stride < img || ckpt_stride < 0 || taps_stride < 0) return DEBLUR_EINVAL;
+    if (p->iters > 0 && ckpt_stride < img * p->iters) return DEBLUR_EINVAL;
+    if (d->kind == PSF_TAPS) {
+        if (taps_stride != 0 && taps_stride < (int64_t)d->ph * d->pw) return DEBLUR_EINVAL;
+    } else if (taps_stride != 0) {
+        return DEBLUR_EINVAL;
+    }
+    return DEBLUR_OK;
+}
+
+}  // namespace
+
+size_t deblur_backward_batch_workspace_bytes(int32_t B, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
+                                             const deblur_params* p, int32_t through_wiener)
+{
+    PsfDev d;
+    if (check_backward_batch(B, H, W, pitch, psf, p, through_wiener, (int64_t)H * pitch,
+                             p ? (int64_t)H * pitch * p->iters : 0, 0, &d))
+        return 0;
+    return (size_t)B * backward_batch_stride(H, W, d, through_wiener == 1);
+}
+
+int deblur_rrrl_backward_batch(int32_t B, const float* f, const float* ckpt, const float* grad_uK, int32_t H,
+                               int32_t W, int32_t pitch, int64_t img_stride, int64_t ckpt_stride,
+                               const deblur_psf* psf, int64_t taps_stride, const float* alpha,
+                               const deblur_params* p, int32_t through_wiener, double K, float pos_floor,
+                               float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0, void* ws,
+                               size_t ws_bytes, void* stream)
+{
+    PsfDev d;
+    if (!f || !grad_uK || !grad_f) return DEBLUR_EINVAL;
+    int s = check_backward_batch(B, H, W, pitch, psf, p, through_wiener, img_stride, ckpt_stride, taps_stride, &d);
+    if (s) return s;
+    if (p->iters > 0 && !ckpt) return DEBLUR_EINVAL;
+    if (through_wiener && (!(K > 0.0) || !std::isfinite(K) || !std::isfinite(pos_floor))) return DEBLUR_EINVAL;
+    // extents over the whole batch
+    const size_t img = ((size_t)(B - 1) * img_stride + (size_t)H * pitch) * sizeof(float);
+    const size_t ck = p->iters > 0 ? ((size_t)(B - 1) * ckpt_stride + (size_t)p->iters * H * pitch) * sizeof(float) : 0;
+    if (overlaps(grad_f, img, f, img) || overlaps(grad_f, img, grad_uK, img) || (ckpt && overlaps(grad_f, img, ckpt, ck)))
+        return DEBLUR_EINVAL;
+    if (grad_u0 && (overlaps(grad_u0, img, grad_f, img) || overlaps(grad_u0, img, f, img) ||
+                    overlaps(grad_u0, img, grad_uK, img) || (ckpt && overlaps(grad_u0, img, ckpt, ck))))
+        return DEBLUR_EINVAL;
+    const size_t stride = backward_batch_stride(H, W, d, through_wiener == 1);
+    if (!ws || ws_bytes / B < stride) return DEBLUR_EWORKSPACE;
+    s = launch_rrrl_backward_batch(B, f, ckpt, grad_uK, H, W, pitch, (size_t)img_stride * sizeof(float),
+                                   (size_t)ckpt_stride * sizeof(float), d, (size_t)taps_stride * sizeof(float), alpha,
+                                   iter_params(p), p->iters, through_wiener == 1, K, pos_floor, grad_f, grad_taps,
+                                   grad_alpha, grad_u0, ws, stride, reinterpret_cast<hipStream_t>(stream));
+    return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EUNSUPPORTED : DEBLUR_EDEVICE);
+}
+
 int deblur_batch_plan_create(const deblur_batch_item* items, int32_t n, int32_t group_size,
                              deblur_batch_plan** plan)
 {

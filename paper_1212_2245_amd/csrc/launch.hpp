@@ -107,21 +107,35 @@ int launch_wiener_batch(const WienerJob* jobs, int n, int H, int W, bool rowwise
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
                   float pos_floor, void* ws, bool rowwise, bool fp64, hipStream_t st);
 
-// 2D transform building blocks on half spectra H x (W/2+1) (complex64)
-void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st);
-void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st);
+// A launch over n images of one shape at once (blockIdx.z = image): image z's
+// planes are the first image's advanced by z times the byte strides s0, s1,
+// s2 of the pointer arguments in order (0: shared by all images).
+struct ZBatch {
+    int n = 1;
+    size_t s0 = 0, s1 = 0, s2 = 0;
+};
+
+// 2D transform building blocks on half spectra H x (W/2+1) (complex64); the
+// ZBatch strides follow the pointer arguments (for the multiplier: the PSF
+// taps, M, h^).
+void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st,
+                        ZBatch zb = {});
+void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st, ZBatch zb = {});
 void launch_fft2_inverse(float2* S, int H, int W, float* out, int pitch, float floor_, bool accumulate,
-                         hipStream_t st);
+                         hipStream_t st, ZBatch zb = {});
 void launch_rows_fwd(const float* x, int pitch, int H, int W, float2* S, hipStream_t st);
 void launch_cols(float2* S, const float2* mult, bool conj_mult, int mode, int H, int W, hipStream_t st);
 int fft_row_batch(int W);
-void launch_spectral_mul(const float2* Sin, const float2* M, bool conjM, float2* Sout, size_t n, hipStream_t st);
+void launch_spectral_mul(const float2* Sin, const float2* M, bool conjM, float2* Sout, size_t n, hipStream_t st,
+                         ZBatch zb = {});
+// (one stride, s0, for all four spectra)
 void launch_wiener_dh_prep(const float2* Fh, const float2* Gh, const float2* hh, float2* Y, size_t n, double K,
-                           hipStream_t st);
+                           hipStream_t st, ZBatch zb = {});
 
 int tap_radius_class(int rad);
 size_t tap_list_bytes(const PsfDev& psf);
-void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st);
+// (ZBatch: n PSFs; strides of the taps and of the lists)
+void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st, ZBatch zb = {});
 // `variant`: 0 = default tile shape for the image size, 1..taps_num_variants()
 // = an explicit tile shape (all give bitwise-identical results).
 int taps_num_variants();
@@ -154,6 +168,18 @@ int launch_rrrl_iterate(const float* f, const float* u_in, float* u_out, int H, 
 // Backward through WR3L (iterations from checkpoints, optionally the Wiener
 // initialisation).
 size_t backward_ws_bytes(int H, int W, const PsfDev& psf, bool through_wiener);
+// The same for B images of one size and PSF box at once (blockIdx.z = image):
+// image z's planes at the first image's plus z times the byte strides
+// (img_stride: f, grad_uK, grad_f, grad_u0; ck_stride: checkpoints;
+// taps_stride: PSF taps; ws_stride: workspaces of backward_batch_stride bytes;
+// grad_taps + z ph pw, grad_alpha + z); alpha: device array of the images'
+// weights, or nullptr for p.alpha.
+size_t backward_batch_stride(int H, int W, const PsfDev& psf, bool through_wiener);
+int launch_rrrl_backward_batch(int B, const float* f, const float* ckpt, const float* grad_uK, int H, int W,
+                               int pitch, size_t img_stride, size_t ck_stride, const PsfDev& psf, size_t taps_stride,
+                               const float* alpha, const IterParams& p, int iters, bool through_wiener, double K,
+                               float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0,
+                               void* ws, size_t ws_stride, hipStream_t st);
 int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int H, int W, int pitch,
                          const PsfDev& psf, const IterParams& p, int iters, bool through_wiener, double K,
                          float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0,

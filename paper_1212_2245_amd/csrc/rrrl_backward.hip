@@ -21,7 +21,12 @@
 // v(clamp(x)) is a scatter onto clamp(x): outputs are formed on a grid
 // extended by the PSF radius and the extension is summed onto the border
 // pixels (fold).  Partial sums are reduced in a fixed order (deterministic).
+//
+// Every kernel runs over a batch of equally shaped images at once: blockIdx.z
+// is the image, whose planes sit at fixed strides from the first image's.  A
+// single image is the batch of one.
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -32,6 +37,28 @@ namespace deblur {
 
 constexpr int BW_TW = 64, BW_NT = 256;
 
+// Byte strides from one image of a batch to the next: workspace, image planes
+// (f, dL/du^K, dL/df, dL/du^0), checkpoints.  alpha: the images' regulariser
+// weights (device array; nullptr: the IterParams value).
+struct BwdZ {
+    size_t ws, img, ck;
+    const float* alpha;
+};
+
+// Stage 1 recomputed from a checkpoint: s (raw), (e, W) = (q - W, W).
+template <int RAD, int TH, int NT>
+__global__ void __launch_bounds__(NT) bwd_stage1(const float* __restrict__ u, const float* __restrict__ f,
+                                                 float2* __restrict__ qw, float* __restrict__ s_out, int H, int W,
+                                                 int pitch, const float* __restrict__ pkg, const int* __restrict__ hdr,
+                                                 IterParams p, BwdZ z)
+{
+    __shared__ float tile[stage1_lds_floats<RAD, TH>()];
+    __shared__ float pk[packed_words_max<RAD>()];
+    const int2 t = xcd_tile();
+    stage1_tile<RAD, TH, NT>(tile, pk, zadv(u, z.ck), zadv(f, z.img), zadv(qw, z.ws), zadv(s_out, z.ws), H, W, pitch,
+                             t.x * 64, t.y * TH, zadv(pkg, z.ws), zadv(hdr, z.ws), p);
+}
+
 // ------------------------------------------------ adjoint of the update step
 template <int RAD, int TH>
 __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ qw, const float* __restrict__ u,
@@ -39,10 +66,20 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
                                                     float2* __restrict__ ab, float* __restrict__ cpl,
                                                     float* __restrict__ du, double* __restrict__ alpha_part,
                                                     int H, int W, int pitch, const float* __restrict__ pkg,
-                                                    const int* __restrict__ hdr, IterParams p)
+                                                    const int* __restrict__ hdr, IterParams p, BwdZ z, size_t lam_z)
 {
     constexpr int TW = BW_TW, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (BW_NT / 64);
     constexpr int UW = TW + 4, UH = TH + 4, GW = TW + 2, GH = TH + 2;
+    qw = zadv(qw, z.ws);
+    u = zadv(u, z.ck);
+    lam = zadv(lam, lam_z);
+    ab = zadv(ab, z.ws);
+    cpl = zadv(cpl, z.ws);
+    du = zadv(du, z.ws);
+    alpha_part = zadv(alpha_part, z.ws);
+    pkg = zadv(pkg, z.ws);
+    hdr = zadv(hdr, z.ws);
+    const float alpha = z.alpha ? z.alpha[blockIdx.z] : p.alpha;
     __shared__ float2 qt[LH * LW];
     __shared__ float ut[UH * UW];
     __shared__ float gt[GH * GW];
@@ -93,15 +130,15 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
         // nn.x = N3 = B e (e = q - W), nn.y = N2 = B W
         const float n1 = nn[i].x, n2 = nn[i].y;
         const float dp = fmaxf(D, 0.0f), dm = fminf(D, 0.0f);
-        const float num = n2 + n1 + p.alpha * dp, den = n2 - p.alpha * dm;
+        const float num = n2 + n1 + alpha * dp, den = n2 - alpha * dm;
         const float rho = num / den;
         const float l = lam[(size_t)y * lam_pitch + x];
         const float a = l * up / den;
         const float b = -a * rho;
-        const float bb = -a * ((n1 + p.alpha * D) / den);
+        const float bb = -a * ((n1 + alpha * D) / den);
         const size_t o = (size_t)y * W + x;
         ab[o] = make_float2(a, bb);
-        cpl[o] = p.alpha * ((D > 0.0f ? a : 0.0f) - (D < 0.0f ? b : 0.0f));
+        cpl[o] = alpha * ((D > 0.0f ? a : 0.0f) - (D < 0.0f ? b : 0.0f));
         du[o] = l * rho;
         apart = (double)a * dp - (double)b * dm;
         }
@@ -118,9 +155,14 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
 template <int RAD, int TH, int SIGN, typename T>
 __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, int vpitch, int H, int W, int wrap,
                                                      T* __restrict__ out, int opitch, int oy, int ox, int OH, int OW,
-                                                     const float* __restrict__ pkg, const int* __restrict__ hdr)
+                                                     const float* __restrict__ pkg, const int* __restrict__ hdr,
+                                                     size_t zws)
 {
     constexpr int TW = BW_TW, LW = TW + 2 * RAD, LH = TH + 2 * RAD, R = TH / (BW_NT / 64);
+    v = zadv(v, zws);
+    out = zadv(out, zws);
+    pkg = zadv(pkg, zws);
+    hdr = zadv(hdr, zws);
     __shared__ T vt[LH * LW];
     __shared__ float pk[packed_words_max<RAD>()];
     const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
@@ -184,20 +226,24 @@ DEBLUR_DEV T strided_sum(const T* __restrict__ p, size_t stride, int n)
 
 template <typename T>
 __global__ void __launch_bounds__(256) adj_fold_x(const T* __restrict__ ext, int epitch, int rx, int W,
-                                                  T* __restrict__ tmp)
+                                                  T* __restrict__ tmp, size_t zws)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, zy = blockIdx.y;
     if (x >= W) return;
+    ext = zadv(ext, zws);
+    tmp = zadv(tmp, zws);
     const int lo = x == 0 ? 0 : x + rx, hi = x == W - 1 ? W - 1 + 2 * rx : x + rx;   // extended columns
     tmp[(size_t)zy * W + x] = strided_sum(ext + (size_t)zy * epitch + lo, 1, hi - lo + 1);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) adj_fold_y(const T* __restrict__ tmp, int ry, int H, int W,
-                                                  T* __restrict__ out, int opitch)
+                                                  T* __restrict__ out, int opitch, size_t zws)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= W) return;
+    tmp = zadv(tmp, zws);
+    out = zadv(out, zws);
     const int lo = y == 0 ? 0 : y + ry, hi = y == H - 1 ? H - 1 + 2 * ry : y + ry;   // extended rows
     out[(size_t)y * opitch + x] = strided_sum(tmp + (size_t)lo * W + x, (size_t)W, hi - lo + 1);
 }
@@ -206,10 +252,16 @@ __global__ void __launch_bounds__(256) adj_fold_y(const T* __restrict__ tmp, int
 __global__ void __launch_bounds__(256) adj_point(const float2* __restrict__ dqw, const float2* __restrict__ qw,
                                                  const float* __restrict__ s_raw, const float* __restrict__ f,
                                                  float* __restrict__ grad_f, float* __restrict__ ds, int H, int W,
-                                                 int pitch, IterParams p)
+                                                 int pitch, IterParams p, BwdZ z)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= W) return;
+    dqw = zadv(dqw, z.ws);
+    qw = zadv(qw, z.ws);
+    s_raw = zadv(s_raw, z.ws);
+    f = zadv(f, z.img);
+    grad_f = zadv(grad_f, z.img);
+    ds = zadv(ds, z.ws);
     const size_t o = (size_t)y * W + x, of = (size_t)y * pitch + x;
     const float2 d = dqw[o], v = qw[o];   // d = (B^T a, B^T bb), v = (e, W)
     const float sr = s_raw[o];
@@ -240,9 +292,14 @@ __global__ void __launch_bounds__(256) adj_point(const float2* __restrict__ dqw,
 template <int TH>
 __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int pitch, const float* __restrict__ cpl,
                                                 const float* __restrict__ du, const float* __restrict__ aT,
-                                                float* __restrict__ lam_out, int H, int W, IterParams p)
+                                                float* __restrict__ lam_out, int H, int W, IterParams p, BwdZ z)
 {
     constexpr int TW = BW_TW, UW = TW + 4, UH = TH + 4, GW = TW + 2, GH = TH + 2;
+    u = zadv(u, z.ck);
+    cpl = zadv(cpl, z.ws);
+    du = zadv(du, z.ws);
+    aT = zadv(aT, z.ws);
+    lam_out = zadv(lam_out, z.ws);
     __shared__ float ut[UH * UW], ct[UH * UW];
     __shared__ float gt[GH * GW], dgx[GH * GW], dgy[GH * GW];
     const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
@@ -317,8 +374,13 @@ template <int RAD>
 __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, const float2* __restrict__ qw,
                                                 const float* __restrict__ ds, const float* __restrict__ u,
                                                 int pitch, int H, int W, int ph, int pw, int bc,
-                                                double* __restrict__ part)
+                                                double* __restrict__ part, BwdZ z)
 {
+    ab = zadv(ab, z.ws);
+    qw = zadv(qw, z.ws);
+    ds = zadv(ds, z.ws);
+    u = zadv(u, z.ck);
+    part = zadv(part, z.ws);
     // LW odd: rows of the extended tile start in different LDS banks
     constexpr int TH = DH_TH, TW = 64, XO = RAD + 8, LW = TW + 2 * XO + 1, LH = TH + 2 * RAD;
     constexpr int MAXB = (2 * RAD + 1) * ((2 * RAD + 1 + 7) / 8);   // lag blocks of the largest PSF
@@ -439,9 +501,13 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
 // Fixed-order reduction of the per-workgroup partial sums.
 __global__ void __launch_bounds__(256) adj_reduce(const double* __restrict__ part, int nblocks, int PP,
                                                   const double* __restrict__ alpha_part, int nalpha,
-                                                  double* __restrict__ dh, double* __restrict__ dalpha)
+                                                  double* __restrict__ dh, double* __restrict__ dalpha, size_t zws)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    part = zadv(part, zws);
+    alpha_part = zadv(alpha_part, zws);
+    dh = zadv(dh, zws);
+    dalpha = zadv(dalpha, zws);
     if (t < PP) {
         // fixed order b = 0, 1, ...; eight loads in flight
         double s = 0.0;
@@ -471,34 +537,34 @@ __global__ void __launch_bounds__(256) adj_reduce(const double* __restrict__ par
     }
 }
 
-__global__ void __launch_bounds__(256) fill_zero_f64(double* __restrict__ p, size_t n)
+__global__ void __launch_bounds__(256) fill_zero_f64(double* __restrict__ p, size_t n, size_t zs)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0;
+    if (i < n) zadv(p, zs)[i] = 0.0;
 }
 
-__global__ void __launch_bounds__(256) fill_zero_f32(float* __restrict__ p, int W, int H, int pitch)
+__global__ void __launch_bounds__(256) fill_zero_f32(float* __restrict__ p, int W, int H, int pitch, size_t zs)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    if (x < W) p[(size_t)y * pitch + x] = 0.0f;
+    if (x < W) zadv(p, zs)[(size_t)y * pitch + x] = 0.0f;
 }
 
 __global__ void __launch_bounds__(256) copy_plane(const float* __restrict__ src, int spitch, float* __restrict__ dst,
-                                                  int dpitch, int W)
+                                                  int dpitch, int W, size_t zsrc, size_t zdst)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    if (x < W) dst[(size_t)y * dpitch + x] = src[(size_t)y * spitch + x];
+    if (x < W) zadv(dst, zdst)[(size_t)y * dpitch + x] = zadv(src, zsrc)[(size_t)y * spitch + x];
 }
 
 // -------------------------------------------------------- Wiener adjoint
 // G = lam0 1[u_pre > floor]
 __global__ void __launch_bounds__(256) wiener_mask(const float* __restrict__ lam0, const float* __restrict__ upre,
-                                                   float* __restrict__ G, int W, float floor_)
+                                                   float* __restrict__ G, int W, float floor_, size_t zws)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x < W) {
         const size_t o = (size_t)y * W + x;
-        G[o] = upre[o] > floor_ ? lam0[o] : 0.0f;
+        zadv(G, zws)[o] = zadv(upre, zws)[o] > floor_ ? zadv(lam0, zws)[o] : 0.0f;
     }
 }
 
@@ -506,10 +572,15 @@ __global__ void __launch_bounds__(256) wiener_mask(const float* __restrict__ lam
 // c2 = -conj(h^)^2 / (|h^|^2+K)^2, on the half spectrum (FP64 arithmetic).
 // (Y may alias Fh: each element is read before it is written by the same thread.)
 __global__ void __launch_bounds__(256) wiener_dh_spectrum(const float2* Fh, const float2* __restrict__ Gh,
-                                                          const float2* __restrict__ hh, float2* Y, size_t n, double K)
+                                                          const float2* __restrict__ hh, float2* Y, size_t n, double K,
+                                                          size_t zs)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    Fh = zadv(Fh, zs);
+    Gh = zadv(Gh, zs);
+    hh = zadv(hh, zs);
+    Y = zadv(Y, zs);
     const double fr = Fh[i].x, fi = Fh[i].y, gr = Gh[i].x, gi = Gh[i].y;
     const double zr = fr * gr + fi * gi, zi = fi * gr - fr * gi;   // F conj(G)
     const double hr = hh[i].x, hi = hh[i].y;
@@ -523,19 +594,27 @@ __global__ void __launch_bounds__(256) wiener_dh_spectrum(const float2* Fh, cons
 
 // dh(j, i) += R((j - cy) mod H, (i - cx) mod W)
 __global__ void __launch_bounds__(256) wiener_dh_gather(const float* __restrict__ R, int H, int W, int ph, int pw,
-                                                        double* __restrict__ dh)
+                                                        double* __restrict__ dh, size_t zws)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ph * pw) return;
+    R = zadv(R, zws);
+    dh = zadv(dh, zws);
     const int j = t / pw, i = t - j * pw;
     const int y = ext_index(j - (ph - 1) / 2, H, BC_PERIODIC), x = ext_index(i - (pw - 1) / 2, W, BC_PERIODIC);
     dh[t] += (double)R[(size_t)y * W + x];
 }
 
+// Image z's dL/dh at grad_taps + z PP, its dL/dalpha at grad_alpha + z.
 __global__ void __launch_bounds__(256) write_grads(const double* __restrict__ dh, int PP, const double* __restrict__ da,
-                                                   float* __restrict__ grad_taps, float* __restrict__ grad_alpha)
+                                                   float* __restrict__ grad_taps, float* __restrict__ grad_alpha,
+                                                   size_t zws)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    dh = zadv(dh, zws);
+    da = zadv(da, zws);
+    if (grad_taps) grad_taps += (size_t)blockIdx.z * PP;
+    if (grad_alpha) grad_alpha += blockIdx.z;
     if (grad_taps && t < PP) grad_taps[t] = (float)dh[t];
     if (grad_alpha && t == 0) grad_alpha[0] = (float)da[0];
 }
@@ -604,10 +683,32 @@ size_t backward_ws_bytes(int H, int W, const PsfDev& psf, bool through_wiener)
     return need;
 }
 
+// Stage-1 tile shape of the recomputation: by the tiles of the whole batch
+// (every shape gives the same bits), as the forward picks its default.
+template <int RAD>
+static void launch_bwd_stage1(int B, const float* f, const float* u, float2* qw, float* s, int H, int W, int pitch,
+                              const float* taps, const int* nt, const IterParams& p, const BwdZ& z, hipStream_t st)
+{
+    const long tiles64 = (long)B * ((W + 63) / 64) * ((H + 63) / 64);
+    auto go = [&](auto th, auto ntr) {
+        constexpr int TH = decltype(th)::value, NT = decltype(ntr)::value;
+        const dim3 g((W + 63) / 64, (H + TH - 1) / TH, B);
+        hipLaunchKernelGGL((bwd_stage1<RAD, TH, NT>), g, dim3(NT), 0, st, u, f, qw, s, H, W, pitch, taps, nt, p, z);
+    };
+    if (tiles64 >= 1024)
+        go(std::integral_constant<int, 32>{}, std::integral_constant<int, 256>{});
+    else if (tiles64 >= 256)
+        go(std::integral_constant<int, 32>{}, std::integral_constant<int, 512>{});
+    else
+        go(std::integral_constant<int, 16>{}, std::integral_constant<int, 512>{});
+}
+
+// One reversed iteration for the B images of a batch (lam: dL/du^{k+1} with
+// its pitch and image stride; u: the checkpoints u^k).
 template <int RAD, int TH>
-static void launch_bwd_iter(const float* f, const float* u, const float* lam, int lam_pitch, float* lam_out,
-                            float* grad_f, int H, int W, int pitch, const PsfDev& psf, const IterParams& p,
-                            unsigned char* w8, const BwdLayout& L, hipStream_t st)
+static void launch_bwd_iter(int B, const float* f, const float* u, const float* lam, int lam_pitch, size_t lam_z,
+                            float* lam_out, float* grad_f, int H, int W, int pitch, const PsfDev& psf,
+                            const IterParams& p, unsigned char* w8, const BwdLayout& L, const BwdZ& z, hipStream_t st)
 {
     const float* taps = reinterpret_cast<const float*>(w8 + L.list + tap_packed_offset(psf.ph, psf.pw));
     const int* nt = reinterpret_cast<const int*>(w8 + L.list);
@@ -623,67 +724,82 @@ static void launch_bwd_iter(const float* f, const float* u, const float* lam, in
     double* apart = reinterpret_cast<double*>(w8 + L.apart);
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
     const bool per = p.bc == BC_PERIODIC;
+    const size_t zw = z.ws;
 
-    launch_taps_stage1(f, u, reinterpret_cast<float*>(qw), H, W, pitch, psf, w8 + L.list, p, 0, st, s);
-    const dim3 gi((W + 63) / 64, (H + TH - 1) / TH);
+    launch_bwd_stage1<RAD>(B, f, u, qw, s, H, W, pitch, taps, nt, p, z, st);
+    const dim3 gi((W + 63) / 64, (H + TH - 1) / TH, B);
     hipLaunchKernelGGL((adj_update<RAD, TH>), gi, dim3(BW_NT), 0, st, (const float2*)qw, u, lam, lam_pitch, ab, c,
-                       du, apart, H, W, pitch, taps, nt, p);
+                       du, apart, H, W, pitch, taps, nt, p, z, lam_z);
     // dq, dW = B^T (a, b)
     if (per) {
         hipLaunchKernelGGL((adj_stencil<RAD, TH, -1, float2>), gi, dim3(BW_NT), 0, st, (const float2*)ab, W, H, W, 1,
-                           dqw, W, 0, 0, H, W, taps, nt);
+                           dqw, W, 0, 0, H, W, taps, nt, zw);
     } else {
         float2* ext = reinterpret_cast<float2*>(w8 + L.ext);
         const int EH = H + 2 * cy, EW = W + 2 * cx;
-        const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH);
+        const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH, B);
         hipLaunchKernelGGL((adj_stencil<RAD, TH, -1, float2>), ge, dim3(BW_NT), 0, st, (const float2*)ab, W, H, W, 0,
-                           ext, EW, -cy, -cx, EH, EW, taps, nt);
+                           ext, EW, -cy, -cx, EH, EW, taps, nt, zw);
         float2* tmp = reinterpret_cast<float2*>(w8 + L.fold);
-        hipLaunchKernelGGL(adj_fold_x<float2>, dim3((W + 255) / 256, EH), dim3(256), 0, st, (const float2*)ext, EW, cx,
-                           W, tmp);
-        hipLaunchKernelGGL(adj_fold_y<float2>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float2*)tmp, cy, H,
-                           W, dqw, W);
+        hipLaunchKernelGGL(adj_fold_x<float2>, dim3((W + 255) / 256, EH, B), dim3(256), 0, st, (const float2*)ext, EW,
+                           cx, W, tmp, zw);
+        hipLaunchKernelGGL(adj_fold_y<float2>, dim3((W + 255) / 256, H, B), dim3(256), 0, st, (const float2*)tmp, cy,
+                           H, W, dqw, W, zw);
     }
-    hipLaunchKernelGGL(adj_point, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float2*)dqw, (const float2*)qw,
-                       (const float*)s, f, grad_f, ds, H, W, pitch, p);
+    hipLaunchKernelGGL(adj_point, dim3((W + 255) / 256, H, B), dim3(256), 0, st, (const float2*)dqw,
+                       (const float2*)qw, (const float*)s, f, grad_f, ds, H, W, pitch, p, z);
     // A^T ds
     if (per) {
         hipLaunchKernelGGL((adj_stencil<RAD, TH, 1, float>), gi, dim3(BW_NT), 0, st, (const float*)ds, W, H, W, 1, aT,
-                           W, 0, 0, H, W, taps, nt);
+                           W, 0, 0, H, W, taps, nt, zw);
     } else {
         float* ext = reinterpret_cast<float*>(w8 + L.ext);
         const int EH = H + 2 * cy, EW = W + 2 * cx;
-        const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH);
+        const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH, B);
         hipLaunchKernelGGL((adj_stencil<RAD, TH, 1, float>), ge, dim3(BW_NT), 0, st, (const float*)ds, W, H, W, 0, ext,
-                           EW, -cy, -cx, EH, EW, taps, nt);
+                           EW, -cy, -cx, EH, EW, taps, nt, zw);
         float* tmp = reinterpret_cast<float*>(w8 + L.fold);
-        hipLaunchKernelGGL(adj_fold_x<float>, dim3((W + 255) / 256, EH), dim3(256), 0, st, (const float*)ext, EW, cx, W,
-                           tmp);
-        hipLaunchKernelGGL(adj_fold_y<float>, dim3((W + 255) / 256, H), dim3(256), 0, st, (const float*)tmp, cy, H, W,
-                           aT, W);
+        hipLaunchKernelGGL(adj_fold_x<float>, dim3((W + 255) / 256, EH, B), dim3(256), 0, st, (const float*)ext, EW, cx,
+                           W, tmp, zw);
+        hipLaunchKernelGGL(adj_fold_y<float>, dim3((W + 255) / 256, H, B), dim3(256), 0, st, (const float*)tmp, cy, H,
+                           W, aT, W, zw);
     }
-    hipLaunchKernelGGL((adj_tv<TH>), dim3((W + 63) / 64, (H + TH - 1) / TH), dim3(BW_NT), 0, st, u, pitch,
-                       (const float*)c, (const float*)du, (const float*)aT, lam_out, H, W, p);
-    hipLaunchKernelGGL((adj_dh<RAD>), dim3((W + 63) / 64, (H + DH_TH - 1) / DH_TH), dim3(BW_NT), 0, st, (const float2*)ab,
-                       (const float2*)qw, (const float*)ds, u, pitch, H, W, psf.ph, psf.pw, p.bc, part);
+    hipLaunchKernelGGL((adj_tv<TH>), dim3((W + 63) / 64, (H + TH - 1) / TH, B), dim3(BW_NT), 0, st, u, pitch,
+                       (const float*)c, (const float*)du, (const float*)aT, lam_out, H, W, p, z);
+    hipLaunchKernelGGL((adj_dh<RAD>), dim3((W + 63) / 64, (H + DH_TH - 1) / DH_TH, B), dim3(BW_NT), 0, st,
+                       (const float2*)ab, (const float2*)qw, (const float*)ds, u, pitch, H, W, psf.ph, psf.pw, p.bc,
+                       part, z);
 }
 
 template <int RAD>
-static void launch_bwd_iter_th(int th, const float* f, const float* u, const float* lam, int lam_pitch,
-                               float* lam_out, float* grad_f, int H, int W, int pitch, const PsfDev& psf,
-                               const IterParams& p, unsigned char* w8, const BwdLayout& L, hipStream_t st)
+static void launch_bwd_iter_th(int th, int B, const float* f, const float* u, const float* lam, int lam_pitch,
+                               size_t lam_z, float* lam_out, float* grad_f, int H, int W, int pitch,
+                               const PsfDev& psf, const IterParams& p, unsigned char* w8, const BwdLayout& L,
+                               const BwdZ& z, hipStream_t st)
 {
     switch (th) {
-        case 4: launch_bwd_iter<RAD, 4>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
-        case 16: launch_bwd_iter<RAD, 16>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
-        default: launch_bwd_iter<RAD, 8>(f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+        case 4:
+            launch_bwd_iter<RAD, 4>(B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
+            break;
+        case 16:
+            launch_bwd_iter<RAD, 16>(B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
+            break;
+        default:
+            launch_bwd_iter<RAD, 8>(B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
+            break;
     }
 }
 
-int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int H, int W, int pitch,
-                         const PsfDev& psf, const IterParams& p, int iters, bool through_wiener, double K,
-                         float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0,
-                         void* ws, hipStream_t st)
+size_t backward_batch_stride(int H, int W, const PsfDev& psf, bool through_wiener)
+{
+    return r256(backward_ws_bytes(H, W, psf, through_wiener));
+}
+
+int launch_rrrl_backward_batch(int B, const float* f, const float* ckpt, const float* grad_uK, int H, int W,
+                               int pitch, size_t img_stride, size_t ck_stride, const PsfDev& psf, size_t taps_stride,
+                               const float* alpha, const IterParams& p, int iters, bool through_wiener, double K,
+                               float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0,
+                               void* ws, size_t ws_stride, hipStream_t st)
 {
     const int rad = bwd_rad(psf);
     if (rad < 0) return -2;
@@ -691,6 +807,8 @@ int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
     const BwdLayout L = bwd_layout(H, W, psf);
     const int PP = psf.ph * psf.pw;
     const int th = bwd_th(p);
+    const BwdZ z{ws_stride, img_stride, ck_stride, alpha};
+    const size_t zw = ws_stride;
     const size_t nb_it = (size_t)((W + 63) / 64) * H;
     const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + DH_TH - 1) / DH_TH);
     double* part = reinterpret_cast<double*>(w8 + L.part);
@@ -700,36 +818,48 @@ int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
     float* lamA = reinterpret_cast<float*>(w8 + L.lamA);
     float* lamB = reinterpret_cast<float*>(w8 + L.lamB);
 
-    launch_compile_taps(psf, w8 + L.list, st);
-    hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((nb_dh * PP + 255) / 256)), dim3(256), 0, st, part,
-                       nb_dh * PP);
-    hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((nb_it + 255) / 256)), dim3(256), 0, st, apart, nb_it);
-    hipLaunchKernelGGL(fill_zero_f32, dim3((W + 255) / 256, H), dim3(256), 0, st, grad_f, W, H, pitch);
+    launch_compile_taps(psf, w8 + L.list, st, ZBatch{B, taps_stride, zw});
+    hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((nb_dh * PP + 255) / 256), 1, B), dim3(256), 0, st, part,
+                       nb_dh * PP, zw);
+    hipLaunchKernelGGL(fill_zero_f64, dim3((unsigned)((nb_it + 255) / 256), 1, B), dim3(256), 0, st, apart, nb_it, zw);
+    hipLaunchKernelGGL(fill_zero_f32, dim3((W + 255) / 256, H, B), dim3(256), 0, st, grad_f, W, H, pitch, img_stride);
 
     const float* lam = grad_uK;
     int lam_pitch = pitch;
+    size_t lam_z = img_stride;
     for (int k = iters - 1; k >= 0; --k) {
         float* lam_out = (k % 2 == 0) ? lamA : lamB;
         const float* u = ckpt + (size_t)k * H * pitch;
         switch (rad) {
-            case 4: launch_bwd_iter_th<4>(th, f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
-            case 8: launch_bwd_iter_th<8>(th, f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
-            case 16: launch_bwd_iter_th<16>(th, f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
-            default: launch_bwd_iter_th<32>(th, f, u, lam, lam_pitch, lam_out, grad_f, H, W, pitch, psf, p, w8, L, st); break;
+            case 4:
+                launch_bwd_iter_th<4>(th, B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
+                break;
+            case 8:
+                launch_bwd_iter_th<8>(th, B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
+                break;
+            case 16:
+                launch_bwd_iter_th<16>(th, B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
+                break;
+            default:
+                launch_bwd_iter_th<32>(th, B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
+                break;
         }
         lam = lam_out;
         lam_pitch = W;
+        lam_z = zw;
     }
-    hipLaunchKernelGGL(adj_reduce, dim3((PP + 255) / 256), dim3(256), 0, st, (const double*)part, (int)nb_dh, PP,
-                       (const double*)apart, (int)nb_it, dh, da);
+    hipLaunchKernelGGL(adj_reduce, dim3((PP + 255) / 256, 1, B), dim3(256), 0, st, (const double*)part, (int)nb_dh, PP,
+                       (const double*)apart, (int)nb_it, dh, da, zw);
     if (iters == 0) {
         // no iteration: lam0 = grad_uK, dalpha = 0 (apart zeroed)
-        hipLaunchKernelGGL(copy_plane, dim3((W + 255) / 256, H), dim3(256), 0, st, grad_uK, pitch, lamA, W, W);
+        hipLaunchKernelGGL(copy_plane, dim3((W + 255) / 256, H, B), dim3(256), 0, st, grad_uK, pitch, lamA, W, W,
+                           img_stride, zw);
         lam = lamA;
     }
-    // lam now holds dL/du^0 (dense, pitch W)
+    // lam now holds dL/du^0 (dense, pitch W, in each image's workspace)
     if (grad_u0)
-        hipLaunchKernelGGL(copy_plane, dim3((W + 255) / 256, H), dim3(256), 0, st, lam, W, grad_u0, pitch, W);
+        hipLaunchKernelGGL(copy_plane, dim3((W + 255) / 256, H, B), dim3(256), 0, st, lam, W, grad_u0, pitch, W, zw,
+                           img_stride);
     if (through_wiener) {
         const size_t half = r256((size_t)H * (W / 2 + 1) * 8), pl = r256((size_t)H * W * 4);
         unsigned char* wb = w8 + L.total;
@@ -742,29 +872,39 @@ int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
         float* R = reinterpret_cast<float*>(wb + 4 * half + 2 * pl);
         const size_t nh = (size_t)H * (W / 2 + 1);
         // M, h^; F^ = DFT(f); u_pre = IDFT(F^ M) (no floor); G = lam0 1[u_pre > floor]
-        launch_wiener_mult(psf, H, W, K, M, hh, st);
-        launch_fft2_forward(f, pitch, H, W, Sa, st);
-        launch_spectral_mul(Sa, M, false, Sb, nh, st);
-        launch_fft2_inverse(Sb, H, W, upre, W, -INFINITY, false, st);
-        hipLaunchKernelGGL(wiener_mask, dim3((W + 255) / 256, H), dim3(256), 0, st, lam, (const float*)upre, G, W,
-                           pos_floor);
-        launch_fft2_forward(G, W, H, W, Sb, st);                     // Sb = G^
-        launch_wiener_dh_prep(Sa, Sb, hh, Sa, nh, K, st);            // Sa <- Y
-        launch_spectral_mul(Sb, M, true, Sb, nh, st);                // dL/df += IDFT(G^ conj M)
-        launch_fft2_inverse(Sb, H, W, grad_f, pitch, 0.0f, true, st);
-        launch_fft2_inverse(Sa, H, W, R, W, -INFINITY, false, st);   // R = IDFT(Y)
-        hipLaunchKernelGGL(wiener_dh_gather, dim3((PP + 255) / 256), dim3(256), 0, st, (const float*)R, H, W, psf.ph,
-                           psf.pw, dh);
+        launch_wiener_mult(psf, H, W, K, M, hh, st, ZBatch{B, taps_stride, zw, zw});
+        launch_fft2_forward(f, pitch, H, W, Sa, st, ZBatch{B, img_stride, zw});
+        launch_spectral_mul(Sa, M, false, Sb, nh, st, ZBatch{B, zw, zw, zw});
+        launch_fft2_inverse(Sb, H, W, upre, W, -INFINITY, false, st, ZBatch{B, zw, zw});
+        hipLaunchKernelGGL(wiener_mask, dim3((W + 255) / 256, H, B), dim3(256), 0, st, lam, (const float*)upre, G, W,
+                           pos_floor, zw);
+        launch_fft2_forward(G, W, H, W, Sb, st, ZBatch{B, zw, zw});                   // Sb = G^
+        launch_wiener_dh_prep(Sa, Sb, hh, Sa, nh, K, st, ZBatch{B, zw});              // Sa <- Y
+        launch_spectral_mul(Sb, M, true, Sb, nh, st, ZBatch{B, zw, zw, zw});          // dL/df += IDFT(G^ conj M)
+        launch_fft2_inverse(Sb, H, W, grad_f, pitch, 0.0f, true, st, ZBatch{B, zw, img_stride});
+        launch_fft2_inverse(Sa, H, W, R, W, -INFINITY, false, st, ZBatch{B, zw, zw});  // R = IDFT(Y)
+        hipLaunchKernelGGL(wiener_dh_gather, dim3((PP + 255) / 256, 1, B), dim3(256), 0, st, (const float*)R, H, W,
+                           psf.ph, psf.pw, dh, zw);
     }
-    hipLaunchKernelGGL(write_grads, dim3((PP + 255) / 256), dim3(256), 0, st, (const double*)dh, PP,
-                       (const double*)da, grad_taps, grad_alpha);
+    hipLaunchKernelGGL(write_grads, dim3((PP + 255) / 256, 1, B), dim3(256), 0, st, (const double*)dh, PP,
+                       (const double*)da, grad_taps, grad_alpha, zw);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
-void launch_wiener_dh_prep(const float2* Fh, const float2* Gh, const float2* hh, float2* Y, size_t n, double K,
-                           hipStream_t st)
+int launch_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int H, int W, int pitch,
+                         const PsfDev& psf, const IterParams& p, int iters, bool through_wiener, double K,
+                         float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha, float* grad_u0,
+                         void* ws, hipStream_t st)
 {
-    hipLaunchKernelGGL(wiener_dh_spectrum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Fh, Gh, hh, Y, n, K);
+    return launch_rrrl_backward_batch(1, f, ckpt, grad_uK, H, W, pitch, 0, 0, psf, 0, nullptr, p, iters,
+                                      through_wiener, K, pos_floor, grad_f, grad_taps, grad_alpha, grad_u0, ws, 0, st);
+}
+
+void launch_wiener_dh_prep(const float2* Fh, const float2* Gh, const float2* hh, float2* Y, size_t n, double K,
+                           hipStream_t st, ZBatch zb)
+{
+    hipLaunchKernelGGL(wiener_dh_spectrum, dim3((unsigned)((n + 255) / 256), 1, zb.n), dim3(256), 0, st, Fh, Gh, hh, Y,
+                       n, K, zb.s0);
 }
 
 }  // namespace deblur

@@ -56,8 +56,14 @@ DEBLUR_DEV void block_scan256(int (&v)[N], int (*tot)[N])
 // Single workgroup of 256 threads (pw <= 256).
 __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restrict__ list,
                                                       TapGroup* __restrict__ groups, float* __restrict__ packed,
-                                                      int* __restrict__ hdr)
+                                                      int* __restrict__ hdr, size_t zt, size_t zl)
 {
+    // blockIdx.z = PSF of a batch (byte strides of the taps and of the lists)
+    if (psf.taps) psf.taps = zadv(psf.taps, zt);
+    list = zadv(list, zl);
+    groups = zadv(groups, zl);
+    packed = zadv(packed, zl);
+    hdr = zadv(hdr, zl);
     __shared__ int tot1[4][1], tot8[4][TAP_GROUP_MAX];
     __shared__ int cls_base[TAP_GROUP_MAX], word_base[TAP_GROUP_MAX];
     __shared__ float hs[65 * 65];             // the PSF array (ph, pw <= 65)
@@ -268,12 +274,13 @@ size_t tap_list_bytes(const PsfDev& psf)
     return tap_packed_offset(psf.ph, psf.pw) + 4 * 2 * P;
 }
 
-void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st)
+void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st, ZBatch zb)
 {
     unsigned char* w8 = reinterpret_cast<unsigned char*>(list);
-    hipLaunchKernelGGL(build_tap_list, dim3(1), dim3(256), 0, st, psf, reinterpret_cast<int4*>(w8 + 256),
+    hipLaunchKernelGGL(build_tap_list, dim3(1, 1, zb.n), dim3(256), 0, st, psf, reinterpret_cast<int4*>(w8 + 256),
                        reinterpret_cast<TapGroup*>(w8 + tap_groups_offset(psf.ph, psf.pw)),
-                       reinterpret_cast<float*>(w8 + tap_packed_offset(psf.ph, psf.pw)), reinterpret_cast<int*>(w8));
+                       reinterpret_cast<float*>(w8 + tap_packed_offset(psf.ph, psf.pw)), reinterpret_cast<int*>(w8),
+                       zb.s0, zb.s1);
 }
 
 static int psf_radius_class(const PsfDev& psf)

@@ -239,17 +239,20 @@ DEBLUR_DEV void mult_2d_block(const PsfDev& psf, int H, int W, double K, C* __re
     }
 }
 
+// blockIdx.z = image of a batch (strides of the taps, M and h^ in bytes)
 __global__ void __launch_bounds__(256) wiener_mult_2d(PsfDev psf, int H, int W, double K, float2* __restrict__ M,
-                                                      float2* __restrict__ hh)
+                                                      float2* __restrict__ hh, size_t zt, size_t zm, size_t zh)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    mult_2d_block<float2>(psf, H, W, K, M, hh, blockIdx.x, blockIdx.y, smem_raw);
+    if (psf.taps) psf.taps = zadv(psf.taps, zt);
+    mult_2d_block<float2>(psf, H, W, K, zadv(M, zm), hh ? zadv(hh, zh) : nullptr, blockIdx.x, blockIdx.y, smem_raw);
 }
 
-static void mult_2d_launch(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
+static void mult_2d_launch(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st,
+                           ZBatch zb)
 {
-    const dim3 grid((W / 2 + 1 + MULT_KX - 1) / MULT_KX, (H + MULT_KY - 1) / MULT_KY);
-    hipLaunchKernelGGL(wiener_mult_2d, grid, dim3(256), MULT_SMEM, st, psf, H, W, K, M, hh);
+    const dim3 grid((W / 2 + 1 + MULT_KX - 1) / MULT_KX, (H + MULT_KY - 1) / MULT_KY, zb.n);
+    hipLaunchKernelGGL(wiener_mult_2d, grid, dim3(256), MULT_SMEM, st, psf, H, W, K, M, hh, zb.s0, zb.s1, zb.s2);
 }
 
 // Row pass: rows (2p, 2p+1) packed as z = f_a + i f_b, FFT along x, unpacked
@@ -288,10 +291,11 @@ DEBLUR_DEV void rows_fwd_block(const float* __restrict__ f, C* __restrict__ S, i
 
 template <typename C>
 __global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__ f, C* __restrict__ S,
-                                                       int H, int W, int pitch, int nb, FftPlan plan)
+                                                       int H, int W, int pitch, int nb, FftPlan plan, size_t zf,
+                                                       size_t zs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    rows_fwd_block(f, S, H, W, pitch, nb, plan, blockIdx.x, smem_raw);
+    rows_fwd_block(zadv(f, zf), zadv(S, zs), H, W, pitch, nb, plan, blockIdx.x, smem_raw);
 }
 
 // The row pass of f and the multiplier M in one launch: they are independent,
@@ -381,19 +385,24 @@ DEBLUR_DEV void cols_block(C* __restrict__ S, const C* __restrict__ M, int H, in
 // columns, which share cache lines of S).
 template <typename C>
 __global__ void __launch_bounds__(256) wiener_cols(C* __restrict__ S, const C* __restrict__ M,
-                                                   int H, int W, int cb, FftPlan plan, int mode, int conjM)
+                                                   int H, int W, int cb, FftPlan plan, int mode, int conjM,
+                                                   size_t zs, size_t zm)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cols_block<C>(S, M, H, W, cb, plan, mode, conjM, xcd_group(blockIdx.x, gridDim.x), smem_raw);
+    cols_block<C>(zadv(S, zs), M ? zadv(M, zm) : nullptr, H, W, cb, plan, mode, conjM,
+                  xcd_group(blockIdx.x, gridDim.x), smem_raw);
 }
 
 // S_out = S_in * M (or conj M), elementwise on the half spectrum (S_out may
 // alias S_in).
 __global__ void __launch_bounds__(256) spectral_mul(const float2* Sin, const float2* __restrict__ M, int conjM,
-                                                    float2* Sout, size_t n)
+                                                    float2* Sout, size_t n, size_t z0, size_t z1, size_t z2)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    Sin = zadv(Sin, z0);
+    M = zadv(M, z1);
+    Sout = zadv(Sout, z2);
     const float2 m = conjM ? cconj(M[i]) : M[i];
     Sout[i] = cmul(Sin[i], m);
 }
@@ -447,10 +456,10 @@ DEBLUR_DEV void rows_inv_block(const C* __restrict__ S, float* __restrict__ u, i
 template <typename C>
 __global__ void __launch_bounds__(256) wiener_rows_inv(const C* __restrict__ S, float* __restrict__ u,
                                                        int H, int W, int pitch, int nb, FftPlan plan,
-                                                       float pos_floor, int accumulate)
+                                                       float pos_floor, int accumulate, size_t zs, size_t zu)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    rows_inv_block<C>(S, u, H, W, pitch, nb, plan, pos_floor, accumulate, blockIdx.x, smem_raw);
+    rows_inv_block<C>(zadv(S, zs), zadv(u, zu), H, W, pitch, nb, plan, pos_floor, accumulate, blockIdx.x, smem_raw);
 }
 
 // ------------------------------------------------- batched form (FP32)
@@ -584,9 +593,9 @@ static int launch_wiener_t(const float* f, float* u, int H, int W, int pitch, co
         const int cb = col_batch(H);
         const size_t lds_c = (size_t)(H + 2 * cb * H) * sizeof(C);
         hipLaunchKernelGGL(wiener_cols<C>, dim3((Wh + cb - 1) / cb), dim3(256), lds_c, st, S, (const C*)M,
-                           H, W, cb, make_plan(H), 0, 0);
+                           H, W, cb, make_plan(H), 0, 0, (size_t)0, (size_t)0);
         hipLaunchKernelGGL(wiener_rows_inv<C>, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st,
-                           (const C*)S, u, H, W, pitch, nb, make_plan(W), pos_floor, 0);
+                           (const C*)S, u, H, W, pitch, nb, make_plan(W), pos_floor, 0, (size_t)0, (size_t)0);
     }
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
@@ -628,48 +637,51 @@ int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDe
 
 int fft_row_batch(int W) { return row_batch(W); }
 
-void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st)
+void launch_wiener_mult(const PsfDev& psf, int H, int W, double K, float2* M, float2* hh, hipStream_t st,
+                        ZBatch zb)
 {
-    mult_2d_launch(psf, H, W, K, M, hh, st);
+    mult_2d_launch(psf, H, W, K, M, hh, st, zb);
 }
 
-void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st)
+void launch_fft2_forward(const float* x, int pitch, int H, int W, float2* S, hipStream_t st, ZBatch zb)
 {
     const int nb = row_batch(W), cb = col_batch(H), Wh = W / 2 + 1, pairs = (H + 1) / 2;
-    hipLaunchKernelGGL(wiener_rows_fwd<float2>, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st, x,
-                       S, H, W, pitch, nb, make_plan(W));
-    hipLaunchKernelGGL(wiener_cols<float2>, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S,
-                       (const float2*)nullptr, H, W, cb, make_plan(H), 1, 0);
+    hipLaunchKernelGGL(wiener_rows_fwd<float2>, dim3((pairs + nb - 1) / nb, 1, zb.n), dim3(256),
+                       (size_t)(W + 2 * nb * W) * 8, st, x, S, H, W, pitch, nb, make_plan(W), zb.s0, zb.s1);
+    hipLaunchKernelGGL(wiener_cols<float2>, dim3((Wh + cb - 1) / cb, 1, zb.n), dim3(256), (size_t)(H + 2 * cb * H) * 8,
+                       st, S, (const float2*)nullptr, H, W, cb, make_plan(H), 1, 0, zb.s1, (size_t)0);
 }
 
 void launch_fft2_inverse(float2* S, int H, int W, float* out, int pitch, float floor_, bool accumulate,
-                         hipStream_t st)
+                         hipStream_t st, ZBatch zb)
 {
     const int nb = row_batch(W), cb = col_batch(H), Wh = W / 2 + 1, pairs = (H + 1) / 2;
-    hipLaunchKernelGGL(wiener_cols<float2>, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S,
-                       (const float2*)nullptr, H, W, cb, make_plan(H), 2, 0);
-    hipLaunchKernelGGL(wiener_rows_inv<float2>, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st,
-                       (const float2*)S, out, H, W, pitch, nb, make_plan(W), floor_, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(wiener_cols<float2>, dim3((Wh + cb - 1) / cb, 1, zb.n), dim3(256), (size_t)(H + 2 * cb * H) * 8,
+                       st, S, (const float2*)nullptr, H, W, cb, make_plan(H), 2, 0, zb.s0, (size_t)0);
+    hipLaunchKernelGGL(wiener_rows_inv<float2>, dim3((pairs + nb - 1) / nb, 1, zb.n), dim3(256),
+                       (size_t)(W + 2 * nb * W) * 8, st, (const float2*)S, out, H, W, pitch, nb, make_plan(W), floor_,
+                       accumulate ? 1 : 0, zb.s0, zb.s1);
 }
 
 void launch_rows_fwd(const float* x, int pitch, int H, int W, float2* S, hipStream_t st)
 {
     const int nb = row_batch(W), pairs = (H + 1) / 2;
     hipLaunchKernelGGL(wiener_rows_fwd<float2>, dim3((pairs + nb - 1) / nb), dim3(256), (size_t)(W + 2 * nb * W) * 8, st, x,
-                       S, H, W, pitch, nb, make_plan(W));
+                       S, H, W, pitch, nb, make_plan(W), (size_t)0, (size_t)0);
 }
 
 void launch_cols(float2* S, const float2* mult, bool conj_mult, int mode, int H, int W, hipStream_t st)
 {
     const int cb = col_batch(H), Wh = W / 2 + 1;
     hipLaunchKernelGGL(wiener_cols<float2>, dim3((Wh + cb - 1) / cb), dim3(256), (size_t)(H + 2 * cb * H) * 8, st, S, mult, H,
-                       W, cb, make_plan(H), mode, conj_mult ? 1 : 0);
+                       W, cb, make_plan(H), mode, conj_mult ? 1 : 0, (size_t)0, (size_t)0);
 }
 
-void launch_spectral_mul(const float2* Sin, const float2* M, bool conjM, float2* Sout, size_t n, hipStream_t st)
+void launch_spectral_mul(const float2* Sin, const float2* M, bool conjM, float2* Sout, size_t n, hipStream_t st,
+                         ZBatch zb)
 {
-    hipLaunchKernelGGL(spectral_mul, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Sin, M, conjM ? 1 : 0,
-                       Sout, n);
+    hipLaunchKernelGGL(spectral_mul, dim3((unsigned)((n + 255) / 256), 1, zb.n), dim3(256), 0, st, Sin, M,
+                       conjM ? 1 : 0, Sout, n, zb.s0, zb.s1, zb.s2);
 }
 
 }  // namespace deblur

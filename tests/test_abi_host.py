@@ -249,3 +249,36 @@ def test_backward_validation(lib):
     assert bw() == _lib.DEBLUR_EWORKSPACE
     assert lib.deblur_workspace_bytes(3, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p)) > \
         lib.deblur_workspace_bytes(2, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p)) > 0
+
+
+def test_backward_batch_validation(lib):
+    E = _lib.DEBLUR_EINVAL
+    p = params(iters=2)
+    img = 64 * 64
+
+    def bb(B=4, f=F, ck=CK, g=V, H=64, W=64, pitch=64, istr=img, cstr=2 * img, psf=None, tstr=25, tw=1, K=0.01,
+           gf=0x58000000, ws=None, wsb=0, pp=None):
+        psf = psf if psf is not None else taps(5, 5)
+        return lib.deblur_rrrl_backward_batch(B, f, ck, g, H, W, pitch, istr, cstr, ctypes.byref(psf), tstr, None,
+                                              ctypes.byref(pp or p), tw, K, 1.0, gf, None, None, None, ws, wsb, None)
+    assert bb(B=0) == E
+    assert bb(B=65536) == E
+    assert bb(f=None) == E
+    assert bb(gf=None) == E
+    assert bb(ck=None) == E                      # iters > 0 needs checkpoints
+    assert bb(tw=2) == E
+    assert bb(K=0.0) == E
+    assert bb(istr=img - 1) == E                 # images would overlap
+    assert bb(cstr=2 * img - 1) == E             # checkpoints of consecutive images would overlap
+    assert bb(tstr=24) == E                      # PSFs would overlap
+    assert bb(psf=box(), tstr=1) == E            # box PSFs are shared: stride 0
+    assert bb(gf=F + 4 * 3 * img) == E           # grad_f overlaps image 3 of f
+    assert bb(H=100) == _lib.DEBLUR_EUNSUPPORTED  # through the Wiener step: 2^a 3^b
+    assert bb() == _lib.DEBLUR_EWORKSPACE
+    assert bb(tstr=0) == _lib.DEBLUR_EWORKSPACE   # one shared PSF is valid
+    one = lib.deblur_workspace_bytes(3, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p))
+    four = lib.deblur_backward_batch_workspace_bytes(4, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p), 1)
+    assert four >= 4 * one and four % 4 == 0
+    assert bb(ws=WS, wsb=four - 1) == _lib.DEBLUR_EWORKSPACE
+    assert lib.deblur_backward_batch_workspace_bytes(0, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p), 1) == 0
+    assert lib.deblur_backward_batch_workspace_bytes(4, 64, 64, 64, ctypes.byref(taps(5, 5)), None, 1) == 0
