@@ -111,9 +111,10 @@ typedef struct {
                         interpolation, the tangent at 65 beyond.  The first call with rf_lut = 1 on a
                         device allocates and uploads the 16 KB table (keep that call out of graph
                         capture); the backward pass rejects it (DEBLUR_EUNSUPPORTED). */
-    int32_t bwd_tile;/* tile rows of deblur_rrrl_backward's iteration kernels: 0 = default (8),
-                        1 = 8, 2 = 4, 3 = 16 rows of 64 columns (an autotuner's choice; all give
-                        bitwise-identical gradients); ignored by the forward entry points; else
+    int32_t bwd_tile;/* tile rows of the backward's iteration kernels: 0 = default (8 rows, 16
+                        when a launch over the batch holds at least 8192 tiles of 16 rows),
+                        1 = 8, 2 = 4, 3 = 16, 4 = 32 rows of 64 columns (an autotuner's choice; all
+                        give bitwise-identical gradients); ignored by the forward entry points; else
                         DEBLUR_EINVAL */
 } deblur_params;
 

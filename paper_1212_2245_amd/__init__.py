@@ -81,7 +81,7 @@ class Params:
     tile: int = 0
     psi: int = PSI_TV   # regulariser: PSI_TV, or PSI_PERONA_MALIK (non-convex, lambda = eps_tv)
     rf_lut: bool = False  # r_f through the lookup table of Sec. 4.1 instead of exactly
-    bwd_tile: int = 0   # tile rows of the backward kernels: 0 default (8), 1: 8, 2: 4, 3: 16
+    bwd_tile: int = 0   # tile rows of the backward kernels: 0 default (by batch size), 1: 8, 2: 4, 3: 16, 4: 32
 
     def c(self) -> _lib.deblur_params:
         return _lib.deblur_params(self.alpha, self.eps_data, self.eps_tv, self.s_min, int(self.iters),

@@ -630,11 +630,25 @@ struct BwdLayout {
 static int bwd_rad(const PsfDev& psf) { return tap_radius_class(max((psf.ph - 1) / 2, (psf.pw - 1) / 2)); }
 
 // Rows per tile of the backward iteration kernels, by bwd_tile variant:
-// 0/1: 8 (the default: at 512^2, 512 workgroups, two per CU), 2: 4, 3: 16.
-// The results do not depend on it (per-pixel sums in tap order; the
+// 1: 8, 2: 4, 3: 16, 4: 32.  The default (0) goes by the workgroups of one
+// launch over the batch: 8 rows while 16-row tiles would leave fewer than
+// 8192 (a single 512^2 image: 512 workgroups of 8 rows, two per CU), else 16
+// (a batch of 512^2 images: the halo rows of the radius are re-read less
+// often).  The results do not depend on it (per-pixel sums in tap order; the
 // dL/dalpha partial sums are per image row).
-constexpr int BWD_VARIANTS = 3;
-static int bwd_th(const IterParams& p) { return p.bwd_tile == 2 ? 4 : (p.bwd_tile == 3 ? 16 : 8); }
+constexpr int BWD_VARIANTS = 4;
+static int bwd_th(const IterParams& p, int B, int H, int W)
+{
+    switch (p.bwd_tile) {
+        case 1: return 8;
+        case 2: return 4;
+        case 3: return 16;
+        case 4: return 32;
+        default: break;
+    }
+    const long tiles16 = (long)B * ((H + 15) / 16) * ((W + 63) / 64);
+    return tiles16 >= 8192 ? 16 : 8;
+}
 int backward_tile_variants() { return BWD_VARIANTS; }
 
 static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
@@ -784,6 +798,9 @@ static void launch_bwd_iter_th(int th, int B, const float* f, const float* u, co
         case 16:
             launch_bwd_iter<RAD, 16>(B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
             break;
+        case 32:
+            launch_bwd_iter<RAD, 32>(B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
+            break;
         default:
             launch_bwd_iter<RAD, 8>(B, f, u, lam, lam_pitch, lam_z, lam_out, grad_f, H, W, pitch, psf, p, w8, L, z, st);
             break;
@@ -806,7 +823,7 @@ int launch_rrrl_backward_batch(int B, const float* f, const float* ckpt, const f
     unsigned char* w8 = reinterpret_cast<unsigned char*>(ws);
     const BwdLayout L = bwd_layout(H, W, psf);
     const int PP = psf.ph * psf.pw;
-    const int th = bwd_th(p);
+    const int th = bwd_th(p, B, H, W);
     const BwdZ z{ws_stride, img_stride, ck_stride, alpha};
     const size_t zw = ws_stride;
     const size_t nb_it = (size_t)((W + 63) / 64) * H;

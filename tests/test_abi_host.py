@@ -201,8 +201,8 @@ def test_batch_validation(lib):
 
 
 def test_backward_tile_validation(lib):
-    assert lib.deblur_backward_tile_variants() == 3
-    assert iterate(lib, p=params(bwd_tile=4)) == _lib.DEBLUR_EINVAL
+    assert lib.deblur_backward_tile_variants() == 4
+    assert iterate(lib, p=params(bwd_tile=5)) == _lib.DEBLUR_EINVAL
     assert iterate(lib, p=params(bwd_tile=-1)) == _lib.DEBLUR_EINVAL
 
 

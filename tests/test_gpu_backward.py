@@ -360,7 +360,7 @@ def test_backward_tile_rows_bitwise(bc):
     (radius class 16)."""
     rng = np.random.default_rng(7)
     n = dbl._lib.load().deblur_backward_tile_variants()
-    assert n == 3
+    assert n == 4
     for H, W, h, tw in ((36, 72, synth.random_psf(rng, 5, 7), False), (48, 96, synth.line_psf(21, 0.4), True)):
         f = rng.uniform(0.0, 255.0, (H, W))
         g = rng.uniform(0.0, 255.0, (H, W))
