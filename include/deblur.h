@@ -141,6 +141,14 @@ int deblur_backward_tile_variants(void);
 size_t deblur_workspace_bytes(int32_t op, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
                               const deblur_params* p);
 
+/* Workspace bytes of the batched entry points (deblur_wiener_batch,
+ * deblur_rrrl_iterate_batch, deblur_rrrl_backward_batch) for B images: op as
+ * deblur_workspace_bytes; B per-image workspaces, each rounded up to 256
+ * bytes.  0 for invalid arguments, B outside 1..65535, or op 1 with the
+ * Fourier-domain iteration (which has no batched form). */
+size_t deblur_workspace_bytes_batch(int32_t op, int32_t B, int32_t H, int32_t W, int32_t pitch,
+                                    const deblur_psf* psf, const deblur_params* p);
+
 /* Wiener initialisation of WR3L (Sec. 2.1 eq. (2); Sec. 3.2):
  *   u0 = max( Re IDFT( DFT(f) conj(h^) / (|h^|^2 + K) ), pos_floor )
  * with h^ the DFT of the PSF centred at index (0,0), periodic continuation.
@@ -161,6 +169,18 @@ int deblur_wiener(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch
  * ...), twice that of deblur_wiener. */
 int deblur_wiener_fp64(const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
                        double K, float pos_floor, void* ws, size_t ws_bytes, void* stream);
+
+/* deblur_wiener (fp64 = 0) or deblur_wiener_fp64 (fp64 = 1) for B images of
+ * one size at once, one launch per kernel over all of them: image b's f and
+ * u0 at f + b img_stride and u0 + b img_stride (floats, >= H pitch), its PSF
+ * at psf->taps + b taps_stride for DEBLUR_PSF_TAPS (>= ph pw; 0: one PSF for
+ * the batch; box kinds: shared, taps_stride 0).  K and pos_floor are shared.
+ * Each image's u0 equals the one-image call's bit for bit.  ws: at least
+ * deblur_workspace_bytes_batch(0 or 4, B, ...) bytes.  1 <= B <= 65535;
+ * other errors as deblur_wiener. */
+int deblur_wiener_batch(int32_t B, const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, int64_t img_stride,
+                        const deblur_psf* psf, int64_t taps_stride, double K, float pos_floor, int32_t fp64,
+                        void* ws, size_t ws_bytes, void* stream);
 
 /* Starting image for RRRL without the Wiener step (Sec. 2.3; the RRRL columns
  * of Table 1 start from an image the paper does not state):
@@ -185,6 +205,22 @@ int deblur_rrrl_start(const float* f, float* u0, int32_t H, int32_t W, int32_t p
 int deblur_rrrl_iterate(const float* f, const float* u_in, float* u_out, int32_t H, int32_t W, int32_t pitch,
                         const deblur_psf* psf, const deblur_params* p, float* ckpt, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* deblur_rrrl_iterate for B images of one size at once, one launch per
+ * kernel and iteration over all of them (the stencil and running-sum paths;
+ * p->conv = DEBLUR_CONV_FFT returns DEBLUR_EUNSUPPORTED).  Image b's f, u_in
+ * and u_out at + b img_stride (floats, >= H pitch), its checkpoints (if ckpt)
+ * at ckpt + b ckpt_stride (>= p->iters H pitch), its PSF at psf->taps +
+ * b taps_stride for DEBLUR_PSF_TAPS (>= ph pw; 0: shared; box kinds: shared,
+ * taps_stride 0), its alpha at alpha[b] (device array of B floats, not
+ * validated; NULL: p->alpha for every image); the other parameters are
+ * shared.  Each image's results equal the one-image call's bit for bit.  ws:
+ * at least deblur_workspace_bytes_batch(1, B, ...) bytes.  1 <= B <= 65535;
+ * other errors as deblur_rrrl_iterate. */
+int deblur_rrrl_iterate_batch(int32_t B, const float* f, const float* u_in, float* u_out, int32_t H, int32_t W,
+                              int32_t pitch, int64_t img_stride, const deblur_psf* psf, int64_t taps_stride,
+                              const float* alpha, const deblur_params* p, float* ckpt, int64_t ckpt_stride, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /* Variant of deblur_rrrl_iterate for callers that cannot allocate device
  * memory (code under stream capture, tight serving loops, hosts that forbid
@@ -250,12 +286,9 @@ int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
  * Strides are in floats: img_stride >= H pitch, ckpt_stride >= p->iters H
  * pitch, taps_stride >= ph pw (or 0).  1 <= B <= 65535.  Each image's results
  * equal deblur_rrrl_backward's for that image bit for bit.  ws: at least
- * deblur_backward_batch_workspace_bytes(...) bytes (B per-image workspaces).
- * Output ranges (over the whole batch) must not overlap the inputs'.
- * Errors as deblur_rrrl_backward; DEBLUR_EINVAL for B or a stride out of
- * range. */
-size_t deblur_backward_batch_workspace_bytes(int32_t B, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
-                                             const deblur_params* p, int32_t through_wiener);
+ * deblur_workspace_bytes_batch(2 or 3, B, ...) bytes.  Output ranges (over
+ * the whole batch) must not overlap the inputs'.  Errors as
+ * deblur_rrrl_backward; DEBLUR_EINVAL for B or a stride out of range. */
 int deblur_rrrl_backward_batch(int32_t B, const float* f, const float* ckpt, const float* grad_uK, int32_t H,
                                int32_t W, int32_t pitch, int64_t img_stride, int64_t ckpt_stride,
                                const deblur_psf* psf, int64_t taps_stride, const float* alpha,

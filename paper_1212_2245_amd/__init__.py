@@ -307,7 +307,7 @@ def deblur_rrrl_backward(f: torch.Tensor, ckpt: torch.Tensor | None, grad_uK: to
     return out
 
 
-__all__ += ["deblur_rrrl_backward_batch"]
+__all__ += ["deblur_wiener_batch", "deblur_rrrl_iterate_batch", "deblur_rrrl_backward_batch"]
 
 
 def _batch_images(t: torch.Tensor, name: str) -> tuple[int, int, int, int, int]:
@@ -317,6 +317,83 @@ def _batch_images(t: torch.Tensor, name: str) -> tuple[int, int, int, int, int]:
     if t.stride(2) != 1:
         raise ValueError(f"{name} must have unit column stride")
     return t.shape[0], t.shape[1], t.shape[2], t.stride(1), t.stride(0)
+
+
+def _batch_psf(taps, B: int):
+    """(deblur_psf, taps stride, (ph, pw), tensor kept alive) of the PSFs of a
+    batch: a Psf (any kind) or [ph, pw] taps shared by the batch, or [B, ph,
+    pw] taps, one PSF per image."""
+    if isinstance(taps, Psf):
+        return taps.c(), 0, taps.array_shape(), taps.taps
+    if taps.dim() == 2:
+        tb, tstride = taps.contiguous(), 0
+    elif taps.dim() == 3 and taps.shape[0] == B:
+        tb = taps.contiguous()
+        tstride = tb.stride(0)
+    else:
+        raise ValueError("taps must be [ph, pw], [B, ph, pw] or a Psf")
+    return Psf.from_taps(tb if tb.dim() == 2 else tb[0]).c(), tstride, (int(tb.shape[-2]), int(tb.shape[-1])), tb
+
+
+def _batch_alpha(alpha, B: int):
+    if alpha is None:
+        return None
+    if not isinstance(alpha, torch.Tensor) or not alpha.is_cuda or alpha.dtype != torch.float32 or alpha.numel() != B:
+        raise ValueError("alpha must be a [B] float32 device tensor")
+    return alpha.contiguous()
+
+
+def deblur_wiener_batch(f: torch.Tensor, u0: torch.Tensor, taps, K: float = 0.01, pos_floor: float = 1.0,
+                        fp64: bool = False, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """deblur_wiener for a batch: f, u0 [B, H, W] (same layout); taps as in
+    deblur_rrrl_backward_batch (a Psf, [ph, pw] or [B, ph, pw])."""
+    lib = _lib.load()
+    B, H, W, pitch, istride = _batch_images(f, "f")
+    if _batch_images(u0, "u0") != (B, H, W, pitch, istride):
+        raise ValueError("f and u0 must have the same shape and strides")
+    cpsf, tstride, _, _keep = _batch_psf(taps, B)
+    op = _lib.OP_WIENER_FP64 if fp64 else _lib.OP_WIENER
+    need = lib.deblur_workspace_bytes_batch(op, B, H, W, pitch, ctypes.byref(cpsf), None)
+    wst = _workspace(need, f, ws)
+    st = lib.deblur_wiener_batch(B, f.data_ptr(), u0.data_ptr(), H, W, pitch, istride, ctypes.byref(cpsf), tstride,
+                                 float(K), float(pos_floor), int(bool(fp64)), wst.data_ptr(), wst.numel(), _stream(f))
+    _lib.check(st, "deblur_wiener_batch")
+    return u0
+
+
+def deblur_rrrl_iterate_batch(f: torch.Tensor, u_in: torch.Tensor, u_out: torch.Tensor, taps, params: Params,
+                              alpha: torch.Tensor | None = None, ckpt: torch.Tensor | None = None,
+                              ws: torch.Tensor | None = None) -> torch.Tensor:
+    """deblur_rrrl_iterate for a batch: f, u_in, u_out [B, H, W] (same
+    layout; u_out may be u_in); taps as in deblur_rrrl_backward_batch;
+    alpha: [B] device float32 weights (None: params.alpha); ckpt (optional):
+    [B, iters, H, W] with each image's iterates as consecutive H x pitch
+    planes."""
+    lib = _lib.load()
+    B, H, W, pitch, istride = _batch_images(f, "f")
+    for t, n in ((u_in, "u_in"), (u_out, "u_out")):
+        if _batch_images(t, n) != (B, H, W, pitch, istride):
+            raise ValueError(f"f and {n} must have the same shape and strides")
+    cstride = 0
+    if ckpt is not None:
+        if ckpt.dim() != 4 or tuple(ckpt.shape) != (B, params.iters, H, W) or ckpt.dtype != torch.float32:
+            raise ValueError("ckpt must be a [B, iters, H, W] float32 tensor")
+        if ckpt.stride(3) != 1 or ckpt.stride(2) != pitch or ckpt.stride(1) != H * pitch:
+            raise ValueError("ckpt must hold each image's iterates as consecutive H x pitch planes")
+        cstride = ckpt.stride(0)
+    cpsf, tstride, _, _keep = _batch_psf(taps, B)
+    alpha = _batch_alpha(alpha, B)
+    cpar = params.c()
+    need = lib.deblur_workspace_bytes_batch(_lib.OP_ITERATE, B, H, W, pitch, ctypes.byref(cpsf), ctypes.byref(cpar))
+    if need == 0:
+        raise ValueError("invalid or unsupported iterate batch arguments")
+    wst = _workspace(need, f, ws)
+    st = lib.deblur_rrrl_iterate_batch(B, f.data_ptr(), u_in.data_ptr(), u_out.data_ptr(), H, W, pitch, istride,
+                                       ctypes.byref(cpsf), tstride, alpha.data_ptr() if alpha is not None else None,
+                                       ctypes.byref(cpar), ckpt.data_ptr() if ckpt is not None else None, cstride,
+                                       wst.data_ptr(), wst.numel(), _stream(f))
+    _lib.check(st, "deblur_rrrl_iterate_batch")
+    return u_out
 
 
 def deblur_rrrl_backward_batch(f: torch.Tensor, ckpt: torch.Tensor | None, grad_uK: torch.Tensor,
@@ -342,26 +419,11 @@ def deblur_rrrl_backward_batch(f: torch.Tensor, ckpt: torch.Tensor | None, grad_
         if ckpt.stride(3) != 1 or ckpt.stride(2) != pitch or ckpt.stride(1) != H * pitch:
             raise ValueError("ckpt must hold each image's iterates as consecutive H x pitch planes")
         cstride = ckpt.stride(0)
-    if isinstance(taps, Psf):
-        cpsf, tstride = taps.c(), 0
-        ph, pw = taps.array_shape()
-    else:
-        if taps.dim() == 2:
-            tb, tstride = taps.contiguous(), 0
-        elif taps.dim() == 3 and taps.shape[0] == B:
-            tb = taps.contiguous()
-            tstride = tb.stride(0)
-        else:
-            raise ValueError("taps must be [ph, pw], [B, ph, pw] or a Psf")
-        ph, pw = int(tb.shape[-2]), int(tb.shape[-1])
-        cpsf = Psf.from_taps(tb if tb.dim() == 2 else tb[0]).c()
+    cpsf, tstride, (ph, pw), _keep = _batch_psf(taps, B)
+    alpha = _batch_alpha(alpha, B)
     cpar = params.c()
-    if alpha is not None:
-        if not alpha.is_cuda or alpha.dtype != torch.float32 or alpha.numel() != B:
-            raise ValueError("alpha must be a [B] float32 device tensor")
-        alpha = alpha.contiguous()
-    need = lib.deblur_backward_batch_workspace_bytes(B, H, W, pitch, ctypes.byref(cpsf), ctypes.byref(cpar),
-                                                     int(bool(through_wiener)))
+    op = _lib.OP_BACKWARD_WIENER if through_wiener else _lib.OP_BACKWARD
+    need = lib.deblur_workspace_bytes_batch(op, B, H, W, pitch, ctypes.byref(cpsf), ctypes.byref(cpar))
     if need == 0:
         raise ValueError("invalid backward batch arguments")
     wst = _workspace(need, f, ws)
@@ -384,39 +446,6 @@ def deblur_rrrl_backward_batch(f: torch.Tensor, ckpt: torch.Tensor | None, grad_
     return out
 
 
-_SIDE_STREAMS: dict = {}
-
-
-def _on_streams(n: int, fn, device, width: int = 4) -> None:
-    """fn(i) for i < n, spread round-robin over up to `width` side streams
-    forked from the current stream and joined back into it: the images of a
-    batch are independent, and their launches (a few hundred workgroups each
-    at 512^2) overlap instead of running one after another.  Tensors made
-    before the call are ordered before the fork; temporaries made inside fn
-    belong to its side stream."""
-    main = torch.cuda.current_stream(device)
-    k = min(n, width)
-    if k <= 1:
-        for i in range(n):
-            fn(i)
-        return
-    key = (str(device), k)
-    if key not in _SIDE_STREAMS:
-        _SIDE_STREAMS[key] = [torch.cuda.Stream(device=device) for _ in range(k)]   # default priority
-    side = _SIDE_STREAMS[key]
-    fork = torch.cuda.Event()
-    fork.record(main)
-    for s in side:
-        s.wait_event(fork)
-    for i in range(n):
-        with torch.cuda.stream(side[i % k]):
-            fn(i)
-    for s in side:
-        join = torch.cuda.Event()
-        join.record(s)
-        main.wait_event(join)
-
-
 class WR3LFunction(torch.autograd.Function):
     """u = WR3L(f; h, alpha) with the hand-written adjoint as backward.
 
@@ -436,9 +465,9 @@ class WR3LFunction(torch.autograd.Function):
     periodic Wiener filter, and a correctly rounded u^0 keeps the GPU
     gradient within 1e-3 of the FP64 one.  The per-iteration checkpoints u^k
     are stored; the backward recomputes every other quantity from them.  The
-    forward runs the images of a batch concurrently on up to four side
-    streams; the backward covers the whole batch with one launch per kernel
-    (deblur_rrrl_backward_batch)."""
+    forward and the backward cover a batch with one launch per kernel
+    (deblur_wiener_batch, deblur_rrrl_iterate_batch,
+    deblur_rrrl_backward_batch)."""
 
     @staticmethod
     def forward(ctx, f, taps, alpha, K: float, iters: int, template: Params | None = None, pos_floor: float = 1.0):
@@ -461,12 +490,9 @@ class WR3LFunction(torch.autograd.Function):
         u = torch.empty_like(fb)
         ck = torch.empty((B, max(iters, 1), H, W), dtype=torch.float32, device=f.device)
         plist = [dataclasses.replace(base, alpha=alphas[i], iters=int(iters)) for i in range(B)]
-
-        def one(i):
-            psf = Psf.from_taps(tb[i])
-            deblur_wiener(fb[i], u[i], psf, K, pos_floor, fp64=True)
-            deblur_rrrl_iterate(fb[i], u[i], u[i], psf, plist[i], ckpt=ck[i] if iters > 0 else None)
-        _on_streams(B, one, f.device)
+        ad = torch.tensor(alphas, dtype=torch.float32).to(f.device)
+        deblur_wiener_batch(fb, u, tb, K, pos_floor, fp64=True)
+        deblur_rrrl_iterate_batch(fb, u, u, tb, plist[0], alpha=ad, ckpt=ck if iters > 0 else None)
         ctx.save_for_backward(fb, tb, ck)
         ctx.plist, ctx.K, ctx.pos_floor = plist, K, pos_floor
         ctx.batched, ctx.shared_taps = batched, taps.dim() == 2
@@ -479,7 +505,7 @@ class WR3LFunction(torch.autograd.Function):
         fb, tb, ck = ctx.saved_tensors
         gb = (grad_u if ctx.batched else grad_u.unsqueeze(0)).contiguous()
         p0 = ctx.plist[0]
-        alphas = torch.tensor([p.alpha for p in ctx.plist], dtype=torch.float32).to(fb.device, non_blocking=True)
+        alphas = torch.tensor([p.alpha for p in ctx.plist], dtype=torch.float32).to(fb.device)
         g = deblur_rrrl_backward_batch(fb, ck if p0.iters > 0 else None, gb, tb, p0, alpha=alphas,
                                        through_wiener=True, K=ctx.K, pos_floor=ctx.pos_floor)
         gf, gt, ga = g["f"], g["taps"], g["alpha"]

@@ -61,7 +61,11 @@ SIGNATURES = [
     ("deblur_rrrl_iterate_noalloc", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _VP, _VP]),
     ("deblur_rrrl_backward", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _PSF, _PAR, _I32, ctypes.c_double,
                                             ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
-    ("deblur_backward_batch_workspace_bytes", _SZ, [_I32, _I32, _I32, _I32, _PSF, _PAR, _I32]),
+    ("deblur_workspace_bytes_batch", _SZ, [_I32, _I32, _I32, _I32, _I32, _PSF, _PAR]),
+    ("deblur_wiener_batch", ctypes.c_int, [_I32, _VP, _VP, _I32, _I32, _I32, ctypes.c_int64, _PSF, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.c_float, _I32, _VP, _SZ, _VP]),
+    ("deblur_rrrl_iterate_batch", ctypes.c_int, [_I32, _VP, _VP, _VP, _I32, _I32, _I32, ctypes.c_int64, _PSF,
+                                                 ctypes.c_int64, _VP, _PAR, _VP, ctypes.c_int64, _VP, _SZ, _VP]),
     ("deblur_rrrl_backward_batch", ctypes.c_int, [_I32, _VP, _VP, _VP, _I32, _I32, _I32, ctypes.c_int64,
                                                   ctypes.c_int64, _PSF, ctypes.c_int64, _VP, _PAR, _I32,
                                                   ctypes.c_double, ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _SZ,

@@ -355,6 +355,20 @@ int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK
 
 namespace {
 
+// Shared checks of the batched entry points: batch size, image stride and
+// PSF stride (in floats).
+int check_batch_common(int32_t B, int32_t H, int32_t pitch, const PsfDev& d, int64_t img_stride, int64_t taps_stride)
+{
+    if (B < 1 || B > 65535) return DEBLUR_EINVAL;
+    if (img_stride < (int64_t)H * pitch || taps_stride < 0) return DEBLUR_EINVAL;
+    if (d.kind == PSF_TAPS) {
+        if (taps_stride != 0 && taps_stride < (int64_t)d.ph * d.pw) return DEBLUR_EINVAL;
+    } else if (taps_stride != 0) {
+        return DEBLUR_EINVAL;
+    }
+    return DEBLUR_OK;
+}
+
 // Validates the shared arguments of a backward batch; DEBLUR_OK or an error.
 int check_backward_batch(int32_t B, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
                          const deblur_params* p, int32_t through_wiener, int64_t img_stride, int64_t ckpt_stride,
@@ -364,27 +378,74 @@ int check_backward_batch(int32_t B, int32_t H, int32_t W, int32_t pitch, const d
     if (through_wiener != 0 && through_wiener != 1) return DEBLUR_EINVAL;
     int s = check_backward(H, W, pitch, psf, p, through_wiener == 1, d);
     if (s) return s;
-    const int64_t img = (int64_t)H * pitch;
-    if (img_stride < img || ckpt_stride < 0 || taps_stride < 0) return DEBLUR_EINVAL;
-    if (p->iters > 0 && ckpt_stride < img * p->iters) return DEBLUR_EINVAL;
-    if (d->kind == PSF_TAPS) {
-        if (taps_stride != 0 && taps_stride < (int64_t)d->ph * d->pw) return DEBLUR_EINVAL;
-    } else if (taps_stride != 0) {
-        return DEBLUR_EINVAL;
-    }
+    if ((s = check_batch_common(B, H, pitch, *d, img_stride, taps_stride))) return s;
+    if (ckpt_stride < 0 || (p->iters > 0 && ckpt_stride < (int64_t)H * pitch * p->iters)) return DEBLUR_EINVAL;
     return DEBLUR_OK;
 }
 
+size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
+
 }  // namespace
 
-size_t deblur_backward_batch_workspace_bytes(int32_t B, int32_t H, int32_t W, int32_t pitch, const deblur_psf* psf,
-                                             const deblur_params* p, int32_t through_wiener)
+size_t deblur_workspace_bytes_batch(int32_t op, int32_t B, int32_t H, int32_t W, int32_t pitch,
+                                    const deblur_psf* psf, const deblur_params* p)
+{
+    if (B < 1 || B > 65535) return 0;
+    if (op == 1 && p && p->conv == DEBLUR_CONV_FFT) return 0;   // the Fourier-domain iteration has no batched form
+    // one workspace per image, each starting on a 256-byte boundary
+    const size_t one = deblur_workspace_bytes(op, H, W, pitch, psf, p);
+    return one ? (size_t)B * round256(one) : 0;
+}
+
+int deblur_wiener_batch(int32_t B, const float* f, float* u0, int32_t H, int32_t W, int32_t pitch, int64_t img_stride,
+                        const deblur_psf* psf, int64_t taps_stride, double K, float pos_floor, int32_t fp64,
+                        void* ws, size_t ws_bytes, void* stream)
 {
     PsfDev d;
-    if (check_backward_batch(B, H, W, pitch, psf, p, through_wiener, (int64_t)H * pitch,
-                             p ? (int64_t)H * pitch * p->iters : 0, 0, &d))
-        return 0;
-    return (size_t)B * backward_batch_stride(H, W, d, through_wiener == 1);
+    if (!f || !u0) return DEBLUR_EINVAL;
+    if (fp64 != 0 && fp64 != 1) return DEBLUR_EINVAL;
+    int s = check_wiener(H, W, pitch, psf, &d);
+    if (s) return s;
+    if ((s = check_batch_common(B, H, pitch, d, img_stride, taps_stride))) return s;
+    if (!(K > 0.0) || !std::isfinite(K) || !(pos_floor > 0.0f) || !std::isfinite(pos_floor)) return DEBLUR_EINVAL;
+    const size_t img = ((size_t)(B - 1) * img_stride + (size_t)H * pitch) * sizeof(float);
+    if (overlaps(f, img, u0, img)) return DEBLUR_EINVAL;
+    const size_t stride = round256(wiener_ws_bytes(H, W, wiener_rowwise(d), fp64 == 1));
+    if (!ws || ws_bytes / B < stride) return DEBLUR_EWORKSPACE;
+    return launch_wiener_z(B, f, u0, H, W, pitch, (size_t)img_stride * sizeof(float), d,
+                           (size_t)taps_stride * sizeof(float), K, pos_floor, ws, stride, wiener_rowwise(d), fp64 == 1,
+                           reinterpret_cast<hipStream_t>(stream)) == 0
+               ? DEBLUR_OK
+               : DEBLUR_EDEVICE;
+}
+
+int deblur_rrrl_iterate_batch(int32_t B, const float* f, const float* u_in, float* u_out, int32_t H, int32_t W,
+                              int32_t pitch, int64_t img_stride, const deblur_psf* psf, int64_t taps_stride,
+                              const float* alpha, const deblur_params* p, float* ckpt, int64_t ckpt_stride, void* ws,
+                              size_t ws_bytes, void* stream)
+{
+    PsfDev d;
+    if (!f || !u_in || !u_out) return DEBLUR_EINVAL;
+    int s = check_iterate(H, W, pitch, psf, p, &d);
+    if (s) return s;
+    if (p->conv == DEBLUR_CONV_FFT) return DEBLUR_EUNSUPPORTED;
+    if ((s = check_batch_common(B, H, pitch, d, img_stride, taps_stride))) return s;
+    if (ckpt && (ckpt_stride < 0 || ckpt_stride < (int64_t)H * pitch * p->iters)) return DEBLUR_EINVAL;
+    const size_t img = ((size_t)(B - 1) * img_stride + (size_t)H * pitch) * sizeof(float);
+    if (overlaps(f, img, u_out, img) || (u_in != u_out && overlaps(u_in, img, u_out, img))) return DEBLUR_EINVAL;
+    if (ckpt && p->iters > 0) {
+        const size_t ck = ((size_t)(B - 1) * ckpt_stride + (size_t)p->iters * H * pitch) * sizeof(float);
+        if (overlaps(ckpt, ck, f, img) || overlaps(ckpt, ck, u_in, img) || overlaps(ckpt, ck, u_out, img))
+            return DEBLUR_EINVAL;
+    }
+    const bool box = use_box(d, p);
+    const size_t stride = round256(iterate_ws_bytes(H, W, pitch, d, box));
+    if (!ws || ws_bytes / B < stride) return DEBLUR_EWORKSPACE;
+    s = launch_rrrl_iterate_batch(B, f, u_in, u_out, H, W, pitch, (size_t)img_stride * sizeof(float), d,
+                                  (size_t)taps_stride * sizeof(float), alpha, iter_params(p), p->iters, ckpt,
+                                  ckpt ? (size_t)ckpt_stride * sizeof(float) : 0, box, ws, stride,
+                                  reinterpret_cast<hipStream_t>(stream));
+    return s == 0 ? DEBLUR_OK : (s == -2 ? DEBLUR_EUNSUPPORTED : DEBLUR_EDEVICE);
 }
 
 int deblur_rrrl_backward_batch(int32_t B, const float* f, const float* ckpt, const float* grad_uK, int32_t H,

@@ -20,6 +20,16 @@ struct IterParams {
     const float* r1_lut;   // device table of r_1 (lookup mode of r_f), or null: exact r_f
 };
 
+// Image z of an iteration launch over a batch of equally shaped images
+// (blockIdx.z = image): byte strides from image 0 of f, of the iterate read
+// (u), of the iterate written (un), of the checkpoints and of the workspace
+// (tap lists, the (q, W) plane); alpha: the images' weights (device array;
+// nullptr: the IterParams value).  All zero: one image.
+struct IterZ {
+    size_t f = 0, u = 0, un = 0, ck = 0, ws = 0;
+    const float* alpha = nullptr;
+};
+
 // Lookup mode of the information divergence (Sec. 4.1): r_1(x) = x - 1 - ln x
 // tabulated at x = k / RF_LUT_PER_UNIT, k = 1 .. RF_LUT_N (x up to 65), read
 // with linear interpolation; r_f(s) = f r_1(s/f); beyond 65 the tangent of
@@ -106,6 +116,12 @@ struct WienerJob {
 int launch_wiener_batch(const WienerJob* jobs, int n, int H, int W, bool rowwise, hipStream_t st);
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
                   float pos_floor, void* ws, bool rowwise, bool fp64, hipStream_t st);
+// The Wiener step of B images of one size at once (blockIdx.z = image):
+// image z's f and u0 at z img_stride bytes, its PSF taps at z taps_stride
+// bytes (0: shared), its workspace of wiener_ws_bytes at z ws_stride bytes.
+int launch_wiener_z(int B, const float* f, float* u, int H, int W, int pitch, size_t img_stride, const PsfDev& psf,
+                    size_t taps_stride, double K, float pos_floor, void* ws, size_t ws_stride, bool rowwise, bool fp64,
+                    hipStream_t st);
 
 // A launch over n images of one shape at once (blockIdx.z = image): image z's
 // planes are the first image's advanced by z times the byte strides s0, s1,
@@ -139,10 +155,14 @@ void launch_compile_taps(const PsfDev& psf, void* list, hipStream_t st, ZBatch z
 // `variant`: 0 = default tile shape for the image size, 1..taps_num_variants()
 // = an explicit tile shape (all give bitwise-identical results).
 int taps_num_variants();
+// (B images at once with the strides of z; the default tile shape then goes
+// by the tiles of the whole batch)
 int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, int pitch, const PsfDev& psf,
-                       const void* list, const IterParams& p, int variant, hipStream_t st, float* s_out = nullptr);
+                       const void* list, const IterParams& p, int variant, hipStream_t st, float* s_out = nullptr,
+                       int B = 1, const IterZ& z = IterZ{});
 int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
-                       const PsfDev& psf, const void* list, const IterParams& p, int variant, hipStream_t st);
+                       const PsfDev& psf, const void* list, const IterParams& p, int variant, hipStream_t st,
+                       int B = 1, const IterZ& z = IterZ{});
 
 // One fused RRRL iteration for a box PSF of length L along x (vert = false)
 // or y (vert = true).
@@ -156,7 +176,8 @@ int box_num_variants();
 int backward_tile_variants();
 int box_default_variant(int H, int W, bool vert);
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
-                         float frac, bool vert, const IterParams& p, hipStream_t st);
+                         float frac, bool vert, const IterParams& p, hipStream_t st, int B = 1,
+                         const IterZ& z = IterZ{});
 
 // Iteration driver: `iters` iterations u_in -> u_out with ping-pong buffers
 // in the workspace; box kinds use the fused running-sum kernel when use_box.
@@ -164,6 +185,14 @@ size_t iterate_ws_bytes(int H, int W, int pitch, const PsfDev& psf, bool use_box
 int launch_rrrl_iterate(const float* f, const float* u_in, float* u_out, int H, int W, int pitch,
                         const PsfDev& psf, const IterParams& p, int iters, float* ckpt, bool use_box, void* ws,
                         hipStream_t st);
+// B images of one size at once: image z's f, u_in, u_out at z img_stride
+// bytes, its checkpoints at z ck_stride, its PSF taps at z taps_stride (0:
+// shared), its workspace (iterate_ws_bytes) at z ws_stride; alpha: device
+// array of the images' weights or nullptr for p.alpha.
+int launch_rrrl_iterate_batch(int B, const float* f, const float* u_in, float* u_out, int H, int W, int pitch,
+                              size_t img_stride, const PsfDev& psf, size_t taps_stride, const float* alpha,
+                              const IterParams& p, int iters, float* ckpt, size_t ck_stride, bool use_box, void* ws,
+                              size_t ws_stride, hipStream_t st);
 
 // Backward through WR3L (iterations from checkpoints, optionally the Wiener
 // initialisation).

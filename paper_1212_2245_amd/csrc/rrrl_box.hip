@@ -11,20 +11,23 @@ namespace deblur {
 // Tiles in raster order (along the blur axis fastest), remapped so that the
 // workgroups of one XCD take a contiguous range: tiles that share halos then
 // mostly share an L2.
+// blockIdx.z = image of a batch of equally shaped images (strides in z).
 template <bool VERT, int TA, int TC>
 __global__ void __launch_bounds__(BOX_NT) rrrl_box_iter(const float* __restrict__ u, const float* __restrict__ f,
                                                         float* __restrict__ un, float* __restrict__ ckpt, int pitch,
-                                                        BoxGeom g, IterParams p, int tiles_along)
+                                                        BoxGeom g, IterParams p, int tiles_along, IterZ z)
 {
     extern __shared__ __align__(16) float box_lds[];
     const int w = xcd_group(blockIdx.x, gridDim.x);
     const int tc = w / tiles_along, ta = w - tc * tiles_along;
-    box_seg_tile<VERT, TA, TC>(box_lds, u, f, un, ckpt, pitch, g, p, ta * TA, tc * TC);
+    if (z.alpha) p.alpha = z.alpha[blockIdx.z];
+    box_seg_tile<VERT, TA, TC>(box_lds, zadv(u, z.u), zadv(f, z.f), zadv(un, z.un), ckpt ? zadv(ckpt, z.ck) : nullptr,
+                               pitch, g, p, ta * TA, tc * TC);
 }
 
 template <bool VERT, int TA, int TC>
 static void launch_box(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
-                       float frac, const IterParams& p, hipStream_t st)
+                       float frac, const IterParams& p, hipStream_t st, int B, const IterZ& z)
 {
     static std::once_flag once;
     std::call_once(once, [] {
@@ -34,8 +37,8 @@ static void launch_box(const float* f, const float* u, float* un, float* ckpt, i
     const BoxGeom g = box_geom<VERT, TA, TC>(H, W, L, frac);
     const int ta = (g.N + TA - 1) / TA, tc = (g.M + TC - 1) / TC;
     const size_t lds = (size_t)box_lds_words<VERT, TA, TC>(g) * sizeof(float);
-    hipLaunchKernelGGL((rrrl_box_iter<VERT, TA, TC>), dim3(ta * tc), dim3(BOX_NT), lds, st, u, f, un, ckpt, pitch, g,
-                       p, ta);
+    hipLaunchKernelGGL((rrrl_box_iter<VERT, TA, TC>), dim3(ta * tc, 1, B), dim3(BOX_NT), lds, st, u, f, un, ckpt, pitch,
+                       g, p, ta, z);
 }
 
 int box_num_variants() { return BOX_VARIANTS; }
@@ -51,17 +54,17 @@ int box_default_variant(int H, int W, bool vert)
 }
 
 int launch_rrrl_box_iter(const float* f, const float* u, float* un, float* ckpt, int H, int W, int pitch, int L,
-                         float frac, bool vert, const IterParams& p, hipStream_t st)
+                         float frac, bool vert, const IterParams& p, hipStream_t st, int B, const IterZ& z)
 {
     const int v = p.tile > 0 ? p.tile : box_default_variant(H, W, vert);
     if (v > box_num_variants()) return -2;
     if (vert)
         with_box_shape<true>(v, [&](auto ta, auto tc) {
-            launch_box<true, decltype(ta)::value, decltype(tc)::value>(f, u, un, ckpt, H, W, pitch, L, frac, p, st);
+            launch_box<true, decltype(ta)::value, decltype(tc)::value>(f, u, un, ckpt, H, W, pitch, L, frac, p, st, B, z);
         });
     else
         with_box_shape<false>(v, [&](auto ta, auto tc) {
-            launch_box<false, decltype(ta)::value, decltype(tc)::value>(f, u, un, ckpt, H, W, pitch, L, frac, p, st);
+            launch_box<false, decltype(ta)::value, decltype(tc)::value>(f, u, un, ckpt, H, W, pitch, L, frac, p, st, B, z);
         });
     return 0;
 }

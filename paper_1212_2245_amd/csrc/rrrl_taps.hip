@@ -201,68 +201,67 @@ int taps_num_variants() { return kNumVariants; }
 
 template <int RAD, int TH, int NT>
 static void stage1_inst(const float* f, const float* u, float2* qw, float* s_out, int H, int W, int pitch,
-                        const float* taps, const int* nt, const IterParams& p, hipStream_t st)
+                        const float* taps, const int* nt, const IterParams& p, hipStream_t st, int B, const IterZ& z)
 {
-    const dim3 g((W + 63) / 64, (H + TH - 1) / TH);
+    const dim3 g((W + 63) / 64, (H + TH - 1) / TH, B);
     hipLaunchKernelGGL((rrrl_taps_stage1<RAD, TH, NT>), g, dim3(NT), 0, st, u, f, qw, s_out, H, W, pitch, taps, nt,
-                       p);
+                       p, z);
 }
 
 template <int RAD, int TH, int NT>
 static void stage2_inst(const float2* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
-                        const float* taps, const int* nt, const IterParams& p, hipStream_t st)
+                        const float* taps, const int* nt, const IterParams& p, hipStream_t st, int B, const IterZ& z)
 {
-    const dim3 g((W + 63) / 64, (H + TH - 1) / TH);
+    const dim3 g((W + 63) / 64, (H + TH - 1) / TH, B);
     hipLaunchKernelGGL((rrrl_taps_stage2<RAD, TH, NT>), g, dim3(NT), 0, st, qw, u, un, ckpt, H, W, pitch, taps, nt,
-                       p);
+                       p, z);
 }
 
 template <int RAD>
 static void launch_stage1_t(int v, const float* f, const float* u, float2* qw, float* s_out, int H, int W,
-                            int pitch, const float* taps, const int* nt, const IterParams& p, hipStream_t st)
+                            int pitch, const float* taps, const int* nt, const IterParams& p, hipStream_t st, int B,
+                            const IterZ& z)
 {
     switch (v) {
-        case 0: stage1_inst<RAD, 64, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
-        case 1: stage1_inst<RAD, 64, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
-        case 2: stage1_inst<RAD, 32, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
-        case 3: stage1_inst<RAD, 32, 512>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
-        case 4: stage1_inst<RAD, 16, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
-        case 5: stage1_inst<RAD, 16, 512>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
-        case 6: stage1_inst<RAD, 32, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
-        default: stage1_inst<RAD, 16, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 0: stage1_inst<RAD, 64, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 1: stage1_inst<RAD, 64, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 2: stage1_inst<RAD, 32, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 3: stage1_inst<RAD, 32, 512>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 4: stage1_inst<RAD, 16, 256>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 5: stage1_inst<RAD, 16, 512>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 6: stage1_inst<RAD, 32, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        default: stage1_inst<RAD, 16, 1024>(f, u, qw, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
     }
 }
 
 template <int RAD>
 static void launch_stage2_t(int v, const float2* qw, const float* u, float* un, float* ckpt, int H, int W,
-                            int pitch, const float* taps, const int* nt, const IterParams& p, hipStream_t st)
+                            int pitch, const float* taps, const int* nt, const IterParams& p, hipStream_t st, int B,
+                            const IterZ& z)
 {
     // 64-row tiles of the two-channel plane exceed LDS for the largest radius
     if (RAD >= 32 && (v == 0 || v == 1)) v = 3;
     switch (v) {
-        case 0: stage2_inst<RAD, (RAD >= 32 ? 32 : 64), 1024>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 1: stage2_inst<RAD, (RAD >= 32 ? 32 : 64), 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 2: stage2_inst<RAD, 32, 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 3: stage2_inst<RAD, 32, 512>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 4: stage2_inst<RAD, 16, 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 5: stage2_inst<RAD, 16, 512>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 6: stage2_inst<RAD, 32, 1024>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        default: stage2_inst<RAD, 16, 1024>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 0: stage2_inst<RAD, (RAD >= 32 ? 32 : 64), 1024>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 1: stage2_inst<RAD, (RAD >= 32 ? 32 : 64), 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 2: stage2_inst<RAD, 32, 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 3: stage2_inst<RAD, 32, 512>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 4: stage2_inst<RAD, 16, 256>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 5: stage2_inst<RAD, 16, 512>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 6: stage2_inst<RAD, 32, 1024>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        default: stage2_inst<RAD, 16, 1024>(qw, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
     }
 }
 
-// Default variant when the caller does not choose one (measured on MI355X
-// with a 71-tap line PSF; indices into kVariants): 64-row tiles of 1024
-// threads for stage 1 and 32-row tiles of 512 threads for stage 2 at about
-// 1 Mpx; smaller images use 16-row tiles.
 // Default tile shape (index into kVariants) by image size, from a sweep of
 // every shape with a sparse (31-px line) and a dense (31x31) PSF at 256^2 ..
 // 2048^2: small images want many workgroups (16 rows x 512 threads, 2 rows
 // per thread), large ones more rows per thread for reuse of the loaded
 // column values (32 x 512, then 32 x 256).  Both stages use the same shape.
-static int default_variant(int H, int W, int /*stage*/)
+// A launch over a batch of B images counts the tiles of all of them.
+static int default_variant(int H, int W, int B)
 {
-    const long tiles64 = (long)((W + 63) / 64) * ((H + 63) / 64);
+    const long tiles64 = (long)B * ((W + 63) / 64) * ((H + 63) / 64);
     if (tiles64 >= 1024) return 2;
     if (tiles64 >= 256) return 3;
     return 5;
@@ -289,36 +288,38 @@ static int psf_radius_class(const PsfDev& psf)
 }
 
 int launch_taps_stage1(const float* f, const float* u, float* qw, int H, int W, int pitch, const PsfDev& psf,
-                       const void* list, const IterParams& p, int variant, hipStream_t st, float* s_out)
+                       const void* list, const IterParams& p, int variant, hipStream_t st, float* s_out, int B,
+                       const IterZ& z)
 {
-    const int v = variant > 0 ? variant - 1 : default_variant(H, W, 1);
+    const int v = variant > 0 ? variant - 1 : default_variant(H, W, B);
     const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
     const int* nt = reinterpret_cast<const int*>(w8);
     const float* taps = reinterpret_cast<const float*>(w8 + tap_packed_offset(psf.ph, psf.pw));
     float2* q2 = reinterpret_cast<float2*>(qw);
     switch (psf_radius_class(psf)) {
-        case 4: launch_stage1_t<4>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
-        case 8: launch_stage1_t<8>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
-        case 16: launch_stage1_t<16>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
-        case 32: launch_stage1_t<32>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st); break;
+        case 4: launch_stage1_t<4>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 8: launch_stage1_t<8>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 16: launch_stage1_t<16>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 32: launch_stage1_t<32>(v, f, u, q2, s_out, H, W, pitch, taps, nt, p, st, B, z); break;
         default: return -2;
     }
     return 0;
 }
 
 int launch_taps_stage2(const float* qw, const float* u, float* un, float* ckpt, int H, int W, int pitch,
-                       const PsfDev& psf, const void* list, const IterParams& p, int variant, hipStream_t st)
+                       const PsfDev& psf, const void* list, const IterParams& p, int variant, hipStream_t st, int B,
+                       const IterZ& z)
 {
-    const int v = variant > 0 ? variant - 1 : default_variant(H, W, 2);
+    const int v = variant > 0 ? variant - 1 : default_variant(H, W, B);
     const unsigned char* w8 = reinterpret_cast<const unsigned char*>(list);
     const int* nt = reinterpret_cast<const int*>(w8);
     const float* taps = reinterpret_cast<const float*>(w8 + tap_packed_offset(psf.ph, psf.pw));
     const float2* q2 = reinterpret_cast<const float2*>(qw);
     switch (psf_radius_class(psf)) {
-        case 4: launch_stage2_t<4>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 8: launch_stage2_t<8>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 16: launch_stage2_t<16>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
-        case 32: launch_stage2_t<32>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st); break;
+        case 4: launch_stage2_t<4>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 8: launch_stage2_t<8>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 16: launch_stage2_t<16>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
+        case 32: launch_stage2_t<32>(v, q2, u, un, ckpt, H, W, pitch, taps, nt, p, st, B, z); break;
         default: return -2;
     }
     return 0;

@@ -311,12 +311,13 @@ template <int RAD, int TH, int NT>
 __global__ void __launch_bounds__(NT) rrrl_taps_stage1(const float* __restrict__ u, const float* __restrict__ f,
                                                        float2* __restrict__ qw, float* __restrict__ s_out, int H,
                                                        int W, int pitch, const float* __restrict__ pkg,
-                                                       const int* __restrict__ hdr, IterParams p)
+                                                       const int* __restrict__ hdr, IterParams p, IterZ z)
 {
     __shared__ float tile[stage1_lds_floats<RAD, TH>()];
     __shared__ float pk[packed_words_max<RAD>()];
     const int2 t = xcd_tile();
-    stage1_tile<RAD, TH, NT>(tile, pk, u, f, qw, s_out, H, W, pitch, t.x * 64, t.y * TH, pkg, hdr, p);
+    stage1_tile<RAD, TH, NT>(tile, pk, zadv(u, z.u), zadv(f, z.f), zadv(qw, z.ws), s_out ? zadv(s_out, z.ws) : nullptr,
+                             H, W, pitch, t.x * 64, t.y * TH, zadv(pkg, z.ws), zadv(hdr, z.ws), p);
 }
 
 template <int RAD, int TH>
@@ -411,11 +412,13 @@ template <int RAD, int TH, int NT>
 __global__ void __launch_bounds__(NT) rrrl_taps_stage2(const float2* __restrict__ qw, const float* __restrict__ u,
                                                        float* __restrict__ u_next, float* __restrict__ ckpt,
                                                        int H, int W, int pitch, const float* __restrict__ pkg,
-                                                       const int* __restrict__ hdr, IterParams p)
+                                                       const int* __restrict__ hdr, IterParams p, IterZ z)
 {
     __shared__ Stage2Smem<RAD, TH> sm;
     const int2 t = xcd_tile();
-    stage2_tile<RAD, TH, NT>(sm, qw, u, u_next, ckpt, H, W, pitch, t.x * 64, t.y * TH, pkg, hdr, p);
+    if (z.alpha) p.alpha = z.alpha[blockIdx.z];
+    stage2_tile<RAD, TH, NT>(sm, zadv(qw, z.ws), zadv(u, z.u), zadv(u_next, z.un), ckpt ? zadv(ckpt, z.ck) : nullptr, H,
+                             W, pitch, t.x * 64, t.y * TH, zadv(pkg, z.ws), zadv(hdr, z.ws), p);
 }
 
 }  // namespace deblur

@@ -79,11 +79,19 @@ DEBLUR_DEV void mult_1d_block(const PsfDev& psf, int n, double K, C* __restrict_
     M[k] = Cplx<C>::make((R)(hk.x / den), (R)(-hk.y / den));
 }
 
+// Kernels of the one-image path also run over a batch of equally shaped
+// images (blockIdx.z = image): image z's f and u at z img bytes, its PSF
+// taps at z taps bytes, its workspace (M, S) at z ws bytes from image 0's.
+struct WienerZ {
+    size_t img, taps, ws;
+};
+
 template <typename C>
-__global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double K, C* __restrict__ M)
+__global__ void __launch_bounds__(256) wiener_mult_1d(PsfDev psf, int n, double K, C* __restrict__ M, WienerZ z)
 {
     __shared__ float hs[MULT_MAXP];
-    mult_1d_block<C>(psf, n, K, M, blockIdx.x, hs);
+    if (psf.taps) psf.taps = zadv(psf.taps, z.taps);
+    mult_1d_block<C>(psf, n, K, zadv(M, z.ws), blockIdx.x, hs);
 }
 
 // One workgroup per `nb` row pairs (block blk); LDS: two ping-pong buffers
@@ -130,10 +138,11 @@ DEBLUR_DEV void rows_fused_block(const float* __restrict__ f, float* __restrict_
 template <typename C>
 __global__ void __launch_bounds__(256) wiener_rows_fused(const float* __restrict__ f, float* __restrict__ u,
                                                          int H, int W, int pitch, int nb, FftPlan plan,
-                                                         const C* __restrict__ M, float pos_floor)
+                                                         const C* __restrict__ M, float pos_floor, WienerZ z)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    rows_fused_block<C>(f, u, H, W, pitch, nb, plan, M, pos_floor, blockIdx.x, smem_raw);
+    rows_fused_block<C>(zadv(f, z.img), zadv(u, z.img), H, W, pitch, nb, plan, zadv(M, z.ws), pos_floor, blockIdx.x,
+                        smem_raw);
 }
 
 // M(ky, kx) for kx <= W/2, stored row-major with row pitch W/2+1 (the
@@ -304,9 +313,14 @@ __global__ void __launch_bounds__(256) wiener_rows_fwd(const float* __restrict__
 template <typename C>
 __global__ void __launch_bounds__(256) wiener_rows_fwd_mult(const float* __restrict__ f, C* __restrict__ S,
                                                             int H, int W, int pitch, int nb, FftPlan plan, int nrow,
-                                                            PsfDev psf, double K, C* __restrict__ M, int gxm)
+                                                            PsfDev psf, double K, C* __restrict__ M, int gxm,
+                                                            WienerZ z)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    f = zadv(f, z.img);
+    S = zadv(S, z.ws);
+    M = zadv(M, z.ws);
+    if (psf.taps) psf.taps = zadv(psf.taps, z.taps);
     if ((int)blockIdx.x < nrow) {
         rows_fwd_block(f, S, H, W, pitch, nb, plan, blockIdx.x, smem_raw);
     } else {
@@ -567,18 +581,18 @@ void prepare_wiener_kernels()
 }
 
 template <typename C>
-static int launch_wiener_t(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
-                           float pos_floor, void* ws, bool rowwise, hipStream_t st)
+static int launch_wiener_t(int B, const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
+                           float pos_floor, void* ws, bool rowwise, const WienerZ& z, hipStream_t st)
 {
     allow_wiener_lds<C>();
     if (rowwise) {
         C* M = reinterpret_cast<C*>(ws);
-        hipLaunchKernelGGL(wiener_mult_1d<C>, dim3((W + 255) / 256), dim3(256), 0, st, psf, W, K, M);
+        hipLaunchKernelGGL(wiener_mult_1d<C>, dim3((W + 255) / 256, 1, B), dim3(256), 0, st, psf, W, K, M, z);
         const int pairs = (H + 1) / 2;
         const int nb = row_batch(W);
         const size_t lds = (size_t)(W + 2 * nb * W) * sizeof(C);
-        hipLaunchKernelGGL(wiener_rows_fused<C>, dim3((pairs + nb - 1) / nb), dim3(256), lds, st, f, u, H, W,
-                           pitch, nb, make_plan(W), (const C*)M, pos_floor);
+        hipLaunchKernelGGL(wiener_rows_fused<C>, dim3((pairs + nb - 1) / nb, 1, B), dim3(256), lds, st, f, u, H, W,
+                           pitch, nb, make_plan(W), (const C*)M, pos_floor, z);
     } else {
         const int Wh = W / 2 + 1;
         C* M = reinterpret_cast<C*>(ws);
@@ -588,14 +602,14 @@ static int launch_wiener_t(const float* f, float* u, int H, int W, int pitch, co
         const size_t lds_r = (size_t)(W + 2 * nb * W) * sizeof(C);
         const int nrow = (pairs + nb - 1) / nb;
         const int gxm = (Wh + MULT_KX - 1) / MULT_KX, gym = (H + MULT_KY - 1) / MULT_KY;
-        hipLaunchKernelGGL(wiener_rows_fwd_mult<C>, dim3(nrow + gxm * gym), dim3(256), std::max(lds_r, MULT_SMEM), st,
-                           f, S, H, W, pitch, nb, make_plan(W), nrow, psf, K, M, gxm);
+        hipLaunchKernelGGL(wiener_rows_fwd_mult<C>, dim3(nrow + gxm * gym, 1, B), dim3(256), std::max(lds_r, MULT_SMEM),
+                           st, f, S, H, W, pitch, nb, make_plan(W), nrow, psf, K, M, gxm, z);
         const int cb = col_batch(H);
         const size_t lds_c = (size_t)(H + 2 * cb * H) * sizeof(C);
-        hipLaunchKernelGGL(wiener_cols<C>, dim3((Wh + cb - 1) / cb), dim3(256), lds_c, st, S, (const C*)M,
-                           H, W, cb, make_plan(H), 0, 0, (size_t)0, (size_t)0);
-        hipLaunchKernelGGL(wiener_rows_inv<C>, dim3((pairs + nb - 1) / nb), dim3(256), lds_r, st,
-                           (const C*)S, u, H, W, pitch, nb, make_plan(W), pos_floor, 0, (size_t)0, (size_t)0);
+        hipLaunchKernelGGL(wiener_cols<C>, dim3((Wh + cb - 1) / cb, 1, B), dim3(256), lds_c, st, S, (const C*)M,
+                           H, W, cb, make_plan(H), 0, 0, z.ws, z.ws);
+        hipLaunchKernelGGL(wiener_rows_inv<C>, dim3((pairs + nb - 1) / nb, 1, B), dim3(256), lds_r, st,
+                           (const C*)S, u, H, W, pitch, nb, make_plan(W), pos_floor, 0, z.ws, z.img);
     }
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
@@ -631,8 +645,16 @@ int launch_wiener_batch(const WienerJob* jobs, int n, int H, int W, bool rowwise
 int launch_wiener(const float* f, float* u, int H, int W, int pitch, const PsfDev& psf, double K,
                   float pos_floor, void* ws, bool rowwise, bool fp64, hipStream_t st)
 {
-    return fp64 ? launch_wiener_t<double2>(f, u, H, W, pitch, psf, K, pos_floor, ws, rowwise, st)
-                : launch_wiener_t<float2>(f, u, H, W, pitch, psf, K, pos_floor, ws, rowwise, st);
+    return launch_wiener_z(1, f, u, H, W, pitch, 0, psf, 0, K, pos_floor, ws, 0, rowwise, fp64, st);
+}
+
+int launch_wiener_z(int B, const float* f, float* u, int H, int W, int pitch, size_t img_stride, const PsfDev& psf,
+                    size_t taps_stride, double K, float pos_floor, void* ws, size_t ws_stride, bool rowwise, bool fp64,
+                    hipStream_t st)
+{
+    const WienerZ z{img_stride, taps_stride, ws_stride};
+    return fp64 ? launch_wiener_t<double2>(B, f, u, H, W, pitch, psf, K, pos_floor, ws, rowwise, z, st)
+                : launch_wiener_t<float2>(B, f, u, H, W, pitch, psf, K, pos_floor, ws, rowwise, z, st);
 }
 
 int fft_row_batch(int W) { return row_batch(W); }

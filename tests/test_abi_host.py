@@ -277,8 +277,57 @@ def test_backward_batch_validation(lib):
     assert bb() == _lib.DEBLUR_EWORKSPACE
     assert bb(tstr=0) == _lib.DEBLUR_EWORKSPACE   # one shared PSF is valid
     one = lib.deblur_workspace_bytes(3, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p))
-    four = lib.deblur_backward_batch_workspace_bytes(4, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p), 1)
-    assert four >= 4 * one and four % 4 == 0
+    four = lib.deblur_workspace_bytes_batch(3, 4, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p))
+    assert four >= 4 * one and four % (4 * 256) == 0
     assert bb(ws=WS, wsb=four - 1) == _lib.DEBLUR_EWORKSPACE
-    assert lib.deblur_backward_batch_workspace_bytes(0, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p), 1) == 0
-    assert lib.deblur_backward_batch_workspace_bytes(4, 64, 64, 64, ctypes.byref(taps(5, 5)), None, 1) == 0
+    assert lib.deblur_workspace_bytes_batch(3, 0, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p)) == 0
+    assert lib.deblur_workspace_bytes_batch(3, 4, 64, 64, 64, ctypes.byref(taps(5, 5)), None) == 0
+
+
+def test_wiener_and_iterate_batch_validation(lib):
+    E = _lib.DEBLUR_EINVAL
+    img = 64 * 64
+
+    def wb(B=4, f=F, u=U, H=64, W=64, pitch=64, istr=img, psf=None, tstr=25, K=0.01, floor=1.0, fp64=0, ws=None,
+           wsb=0):
+        psf = psf if psf is not None else taps(5, 5)
+        return lib.deblur_wiener_batch(B, f, u, H, W, pitch, istr, ctypes.byref(psf), tstr, K, floor, fp64, ws, wsb,
+                                       None)
+    assert wb(B=0) == E
+    assert wb(f=None) == E
+    assert wb(fp64=2) == E
+    assert wb(K=0.0) == E
+    assert wb(floor=0.0) == E
+    assert wb(istr=img - 1) == E
+    assert wb(tstr=24) == E
+    assert wb(psf=box(), tstr=25) == E
+    assert wb(u=F + 4 * 3 * img) == E              # u0 overlaps image 3 of f
+    assert wb(H=100) == _lib.DEBLUR_EUNSUPPORTED
+    assert wb() == _lib.DEBLUR_EWORKSPACE
+    need = lib.deblur_workspace_bytes_batch(4, 4, 64, 64, 64, ctypes.byref(taps(5, 5)), None)
+    assert need >= 4 * lib.deblur_workspace_bytes(4, 64, 64, 64, ctypes.byref(taps(5, 5)), None) > 0
+    assert wb(fp64=1, ws=WS, wsb=need - 1) == _lib.DEBLUR_EWORKSPACE
+
+    p = params(iters=3)
+
+    def ib(B=4, f=F, ui=U, uo=U, H=64, W=64, pitch=64, istr=img, psf=None, tstr=25, pp=None, ck=None, cstr=0,
+           ws=None, wsb=0):
+        psf = psf if psf is not None else taps(5, 5)
+        return lib.deblur_rrrl_iterate_batch(B, f, ui, uo, H, W, pitch, istr, ctypes.byref(psf), tstr, None,
+                                             ctypes.byref(pp or p), ck, cstr, ws, wsb, None)
+    assert ib(B=65536) == E
+    assert ib(uo=None) == E
+    assert ib(istr=img - 1) == E
+    assert ib(tstr=24) == E
+    assert ib(psf=box(), tstr=1) == E
+    assert ib(uo=F) == E                            # output overlaps f
+    assert ib(ck=CK, cstr=3 * img - 1) == E         # checkpoints of consecutive images overlap
+    assert ib(ck=U + 4 * img, cstr=3 * img) == E    # checkpoints overlap image 1 of u
+    assert ib(pp=params(iters=3, conv=_lib.CONV_FFT, boundary=_lib.BC_PERIODIC)) == _lib.DEBLUR_EUNSUPPORTED
+    assert lib.deblur_workspace_bytes_batch(1, 4, 64, 64, 64, ctypes.byref(taps(5, 5)),
+                                            ctypes.byref(params(conv=_lib.CONV_FFT, boundary=_lib.BC_PERIODIC))) == 0
+    assert ib() == _lib.DEBLUR_EWORKSPACE
+    assert ib(psf=box(), tstr=0) == _lib.DEBLUR_EWORKSPACE
+    need = lib.deblur_workspace_bytes_batch(1, 4, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p))
+    assert need >= 4 * lib.deblur_workspace_bytes(1, 64, 64, 64, ctypes.byref(taps(5, 5)), ctypes.byref(p)) > 0
+    assert ib(ws=WS, wsb=need - 1) == _lib.DEBLUR_EWORKSPACE
