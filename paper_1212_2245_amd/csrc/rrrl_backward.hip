@@ -200,9 +200,12 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
 }
 
 // Fold of an output extended by (ry, rx): every image pixel sums the grid
-// points whose clamped position it is.  Separable: first along x (every
-// extended row, into tmp of EH x W), then along y.  Border pixels sum up to
-// 2r + 1 values; the loads go out eight at a time.
+// points whose clamped position it is.  Only border pixels have more than one
+// (their own point plus the extension beyond them); an interior pixel's value
+// is its own grid point, read in place by the consumers (ext_or_border).  The
+// border pixels' sums go to a buffer of 2W + 2H entries (border_index): first
+// along x for every extended row (the columns that clamp to x), then along y
+// (the rows that clamp to y), each in order, with the loads eight at a time.
 DEBLUR_DEV void add_to(float& a, float b) { a += b; }
 DEBLUR_DEV void add_to(float2& a, float2 b)
 {
@@ -210,46 +213,82 @@ DEBLUR_DEV void add_to(float2& a, float2 b)
     a.y += b.y;
 }
 
-template <typename T>
-DEBLUR_DEV T strided_sum(const T* __restrict__ p, size_t stride, int n)
+// Slot of border pixel (y, x) in the fold buffer, -1 for interior pixels:
+// row 0, row H-1, then column 0 and column W-1 without their end rows.
+DEBLUR_DEV int border_index(int y, int x, int H, int W)
 {
+    if (y == 0) return x;
+    if (y == H - 1) return W + x;
+    if (x == 0) return 2 * W + (y - 1);
+    if (x == W - 1) return 2 * W + (H - 2) + (y - 1);
+    return -1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) adj_fold_border(const T* __restrict__ ext, int epitch, int ry, int rx, int H,
+                                                       int W, T* __restrict__ bd, size_t zws)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int y, x;
+    if (t < W) {
+        y = 0, x = t;
+    } else if (t < 2 * W) {
+        y = H - 1, x = t - W;
+        if (H == 1) return;
+    } else if (t < 2 * W + max(H - 2, 0)) {
+        y = t - 2 * W + 1, x = 0;
+    } else if (t < 2 * W + 2 * max(H - 2, 0)) {
+        y = t - 2 * W - (H - 2) + 1, x = W - 1;
+        if (W == 1) return;
+    } else {
+        return;
+    }
+    ext = zadv(ext, zws);
+    bd = zadv(bd, zws);
+    const int lox = x == 0 ? 0 : x + rx, hix = x == W - 1 ? W - 1 + 2 * rx : x + rx;   // extended columns
+    const int loy = y == 0 ? 0 : y + ry, hiy = y == H - 1 ? H - 1 + 2 * ry : y + ry;   // extended rows
     T acc{};
-    for (int b0 = 0; b0 < n; b0 += 8) {
+    for (int b0 = loy; b0 <= hiy; b0 += 8) {
         T v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = b0 + k < n ? p[(size_t)(b0 + k) * stride] : T{};
+        for (int k = 0; k < 8; ++k) {
+            v[k] = T{};
+            if (b0 + k <= hiy) {
+                const T* row = ext + (size_t)(b0 + k) * epitch;
+                for (int c0 = lox; c0 <= hix; c0 += 8) {
+                    T w[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) w[q] = c0 + q <= hix ? row[c0 + q] : T{};
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) add_to(v[k], w[q]);
+                }
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 8; ++k) add_to(acc, v[k]);
     }
-    return acc;
+    bd[border_index(y, x, H, W)] = acc;
 }
 
+// A transposed-blur output at image pixel (y, x): the folded value of a border
+// pixel, else the pixel's own point of the extended grid (origin (oy, ox)).
+// Periodic continuation: bd = nullptr, oy = ox = 0 (the plain image grid).
 template <typename T>
-__global__ void __launch_bounds__(256) adj_fold_x(const T* __restrict__ ext, int epitch, int rx, int W,
-                                                  T* __restrict__ tmp, size_t zws)
+DEBLUR_DEV T ext_or_border(const T* __restrict__ ext, int epitch, int oy, int ox, const T* __restrict__ bd, int y,
+                           int x, int H, int W)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, zy = blockIdx.y;
-    if (x >= W) return;
-    ext = zadv(ext, zws);
-    tmp = zadv(tmp, zws);
-    const int lo = x == 0 ? 0 : x + rx, hi = x == W - 1 ? W - 1 + 2 * rx : x + rx;   // extended columns
-    tmp[(size_t)zy * W + x] = strided_sum(ext + (size_t)zy * epitch + lo, 1, hi - lo + 1);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) adj_fold_y(const T* __restrict__ tmp, int ry, int H, int W,
-                                                  T* __restrict__ out, int opitch, size_t zws)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    if (x >= W) return;
-    tmp = zadv(tmp, zws);
-    out = zadv(out, zws);
-    const int lo = y == 0 ? 0 : y + ry, hi = y == H - 1 ? H - 1 + 2 * ry : y + ry;   // extended rows
-    out[(size_t)y * opitch + x] = strided_sum(tmp + (size_t)lo * W + x, (size_t)W, hi - lo + 1);
+    if (bd) {
+        const int b = border_index(y, x, H, W);
+        if (b >= 0) return bd[b];
+    }
+    return ext[(size_t)(y + oy) * epitch + x + ox];
 }
 
 // ------------------------------- adjoint of W, q = W f / s, r_f and the guard
-__global__ void __launch_bounds__(256) adj_point(const float2* __restrict__ dqw, const float2* __restrict__ qw,
+// (dq, dW) = B^T (a, bb): on the extended grid (pitch epitch, origin (oy, ox))
+// with the folded border values in bd (nullptr: periodic, no fold).
+__global__ void __launch_bounds__(256) adj_point(const float2* __restrict__ dqw, int epitch, int oy, int ox,
+                                                 const float2* __restrict__ dbd, const float2* __restrict__ qw,
                                                  const float* __restrict__ s_raw, const float* __restrict__ f,
                                                  float* __restrict__ grad_f, float* __restrict__ ds, int H, int W,
                                                  int pitch, IterParams p, BwdZ z)
@@ -257,13 +296,15 @@ __global__ void __launch_bounds__(256) adj_point(const float2* __restrict__ dqw,
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= W) return;
     dqw = zadv(dqw, z.ws);
+    if (dbd) dbd = zadv(dbd, z.ws);
     qw = zadv(qw, z.ws);
     s_raw = zadv(s_raw, z.ws);
     f = zadv(f, z.img);
     grad_f = zadv(grad_f, z.img);
     ds = zadv(ds, z.ws);
     const size_t o = (size_t)y * W + x, of = (size_t)y * pitch + x;
-    const float2 d = dqw[o], v = qw[o];   // d = (B^T a, B^T bb), v = (e, W)
+    const float2 d = ext_or_border(dqw, epitch, oy, ox, dbd, y, x, H, W);   // (B^T a, B^T bb)
+    const float2 v = qw[o];                                                   // (e, W)
     const float sr = s_raw[o];
     const float st = fmaxf(sr, p.s_min);
     const float fv = f[of];
@@ -289,9 +330,12 @@ __global__ void __launch_bounds__(256) adj_point(const float2* __restrict__ dqw,
 // ------------------------------------------ adjoint of the diffusion term
 // lam_out = du + aT + (L_g c) + (through g), c = dL/dD, frozen-g operator L_g
 // symmetric; g = Psi'(gx^2 + gy^2) with central differences of clamped u.
+// aT = A^T ds on the extended grid (pitch epitch, origin (oy, ox)) with the
+// folded border values in abd (nullptr: periodic, no fold).
 template <int TH>
 __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int pitch, const float* __restrict__ cpl,
-                                                const float* __restrict__ du, const float* __restrict__ aT,
+                                                const float* __restrict__ du, const float* __restrict__ aT, int epitch,
+                                                int oy, int ox, const float* __restrict__ abd,
                                                 float* __restrict__ lam_out, int H, int W, IterParams p, BwdZ z)
 {
     constexpr int TW = BW_TW, UW = TW + 4, UH = TH + 4, GW = TW + 2, GH = TH + 2;
@@ -299,6 +343,7 @@ __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int
     cpl = zadv(cpl, z.ws);
     du = zadv(du, z.ws);
     aT = zadv(aT, z.ws);
+    if (abd) abd = zadv(abd, z.ws);
     lam_out = zadv(lam_out, z.ws);
     __shared__ float ut[UH * UW], ct[UH * UW];
     __shared__ float gt[GH * GW], dgx[GH * GW], dgy[GH * GW];
@@ -352,7 +397,7 @@ __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int
         if (y < H - 1) acc -= 0.5f * dgy[k + GW];
         if (y == 0) acc -= 0.5f * dgy[k];
         const size_t o = (size_t)y * W + x;
-        lam_out[o] = du[o] + aT[o] + acc;
+        lam_out[o] = du[o] + ext_or_border(aT, epitch, oy, ox, abd, y, x, H, W) + acc;
     }
 }
 
@@ -623,8 +668,7 @@ __global__ void __launch_bounds__(256) write_grads(const double* __restrict__ dh
 static size_t r256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 struct BwdLayout {
-    size_t list, qw, s, ab, c, du, ds, aT, lamA, lamB, dqw, ext, fold, part, apart, dh, da, total;
-    size_t wiener;  // start of the Wiener-adjoint region (reuses the iteration planes)
+    size_t list, qw, s, ab, c, du, ds, lamA, lamB, ext, bd2, bd1, part, apart, dh, da, total;
 };
 
 static int bwd_rad(const PsfDev& psf) { return tap_radius_class(max((psf.ph - 1) / 2, (psf.pw - 1) / 2)); }
@@ -667,18 +711,16 @@ static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
     L.c = o; o += pl;
     L.du = o; o += pl;
     L.ds = o; o += pl;
-    L.aT = o; o += pl;
     L.lamA = o; o += pl;
     L.lamB = o; o += pl;
-    L.dqw = o; o += pl2;
-    L.ext = o; o += ext2;
-    L.fold = o; o += r256((size_t)(H + 2 * cy) * W * 8);
+    L.ext = o; o += ext2;   // B^T (a, bb), then A^T ds: the extended grid (periodic: the image grid)
+    L.bd2 = o; o += r256((size_t)(2 * W + 2 * H) * 8);   // folded border values of B^T (a, bb)
+    L.bd1 = o; o += r256((size_t)(2 * W + 2 * H) * 4);   // and of A^T ds
     L.part = o; o += r256(nb_dh * psf.ph * psf.pw * 8);
     L.apart = o; o += r256(nb_it * 8);
     L.dh = o; o += r256((size_t)psf.ph * psf.pw * 8);
     L.da = o; o += 256;
     L.total = o;
-    L.wiener = L.qw;  // the Wiener adjoint runs after the iterations: reuse from qw on
     return L;
 }
 
@@ -687,12 +729,10 @@ size_t backward_ws_bytes(int H, int W, const PsfDev& psf, bool through_wiener)
     BwdLayout L = bwd_layout(H, W, psf);
     size_t need = L.total;
     if (through_wiener) {
+        // after the iteration planes (lam0 lives in lamA/lamB, dh/da are kept):
         // M, S1, S2, h^ (half planes, complex64) + u_pre, G, R (real planes)
         const size_t half = r256((size_t)H * (W / 2 + 1) * 8), pl = r256((size_t)H * W * 4);
-        const size_t w = L.wiener + 4 * half + 3 * pl;
-        // the Wiener region must not overlap lamA/lamB (lam0 lives there) or dh/da
-        need = std::max(need, L.total + 4 * half + 3 * pl);
-        (void)w;
+        need += 4 * half + 3 * pl;
     }
     return need;
 }
@@ -732,54 +772,43 @@ static void launch_bwd_iter(int B, const float* f, const float* u, const float* 
     float* c = reinterpret_cast<float*>(w8 + L.c);
     float* du = reinterpret_cast<float*>(w8 + L.du);
     float* ds = reinterpret_cast<float*>(w8 + L.ds);
-    float* aT = reinterpret_cast<float*>(w8 + L.aT);
-    float2* dqw = reinterpret_cast<float2*>(w8 + L.dqw);
     double* part = reinterpret_cast<double*>(w8 + L.part);
     double* apart = reinterpret_cast<double*>(w8 + L.apart);
     const int cy = (psf.ph - 1) / 2, cx = (psf.pw - 1) / 2;
     const bool per = p.bc == BC_PERIODIC;
     const size_t zw = z.ws;
+    // the transposed blurs' outputs: the extended grid (EH x EW, origin
+    // (-cy, -cx)) with the border folded into bd; periodic: the image grid
+    const int EH = per ? H : H + 2 * cy, EW = per ? W : W + 2 * cx;
+    const int oy = per ? 0 : cy, ox = per ? 0 : cx;
+    const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH, B);
+    const unsigned nbd = (unsigned)((2 * W + 2 * H + 255) / 256);
 
     launch_bwd_stage1<RAD>(B, f, u, qw, s, H, W, pitch, taps, nt, p, z, st);
     const dim3 gi((W + 63) / 64, (H + TH - 1) / TH, B);
     hipLaunchKernelGGL((adj_update<RAD, TH>), gi, dim3(BW_NT), 0, st, (const float2*)qw, u, lam, lam_pitch, ab, c,
                        du, apart, H, W, pitch, taps, nt, p, z, lam_z);
     // dq, dW = B^T (a, b)
-    if (per) {
-        hipLaunchKernelGGL((adj_stencil<RAD, TH, -1, float2>), gi, dim3(BW_NT), 0, st, (const float2*)ab, W, H, W, 1,
-                           dqw, W, 0, 0, H, W, taps, nt, zw);
-    } else {
-        float2* ext = reinterpret_cast<float2*>(w8 + L.ext);
-        const int EH = H + 2 * cy, EW = W + 2 * cx;
-        const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH, B);
-        hipLaunchKernelGGL((adj_stencil<RAD, TH, -1, float2>), ge, dim3(BW_NT), 0, st, (const float2*)ab, W, H, W, 0,
-                           ext, EW, -cy, -cx, EH, EW, taps, nt, zw);
-        float2* tmp = reinterpret_cast<float2*>(w8 + L.fold);
-        hipLaunchKernelGGL(adj_fold_x<float2>, dim3((W + 255) / 256, EH, B), dim3(256), 0, st, (const float2*)ext, EW,
-                           cx, W, tmp, zw);
-        hipLaunchKernelGGL(adj_fold_y<float2>, dim3((W + 255) / 256, H, B), dim3(256), 0, st, (const float2*)tmp, cy,
-                           H, W, dqw, W, zw);
-    }
-    hipLaunchKernelGGL(adj_point, dim3((W + 255) / 256, H, B), dim3(256), 0, st, (const float2*)dqw,
-                       (const float2*)qw, (const float*)s, f, grad_f, ds, H, W, pitch, p, z);
+    float2* ext2 = reinterpret_cast<float2*>(w8 + L.ext);
+    float2* bd2 = per ? nullptr : reinterpret_cast<float2*>(w8 + L.bd2);
+    hipLaunchKernelGGL((adj_stencil<RAD, TH, -1, float2>), ge, dim3(BW_NT), 0, st, (const float2*)ab, W, H, W,
+                       per ? 1 : 0, ext2, EW, -oy, -ox, EH, EW, taps, nt, zw);
+    if (!per)
+        hipLaunchKernelGGL(adj_fold_border<float2>, dim3(nbd, 1, B), dim3(256), 0, st, (const float2*)ext2, EW, cy, cx,
+                           H, W, bd2, zw);
+    hipLaunchKernelGGL(adj_point, dim3((W + 255) / 256, H, B), dim3(256), 0, st, (const float2*)ext2, EW, oy, ox,
+                       (const float2*)bd2, (const float2*)qw, (const float*)s, f, grad_f, ds, H, W, pitch, p, z);
     // A^T ds
-    if (per) {
-        hipLaunchKernelGGL((adj_stencil<RAD, TH, 1, float>), gi, dim3(BW_NT), 0, st, (const float*)ds, W, H, W, 1, aT,
-                           W, 0, 0, H, W, taps, nt, zw);
-    } else {
-        float* ext = reinterpret_cast<float*>(w8 + L.ext);
-        const int EH = H + 2 * cy, EW = W + 2 * cx;
-        const dim3 ge((EW + 63) / 64, (EH + TH - 1) / TH, B);
-        hipLaunchKernelGGL((adj_stencil<RAD, TH, 1, float>), ge, dim3(BW_NT), 0, st, (const float*)ds, W, H, W, 0, ext,
-                           EW, -cy, -cx, EH, EW, taps, nt, zw);
-        float* tmp = reinterpret_cast<float*>(w8 + L.fold);
-        hipLaunchKernelGGL(adj_fold_x<float>, dim3((W + 255) / 256, EH, B), dim3(256), 0, st, (const float*)ext, EW, cx,
-                           W, tmp, zw);
-        hipLaunchKernelGGL(adj_fold_y<float>, dim3((W + 255) / 256, H, B), dim3(256), 0, st, (const float*)tmp, cy, H,
-                           W, aT, W, zw);
-    }
+    float* ext1 = reinterpret_cast<float*>(w8 + L.ext);
+    float* bd1 = per ? nullptr : reinterpret_cast<float*>(w8 + L.bd1);
+    hipLaunchKernelGGL((adj_stencil<RAD, TH, 1, float>), ge, dim3(BW_NT), 0, st, (const float*)ds, W, H, W,
+                       per ? 1 : 0, ext1, EW, -oy, -ox, EH, EW, taps, nt, zw);
+    if (!per)
+        hipLaunchKernelGGL(adj_fold_border<float>, dim3(nbd, 1, B), dim3(256), 0, st, (const float*)ext1, EW, cy, cx, H,
+                           W, bd1, zw);
     hipLaunchKernelGGL((adj_tv<TH>), dim3((W + 63) / 64, (H + TH - 1) / TH, B), dim3(BW_NT), 0, st, u, pitch,
-                       (const float*)c, (const float*)du, (const float*)aT, lam_out, H, W, p, z);
+                       (const float*)c, (const float*)du, (const float*)ext1, EW, oy, ox, (const float*)bd1, lam_out,
+                       H, W, p, z);
     hipLaunchKernelGGL((adj_dh<RAD>), dim3((W + 63) / 64, (H + DH_TH - 1) / DH_TH, B), dim3(BW_NT), 0, st,
                        (const float2*)ab, (const float2*)qw, (const float*)ds, u, pitch, H, W, psf.ph, psf.pw, p.bc,
                        part, z);
