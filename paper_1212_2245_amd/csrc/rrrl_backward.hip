@@ -543,6 +543,134 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
     }
 }
 
+// The same partial sums on the matrix cores, for PSF arrays of at most 32 x 32
+// entries (radius class 16): one 32 x 32 block of lags covers the whole
+// array.  Written as products of matrices, for an image row y of the tile and
+// a column x' of the extended grid:
+//   a e   and  bb W :  D[dy][dx] += E(y + dy, x') * A(y, x' - dx)
+//   ds u           :  D[dy][dx] += U(y - dy, x') * S(y, x' + dx)
+// with A, S zero outside the tile.  K runs along x' two columns per
+// v_mfma_f32_32x32x2f32 (lane l: block row / column l mod 32, K index
+// l / 32; accumulator r holds row 8 (r/4) + 4 (l/32) + r mod 4, column
+// l mod 32).  Rows and columns of the block beyond the PSF read clamped
+// (in-range) operands and are discarded.  Each of the three products is
+// staged in turn (an extended tile of e, W or u; the tile of a, bb or ds
+// with zero margins of twice the radius), so two workgroups fit a CU.  A
+// wave takes every fourth tile row; the four waves' blocks are summed in a
+// fixed order (FP64) into this workgroup's slot of `part`.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+constexpr int DHM_TB = 16, DHM_TW = 256;
+
+template <int RAD>
+__global__ void __launch_bounds__(256) adj_dh_mfma(const float2* __restrict__ ab, const float2* __restrict__ qw,
+                                                   const float* __restrict__ ds, const float* __restrict__ u,
+                                                   int pitch, int H, int W, int ph, int pw, int bc,
+                                                   double* __restrict__ part, BwdZ z)
+{
+    constexpr int TB = DHM_TB, TW = DHM_TW;
+    constexpr int EH = TB + 2 * RAD, QP = TW + 2 * RAD + 1, AP = TW + 4 * RAD + 1;   // odd pitches
+    // K steps run in groups of eight (rounded up) with the next group read
+    // ahead: reads pass the end of a row by at most 29 columns, into the next
+    // row or a zeroed tail.  A step past the useful columns multiplies by the
+    // zero margin of the tile plane (2 RAD >= 32 zero columns on each side).
+    constexpr int TAIL = 64;
+    static_assert(2 * RAD >= 30 && 4 * 1024 <= EH * QP, "margins and reduction space");
+    __shared__ float qe[EH * QP + TAIL];   // columns x0 - RAD .., rows y0 - RAD ..
+    __shared__ float at[TB * AP + TAIL];   // columns x0 - 2 RAD .., rows y0 ..
+    ab = zadv(ab, z.ws);
+    qw = zadv(qw, z.ws);
+    ds = zadv(ds, z.ws);
+    u = zadv(u, z.ck);
+    part = zadv(part, z.ws);
+    const int2 txy = xcd_tile();
+    const int x0 = txy.x * TW, y0 = txy.y * TB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int bi = lane & 31, k = lane >> 5;
+    const int cy = (ph - 1) / 2, cx = (pw - 1) / 2;
+    const int dy = min(bi - cy, cy), dx = min(bi - cx, cx);   // this lane's lags (clamped beyond the PSF)
+    const int c_lo = (RAD - cx) & ~1, c_hi = RAD + TW + cx;   // columns x' with a non-zero product
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    if (tid < TAIL) {
+        qe[EH * QP + tid] = 0.0f;
+        at[TB * AP + tid] = 0.0f;
+    }
+
+    for (int phase = 0; phase < 3; ++phase) {
+        if (phase) __syncthreads();
+        // eight loads in flight per thread (a fully unrolled copy would hold
+        // the whole tile in registers)
+        stage_to_lds_n<8>(qe, EH * QP, [&](int idx) {
+            const int r = idx / QP, c = idx - r * QP;
+            const int gy = ext_index(y0 - RAD + r, H, bc), gx = ext_index(x0 - RAD + min(c, QP - 2), W, bc);
+            return phase == 2 ? u[(size_t)gy * pitch + gx] : (phase == 0 ? qw[(size_t)gy * W + gx].x
+                                                                          : qw[(size_t)gy * W + gx].y);
+        });
+        stage_to_lds_n<8>(at, TB * AP, [&](int idx) {
+            const int t = idx / AP, x = x0 - 2 * RAD + (idx - t * AP), y = y0 + t;
+            if (y >= H || x < x0 || x >= x0 + TW || x >= W) return 0.0f;
+            const size_t o = (size_t)y * W + x;
+            return phase == 2 ? ds[o] : (phase == 0 ? ab[o].x : ab[o].y);
+        });
+        __syncthreads();
+        const int sy = phase == 2 ? -dy : dy, sx = phase == 2 ? dx : -dx;
+        const int steps8 = (((c_hi - c_lo + 1) >> 1) + 7) & ~7;
+        for (int t = wave; t < TB; t += 4) {
+            if (y0 + t >= H) break;
+            const float* ar = qe + (t + RAD + sy) * QP + k + c_lo;
+            const float* br = at + t * AP + RAD + sx + k + c_lo;
+            // software pipeline: the operands of the next eight K steps are
+            // read from LDS while the current eight run on the matrix core
+            float a[8], b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                a[q] = ar[2 * q];
+                b[q] = br[2 * q];
+            }
+            for (int n = 0; n < steps8; n += 8) {
+                float a2[8], b2[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    a2[q] = ar[2 * (n + 8 + q)];
+                    b2[q] = br[2 * (n + 8 + q)];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], b[q], acc, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    a[q] = a2[q];
+                    b[q] = b2[q];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    float* red = qe;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[wave * 1024 + (8 * (r >> 2) + 4 * k + (r & 3)) * 32 + bi] = acc[r];
+    __syncthreads();
+    const size_t base = (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * ph * pw;
+    for (int o = tid; o < 1024; o += 256) {
+        const int j = o >> 5, i = o & 31;
+        if (j < ph && i < pw) {
+            double sum = 0.0;
+            for (int w = 0; w < 4; ++w) sum += (double)red[w * 1024 + o];
+            part[base + j * pw + i] += sum;
+        }
+    }
+}
+
+// The dL/dh kernel for a PSF: the matrix-core one for arrays of at most
+// 32 x 32 entries in radius class 16, else the vector one; and its number of
+// workgroups (partial-sum slots) per image.
+static bool dh_on_mfma(const PsfDev& psf, int rad) { return rad == 16 && psf.ph <= 32 && psf.pw <= 32; }
+static size_t dh_blocks(int H, int W, const PsfDev& psf, int rad)
+{
+    if (dh_on_mfma(psf, rad)) return (size_t)((W + DHM_TW - 1) / DHM_TW) * ((H + DHM_TB - 1) / DHM_TB);
+    return (size_t)((W + 63) / 64) * ((H + DH_TH - 1) / DH_TH);
+}
+
 // Fixed-order reduction of the per-workgroup partial sums.
 __global__ void __launch_bounds__(256) adj_reduce(const double* __restrict__ part, int nblocks, int PP,
                                                   const double* __restrict__ alpha_part, int nalpha,
@@ -702,7 +830,7 @@ static BwdLayout bwd_layout(int H, int W, const PsfDev& psf)
     const size_t pl = r256((size_t)H * W * 4), pl2 = r256((size_t)H * W * 8);
     const size_t ext2 = r256((size_t)(H + 2 * cy) * (W + 2 * cx) * 8);
     const size_t nb_it = (size_t)((W + 63) / 64) * H;      // dL/dalpha slots: per image row and 64 columns
-    const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + DH_TH - 1) / DH_TH);
+    const size_t nb_dh = dh_blocks(H, W, psf, bwd_rad(psf));
     size_t o = 0;
     L.list = o; o += r256(tap_list_bytes(psf));
     L.qw = o; o += pl2;
@@ -809,6 +937,14 @@ static void launch_bwd_iter(int B, const float* f, const float* u, const float* 
     hipLaunchKernelGGL((adj_tv<TH>), dim3((W + 63) / 64, (H + TH - 1) / TH, B), dim3(BW_NT), 0, st, u, pitch,
                        (const float*)c, (const float*)du, (const float*)ext1, EW, oy, ox, (const float*)bd1, lam_out,
                        H, W, p, z);
+    if constexpr (RAD == 16) {
+        if (dh_on_mfma(psf, RAD)) {
+            hipLaunchKernelGGL((adj_dh_mfma<RAD>), dim3((W + DHM_TW - 1) / DHM_TW, (H + DHM_TB - 1) / DHM_TB, B),
+                               dim3(256), 0, st, (const float2*)ab, (const float2*)qw, (const float*)ds, u, pitch, H, W,
+                               psf.ph, psf.pw, p.bc, part, z);
+            return;
+        }
+    }
     hipLaunchKernelGGL((adj_dh<RAD>), dim3((W + 63) / 64, (H + DH_TH - 1) / DH_TH, B), dim3(BW_NT), 0, st,
                        (const float2*)ab, (const float2*)qw, (const float*)ds, u, pitch, H, W, psf.ph, psf.pw, p.bc,
                        part, z);
@@ -856,7 +992,7 @@ int launch_rrrl_backward_batch(int B, const float* f, const float* ckpt, const f
     const BwdZ z{ws_stride, img_stride, ck_stride, alpha};
     const size_t zw = ws_stride;
     const size_t nb_it = (size_t)((W + 63) / 64) * H;
-    const size_t nb_dh = (size_t)((W + 63) / 64) * ((H + DH_TH - 1) / DH_TH);
+    const size_t nb_dh = dh_blocks(H, W, psf, rad);
     double* part = reinterpret_cast<double*>(w8 + L.part);
     double* apart = reinterpret_cast<double*>(w8 + L.apart);
     double* dh = reinterpret_cast<double*>(w8 + L.dh);
