@@ -556,13 +556,13 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
 // (in-range) operands and are discarded.  Each of the three products is
 // staged in turn (an extended tile of e, W or u; the tile of a, bb or ds
 // with zero margins of twice the radius), so two workgroups fit a CU.  A
-// wave takes every fourth tile row; the four waves' blocks are summed in a
+// wave takes every eighth tile row; the eight waves' blocks are summed in a
 // fixed order (FP64) into this workgroup's slot of `part`.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
-constexpr int DHM_TB = 16, DHM_TW = 256;
+constexpr int DHM_TB = 16, DHM_TW = 256, DHM_NT = 512, DHM_WAVES = DHM_NT / 64;
 
 template <int RAD>
-__global__ void __launch_bounds__(256) adj_dh_mfma(const float2* __restrict__ ab, const float2* __restrict__ qw,
+__global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__ ab, const float2* __restrict__ qw,
                                                    const float* __restrict__ ds, const float* __restrict__ u,
                                                    int pitch, int H, int W, int ph, int pw, int bc,
                                                    double* __restrict__ part, BwdZ z)
@@ -574,7 +574,7 @@ __global__ void __launch_bounds__(256) adj_dh_mfma(const float2* __restrict__ ab
     // row or a zeroed tail.  A step past the useful columns multiplies by the
     // zero margin of the tile plane (2 RAD >= 32 zero columns on each side).
     constexpr int TAIL = 64;
-    static_assert(2 * RAD >= 30 && 4 * 1024 <= EH * QP, "margins and reduction space");
+    static_assert(2 * RAD >= 30 && DHM_WAVES * 1024 <= EH * QP, "margins and reduction space");
     __shared__ float qe[EH * QP + TAIL];   // columns x0 - RAD .., rows y0 - RAD ..
     __shared__ float at[TB * AP + TAIL];   // columns x0 - 2 RAD .., rows y0 ..
     ab = zadv(ab, z.ws);
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(256) adj_dh_mfma(const float2* __restrict__ ab
         __syncthreads();
         const int sy = phase == 2 ? -dy : dy, sx = phase == 2 ? dx : -dx;
         const int steps8 = (((c_hi - c_lo + 1) >> 1) + 7) & ~7;
-        for (int t = wave; t < TB; t += 4) {
+        for (int t = wave; t < TB; t += DHM_WAVES) {
             if (y0 + t >= H) break;
             const float* ar = qe + (t + RAD + sy) * QP + k + c_lo;
             const float* br = at + t * AP + RAD + sx + k + c_lo;
@@ -651,11 +651,11 @@ __global__ void __launch_bounds__(256) adj_dh_mfma(const float2* __restrict__ ab
     for (int r = 0; r < 16; ++r) red[wave * 1024 + (8 * (r >> 2) + 4 * k + (r & 3)) * 32 + bi] = acc[r];
     __syncthreads();
     const size_t base = (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * ph * pw;
-    for (int o = tid; o < 1024; o += 256) {
+    for (int o = tid; o < 1024; o += DHM_NT) {
         const int j = o >> 5, i = o & 31;
         if (j < ph && i < pw) {
             double sum = 0.0;
-            for (int w = 0; w < 4; ++w) sum += (double)red[w * 1024 + o];
+            for (int w = 0; w < DHM_WAVES; ++w) sum += (double)red[w * 1024 + o];
             part[base + j * pw + i] += sum;
         }
     }
@@ -940,7 +940,7 @@ static void launch_bwd_iter(int B, const float* f, const float* u, const float* 
     if constexpr (RAD == 16) {
         if (dh_on_mfma(psf, RAD)) {
             hipLaunchKernelGGL((adj_dh_mfma<RAD>), dim3((W + DHM_TW - 1) / DHM_TW, (H + DHM_TB - 1) / DHM_TB, B),
-                               dim3(256), 0, st, (const float2*)ab, (const float2*)qw, (const float*)ds, u, pitch, H, W,
+                               dim3(DHM_NT), 0, st, (const float2*)ab, (const float2*)qw, (const float*)ds, u, pitch, H, W,
                                psf.ph, psf.pw, p.bc, part, z);
             return;
         }
