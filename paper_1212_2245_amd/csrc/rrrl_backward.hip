@@ -89,15 +89,38 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
     const int tid = threadIdx.x;
     int cnt[TAP_GROUP_MAX];
     load_groups<RAD>(pk, pkg, hdr, cnt);
-    stage_to_lds<BW_NT, LH * LW>(qt, [&](int idx) {
-        const int ly = idx / LW, lx = idx - ly * LW;
-        const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
-        return qw[(size_t)gy * W + gx];
-    });
-    stage_to_lds<BW_NT, UH * UW>(ut, [&](int idx) {
-        const int ly = idx / UW, lx = idx - ly * UW;
-        return u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
-    });
+    // tiles whose halo lies inside the image need no continuation: plain row
+    // copies (16-byte loads of two (e, W) pairs from an even column)
+    const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
+    if (inner && W % 2 == 0 && ((uintptr_t)qw & 15) == 0) {
+        copy_rows_f4<BW_NT, LH, 2 * LW>(reinterpret_cast<float*>(qt),
+                                        reinterpret_cast<const float*>(qw + (size_t)(y0 - RAD) * W + (x0 - RAD)),
+                                        2 * (size_t)W);
+    } else if (inner) {
+        const float2* src = qw + (size_t)(y0 - RAD) * W + (x0 - RAD);
+        stage_to_lds<BW_NT, LH * LW>(qt, [&](int idx) {
+            const int ly = idx / LW;
+            return src[(size_t)ly * W + (idx - ly * LW)];
+        });
+    } else {
+        stage_to_lds<BW_NT, LH * LW>(qt, [&](int idx) {
+            const int ly = idx / LW, lx = idx - ly * LW;
+            const int gy = ext_index(y0 - RAD + ly, H, p.bc), gx = ext_index(x0 - RAD + lx, W, p.bc);
+            return qw[(size_t)gy * W + gx];
+        });
+    }
+    if (inner) {
+        const float* src = u + (size_t)(y0 - 2) * pitch + (x0 - 2);
+        stage_to_lds<BW_NT, UH * UW>(ut, [&](int idx) {
+            const int ly = idx / UW;
+            return src[(size_t)ly * pitch + (idx - ly * UW)];
+        });
+    } else {
+        stage_to_lds<BW_NT, UH * UW>(ut, [&](int idx) {
+            const int ly = idx / UW, lx = idx - ly * UW;
+            return u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
+        });
+    }
     __syncthreads();
     for (int idx = tid; idx < GH * GW; idx += BW_NT) {
         const int a = idx / GW, b = idx - a * GW;
@@ -170,7 +193,14 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
     const int tid = threadIdx.x;
     int cnt[TAP_GROUP_MAX];
     load_groups<RAD>(pk, pkg, hdr, cnt);
-    stage_to_lds<BW_NT, LH * LW>(vt, [&](int idx) {
+    const bool inner = zy0 >= RAD && zx0 >= RAD && zy0 + TH + RAD <= H && zx0 + TW + RAD <= W;
+    if (inner) {   // the window lies inside the input: plain row copies
+        const T* src = v + (size_t)(zy0 - RAD) * vpitch + (zx0 - RAD);
+        stage_to_lds<BW_NT, LH * LW>(vt, [&](int idx) {
+            const int ly = idx / LW;
+            return src[(size_t)ly * vpitch + (idx - ly * LW)];
+        });
+    } else stage_to_lds<BW_NT, LH * LW>(vt, [&](int idx) {
         const int ly = idx / LW, lx = idx - ly * LW;
         int gy = zy0 - RAD + ly, gx = zx0 - RAD + lx;
         T val{};
@@ -350,14 +380,27 @@ __global__ void __launch_bounds__(BW_NT) adj_tv(const float* __restrict__ u, int
     const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
     const int x0 = tile_xy.x * TW, y0 = tile_xy.y * TH;
     const int tid = threadIdx.x;
-    stage_to_lds<BW_NT, UH * UW>(ut, [&](int idx) {
-        const int ly = idx / UW, lx = idx - ly * UW;
-        return u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
-    });
-    stage_to_lds<BW_NT, UH * UW>(ct, [&](int idx) {
-        const int ly = idx / UW, lx = idx - ly * UW;
-        return cpl[(size_t)clampi(y0 - 2 + ly, H) * W + clampi(x0 - 2 + lx, W)];
-    });
+    if (x0 >= 2 && y0 >= 2 && x0 + TW + 2 <= W && y0 + TH + 2 <= H) {   // no clamping needed
+        const float* su = u + (size_t)(y0 - 2) * pitch + (x0 - 2);
+        const float* sc = cpl + (size_t)(y0 - 2) * W + (x0 - 2);
+        stage_to_lds<BW_NT, UH * UW>(ut, [&](int idx) {
+            const int ly = idx / UW;
+            return su[(size_t)ly * pitch + (idx - ly * UW)];
+        });
+        stage_to_lds<BW_NT, UH * UW>(ct, [&](int idx) {
+            const int ly = idx / UW;
+            return sc[(size_t)ly * W + (idx - ly * UW)];
+        });
+    } else {
+        stage_to_lds<BW_NT, UH * UW>(ut, [&](int idx) {
+            const int ly = idx / UW, lx = idx - ly * UW;
+            return u[(size_t)clampi(y0 - 2 + ly, H) * pitch + clampi(x0 - 2 + lx, W)];
+        });
+        stage_to_lds<BW_NT, UH * UW>(ct, [&](int idx) {
+            const int ly = idx / UW, lx = idx - ly * UW;
+            return cpl[(size_t)clampi(y0 - 2 + ly, H) * W + clampi(x0 - 2 + lx, W)];
+        });
+    }
     __syncthreads();
     // at grid points (y0-1+a, x0-1+b): g, and dL/dgx, dL/dgy through g
     for (int idx = tid; idx < GH * GW; idx += BW_NT) {
