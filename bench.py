@@ -102,6 +102,8 @@ def parse_args():
     ap.add_argument("--solo-calls", type=int, default=0,
                     help="with --summarize-trace: launches per class kernel on the bench's timing stream")
     ap.add_argument("--command", default="", help="command line recorded in summaries")
+    ap.add_argument("--only-grad", action="store_true",
+                    help="run only the differentiation workload (forward + backward timings) and print its JSON")
     ap.add_argument("--quality", action="store_true",
                     help="print the SNR table of the methods on the Table 1 stand-ins (one JSON line) and exit")
     return ap.parse_args()
@@ -661,6 +663,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only_grad:
+        print(json.dumps({"grad512x64": config4(dev, args)}), flush=True)
+        return
 
     t0 = time.perf_counter()
     cases, items = batch_workload(dev, args.batch_images)
