@@ -25,6 +25,9 @@ CASES = [
     ("no_iterations", 4, 64, 64, 64, "random", False, True, dbl.BC_REPLICATE, 0, True),
     ("box_shared", 3, 48, 64, 72, "box", True, True, dbl.BC_REPLICATE, 2, True),
     ("dense_r32", 2, 96, 96, 96, "dense", False, True, dbl.BC_REPLICATE, 2, False),
+    # 32 x 512^2: the batch's default tile rows switch to 16 (the one-image calls keep 8) and dL/dh
+    # runs on the matrix cores over two column tiles per image
+    ("large_batch_default_rows", 32, 512, 512, 512, "line", False, True, dbl.BC_REPLICATE, 2, True),
 ]
 
 

@@ -67,6 +67,8 @@ ITER_CASES = [
     ("box_runsum", "box_h", 4, 48, 64, 72, 2, True, True, True, dbl.BC_REPLICATE, dbl.CONV_AUTO),
     ("box_frac_stencil", "box_v_frac", 3, 40, 64, 64, 3, False, True, True, dbl.BC_REPLICATE, dbl.CONV_STENCIL),
     ("no_iterations", "lines", 3, 32, 64, 64, 0, False, False, True, dbl.BC_REPLICATE, dbl.CONV_AUTO),
+    # 16 x 512^2: the batch's default stencil tile switches to 32 rows (the one-image calls take 16)
+    ("large_batch", "lines", 16, 512, 512, 512, 2, True, True, True, dbl.BC_REPLICATE, dbl.CONV_AUTO),
 ]
 
 
