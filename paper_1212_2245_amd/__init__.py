@@ -490,11 +490,12 @@ class WR3LFunction(torch.autograd.Function):
         u = torch.empty_like(fb)
         ck = torch.empty((B, max(iters, 1), H, W), dtype=torch.float32, device=f.device)
         plist = [dataclasses.replace(base, alpha=alphas[i], iters=int(iters)) for i in range(B)]
-        ad = torch.tensor(alphas, dtype=torch.float32).to(f.device)
+        # one upload of the weights (pinned, without blocking the host), kept for the backward
+        ad = torch.tensor(alphas, dtype=torch.float32).pin_memory().to(f.device, non_blocking=True)
         deblur_wiener_batch(fb, u, tb, K, pos_floor, fp64=True)
         deblur_rrrl_iterate_batch(fb, u, u, tb, plist[0], alpha=ad, ckpt=ck if iters > 0 else None)
         ctx.save_for_backward(fb, tb, ck)
-        ctx.plist, ctx.K, ctx.pos_floor = plist, K, pos_floor
+        ctx.plist, ctx.K, ctx.pos_floor, ctx.alpha_dev = plist, K, pos_floor, ad
         ctx.batched, ctx.shared_taps = batched, taps.dim() == 2
         ctx.alpha_shape = a.numel()
         ctx.alpha_like = alpha if isinstance(alpha, torch.Tensor) else None
@@ -505,8 +506,7 @@ class WR3LFunction(torch.autograd.Function):
         fb, tb, ck = ctx.saved_tensors
         gb = (grad_u if ctx.batched else grad_u.unsqueeze(0)).contiguous()
         p0 = ctx.plist[0]
-        alphas = torch.tensor([p.alpha for p in ctx.plist], dtype=torch.float32).to(fb.device)
-        g = deblur_rrrl_backward_batch(fb, ck if p0.iters > 0 else None, gb, tb, p0, alpha=alphas,
+        g = deblur_rrrl_backward_batch(fb, ck if p0.iters > 0 else None, gb, tb, p0, alpha=ctx.alpha_dev,
                                        through_wiener=True, K=ctx.K, pos_floor=ctx.pos_floor)
         gf, gt, ga = g["f"], g["taps"], g["alpha"]
         if ctx.shared_taps:

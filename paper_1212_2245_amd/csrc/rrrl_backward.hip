@@ -909,7 +909,8 @@ size_t backward_ws_bytes(int H, int W, const PsfDev& psf, bool through_wiener)
 }
 
 // Stage-1 tile shape of the recomputation: by the tiles of the whole batch
-// (every shape gives the same bits), as the forward picks its default.
+// (every shape gives the same bits), as the forward picks its default (a
+// large batch of several images: 32 x 512).
 template <int RAD>
 static void launch_bwd_stage1(int B, const float* f, const float* u, float2* qw, float* s, int H, int W, int pitch,
                               const float* taps, const int* nt, const IterParams& p, const BwdZ& z, hipStream_t st)
@@ -920,7 +921,9 @@ static void launch_bwd_stage1(int B, const float* f, const float* u, float2* qw,
         const dim3 g((W + 63) / 64, (H + TH - 1) / TH, B);
         hipLaunchKernelGGL((bwd_stage1<RAD, TH, NT>), g, dim3(NT), 0, st, u, f, qw, s, H, W, pitch, taps, nt, p, z);
     };
-    if (tiles64 >= 1024)
+    if (tiles64 >= 1024 && B > 1)
+        go(std::integral_constant<int, 32>{}, std::integral_constant<int, 512>{});
+    else if (tiles64 >= 1024)
         go(std::integral_constant<int, 32>{}, std::integral_constant<int, 256>{});
     else if (tiles64 >= 256)
         go(std::integral_constant<int, 32>{}, std::integral_constant<int, 512>{});
