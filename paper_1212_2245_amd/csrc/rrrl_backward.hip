@@ -83,12 +83,14 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
     __shared__ float2 qt[LH * LW];
     __shared__ float ut[UH * UW];
     __shared__ float gt[GH * GW];
-    __shared__ float pk[packed_words_max<RAD>()];
     const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
     const int x0 = tile_xy.x * TW, y0 = tile_xy.y * TH;
     const int tid = threadIdx.x;
+    // the packed taps are read in place (wave-uniform addresses: scalar
+    // loads), which leaves LDS for three workgroups per CU at 16 rows
     int cnt[TAP_GROUP_MAX];
-    load_groups<RAD>(pk, pkg, hdr, cnt);
+#pragma unroll
+    for (int q = 0; q < TAP_GROUP_MAX; ++q) cnt[q] = hdr[2 + q];
     // tiles whose halo lies inside the image need no continuation: plain row
     // copies (16-byte loads of two (e, W) pairs from an even column)
     const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
@@ -132,7 +134,7 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
     float2 nn[R];   // (N3, N2) = B (e, W)
 #pragma unroll
     for (int i = 0; i < R; ++i) nn[i] = make_float2(0.0f, 0.0f);
-    stencil_groups<1, R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, pk, cnt, nn);
+    stencil_groups<1, R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, pkg, cnt, nn);
     __syncthreads();
     const int x = x0 + tx;
     const int ntx = (W + TW - 1) / TW;
