@@ -78,8 +78,8 @@ __global__ void __launch_bounds__(NT) batch_stage1(const BatchTile* __restrict__
     __shared__ float pk[packed_words_max<RAD>()];
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
-    stage1_tile<RAD, TH, NT>(tile, pk, im.buf[src], im.f, im.qw, nullptr, im.H, im.W, im.pitch, t.x0, t.y0, im.taps,
-                             im.hdr, im.p);
+    stage1_tile<RAD, TH, NT>(tile, pk, global_ptr(im.buf[src]), global_ptr(im.f), global_ptr(im.qw), nullptr, im.H,
+                             im.W, im.pitch, t.x0, t.y0, global_ptr(im.taps), global_ptr(im.hdr), im.p);
 }
 
 template <int RAD, int TH, int NT>
@@ -90,8 +90,8 @@ __global__ void __launch_bounds__(NT) batch_stage2(const BatchTile* __restrict__
     __shared__ Stage2Smem<RAD, TH> sm;
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
-    stage2_tile<RAD, TH, NT>(sm, im.qw, im.buf[src], im.buf[1 - src], nullptr, im.H, im.W, im.pitch, t.x0, t.y0,
-                             im.taps, im.hdr, im.p);
+    stage2_tile<RAD, TH, NT>(sm, global_ptr(im.qw), global_ptr(im.buf[src]), global_ptr(im.buf[1 - src]), nullptr,
+                             im.H, im.W, im.pitch, t.x0, t.y0, global_ptr(im.taps), global_ptr(im.hdr), im.p);
     count_tile(im, t.img, cnt, ts);
 }
 
@@ -109,7 +109,8 @@ __global__ void __launch_bounds__(BOX_NT) batch_box(const BatchTile* __restrict_
     const BatchTile t = tiles[blockIdx.x];
     const BatchImg& im = imgs[t.img];
     const BoxGeom g = box_geom<VERT, TA, TC>(im.H, im.W, im.L, im.frac);
-    box_seg_tile<VERT, TA, TC>(box_lds, im.buf[src], im.f, im.buf[1 - src], nullptr, im.pitch, g, im.p, t.x0, t.y0);
+    box_seg_tile<VERT, TA, TC>(box_lds, global_ptr(im.buf[src]), global_ptr(im.f), global_ptr(im.buf[1 - src]),
+                               nullptr, im.pitch, g, im.p, t.x0, t.y0);
     count_tile(im, t.img, cnt, ts);
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define DEBLUR_DEV __device__ __forceinline__
 
 namespace deblur {
@@ -39,10 +41,26 @@ DEBLUR_DEV int clampi(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
 // Launches over a batch of equally shaped images take the image index from
 // blockIdx.z: image z's plane is the first image's advanced by z times a
 // byte stride (stride 0: one plane shared by the batch).
+// A pointer read from device memory (a descriptor of a batched launch) is
+// generic to the compiler, which then emits flat accesses (slower, and
+// counted with the LDS operations, so an LDS wait also waits for them).
+// Every such pointer here addresses global memory: the cast lets the
+// compiler emit global accesses.
+template <typename T>
+DEBLUR_DEV T* global_ptr(T* p)
+{
+    using G = __attribute__((address_space(1))) T;
+    G* g = (G*)(uintptr_t)p;   // the same address, as a global-space pointer
+    return (T*)g;
+}
+
+// (Byte-pointer arithmetic, not an integer round trip: the compiler keeps
+// the pointer's global address space and emits global, not flat, accesses.)
 template <typename T>
 DEBLUR_DEV T* zadv(T* p, size_t stride)
 {
-    return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (size_t)blockIdx.z * stride);
+    using B = typename std::conditional<std::is_const<T>::value, const unsigned char, unsigned char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (size_t)blockIdx.z * stride);
 }
 
 // Cooperative copy of N elements into LDS: lds[idx] = fetch(idx), idx < N,

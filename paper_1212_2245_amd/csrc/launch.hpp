@@ -56,7 +56,7 @@ DEBLUR_DEV float rf_lookup(float f, float s, const float* __restrict__ lut)
 // lookup mode.
 DEBLUR_DEV float rf_eval(float f, float s, const IterParams& p)
 {
-    return p.r1_lut ? rf_lookup(f, s, p.r1_lut) : info_div(f, s);
+    return p.r1_lut ? rf_lookup(f, s, global_ptr(p.r1_lut)) : info_div(f, s);
 }
 
 // Diffusivity g = 2 Psi'(z), z = |grad u|^2, in the scaling of the data

@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) build_tap_list(PsfDev psf, int4* __restri
                                                       int* __restrict__ hdr, size_t zt, size_t zl)
 {
     // blockIdx.z = PSF of a batch (byte strides of the taps and of the lists)
-    if (psf.taps) psf.taps = zadv(psf.taps, zt);
+    if (psf.taps) psf.taps = global_ptr(zadv(psf.taps, zt));
     list = zadv(list, zl);
     groups = zadv(groups, zl);
     packed = zadv(packed, zl);
