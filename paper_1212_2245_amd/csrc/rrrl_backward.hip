@@ -189,12 +189,13 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
     pkg = zadv(pkg, zws);
     hdr = zadv(hdr, zws);
     __shared__ T vt[LH * LW];
-    __shared__ float pk[packed_words_max<RAD>()];
     const int2 tile_xy = xcd_tile();   // XCD-aware tile order (halo rows share an L2)
     const int zx0 = ox + tile_xy.x * TW, zy0 = oy + tile_xy.y * TH;
     const int tid = threadIdx.x;
+    // the packed taps are read in place (wave-uniform addresses: scalar loads)
     int cnt[TAP_GROUP_MAX];
-    load_groups<RAD>(pk, pkg, hdr, cnt);
+#pragma unroll
+    for (int q = 0; q < TAP_GROUP_MAX; ++q) cnt[q] = hdr[2 + q];
     const bool inner = zy0 >= RAD && zx0 >= RAD && zy0 + TH + RAD <= H && zx0 + TW + RAD <= W;
     if (inner) {   // the window lies inside the input: plain row copies
         const T* src = v + (size_t)(zy0 - RAD) * vpitch + (zx0 - RAD);
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
     T acc[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) acc[i] = T{};
-    stencil_groups<SIGN, R, LW>(vt + (ty * R + RAD) * LW + tx + RAD, pk, cnt, acc);
+    stencil_groups<SIGN, R, LW>(vt + (ty * R + RAD) * LW + tx + RAD, pkg, cnt, acc);
     const int zx = zx0 + tx;
     if (zx >= ox + OW) return;
 #pragma unroll
