@@ -93,9 +93,6 @@ static_assert(sizeof(TapGroup) == 48, "three 16-byte words per group");
 constexpr int TAP_GROUP_MAX = 8;
 inline size_t tap_groups_offset(int ph, int pw) { return 256 + 16 * (size_t)ph * pw; }
 inline size_t tap_packed_offset(int ph, int pw) { return tap_groups_offset(ph, pw) + 48 * (size_t)ph * pw; }
-// LDS words for the packed groups of any PSF of radius class RAD
-template <int RAD>
-constexpr int packed_words_max() { return 2 * (2 * RAD + 1) * (2 * RAD + 1); }
 
 // Wiener step; fp64: M, spectra and transforms in FP64 (output rounded once).
 size_t wiener_ws_bytes(int H, int W, bool rowwise, bool fp64 = false);

@@ -89,8 +89,7 @@ __global__ void __launch_bounds__(BW_NT) adj_update(const float2* __restrict__ q
     // the packed taps are read in place (wave-uniform addresses: scalar
     // loads), which leaves LDS for three workgroups per CU at 16 rows
     int cnt[TAP_GROUP_MAX];
-#pragma unroll
-    for (int q = 0; q < TAP_GROUP_MAX; ++q) cnt[q] = hdr[2 + q];
+    group_counts(hdr, cnt);
     // tiles whose halo lies inside the image need no continuation: plain row
     // copies (16-byte loads of two (e, W) pairs from an even column)
     const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
@@ -194,8 +193,7 @@ __global__ void __launch_bounds__(BW_NT) adj_stencil(const T* __restrict__ v, in
     const int tid = threadIdx.x;
     // the packed taps are read in place (wave-uniform addresses: scalar loads)
     int cnt[TAP_GROUP_MAX];
-#pragma unroll
-    for (int q = 0; q < TAP_GROUP_MAX; ++q) cnt[q] = hdr[2 + q];
+    group_counts(hdr, cnt);
     const bool inner = zy0 >= RAD && zx0 >= RAD && zy0 + TH + RAD <= H && zx0 + TW + RAD <= W;
     if (inner) {   // the window lies inside the input: plain row copies
         const T* src = v + (size_t)(zy0 - RAD) * vpitch + (zx0 - RAD);

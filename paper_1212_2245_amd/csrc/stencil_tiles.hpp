@@ -81,10 +81,11 @@ DEBLUR_DEV void group_fma_b(const float2* __restrict__ p, const float* w, float 
 
 // Sum over all column groups in list order (by run length, longest first,
 // then column-major): the order is the same for every tile shape, so the
-// result of a pixel does not depend on the tiling.  The groups are read from
-// the packed copy in LDS (pk: per group one word (dx & 0xffff) | (dy0 << 16)
-// and its S weights); cnt[S - 1] = number of groups of length S.  Each length
-// has its own loop (no per-group dispatch).
+// result of a pixel does not depend on the tiling.  The groups are read in
+// place from the compiled tap list (pk: per group one word (dx & 0xffff) |
+// (dy0 << 16) and its S weights; the addresses are the same for every lane,
+// so they are scalar loads and take no LDS); cnt[S - 1] = number of groups of
+// length S.  Each length has its own loop (no per-group dispatch).
 DEBLUR_DEV void unpack_offsets(const float* d, int& dx, int& dy0)
 {
     const int h = __builtin_amdgcn_readfirstlane(__float_as_int(d[0]));
@@ -167,15 +168,27 @@ DEBLUR_DEV void corr_groups(const float2* __restrict__ base, const float* __rest
     corr_class<1, R, LW>(base, pk, cnt[0], n1, n2);
 }
 
-// Copies the packed groups (hdr[10] words at pkg) into LDS and the eight
-// per-length counts into cnt (registers, uniform).
-template <int RAD>
-DEBLUR_DEV void load_groups(float* __restrict__ pk, const float* __restrict__ pkg, const int* __restrict__ hdr,
-                            int (&cnt)[TAP_GROUP_MAX])
+// The eight per-length group counts of a compiled PSF (registers, uniform).
+DEBLUR_DEV void group_counts(const int* __restrict__ hdr, int (&cnt)[TAP_GROUP_MAX])
 {
-    const int nw = min(hdr[10], packed_words_max<RAD>());
 #pragma unroll
     for (int q = 0; q < TAP_GROUP_MAX; ++q) cnt[q] = hdr[2 + q];
+}
+
+// The forward stage tiles read a sparse PSF's packed groups in place (scalar
+// loads) and stage a dense one's in LDS, where its many weights are read
+// faster (31x31 Gaussian at 2048^2: 357-361 us per iteration from LDS,
+// 395-402 us in place; the 31-pixel lines, about 100 words, gain in place).
+constexpr int DIRECT_TAP_WORDS = 512;
+template <int RAD>
+constexpr int packed_words_max() { return 2 * (2 * RAD + 1) * (2 * RAD + 1); }
+
+// Copies the packed groups (hdr[10] words at pkg) into LDS (at most pk's
+// capacity for the radius class).
+template <int RAD>
+DEBLUR_DEV void stage_groups(float* __restrict__ pk, const float* __restrict__ pkg, const int* __restrict__ hdr)
+{
+    const int nw = min(hdr[10], packed_words_max<RAD>());
     stage_to_lds_n<4>(pk, nw, [&](int i) { return pkg[i]; });
 }
 
@@ -252,7 +265,9 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, float* __restrict__ pk, co
         fr[i] = (x < W && y < H) ? f[(size_t)y * pitch + x] : 0.0f;
     }
     int cnt[TAP_GROUP_MAX];
-    load_groups<RAD>(pk, pkg, hdr, cnt);
+    group_counts(hdr, cnt);
+    const bool direct = hdr[10] <= DIRECT_TAP_WORDS;   // uniform: taps in place or staged
+    if (!direct) stage_groups<RAD>(pk, pkg, hdr);
     const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
     if (inner && pitch % 4 == 0 && ((uintptr_t)u & 15) == 0) {
         // rows start at x0 - RAD, a multiple of 4: 16-byte loads
@@ -279,7 +294,10 @@ DEBLUR_DEV void stage1_tile(float* __restrict__ tile, float* __restrict__ pk, co
     float acc[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) acc[i] = 0.0f;
-    blur_groups<R, LW>(tile + (ty * R + RAD) * LW + tx + RAD, pk, cnt, acc);   // A: E(u)(x - d)
+    if (direct)
+        blur_groups<R, LW>(tile + (ty * R + RAD) * LW + tx + RAD, pkg, cnt, acc);
+    else
+        blur_groups<R, LW>(tile + (ty * R + RAD) * LW + tx + RAD, pk, cnt, acc);   // A: E(u)(x - d)
     if (x >= W) return;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -342,7 +360,9 @@ DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ 
     float* __restrict__ gt = sm.gt;
     const int tid = threadIdx.x;
     int cnt[TAP_GROUP_MAX];
-    load_groups<RAD>(sm.pk, pkg, hdr, cnt);
+    group_counts(hdr, cnt);
+    const bool direct = hdr[10] <= DIRECT_TAP_WORDS;   // uniform: taps in place or staged
+    if (!direct) stage_groups<RAD>(sm.pk, pkg, hdr);
     const bool inner = x0 >= RAD && y0 >= RAD && x0 + TW + RAD <= W && y0 + TH + RAD <= H;
     if (inner && W % 2 == 0 && ((uintptr_t)qw & 15) == 0) {
         // (q, W) pairs from an even column: 16-byte loads of two pairs
@@ -383,7 +403,10 @@ DEBLUR_DEV void stage2_tile(Stage2Smem<RAD, TH>& sm, const float2* __restrict__ 
     float n1[R], n2[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) n1[i] = n2[i] = 0.0f;
-    corr_groups<R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, sm.pk, cnt, n1, n2);   // B: E(q, W)(x + d)
+    if (direct)
+        corr_groups<R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, pkg, cnt, n1, n2);   // B: E(q, W)(x + d)
+    else
+        corr_groups<R, LW>(qt + (ty * R + RAD) * LW + tx + RAD, sm.pk, cnt, n1, n2);
     __syncthreads();   // gt complete
     const int x = x0 + tx;
     if (x >= W) return;
