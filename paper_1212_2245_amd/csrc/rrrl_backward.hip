@@ -597,13 +597,16 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
 // v_mfma_f32_32x32x2f32 (lane l: block row / column l mod 32, K index
 // l / 32; accumulator r holds row 8 (r/4) + 4 (l/32) + r mod 4, column
 // l mod 32).  Rows and columns of the block beyond the PSF read clamped
-// (in-range) operands and are discarded.  Each of the three products is
-// staged in turn (an extended tile of e, W or u; the tile of a, bb or ds
-// with zero margins of twice the radius), so two workgroups fit a CU.  A
-// wave takes every eighth tile row; the eight waves' blocks are summed in a
-// fixed order (FP64) into this workgroup's slot of `part`.
+// (in-range) operands and are discarded.  A workgroup marches down a segment
+// of DHM_SEG rows of a 256-column strip, DHM_TB (= RAD) rows per step, for
+// each of the three products in turn: the extended rows of e, W or u are a
+// ring of three blocks of DHM_TB rows, and a step stages only the block that
+// enters its halo (plus the tile plane of a, bb or ds with zero margins of
+// twice the radius), so two workgroups fit a CU.  A wave takes every eighth
+// row of a step; the eight waves' blocks are summed in a fixed order (FP64)
+// into this workgroup's slot of `part`.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
-constexpr int DHM_TB = 16, DHM_TW = 256, DHM_NT = 512, DHM_WAVES = DHM_NT / 64;
+constexpr int DHM_TB = 16, DHM_TW = 256, DHM_NT = 512, DHM_WAVES = DHM_NT / 64, DHM_SEG = 128;
 
 template <int RAD>
 __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__ ab, const float2* __restrict__ qw,
@@ -612,79 +615,96 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
                                                    double* __restrict__ part, BwdZ z)
 {
     constexpr int TB = DHM_TB, TW = DHM_TW;
-    constexpr int EH = TB + 2 * RAD, QP = TW + 2 * RAD + 1, AP = TW + 4 * RAD + 1;   // odd pitches
+    static_assert(TB == RAD, "the halo of a step is one block of rows above and one below");
+    constexpr int QP = TW + 2 * RAD + 1, AP = TW + 4 * RAD + 1;   // odd pitches
     // K steps run in groups of eight (rounded up) with the next group read
     // ahead: reads pass the end of a row by at most 29 columns, into the next
     // row or a zeroed tail.  A step past the useful columns multiplies by the
     // zero margin of the tile plane (2 RAD >= 32 zero columns on each side).
     constexpr int TAIL = 64;
-    static_assert(2 * RAD >= 30 && DHM_WAVES * 1024 <= EH * QP, "margins and reduction space");
-    __shared__ float qe[EH * QP + TAIL];   // columns x0 - RAD .., rows y0 - RAD ..
-    __shared__ float at[TB * AP + TAIL];   // columns x0 - 2 RAD .., rows y0 ..
+    static_assert(2 * RAD >= 30 && DHM_WAVES * 1024 <= 3 * TB * QP, "margins and reduction space");
+    // extended rows as a ring of three blocks of TB rows (block b: rows
+    // ys - TB + TB b .., slot b mod 3); the tile plane of the current step
+    __shared__ float qe[3 * TB * QP + TAIL];   // columns x0 - RAD ..
+    __shared__ float at[TB * AP + TAIL];       // columns x0 - 2 RAD ..
     ab = zadv(ab, z.ws);
     qw = zadv(qw, z.ws);
     ds = zadv(ds, z.ws);
     u = zadv(u, z.ck);
     part = zadv(part, z.ws);
     const int2 txy = xcd_tile();
-    const int x0 = txy.x * TW, y0 = txy.y * TB;
+    const int x0 = txy.x * TW, ys = txy.y * DHM_SEG;
+    const int nsteps = (min(DHM_SEG, H - ys) + TB - 1) / TB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int bi = lane & 31, k = lane >> 5;
     const int cy = (ph - 1) / 2, cx = (pw - 1) / 2;
     const int dy = min(bi - cy, cy), dx = min(bi - cx, cx);   // this lane's lags (clamped beyond the PSF)
     const int c_lo = (RAD - cx) & ~1, c_hi = RAD + TW + cx;   // columns x' with a non-zero product
+    const int steps8 = (((c_hi - c_lo + 1) >> 1) + 7) & ~7;
     floatx16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
     if (tid < TAIL) {
-        qe[EH * QP + tid] = 0.0f;
+        qe[3 * TB * QP + tid] = 0.0f;
         at[TB * AP + tid] = 0.0f;
     }
-
-    for (int phase = 0; phase < 3; ++phase) {
-        if (phase) __syncthreads();
-        // eight loads in flight per thread (a fully unrolled copy would hold
-        // the whole tile in registers)
-        stage_to_lds_n<8>(qe, EH * QP, [&](int idx) {
+    // block b of the extended rows of product `phase` into its ring slot
+    auto stage_block = [&](int phase, int b) {
+        float* dst = qe + (b % 3) * TB * QP;
+        const int r0 = ys - TB + TB * b;
+        stage_to_lds_n<8>(dst, TB * QP, [&](int idx) {
             const int r = idx / QP, c = idx - r * QP;
-            const int gy = ext_index(y0 - RAD + r, H, bc), gx = ext_index(x0 - RAD + min(c, QP - 2), W, bc);
+            const int gy = ext_index(r0 + r, H, bc), gx = ext_index(x0 - RAD + min(c, QP - 2), W, bc);
             return phase == 2 ? u[(size_t)gy * pitch + gx] : (phase == 0 ? qw[(size_t)gy * W + gx].x
                                                                           : qw[(size_t)gy * W + gx].y);
         });
-        stage_to_lds_n<8>(at, TB * AP, [&](int idx) {
-            const int t = idx / AP, x = x0 - 2 * RAD + (idx - t * AP), y = y0 + t;
-            if (y >= H || x < x0 || x >= x0 + TW || x >= W) return 0.0f;
-            const size_t o = (size_t)y * W + x;
-            return phase == 2 ? ds[o] : (phase == 0 ? ab[o].x : ab[o].y);
-        });
-        __syncthreads();
+    };
+
+    for (int phase = 0; phase < 3; ++phase) {
         const int sy = phase == 2 ? -dy : dy, sx = phase == 2 ? dx : -dx;
-        const int steps8 = (((c_hi - c_lo + 1) >> 1) + 7) & ~7;
-        for (int t = wave; t < TB; t += DHM_WAVES) {
-            if (y0 + t >= H) break;
-            const float* ar = qe + (t + RAD + sy) * QP + k + c_lo;
-            const float* br = at + t * AP + RAD + sx + k + c_lo;
-            // software pipeline: the operands of the next eight K steps are
-            // read from LDS while the current eight run on the matrix core
-            float a[8], b[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                a[q] = ar[2 * q];
-                b[q] = br[2 * q];
+        for (int s = 0; s < nsteps; ++s) {
+            const int y0 = ys + TB * s;
+            __syncthreads();   // the previous step's reads of the slot and of the tile plane are done
+            if (s == 0) {
+                stage_block(phase, 0);
+                stage_block(phase, 1);
             }
-            for (int n = 0; n < steps8; n += 8) {
-                float a2[8], b2[8];
+            stage_block(phase, s + 2);
+            stage_to_lds_n<8>(at, TB * AP, [&](int idx) {
+                const int t = idx / AP, x = x0 - 2 * RAD + (idx - t * AP), y = y0 + t;
+                if (y >= H || x < x0 || x >= x0 + TW || x >= W) return 0.0f;
+                const size_t o = (size_t)y * W + x;
+                return phase == 2 ? ds[o] : (phase == 0 ? ab[o].x : ab[o].y);
+            });
+            __syncthreads();
+            for (int t = wave; t < TB; t += DHM_WAVES) {
+                if (y0 + t >= H) break;
+                // ring row of extended row y0 + t + sy (block-relative q)
+                const int q = TB + TB * s + t + sy;
+                const float* ar = qe + ((q / TB) % 3 * TB + q % TB) * QP + k + c_lo;
+                const float* br = at + t * AP + RAD + sx + k + c_lo;
+                // the operands of the next eight K steps are read from LDS
+                // while the current eight run on the matrix core
+                float a[8], b[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    a2[q] = ar[2 * (n + 8 + q)];
-                    b2[q] = br[2 * (n + 8 + q)];
+                for (int m = 0; m < 8; ++m) {
+                    a[m] = ar[2 * m];
+                    b[m] = br[2 * m];
                 }
+                for (int n = 0; n < steps8; n += 8) {
+                    float a2[8], b2[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], b[q], acc, 0, 0, 0);
+                    for (int m = 0; m < 8; ++m) {
+                        a2[m] = ar[2 * (n + 8 + m)];
+                        b2[m] = br[2 * (n + 8 + m)];
+                    }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    a[q] = a2[q];
-                    b[q] = b2[q];
+                    for (int m = 0; m < 8; ++m) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[m], b[m], acc, 0, 0, 0);
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        a[m] = a2[m];
+                        b[m] = b2[m];
+                    }
                 }
             }
         }
@@ -711,7 +731,7 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
 static bool dh_on_mfma(const PsfDev& psf, int rad) { return rad == 16 && psf.ph <= 32 && psf.pw <= 32; }
 static size_t dh_blocks(int H, int W, const PsfDev& psf, int rad)
 {
-    if (dh_on_mfma(psf, rad)) return (size_t)((W + DHM_TW - 1) / DHM_TW) * ((H + DHM_TB - 1) / DHM_TB);
+    if (dh_on_mfma(psf, rad)) return (size_t)((W + DHM_TW - 1) / DHM_TW) * ((H + DHM_SEG - 1) / DHM_SEG);
     return (size_t)((W + 63) / 64) * ((H + DH_TH - 1) / DH_TH);
 }
 
@@ -986,7 +1006,7 @@ static void launch_bwd_iter(int B, const float* f, const float* u, const float* 
                        H, W, p, z);
     if constexpr (RAD == 16) {
         if (dh_on_mfma(psf, RAD)) {
-            hipLaunchKernelGGL((adj_dh_mfma<RAD>), dim3((W + DHM_TW - 1) / DHM_TW, (H + DHM_TB - 1) / DHM_TB, B),
+            hipLaunchKernelGGL((adj_dh_mfma<RAD>), dim3((W + DHM_TW - 1) / DHM_TW, (H + DHM_SEG - 1) / DHM_SEG, B),
                                dim3(DHM_NT), 0, st, (const float2*)ab, (const float2*)qw, (const float*)ds, u, pitch, H, W,
                                psf.ph, psf.pw, p.bc, part, z);
             return;
