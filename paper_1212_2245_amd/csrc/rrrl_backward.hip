@@ -593,11 +593,17 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
 // a column x' of the extended grid:
 //   a e   and  bb W :  D[dy][dx] += E(y + dy, x') * A(y, x' - dx)
 //   ds u           :  D[dy][dx] += U(y - dy, x') * S(y, x' + dx)
-// with A, S zero outside the tile.  K runs along x' two columns per
-// v_mfma_f32_32x32x2f32 (lane l: block row / column l mod 32, K index
-// l / 32; accumulator r holds row 8 (r/4) + 4 (l/32) + r mod 4, column
-// l mod 32).  Rows and columns of the block beyond the PSF read clamped
-// (in-range) operands and are discarded.  A workgroup marches down a segment
+// with A, S zero outside the tile.  Each operand value v is staged as two
+// bfloat16 numbers, hi = v rounded to nearest even and lo = (v - hi) rounded
+// likewise (|v - hi - lo| <= 2^-16 |v|), and a product is taken as
+// lo hi' + hi lo' + hi hi' (the dropped lo lo' and the two remainders bound
+// its relative error by about 3 * 2^-16; the products are exact and summed in
+// FP32).  K runs along x' sixteen columns per v_mfma_f32_32x32x16_bf16,
+// three per step (lane l: block row / column l mod 32, columns 8 (l/32) ..
+// 8 (l/32) + 7 of the step in both operands, so the order in which the
+// instruction pairs them does not matter; accumulator r holds row
+// 8 (r/4) + 4 (l/32) + r mod 4, column l mod 32).  Rows and columns of the
+// block beyond the PSF read clamped (in-range) operands and are discarded.  A workgroup marches down a segment
 // of DHM_SEG rows of a 256-column strip, DHM_TB (= RAD) rows per step, for
 // each of the three products in turn: the extended rows of e, W or u are a
 // ring of three blocks of DHM_TB rows, and a step stages only the block that
@@ -606,6 +612,30 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
 // row of a step; the eight waves' blocks are summed in a fixed order (FP64)
 // into this workgroup's slot of `part`.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+
+// v = hi + lo as bfloat16 bit patterns, packed hi << 16 | lo (finite v).
+DEBLUR_DEV unsigned bf16_split(float v)
+{
+    auto rne = [](float x) {
+        const unsigned b = __float_as_uint(x);
+        return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+    };
+    const unsigned hi = rne(v);
+    return hi << 16 | rne(v - __uint_as_float(hi << 16));
+}
+
+// One half (selector 0x07060302: the hi parts, 0x05040100: the lo parts) of
+// eight packed words as an MFMA operand.
+DEBLUR_DEV bf16x8 bf16_halves(const unsigned (&w)[8], unsigned sel)
+{
+    uintx4 o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_perm(w[2 * i + 1], w[2 * i], sel);
+    return __builtin_bit_cast(bf16x8, o);
+}
+
 constexpr int DHM_TB = 16, DHM_TW = 256, DHM_NT = 512, DHM_WAVES = DHM_NT / 64, DHM_SEG = 128;
 
 template <int RAD>
@@ -617,16 +647,16 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
     constexpr int TB = DHM_TB, TW = DHM_TW;
     static_assert(TB == RAD, "the halo of a step is one block of rows above and one below");
     constexpr int QP = TW + 2 * RAD + 1, AP = TW + 4 * RAD + 1;   // odd pitches
-    // K steps run in groups of eight (rounded up) with the next group read
-    // ahead: reads pass the end of a row by at most 29 columns, into the next
-    // row or a zeroed tail.  A step past the useful columns multiplies by the
-    // zero margin of the tile plane (2 RAD >= 32 zero columns on each side).
+    // K steps of sixteen columns (rounded up) with the next step read ahead:
+    // reads pass the end of a row by at most 29 columns, into the next row or
+    // a zeroed tail.  A step past the useful columns multiplies by the zero
+    // margin of the tile plane (2 RAD >= 32 zero columns on each side).
     constexpr int TAIL = 64;
     static_assert(2 * RAD >= 30 && DHM_WAVES * 1024 <= 3 * TB * QP, "margins and reduction space");
     // extended rows as a ring of three blocks of TB rows (block b: rows
     // ys - TB + TB b .., slot b mod 3); the tile plane of the current step
-    __shared__ float qe[3 * TB * QP + TAIL];   // columns x0 - RAD ..
-    __shared__ float at[TB * AP + TAIL];       // columns x0 - 2 RAD ..
+    __shared__ unsigned qe[3 * TB * QP + TAIL];   // columns x0 - RAD .. (split words)
+    __shared__ unsigned at[TB * AP + TAIL];       // columns x0 - 2 RAD ..
     ab = zadv(ab, z.ws);
     qw = zadv(qw, z.ws);
     ds = zadv(ds, z.ws);
@@ -640,23 +670,23 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
     const int cy = (ph - 1) / 2, cx = (pw - 1) / 2;
     const int dy = min(bi - cy, cy), dx = min(bi - cx, cx);   // this lane's lags (clamped beyond the PSF)
     const int c_lo = (RAD - cx) & ~1, c_hi = RAD + TW + cx;   // columns x' with a non-zero product
-    const int steps8 = (((c_hi - c_lo + 1) >> 1) + 7) & ~7;
+    const int nk = (c_hi - c_lo + 16) / 16;   // K steps
     floatx16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
     if (tid < TAIL) {
-        qe[3 * TB * QP + tid] = 0.0f;
-        at[TB * AP + tid] = 0.0f;
+        qe[3 * TB * QP + tid] = 0u;
+        at[TB * AP + tid] = 0u;
     }
     // block b of the extended rows of product `phase` into its ring slot
     auto stage_block = [&](int phase, int b) {
-        float* dst = qe + (b % 3) * TB * QP;
+        unsigned* dst = qe + (b % 3) * TB * QP;
         const int r0 = ys - TB + TB * b;
         stage_to_lds_n<8>(dst, TB * QP, [&](int idx) {
             const int r = idx / QP, c = idx - r * QP;
             const int gy = ext_index(r0 + r, H, bc), gx = ext_index(x0 - RAD + min(c, QP - 2), W, bc);
-            return phase == 2 ? u[(size_t)gy * pitch + gx] : (phase == 0 ? qw[(size_t)gy * W + gx].x
-                                                                          : qw[(size_t)gy * W + gx].y);
+            return bf16_split(phase == 2 ? u[(size_t)gy * pitch + gx]
+                                         : (phase == 0 ? qw[(size_t)gy * W + gx].x : qw[(size_t)gy * W + gx].y));
         });
     };
 
@@ -672,34 +702,37 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
             stage_block(phase, s + 2);
             stage_to_lds_n<8>(at, TB * AP, [&](int idx) {
                 const int t = idx / AP, x = x0 - 2 * RAD + (idx - t * AP), y = y0 + t;
-                if (y >= H || x < x0 || x >= x0 + TW || x >= W) return 0.0f;
+                if (y >= H || x < x0 || x >= x0 + TW || x >= W) return 0u;
                 const size_t o = (size_t)y * W + x;
-                return phase == 2 ? ds[o] : (phase == 0 ? ab[o].x : ab[o].y);
+                return bf16_split(phase == 2 ? ds[o] : (phase == 0 ? ab[o].x : ab[o].y));
             });
             __syncthreads();
             for (int t = wave; t < TB; t += DHM_WAVES) {
                 if (y0 + t >= H) break;
                 // ring row of extended row y0 + t + sy (block-relative q)
                 const int q = TB + TB * s + t + sy;
-                const float* ar = qe + ((q / TB) % 3 * TB + q % TB) * QP + k + c_lo;
-                const float* br = at + t * AP + RAD + sx + k + c_lo;
-                // the operands of the next eight K steps are read from LDS
-                // while the current eight run on the matrix core
-                float a[8], b[8];
+                const unsigned* ar = qe + ((q / TB) % 3 * TB + q % TB) * QP + 8 * k + c_lo;
+                const unsigned* br = at + t * AP + RAD + sx + 8 * k + c_lo;
+                // the words of the next K step are read from LDS while the
+                // current step's three products run on the matrix core
+                unsigned a[8], b[8];
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
-                    a[m] = ar[2 * m];
-                    b[m] = br[2 * m];
+                    a[m] = ar[m];
+                    b[m] = br[m];
                 }
-                for (int n = 0; n < steps8; n += 8) {
-                    float a2[8], b2[8];
+                for (int n = 0; n < nk; ++n) {
+                    unsigned a2[8], b2[8];
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
-                        a2[m] = ar[2 * (n + 8 + m)];
-                        b2[m] = br[2 * (n + 8 + m)];
+                        a2[m] = ar[16 * (n + 1) + m];
+                        b2[m] = br[16 * (n + 1) + m];
                     }
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[m], b[m], acc, 0, 0, 0);
+                    const bf16x8 ah = bf16_halves(a, 0x07060302u), al = bf16_halves(a, 0x05040100u);
+                    const bf16x8 bh = bf16_halves(b, 0x07060302u), bl = bf16_halves(b, 0x05040100u);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
                         a[m] = a2[m];
@@ -710,7 +743,7 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
         }
     }
     __syncthreads();
-    float* red = qe;
+    float* red = reinterpret_cast<float*>(qe);
 #pragma unroll
     for (int r = 0; r < 16; ++r) red[wave * 1024 + (8 * (r >> 2) + 4 * k + (r & 3)) * 32 + bi] = acc[r];
     __syncthreads();
