@@ -261,8 +261,12 @@ int deblur_rrrl_iterate_noalloc(const float* f, const float* u_in, float* u_out,
  * K, pos_floor: the Wiener parameters of the forward call (used when
  * through_wiener; then H and W must be 2^a 3^b <= 2048).  Derivatives of
  * max/min take the branch taken (0 at ties); d r_f/df is taken as 0 where
- * f <= 0.  Partial sums are reduced in a fixed order: results are
- * deterministic.  Output buffers must not overlap the inputs. */
+ * f <= 0.  For PSF arrays of at most 32 x 32 entries whose longer side has
+ * more than 16, dL/dh runs on the matrix cores with each factor split into
+ * two bfloat16 parts: a product's relative error is about 3 * 2^-16, and
+ * the sums are FP32.
+ * Partial sums are reduced in a fixed order: results are deterministic.
+ * Output buffers must not overlap the inputs. */
 int deblur_rrrl_backward(const float* f, const float* ckpt, const float* grad_uK, int32_t H, int32_t W,
                          int32_t pitch, const deblur_psf* psf, const deblur_params* p, int32_t through_wiener,
                          double K, float pos_floor, float* grad_f, float* grad_taps, float* grad_alpha,
