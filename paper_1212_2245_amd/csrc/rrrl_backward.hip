@@ -714,29 +714,30 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
                 const unsigned* ar = qe + ((q / TB) % 3 * TB + q % TB) * QP + 8 * k + c_lo;
                 const unsigned* br = at + t * AP + RAD + sx + 8 * k + c_lo;
                 // the words of the next K step are read from LDS while the
-                // current step's three products run on the matrix core
-                unsigned a[8], b[8];
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    a[m] = ar[m];
-                    b[m] = br[m];
-                }
-                for (int n = 0; n < nk; ++n) {
-                    unsigned a2[8], b2[8];
+                // current step's three products run on the matrix core; two
+                // register sets take turns (steps read: 0 .. nk)
+                unsigned a[8], b[8], a2[8], b2[8];
+                auto words = [&](unsigned (&x)[8], unsigned (&y)[8], int n) {
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
-                        a2[m] = ar[16 * (n + 1) + m];
-                        b2[m] = br[16 * (n + 1) + m];
+                        x[m] = ar[16 * n + m];
+                        y[m] = br[16 * n + m];
                     }
-                    const bf16x8 ah = bf16_halves(a, 0x07060302u), al = bf16_halves(a, 0x05040100u);
-                    const bf16x8 bh = bf16_halves(b, 0x07060302u), bl = bf16_halves(b, 0x05040100u);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) {
-                        a[m] = a2[m];
-                        b[m] = b2[m];
+                };
+                auto products = [&](const unsigned (&x)[8], const unsigned (&y)[8]) {
+                    const bf16x8 xh = bf16_halves(x, 0x07060302u), xl = bf16_halves(x, 0x05040100u);
+                    const bf16x8 yh = bf16_halves(y, 0x07060302u), yl = bf16_halves(y, 0x05040100u);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl, yh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, yl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, yh, acc, 0, 0, 0);
+                };
+                words(a, b, 0);
+                for (int n = 0; n < nk; n += 2) {
+                    words(a2, b2, n + 1);
+                    products(a, b);
+                    if (n + 1 < nk) {
+                        words(a, b, n + 2);
+                        products(a2, b2);
                     }
                 }
             }
