@@ -113,6 +113,14 @@ CASES = [
     # PSF reach comparable to the image: the transposes' border folds span most of a row or column
     ("line31_on_32", 32, 32, lambda: synth.line_psf(31, 0.9), oracle.BC_REPLICATE, True, 2, True),
     ("line31_on_32x36_periodic", 32, 36, lambda: synth.line_psf(31, 0.9), oracle.BC_PERIODIC, True, 2, False),
+    # PSF arrays of the matrix-core dL/dh path (longer side 17..31) that are not square: unequal row and
+    # column lags, down to a single row or column
+    ("rect17x31_rep", 48, 64, lambda: synth.random_psf(np.random.default_rng(21), 17, 31), oracle.BC_REPLICATE,
+     True, 2, True),
+    ("row1x25_periodic", 36, 48, lambda: synth.random_psf(np.random.default_rng(22), 1, 25), oracle.BC_PERIODIC,
+     True, 2, False),
+    ("col29x3_rep", 64, 48, lambda: synth.random_psf(np.random.default_rng(23), 29, 3), oracle.BC_REPLICATE, True,
+     3, True),
 ]
 
 
