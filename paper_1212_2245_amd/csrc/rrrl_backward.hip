@@ -646,7 +646,11 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
 {
     constexpr int TB = DHM_TB, TW = DHM_TW;
     static_assert(TB == RAD, "the halo of a step is one block of rows above and one below");
-    constexpr int QP = TW + 2 * RAD + 1, AP = TW + 4 * RAD + 1;   // odd pitches
+    // extended rows: a pitch of whole 16-byte units, so that the eight words a
+    // lane reads per step are two aligned 16-byte reads (the lanes of a half
+    // read rows 292 words apart: disjoint banks); the tile plane keeps an odd
+    // pitch (its lanes start at different columns)
+    constexpr int QP = (TW + 2 * RAD + 1 + 3) & ~3, AP = TW + 4 * RAD + 1;
     // K steps of sixteen columns (rounded up) with the next step read ahead:
     // reads pass the end of a row by at most 29 columns, into the next row or
     // a zeroed tail.  A step past the useful columns multiplies by the zero
@@ -655,7 +659,7 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
     static_assert(2 * RAD >= 30 && DHM_WAVES * 1024 <= 3 * TB * QP, "margins and reduction space");
     // extended rows as a ring of three blocks of TB rows (block b: rows
     // ys - TB + TB b .., slot b mod 3); the tile plane of the current step
-    __shared__ unsigned qe[3 * TB * QP + TAIL];   // columns x0 - RAD .. (split words)
+    __shared__ __align__(16) unsigned qe[3 * TB * QP + TAIL];   // columns x0 - RAD .. (split words)
     __shared__ unsigned at[TB * AP + TAIL];       // columns x0 - 2 RAD ..
     ab = zadv(ab, z.ws);
     qw = zadv(qw, z.ws);
@@ -669,7 +673,7 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
     const int bi = lane & 31, k = lane >> 5;
     const int cy = (ph - 1) / 2, cx = (pw - 1) / 2;
     const int dy = min(bi - cy, cy), dx = min(bi - cx, cx);   // this lane's lags (clamped beyond the PSF)
-    const int c_lo = (RAD - cx) & ~1, c_hi = RAD + TW + cx;   // columns x' with a non-zero product
+    const int c_lo = (RAD - cx) & ~3, c_hi = RAD + TW + cx;   // columns x' with a non-zero product
     const int nk = (c_hi - c_lo + 16) / 16;   // K steps
     floatx16 acc;
 #pragma unroll
@@ -684,7 +688,7 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
         const int r0 = ys - TB + TB * b;
         stage_to_lds_n<8>(dst, TB * QP, [&](int idx) {
             const int r = idx / QP, c = idx - r * QP;
-            const int gy = ext_index(r0 + r, H, bc), gx = ext_index(x0 - RAD + min(c, QP - 2), W, bc);
+            const int gy = ext_index(r0 + r, H, bc), gx = ext_index(x0 - RAD + min(c, TW + 2 * RAD - 1), W, bc);
             return bf16_split(phase == 2 ? u[(size_t)gy * pitch + gx]
                                          : (phase == 0 ? qw[(size_t)gy * W + gx].x : qw[(size_t)gy * W + gx].y));
         });
@@ -719,9 +723,13 @@ __global__ void __launch_bounds__(DHM_NT) adj_dh_mfma(const float2* __restrict__
                 unsigned a[8], b[8], a2[8], b2[8];
                 auto words = [&](unsigned (&x)[8], unsigned (&y)[8], int n) {
 #pragma unroll
-                    for (int m = 0; m < 8; ++m) {
-                        x[m] = ar[16 * n + m];
-                        y[m] = br[16 * n + m];
+                    for (int m = 0; m < 8; ++m) y[m] = br[16 * n + m];
+                    const uintx4* a4 = reinterpret_cast<const uintx4*>(ar + 16 * n);
+                    const uintx4 lo4 = a4[0], hi4 = a4[1];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        x[m] = lo4[m];
+                        x[4 + m] = hi4[m];
                     }
                 };
                 auto products = [&](const unsigned (&x)[8], const unsigned (&y)[8]) {
