@@ -603,14 +603,14 @@ __global__ void __launch_bounds__(BW_NT) adj_dh(const float2* __restrict__ ab, c
 // 8 (l/32) + 7 of the step in both operands, so the order in which the
 // instruction pairs them does not matter; accumulator r holds row
 // 8 (r/4) + 4 (l/32) + r mod 4, column l mod 32).  Rows and columns of the
-// block beyond the PSF read clamped (in-range) operands and are discarded.  A workgroup marches down a segment
-// of DHM_SEG rows of a 256-column strip, DHM_TB (= RAD) rows per step, for
-// each of the three products in turn: the extended rows of e, W or u are a
-// ring of three blocks of DHM_TB rows, and a step stages only the block that
-// enters its halo (plus the tile plane of a, bb or ds with zero margins of
-// twice the radius), so two workgroups fit a CU.  A wave takes every eighth
-// row of a step; the eight waves' blocks are summed in a fixed order (FP64)
-// into this workgroup's slot of `part`.
+// block beyond the PSF read clamped (in-range) operands and are discarded.
+// A workgroup marches down a segment of DHM_SEG rows of a 256-column strip,
+// DHM_TB (= RAD) rows per step, for each of the three products in turn: the
+// extended rows of e, W or u are a ring of three blocks of DHM_TB rows, and a
+// step stages only the block that enters its halo (plus the tile plane of a,
+// bb or ds with zero margins of twice the radius), so two workgroups fit a
+// CU.  A wave takes every eighth row of a step; the eight waves' blocks are
+// summed in a fixed order (FP64) into this workgroup's slot of `part`.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
